@@ -1,0 +1,359 @@
+/*
+ * oracle.c -- CPU reference for the randomized orthogonal projection of
+ * Rokhlin & Tygert, "A fast randomized algorithm for orthogonal projection".
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link or call this
+ * file; only the test-suite, the smoke check and the benchmark's CPU-baseline
+ * leg do.  It shares no code, header or table with the GPU library: every
+ * routine here is written from the paper's definitions, plainly and slowly,
+ * in IEEE double precision, with an extended-precision (binary128) residual
+ * where the definition must be evaluated beyond double rounding.
+ *
+ * Contents
+ *   orc_splitmix64_*     SplitMix64 (Steele, Lea, Flood 2014) and the draw
+ *                        order of the sketch's random tables.
+ *   orc_srft_tables      signs, block/in-block permutations, sorted subset J
+ *                        of the subsampled randomized Fourier sketch.
+ *   orc_qrcp             Businger-Golub column-pivoted Householder QR
+ *                        (Sec. 4, eq. QR_decomp; Householder reflections as
+ *                        stated at the end of Sec. 5).
+ *   orc_project          The three outputs of the problem statement (Sec. 1,
+ *                        items 1-3; Sec. 4, first paragraph): x = argmin
+ *                        |A^T x - b| (Remark 4.1), row projection A^T x and
+ *                        null projection b - A^T x (eq. basic_identity).
+ *                        Evaluated by Householder QR of A^T plus iterative
+ *                        refinement (the refinement of Remark 4.3) with the
+ *                        residuals in binary128.
+ *
+ * Conventions
+ *   A is row-major m x n with leading dimension lda (element (i,j) at
+ *   A[i*lda + j]).  Right-hand sides are column-major n x k (column c at
+ *   B + c*ldb).  X is column-major m x k.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef __float128 quad;
+
+/* ------------------------------------------------------------------------ */
+/* SplitMix64: state advances by the golden-ratio increment; each output is  */
+/* the published 64-bit finalizer of the new state.                          */
+/* ------------------------------------------------------------------------ */
+static uint64_t sm64_next(uint64_t *state)
+{
+    uint64_t z = (*state += 0x9e3779b97f4a7c15ULL);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+/* Uniform integer in [0, range): high word of the 128-bit product. */
+static uint64_t sm64_below(uint64_t *state, uint64_t range)
+{
+    unsigned __int128 p = (unsigned __int128)sm64_next(state) * range;
+    return (uint64_t)(p >> 64);
+}
+
+void orc_splitmix64_stream(uint64_t seed, int64_t count, uint64_t *out)
+{
+    uint64_t s = seed;
+    for (int64_t i = 0; i < count; ++i) out[i] = sm64_next(&s);
+}
+
+/* Seed of batch instance i: first output of a generator started at seed^i. */
+uint64_t orc_instance_seed(uint64_t seed, int64_t i)
+{
+    uint64_t s = seed ^ (uint64_t)i;
+    return sm64_next(&s);
+}
+
+/* Padded length and grid split of the sketch's Fourier transform:
+ * np = max(4, 2^ceil(log2 n)), n2 = 2^floor(e/2), n1 = np/n2. */
+void orc_srft_dims(int64_t n, int64_t *np, int64_t *n1, int64_t *n2)
+{
+    int64_t p = 4;
+    int e = 2;
+    while (p < n) { p <<= 1; ++e; }
+    *np = p;
+    *n2 = (int64_t)1 << (e / 2);
+    *n1 = p / *n2;
+}
+
+/*
+ * Random tables of the sketch, drawn from one SplitMix64 stream started at
+ * `seed`, in this order:
+ *   1. np signs: draw t gives sign[t] = -1 if its top bit is set, else +1;
+ *   2. sigma, a permutation of [0,n1): Fisher-Yates from the top
+ *      (for j = n1-1..1: r = below(j+1); swap sigma[j], sigma[r]);
+ *   3. tau, a permutation of [0,n2), drawn the same way;
+ *   4. J, an l-subset of [0,np) in increasing order by selection sampling
+ *      (for t = 0,1,..: keep t iff below(np - t) < l - kept).
+ * The permutation of the padded row is pi(t) = sigma[t / n2]*n2 + tau[t % n2].
+ */
+int orc_srft_tables(uint64_t seed, int64_t n, int64_t l, int8_t *sign,
+                    int32_t *sigma, int32_t *tau, int32_t *J)
+{
+    int64_t np, n1, n2;
+    orc_srft_dims(n, &np, &n1, &n2);
+    if (l < 1 || l > np) return 1;
+    uint64_t s = seed;
+    for (int64_t t = 0; t < np; ++t)
+        sign[t] = (sm64_next(&s) >> 63) ? (int8_t)-1 : (int8_t)1;
+    for (int64_t j = 0; j < n1; ++j) sigma[j] = (int32_t)j;
+    for (int64_t j = n1 - 1; j >= 1; --j) {
+        int64_t r = (int64_t)sm64_below(&s, (uint64_t)(j + 1));
+        int32_t tmp = sigma[j]; sigma[j] = sigma[r]; sigma[r] = tmp;
+    }
+    for (int64_t j = 0; j < n2; ++j) tau[j] = (int32_t)j;
+    for (int64_t j = n2 - 1; j >= 1; --j) {
+        int64_t r = (int64_t)sm64_below(&s, (uint64_t)(j + 1));
+        int32_t tmp = tau[j]; tau[j] = tau[r]; tau[r] = tmp;
+    }
+    int64_t kept = 0;
+    for (int64_t t = 0; t < np && kept < l; ++t) {
+        if ((int64_t)sm64_below(&s, (uint64_t)(np - t)) < l - kept) J[kept++] = (int32_t)t;
+    }
+    return kept == l ? 0 : 2;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Column-pivoted Householder QR (Businger-Golub), eq. QR_decomp:            */
+/*   M Pi^T = Q R, M is rows x cols column-major (ld = ldm), rows >= cols.   */
+/* At step k the pivot is the not-yet-chosen column whose trailing part      */
+/* M[k:, j] has the largest 2-norm (recomputed from scratch every step; ties */
+/* go to the lowest original column index).  The reflector is               */
+/* H = I - tau v v^T with v[0] = 1, beta = -sign(alpha)*|x| (sign(0) = +1).  */
+/* Outputs: R (cols x cols, row-major, upper triangle; zeros below) and piv, */
+/* with column k of M Pi^T equal to column piv[k] of M.  M is overwritten.   */
+/* ------------------------------------------------------------------------ */
+int orc_qrcp(int64_t rows, int64_t cols, double *M, int64_t ldm, double *R, int32_t *piv)
+{
+    if (rows < cols || cols < 1) return 1;
+    char *done = (char *)calloc((size_t)cols, 1);
+    double *nrm = (double *)malloc(sizeof(double) * (size_t)cols);
+    double *v = (double *)malloc(sizeof(double) * (size_t)rows);
+    if (!done || !nrm || !v) { free(done); free(nrm); free(v); return 3; }
+    memset(R, 0, sizeof(double) * (size_t)(cols * cols));
+    for (int64_t k = 0; k < cols; ++k) {
+        /* norms of the trailing parts of the remaining columns */
+        #pragma omp parallel for schedule(static)
+        for (int64_t j = 0; j < cols; ++j) {
+            if (done[j]) continue;
+            const double *c = M + j * ldm;
+            double s = 0.0;
+            for (int64_t i = k; i < rows; ++i) s += c[i] * c[i];
+            nrm[j] = s;
+        }
+        int64_t p = -1;
+        for (int64_t j = 0; j < cols; ++j) {
+            if (done[j]) continue;
+            if (p < 0 || nrm[j] > nrm[p]) p = j;
+        }
+        done[p] = 1;
+        piv[k] = (int32_t)p;
+        double *x = M + p * ldm;
+        /* R entries above the diagonal were produced by earlier reflectors */
+        for (int64_t i = 0; i < k; ++i) R[i * cols + k] = x[i];
+        double alpha = x[k];
+        double xnorm = sqrt(nrm[p]);
+        double beta, tau;
+        if (xnorm == 0.0) {
+            beta = 0.0; tau = 0.0;
+            for (int64_t i = k; i < rows; ++i) v[i] = 0.0;
+            v[k] = 1.0;
+        } else {
+            beta = (alpha >= 0.0) ? -xnorm : xnorm;
+            tau = (beta - alpha) / beta;
+            double inv = 1.0 / (alpha - beta);
+            v[k] = 1.0;
+            for (int64_t i = k + 1; i < rows; ++i) v[i] = x[i] * inv;
+        }
+        R[k * cols + k] = beta;
+        x[k] = beta;
+        for (int64_t i = k + 1; i < rows; ++i) x[i] = 0.0;
+        /* apply H_k to every other remaining column */
+        #pragma omp parallel for schedule(static)
+        for (int64_t j = 0; j < cols; ++j) {
+            if (done[j]) continue;
+            double *c = M + j * ldm;
+            double w = 0.0;
+            for (int64_t i = k; i < rows; ++i) w += v[i] * c[i];
+            w *= tau;
+            for (int64_t i = k; i < rows; ++i) c[i] -= w * v[i];
+        }
+    }
+    free(done); free(nrm); free(v);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Projection, row projection and least squares (Sec. 1; Sec. 4; Rem. 4.1).  */
+/* ------------------------------------------------------------------------ */
+
+/* Householder QR of A^T (n x m): the columns of A^T are the rows of A.     */
+/* H holds them as m vectors of length n; on return H[j][j+1:] holds the     */
+/* reflector tails (v[0] = 1 implied), tau[j] the scalar, Rd the diagonal.   */
+static void householder_at(int64_t m, int64_t n, double *H, double *tau, double *Rd)
+{
+    for (int64_t j = 0; j < m; ++j) {
+        double *x = H + j * n;
+        double s = 0.0;
+        for (int64_t i = j; i < n; ++i) s += x[i] * x[i];
+        double xnorm = sqrt(s), alpha = x[j];
+        double beta, t;
+        if (xnorm == 0.0) { beta = 0.0; t = 0.0; }
+        else {
+            beta = (alpha >= 0.0) ? -xnorm : xnorm;
+            t = (beta - alpha) / beta;
+            double inv = 1.0 / (alpha - beta);
+            for (int64_t i = j + 1; i < n; ++i) x[i] *= inv;
+        }
+        tau[j] = t;
+        Rd[j] = beta;
+        x[j] = 1.0; /* temporarily v[0] */
+        #pragma omp parallel for schedule(static)
+        for (int64_t c = j + 1; c < m; ++c) {
+            double *y = H + c * n;
+            double w = 0.0;
+            for (int64_t i = j; i < n; ++i) w += x[i] * y[i];
+            w *= t;
+            for (int64_t i = j; i < n; ++i) y[i] -= w * x[i];
+        }
+        x[j] = beta;
+    }
+}
+
+/* R of A^T: R[i][j] = H[j][i] for i < j, diagonal Rd. Solve R y = c. */
+static void solve_r(int64_t m, int64_t n, const double *H, const double *Rd, double *y)
+{
+    for (int64_t i = m - 1; i >= 0; --i) {
+        double s = y[i];
+        for (int64_t j = i + 1; j < m; ++j) s -= H[j * n + i] * y[j];
+        y[i] = s / Rd[i];
+    }
+}
+
+/* Solve R^T y = c (forward substitution). */
+static void solve_rt(int64_t m, int64_t n, const double *H, const double *Rd, double *y)
+{
+    for (int64_t i = 0; i < m; ++i) {
+        double s = y[i];
+        const double *col = H + i * n; /* column i of R above the diagonal: H[i][0..i-1] */
+        for (int64_t j = 0; j < i; ++j) s -= col[j] * y[j];
+        y[i] = s / Rd[i];
+    }
+}
+
+/*
+ * For each of the k columns b of B:
+ *   x = argmin_h |A^T h - b|        (written to X if X != NULL)
+ *   p = A^T x                       (row-space projection, to P if != NULL)
+ *   z = b - A^T x                   (null-space projection, to Z if != NULL)
+ * Start: x0 from the Householder QR of A^T (x0 = R^{-1} [Q^T b]_{0:m}).
+ * Refinement (Remark 4.3): r = b - A^T x and s = A r evaluated in binary128,
+ * correction d = R^{-1} R^{-T} s in double, x += d kept in binary128; stop
+ * when |d| <= 1e-22 |x|, when |d| stops decreasing, or after maxit steps.
+ * z and p are formed from the binary128 x in binary128 and rounded once.
+ * info (length >= 2, may be NULL): info[0] = refinement steps taken,
+ * info[1] = |d|/|x| of the last step (maximum over columns).
+ */
+int orc_project(int64_t m, int64_t n, const double *A, int64_t lda, int64_t k,
+                const double *B, int64_t ldb, double *Z, int64_t ldz,
+                double *P, int64_t ldp, double *X, int64_t ldx, int maxit, double *info)
+{
+    if (m < 1 || n < m || lda < n || k < 0 || (k > 0 && ldb < n)) return 1;
+    double *H = (double *)malloc(sizeof(double) * (size_t)(m * n));
+    double *tau = (double *)malloc(sizeof(double) * (size_t)m);
+    double *Rd = (double *)malloc(sizeof(double) * (size_t)m);
+    quad *xq = (quad *)malloc(sizeof(quad) * (size_t)(m * (k > 0 ? k : 1)));
+    if (!H || !tau || !Rd || !xq) { free(H); free(tau); free(Rd); free(xq); return 3; }
+    for (int64_t i = 0; i < m; ++i) memcpy(H + i * n, A + i * lda, sizeof(double) * (size_t)n);
+    householder_at(m, n, H, tau, Rd);
+
+    int steps_max = 0;
+    double last_ratio = 0.0;
+    #pragma omp parallel for schedule(dynamic, 1) reduction(max:steps_max, last_ratio)
+    for (int64_t c = 0; c < k; ++c) {
+        const double *b = B + c * ldb;
+        double *w = (double *)malloc(sizeof(double) * (size_t)n);
+        quad *r = (quad *)malloc(sizeof(quad) * (size_t)n);
+        double *d = (double *)malloc(sizeof(double) * (size_t)m);
+        quad *x = xq + c * m;
+        /* x0: apply H_0 .. H_{m-1} to b, then back-substitute with R */
+        memcpy(w, b, sizeof(double) * (size_t)n);
+        for (int64_t j = 0; j < m; ++j) {
+            const double *v = H + j * n;
+            double s = w[j];
+            for (int64_t i = j + 1; i < n; ++i) s += v[i] * w[i];
+            s *= tau[j];
+            w[j] -= s;
+            for (int64_t i = j + 1; i < n; ++i) w[i] -= s * v[i];
+        }
+        memcpy(d, w, sizeof(double) * (size_t)m);
+        solve_r(m, n, H, Rd, d);
+        for (int64_t i = 0; i < m; ++i) x[i] = (quad)d[i];
+        double prev = INFINITY, ratio = 0.0;
+        int steps = 0;
+        for (int it = 0; it < maxit; ++it) {
+            /* r = b - A^T x in binary128 */
+            for (int64_t t = 0; t < n; ++t) r[t] = (quad)b[t];
+            for (int64_t i = 0; i < m; ++i) {
+                const double *a = A + i * lda;
+                quad xi = x[i];
+                for (int64_t t = 0; t < n; ++t) r[t] -= (quad)a[t] * xi;
+            }
+            /* s = A r in binary128, rounded once to double */
+            for (int64_t i = 0; i < m; ++i) {
+                const double *a = A + i * lda;
+                quad s = 0;
+                for (int64_t t = 0; t < n; ++t) s += (quad)a[t] * r[t];
+                d[i] = (double)s;
+            }
+            solve_rt(m, n, H, Rd, d);
+            solve_r(m, n, H, Rd, d);
+            double dn = 0.0, xn = 0.0;
+            for (int64_t i = 0; i < m; ++i) {
+                x[i] += (quad)d[i];
+                dn += d[i] * d[i];
+                double xd = (double)x[i];
+                xn += xd * xd;
+            }
+            dn = sqrt(dn); xn = sqrt(xn);
+            ++steps;
+            ratio = xn > 0.0 ? dn / xn : 0.0;
+            if (dn <= 1e-22 * xn || dn >= prev) break;
+            prev = dn;
+        }
+        /* p = A^T x and z = b - A^T x in binary128 */
+        for (int64_t t = 0; t < n; ++t) r[t] = 0;
+        for (int64_t i = 0; i < m; ++i) {
+            const double *a = A + i * lda;
+            quad xi = x[i];
+            for (int64_t t = 0; t < n; ++t) r[t] += (quad)a[t] * xi;
+        }
+        if (P) for (int64_t t = 0; t < n; ++t) P[c * ldp + t] = (double)r[t];
+        if (Z) for (int64_t t = 0; t < n; ++t) Z[c * ldz + t] = (double)((quad)b[t] - r[t]);
+        if (X) for (int64_t i = 0; i < m; ++i) X[c * ldx + i] = (double)x[i];
+        if (steps > steps_max) steps_max = steps;
+        if (ratio > last_ratio) last_ratio = ratio;
+        free(w); free(r); free(d);
+    }
+    if (info) { info[0] = steps_max; info[1] = last_ratio; }
+    free(H); free(tau); free(Rd); free(xq);
+    return 0;
+}
+
+/* Number of OpenMP threads the oracle runs with. */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
