@@ -1,0 +1,178 @@
+/*
+ * rtproj.h -- randomized, preconditioned orthogonal projection on AMD gfx950.
+ *
+ * Implements the method of Rokhlin & Tygert, "A fast randomized algorithm for
+ * orthogonal projection": for a full-rank m x n matrix A with m <= n and right-
+ * hand sides b (length n) it returns
+ *   - the least-squares solution x = argmin |A^T x - b|        (Remark 4.1),
+ *   - the projection onto the row space of A,  A^T x           (Sec. 4),
+ *   - the projection onto the null space of A, b - A^T x       (eq. basic_identity),
+ * through the preconditioned identity (eq. basic_precond) with P = Pi^T R^T
+ * taken from a column-pivoted QR (eq. QR_decomp) of a randomized sketch
+ * S = A G (eq. testing).
+ *
+ * Layouts (all matrices live in device memory unless stated otherwise):
+ *   A   row-major m x n, element (i, j) at A[i*lda + j], lda >= n.
+ *   B   column-major n x k: right-hand side c starts at B + c*ldb, ldb >= n.
+ *       (A C-contiguous torch tensor of shape (k, n).)  Same for Z and Y.
+ *   X   column-major m x k, ldx >= m.
+ * All floating-point data at the interface is IEEE binary64.
+ *
+ * Ownership and lifetime: a plan owns its device workspaces (allocated with
+ * hipMalloc at creation and grown on demand).  A is BORROWED by
+ * rtproj_precondition: every projection applies A and A^T again (the costs
+ * C_A and C_{A^*} of Sec. 4.1), so A must stay valid and unchanged until the
+ * next rtproj_precondition or rtproj_plan_destroy.  Outputs are owned by the
+ * caller.  Z (or Y) may alias B only with identical pointer and leading
+ * dimension.
+ *
+ * Streams and synchronisation: every call enqueues its work on the plan's
+ * stream (rtproj_plan_set_stream; default: the null stream).
+ * rtproj_precondition blocks until the sketch's pivoted QR has finished, to
+ * read the rank test (a few bytes).  The project calls are asynchronous unless
+ * refinement runs with a convergence test (set_refinement with rtol > 0),
+ * which reads one flag per refinement step.  A plan is not thread-safe;
+ * distinct plans are independent.
+ *
+ * Errors: every entry point returns an rtproj_status; nothing is thrown and
+ * nothing aborts.  Argument errors are detected on the host before any device
+ * work and leave the plan unchanged.  rtproj_last_error() returns a
+ * thread-local message for the last failure.
+ */
+#ifndef RTPROJ_H
+#define RTPROJ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rtproj_plan_s *rtproj_plan;
+
+typedef enum {
+    RTPROJ_OK = 0,
+    RTPROJ_ERR_INVALID_ARG = 1, /* bad size, leading dimension or null pointer */
+    RTPROJ_ERR_ALLOC = 2,       /* device allocation failed                      */
+    RTPROJ_ERR_DEVICE = 3,      /* HIP runtime or kernel failure                 */
+    RTPROJ_ERR_STATE = 4,       /* projection requested before preconditioning   */
+    RTPROJ_ERR_RANK = 5,        /* A (numerically) rank deficient: the pivoted QR
+                                   of the sketch or the Cholesky of the Gram failed */
+    RTPROJ_ERR_NOCONV = 6,      /* refinement did not contract                   */
+    RTPROJ_ERR_UNSUPPORTED = 7  /* size or mode this build does not handle       */
+} rtproj_status;
+
+/* Arithmetic used by the preconditioner (the projection's residuals, the
+ * solves with R and Pi, and the Cholesky are always binary64). */
+typedef enum {
+    RTPROJ_PREC_FP64 = 0,       /* sketch, P^{-1}A and its Gram in binary64           */
+    RTPROJ_PREC_MIXED_FP32 = 1, /* sketch, P^{-1}A and Gram in binary32 (MFMA)        */
+    RTPROJ_PREC_MIXED_BF16 = 2  /* binary32 sketch; Gram from row-scaled bfloat16
+                                   P^{-1}A with binary32 accumulation (MFMA)          */
+} rtproj_precision;
+
+typedef struct {
+    int64_t m, n, l;           /* sizes of the plan                                  */
+    int64_t np;                /* padded Fourier length of the sketch               */
+    double kappa_est;          /* |R_11 / R_mm| of the pivoted QR of the sketch      */
+    double rdiag_min;          /* |R_mm|                                             */
+    int precision;             /* rtproj_precision in effect                         */
+    int refine_steps;          /* refinement steps taken by the last projection     */
+    double refine_last_ratio;  /* |dx| / |x| of the last refinement step             */
+    int qrcp_blocks;           /* workgroups of the cooperative pivoted QR           */
+} rtproj_info;
+
+/*
+ * Create a plan for m x n matrices (1 <= m <= l <= n, Sec. 4: "m <= l <= n")
+ * sketched to l columns; `seed` fixes the random sketch (signs, permutations,
+ * subsample; see rtproj_sketch_tables).  Allocates device memory on the
+ * current HIP device.  On error *out is NULL.
+ */
+rtproj_status rtproj_plan_create(int64_t m, int64_t n, int64_t l, uint64_t seed, rtproj_plan *out);
+
+/* Release every resource of the plan (NULL is accepted). */
+rtproj_status rtproj_plan_destroy(rtproj_plan plan);
+
+/* Stream (a hipStream_t) on which the plan enqueues its work. */
+rtproj_status rtproj_plan_set_stream(rtproj_plan plan, void *hip_stream);
+
+/* Precision of the preconditioner (rtproj_precision).  Takes effect at the
+ * next rtproj_precondition. */
+rtproj_status rtproj_plan_set_precision(rtproj_plan plan, int precision);
+
+/*
+ * Iterative refinement of the least-squares solution (Remark 4.3): up to
+ * `max_steps` steps x <- x + M^{-1} A (b - A^T x) with M = P X P^T the
+ * preconditioned normal matrix, residuals accumulated in double-binary64
+ * (error-free transformations) and x kept as an unevaluated sum of two
+ * binary64 numbers.  rtol > 0 stops early once |dx| <= rtol |x| (one device-
+ * to-host read per step); rtol = 0 runs exactly max_steps steps without any
+ * host synchronisation.  max_steps = 0 returns the unrefined projection
+ * (the seven steps of Sec. 4 in binary64).  Default: max_steps = 3, rtol = 0.
+ */
+rtproj_status rtproj_plan_set_refinement(rtproj_plan plan, int max_steps, double rtol);
+
+/*
+ * Build the preconditioner for A (row-major m x n, lda >= n, device):
+ * sketch S = A G (eq. testing), pivoted QR S^T = Q R Pi (eq. QR_decomp),
+ * P^- = Pi^T R^{-1} (eq. scary) in its transposed form R^{-T}, the
+ * preconditioned matrix P^{-1}A = R^{-T} Pi A, its Gram X (the matrix X of
+ * Sec. 4, steps a-e) and the Cholesky factor of X in place of Y = X^{-1}
+ * (eq. inversion).  Blocks the host until the pivoted QR is done (rank test).
+ * Returns RTPROJ_ERR_RANK if |R_mm| <= m * 2^-52 * |R_11| or the Cholesky
+ * breaks down.  A is borrowed (see above).
+ */
+rtproj_status rtproj_precondition(rtproj_plan plan, const double *A, int64_t lda);
+
+/*
+ * Apply the projector to k right-hand sides (B column-major n x k, ldb >= n):
+ *   rtproj_project_null: Z = B - A^T X   (ldz >= n)
+ *   rtproj_project_row:  Y = A^T X       (ldy >= n)
+ *   rtproj_lstsq:        X               (ldx >= m)
+ *   rtproj_project_all:  any of Z, Y, X (NULL to skip)
+ * following the seven steps of Sec. 4 (c = A b, d = Pi c, R^T e = d,
+ * f = Y e, R g = f, h = Pi^T g, b~ = A^T h) plus the refinement configured by
+ * rtproj_plan_set_refinement.  k = 0 is a no-op.  RTPROJ_ERR_STATE before
+ * the first successful rtproj_precondition.
+ */
+rtproj_status rtproj_project_null(rtproj_plan plan, const double *B, int64_t ldb, int64_t k,
+                                  double *Z, int64_t ldz);
+rtproj_status rtproj_project_row(rtproj_plan plan, const double *B, int64_t ldb, int64_t k,
+                                 double *Y, int64_t ldy);
+rtproj_status rtproj_lstsq(rtproj_plan plan, const double *B, int64_t ldb, int64_t k,
+                           double *X, int64_t ldx);
+rtproj_status rtproj_project_all(rtproj_plan plan, const double *B, int64_t ldb, int64_t k,
+                                 double *Z, int64_t ldz, double *Y, int64_t ldy,
+                                 double *X, int64_t ldx);
+
+/* Sizes, rank estimate and refinement statistics (synchronises the stream). */
+rtproj_status rtproj_plan_info(rtproj_plan plan, rtproj_info *out);
+
+/*
+ * Copy plan state to device buffers supplied by the caller (synchronous):
+ *   S    m x l row-major sketch (lds >= l; NULL to skip)
+ *   R    m x m row-major upper-triangular factor of the pivoted QR (NULL to skip)
+ *   piv  m int32: column k of S^T Pi^T is column piv[k] of S^T (NULL to skip)
+ *   L    m x m row-major lower Cholesky factor of the Gram X (NULL to skip)
+ * RTPROJ_ERR_STATE before preconditioning.
+ */
+rtproj_status rtproj_plan_export(rtproj_plan plan, double *S, int64_t lds, double *R,
+                                 int32_t *piv, double *L);
+
+/*
+ * Host copies of the plan's random sketch tables (for inspection):
+ * sign[np] (+1/-1), sigma[n1], tau[n2] (permutations), J[l] (sorted subset of
+ * [0, np)), with np = max(4, 2^ceil(log2 n)), n2 = 2^floor(log2(np)/2),
+ * n1 = np / n2.  Any pointer may be NULL; dims may be NULL.
+ */
+rtproj_status rtproj_sketch_tables(rtproj_plan plan, int64_t *dims3, int8_t *sign,
+                                   int32_t *sigma, int32_t *tau, int32_t *J);
+
+const char *rtproj_status_string(rtproj_status status);
+const char *rtproj_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTPROJ_H */

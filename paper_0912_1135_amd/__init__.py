@@ -1,1 +1,201 @@
-"""MI355X-native randomized orthogonal projection (Rokhlin & Tygert)."""
+"""MI355X-native randomized orthogonal projection (Rokhlin & Tygert).
+
+Python binding of ``librtproj.so`` (the C ABI declared in include/rtproj.h).
+Argument marshalling only: every step runs in the library's gfx950 kernels.
+PyTorch supplies device memory and streams.  There is no CPU fallback: if the
+library is missing, every call raises.
+
+Layout conventions (torch view of the C layouts):
+  A  (m, n) float64 CUDA tensor with unit column stride (row-major m x n)
+  B  (k, n) float64 CUDA tensor with unit column stride: row c is right-hand
+     side c (column-major n x k in the C ABI); Z and Y have the same shape
+  X  (k, m) float64: row c is the least-squares solution for right-hand side c
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librtproj.so")
+_lib = None
+
+PREC_FP64, PREC_MIXED_FP32, PREC_MIXED_BF16 = 0, 1, 2
+STATUS = {0: "OK", 1: "ERR_INVALID_ARG", 2: "ERR_ALLOC", 3: "ERR_DEVICE", 4: "ERR_STATE",
+          5: "ERR_RANK", 6: "ERR_NOCONV", 7: "ERR_UNSUPPORTED"}
+
+
+class RtprojError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("l", ctypes.c_int64), ("np", ctypes.c_int64),
+                ("kappa_est", ctypes.c_double), ("rdiag_min", ctypes.c_double), ("precision", ctypes.c_int),
+                ("refine_steps", ctypes.c_int), ("refine_last_ratio", ctypes.c_double),
+                ("qrcp_blocks", ctypes.c_int)]
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(there is no fallback implementation)")
+        L = ctypes.CDLL(LIB_PATH)
+        i64, u64, vp, ip, dp = ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        L.rtproj_plan_create.argtypes = [i64, i64, i64, u64, ctypes.POINTER(vp)]
+        L.rtproj_plan_destroy.argtypes = [vp]
+        L.rtproj_plan_set_stream.argtypes = [vp, vp]
+        L.rtproj_plan_set_precision.argtypes = [vp, ip]
+        L.rtproj_plan_set_refinement.argtypes = [vp, ip, dp]
+        L.rtproj_precondition.argtypes = [vp, vp, i64]
+        L.rtproj_project_null.argtypes = [vp, vp, i64, i64, vp, i64]
+        L.rtproj_project_row.argtypes = [vp, vp, i64, i64, vp, i64]
+        L.rtproj_lstsq.argtypes = [vp, vp, i64, i64, vp, i64]
+        L.rtproj_project_all.argtypes = [vp, vp, i64, i64, vp, i64, vp, i64, vp, i64]
+        L.rtproj_plan_info.argtypes = [vp, ctypes.POINTER(_Info)]
+        L.rtproj_plan_export.argtypes = [vp, vp, i64, vp, vp, vp]
+        L.rtproj_sketch_tables.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.rtproj_status_string.argtypes = [ip]
+        L.rtproj_status_string.restype = ctypes.c_char_p
+        L.rtproj_last_error.restype = ctypes.c_char_p
+        for name in ["rtproj_plan_create", "rtproj_plan_destroy", "rtproj_plan_set_stream",
+                     "rtproj_plan_set_precision", "rtproj_plan_set_refinement", "rtproj_precondition",
+                     "rtproj_project_null", "rtproj_project_row", "rtproj_lstsq", "rtproj_project_all",
+                     "rtproj_plan_info", "rtproj_plan_export", "rtproj_sketch_tables"]:
+            getattr(L, name).restype = ip
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise RtprojError(status, lib().rtproj_last_error().decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _check_tensor(t, name, rows=None, cols=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError(f"{name} must be a float64 CUDA tensor")
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{name} must be 2-D with unit stride along its last dimension")
+    if rows is not None and t.shape[0] != rows:
+        raise ValueError(f"{name} has {t.shape[0]} rows, expected {rows}")
+    if cols is not None and t.shape[1] != cols:
+        raise ValueError(f"{name} has {t.shape[1]} columns, expected {cols}")
+
+
+class Plan:
+    """A plan for m x n matrices sketched to l columns (rtproj_plan)."""
+
+    def __init__(self, m: int, n: int, l: int, seed: int, stream=None):
+        h = ctypes.c_void_p()
+        _check(lib().rtproj_plan_create(m, n, l, seed, ctypes.byref(h)))
+        self.handle, self.m, self.n, self.l, self.seed = h, m, n, l, seed
+        self._A = None
+        self.set_stream(stream)
+
+    def close(self):
+        if self.handle:
+            lib().rtproj_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream=None):
+        """Enqueue on `stream` (a torch.cuda.Stream; default: torch's current stream)."""
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().rtproj_plan_set_stream(self.handle, ctypes.c_void_p(s.cuda_stream)))
+
+    def set_precision(self, precision: int):
+        _check(lib().rtproj_plan_set_precision(self.handle, precision))
+
+    def set_refinement(self, max_steps: int, rtol: float = 0.0):
+        _check(lib().rtproj_plan_set_refinement(self.handle, max_steps, rtol))
+
+    def precondition(self, A):
+        _check_tensor(A, "A", self.m, self.n)
+        _check(lib().rtproj_precondition(self.handle, _ptr(A), A.stride(0)))
+        self._A = A  # the plan borrows A
+
+    def _rhs(self, B):
+        _check_tensor(B, "B", None, self.n)
+        return B.shape[0]
+
+    def project_null(self, B, out=None):
+        import torch
+        k = self._rhs(B)
+        Z = out if out is not None else torch.empty_like(B)
+        _check(lib().rtproj_project_null(self.handle, _ptr(B), B.stride(0), k, _ptr(Z), Z.stride(0)))
+        return Z
+
+    def project_row(self, B, out=None):
+        import torch
+        k = self._rhs(B)
+        Y = out if out is not None else torch.empty_like(B)
+        _check(lib().rtproj_project_row(self.handle, _ptr(B), B.stride(0), k, _ptr(Y), Y.stride(0)))
+        return Y
+
+    def lstsq(self, B, out=None):
+        import torch
+        k = self._rhs(B)
+        X = out if out is not None else torch.empty((k, self.m), dtype=B.dtype, device=B.device)
+        _check(lib().rtproj_lstsq(self.handle, _ptr(B), B.stride(0), k, _ptr(X), X.stride(0)))
+        return X
+
+    def project_all(self, B, Z=None, Y=None, X=None, want=(True, True, True)):
+        import torch
+        k = self._rhs(B)
+        if want[0] and Z is None:
+            Z = torch.empty_like(B)
+        if want[1] and Y is None:
+            Y = torch.empty_like(B)
+        if want[2] and X is None:
+            X = torch.empty((k, self.m), dtype=B.dtype, device=B.device)
+        _check(lib().rtproj_project_all(self.handle, _ptr(B), B.stride(0), k,
+                                        _ptr(Z), Z.stride(0) if Z is not None else 0,
+                                        _ptr(Y), Y.stride(0) if Y is not None else 0,
+                                        _ptr(X), X.stride(0) if X is not None else 0))
+        return Z, Y, X
+
+    def info(self) -> dict:
+        inf = _Info()
+        _check(lib().rtproj_plan_info(self.handle, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in _Info._fields_}
+
+    def export(self):
+        """Device copies of S (m x l), R (m x m), piv (m), L (m x m)."""
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        S = torch.empty((self.m, self.l), dtype=torch.float64, device=dev)
+        R = torch.empty((self.m, self.m), dtype=torch.float64, device=dev)
+        piv = torch.empty(self.m, dtype=torch.int32, device=dev)
+        L = torch.empty((self.m, self.m), dtype=torch.float64, device=dev)
+        _check(lib().rtproj_plan_export(self.handle, _ptr(S), self.l, _ptr(R), _ptr(piv), _ptr(L)))
+        return dict(S=S, R=R, piv=piv, L=L)
+
+    def sketch_tables(self) -> dict:
+        import numpy as np
+        dims = np.zeros(3, dtype=np.int64)
+        _check(lib().rtproj_sketch_tables(self.handle, dims.ctypes.data, None, None, None, None))
+        np_, n1, n2 = (int(v) for v in dims)
+        sign = np.empty(np_, dtype=np.int8)
+        sigma = np.empty(n1, dtype=np.int32)
+        tau = np.empty(n2, dtype=np.int32)
+        J = np.empty(self.l, dtype=np.int32)
+        _check(lib().rtproj_sketch_tables(self.handle, None, sign.ctypes.data, sigma.ctypes.data,
+                                          tau.ctypes.data, J.ctypes.data))
+        return dict(np=np_, n1=n1, n2=n2, sign=sign, sigma=sigma, tau=tau, J=J)

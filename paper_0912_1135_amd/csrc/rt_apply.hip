@@ -1,0 +1,291 @@
+// The projection: the seven steps of Sec. 4 applied to blocks of k right-hand
+// sides, and the refinement of the least-squares solution (Remark 4.3).
+//
+//   c = A b                          ab_partial + ab_reduce   (step 1)
+//   h = Pi^T R^{-1} L^{-T} L^{-1} R^{-T} Pi c                (steps 2-6)
+//                                    apply_minv, with T' = L^{-1} R^{-T} Pi
+//                                    stored explicitly: h = T'^T (T' c)
+//   b~ = A^T h, z = b - b~           atx                      (step 7)
+//
+// Refinement: r = b - A^T x and s = A r are accumulated with Dot2 (error-free
+// products and sums, i.e. about twice binary64 precision) and x is kept as an
+// unevaluated pair (x_hi, x_lo).  The contractions over the long dimension n
+// are VALU kernels that stream A once per pass with coalesced loads; the
+// right-hand-side blocks are small and staged through LDS.
+#include "rt_common.h"
+
+namespace rt {
+
+namespace {
+
+constexpr int AB_RB = 32;   // rows of A per block
+constexpr int AB_TC = 64;   // columns of A per LDS stage
+constexpr int AB_KJ = 16;   // right-hand sides per block
+
+// part[s][j][row] = sum_{t in split s} A[row][t] * B[t][j] (column-major m x k
+// per split).  dd: Dot2 accumulation, hi in part_hi and error in part_lo.
+template <bool DD>
+__global__ __launch_bounds__(256) void ab_partial_kernel(ApplyArgs a, const double *B, int64_t ldb, int splits,
+                                                         double *part_hi, double *part_lo)
+{
+    __shared__ double As[AB_RB][AB_TC + 1];
+    __shared__ double Bs[AB_TC][AB_KJ];
+    const int r0 = blockIdx.x * AB_RB;
+    const int split = blockIdx.y;
+    const int j0 = blockIdx.z * AB_KJ;
+    const int64_t len = ((int64_t)a.n + splits - 1) / splits;
+    const int64_t t0 = (int64_t)split * len;
+    const int64_t t1 = min<int64_t>(a.n, t0 + len);
+    const int tid = threadIdx.x;
+    // two outputs per thread: (row, j) = (o / 16, o % 16), o = tid, tid + 256
+    double s[2] = {0.0, 0.0}, c[2] = {0.0, 0.0};
+    for (int64_t tb = t0; tb < t1; tb += AB_TC) {
+        for (int e = tid; e < AB_RB * AB_TC; e += 256) {
+            const int rr = e / AB_TC, tt = e % AB_TC;
+            const int64_t t = tb + tt;
+            const int row = r0 + rr;
+            As[rr][tt] = (row < a.m && t < t1) ? a.A[(int64_t)row * a.lda + t] : 0.0;
+        }
+        for (int e = tid; e < AB_TC * AB_KJ; e += 256) {
+            const int jj = e / AB_TC, tt = e % AB_TC;
+            const int64_t t = tb + tt;
+            const int j = j0 + jj;
+            Bs[tt][jj] = (j < a.k && t < t1) ? B[(int64_t)j * ldb + t] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int o = tid + 256 * q;
+            const int rr = o >> 4, jj = o & 15;
+            double sq = s[q], cq = c[q];
+#pragma unroll 8
+            for (int tt = 0; tt < AB_TC; ++tt) {
+                if (DD) dot2_acc(As[rr][tt], Bs[tt][jj], sq, cq);
+                else sq = __builtin_fma(As[rr][tt], Bs[tt][jj], sq);
+            }
+            s[q] = sq;
+            c[q] = cq;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int o = tid + 256 * q;
+        const int row = r0 + (o >> 4), j = j0 + (o & 15);
+        if (row < a.m && j < a.k) {
+            const int64_t idx = (int64_t)split * a.m * a.k + (int64_t)j * a.m + row;
+            part_hi[idx] = s[q];
+            if (DD) part_lo[idx] = c[q];
+        }
+    }
+}
+
+__global__ void ab_reduce_kernel(const double *ph, const double *pl, int m, int k, int splits, int dd, double *out,
+                                 int64_t ldo)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)m * k) return;
+    const int j = (int)(e / m), row = (int)(e % m);
+    double s = 0.0, c = 0.0;
+    for (int p = 0; p < splits; ++p) {
+        const int64_t idx = (int64_t)p * m * k + e;
+        if (dd) {
+            double t, err;
+            two_sum(s, ph[idx], t, err);
+            s = t;
+            c += err + pl[idx];
+        } else {
+            s += ph[idx];
+        }
+    }
+    out[(int64_t)j * ldo + row] = s + c;
+}
+
+constexpr int ATX_T = 256;  // columns t of A per block (one per thread)
+constexpr int ATX_MC = 64;  // rows of x staged in LDS at a time
+
+// y(t, j) = sum_i A[i][t] (xhi[i][j] + xlo[i][j]); then
+//   mode 0: R = round(B - y)
+//   mode 1: Y = round(y), Z = round(B - y)
+template <bool DD>
+__global__ __launch_bounds__(ATX_T) void atx_kernel(ApplyArgs a, const double *xhi, const double *xlo, int64_t ldx,
+                                                    const double *B, int64_t ldb, double *Rout, int64_t ldr,
+                                                    double *Y, int64_t ldy, double *Z, int64_t ldz)
+{
+    __shared__ double xh[ATX_MC][AB_KJ];
+    __shared__ double xl[ATX_MC][AB_KJ];
+    const int64_t t = (int64_t)blockIdx.x * ATX_T + threadIdx.x;
+    const int j0 = blockIdx.y * AB_KJ;
+    const int kj = min(AB_KJ, a.k - j0);
+    double s[AB_KJ], c[AB_KJ];
+#pragma unroll
+    for (int j = 0; j < AB_KJ; ++j) { s[j] = 0.0; c[j] = 0.0; }
+    const bool active = t < a.n;
+    for (int i0 = 0; i0 < a.m; i0 += ATX_MC) {
+        const int mc = min(ATX_MC, a.m - i0);
+        for (int e = threadIdx.x; e < ATX_MC * AB_KJ; e += ATX_T) {
+            const int ii = e / AB_KJ, jj = e % AB_KJ;
+            const bool ok = ii < mc && jj < kj;
+            xh[ii][jj] = ok ? xhi[(int64_t)(j0 + jj) * ldx + i0 + ii] : 0.0;
+            xl[ii][jj] = (ok && DD && xlo) ? xlo[(int64_t)(j0 + jj) * ldx + i0 + ii] : 0.0;
+        }
+        __syncthreads();
+        if (active) {
+            for (int ii = 0; ii < mc; ++ii) {
+                const double av = a.A[(int64_t)(i0 + ii) * a.lda + t];
+#pragma unroll
+                for (int j = 0; j < AB_KJ; ++j) {
+                    if (DD) {
+                        dot2_acc(av, xh[ii][j], s[j], c[j]);
+                        c[j] = __builtin_fma(av, xl[ii][j], c[j]);
+                    } else {
+                        s[j] = __builtin_fma(av, xh[ii][j], s[j]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (!active) return;
+    for (int j = 0; j < kj; ++j) {
+        const int col = j0 + j;
+        double zr = 0.0;
+        if (B) {
+            double d, e;
+            two_sum(B[(int64_t)col * ldb + t], -s[j], d, e);
+            zr = d + (e - c[j]);
+        }
+        if (Rout) Rout[(int64_t)col * ldr + t] = zr;
+        if (Y) Y[(int64_t)col * ldy + t] = s[j] + c[j];
+        if (Z) Z[(int64_t)col * ldz + t] = zr;
+    }
+}
+
+// out(i, j) = sum_r M[r*m + i] * V[r + j*ldv]  (out = M^T V, M row-major m x m)
+__global__ __launch_bounds__(256) void mtv_kernel(const double *M, int m, const double *V, int64_t ldv, double *out,
+                                                  int64_t ldo)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= m) return;
+    const double *v = V + (int64_t)j * ldv;
+    double s0 = 0.0, s1 = 0.0;
+    int r = 0;
+    for (; r + 1 < m; r += 2) {
+        s0 = __builtin_fma(M[(int64_t)r * m + i], v[r], s0);
+        s1 = __builtin_fma(M[(int64_t)(r + 1) * m + i], v[r + 1], s1);
+    }
+    if (r < m) s0 = __builtin_fma(M[(int64_t)r * m + i], v[r], s0);
+    out[(int64_t)j * ldo + i] = s0 + s1;
+}
+
+__global__ __launch_bounds__(256) void dd_update_kernel(double *xhi, double *xlo, const double *D, int total,
+                                                        double *norms)
+{
+    __shared__ double r0[256], r1[256];
+    double nd = 0.0, nx = 0.0;
+    for (int e = threadIdx.x; e < total; e += 256) {
+        const double d = D[e];
+        double s, err;
+        two_sum(xhi[e], d, s, err);
+        const double lo = xlo[e] + err;
+        const double hi = s + lo;
+        xlo[e] = lo - (hi - s);
+        xhi[e] = hi;
+        nd += d * d;
+        nx += hi * hi;
+    }
+    r0[threadIdx.x] = nd;
+    r1[threadIdx.x] = nx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            r0[threadIdx.x] += r0[threadIdx.x + s];
+            r1[threadIdx.x] += r1[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        norms[0] = r0[0];
+        norms[1] = r1[0];
+    }
+}
+
+__global__ void copy_cols_kernel(const double *src, int64_t lds, double *dst, int64_t ldd, int rows, int cols,
+                                 double *zero_out, int64_t ldz)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)rows * cols) return;
+    const int j = (int)(e / rows), i = (int)(e % rows);
+    dst[(int64_t)j * ldd + i] = src[(int64_t)j * lds + i];
+    if (zero_out) zero_out[(int64_t)j * ldz + i] = 0.0;
+}
+
+}  // namespace
+
+hipError_t ab_partial_f64(const ApplyArgs &a, const double *B, int64_t ldb, int splits, double *part_hi,
+                          double *part_lo, int dd, hipStream_t stream)
+{
+    dim3 grid((a.m + AB_RB - 1) / AB_RB, splits, (a.k + AB_KJ - 1) / AB_KJ);
+    if (dd) hipLaunchKernelGGL(ab_partial_kernel<true>, grid, dim3(256), 0, stream, a, B, ldb, splits, part_hi, part_lo);
+    else hipLaunchKernelGGL(ab_partial_kernel<false>, grid, dim3(256), 0, stream, a, B, ldb, splits, part_hi, part_lo);
+    return hipGetLastError();
+}
+
+hipError_t ab_reduce_f64(const double *part_hi, const double *part_lo, int m, int k, int splits, int dd, double *out,
+                         int64_t ldo, hipStream_t stream)
+{
+    const int64_t total = (int64_t)m * k;
+    hipLaunchKernelGGL(ab_reduce_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, part_hi, part_lo,
+                       m, k, splits, dd, out, ldo);
+    return hipGetLastError();
+}
+
+hipError_t atx_f64(const ApplyArgs &a, const double *Xhi, const double *Xlo, int64_t ldx, const double *B,
+                   int64_t ldb, double *Rout, int64_t ldr, double *Y, int64_t ldy, double *Z, int64_t ldz, int dd,
+                   hipStream_t stream)
+{
+    dim3 grid((unsigned)((a.n + ATX_T - 1) / ATX_T), (a.k + AB_KJ - 1) / AB_KJ);
+    if (dd)
+        hipLaunchKernelGGL(atx_kernel<true>, grid, dim3(ATX_T), 0, stream, a, Xhi, Xlo, ldx, B, ldb, Rout, ldr, Y, ldy,
+                           Z, ldz);
+    else
+        hipLaunchKernelGGL(atx_kernel<false>, grid, dim3(ATX_T), 0, stream, a, Xhi, Xlo, ldx, B, ldb, Rout, ldr, Y,
+                           ldy, Z, ldz);
+    return hipGetLastError();
+}
+
+hipError_t apply_minv_f64(const double *T, int64_t ldt, const int32_t *piv, int m, int k, const double *C, int64_t ldc,
+                          double *tmp, double *H, int64_t ldh, hipStream_t stream)
+{
+    // T holds T'^T (row-major), i.e. T'(i, r) = T[r*m + i]; H = T'^T (T' C).
+    // tmp = T' C: tmp(i, j) = sum_r T'(i, r) C(r, j) = sum_r T[r*m + i] C(r, j)
+    (void)ldt;
+    (void)piv;
+    dim3 grid((m + 255) / 256, k);
+    hipLaunchKernelGGL(mtv_kernel, grid, dim3(256), 0, stream, T, m, C, ldc, tmp, (int64_t)m);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // H(i, j) = sum_r T'(r, i) tmp(r, j) = sum_r T'[r*m + i] ...: needs T' row-major,
+    // which is stored right after T'^T.
+    hipLaunchKernelGGL(mtv_kernel, grid, dim3(256), 0, stream, T + (int64_t)m * m, m, tmp, (int64_t)m, H, ldh);
+    return hipGetLastError();
+}
+
+hipError_t dd_update_f64(double *Xhi, double *Xlo, const double *D, int m, int k, double *norms, hipStream_t stream)
+{
+    hipLaunchKernelGGL(dd_update_kernel, dim3(1), dim3(256), 0, stream, Xhi, Xlo, D, m * k, norms);
+    return hipGetLastError();
+}
+
+hipError_t copy_cols_f64(const double *src, int64_t lds, double *dst, int64_t ldd, int rows, int cols,
+                         double *zero_out, int64_t ldz, hipStream_t stream)
+{
+    const int64_t total = (int64_t)rows * cols;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(copy_cols_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, src, lds, dst,
+                       ldd, rows, cols, zero_out, ldz);
+    return hipGetLastError();
+}
+
+}  // namespace rt

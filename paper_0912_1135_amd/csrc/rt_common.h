@@ -1,0 +1,157 @@
+// Internal declarations shared by the gfx950 kernels and the host runtime of
+// the randomized orthogonal projection library.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+
+namespace rt {
+
+// ---------------------------------------------------------------- device
+// Four binary64 accumulators of one lane of a 16x16x4 f64 MFMA.
+typedef double double4v __attribute__((ext_vector_type(4)));
+
+// Output element (row, col) held by lane `lane`, register r of a 16x16 f64
+// MFMA tile: col = lane % 16, row = 4 * (lane / 16) + r.
+__device__ __forceinline__ int mfma16_row(int lane, int r) { return 4 * (lane >> 4) + r; }
+__device__ __forceinline__ int mfma16_col(int lane) { return lane & 15; }
+
+// Error-free transformations (Knuth's TwoSum, FMA-based TwoProd).
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e)
+{
+    s = a + b;
+    double z = s - a;
+    e = (a - (s - z)) + (b - z);
+}
+__device__ __forceinline__ void two_prod(double a, double b, double &p, double &e)
+{
+    p = a * b;
+    e = __builtin_fma(a, b, -p);
+}
+// (s, c) += a*b, with s the running sum and c the accumulated error
+// (Ogita-Rump-Oishi Dot2).
+__device__ __forceinline__ void dot2_acc(double a, double b, double &s, double &c)
+{
+    double p, ep, t, es;
+    two_prod(a, b, p, ep);
+    two_sum(s, p, t, es);
+    s = t;
+    c += ep + es;
+}
+
+// ---------------------------------------------------------------- GEMM
+// C(i,j) = alpha * sum_k A(i,k) B(k,j) + beta * C(i,j), binary64 on MFMA.
+//   A(i,k) = A[ga(i)*a_i + k*a_k], ga(i) = a_gather ? a_gather[i] : i
+//   B(k,j) = B[gb(k)*b_k + j*b_j], gb(k) = b_gather ? b_gather[k] : k
+//   C(i,j) = C[i*c_i + j*c_j] (+ split * c_split for split-K partials)
+// a_lower: A is lower triangular (A(i,k) = 0 for k > i, never read).
+// c_lower: only output tiles on or below the diagonal are computed.
+// ksplit > 1: grid.z = ksplit; each split writes alpha*partial (beta ignored)
+// to C + split*c_split.
+struct GemmArgs {
+    int M, N, K;
+    const double *A; int64_t a_i, a_k; const int32_t *a_gather;
+    const double *B; int64_t b_k, b_j; const int32_t *b_gather;
+    double *C; int64_t c_i, c_j; int64_t c_split;
+    double alpha, beta;
+    int a_lower, c_lower, ksplit;
+};
+
+// Launches GEMM with 64x64 or 128x128 tiles (chosen from M, N).
+hipError_t gemm_f64(const GemmArgs &g, hipStream_t stream);
+
+// out(i,j) = sum_{s<splits} part[s*stride + i*ld + j] for i,j < M x N
+// (row-major, fixed summation order); if mirror, out(j,i) = out(i,j) too and
+// only i >= j is summed.
+hipError_t reduce_splits_f64(const double *part, int64_t stride, int splits, int M, int N,
+                             int64_t ld, double *out, int64_t ldo, int mirror, hipStream_t stream);
+
+// ---------------------------------------------------------------- sketch
+struct SketchTables {
+    int64_t n, np, n1, n2, l;
+    const int8_t *sign;      // np
+    const int32_t *sigma;    // n1
+    const int32_t *tau_inv;  // n2: tau_inv[u] = t2 with tau[t2] = u
+    const double *tw1;       // n1/2 complex (re,im): exp(-2 pi i j / n1)
+    const double *tw2;       // n2/2 complex: exp(-2 pi i j / n2)
+    const double *twh;       // (np / tl) complex: exp(-2 pi i (j*tl) / np)
+    const double *twl;       // tl complex: exp(-2 pi i j / np)
+    int tl_bits;             // log2(tl)
+    const int32_t *sel_off;  // n1/2 + 2 offsets (CSR by k1-pair)
+    const int32_t *sel;      // l entries of (k, part, q) triples
+};
+// S (m x l row-major, lds) = A G for the SRFT; Zbuf holds one row chunk of
+// the intermediate (rows_chunk/2 x np complex binary64).
+hipError_t sketch_f64(const SketchTables &t, const double *A, int64_t lda, int64_t m,
+                      double *S, int64_t lds, double *zbuf, int64_t rows_chunk, hipStream_t stream);
+
+// ---------------------------------------------------------------- pivoted QR
+struct QrcpWork {
+    unsigned *counter;   // grid barrier arrival counter (zeroed by the launcher)
+    unsigned *flag;      // reflector-published flag
+    int *err;            // 1: barrier timeout
+    double *slots;       // 2 * blocks * 2 doubles (norm^2, column)
+    double *vbuf;        // 2 * rows doubles
+    double *scal;        // 2 * 4 doubles (tau, beta, ...)
+};
+// Column-pivoted Householder QR of M = S^T (rows = l, cols = m; column j of M
+// is row j of S, S row-major with ld lds).  R: m x m row-major (upper; the
+// strictly lower part is set to zero).  piv: m int32.
+hipError_t qrcp_f64(const double *S, int64_t lds, int rows, int cols, double *R, int32_t *piv,
+                    const QrcpWork &w, int blocks, size_t lds_bytes_max, hipStream_t stream);
+int qrcp_max_blocks(int rows, int cols, int cu_count, size_t lds_max);
+hipError_t zero_u32(unsigned *p, int n, hipStream_t stream);
+
+// ---------------------------------------------------------------- factor
+// Inverse of each nb x nb diagonal block of the lower-triangular matrix
+// L(i,j) = T[i*t_i + j*t_j] (j <= i), m x m; Dinv: nblk blocks of nb*nb
+// row-major; the tail block is padded with the identity.
+hipError_t tri_diag_inv_f64(const double *T, int64_t t_i, int64_t t_j, int m, int nb,
+                            double *Dinv, hipStream_t stream);
+// Cholesky of the nb x nb (or smaller tail) diagonal block at (b*nb, b*nb) of
+// X (row-major, ldx): writes L's diagonal block into L (row-major, ldl, zeros
+// above) and its inverse into Dinv + b*nb*nb; sets *err = 1 on breakdown.
+hipError_t chol_diag_f64(const double *X, int64_t ldx, int m, int nb, int b, double *L, int64_t ldl,
+                         double *Dinv, int *err, hipStream_t stream);
+// Set a row-major m x n matrix to the identity (or zero if ident = 0).
+hipError_t set_matrix_f64(double *X, int64_t ld, int m, int n, int ident, hipStream_t stream);
+// Zero the strictly upper (upper = 1) or strictly lower part of a row-major m x m matrix.
+hipError_t zero_triangle_f64(double *X, int64_t ld, int m, int upper, hipStream_t stream);
+// out = [T'^T ; T'] (two row-major m x m blocks) with T' = T Pi.
+hipError_t form_tp_f64(const double *T, const int32_t *piv, int m, double *out, hipStream_t stream);
+// |R_11| and |R_mm| of the row-major R (for the rank test), written to out[0..1].
+hipError_t rdiag_ends_f64(const double *R, int64_t ldr, int m, double *out, hipStream_t stream);
+
+// ---------------------------------------------------------------- apply
+// C (m x k, column-major, ldc) partials: P[s] = A(:, split s) * B(split s, :)
+// in binary64 (ddot = 0) or Dot2 (ddot = 1: hi in P, lo in P2).
+struct ApplyArgs {
+    int m, n, k;
+    const double *A; int64_t lda;
+};
+hipError_t ab_partial_f64(const ApplyArgs &a, const double *B, int64_t ldb, int splits,
+                          double *part_hi, double *part_lo, int dd, hipStream_t stream);
+// out (m x k, col-major ldo) = sum of partials (dd: compensated, rounded once).
+hipError_t ab_reduce_f64(const double *part_hi, const double *part_lo, int m, int k, int splits,
+                         int dd, double *out, int64_t ldo, hipStream_t stream);
+// R = B - A^T (Xhi + Xlo) (n x k, col-major), Dot2 over m; mode 0: write
+// r = round(B - A^T x) to Rout; mode 1: write Y = round(A^T x) and
+// Z = round(B - A^T x) (either may be NULL); dd = 0 uses plain binary64 and
+// ignores Xlo.
+hipError_t atx_f64(const ApplyArgs &a, const double *Xhi, const double *Xlo, int64_t ldx,
+                   const double *B, int64_t ldb, double *Rout, int64_t ldr,
+                   double *Y, int64_t ldy, double *Z, int64_t ldz, int dd, hipStream_t stream);
+// H (m x k, col-major) = Pi^T T^T T Pi C  (the seven-step core with
+// P^{-1} = R^{-T} Pi and Y = X^{-1} = L^{-T} L^{-1} folded into T = L^{-1} R^{-T}).
+// tmp: m*k doubles.
+hipError_t apply_minv_f64(const double *T, int64_t ldt, const int32_t *piv, int m, int k,
+                          const double *C, int64_t ldc, double *tmp, double *H, int64_t ldh,
+                          hipStream_t stream);
+// (Xhi, Xlo) += D (double-binary64 update); norms[0] = |D|_F^2, norms[1] = |Xhi|_F^2.
+hipError_t dd_update_f64(double *Xhi, double *Xlo, const double *D, int m, int k, double *norms,
+                         hipStream_t stream);
+// Copy an m x k column-major block (ld -> ld2), optionally zeroing `zero_out`.
+hipError_t copy_cols_f64(const double *src, int64_t lds, double *dst, int64_t ldd, int rows, int cols,
+                         double *zero_out, int64_t ldz, hipStream_t stream);
+
+}  // namespace rt

@@ -1,0 +1,161 @@
+// Binary64 GEMM on the gfx950 matrix cores (v_mfma_f64_16x16x4_f64), LDS-tiled.
+//
+// One kernel serves every dense contraction of the preconditioner: the
+// triangular products with the explicitly inverted factor (P^- of eq. scary),
+// the Gram (P^{-1}A)(P^{-1}A)^T (steps a-e of Sec. 4), the blocked Cholesky
+// updates and the right-looking triangular solves.  256 threads = 4 waves in
+// a 2 x 2 arrangement; each wave owns (BM/2) x (BN/2) of the output as
+// 16 x 16 MFMA tiles; K advances in chunks of 16 staged through LDS.
+#include "rt_common.h"
+
+namespace rt {
+
+namespace {
+
+constexpr int KC = 16;
+
+template <int BM, int BN, bool A_KC, bool B_KC>
+__global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g)
+{
+    __shared__ double As[KC][BM + 1];
+    __shared__ double Bs[KC][BN + 1];
+    constexpr int TM = BM / 32, TN = BN / 32;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+
+    int ti, tj;
+    if (g.c_lower) {
+        const int t = blockIdx.x;
+        ti = (int)((__builtin_sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+        while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+        while (ti * (ti + 1) / 2 > t) --ti;
+        tj = t - ti * (ti + 1) / 2;
+    } else {
+        ti = blockIdx.y;
+        tj = blockIdx.x;
+    }
+    const int i0 = ti * BM, j0 = tj * BN;
+    int kbeg = 0, kend = g.K;
+    if (g.ksplit > 1) {
+        int ks = (g.K + g.ksplit - 1) / g.ksplit;
+        ks = (ks + KC - 1) / KC * KC;
+        kbeg = blockIdx.z * ks;
+        kend = min(g.K, kbeg + ks);
+    }
+    if (g.a_lower) kend = min(kend, i0 + BM);
+
+    double4v acc[TM][TN];
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) acc[a][b] = double4v{0.0, 0.0, 0.0, 0.0};
+
+    for (int k0 = kbeg; k0 < kend; k0 += KC) {
+        // A tile (BM x KC) -> As[k][i]
+        for (int e = tid; e < BM * KC; e += 256) {
+            int ii, kk;
+            if (A_KC) { ii = e / KC; kk = e % KC; } else { ii = e % BM; kk = e / BM; }
+            const int i = i0 + ii, k = k0 + kk;
+            double v = 0.0;
+            if (i < g.M && k < kend && !(g.a_lower && k > i)) {
+                const int64_t gi = g.a_gather ? (int64_t)g.a_gather[i] : (int64_t)i;
+                v = g.A[gi * g.a_i + (int64_t)k * g.a_k];
+            }
+            As[kk][ii] = v;
+        }
+        // B tile (KC x BN) -> Bs[k][j]
+        for (int e = tid; e < BN * KC; e += 256) {
+            int jj, kk;
+            if (B_KC) { jj = e / KC; kk = e % KC; } else { jj = e % BN; kk = e / BN; }
+            const int j = j0 + jj, k = k0 + kk;
+            double v = 0.0;
+            if (j < g.N && k < kend) {
+                const int64_t gk = g.b_gather ? (int64_t)g.b_gather[k] : (int64_t)k;
+                v = g.B[gk * g.b_k + (int64_t)j * g.b_j];
+            }
+            Bs[kk][jj] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < KC; kk += 4) {
+            double av[TM], bv[TN];
+#pragma unroll
+            for (int a = 0; a < TM; ++a) av[a] = As[kk + (lane >> 4)][wm * (BM / 2) + a * 16 + (lane & 15)];
+#pragma unroll
+            for (int b = 0; b < TN; ++b) bv[b] = Bs[kk + (lane >> 4)][wn * (BN / 2) + b * 16 + (lane & 15)];
+#pragma unroll
+            for (int a = 0; a < TM; ++a)
+#pragma unroll
+                for (int b = 0; b < TN; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+
+    double *C = g.C + (g.ksplit > 1 ? (int64_t)blockIdx.z * g.c_split : 0);
+    const bool use_beta = (g.ksplit <= 1) && (g.beta != 0.0);
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + wm * (BM / 2) + a * 16 + mfma16_row(lane, r);
+                const int j = j0 + wn * (BN / 2) + b * 16 + mfma16_col(lane);
+                if (i < g.M && j < g.N) {
+                    double *p = C + (int64_t)i * g.c_i + (int64_t)j * g.c_j;
+                    double v = g.alpha * acc[a][b][r];
+                    if (use_beta) v += g.beta * *p;
+                    *p = v;
+                }
+            }
+}
+
+template <int BM, int BN>
+hipError_t launch_tile(const GemmArgs &g, hipStream_t s)
+{
+    dim3 grid, block(256);
+    const int gm = (g.M + BM - 1) / BM, gn = (g.N + BN - 1) / BN;
+    if (g.c_lower) grid = dim3(gm * (gm + 1) / 2, 1, g.ksplit > 1 ? g.ksplit : 1);
+    else grid = dim3(gn, gm, g.ksplit > 1 ? g.ksplit : 1);
+    const bool akc = (g.a_k == 1), bkc = (g.b_k == 1);
+    if (akc && bkc) hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, true, true>), grid, block, 0, s, g);
+    else if (akc) hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, true, false>), grid, block, 0, s, g);
+    else if (bkc) hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, false, true>), grid, block, 0, s, g);
+    else hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, false, false>), grid, block, 0, s, g);
+    return hipGetLastError();
+}
+
+__global__ void reduce_splits_kernel(const double *part, int64_t stride, int splits, int M, int N,
+                                     int64_t ld, double *out, int64_t ldo, int mirror)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)M * N) return;
+    const int i = (int)(e / N), j = (int)(e % N);
+    if (mirror && j > i) return;
+    double s = 0.0;
+    for (int p = 0; p < splits; ++p) s += part[p * stride + (int64_t)i * ld + j];
+    out[(int64_t)i * ldo + j] = s;
+    if (mirror) out[(int64_t)j * ldo + i] = s;
+}
+
+}  // namespace
+
+hipError_t gemm_f64(const GemmArgs &g, hipStream_t stream)
+{
+    if (g.M <= 0 || g.N <= 0) return hipSuccess;
+    if (g.M >= 128 && g.N >= 128 && !g.a_lower) return launch_tile<128, 128>(g, stream);
+    return launch_tile<64, 64>(g, stream);
+}
+
+hipError_t reduce_splits_f64(const double *part, int64_t stride, int splits, int M, int N, int64_t ld,
+                             double *out, int64_t ldo, int mirror, hipStream_t stream)
+{
+    const int64_t total = (int64_t)M * N;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(reduce_splits_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream,
+                       part, stride, splits, M, N, ld, out, ldo, mirror);
+    return hipGetLastError();
+}
+
+}  // namespace rt

@@ -1,0 +1,639 @@
+// Host runtime and C ABI of the randomized orthogonal projection library
+// (see include/rtproj.h for the contract).
+//
+// Preconditioning (Sec. 4, first two step lists):
+//   1. S = A G, the SRFT sketch of eq. testing              sketch_f64
+//   2. S^T = Q R Pi, eq. QR_decomp                           qrcp_f64 (cooperative)
+//   3. R^{-T}, the transposed P^- of eq. scary               blocked TRSM on MFMA
+//   4. W = P^{-1} A = R^{-T} (Pi A)                          triangular GEMM on MFMA
+//   5. X = W W^T (steps a-e)                                 SYRK on MFMA, split-K
+//   6. X = L L^T (replaces the inverse of eq. inversion)     blocked Cholesky
+//   7. T = L^{-1} R^{-T}, T' = T Pi, so that
+//      (A A^T)^{-1} = Pi^T R^{-1} X^{-1} R^{-T} Pi = T'^T T'
+// Projection (the seven steps of Sec. 4; Remark 4.1; Remark 4.3):
+//   c = A b, x = T'^T (T' c), then refinement steps
+//   x += T'^T T' A (b - A^T x) with Dot2 residuals, then
+//   A^T x (row projection) and b - A^T x (null projection).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rtproj.h"
+#include "rt_common.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+rtproj_status fail(rtproj_status s, const std::string &msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+#define RT_HIP(expr)                                                                                  \
+    do {                                                                                              \
+        hipError_t _e = (expr);                                                                       \
+        if (_e != hipSuccess)                                                                         \
+            return fail(RTPROJ_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));        \
+    } while (0)
+
+constexpr int NB = 64;  // block size of the triangular solves and the Cholesky
+
+// ------------------------------------------------------------ random tables
+// SplitMix64 (Steele, Lea and Flood, 2014): the state advances by the golden
+// ratio increment and each output is the finalizer of the new state.
+struct SplitMix64 {
+    uint64_t s;
+    uint64_t next()
+    {
+        s += 0x9e3779b97f4a7c15ULL;
+        uint64_t z = s;
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+        return z ^ (z >> 31);
+    }
+    // uniform in [0, range): high half of next() * range
+    uint64_t below(uint64_t range) { return (uint64_t)(((unsigned __int128)next() * range) >> 64); }
+};
+
+struct HostTables {
+    int64_t np = 0, n1 = 0, n2 = 0;
+    std::vector<int8_t> sign;
+    std::vector<int32_t> sigma, tau, J;
+};
+
+// Draw order: np signs (top bit set -> -1), Fisher-Yates of sigma over
+// [0, n1) from the top, the same for tau over [0, n2), then the sorted
+// l-subset J of [0, np) by selection sampling.
+void draw_tables(uint64_t seed, int64_t n, int64_t l, HostTables &t)
+{
+    int64_t np = 4;
+    int e = 2;
+    while (np < n) { np <<= 1; ++e; }
+    t.np = np;
+    t.n2 = int64_t(1) << (e / 2);
+    t.n1 = np / t.n2;
+    SplitMix64 g{seed};
+    t.sign.resize(np);
+    for (int64_t i = 0; i < np; ++i) t.sign[i] = (g.next() >> 63) ? int8_t(-1) : int8_t(1);
+    t.sigma.resize(t.n1);
+    for (int64_t i = 0; i < t.n1; ++i) t.sigma[i] = (int32_t)i;
+    for (int64_t j = t.n1 - 1; j >= 1; --j) std::swap(t.sigma[j], t.sigma[g.below((uint64_t)j + 1)]);
+    t.tau.resize(t.n2);
+    for (int64_t i = 0; i < t.n2; ++i) t.tau[i] = (int32_t)i;
+    for (int64_t j = t.n2 - 1; j >= 1; --j) std::swap(t.tau[j], t.tau[g.below((uint64_t)j + 1)]);
+    t.J.clear();
+    t.J.reserve(l);
+    for (int64_t i = 0; i < np && (int64_t)t.J.size() < l; ++i)
+        if ((int64_t)g.below((uint64_t)(np - i)) < l - (int64_t)t.J.size()) t.J.push_back((int32_t)i);
+}
+
+void twiddles(int64_t len, int64_t count, int64_t step, std::vector<double> &out)
+{
+    // out[j] = exp(-2 pi i j*step / len), j < count, from long-double cos/sin
+    out.resize(2 * count);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int64_t j = 0; j < count; ++j) {
+        const long double ang = -2.0L * pi * (long double)((j * step) % len) / (long double)len;
+        out[2 * j] = (double)cosl(ang);
+        out[2 * j + 1] = (double)sinl(ang);
+    }
+}
+
+template <class T>
+hipError_t dalloc(T **p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc((void **)p, count * sizeof(T));
+}
+
+}  // namespace
+
+struct rtproj_plan_s {
+    int64_t m = 0, n = 0, l = 0;
+    uint64_t seed = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int cu_count = 0;
+    size_t lds_max = 0;
+    int precision = RTPROJ_PREC_FP64;
+    int refine_steps = 3;
+    double refine_rtol = 0.0;
+    HostTables tab;
+    // device tables
+    int8_t *d_sign = nullptr;
+    int32_t *d_sigma = nullptr, *d_tauinv = nullptr, *d_sel_off = nullptr, *d_sel = nullptr;
+    double *d_tw1 = nullptr, *d_tw2 = nullptr, *d_twh = nullptr, *d_twl = nullptr;
+    int tl_bits = 0;
+    // preconditioner state
+    double *d_zbuf = nullptr;
+    int64_t rows_chunk = 0;
+    double *d_S = nullptr, *d_R = nullptr, *d_Y = nullptr, *d_W = nullptr, *d_part = nullptr;
+    double *d_G = nullptr, *d_L = nullptr, *d_Tp = nullptr, *d_DinvR = nullptr, *d_DinvL = nullptr;
+    int32_t *d_piv = nullptr;
+    unsigned *d_sync = nullptr;
+    double *d_slots = nullptr, *d_vbuf = nullptr, *d_scal = nullptr, *d_diag = nullptr;
+    int *d_err = nullptr;
+    int qr_blocks = 0;
+    int syrk_splits = 1;
+    // projection workspace
+    int64_t kcap = 0;
+    int ab_splits = 1;
+    double *d_c = nullptr, *d_tmp = nullptr, *d_xhi = nullptr, *d_xlo = nullptr, *d_d = nullptr, *d_r = nullptr;
+    double *d_ph = nullptr, *d_pl = nullptr, *d_norms = nullptr;
+    // borrowed operand
+    const double *A = nullptr;
+    int64_t lda = 0;
+    bool ready = false;
+    rtproj_info info{};
+
+    rt::SketchTables sketch_tables() const
+    {
+        rt::SketchTables t;
+        t.n = n; t.np = tab.np; t.n1 = tab.n1; t.n2 = tab.n2; t.l = l;
+        t.sign = d_sign; t.sigma = d_sigma; t.tau_inv = d_tauinv;
+        t.tw1 = d_tw1; t.tw2 = d_tw2; t.twh = d_twh; t.twl = d_twl; t.tl_bits = tl_bits;
+        t.sel_off = d_sel_off; t.sel = d_sel;
+        return t;
+    }
+};
+
+namespace {
+
+void release(rtproj_plan p)
+{
+    void *bufs[] = {p->d_sign, p->d_sigma, p->d_tauinv, p->d_sel_off, p->d_sel, p->d_tw1, p->d_tw2, p->d_twh,
+                    p->d_twl, p->d_zbuf, p->d_S, p->d_R, p->d_Y, p->d_W, p->d_part, p->d_G, p->d_L, p->d_Tp,
+                    p->d_DinvR, p->d_DinvL, p->d_piv, p->d_sync, p->d_slots, p->d_vbuf, p->d_scal, p->d_diag,
+                    p->d_c, p->d_tmp, p->d_xhi, p->d_xlo, p->d_d, p->d_r, p->d_ph, p->d_pl, p->d_norms, p->d_err};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+}
+
+rtproj_status upload_tables(rtproj_plan p)
+{
+    const HostTables &t = p->tab;
+    const int64_t np = t.np, n1 = t.n1, n2 = t.n2, l = p->l;
+    std::vector<int32_t> tauinv(n2);
+    for (int64_t i = 0; i < n2; ++i) tauinv[t.tau[i]] = (int32_t)i;
+    // selection lists, grouped by the k1-pair w = min(k1, n1 - k1) that owns k
+    std::vector<std::vector<int32_t>> lists(n1 / 2 + 1);
+    for (int64_t q = 0; q < l; ++q) {
+        const int64_t j = t.J[q];
+        int64_t k;
+        int part;
+        if (j == 0) { k = 0; part = 0; }
+        else if (j == 1) { k = np / 2; part = 0; }
+        else { k = j / 2; part = (int)(j % 2); }
+        const int64_t k1 = k % n1;
+        const int64_t w = std::min(k1, n1 - k1);
+        lists[w].push_back((int32_t)k);
+        lists[w].push_back(part);
+        lists[w].push_back((int32_t)q);
+    }
+    std::vector<int32_t> off(n1 / 2 + 2, 0), sel;
+    sel.reserve(3 * l);
+    for (int64_t w = 0; w <= n1 / 2; ++w) {
+        off[w] = (int32_t)(sel.size() / 3);
+        sel.insert(sel.end(), lists[w].begin(), lists[w].end());
+    }
+    off[n1 / 2 + 1] = (int32_t)(sel.size() / 3);
+    int e = 0;
+    while ((int64_t(1) << e) < np) ++e;
+    p->tl_bits = (e + 1) / 2;
+    const int64_t tl = int64_t(1) << p->tl_bits;
+    std::vector<double> tw1, tw2, twh, twl;
+    twiddles(n1, n1 / 2, 1, tw1);
+    twiddles(n2, n2 / 2, 1, tw2);
+    twiddles(np, np / tl, tl, twh);
+    twiddles(np, tl, 1, twl);
+    RT_HIP(dalloc(&p->d_sign, np));
+    RT_HIP(dalloc(&p->d_sigma, n1));
+    RT_HIP(dalloc(&p->d_tauinv, n2));
+    RT_HIP(dalloc(&p->d_sel_off, off.size()));
+    RT_HIP(dalloc(&p->d_sel, sel.size()));
+    RT_HIP(dalloc(&p->d_tw1, tw1.size()));
+    RT_HIP(dalloc(&p->d_tw2, tw2.size()));
+    RT_HIP(dalloc(&p->d_twh, twh.size()));
+    RT_HIP(dalloc(&p->d_twl, twl.size()));
+    RT_HIP(hipMemcpy(p->d_sign, t.sign.data(), np, hipMemcpyHostToDevice));
+    RT_HIP(hipMemcpy(p->d_sigma, t.sigma.data(), n1 * 4, hipMemcpyHostToDevice));
+    RT_HIP(hipMemcpy(p->d_tauinv, tauinv.data(), n2 * 4, hipMemcpyHostToDevice));
+    RT_HIP(hipMemcpy(p->d_sel_off, off.data(), off.size() * 4, hipMemcpyHostToDevice));
+    RT_HIP(hipMemcpy(p->d_sel, sel.data(), sel.size() * 4, hipMemcpyHostToDevice));
+    RT_HIP(hipMemcpy(p->d_tw1, tw1.data(), tw1.size() * 8, hipMemcpyHostToDevice));
+    RT_HIP(hipMemcpy(p->d_tw2, tw2.data(), tw2.size() * 8, hipMemcpyHostToDevice));
+    RT_HIP(hipMemcpy(p->d_twh, twh.data(), twh.size() * 8, hipMemcpyHostToDevice));
+    RT_HIP(hipMemcpy(p->d_twl, twl.data(), twl.size() * 8, hipMemcpyHostToDevice));
+    return RTPROJ_OK;
+}
+
+rtproj_status alloc_state(rtproj_plan p)
+{
+    const int64_t m = p->m, n = p->n, l = p->l, np = p->tab.np;
+    // sketch intermediate: at most ~64 MiB of row pairs at a time
+    int64_t pairs = std::max<int64_t>(1, (int64_t(64) << 20) / (np * 16));
+    p->rows_chunk = std::min<int64_t>(2 * pairs, (m + 1) / 2 * 2);
+    RT_HIP(dalloc(&p->d_zbuf, (size_t)(p->rows_chunk / 2) * np * 2));
+    RT_HIP(dalloc(&p->d_S, (size_t)m * l));
+    RT_HIP(dalloc(&p->d_R, (size_t)m * m));
+    RT_HIP(dalloc(&p->d_Y, (size_t)m * m));
+    RT_HIP(dalloc(&p->d_W, (size_t)m * n));
+    const int gt = (int)((m + 127) / 128);
+    const int tiles = gt * (gt + 1) / 2;
+    p->syrk_splits = (int)std::max<int64_t>(1, std::min<int64_t>({64, (4 * p->cu_count + tiles - 1) / tiles, n / 256}));
+    RT_HIP(dalloc(&p->d_part, (size_t)p->syrk_splits * m * m));
+    RT_HIP(dalloc(&p->d_G, (size_t)m * m));
+    RT_HIP(dalloc(&p->d_L, (size_t)m * m));
+    RT_HIP(dalloc(&p->d_Tp, (size_t)2 * m * m));
+    const int64_t nblk = (m + NB - 1) / NB;
+    RT_HIP(dalloc(&p->d_DinvR, (size_t)nblk * NB * NB));
+    RT_HIP(dalloc(&p->d_DinvL, (size_t)nblk * NB * NB));
+    RT_HIP(dalloc(&p->d_piv, (size_t)m));
+    RT_HIP(dalloc(&p->d_sync, 4));
+    p->qr_blocks = rt::qrcp_max_blocks((int)l, (int)m, p->cu_count, p->lds_max);
+    if (p->qr_blocks <= 0)
+        return fail(RTPROJ_ERR_UNSUPPORTED, "pivoted QR: the sketch's columns do not fit in LDS for this (m, l)");
+    RT_HIP(dalloc(&p->d_slots, (size_t)4 * p->qr_blocks));
+    RT_HIP(dalloc(&p->d_vbuf, (size_t)2 * l));
+    RT_HIP(dalloc(&p->d_scal, 8));
+    RT_HIP(dalloc(&p->d_diag, 8));
+    RT_HIP(dalloc(&p->d_err, 4));
+    return RTPROJ_OK;
+}
+
+rtproj_status ensure_k(rtproj_plan p, int64_t k)
+{
+    if (k <= p->kcap) return RTPROJ_OK;
+    double **bufs[] = {&p->d_c, &p->d_tmp, &p->d_xhi, &p->d_xlo, &p->d_d, &p->d_r, &p->d_ph, &p->d_pl, &p->d_norms};
+    for (double **b : bufs)
+        if (*b) { (void)hipFree(*b); *b = nullptr; }
+    p->kcap = 0;
+    const int64_t m = p->m, n = p->n;
+    const int64_t rb = (m + 31) / 32, kb = (k + 15) / 16;
+    p->ab_splits = (int)std::max<int64_t>(1, std::min<int64_t>(n / 256, (4 * p->cu_count + rb * kb - 1) / (rb * kb)));
+    RT_HIP(dalloc(&p->d_c, (size_t)m * k));
+    RT_HIP(dalloc(&p->d_tmp, (size_t)m * k));
+    RT_HIP(dalloc(&p->d_xhi, (size_t)m * k));
+    RT_HIP(dalloc(&p->d_xlo, (size_t)m * k));
+    RT_HIP(dalloc(&p->d_d, (size_t)m * k));
+    RT_HIP(dalloc(&p->d_r, (size_t)n * k));
+    RT_HIP(dalloc(&p->d_ph, (size_t)p->ab_splits * m * k));
+    RT_HIP(dalloc(&p->d_pl, (size_t)p->ab_splits * m * k));
+    RT_HIP(dalloc(&p->d_norms, 4));
+    p->kcap = k;
+    return RTPROJ_OK;
+}
+
+// In-place blocked forward substitution L X = B for the m x m lower-triangular
+// L(i,j) = Lp[i*l_i + j*l_j] with inverted diagonal blocks Dinv; B (row-major
+// m x ncols, ld ldb) is overwritten by X.  rhs_lower: B is lower triangular
+// (then so is X, and the columns right of each block stay zero).
+rtproj_status trsm_lower(rtproj_plan p, const double *Lp, int64_t l_i, int64_t l_j, const double *Dinv, double *B,
+                         int64_t ldb, int64_t m, int64_t ncols, bool rhs_lower)
+{
+    const int64_t nblk = (m + NB - 1) / NB;
+    for (int64_t b = 0; b < nblk; ++b) {
+        const int64_t r0 = b * NB, nbb = std::min<int64_t>(NB, m - r0);
+        const int64_t cols = rhs_lower ? std::min<int64_t>(ncols, r0 + nbb) : ncols;
+        rt::GemmArgs g{};
+        g.M = (int)nbb; g.N = (int)cols; g.K = (int)nbb;
+        g.A = Dinv + b * NB * NB; g.a_i = NB; g.a_k = 1;
+        g.B = B + r0 * ldb; g.b_k = ldb; g.b_j = 1;
+        g.C = B + r0 * ldb; g.c_i = ldb; g.c_j = 1;
+        g.alpha = 1.0; g.beta = 0.0; g.ksplit = 1;
+        RT_HIP(rt::gemm_f64(g, p->stream));
+        const int64_t rest = m - r0 - nbb;
+        if (rest <= 0) continue;
+        rt::GemmArgs u{};
+        u.M = (int)rest; u.N = (int)cols; u.K = (int)nbb;
+        u.A = Lp + (r0 + nbb) * l_i + r0 * l_j; u.a_i = l_i; u.a_k = l_j;
+        u.B = B + r0 * ldb; u.b_k = ldb; u.b_j = 1;
+        u.C = B + (r0 + nbb) * ldb; u.c_i = ldb; u.c_j = 1;
+        u.alpha = -1.0; u.beta = 1.0; u.ksplit = 1;
+        RT_HIP(rt::gemm_f64(u, p->stream));
+    }
+    return RTPROJ_OK;
+}
+
+rtproj_status cholesky(rtproj_plan p)
+{
+    const int64_t m = p->m;
+    const int64_t nblk = (m + NB - 1) / NB;
+    RT_HIP(rt::set_matrix_f64(p->d_L, m, (int)m, (int)m, 0, p->stream));
+    for (int64_t b = 0; b < nblk; ++b) {
+        const int64_t r0 = b * NB, nbb = std::min<int64_t>(NB, m - r0);
+        RT_HIP(rt::chol_diag_f64(p->d_G, m, (int)m, NB, (int)b, p->d_L, m, p->d_DinvL, p->d_err, p->stream));
+        const int64_t rest = m - r0 - nbb;
+        if (rest <= 0) continue;
+        // panel: L21 = X21 L11^{-T}
+        rt::GemmArgs g{};
+        g.M = (int)rest; g.N = (int)nbb; g.K = (int)nbb;
+        g.A = p->d_G + (r0 + nbb) * m + r0; g.a_i = m; g.a_k = 1;
+        g.B = p->d_DinvL + b * NB * NB; g.b_k = 1; g.b_j = NB;
+        g.C = p->d_L + (r0 + nbb) * m + r0; g.c_i = m; g.c_j = 1;
+        g.alpha = 1.0; g.ksplit = 1;
+        RT_HIP(rt::gemm_f64(g, p->stream));
+        // trailing update: X22 -= L21 L21^T (lower tiles)
+        rt::GemmArgs u{};
+        u.M = (int)rest; u.N = (int)rest; u.K = (int)nbb;
+        u.A = p->d_L + (r0 + nbb) * m + r0; u.a_i = m; u.a_k = 1;
+        u.B = p->d_L + (r0 + nbb) * m + r0; u.b_k = 1; u.b_j = m;
+        u.C = p->d_G + (r0 + nbb) * m + (r0 + nbb); u.c_i = m; u.c_j = 1;
+        u.alpha = -1.0; u.beta = 1.0; u.c_lower = 1; u.ksplit = 1;
+        RT_HIP(rt::gemm_f64(u, p->stream));
+    }
+    return RTPROJ_OK;
+}
+
+bool ld_ok(int64_t ld, int64_t need) { return ld >= need && ld > 0; }
+
+rtproj_status project(rtproj_plan p, const double *B, int64_t ldb, int64_t k, double *Z, int64_t ldz, double *Y,
+                      int64_t ldy, double *X, int64_t ldx)
+{
+    if (!p) return fail(RTPROJ_ERR_INVALID_ARG, "null plan");
+    if (k < 0) return fail(RTPROJ_ERR_INVALID_ARG, "k < 0");
+    if (k == 0) return RTPROJ_OK;
+    if (!B) return fail(RTPROJ_ERR_INVALID_ARG, "B is NULL");
+    if (!ld_ok(ldb, p->n)) return fail(RTPROJ_ERR_INVALID_ARG, "ldb < n");
+    if (Z && !ld_ok(ldz, p->n)) return fail(RTPROJ_ERR_INVALID_ARG, "ldz < n");
+    if (Y && !ld_ok(ldy, p->n)) return fail(RTPROJ_ERR_INVALID_ARG, "ldy < n");
+    if (X && !ld_ok(ldx, p->m)) return fail(RTPROJ_ERR_INVALID_ARG, "ldx < m");
+    if ((Z == B && ldz != ldb) || (Y == B && ldy != ldb))
+        return fail(RTPROJ_ERR_INVALID_ARG, "an output aliases B with a different leading dimension");
+    if (!p->ready) return fail(RTPROJ_ERR_STATE, "project called before a successful rtproj_precondition");
+    rtproj_status st = ensure_k(p, k);
+    if (st != RTPROJ_OK) return st;
+    const int64_t m = p->m, n = p->n;
+    hipStream_t s = p->stream;
+    rt::ApplyArgs a{(int)m, (int)n, (int)k, p->A, p->lda};
+    const double *T = p->d_Tp;
+    // step 1: c = A b
+    RT_HIP(rt::ab_partial_f64(a, B, ldb, p->ab_splits, p->d_ph, p->d_pl, 0, s));
+    RT_HIP(rt::ab_reduce_f64(p->d_ph, p->d_pl, (int)m, (int)k, p->ab_splits, 0, p->d_c, m, s));
+    // steps 2-6: x = Pi^T R^{-1} Y R^{-T} Pi c
+    RT_HIP(rt::apply_minv_f64(T, m, p->d_piv, (int)m, (int)k, p->d_c, m, p->d_tmp, p->d_xhi, m, s));
+    RT_HIP(rt::set_matrix_f64(p->d_xlo, m, (int)k, (int)m, 0, s));
+    int steps = 0;
+    double ratio = 0.0;
+    for (int it = 0; it < p->refine_steps; ++it) {
+        RT_HIP(rt::atx_f64(a, p->d_xhi, p->d_xlo, m, B, ldb, p->d_r, n, nullptr, 0, nullptr, 0, 1, s));
+        RT_HIP(rt::ab_partial_f64(a, p->d_r, n, p->ab_splits, p->d_ph, p->d_pl, 1, s));
+        RT_HIP(rt::ab_reduce_f64(p->d_ph, p->d_pl, (int)m, (int)k, p->ab_splits, 1, p->d_c, m, s));
+        RT_HIP(rt::apply_minv_f64(T, m, p->d_piv, (int)m, (int)k, p->d_c, m, p->d_tmp, p->d_d, m, s));
+        RT_HIP(rt::dd_update_f64(p->d_xhi, p->d_xlo, p->d_d, (int)m, (int)k, p->d_norms, s));
+        ++steps;
+        if (p->refine_rtol > 0.0) {
+            double nrm[2];
+            RT_HIP(hipMemcpyAsync(nrm, p->d_norms, 16, hipMemcpyDeviceToHost, s));
+            RT_HIP(hipStreamSynchronize(s));
+            ratio = nrm[1] > 0 ? std::sqrt(nrm[0] / nrm[1]) : 0.0;
+            if (ratio <= p->refine_rtol) break;
+        }
+    }
+    // step 7: b~ = A^T x, z = b - b~
+    if (Z || Y)
+        RT_HIP(rt::atx_f64(a, p->d_xhi, p->d_xlo, m, B, ldb, nullptr, 0, Y, ldy, Z, ldz, steps > 0 ? 1 : 0, s));
+    if (X) RT_HIP(rt::copy_cols_f64(p->d_xhi, m, X, ldx, (int)m, (int)k, nullptr, 0, s));
+    p->info.refine_steps = steps;
+    p->info.refine_last_ratio = ratio;
+    return RTPROJ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *rtproj_status_string(rtproj_status s)
+{
+    switch (s) {
+    case RTPROJ_OK: return "ok";
+    case RTPROJ_ERR_INVALID_ARG: return "invalid argument";
+    case RTPROJ_ERR_ALLOC: return "device allocation failed";
+    case RTPROJ_ERR_DEVICE: return "device error";
+    case RTPROJ_ERR_STATE: return "plan not preconditioned";
+    case RTPROJ_ERR_RANK: return "matrix numerically rank deficient";
+    case RTPROJ_ERR_NOCONV: return "refinement did not converge";
+    case RTPROJ_ERR_UNSUPPORTED: return "unsupported size or mode";
+    }
+    return "unknown status";
+}
+
+const char *rtproj_last_error(void) { return g_last_error.c_str(); }
+
+rtproj_status rtproj_plan_create(int64_t m, int64_t n, int64_t l, uint64_t seed, rtproj_plan *out)
+{
+    if (!out) return fail(RTPROJ_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (m < 1 || n < m || l < m || l > n)
+        return fail(RTPROJ_ERR_INVALID_ARG, "sizes must satisfy 1 <= m <= l <= n");
+    if (n > (int64_t(1) << 30) || m > 32768)
+        return fail(RTPROJ_ERR_UNSUPPORTED, "n above 2^30 or m above 32768");
+    rtproj_plan p = new (std::nothrow) rtproj_plan_s();
+    if (!p) return fail(RTPROJ_ERR_ALLOC, "host allocation failed");
+    p->m = m; p->n = n; p->l = l; p->seed = seed;
+    hipError_t e = hipGetDevice(&p->device);
+    hipDeviceProp_t prop;
+    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, p->device);
+    if (e != hipSuccess) {
+        delete p;
+        return fail(RTPROJ_ERR_DEVICE, std::string("hipGetDeviceProperties: ") + hipGetErrorString(e));
+    }
+    p->cu_count = prop.multiProcessorCount;
+    p->lds_max = prop.sharedMemPerBlock;
+    draw_tables(seed, n, l, p->tab);
+    rtproj_status st = upload_tables(p);
+    if (st == RTPROJ_OK) st = alloc_state(p);
+    if (st != RTPROJ_OK) {
+        release(p);
+        delete p;
+        return st == RTPROJ_ERR_DEVICE ? fail(RTPROJ_ERR_ALLOC, g_last_error) : st;
+    }
+    p->info.m = m; p->info.n = n; p->info.l = l; p->info.np = p->tab.np;
+    p->info.precision = p->precision;
+    p->info.qrcp_blocks = p->qr_blocks;
+    *out = p;
+    return RTPROJ_OK;
+}
+
+rtproj_status rtproj_plan_destroy(rtproj_plan p)
+{
+    if (!p) return RTPROJ_OK;
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    else (void)hipDeviceSynchronize();
+    release(p);
+    delete p;
+    return RTPROJ_OK;
+}
+
+rtproj_status rtproj_plan_set_stream(rtproj_plan p, void *stream)
+{
+    if (!p) return fail(RTPROJ_ERR_INVALID_ARG, "null plan");
+    p->stream = (hipStream_t)stream;
+    return RTPROJ_OK;
+}
+
+rtproj_status rtproj_plan_set_precision(rtproj_plan p, int precision)
+{
+    if (!p) return fail(RTPROJ_ERR_INVALID_ARG, "null plan");
+    if (precision != RTPROJ_PREC_FP64)
+        return fail(RTPROJ_ERR_UNSUPPORTED, "only RTPROJ_PREC_FP64 is available in this build");
+    p->precision = precision;
+    p->info.precision = precision;
+    return RTPROJ_OK;
+}
+
+rtproj_status rtproj_plan_set_refinement(rtproj_plan p, int max_steps, double rtol)
+{
+    if (!p) return fail(RTPROJ_ERR_INVALID_ARG, "null plan");
+    if (max_steps < 0 || max_steps > 64 || !(rtol >= 0.0))
+        return fail(RTPROJ_ERR_INVALID_ARG, "max_steps must be in [0, 64] and rtol >= 0");
+    p->refine_steps = max_steps;
+    p->refine_rtol = rtol;
+    return RTPROJ_OK;
+}
+
+rtproj_status rtproj_precondition(rtproj_plan p, const double *A, int64_t lda)
+{
+    if (!p) return fail(RTPROJ_ERR_INVALID_ARG, "null plan");
+    if (!A) return fail(RTPROJ_ERR_INVALID_ARG, "A is NULL");
+    if (lda < p->n) return fail(RTPROJ_ERR_INVALID_ARG, "lda < n");
+    p->ready = false;
+    p->A = A;
+    p->lda = lda;
+    const int64_t m = p->m, n = p->n, l = p->l;
+    hipStream_t s = p->stream;
+    // 1. sketch
+    RT_HIP(rt::sketch_f64(p->sketch_tables(), A, lda, m, p->d_S, l, p->d_zbuf, p->rows_chunk, s));
+    // 2. pivoted QR of S^T
+    RT_HIP(rt::set_matrix_f64(p->d_R, m, (int)m, (int)m, 0, s));
+    rt::QrcpWork w;
+    w.counter = p->d_sync;
+    w.flag = p->d_sync + 1;
+    w.err = reinterpret_cast<int *>(p->d_sync + 2);
+    w.slots = p->d_slots;
+    w.vbuf = p->d_vbuf;
+    w.scal = p->d_scal;
+    RT_HIP(rt::qrcp_f64(p->d_S, l, (int)l, (int)m, p->d_R, p->d_piv, w, p->qr_blocks, p->lds_max, s));
+    RT_HIP(rt::rdiag_ends_f64(p->d_R, m, (int)m, p->d_diag, s));
+    double diag[4];
+    unsigned sync[4];
+    RT_HIP(hipMemcpyAsync(diag, p->d_diag, 32, hipMemcpyDeviceToHost, s));
+    RT_HIP(hipMemcpyAsync(sync, p->d_sync, 16, hipMemcpyDeviceToHost, s));
+    RT_HIP(hipStreamSynchronize(s));
+    if (sync[2] == 2) return fail(RTPROJ_ERR_RANK, "pivoted QR: no finite pivot (A contains NaN or Inf)");
+    if (sync[2] != 0) return fail(RTPROJ_ERR_DEVICE, "pivoted QR: cooperative barrier timed out");
+    p->info.rdiag_min = diag[2];
+    p->info.kappa_est = diag[2] > 0 ? diag[3] / diag[2] : INFINITY;
+    if (!(diag[2] > (double)m * std::ldexp(1.0, -52) * diag[3]))
+        return fail(RTPROJ_ERR_RANK, "pivoted QR of the sketch: |R_mm| <= m eps |R_11| (rank deficient A)");
+    // 3. R^{-T} (lower) by forward substitution on the identity
+    RT_HIP(rt::tri_diag_inv_f64(p->d_R, 1, m, (int)m, NB, p->d_DinvR, s));
+    RT_HIP(rt::set_matrix_f64(p->d_Y, m, (int)m, (int)m, 1, s));
+    rtproj_status st = trsm_lower(p, p->d_R, 1, m, p->d_DinvR, p->d_Y, m, m, m, true);
+    if (st != RTPROJ_OK) return st;
+    // 4. W = R^{-T} (Pi A)
+    {
+        rt::GemmArgs g{};
+        g.M = (int)m; g.N = (int)n; g.K = (int)m;
+        g.A = p->d_Y; g.a_i = m; g.a_k = 1; g.a_lower = 1;
+        g.B = A; g.b_k = lda; g.b_j = 1; g.b_gather = p->d_piv;
+        g.C = p->d_W; g.c_i = n; g.c_j = 1;
+        g.alpha = 1.0; g.ksplit = 1;
+        RT_HIP(rt::gemm_f64(g, s));
+    }
+    // 5. Gram X = W W^T (lower tiles, split over n, fixed-order reduction)
+    {
+        rt::GemmArgs g{};
+        g.M = (int)m; g.N = (int)m; g.K = (int)n;
+        g.A = p->d_W; g.a_i = n; g.a_k = 1;
+        g.B = p->d_W; g.b_k = 1; g.b_j = n;
+        g.C = p->d_part; g.c_i = m; g.c_j = 1; g.c_split = m * m;
+        g.alpha = 1.0; g.c_lower = 1; g.ksplit = p->syrk_splits;
+        RT_HIP(rt::gemm_f64(g, s));
+        RT_HIP(rt::reduce_splits_f64(p->d_part, m * m, g.ksplit > 1 ? g.ksplit : 1, (int)m, (int)m, m, p->d_G, m, 1, s));
+    }
+    // 6. Cholesky X = L L^T
+    RT_HIP(rt::zero_u32(reinterpret_cast<unsigned *>(p->d_err), 1, s));
+    st = cholesky(p);
+    if (st != RTPROJ_OK) return st;
+    // 7. T = L^{-1} R^{-T} (in place in d_Y), T' = T Pi
+    st = trsm_lower(p, p->d_L, m, 1, p->d_DinvL, p->d_Y, m, m, m, true);
+    if (st != RTPROJ_OK) return st;
+    RT_HIP(rt::form_tp_f64(p->d_Y, p->d_piv, (int)m, p->d_Tp, s));
+    int cerr = 0;
+    RT_HIP(hipMemcpyAsync(&cerr, p->d_err, 4, hipMemcpyDeviceToHost, s));
+    RT_HIP(hipStreamSynchronize(s));
+    if (cerr) return fail(RTPROJ_ERR_RANK, "Cholesky of the preconditioned Gram broke down");
+    p->ready = true;
+    return RTPROJ_OK;
+}
+
+rtproj_status rtproj_project_null(rtproj_plan p, const double *B, int64_t ldb, int64_t k, double *Z, int64_t ldz)
+{
+    if (k > 0 && !Z) return fail(RTPROJ_ERR_INVALID_ARG, "Z is NULL");
+    return project(p, B, ldb, k, Z, ldz, nullptr, 0, nullptr, 0);
+}
+
+rtproj_status rtproj_project_row(rtproj_plan p, const double *B, int64_t ldb, int64_t k, double *Y, int64_t ldy)
+{
+    if (k > 0 && !Y) return fail(RTPROJ_ERR_INVALID_ARG, "Y is NULL");
+    return project(p, B, ldb, k, nullptr, 0, Y, ldy, nullptr, 0);
+}
+
+rtproj_status rtproj_lstsq(rtproj_plan p, const double *B, int64_t ldb, int64_t k, double *X, int64_t ldx)
+{
+    if (k > 0 && !X) return fail(RTPROJ_ERR_INVALID_ARG, "X is NULL");
+    return project(p, B, ldb, k, nullptr, 0, nullptr, 0, X, ldx);
+}
+
+rtproj_status rtproj_project_all(rtproj_plan p, const double *B, int64_t ldb, int64_t k, double *Z, int64_t ldz,
+                                 double *Y, int64_t ldy, double *X, int64_t ldx)
+{
+    return project(p, B, ldb, k, Z, ldz, Y, ldy, X, ldx);
+}
+
+rtproj_status rtproj_plan_info(rtproj_plan p, rtproj_info *out)
+{
+    if (!p || !out) return fail(RTPROJ_ERR_INVALID_ARG, "null argument");
+    RT_HIP(hipStreamSynchronize(p->stream));
+    *out = p->info;
+    return RTPROJ_OK;
+}
+
+rtproj_status rtproj_plan_export(rtproj_plan p, double *S, int64_t lds, double *R, int32_t *piv, double *L)
+{
+    if (!p) return fail(RTPROJ_ERR_INVALID_ARG, "null plan");
+    if (!p->ready) return fail(RTPROJ_ERR_STATE, "plan not preconditioned");
+    if (S && lds < p->l) return fail(RTPROJ_ERR_INVALID_ARG, "lds < l");
+    const int64_t m = p->m;
+    if (S)
+        RT_HIP(hipMemcpy2DAsync(S, lds * 8, p->d_S, p->l * 8, p->l * 8, m, hipMemcpyDeviceToDevice, p->stream));
+    if (R) RT_HIP(hipMemcpyAsync(R, p->d_R, m * m * 8, hipMemcpyDeviceToDevice, p->stream));
+    if (piv) RT_HIP(hipMemcpyAsync(piv, p->d_piv, m * 4, hipMemcpyDeviceToDevice, p->stream));
+    if (L) RT_HIP(hipMemcpyAsync(L, p->d_L, m * m * 8, hipMemcpyDeviceToDevice, p->stream));
+    RT_HIP(hipStreamSynchronize(p->stream));
+    return RTPROJ_OK;
+}
+
+rtproj_status rtproj_sketch_tables(rtproj_plan p, int64_t *dims3, int8_t *sign, int32_t *sigma, int32_t *tau,
+                                   int32_t *J)
+{
+    if (!p) return fail(RTPROJ_ERR_INVALID_ARG, "null plan");
+    const HostTables &t = p->tab;
+    if (dims3) { dims3[0] = t.np; dims3[1] = t.n1; dims3[2] = t.n2; }
+    if (sign) std::memcpy(sign, t.sign.data(), t.sign.size());
+    if (sigma) std::memcpy(sigma, t.sigma.data(), t.sigma.size() * 4);
+    if (tau) std::memcpy(tau, t.tau.data(), t.tau.size() * 4);
+    if (J) std::memcpy(J, t.J.data(), t.J.size() * 4);
+    return RTPROJ_OK;
+}
+
+}  // extern "C"

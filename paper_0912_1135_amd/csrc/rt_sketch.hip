@@ -1,0 +1,193 @@
+// Randomized sketch S = A G (Sec. 4, eq. testing) with G a subsampled
+// randomized Fourier transform: per row a of A, y = Pi D pad(a), Y = FFT(y),
+// keep l entries of the orthonormal real packing of Y, scaled by sqrt(np/l).
+//
+// Two rows are transformed together as one complex signal (real part = row
+// 2p, imaginary part = row 2p+1) and separated after the transform with the
+// conjugate symmetry of real spectra.  The np-point transform is a four-step
+// FFT over the n1 x n2 grid t = t1*n2 + t2, k = k1 + n1*k2:
+//   pass 1: for each column t2: n1-point FFT over t1 (in LDS), times the
+//           twiddle exp(-2 pi i t2 k1 / np);
+//   pass 2: for each k1: n2-point FFT over t2 (in LDS), then unpack the two
+//           real spectra and write only the l selected outputs.
+// The permutation pi(t) = sigma[t1]*n2 + tau[t2] is folded into the loads:
+// a pass-1 block takes the columns t2 = tau^{-1}(u) for a run of u, so each
+// of its n1 gathers reads a contiguous run of A's row (coalesced); the
+// intermediate stays in the tau-image order u and pass 2 places entry u at
+// position tau^{-1}(u) in LDS.
+#include <algorithm>
+
+#include "rt_common.h"
+
+namespace rt {
+
+namespace {
+
+struct cplx { double re, im; };
+
+__device__ __forceinline__ cplx cmul(cplx a, cplx b)
+{
+    return cplx{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+
+__device__ __forceinline__ unsigned bitrev(unsigned x, int bits)
+{
+    return bits == 0 ? 0u : (__builtin_bitreverse32(x) >> (32 - bits));
+}
+
+// In-place radix-2 decimation-in-time FFT of `cols` columns of length `len`
+// stored column after column in LDS (input already in bit-reversed order).
+// tw: len/2 twiddles exp(-2 pi i j / len) in LDS.
+__device__ void lds_fft_cols(cplx *buf, int len, int cols, const cplx *tw)
+{
+    const int half = len >> 1;
+    for (int h = 1; h < len; h <<= 1) {
+        const int stride = half / h;  // twiddle index step: len / (2h)
+        for (int e = threadIdx.x; e < half * cols; e += blockDim.x) {
+            const int c = e / half, q = e - c * half;
+            const int grp = q / h, pos = q - grp * h;
+            const int i0 = grp * 2 * h + pos, i1 = i0 + h;
+            cplx *col = buf + (int64_t)c * len;
+            const cplx w = tw[pos * stride];
+            const cplx a = col[i0];
+            const cplx b = cmul(col[i1], w);
+            col[i0] = cplx{a.re + b.re, a.im + b.im};
+            col[i1] = cplx{a.re - b.re, a.im - b.im};
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void sketch_pass1(SketchTables t, const double *A, int64_t lda, int64_t m,
+                                                    int64_t row0, cplx *zbuf, int tw_cols, int bits1)
+{
+    extern __shared__ cplx smem[];
+    const int n1 = (int)t.n1, n2 = (int)t.n2;
+    cplx *tw = smem;                 // n1/2
+    cplx *buf = smem + (n1 >> 1);    // tw_cols x n1
+    const int64_t pair = blockIdx.y;
+    const int64_t r0 = row0 + 2 * pair, r1 = r0 + 1;
+    const int u0 = blockIdx.x * tw_cols;
+    const cplx *tw1 = reinterpret_cast<const cplx *>(t.tw1);
+    for (int e = threadIdx.x; e < (n1 >> 1); e += blockDim.x) tw[e] = tw1[e];
+    const double *a0 = A + r0 * lda;
+    const double *a1 = A + r1 * lda;
+    const bool has1 = r1 < m;
+    for (int e = threadIdx.x; e < n1 * tw_cols; e += blockDim.x) {
+        const int t1 = e / tw_cols, j = e - t1 * tw_cols;
+        const int64_t src = (int64_t)t.sigma[t1] * n2 + u0 + j;
+        double re = 0.0, im = 0.0;
+        if (src < t.n) {
+            const double s = (double)t.sign[src];
+            re = s * a0[src];
+            if (has1) im = s * a1[src];
+        }
+        buf[(int64_t)j * n1 + bitrev((unsigned)t1, bits1)] = cplx{re, im};
+    }
+    __syncthreads();
+    lds_fft_cols(buf, n1, tw_cols, tw);
+    const cplx *twh = reinterpret_cast<const cplx *>(t.twh);
+    const cplx *twl = reinterpret_cast<const cplx *>(t.twl);
+    const int tl_mask = (1 << t.tl_bits) - 1;
+    cplx *zp = zbuf + pair * t.np;
+    for (int e = threadIdx.x; e < n1 * tw_cols; e += blockDim.x) {
+        const int k1 = e / tw_cols, j = e - k1 * tw_cols;
+        const int t2 = t.tau_inv[u0 + j];
+        const int idx = t2 * k1;  // < np, no reduction needed
+        const cplx w = cmul(twh[idx >> t.tl_bits], twl[idx & tl_mask]);
+        zp[(int64_t)k1 * n2 + u0 + j] = cmul(buf[(int64_t)j * n1 + k1], w);
+    }
+}
+
+__global__ __launch_bounds__(256) void sketch_pass2(SketchTables t, int64_t m, int64_t row0, int64_t npairs,
+                                                    const cplx *zbuf, double *S, int64_t lds, int cp, int bits2)
+{
+    extern __shared__ cplx smem[];
+    const int n1 = (int)t.n1, n2 = (int)t.n2;
+    cplx *tw = smem;               // n2/2
+    cplx *buf = smem + (n2 >> 1);  // cp x 2 x n2
+    const int w = blockIdx.x;      // k1-pair index: ka = w, kb = (n1 - w) % n1
+    const int ka = w, kb = (n1 - w) % n1;
+    const int ncol = (ka == kb) ? 1 : 2;
+    const int64_t p0 = (int64_t)blockIdx.y * cp;
+    const int pc = (int)min<int64_t>(cp, npairs - p0);
+    const cplx *tw2 = reinterpret_cast<const cplx *>(t.tw2);
+    for (int e = threadIdx.x; e < (n2 >> 1); e += blockDim.x) tw[e] = tw2[e];
+    for (int e = threadIdx.x; e < pc * ncol * n2; e += blockDim.x) {
+        const int c = e / n2, u = e - c * n2;
+        const int p = c / ncol, col = c - p * ncol;
+        const int k1 = col == 0 ? ka : kb;
+        const int t2 = t.tau_inv[u];
+        buf[(int64_t)(p * 2 + col) * n2 + bitrev((unsigned)t2, bits2)] = zbuf[(p0 + p) * t.np + (int64_t)k1 * n2 + u];
+    }
+    __syncthreads();
+    // FFT every loaded column; columns are laid out p*2 + col, so transform
+    // 2*pc columns (an unused second column is harmless zero work when ncol = 1).
+    lds_fft_cols(buf, n2, pc * 2, tw);
+    const int beg = t.sel_off[w], cnt = t.sel_off[w + 1] - beg;
+    const double sc1 = 1.0 / __builtin_sqrt((double)t.l);
+    const double sc2 = __builtin_sqrt(2.0) * sc1;
+    const int64_t half = t.np >> 1;
+    for (int e = threadIdx.x; e < cnt * pc; e += blockDim.x) {
+        const int p = e / cnt, s = e - p * cnt;
+        const int32_t *ent = t.sel + 3 * (beg + s);
+        const int64_t k = ent[0];
+        const int part = ent[1], q = ent[2];
+        const int k1 = (int)(k % n1), k2 = (int)(k / n1);
+        const int64_t kp = (t.np - k) % t.np;
+        const int kp1 = (int)(kp % n1), kp2 = (int)(kp / n1);
+        const cplx y = buf[(int64_t)(p * 2 + (k1 == ka ? 0 : 1)) * n2 + k2];
+        const cplx yp = buf[(int64_t)(p * 2 + (kp1 == ka ? 0 : 1)) * n2 + kp2];
+        // spectra of the two real rows: Ya = (Y_k + conj Y_{np-k})/2,
+        // Yb = (Y_k - conj Y_{np-k})/(2i)
+        const double ar = 0.5 * (y.re + yp.re), ai = 0.5 * (y.im - yp.im);
+        const double br = 0.5 * (y.im + yp.im), bi = -0.5 * (y.re - yp.re);
+        const double sc = (k == 0 || k == half) ? sc1 : sc2;
+        const int64_t r0 = row0 + 2 * (p0 + p);
+        S[r0 * lds + q] = sc * (part ? ai : ar);
+        if (r0 + 1 < m) S[(r0 + 1) * lds + q] = sc * (part ? bi : br);
+    }
+}
+
+int ilog2(int64_t v)
+{
+    int b = 0;
+    while ((int64_t(1) << b) < v) ++b;
+    return b;
+}
+
+}  // namespace
+
+hipError_t sketch_f64(const SketchTables &t, const double *A, int64_t lda, int64_t m, double *S, int64_t lds,
+                      double *zbuf, int64_t rows_chunk, hipStream_t stream)
+{
+    const int n1 = (int)t.n1, n2 = (int)t.n2;
+    const int bits1 = ilog2(n1), bits2 = ilog2(n2);
+    int tw_cols = n2 < 16 ? n2 : 16;
+    while (tw_cols > 1 && (int64_t)tw_cols * n1 * 16 > 64 * 1024) tw_cols >>= 1;
+    int cp = (int)((64 * 1024) / (2 * 16 * (int64_t)n2));
+    if (cp < 1) cp = 1;
+    if (cp > 8) cp = 8;
+    const size_t sm1 = (size_t)((n1 >> 1) + (int64_t)tw_cols * n1) * 16;
+    const size_t sm2 = (size_t)((n2 >> 1) + (int64_t)cp * 2 * n2) * 16;
+    cplx *z = reinterpret_cast<cplx *>(zbuf);
+    hipError_t ea = hipFuncSetAttribute((const void *)sketch_pass1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm1);
+    if (ea != hipSuccess) return ea;
+    ea = hipFuncSetAttribute((const void *)sketch_pass2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm2);
+    if (ea != hipSuccess) return ea;
+    for (int64_t row0 = 0; row0 < m; row0 += rows_chunk) {
+        const int64_t rows = std::min<int64_t>(rows_chunk, m - row0);
+        const int64_t npairs = (rows + 1) / 2;
+        hipLaunchKernelGGL(sketch_pass1, dim3(n2 / tw_cols, (unsigned)npairs), dim3(256), sm1, stream, t, A, lda,
+                           m, row0, z, tw_cols, bits1);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(sketch_pass2, dim3(n1 / 2 + 1, (unsigned)((npairs + cp - 1) / cp)), dim3(256), sm2, stream,
+                           t, m, row0, npairs, (const cplx *)z, S, lds, cp, bits2);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace rt

@@ -1,0 +1,55 @@
+"""Host-side checks of the C ABI library (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rtproj.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rtproj_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_symbols()
+    for need in ["rtproj_plan_create", "rtproj_precondition", "rtproj_project_null", "rtproj_project_row",
+                 "rtproj_lstsq", "rtproj_project_all", "rtproj_plan_destroy"]:
+        assert need in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_0912_1135_amd as rt
+    if not os.path.exists(rt.LIB_PATH):
+        pytest.skip("library not built")
+    L = ctypes.CDLL(rt.LIB_PATH)
+    missing = [n for n in declared_symbols() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_status_strings_without_device():
+    import paper_0912_1135_amd as rt
+    if not os.path.exists(rt.LIB_PATH):
+        pytest.skip("library not built")
+    L = rt.lib()
+    for s in range(8):
+        assert L.rtproj_status_string(s).decode()
+    assert L.rtproj_status_string(99).decode() == "unknown status"
+
+
+def test_binding_rejects_bad_arguments_before_device_work():
+    import paper_0912_1135_amd as rt
+    if not os.path.exists(rt.LIB_PATH):
+        pytest.skip("library not built")
+    h = ctypes.c_void_p()
+    # sizes are validated on the host before any HIP call
+    assert rt.lib().rtproj_plan_create(10, 5, 6, 0, ctypes.byref(h)) == 1
+    assert rt.lib().rtproj_plan_create(0, 5, 1, 0, ctypes.byref(h)) == 1
+    assert rt.lib().rtproj_plan_create(4, 10, 11, 0, ctypes.byref(h)) == 1
+    assert rt.lib().rtproj_plan_create(4, 10, 3, 0, ctypes.byref(h)) == 1
+    assert not h.value
+    assert rt.lib().rtproj_project_null(None, None, 0, 1, None, 0) == 1
