@@ -182,6 +182,7 @@ __global__ __launch_bounds__(256) void mtv_kernel(const double *M, int m, const 
 __global__ __launch_bounds__(256) void dd_update_kernel(double *xhi, double *xlo, const double *D, int total,
                                                         double *norms)
 {
+#pragma clang fp contract(off)
     __shared__ double r0[256], r1[256];
     double nd = 0.0, nx = 0.0;
     for (int e = threadIdx.x; e < total; e += 256) {

@@ -11,20 +11,24 @@ namespace rt {
 // Four binary64 accumulators of one lane of a 16x16x4 f64 MFMA.
 typedef double double4v __attribute__((ext_vector_type(4)));
 
-// Output element (row, col) held by lane `lane`, register r of a 16x16 f64
-// MFMA tile: col = lane % 16, row = 4 * (lane / 16) + r.
-__device__ __forceinline__ int mfma16_row(int lane, int r) { return 4 * (lane >> 4) + r; }
+// Output element (row, col) held by lane `lane`, register r of a 16x16x4 f64
+// MFMA tile: col = lane % 16, row = lane / 16 + 4 * r (measured on gfx950).
+__device__ __forceinline__ int mfma16_row(int lane, int r) { return (lane >> 4) + 4 * r; }
 __device__ __forceinline__ int mfma16_col(int lane) { return lane & 15; }
 
-// Error-free transformations (Knuth's TwoSum, FMA-based TwoProd).
+// Error-free transformations (Knuth's TwoSum, FMA-based TwoProd).  FMA
+// contraction is switched off inside them: fusing the rounded product into a
+// following sum would break the error-free property.
 __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e)
 {
+#pragma clang fp contract(off)
     s = a + b;
     double z = s - a;
     e = (a - (s - z)) + (b - z);
 }
 __device__ __forceinline__ void two_prod(double a, double b, double &p, double &e)
 {
+#pragma clang fp contract(off)
     p = a * b;
     e = __builtin_fma(a, b, -p);
 }
@@ -32,6 +36,7 @@ __device__ __forceinline__ void two_prod(double a, double b, double &p, double &
 // (Ogita-Rump-Oishi Dot2).
 __device__ __forceinline__ void dot2_acc(double a, double b, double &s, double &c)
 {
+#pragma clang fp contract(off)
     double p, ep, t, es;
     two_prod(a, b, p, ep);
     two_sum(s, p, t, es);
