@@ -81,6 +81,14 @@ typedef struct {
     int refine_steps;          /* refinement steps taken by the last projection     */
     double refine_last_ratio;  /* |dx| / |x| of the last refinement step             */
     int qrcp_blocks;           /* workgroups of the cooperative pivoted QR           */
+    /* Per-stage device time, accumulated since rtproj_plan_set_timing(plan, 1),
+     * measured with HIP events on the plan's stream (zero while timing is off).
+     * Stages: 0 sketch, 1 pivoted QR, 2 R^{-T} solve, 3 P^{-1}A product, 4 Gram,
+     * 5 Cholesky, 6 L^{-1}R^{-T} solve, 7 A b, 8 applications of (AA^T)^{-1},
+     * 9 refinement residual b - A^T x, 10 refinement product A r,
+     * 11 final A^T x and b - A^T x, 12..15 unused. */
+    double t_stage_ms[16];
+    int64_t stage_calls[16];
 } rtproj_info;
 
 /*
@@ -146,7 +154,12 @@ rtproj_status rtproj_project_all(rtproj_plan plan, const double *B, int64_t ldb,
                                  double *Z, int64_t ldz, double *Y, int64_t ldy,
                                  double *X, int64_t ldx);
 
-/* Sizes, rank estimate and refinement statistics (synchronises the stream). */
+/* Enable (1, also resets the accumulated stage times) or disable (0) the
+ * per-stage event timing reported in rtproj_info.t_stage_ms. */
+rtproj_status rtproj_plan_set_timing(rtproj_plan plan, int enable);
+
+/* Sizes, rank estimate, refinement and stage-timing statistics (synchronises
+ * the stream). */
 rtproj_status rtproj_plan_info(rtproj_plan plan, rtproj_info *out);
 
 /*

@@ -35,7 +35,11 @@ class _Info(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("l", ctypes.c_int64), ("np", ctypes.c_int64),
                 ("kappa_est", ctypes.c_double), ("rdiag_min", ctypes.c_double), ("precision", ctypes.c_int),
                 ("refine_steps", ctypes.c_int), ("refine_last_ratio", ctypes.c_double),
-                ("qrcp_blocks", ctypes.c_int)]
+                ("qrcp_blocks", ctypes.c_int), ("t_stage_ms", ctypes.c_double * 16),
+                ("stage_calls", ctypes.c_int64 * 16)]
+
+STAGES = ["sketch", "qrcp", "rinv_trsm", "w_gemm", "gram_syrk", "cholesky", "t_trsm", "ab",
+          "minv", "refine_atx", "refine_ab", "final_atx"]
 
 
 def lib():
@@ -58,6 +62,7 @@ def lib():
         L.rtproj_lstsq.argtypes = [vp, vp, i64, i64, vp, i64]
         L.rtproj_project_all.argtypes = [vp, vp, i64, i64, vp, i64, vp, i64, vp, i64]
         L.rtproj_plan_info.argtypes = [vp, ctypes.POINTER(_Info)]
+        L.rtproj_plan_set_timing.argtypes = [vp, ip]
         L.rtproj_plan_export.argtypes = [vp, vp, i64, vp, vp, vp]
         L.rtproj_sketch_tables.argtypes = [vp, vp, vp, vp, vp, vp]
         L.rtproj_status_string.argtypes = [ip]
@@ -66,7 +71,8 @@ def lib():
         for name in ["rtproj_plan_create", "rtproj_plan_destroy", "rtproj_plan_set_stream",
                      "rtproj_plan_set_precision", "rtproj_plan_set_refinement", "rtproj_precondition",
                      "rtproj_project_null", "rtproj_project_row", "rtproj_lstsq", "rtproj_project_all",
-                     "rtproj_plan_info", "rtproj_plan_export", "rtproj_sketch_tables"]:
+                     "rtproj_plan_info", "rtproj_plan_export", "rtproj_sketch_tables",
+                     "rtproj_plan_set_timing"]:
             getattr(L, name).restype = ip
         _lib = L
     return _lib
@@ -171,10 +177,16 @@ class Plan:
                                         _ptr(X), X.stride(0) if X is not None else 0))
         return Z, Y, X
 
+    def set_timing(self, enable: bool):
+        _check(lib().rtproj_plan_set_timing(self.handle, 1 if enable else 0))
+
     def info(self) -> dict:
         inf = _Info()
         _check(lib().rtproj_plan_info(self.handle, ctypes.byref(inf)))
-        return {f: getattr(inf, f) for f, _ in _Info._fields_}
+        d = {f: getattr(inf, f) for f, _ in _Info._fields_ if f not in ("t_stage_ms", "stage_calls")}
+        d["stage_ms"] = {name: inf.t_stage_ms[i] for i, name in enumerate(STAGES)}
+        d["stage_calls"] = {name: inf.stage_calls[i] for i, name in enumerate(STAGES)}
+        return d
 
     def export(self):
         """Device copies of S (m x l), R (m x m), piv (m), L (m x m)."""

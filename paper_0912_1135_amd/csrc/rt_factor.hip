@@ -11,19 +11,24 @@ namespace {
 
 constexpr int NBMAX = 64;
 
-// X = L^{-1} for an nb x nb lower-triangular L in LDS (row-major, ld NBMAX);
-// one thread per column, forward substitution down the column.
+// X = L^{-1} for an nb x nb lower-triangular L in LDS (row-major, ld NBMAX),
+// row by row: X[i][j] = -(sum_{j<=k<i} L[i][k] X[k][j]) / L[i][i] for j < i,
+// X[i][i] = 1/L[i][i].  Four threads share each column's dot product.
 __device__ void lower_inverse_lds(const double *L, double *X, int nb)
 {
-    const int j = threadIdx.x;
-    if (j < nb) {
-        for (int i = 0; i < nb; ++i) {
-            double s = (i == j) ? 1.0 : 0.0;
-            for (int k = j; k < i; ++k) s -= L[i * NBMAX + k] * X[k * NBMAX + j];
-            X[i * NBMAX + j] = (i < j) ? 0.0 : s / L[i * NBMAX + i];
+    const int j = threadIdx.x >> 2, q = threadIdx.x & 3;
+    for (int i = 0; i < nb; ++i) {
+        double s = 0.0;
+        if (j < i)
+            for (int k = j + q; k < i; k += 4) s += L[i * NBMAX + k] * X[k * NBMAX + j];
+        s += __shfl_xor(s, 1, 64);
+        s += __shfl_xor(s, 2, 64);
+        if (q == 0 && j < nb) {
+            const double d = L[i * NBMAX + i];
+            X[i * NBMAX + j] = (j < i) ? -s / d : ((j == i) ? 1.0 / d : 0.0);
         }
+        __syncthreads();
     }
-    __syncthreads();
 }
 
 __global__ __launch_bounds__(256) void tri_diag_inv_kernel(const double *T, int64_t t_i, int64_t t_j, int m, int nb,

@@ -153,6 +153,10 @@ struct rtproj_plan_s {
     int64_t lda = 0;
     bool ready = false;
     rtproj_info info{};
+    // stage timing (HIP events on the plan's stream)
+    bool timing = false;
+    struct StageEvents { int stage; hipEvent_t start, stop; };
+    std::vector<StageEvents> pending;
 
     rt::SketchTables sketch_tables() const
     {
@@ -167,8 +171,47 @@ struct rtproj_plan_s {
 
 namespace {
 
+// Records a start event on construction and a stop event on destruction
+// when the plan's stage timing is enabled.
+struct StageScope {
+    rtproj_plan p;
+    int stage;
+    hipEvent_t start = nullptr, stop = nullptr;
+    StageScope(rtproj_plan plan, int st) : p(plan), stage(st)
+    {
+        if (p->timing && hipEventCreate(&start) == hipSuccess && hipEventCreate(&stop) == hipSuccess)
+            (void)hipEventRecord(start, p->stream);
+    }
+    ~StageScope()
+    {
+        if (start && stop) {
+            (void)hipEventRecord(stop, p->stream);
+            p->pending.push_back({stage, start, stop});
+        }
+    }
+};
+
+void collect_timing(rtproj_plan p)
+{
+    for (auto &e : p->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e.start, e.stop) == hipSuccess) {
+            p->info.t_stage_ms[e.stage] += ms;
+            p->info.stage_calls[e.stage] += 1;
+        }
+        (void)hipEventDestroy(e.start);
+        (void)hipEventDestroy(e.stop);
+    }
+    p->pending.clear();
+}
+
 void release(rtproj_plan p)
 {
+    for (auto &e : p->pending) {
+        (void)hipEventDestroy(e.start);
+        (void)hipEventDestroy(e.stop);
+    }
+    p->pending.clear();
     void *bufs[] = {p->d_sign, p->d_sigma, p->d_tauinv, p->d_sel_off, p->d_sel, p->d_tw1, p->d_tw2, p->d_twh,
                     p->d_twl, p->d_zbuf, p->d_S, p->d_R, p->d_Y, p->d_W, p->d_part, p->d_G, p->d_L, p->d_Tp,
                     p->d_DinvR, p->d_DinvL, p->d_piv, p->d_sync, p->d_slots, p->d_vbuf, p->d_scal, p->d_diag,
@@ -262,7 +305,7 @@ rtproj_status alloc_state(rtproj_plan p)
     if (p->qr_blocks <= 0)
         return fail(RTPROJ_ERR_UNSUPPORTED, "pivoted QR: the sketch's columns do not fit in LDS for this (m, l)");
     RT_HIP(dalloc(&p->d_slots, (size_t)4 * p->qr_blocks));
-    RT_HIP(dalloc(&p->d_vbuf, (size_t)2 * l));
+    RT_HIP(dalloc(&p->d_vbuf, (size_t)2 * p->qr_blocks * l));
     RT_HIP(dalloc(&p->d_scal, 8));
     RT_HIP(dalloc(&p->d_diag, 8));
     RT_HIP(dalloc(&p->d_err, 4));
@@ -355,6 +398,29 @@ rtproj_status cholesky(rtproj_plan p)
 
 bool ld_ok(int64_t ld, int64_t need) { return ld >= need && ld > 0; }
 
+// H = T'^T (T' C) = (A A^T)^{-1} C for an m x k column-major block C: two
+// MFMA GEMMs with the K = m contraction split over blocks and reduced in a
+// fixed order.  d_Tp holds T'^T (row-major) followed by T' (row-major).
+rtproj_status apply_minv(rtproj_plan p, const double *C, int64_t ldc, double *H, int64_t ldh, int64_t k)
+{
+    const int64_t m = p->m;
+    const int splits = (int)std::max<int64_t>(1, std::min<int64_t>(p->ab_splits, (m + 63) / 64));
+    for (int pass = 0; pass < 2; ++pass) {
+        rt::GemmArgs g{};
+        g.M = (int)m; g.N = (int)k; g.K = (int)m;
+        g.A = p->d_Tp + (pass == 0 ? m * m : 0); g.a_i = m; g.a_k = 1;
+        g.B = pass == 0 ? C : p->d_tmp; g.b_k = 1; g.b_j = pass == 0 ? ldc : m;
+        g.C = p->d_ph; g.c_i = 1; g.c_j = m; g.c_split = m * k;
+        g.alpha = 1.0; g.ksplit = splits;
+        RT_HIP(rt::gemm_f64(g, p->stream));
+        // partial s is column-major m x k, i.e. row-major k x m
+        double *out = pass == 0 ? p->d_tmp : H;
+        const int64_t ldo = pass == 0 ? m : ldh;
+        RT_HIP(rt::reduce_splits_f64(p->d_ph, m * k, splits, (int)k, (int)m, m, out, ldo, 0, p->stream));
+    }
+    return RTPROJ_OK;
+}
+
 rtproj_status project(rtproj_plan p, const double *B, int64_t ldb, int64_t k, double *Z, int64_t ldz, double *Y,
                       int64_t ldy, double *X, int64_t ldx)
 {
@@ -374,21 +440,37 @@ rtproj_status project(rtproj_plan p, const double *B, int64_t ldb, int64_t k, do
     const int64_t m = p->m, n = p->n;
     hipStream_t s = p->stream;
     rt::ApplyArgs a{(int)m, (int)n, (int)k, p->A, p->lda};
-    const double *T = p->d_Tp;
     // step 1: c = A b
-    RT_HIP(rt::ab_partial_f64(a, B, ldb, p->ab_splits, p->d_ph, p->d_pl, 0, s));
-    RT_HIP(rt::ab_reduce_f64(p->d_ph, p->d_pl, (int)m, (int)k, p->ab_splits, 0, p->d_c, m, s));
+    {
+        StageScope sc(p, 7);
+        RT_HIP(rt::ab_partial_f64(a, B, ldb, p->ab_splits, p->d_ph, p->d_pl, 0, s));
+        RT_HIP(rt::ab_reduce_f64(p->d_ph, p->d_pl, (int)m, (int)k, p->ab_splits, 0, p->d_c, m, s));
+    }
     // steps 2-6: x = Pi^T R^{-1} Y R^{-T} Pi c
-    RT_HIP(rt::apply_minv_f64(T, m, p->d_piv, (int)m, (int)k, p->d_c, m, p->d_tmp, p->d_xhi, m, s));
-    RT_HIP(rt::set_matrix_f64(p->d_xlo, m, (int)k, (int)m, 0, s));
+    {
+        StageScope sc(p, 8);
+        st = apply_minv(p, p->d_c, m, p->d_xhi, m, k);
+        if (st != RTPROJ_OK) return st;
+        RT_HIP(rt::set_matrix_f64(p->d_xlo, m, (int)k, (int)m, 0, s));
+    }
     int steps = 0;
     double ratio = 0.0;
     for (int it = 0; it < p->refine_steps; ++it) {
-        RT_HIP(rt::atx_f64(a, p->d_xhi, p->d_xlo, m, B, ldb, p->d_r, n, nullptr, 0, nullptr, 0, 1, s));
-        RT_HIP(rt::ab_partial_f64(a, p->d_r, n, p->ab_splits, p->d_ph, p->d_pl, 1, s));
-        RT_HIP(rt::ab_reduce_f64(p->d_ph, p->d_pl, (int)m, (int)k, p->ab_splits, 1, p->d_c, m, s));
-        RT_HIP(rt::apply_minv_f64(T, m, p->d_piv, (int)m, (int)k, p->d_c, m, p->d_tmp, p->d_d, m, s));
-        RT_HIP(rt::dd_update_f64(p->d_xhi, p->d_xlo, p->d_d, (int)m, (int)k, p->d_norms, s));
+        {
+            StageScope sc(p, 9);
+            RT_HIP(rt::atx_f64(a, p->d_xhi, p->d_xlo, m, B, ldb, p->d_r, n, nullptr, 0, nullptr, 0, 1, s));
+        }
+        {
+            StageScope sc(p, 10);
+            RT_HIP(rt::ab_partial_f64(a, p->d_r, n, p->ab_splits, p->d_ph, p->d_pl, 1, s));
+            RT_HIP(rt::ab_reduce_f64(p->d_ph, p->d_pl, (int)m, (int)k, p->ab_splits, 1, p->d_c, m, s));
+        }
+        {
+            StageScope sc(p, 8);
+            st = apply_minv(p, p->d_c, m, p->d_d, m, k);
+            if (st != RTPROJ_OK) return st;
+            RT_HIP(rt::dd_update_f64(p->d_xhi, p->d_xlo, p->d_d, (int)m, (int)k, p->d_norms, s));
+        }
         ++steps;
         if (p->refine_rtol > 0.0) {
             double nrm[2];
@@ -399,8 +481,10 @@ rtproj_status project(rtproj_plan p, const double *B, int64_t ldb, int64_t k, do
         }
     }
     // step 7: b~ = A^T x, z = b - b~
-    if (Z || Y)
+    if (Z || Y) {
+        StageScope sc(p, 11);
         RT_HIP(rt::atx_f64(a, p->d_xhi, p->d_xlo, m, B, ldb, nullptr, 0, Y, ldy, Z, ldz, steps > 0 ? 1 : 0, s));
+    }
     if (X) RT_HIP(rt::copy_cols_f64(p->d_xhi, m, X, ldx, (int)m, (int)k, nullptr, 0, s));
     p->info.refine_steps = steps;
     p->info.refine_last_ratio = ratio;
@@ -511,22 +595,28 @@ rtproj_status rtproj_precondition(rtproj_plan p, const double *A, int64_t lda)
     const int64_t m = p->m, n = p->n, l = p->l;
     hipStream_t s = p->stream;
     // 1. sketch
-    RT_HIP(rt::sketch_f64(p->sketch_tables(), A, lda, m, p->d_S, l, p->d_zbuf, p->rows_chunk, s));
+    {
+        StageScope sc(p, 0);
+        RT_HIP(rt::sketch_f64(p->sketch_tables(), A, lda, m, p->d_S, l, p->d_zbuf, p->rows_chunk, s));
+    }
     // 2. pivoted QR of S^T
-    RT_HIP(rt::set_matrix_f64(p->d_R, m, (int)m, (int)m, 0, s));
-    rt::QrcpWork w;
-    w.counter = p->d_sync;
-    w.flag = p->d_sync + 1;
-    w.err = reinterpret_cast<int *>(p->d_sync + 2);
-    w.slots = p->d_slots;
-    w.vbuf = p->d_vbuf;
-    w.scal = p->d_scal;
-    RT_HIP(rt::qrcp_f64(p->d_S, l, (int)l, (int)m, p->d_R, p->d_piv, w, p->qr_blocks, p->lds_max, s));
-    RT_HIP(rt::rdiag_ends_f64(p->d_R, m, (int)m, p->d_diag, s));
     double diag[4];
     unsigned sync[4];
-    RT_HIP(hipMemcpyAsync(diag, p->d_diag, 32, hipMemcpyDeviceToHost, s));
-    RT_HIP(hipMemcpyAsync(sync, p->d_sync, 16, hipMemcpyDeviceToHost, s));
+    {
+        StageScope sc(p, 1);
+        RT_HIP(rt::set_matrix_f64(p->d_R, m, (int)m, (int)m, 0, s));
+        rt::QrcpWork w;
+        w.counter = p->d_sync;
+        w.flag = p->d_sync + 1;
+        w.err = reinterpret_cast<int *>(p->d_sync + 2);
+        w.slots = p->d_slots;
+        w.vbuf = p->d_vbuf;
+        w.scal = p->d_scal;
+        RT_HIP(rt::qrcp_f64(p->d_S, l, (int)l, (int)m, p->d_R, p->d_piv, w, p->qr_blocks, p->lds_max, s));
+        RT_HIP(rt::rdiag_ends_f64(p->d_R, m, (int)m, p->d_diag, s));
+        RT_HIP(hipMemcpyAsync(diag, p->d_diag, 32, hipMemcpyDeviceToHost, s));
+        RT_HIP(hipMemcpyAsync(sync, p->d_sync, 16, hipMemcpyDeviceToHost, s));
+    }
     RT_HIP(hipStreamSynchronize(s));
     if (sync[2] == 2) return fail(RTPROJ_ERR_RANK, "pivoted QR: no finite pivot (A contains NaN or Inf)");
     if (sync[2] != 0) return fail(RTPROJ_ERR_DEVICE, "pivoted QR: cooperative barrier timed out");
@@ -535,12 +625,17 @@ rtproj_status rtproj_precondition(rtproj_plan p, const double *A, int64_t lda)
     if (!(diag[2] > (double)m * std::ldexp(1.0, -52) * diag[3]))
         return fail(RTPROJ_ERR_RANK, "pivoted QR of the sketch: |R_mm| <= m eps |R_11| (rank deficient A)");
     // 3. R^{-T} (lower) by forward substitution on the identity
-    RT_HIP(rt::tri_diag_inv_f64(p->d_R, 1, m, (int)m, NB, p->d_DinvR, s));
-    RT_HIP(rt::set_matrix_f64(p->d_Y, m, (int)m, (int)m, 1, s));
-    rtproj_status st = trsm_lower(p, p->d_R, 1, m, p->d_DinvR, p->d_Y, m, m, m, true);
+    rtproj_status st;
+    {
+        StageScope sc(p, 2);
+        RT_HIP(rt::tri_diag_inv_f64(p->d_R, 1, m, (int)m, NB, p->d_DinvR, s));
+        RT_HIP(rt::set_matrix_f64(p->d_Y, m, (int)m, (int)m, 1, s));
+        st = trsm_lower(p, p->d_R, 1, m, p->d_DinvR, p->d_Y, m, m, m, true);
+    }
     if (st != RTPROJ_OK) return st;
     // 4. W = R^{-T} (Pi A)
     {
+        StageScope sc(p, 3);
         rt::GemmArgs g{};
         g.M = (int)m; g.N = (int)n; g.K = (int)m;
         g.A = p->d_Y; g.a_i = m; g.a_k = 1; g.a_lower = 1;
@@ -551,6 +646,7 @@ rtproj_status rtproj_precondition(rtproj_plan p, const double *A, int64_t lda)
     }
     // 5. Gram X = W W^T (lower tiles, split over n, fixed-order reduction)
     {
+        StageScope sc(p, 4);
         rt::GemmArgs g{};
         g.M = (int)m; g.N = (int)m; g.K = (int)n;
         g.A = p->d_W; g.a_i = n; g.a_k = 1;
@@ -561,13 +657,19 @@ rtproj_status rtproj_precondition(rtproj_plan p, const double *A, int64_t lda)
         RT_HIP(rt::reduce_splits_f64(p->d_part, m * m, g.ksplit > 1 ? g.ksplit : 1, (int)m, (int)m, m, p->d_G, m, 1, s));
     }
     // 6. Cholesky X = L L^T
-    RT_HIP(rt::zero_u32(reinterpret_cast<unsigned *>(p->d_err), 1, s));
-    st = cholesky(p);
+    {
+        StageScope sc(p, 5);
+        RT_HIP(rt::zero_u32(reinterpret_cast<unsigned *>(p->d_err), 1, s));
+        st = cholesky(p);
+    }
     if (st != RTPROJ_OK) return st;
     // 7. T = L^{-1} R^{-T} (in place in d_Y), T' = T Pi
-    st = trsm_lower(p, p->d_L, m, 1, p->d_DinvL, p->d_Y, m, m, m, true);
+    {
+        StageScope sc(p, 6);
+        st = trsm_lower(p, p->d_L, m, 1, p->d_DinvL, p->d_Y, m, m, m, true);
+        if (st == RTPROJ_OK) RT_HIP(rt::form_tp_f64(p->d_Y, p->d_piv, (int)m, p->d_Tp, s));
+    }
     if (st != RTPROJ_OK) return st;
-    RT_HIP(rt::form_tp_f64(p->d_Y, p->d_piv, (int)m, p->d_Tp, s));
     int cerr = 0;
     RT_HIP(hipMemcpyAsync(&cerr, p->d_err, 4, hipMemcpyDeviceToHost, s));
     RT_HIP(hipStreamSynchronize(s));
@@ -600,10 +702,23 @@ rtproj_status rtproj_project_all(rtproj_plan p, const double *B, int64_t ldb, in
     return project(p, B, ldb, k, Z, ldz, Y, ldy, X, ldx);
 }
 
+rtproj_status rtproj_plan_set_timing(rtproj_plan p, int enable)
+{
+    if (!p) return fail(RTPROJ_ERR_INVALID_ARG, "null plan");
+    RT_HIP(hipStreamSynchronize(p->stream));
+    collect_timing(p);
+    p->timing = enable != 0;
+    if (enable) {
+        for (int i = 0; i < 16; ++i) { p->info.t_stage_ms[i] = 0.0; p->info.stage_calls[i] = 0; }
+    }
+    return RTPROJ_OK;
+}
+
 rtproj_status rtproj_plan_info(rtproj_plan p, rtproj_info *out)
 {
     if (!p || !out) return fail(RTPROJ_ERR_INVALID_ARG, "null argument");
     RT_HIP(hipStreamSynchronize(p->stream));
+    collect_timing(p);
     *out = p->info;
     return RTPROJ_OK;
 }

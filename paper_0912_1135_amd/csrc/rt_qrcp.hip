@@ -3,16 +3,18 @@
 // remaining column with the largest trailing 2-norm (ties: lowest index).
 //
 // One cooperative launch.  Block g owns columns j = g, g + G, g + 2G, ... of
-// S^T and keeps them resident in LDS for the whole factorization.  Each step:
-//   1. every block posts its best candidate (trailing norm^2, column);
+// the input and keeps them resident in LDS for the whole factorization.  Each
+// step costs ONE grid barrier:
+//   1. every block posts its best remaining column (trailing norm^2, index,
+//      and the trailing part of the column itself) to a double-buffered slot;
 //   2. grid barrier;
-//   3. every block reads the G candidates and agrees on the pivot p;
-//   4. p's owner forms the reflector H = I - tau v v^T (v[k] = 1,
-//      beta = -sign(alpha) |x|), writes v, tau, the new column of R and
-//      piv[k], then raises a flag; the other blocks wait for the flag;
-//   5. every block applies H to its remaining columns and, in the same
-//      pass, accumulates the trailing norms for the next step.
-// The norms are recomputed exactly every step (no downdating).  Every wait is
+//   3. every block reads the G candidates, agrees on the pivot p (largest
+//      norm, lowest index) and rebuilds the reflector H = I - tau v v^T
+//      (v[k] = 1, beta = -sign(alpha)|x|) from p's posted column;
+//   4. p's owner writes the new column of R and piv[k];
+//   5. every block applies H to its remaining columns and, in the same pass,
+//      accumulates the trailing norms for the next step.
+// Norms are recomputed exactly every step (no downdating).  Every wait is
 // bounded: a block that spins too long records an error and returns, so the
 // grid always drains.
 #include "rt_common.h"
@@ -31,90 +33,124 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Sum `n` per-thread values across the block; result in out[0..n) (LDS) for
-// all threads after return.
-__device__ void block_sums(double *vals, int n, double *scratch, double *out)
+// Sum over each group of TPC consecutive lanes; every lane of the group gets
+// the result.  Groups wider than a wave combine the wave sums through LDS
+// (`scratch`, one slot per wave) with two block barriers.
+template <int TPC>
+__device__ __forceinline__ double group_sum(double v, double *scratch)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int c = 0; c < n; ++c) {
-        const double s = wave_sum(vals[c]);
-        if (lane == 0) scratch[wave * QR_MAXCOL + c] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x < n) {
+    if constexpr (TPC <= 64) {
+#pragma unroll
+        for (int o = TPC / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        return v;
+    } else {
+        v = wave_sum(v);
+        const int wave = threadIdx.x >> 6, w0 = (wave * 64 / TPC) * (TPC / 64);
+        if ((threadIdx.x & 63) == 0) scratch[wave] = v;
+        __syncthreads();
         double s = 0.0;
-        for (int w = 0; w < QR_THREADS / 64; ++w) s += scratch[w * QR_MAXCOL + threadIdx.x];
-        out[threadIdx.x] = s;
+#pragma unroll
+        for (int w = 0; w < TPC / 64; ++w) s += scratch[w0 + w];
+        __syncthreads();
+        return s;
     }
-    __syncthreads();
 }
 
+__device__ __forceinline__ bool spin_until(unsigned *addr, unsigned target, int *err)
+{
+    long spins = 0;
+    // relaxed polling (no cache invalidation per poll); the caller issues one
+    // acquire fence after the wait
+    while (__hip_atomic_load(addr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > SPIN_LIMIT || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+    }
+    return true;
+}
+
+template <int NC>
 __global__ __launch_bounds__(QR_THREADS) void qrcp_kernel(const double *S, int64_t lds, int rows, int cols,
-                                                          double *R, int32_t *piv, QrcpWork w, int G, int ncol_max)
+                                                          double *R, int32_t *piv, QrcpWork w, int G)
 {
     extern __shared__ double smem[];
-    double *colbuf = smem;                          // ncol_max x rows
-    double *v = smem + (int64_t)ncol_max * rows;    // rows
+    double *colbuf = smem;                     // NC x rows
+    double *v = smem + (int64_t)NC * rows;     // rows
     __shared__ double scratch[(QR_THREADS / 64) * QR_MAXCOL];
     __shared__ double nrm[QR_MAXCOL];
-    __shared__ double dots[QR_MAXCOL];
     __shared__ int done[QR_MAXCOL];
-    __shared__ int s_p, s_abort;
-    __shared__ double s_pn, s_tau;
+    __shared__ int s_p, s_abort, s_best;
+    __shared__ double s_pn;
 
     const int g = blockIdx.x, tid = threadIdx.x;
     int ncol = 0;
-    while (ncol < ncol_max && g + G * ncol < cols) ++ncol;
+    while (ncol < NC && g + G * ncol < cols) ++ncol;
+    // candidate slots: header (norm^2, column) and the column's values
+    double *hdr = w.slots;                 // 2 x G x 2
+    double *cand = w.vbuf;                 // 2 x G x rows
 
     for (int c = 0; c < ncol; ++c) {
         const double *src = S + (int64_t)(g + G * c) * lds;
         for (int i = tid; i < rows; i += QR_THREADS) colbuf[(int64_t)c * rows + i] = src[i];
     }
-    if (tid < QR_MAXCOL) done[tid] = 0;
+    if (tid < QR_MAXCOL) done[tid] = (tid < ncol) ? 0 : 1;
     if (tid == 0) s_abort = 0;
-    double part[QR_MAXCOL];
-    for (int c = 0; c < QR_MAXCOL; ++c) part[c] = 0.0;
     __syncthreads();
-    for (int c = 0; c < ncol; ++c)
-        for (int i = tid; i < rows; i += QR_THREADS) {
-            const double x = colbuf[(int64_t)c * rows + i];
-            part[c] += x * x;
-        }
-    block_sums(part, ncol, scratch, nrm);
+    // each column is owned by a group of TPC = 256/NC consecutive lanes
+    constexpr int TPC = QR_THREADS / NC;
+    const int mc = tid / TPC, mq = tid % TPC;
+    const bool mine = mc < ncol;
+    {
+        double part = 0.0;
+        if (mine)
+            for (int i = mq; i < rows; i += TPC) {
+                const double x = colbuf[(int64_t)mc * rows + i];
+                part += x * x;
+            }
+        part = group_sum<TPC>(part, scratch);
+        if (mine && mq == 0) nrm[mc] = part;
+        __syncthreads();
+    }
 
     for (int k = 0; k < cols; ++k) {
         const int buf = k & 1;
         // 1. post the local candidate
         if (tid == 0) {
             double bn = -1.0;
-            int bj = -1;
+            int bc = -1;
             for (int c = 0; c < ncol; ++c)
-                if (!done[c] && nrm[c] > bn) { bn = nrm[c]; bj = g + G * c; }
-            w.slots[(buf * G + g) * 2 + 0] = bn;
-            w.slots[(buf * G + g) * 2 + 1] = (double)bj;
-            // 2. grid barrier (arrival counter is monotonic across steps)
+                if (!done[c] && nrm[c] > bn) { bn = nrm[c]; bc = c; }
+            s_best = bc;
+            hdr[(buf * G + g) * 2 + 0] = bn;
+            hdr[(buf * G + g) * 2 + 1] = bc >= 0 ? (double)(g + G * bc) : -1.0;
+        }
+        __syncthreads();
+        if (s_best >= 0) {
+            const double *x = colbuf + (int64_t)s_best * rows;
+            double *dst = cand + ((int64_t)buf * G + g) * rows;
+            for (int i = k + tid; i < rows; i += QR_THREADS) dst[i] = x[i];
+        }
+        // every wave's stores are complete before the barrier; one agent-scope
+        // release (L2 write-back) per block then publishes them
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __syncthreads();
+        // 2. grid barrier (arrival counter is monotonic across steps)
+        if (tid == 0) {
             __hip_atomic_fetch_add(w.counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            const unsigned target = (unsigned)(k + 1) * (unsigned)G;
-            long spins = 0;
-            while (__hip_atomic_load(w.counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                __builtin_amdgcn_s_sleep(1);
-                if (++spins > SPIN_LIMIT || __hip_atomic_load(w.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                    __hip_atomic_store(w.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    s_abort = 1;
-                    break;
-                }
-            }
+            if (!spin_until(w.counter, (unsigned)(k + 1) * (unsigned)G, w.err)) s_abort = 1;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         __syncthreads();
         if (s_abort) return;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         // 3. agree on the pivot (wave 0 scans the G candidates)
         if (tid < 64) {
             double bn = -2.0;
             int bj = 0x7fffffff;
             for (int q = tid; q < G; q += 64) {
-                const double n = w.slots[(buf * G + q) * 2 + 0];
-                const int j = (int)w.slots[(buf * G + q) * 2 + 1];
+                const double n = hdr[(buf * G + q) * 2 + 0];
+                const int j = (int)hdr[(buf * G + q) * 2 + 1];
                 if (j >= 0 && (n > bn || (n == bn && j < bj))) { bn = n; bj = j; }
             }
             for (int o = 32; o > 0; o >>= 1) {
@@ -132,77 +168,51 @@ __global__ __launch_bounds__(QR_THREADS) void qrcp_kernel(const double *S, int64
             if (tid == 0 && g == 0) __hip_atomic_store(w.err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return;
         }
+        const double *xp = cand + ((int64_t)buf * G + (p % G)) * rows;
+        const double alpha = xp[k];
+        const double xnorm = __builtin_sqrt(s_pn);
+        double beta, tau, inv;
+        if (xnorm == 0.0) { beta = 0.0; tau = 0.0; inv = 0.0; }
+        else {
+            beta = alpha >= 0.0 ? -xnorm : xnorm;
+            tau = (beta - alpha) / beta;
+            inv = 1.0 / (alpha - beta);
+        }
+        for (int i = k + tid; i < rows; i += QR_THREADS) v[i] = (i == k) ? 1.0 : xp[i] * inv;
+        // 4. owner: column k of R and piv[k]
         if (p % G == g) {
-            // 4. owner: reflector from the trailing part of column p
             const int c = p / G;
-            double *x = colbuf + (int64_t)c * rows;
-            const double alpha = x[k];
-            const double xnorm = __builtin_sqrt(s_pn);
-            double beta, tau, inv;
-            if (xnorm == 0.0) { beta = 0.0; tau = 0.0; inv = 0.0; }
-            else {
-                beta = alpha >= 0.0 ? -xnorm : xnorm;
-                tau = (beta - alpha) / beta;
-                inv = 1.0 / (alpha - beta);
-            }
-            double *vg = w.vbuf + (int64_t)buf * rows;
-            for (int i = k + tid; i < rows; i += QR_THREADS) {
-                const double vi = (i == k) ? 1.0 : x[i] * inv;
-                v[i] = vi;
-                vg[i] = vi;
-            }
+            const double *x = colbuf + (int64_t)c * rows;
             for (int i = tid; i < k; i += QR_THREADS) R[(int64_t)i * cols + k] = x[i];
             if (tid == 0) {
                 R[(int64_t)k * cols + k] = beta;
                 piv[k] = p;
-                w.scal[buf * 4 + 0] = tau;
-                s_tau = tau;
                 done[c] = 1;
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __syncthreads();
-            if (tid == 0) __hip_atomic_store(w.flag, (unsigned)(k + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            if (tid == 0) {
-                long spins = 0;
-                while (__hip_atomic_load(w.flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)(k + 1)) {
-                    __builtin_amdgcn_s_sleep(1);
-                    if (++spins > SPIN_LIMIT || __hip_atomic_load(w.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                        __hip_atomic_store(w.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        s_abort = 1;
-                        break;
-                    }
-                }
-            }
-            __syncthreads();
-            if (s_abort) return;
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            const double *vg = w.vbuf + (int64_t)buf * rows;
-            for (int i = k + tid; i < rows; i += QR_THREADS) v[i] = vg[i];
-            if (tid == 0) s_tau = w.scal[buf * 4 + 0];
         }
         __syncthreads();
         // 5. apply H_k to the remaining owned columns; accumulate next norms
-        const double tau = s_tau;
-        for (int c = 0; c < QR_MAXCOL; ++c) part[c] = 0.0;
-        for (int c = 0; c < ncol; ++c) {
-            if (done[c]) continue;
-            const double *x = colbuf + (int64_t)c * rows;
-            for (int i = k + tid; i < rows; i += QR_THREADS) part[c] += v[i] * x[i];
-        }
-        block_sums(part, ncol, scratch, dots);
-        for (int c = 0; c < QR_MAXCOL; ++c) part[c] = 0.0;
-        for (int c = 0; c < ncol; ++c) {
-            if (done[c]) continue;
-            double *x = colbuf + (int64_t)c * rows;
-            const double f = tau * dots[c];
-            for (int i = k + tid; i < rows; i += QR_THREADS) {
-                const double nx = x[i] - f * v[i];
-                x[i] = nx;
-                if (i > k) part[c] += nx * nx;
+        {
+            const bool act = mine && !done[mc];
+            double *x = colbuf + (int64_t)mc * rows;
+            const int i0 = k + ((mq - k % TPC + TPC) % TPC);
+            double dot = 0.0;
+            if (act)
+                for (int i = i0; i < rows; i += TPC) dot += v[i] * x[i];
+            dot = group_sum<TPC>(dot, scratch);
+            double nn = 0.0;
+            if (act) {
+                const double f = tau * dot;
+                for (int i = i0; i < rows; i += TPC) {
+                    const double nx = x[i] - f * v[i];
+                    x[i] = nx;
+                    if (i > k) nn += nx * nx;
+                }
             }
+            nn = group_sum<TPC>(nn, scratch);
+            if (act && mq == 0) nrm[mc] = nn;
+            __syncthreads();
         }
-        block_sums(part, ncol, scratch, nrm);
     }
 }
 
@@ -212,17 +222,33 @@ __global__ void zero_u32_kernel(unsigned *p, int n)
     if (i < n) p[i] = 0u;
 }
 
+template <int NC>
+hipError_t launch_qrcp(const double *S, int64_t lds, int rows, int cols, double *R, int32_t *piv, const QrcpWork &w,
+                       int G, size_t shmem, hipStream_t stream)
+{
+    hipError_t e = hipFuncSetAttribute((const void *)qrcp_kernel<NC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)shmem);
+    if (e != hipSuccess) return e;
+    QrcpWork wk = w;
+    int rows_ = rows, cols_ = cols, G_ = G;
+    int64_t lds_ = lds;
+    void *args[] = {(void *)&S, (void *)&lds_, (void *)&rows_, (void *)&cols_, (void *)&R, (void *)&piv,
+                    (void *)&wk, (void *)&G_};
+    return hipLaunchCooperativeKernel((const void *)qrcp_kernel<NC>, dim3(G), dim3(QR_THREADS), args,
+                                      (unsigned)shmem, stream);
+}
+
 }  // namespace
 
 int qrcp_max_blocks(int rows, int cols, int cu_count, size_t lds_max)
 {
-    // smallest column count per block that fits LDS, then as many blocks as
-    // there are compute units (one resident block per CU at most).
-    for (int ncol = 1; ncol <= QR_MAXCOL; ++ncol) {
+    // fewest blocks (one barrier participant each) whose columns fit in LDS,
+    // at most one block per compute unit
+    for (int ncol = QR_MAXCOL; ncol >= 1; ncol >>= 1) {
         const size_t need = ((size_t)ncol + 1) * (size_t)rows * sizeof(double) + 4096;
-        if (need > lds_max) return -1;
+        if (need > lds_max) continue;
         const int G = (cols + ncol - 1) / ncol;
-        if (G <= cu_count) return G;
+        return G <= cu_count ? G : -1;
     }
     return -1;
 }
@@ -237,23 +263,21 @@ hipError_t qrcp_f64(const double *S, int64_t lds, int rows, int cols, double *R,
                     int blocks, size_t lds_bytes_max, hipStream_t stream)
 {
     const int G = blocks;
-    const int ncol_max = (cols + G - 1) / G;
-    if (ncol_max > QR_MAXCOL) return hipErrorInvalidValue;
-    const size_t shmem = ((size_t)ncol_max + 1) * (size_t)rows * sizeof(double);
-    if (shmem > lds_bytes_max) return hipErrorInvalidValue;
-    hipError_t e = hipFuncSetAttribute((const void *)qrcp_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)shmem);
+    const int need_cols = (cols + G - 1) / G;
+    int nc = 1;
+    while (nc < need_cols) nc <<= 1;
+    if (nc > QR_MAXCOL) return hipErrorInvalidValue;
+    const size_t shmem = ((size_t)nc + 1) * (size_t)rows * sizeof(double);
+    if (shmem + 4096 > lds_bytes_max) return hipErrorInvalidValue;
+    hipError_t e = zero_u32(w.counter, 4, stream);  // counter, flag, err
     if (e != hipSuccess) return e;
-    // counter, flag and err live in one 4-word block
-    e = zero_u32(w.counter, 4, stream);
-    if (e != hipSuccess) return e;
-    QrcpWork wk = w;
-    int rows_ = rows, cols_ = cols, G_ = G, ncm = ncol_max;
-    int64_t lds_ = lds;
-    void *args[] = {(void *)&S, (void *)&lds_, (void *)&rows_, (void *)&cols_, (void *)&R, (void *)&piv,
-                    (void *)&wk, (void *)&G_, (void *)&ncm};
-    return hipLaunchCooperativeKernel((const void *)qrcp_kernel, dim3(G), dim3(QR_THREADS), args, (unsigned)shmem,
-                                      stream);
+    switch (nc) {
+    case 1: return launch_qrcp<1>(S, lds, rows, cols, R, piv, w, G, shmem, stream);
+    case 2: return launch_qrcp<2>(S, lds, rows, cols, R, piv, w, G, shmem, stream);
+    case 4: return launch_qrcp<4>(S, lds, rows, cols, R, piv, w, G, shmem, stream);
+    case 8: return launch_qrcp<8>(S, lds, rows, cols, R, piv, w, G, shmem, stream);
+    default: return launch_qrcp<16>(S, lds, rows, cols, R, piv, w, G, shmem, stream);
+    }
 }
 
 }  // namespace rt
