@@ -60,7 +60,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", help="c1 or c2 (single-instance binary64 workloads)")
-    ap.add_argument("--refine-steps", type=int, default=3)
+    ap.add_argument("--refine-steps", type=int, default=-1, help="-1: chosen from the pivoted-QR rank estimate")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     args = ap.parse_args()
@@ -151,7 +151,7 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"fp64 plain: A = U diag(sigma) V^T, m={m}, n={n}, sigma log-spaced 1..1/{kappa:g}, "
                                f"l={l}, k={k} Gaussian RHS", "m": m, "n": n, "l": l, "k": k, "kappa": kappa,
-                   "precision": "fp64", "refine_steps": args.refine_steps, "parallelism": "single GPU"},
+                   "precision": "fp64", "refine_steps": info["refine_steps"], "parallelism": "single GPU"},
         "roofline": roof,
         "stages": stages,
         "kappa_est": info["kappa_est"],

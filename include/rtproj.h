@@ -117,7 +117,9 @@ rtproj_status rtproj_plan_set_precision(rtproj_plan plan, int precision);
  * binary64 numbers.  rtol > 0 stops early once |dx| <= rtol |x| (one device-
  * to-host read per step); rtol = 0 runs exactly max_steps steps without any
  * host synchronisation.  max_steps = 0 returns the unrefined projection
- * (the seven steps of Sec. 4 in binary64).  Default: max_steps = 3, rtol = 0.
+ * (the seven steps of Sec. 4 in binary64); max_steps = -1 (the default)
+ * chooses the count from the rank estimate of the pivoted QR: with
+ * rho = 16 u kappa_est the fewest steps s >= 1 with rho^(s+1) <= 1e-14.
  */
 rtproj_status rtproj_plan_set_refinement(rtproj_plan plan, int max_steps, double rtol);
 

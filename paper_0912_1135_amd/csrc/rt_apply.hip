@@ -101,7 +101,7 @@ __global__ void ab_reduce_kernel(const double *ph, const double *pl, int m, int 
     out[(int64_t)j * ldo + row] = s + c;
 }
 
-constexpr int ATX_T = 256;  // columns t of A per block (one per thread)
+constexpr int ATX_T = 128;  // columns t of A per block (one per thread)
 constexpr int ATX_MC = 64;  // rows of x staged in LDS at a time
 
 // y(t, j) = sum_i A[i][t] (xhi[i][j] + xlo[i][j]); then
@@ -131,15 +131,22 @@ __global__ __launch_bounds__(ATX_T) void atx_kernel(ApplyArgs a, const double *x
         }
         __syncthreads();
         if (active) {
-            for (int ii = 0; ii < mc; ++ii) {
-                const double av = a.A[(int64_t)(i0 + ii) * a.lda + t];
+            const double *ap = a.A + (int64_t)i0 * a.lda + t;
+            for (int ii = 0; ii < mc; ii += 8) {
+                // eight loads in flight before the 8 x 16 compensated updates
+                double av[8];
 #pragma unroll
-                for (int j = 0; j < AB_KJ; ++j) {
-                    if (DD) {
-                        dot2_acc(av, xh[ii][j], s[j], c[j]);
-                        c[j] = __builtin_fma(av, xl[ii][j], c[j]);
-                    } else {
-                        s[j] = __builtin_fma(av, xh[ii][j], s[j]);
+                for (int u = 0; u < 8; ++u) av[u] = (ii + u < mc) ? ap[(int64_t)(ii + u) * a.lda] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+#pragma unroll
+                    for (int j = 0; j < AB_KJ; ++j) {
+                        if (DD) {
+                            dot2_acc(av[u], xh[ii + u][j], s[j], c[j]);
+                            c[j] = __builtin_fma(av[u], xl[ii + u][j], c[j]);
+                        } else {
+                            s[j] = __builtin_fma(av[u], xh[ii + u][j], s[j]);
+                        }
                     }
                 }
             }

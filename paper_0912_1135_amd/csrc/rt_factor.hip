@@ -11,78 +11,90 @@ namespace {
 
 constexpr int NBMAX = 64;
 
-// X = L^{-1} for an nb x nb lower-triangular L in LDS (row-major, ld NBMAX),
-// row by row: X[i][j] = -(sum_{j<=k<i} L[i][k] X[k][j]) / L[i][i] for j < i,
-// X[i][i] = 1/L[i][i].  Four threads share each column's dot product.
-__device__ void lower_inverse_lds(const double *L, double *X, int nb)
+constexpr int LDP = NBMAX + 1;  // padded LDS row stride
+
+// X = L^{-1} for the NBMAX x NBMAX lower-triangular L in LDS (row stride LDP).
+// Columns are independent: four lanes own column j = tid/4 and split the dot
+// products of the forward substitution
+//   X[i][j] = -(sum_{j<=k<i} L[i][k] X[k][j]) / L[i][i],  X[j][j] = 1/L[j][j],
+// so no block barrier is needed inside.
+__device__ void lower_inverse_lds(const double *L, double *X)
 {
     const int j = threadIdx.x >> 2, q = threadIdx.x & 3;
-    for (int i = 0; i < nb; ++i) {
+    for (int i = 0; i < NBMAX; ++i) {
         double s = 0.0;
-        if (j < i)
-            for (int k = j + q; k < i; k += 4) s += L[i * NBMAX + k] * X[k * NBMAX + j];
+        if (i > j)
+            for (int k = j + q; k < i; k += 4) s += L[i * LDP + k] * X[k * LDP + j];
         s += __shfl_xor(s, 1, 64);
         s += __shfl_xor(s, 2, 64);
-        if (q == 0 && j < nb) {
-            const double d = L[i * NBMAX + i];
-            X[i * NBMAX + j] = (j < i) ? -s / d : ((j == i) ? 1.0 / d : 0.0);
+        if (q == 0) {
+            const double d = L[i * LDP + i];
+            X[i * LDP + j] = (i > j) ? -s / d : ((i == j) ? 1.0 / d : 0.0);
         }
-        __syncthreads();
+        // the four lanes of a column are in one wave: they see each other's
+        // LDS writes after a wave-level barrier
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+    __syncthreads();
 }
 
 __global__ __launch_bounds__(256) void tri_diag_inv_kernel(const double *T, int64_t t_i, int64_t t_j, int m, int nb,
                                                            double *Dinv)
 {
-    __shared__ double L[NBMAX * NBMAX];
-    __shared__ double X[NBMAX * NBMAX];
+    __shared__ double L[NBMAX * LDP];
+    __shared__ double X[NBMAX * LDP];
     const int b = blockIdx.x;
     const int base = b * nb, nbb = min(nb, m - base);
-    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
-        const int i = e / nb, j = e % nb;
+    for (int e = threadIdx.x; e < NBMAX * NBMAX; e += blockDim.x) {
+        const int i = e / NBMAX, j = e % NBMAX;
         double v;
         if (i < nbb && j < nbb) v = (j <= i) ? T[(int64_t)(base + i) * t_i + (int64_t)(base + j) * t_j] : 0.0;
         else v = (i == j) ? 1.0 : 0.0;
-        L[i * NBMAX + j] = v;
+        L[i * LDP + j] = v;
     }
     __syncthreads();
-    lower_inverse_lds(L, X, nb);
+    lower_inverse_lds(L, X);
     double *out = Dinv + (int64_t)b * nb * nb;
-    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) out[e] = X[(e / nb) * NBMAX + (e % nb)];
+    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) out[e] = X[(e / nb) * LDP + (e % nb)];
 }
 
+// Cholesky of one NBMAX x NBMAX diagonal block (right-looking).  Four lanes
+// own row i = tid/4 and split its columns by c mod 4.
 __global__ __launch_bounds__(256) void chol_diag_kernel(const double *Xg, int64_t ldx, int m, int nb, int b, double *Lg,
                                                         int64_t ldl, double *Dinv, int *err)
 {
-    __shared__ double A[NBMAX * NBMAX];
-    __shared__ double X[NBMAX * NBMAX];
+    __shared__ double A[NBMAX * LDP];
+    __shared__ double X[NBMAX * LDP];
     __shared__ int bad;
     const int base = b * nb, nbb = min(nb, m - base);
-    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
-        const int i = e / nb, j = e % nb;
+    for (int e = threadIdx.x; e < NBMAX * NBMAX; e += blockDim.x) {
+        const int i = e / NBMAX, j = e % NBMAX;
         double v;
         if (i < nbb && j < nbb) v = (j <= i) ? Xg[(int64_t)(base + i) * ldx + base + j] : 0.0;
         else v = (i == j) ? 1.0 : 0.0;
-        A[i * NBMAX + j] = v;
+        A[i * LDP + j] = v;
     }
     if (threadIdx.x == 0) bad = 0;
     __syncthreads();
-    for (int j = 0; j < nb; ++j) {
-        // column j: pivot, scale, then rank-1 update of the trailing lower part
-        const double d = A[j * NBMAX + j];
+    const int i = threadIdx.x >> 2, q = threadIdx.x & 3;
+    for (int j = 0; j < NBMAX; ++j) {
+        const double d = A[j * LDP + j];
         if (!(d > 0.0) || !isfinite(d)) {
             if (threadIdx.x == 0) bad = 1;
             break;
         }
         const double ljj = __builtin_sqrt(d);
         __syncthreads();
-        if (threadIdx.x == 0) A[j * NBMAX + j] = ljj;
-        for (int i = j + 1 + threadIdx.x; i < nb; i += blockDim.x) A[i * NBMAX + j] /= ljj;
+        if (q == 0) {
+            if (i == j) A[j * LDP + j] = ljj;
+            else if (i > j) A[i * LDP + j] /= ljj;
+        }
         __syncthreads();
-        const int rem = nb - j - 1;
-        for (int e = threadIdx.x; e < rem * rem; e += blockDim.x) {
-            const int i = j + 1 + e / rem, c = j + 1 + e % rem;
-            if (c <= i) A[i * NBMAX + c] -= A[i * NBMAX + j] * A[c * NBMAX + j];
+        if (i > j) {
+            const double lij = A[i * LDP + j];
+            for (int c = j + 1 + ((q - (j + 1)) & 3); c <= i; c += 4) A[i * LDP + c] -= lij * A[c * LDP + j];
         }
         __syncthreads();
     }
@@ -91,18 +103,18 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(const double *Xg, int64_
         if (threadIdx.x == 0) atomicExch(err, 1);
         return;
     }
-    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
-        const int i = e / nb, j = e % nb;
-        if (j > i) A[i * NBMAX + j] = 0.0;
+    for (int e = threadIdx.x; e < NBMAX * NBMAX; e += blockDim.x) {
+        const int r = e / NBMAX, c = e % NBMAX;
+        if (c > r) A[r * LDP + c] = 0.0;
     }
     __syncthreads();
     for (int e = threadIdx.x; e < nbb * nbb; e += blockDim.x) {
-        const int i = e / nbb, j = e % nbb;
-        Lg[(int64_t)(base + i) * ldl + base + j] = A[i * NBMAX + j];
+        const int r = e / nbb, c = e % nbb;
+        Lg[(int64_t)(base + r) * ldl + base + c] = A[r * LDP + c];
     }
-    lower_inverse_lds(A, X, nb);
+    lower_inverse_lds(A, X);
     double *out = Dinv + (int64_t)b * nb * nb;
-    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) out[e] = X[(e / nb) * NBMAX + (e % nb)];
+    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) out[e] = X[(e / nb) * LDP + (e % nb)];
 }
 
 __global__ void set_matrix_kernel(double *X, int64_t ld, int m, int n, int ident)
@@ -173,7 +185,7 @@ hipError_t form_tp_f64(const double *T, const int32_t *piv, int m, double *out, 
 
 hipError_t tri_diag_inv_f64(const double *T, int64_t t_i, int64_t t_j, int m, int nb, double *Dinv, hipStream_t stream)
 {
-    if (nb > NBMAX) return hipErrorInvalidValue;
+    if (nb != NBMAX) return hipErrorInvalidValue;
     const int nblk = (m + nb - 1) / nb;
     hipLaunchKernelGGL(tri_diag_inv_kernel, dim3(nblk), dim3(256), 0, stream, T, t_i, t_j, m, nb, Dinv);
     return hipGetLastError();
@@ -182,7 +194,7 @@ hipError_t tri_diag_inv_f64(const double *T, int64_t t_i, int64_t t_j, int m, in
 hipError_t chol_diag_f64(const double *X, int64_t ldx, int m, int nb, int b, double *L, int64_t ldl, double *Dinv,
                          int *err, hipStream_t stream)
 {
-    if (nb > NBMAX) return hipErrorInvalidValue;
+    if (nb != NBMAX) return hipErrorInvalidValue;
     hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(256), 0, stream, X, ldx, m, nb, b, L, ldl, Dinv, err);
     return hipGetLastError();
 }

@@ -14,12 +14,26 @@ namespace {
 
 constexpr int KC = 16;
 
+// LDS layout of an operand tile with MN extent T: a K-contiguous operand is
+// kept MN-major ([T][KC+1], k fastest, as loaded), an MN-contiguous one
+// K-major ([KC][T+16]); both paddings make the coalesced stores and the MFMA
+// operand reads (16 consecutive MN indices x 4 consecutive k per wave)
+// bank-conflict free.
+template <int T, bool KCONTIG>
+struct TileLayout {
+    static constexpr int size = KCONTIG ? T * (KC + 1) : KC * (T + 16);
+    __device__ static int at(int mn, int k) { return KCONTIG ? mn * (KC + 1) + k : k * (T + 16) + mn; }
+};
+
 template <int BM, int BN, bool A_KC, bool B_KC>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g)
 {
-    __shared__ double As[KC][BM + 1];
-    __shared__ double Bs[KC][BN + 1];
+    using LA = TileLayout<BM, A_KC>;
+    using LB = TileLayout<BN, B_KC>;
+    __shared__ double As[2][LA::size];
+    __shared__ double Bs[2][LB::size];
     constexpr int TM = BM / 32, TN = BN / 32;
+    constexpr int NA = BM * KC / 256, NB = BN * KC / 256;  // elements per thread
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
 
@@ -44,52 +58,81 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g)
     }
     if (g.a_lower) kend = min(kend, i0 + BM);
 
-    double4v acc[TM][TN];
+    // element e of this thread's share: (mn, k) of the tile, consecutive
+    // threads along the operand's contiguous dimension
+    auto a_coord = [&](int e, int &ii, int &kk) {
+        const int x = tid + 256 * e;
+        if (A_KC) { ii = x / KC; kk = x % KC; } else { ii = x % BM; kk = x / BM; }
+    };
+    auto b_coord = [&](int e, int &jj, int &kk) {
+        const int x = tid + 256 * e;
+        if (B_KC) { jj = x / KC; kk = x % KC; } else { jj = x % BN; kk = x / BN; }
+    };
+    double ra[NA], rb[NB];
+    auto load = [&](int k0) {
 #pragma unroll
-    for (int a = 0; a < TM; ++a)
-#pragma unroll
-        for (int b = 0; b < TN; ++b) acc[a][b] = double4v{0.0, 0.0, 0.0, 0.0};
-
-    for (int k0 = kbeg; k0 < kend; k0 += KC) {
-        // A tile (BM x KC) -> As[k][i]
-        for (int e = tid; e < BM * KC; e += 256) {
+        for (int e = 0; e < NA; ++e) {
             int ii, kk;
-            if (A_KC) { ii = e / KC; kk = e % KC; } else { ii = e % BM; kk = e / BM; }
+            a_coord(e, ii, kk);
             const int i = i0 + ii, k = k0 + kk;
             double v = 0.0;
             if (i < g.M && k < kend && !(g.a_lower && k > i)) {
                 const int64_t gi = g.a_gather ? (int64_t)g.a_gather[i] : (int64_t)i;
                 v = g.A[gi * g.a_i + (int64_t)k * g.a_k];
             }
-            As[kk][ii] = v;
+            ra[e] = v;
         }
-        // B tile (KC x BN) -> Bs[k][j]
-        for (int e = tid; e < BN * KC; e += 256) {
+#pragma unroll
+        for (int e = 0; e < NB; ++e) {
             int jj, kk;
-            if (B_KC) { jj = e / KC; kk = e % KC; } else { jj = e % BN; kk = e / BN; }
+            b_coord(e, jj, kk);
             const int j = j0 + jj, k = k0 + kk;
             double v = 0.0;
             if (j < g.N && k < kend) {
                 const int64_t gk = g.b_gather ? (int64_t)g.b_gather[k] : (int64_t)k;
                 v = g.B[gk * g.b_k + (int64_t)j * g.b_j];
             }
-            Bs[kk][jj] = v;
+            rb[e] = v;
+        }
+    };
+
+    double4v acc[TM][TN];
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) acc[a][b] = double4v{0.0, 0.0, 0.0, 0.0};
+
+    int buf = 0;
+    if (kbeg < kend) load(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += KC) {
+#pragma unroll
+        for (int e = 0; e < NA; ++e) {
+            int ii, kk;
+            a_coord(e, ii, kk);
+            As[buf][LA::at(ii, kk)] = ra[e];
+        }
+#pragma unroll
+        for (int e = 0; e < NB; ++e) {
+            int jj, kk;
+            b_coord(e, jj, kk);
+            Bs[buf][LB::at(jj, kk)] = rb[e];
         }
         __syncthreads();
+        if (k0 + KC < kend) load(k0 + KC);  // next chunk in flight during the MFMAs
 #pragma unroll
         for (int kk = 0; kk < KC; kk += 4) {
             double av[TM], bv[TN];
 #pragma unroll
-            for (int a = 0; a < TM; ++a) av[a] = As[kk + (lane >> 4)][wm * (BM / 2) + a * 16 + (lane & 15)];
+            for (int a = 0; a < TM; ++a) av[a] = As[buf][LA::at(wm * (BM / 2) + a * 16 + (lane & 15), kk + (lane >> 4))];
 #pragma unroll
-            for (int b = 0; b < TN; ++b) bv[b] = Bs[kk + (lane >> 4)][wn * (BN / 2) + b * 16 + (lane & 15)];
+            for (int b = 0; b < TN; ++b) bv[b] = Bs[buf][LB::at(wn * (BN / 2) + b * 16 + (lane & 15), kk + (lane >> 4))];
 #pragma unroll
             for (int a = 0; a < TM; ++a)
 #pragma unroll
                 for (int b = 0; b < TN; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
         }
-        __syncthreads();
+        buf ^= 1;
     }
 
     double *C = g.C + (g.ksplit > 1 ? (int64_t)blockIdx.z * g.c_split : 0);

@@ -124,7 +124,7 @@ struct rtproj_plan_s {
     int cu_count = 0;
     size_t lds_max = 0;
     int precision = RTPROJ_PREC_FP64;
-    int refine_steps = 3;
+    int refine_steps = -1;  // -1: chosen from the rank estimate of the pivoted QR
     double refine_rtol = 0.0;
     HostTables tab;
     // device tables
@@ -398,6 +398,18 @@ rtproj_status cholesky(rtproj_plan p)
 
 bool ld_ok(int64_t ld, int64_t need) { return ld >= need && ld > 0; }
 
+// Refinement steps when none were requested: the contraction of a step is
+// about c u kappa(A); with kappa_est = max|R_ii| / min|R_ii| from the pivoted
+// QR and a safety factor c = 16, take the fewest steps s >= 1 with
+// rho^(s+1) <= 1e-14 (binary64 accuracy of x with margin), at most 6.
+int auto_refine_steps(double kappa_est)
+{
+    const double rho = std::min(0.5, 16.0 * std::ldexp(1.0, -52) * std::max(1.0, kappa_est));
+    int s = 1;
+    while (s < 6 && std::pow(rho, s + 1) > 1e-14) ++s;
+    return s;
+}
+
 // H = T'^T (T' C) = (A A^T)^{-1} C for an m x k column-major block C: two
 // MFMA GEMMs with the K = m contraction split over blocks and reduced in a
 // fixed order.  d_Tp holds T'^T (row-major) followed by T' (row-major).
@@ -455,7 +467,8 @@ rtproj_status project(rtproj_plan p, const double *B, int64_t ldb, int64_t k, do
     }
     int steps = 0;
     double ratio = 0.0;
-    for (int it = 0; it < p->refine_steps; ++it) {
+    const int nsteps = p->refine_steps >= 0 ? p->refine_steps : auto_refine_steps(p->info.kappa_est);
+    for (int it = 0; it < nsteps; ++it) {
         {
             StageScope sc(p, 9);
             RT_HIP(rt::atx_f64(a, p->d_xhi, p->d_xlo, m, B, ldb, p->d_r, n, nullptr, 0, nullptr, 0, 1, s));
@@ -577,8 +590,8 @@ rtproj_status rtproj_plan_set_precision(rtproj_plan p, int precision)
 rtproj_status rtproj_plan_set_refinement(rtproj_plan p, int max_steps, double rtol)
 {
     if (!p) return fail(RTPROJ_ERR_INVALID_ARG, "null plan");
-    if (max_steps < 0 || max_steps > 64 || !(rtol >= 0.0))
-        return fail(RTPROJ_ERR_INVALID_ARG, "max_steps must be in [0, 64] and rtol >= 0");
+    if (max_steps < -1 || max_steps > 64 || !(rtol >= 0.0))
+        return fail(RTPROJ_ERR_INVALID_ARG, "max_steps must be in [-1, 64] and rtol >= 0");
     p->refine_steps = max_steps;
     p->refine_rtol = rtol;
     return RTPROJ_OK;
