@@ -92,12 +92,13 @@ hipError_t sketch_f64(const SketchTables &t, const double *A, int64_t lda, int64
 
 // ---------------------------------------------------------------- pivoted QR
 struct QrcpWork {
-    unsigned *counter;   // grid barrier arrival counter (zeroed by the launcher)
-    unsigned *flag;      // reflector-published flag
-    int *err;            // 1: barrier timeout
-    double *slots;       // 2 * blocks * 2 doubles (norm^2, column)
-    double *vbuf;        // 2 * rows doubles
-    double *scal;        // 2 * 4 doubles (tau, beta, ...)
+    unsigned *counter;   // published-pivot step flag (zeroed by the launcher)
+    unsigned *flag;      // spare
+    int *err;            // 1: wait timeout, 2: no finite pivot
+    unsigned *arrive;    // blocks: per-block arrival step (zeroed by the launcher)
+    double *slots;       // 2 * blocks * 2 doubles: candidate (norm^2, column)
+    double *vbuf;        // 2 * blocks * rows doubles: candidate columns
+    double *pick;        // 2 * 2 doubles: published (norm^2, column)
 };
 // Column-pivoted Householder QR of M = S^T (rows = l, cols = m; column j of M
 // is row j of S, S row-major with ld lds).  R: m x m row-major (upper; the

@@ -78,6 +78,8 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(const double *Xg, int64_
     }
     if (threadIdx.x == 0) bad = 0;
     __syncthreads();
+    __shared__ double colj[NBMAX];
+    __shared__ double diag[NBMAX];
     const int i = threadIdx.x >> 2, q = threadIdx.x & 3;
     for (int j = 0; j < NBMAX; ++j) {
         const double d = A[j * LDP + j];
@@ -86,15 +88,25 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(const double *Xg, int64_
             break;
         }
         const double ljj = __builtin_sqrt(d);
-        __syncthreads();
-        if (q == 0) {
-            if (i == j) A[j * LDP + j] = ljj;
-            else if (i > j) A[i * LDP + j] /= ljj;
+        // column j of L into its own vector, so the update below reads it
+        // without any dependence on the stores into A.  The diagonal entry is
+        // kept aside (every thread has just read A[j][j]) and stored after
+        // the loop.
+        if (q == 0 && i >= j) {
+            const double lij = (i == j) ? ljj : A[i * LDP + j] / ljj;
+            colj[i] = lij;
+            if (i == j) diag[j] = ljj;
+            else A[i * LDP + j] = lij;
         }
         __syncthreads();
         if (i > j) {
-            const double lij = A[i * LDP + j];
-            for (int c = j + 1 + ((q - (j + 1)) & 3); c <= i; c += 4) A[i * LDP + c] -= lij * A[c * LDP + j];
+            const double lij = colj[i];
+            const int c0 = j + 1 + ((q - (j + 1)) & 3);
+#pragma unroll
+            for (int r = 0; r < NBMAX / 4; ++r) {
+                const int c = c0 + 4 * r;
+                if (c <= i) A[i * LDP + c] -= lij * colj[c];
+            }
         }
         __syncthreads();
     }
@@ -103,6 +115,7 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(const double *Xg, int64_
         if (threadIdx.x == 0) atomicExch(err, 1);
         return;
     }
+    if (threadIdx.x < NBMAX) A[threadIdx.x * LDP + threadIdx.x] = diag[threadIdx.x];
     for (int e = threadIdx.x; e < NBMAX * NBMAX; e += blockDim.x) {
         const int r = e / NBMAX, c = e % NBMAX;
         if (c > r) A[r * LDP + c] = 0.0;

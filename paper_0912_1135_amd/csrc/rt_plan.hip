@@ -304,7 +304,7 @@ rtproj_status alloc_state(rtproj_plan p)
     p->qr_blocks = rt::qrcp_max_blocks((int)l, (int)m, p->cu_count, p->lds_max);
     if (p->qr_blocks <= 0)
         return fail(RTPROJ_ERR_UNSUPPORTED, "pivoted QR: the sketch's columns do not fit in LDS for this (m, l)");
-    RT_HIP(dalloc(&p->d_slots, (size_t)4 * p->qr_blocks));
+    RT_HIP(dalloc(&p->d_slots, (size_t)5 * p->qr_blocks));  // candidates + arrival flags
     RT_HIP(dalloc(&p->d_vbuf, (size_t)2 * p->qr_blocks * l));
     RT_HIP(dalloc(&p->d_scal, 8));
     RT_HIP(dalloc(&p->d_diag, 8));
@@ -622,9 +622,10 @@ rtproj_status rtproj_precondition(rtproj_plan p, const double *A, int64_t lda)
         w.counter = p->d_sync;
         w.flag = p->d_sync + 1;
         w.err = reinterpret_cast<int *>(p->d_sync + 2);
+        w.arrive = reinterpret_cast<unsigned *>(p->d_slots + 4 * p->qr_blocks);
         w.slots = p->d_slots;
         w.vbuf = p->d_vbuf;
-        w.scal = p->d_scal;
+        w.pick = p->d_scal;
         RT_HIP(rt::qrcp_f64(p->d_S, l, (int)l, (int)m, p->d_R, p->d_piv, w, p->qr_blocks, p->lds_max, s));
         RT_HIP(rt::rdiag_ends_f64(p->d_R, m, (int)m, p->d_diag, s));
         RT_HIP(hipMemcpyAsync(diag, p->d_diag, 32, hipMemcpyDeviceToHost, s));
