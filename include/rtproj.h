@@ -67,9 +67,13 @@ typedef enum {
  * solves with R and Pi, and the Cholesky are always binary64). */
 typedef enum {
     RTPROJ_PREC_FP64 = 0,       /* sketch, P^{-1}A and its Gram in binary64           */
-    RTPROJ_PREC_MIXED_FP32 = 1, /* sketch, P^{-1}A and Gram in binary32 (MFMA)        */
-    RTPROJ_PREC_MIXED_BF16 = 2  /* binary32 sketch; Gram from row-scaled bfloat16
-                                   P^{-1}A with binary32 accumulation (MFMA)          */
+    RTPROJ_PREC_MIXED_FP32 = 1, /* binary32 sketch and Gram (binary32 MFMA); P^{-1}A
+                                   in binary32 when kappa_est <= 1e5, else binary64;
+                                   the sketch is redone in binary64 when the Gram's
+                                   Cholesky shows cond(P^{-1}A) > 10                 */
+    RTPROJ_PREC_MIXED_BF16 = 2  /* binary32 sketch; Gram from row-scaled (powers of
+                                   two) bfloat16 P^{-1}A on MFMA with binary32
+                                   accumulation; P^{-1}A as in MIXED_FP32             */
 } rtproj_precision;
 
 typedef struct {
@@ -81,6 +85,11 @@ typedef struct {
     int refine_steps;          /* refinement steps taken by the last projection     */
     double refine_last_ratio;  /* |dx| / |x| of the last refinement step             */
     int qrcp_blocks;           /* workgroups of the cooperative pivoted QR           */
+    int sketch_bits, w_bits, gram_bits; /* precisions used by the last precondition:
+                                   64 binary64, 32 binary32, 16 bfloat16             */
+    int sketch_escalated;      /* 1 if a binary32 sketch was redone in binary64      */
+    double gram_cond_est;      /* max/min diag of the Gram's Cholesky factor, a lower
+                                   bound on cond(P^{-1}A)                            */
     /* Per-stage device time, accumulated since rtproj_plan_set_timing(plan, 1),
      * measured with HIP events on the plan's stream (zero while timing is off).
      * Stages: 0 sketch, 1 pivoted QR, 2 R^{-T} solve, 3 P^{-1}A product, 4 Gram,

@@ -35,7 +35,9 @@ class _Info(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("l", ctypes.c_int64), ("np", ctypes.c_int64),
                 ("kappa_est", ctypes.c_double), ("rdiag_min", ctypes.c_double), ("precision", ctypes.c_int),
                 ("refine_steps", ctypes.c_int), ("refine_last_ratio", ctypes.c_double),
-                ("qrcp_blocks", ctypes.c_int), ("t_stage_ms", ctypes.c_double * 16),
+                ("qrcp_blocks", ctypes.c_int), ("sketch_bits", ctypes.c_int), ("w_bits", ctypes.c_int),
+                ("gram_bits", ctypes.c_int), ("sketch_escalated", ctypes.c_int), ("gram_cond_est", ctypes.c_double),
+                ("t_stage_ms", ctypes.c_double * 16),
                 ("stage_calls", ctypes.c_int64 * 16)]
 
 STAGES = ["sketch", "qrcp", "rinv_trsm", "w_gemm", "gram_syrk", "cholesky", "t_trsm", "ab",

@@ -71,6 +71,29 @@ hipError_t gemm_f64(const GemmArgs &g, hipStream_t stream);
 hipError_t reduce_splits_f64(const double *part, int64_t stride, int splits, int M, int N,
                              int64_t ld, double *out, int64_t ldo, int mirror, hipStream_t stream);
 
+// ---------------------------------------------------------------- reduced precision
+// C(i,j) = alpha * sum_k A(i,k) B(k,j) on binary32 or bfloat16 MFMA with
+// binary32 accumulation.  A/B are read from binary64 (x_dbl = 1) or binary32
+// storage, multiplied by the optional power-of-two scales a_scale[i] /
+// b_scale[j] and rounded; C is written as binary64 (c_dbl = 1) or binary32.
+enum { MX_F32 = 0, MX_BF16 = 1 };
+struct GemmMxArgs {
+    int M, N, K;
+    const void *A; int a_dbl; int64_t a_i, a_k; const int32_t *a_gather; const float *a_scale;
+    const void *B; int b_dbl; int64_t b_k, b_j; const int32_t *b_gather; const float *b_scale;
+    void *C; int c_dbl; int64_t c_i, c_j, c_split;
+    float alpha;
+    int a_lower, c_lower, ksplit;
+};
+hipError_t gemm_mx(const GemmMxArgs &g, int mode, hipStream_t stream);
+// out(i,j) = sum_s part[s*stride + i*ld + j] / (sa[i] sb[j]) in binary64.
+hipError_t reduce_f32_splits(const float *part, int64_t stride, int splits, int M, int N, int64_t ld,
+                             const float *sa, const float *sb, double *out, int64_t ldo, int mirror,
+                             hipStream_t stream);
+// scale[i] = 2^-e, e = exponent of max_j |W_ij| (row-major m x n).
+hipError_t row_pow2_scale(const void *W, int is_dbl, int64_t ldw, int m, int n, float *scale, hipStream_t stream);
+hipError_t to_f32(const double *src, int64_t lds, float *dst, int64_t ldd, int m, int64_t n, hipStream_t stream);
+
 // ---------------------------------------------------------------- sketch
 struct SketchTables {
     int64_t n, np, n1, n2, l;
@@ -81,6 +104,7 @@ struct SketchTables {
     const double *tw2;       // n2/2 complex: exp(-2 pi i j / n2)
     const double *twh;       // (np / tl) complex: exp(-2 pi i (j*tl) / np)
     const double *twl;       // tl complex: exp(-2 pi i j / np)
+    const float *tw1f, *tw2f, *twhf, *twlf;  // binary32 copies of the four tables
     int tl_bits;             // log2(tl)
     const int32_t *sel_off;  // n1/2 + 2 offsets (CSR by k1-pair)
     const int32_t *sel;      // l entries of (k, part, q) triples
@@ -88,6 +112,10 @@ struct SketchTables {
 // S (m x l row-major, lds) = A G for the SRFT; Zbuf holds one row chunk of
 // the intermediate (rows_chunk/2 x np complex binary64).
 hipError_t sketch_f64(const SketchTables &t, const double *A, int64_t lda, int64_t m,
+                      double *S, int64_t lds, double *zbuf, int64_t rows_chunk, hipStream_t stream);
+// Same sketch with the transform in binary32 (A rounded on load; S written in
+// binary64).
+hipError_t sketch_f32(const SketchTables &t, const double *A, int64_t lda, int64_t m,
                       double *S, int64_t lds, double *zbuf, int64_t rows_chunk, hipStream_t stream);
 
 // ---------------------------------------------------------------- pivoted QR

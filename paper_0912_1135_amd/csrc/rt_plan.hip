@@ -44,6 +44,13 @@ rtproj_status fail(rtproj_status s, const std::string &msg)
     } while (0)
 
 constexpr int NB = 64;  // block size of the triangular solves and the Cholesky
+// P^{-1}A is formed in binary32 only while the rank estimate of the pivoted QR
+// is at most this: its rounding error grows like 2^-24 kappa and must leave
+// the refinement a contraction well below 1.
+constexpr double RT_W32_KAPPA_MAX = 1e5;
+// Reduced-precision modes redo the sketch in binary64 when max/min diag of
+// the Gram's Cholesky factor exceeds this (a healthy preconditioner gives ~3).
+constexpr double RT_COND_ESCALATE = 10.0;
 
 // ------------------------------------------------------------ random tables
 // SplitMix64 (Steele, Lea and Flood, 2014): the state advances by the golden
@@ -131,6 +138,7 @@ struct rtproj_plan_s {
     int8_t *d_sign = nullptr;
     int32_t *d_sigma = nullptr, *d_tauinv = nullptr, *d_sel_off = nullptr, *d_sel = nullptr;
     double *d_tw1 = nullptr, *d_tw2 = nullptr, *d_twh = nullptr, *d_twl = nullptr;
+    float *d_tw1f = nullptr, *d_tw2f = nullptr, *d_twhf = nullptr, *d_twlf = nullptr;
     int tl_bits = 0;
     // preconditioner state
     double *d_zbuf = nullptr;
@@ -141,7 +149,9 @@ struct rtproj_plan_s {
     unsigned *d_sync = nullptr;
     double *d_slots = nullptr, *d_vbuf = nullptr, *d_scal = nullptr, *d_diag = nullptr;
     int *d_err = nullptr;
+    float *d_rowscale = nullptr;
     int qr_blocks = 0;
+    bool w32 = false;          // P^{-1}A held in binary32 by the last precondition
     int syrk_splits = 1;
     // projection workspace
     int64_t kcap = 0;
@@ -164,6 +174,7 @@ struct rtproj_plan_s {
         t.n = n; t.np = tab.np; t.n1 = tab.n1; t.n2 = tab.n2; t.l = l;
         t.sign = d_sign; t.sigma = d_sigma; t.tau_inv = d_tauinv;
         t.tw1 = d_tw1; t.tw2 = d_tw2; t.twh = d_twh; t.twl = d_twl; t.tl_bits = tl_bits;
+        t.tw1f = d_tw1f; t.tw2f = d_tw2f; t.twhf = d_twhf; t.twlf = d_twlf;
         t.sel_off = d_sel_off; t.sel = d_sel;
         return t;
     }
@@ -213,7 +224,7 @@ void release(rtproj_plan p)
     }
     p->pending.clear();
     void *bufs[] = {p->d_sign, p->d_sigma, p->d_tauinv, p->d_sel_off, p->d_sel, p->d_tw1, p->d_tw2, p->d_twh,
-                    p->d_twl, p->d_zbuf, p->d_S, p->d_R, p->d_Y, p->d_W, p->d_part, p->d_G, p->d_L, p->d_Tp,
+                    p->d_twl, p->d_tw1f, p->d_tw2f, p->d_twhf, p->d_twlf, p->d_rowscale, p->d_zbuf, p->d_S, p->d_R, p->d_Y, p->d_W, p->d_part, p->d_G, p->d_L, p->d_Tp,
                     p->d_DinvR, p->d_DinvL, p->d_piv, p->d_sync, p->d_slots, p->d_vbuf, p->d_scal, p->d_diag,
                     p->d_c, p->d_tmp, p->d_xhi, p->d_xlo, p->d_d, p->d_r, p->d_ph, p->d_pl, p->d_norms, p->d_err};
     for (void *b : bufs)
@@ -275,6 +286,14 @@ rtproj_status upload_tables(rtproj_plan p)
     RT_HIP(hipMemcpy(p->d_tw2, tw2.data(), tw2.size() * 8, hipMemcpyHostToDevice));
     RT_HIP(hipMemcpy(p->d_twh, twh.data(), twh.size() * 8, hipMemcpyHostToDevice));
     RT_HIP(hipMemcpy(p->d_twl, twl.data(), twl.size() * 8, hipMemcpyHostToDevice));
+    // binary32 copies for the reduced-precision sketch
+    std::vector<double> *srcs[] = {&tw1, &tw2, &twh, &twl};
+    float **dsts[] = {&p->d_tw1f, &p->d_tw2f, &p->d_twhf, &p->d_twlf};
+    for (int i = 0; i < 4; ++i) {
+        std::vector<float> f(srcs[i]->begin(), srcs[i]->end());
+        RT_HIP(dalloc(dsts[i], f.size()));
+        RT_HIP(hipMemcpy(*dsts[i], f.data(), f.size() * 4, hipMemcpyHostToDevice));
+    }
     return RTPROJ_OK;
 }
 
@@ -309,6 +328,7 @@ rtproj_status alloc_state(rtproj_plan p)
     RT_HIP(dalloc(&p->d_scal, 8));
     RT_HIP(dalloc(&p->d_diag, 8));
     RT_HIP(dalloc(&p->d_err, 4));
+    RT_HIP(dalloc(&p->d_rowscale, (size_t)m));
     return RTPROJ_OK;
 }
 
@@ -399,14 +419,22 @@ rtproj_status cholesky(rtproj_plan p)
 bool ld_ok(int64_t ld, int64_t need) { return ld >= need && ld > 0; }
 
 // Refinement steps when none were requested: the contraction of a step is
-// about c u kappa(A); with kappa_est = max|R_ii| / min|R_ii| from the pivoted
-// QR and a safety factor c = 16, take the fewest steps s >= 1 with
-// rho^(s+1) <= 1e-14 (binary64 accuracy of x with margin), at most 6.
-int auto_refine_steps(double kappa_est)
+// about c u_W kappa(A) plus the Gram's rounding; with kappa_est =
+// max|R_ii| / min|R_ii| from the pivoted QR and a safety factor c = 16, take
+// the fewest steps s >= 1 with rho^(s+1) <= 1e-14 (binary64 accuracy of x
+// with margin), at most 12.
+int auto_refine_steps(double kappa_est, int precision, bool w32, double cond_w)
 {
-    const double rho = std::min(0.5, 16.0 * std::ldexp(1.0, -52) * std::max(1.0, kappa_est));
+    // W's error ~ u_W kappa; the Gram's own rounding adds ~16 u_G (binary32)
+    // or a few units of 2^-8 (bfloat16 inputs, binary32 accumulation)
+    const double uw = w32 ? std::ldexp(1.0, -23) : std::ldexp(1.0, -52);
+    double gram = 0.0;
+    const double c2 = std::max(1.0, cond_w * cond_w / 9.0);  // relative to a healthy cond ~ 3
+    if (precision == RTPROJ_PREC_MIXED_FP32) gram = 16.0 * std::ldexp(1.0, -23) * c2;
+    if (precision == RTPROJ_PREC_MIXED_BF16) gram = 4e-3 * c2;
+    const double rho = std::min(0.5, 16.0 * uw * std::max(1.0, kappa_est) + gram);
     int s = 1;
-    while (s < 6 && std::pow(rho, s + 1) > 1e-14) ++s;
+    while (s < 12 && std::pow(rho, s + 1) > 1e-14) ++s;
     return s;
 }
 
@@ -467,7 +495,9 @@ rtproj_status project(rtproj_plan p, const double *B, int64_t ldb, int64_t k, do
     }
     int steps = 0;
     double ratio = 0.0;
-    const int nsteps = p->refine_steps >= 0 ? p->refine_steps : auto_refine_steps(p->info.kappa_est);
+    const int nsteps = p->refine_steps >= 0 ? p->refine_steps
+                                            : auto_refine_steps(p->info.kappa_est, p->precision, p->w32,
+                                                                p->info.gram_cond_est);
     for (int it = 0; it < nsteps; ++it) {
         {
             StageScope sc(p, 9);
@@ -580,8 +610,8 @@ rtproj_status rtproj_plan_set_stream(rtproj_plan p, void *stream)
 rtproj_status rtproj_plan_set_precision(rtproj_plan p, int precision)
 {
     if (!p) return fail(RTPROJ_ERR_INVALID_ARG, "null plan");
-    if (precision != RTPROJ_PREC_FP64)
-        return fail(RTPROJ_ERR_UNSUPPORTED, "only RTPROJ_PREC_FP64 is available in this build");
+    if (precision != RTPROJ_PREC_FP64 && precision != RTPROJ_PREC_MIXED_FP32 && precision != RTPROJ_PREC_MIXED_BF16)
+        return fail(RTPROJ_ERR_INVALID_ARG, "unknown precision");
     p->precision = precision;
     p->info.precision = precision;
     return RTPROJ_OK;
@@ -597,20 +627,22 @@ rtproj_status rtproj_plan_set_refinement(rtproj_plan p, int max_steps, double rt
     return RTPROJ_OK;
 }
 
-rtproj_status rtproj_precondition(rtproj_plan p, const double *A, int64_t lda)
+}  // extern "C"
+
+namespace {
+
+// One pass of the preconditioner; sketch64 forces the binary64 sketch.
+rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, bool sketch64)
 {
-    if (!p) return fail(RTPROJ_ERR_INVALID_ARG, "null plan");
-    if (!A) return fail(RTPROJ_ERR_INVALID_ARG, "A is NULL");
-    if (lda < p->n) return fail(RTPROJ_ERR_INVALID_ARG, "lda < n");
-    p->ready = false;
-    p->A = A;
-    p->lda = lda;
     const int64_t m = p->m, n = p->n, l = p->l;
     hipStream_t s = p->stream;
     // 1. sketch
     {
         StageScope sc(p, 0);
-        RT_HIP(rt::sketch_f64(p->sketch_tables(), A, lda, m, p->d_S, l, p->d_zbuf, p->rows_chunk, s));
+        if (p->precision == RTPROJ_PREC_FP64 || sketch64)
+            RT_HIP(rt::sketch_f64(p->sketch_tables(), A, lda, m, p->d_S, l, p->d_zbuf, p->rows_chunk, s));
+        else
+            RT_HIP(rt::sketch_f32(p->sketch_tables(), A, lda, m, p->d_S, l, p->d_zbuf, p->rows_chunk, s));
     }
     // 2. pivoted QR of S^T
     double diag[4];
@@ -647,29 +679,61 @@ rtproj_status rtproj_precondition(rtproj_plan p, const double *A, int64_t lda)
         st = trsm_lower(p, p->d_R, 1, m, p->d_DinvR, p->d_Y, m, m, m, true);
     }
     if (st != RTPROJ_OK) return st;
-    // 4. W = R^{-T} (Pi A)
+    // 4. W = R^{-T} (Pi A), binary32 when the rank estimate allows it
+    const bool lp = p->precision != RTPROJ_PREC_FP64;
+    p->w32 = lp && p->info.kappa_est <= RT_W32_KAPPA_MAX;
     {
         StageScope sc(p, 3);
-        rt::GemmArgs g{};
-        g.M = (int)m; g.N = (int)n; g.K = (int)m;
-        g.A = p->d_Y; g.a_i = m; g.a_k = 1; g.a_lower = 1;
-        g.B = A; g.b_k = lda; g.b_j = 1; g.b_gather = p->d_piv;
-        g.C = p->d_W; g.c_i = n; g.c_j = 1;
-        g.alpha = 1.0; g.ksplit = 1;
-        RT_HIP(rt::gemm_f64(g, s));
+        if (p->w32) {
+            rt::GemmMxArgs g{};
+            g.M = (int)m; g.N = (int)n; g.K = (int)m;
+            g.A = p->d_Y; g.a_dbl = 1; g.a_i = m; g.a_k = 1; g.a_lower = 1;
+            g.B = A; g.b_dbl = 1; g.b_k = lda; g.b_j = 1; g.b_gather = p->d_piv;
+            g.C = p->d_W; g.c_dbl = 0; g.c_i = n; g.c_j = 1;
+            g.alpha = 1.f; g.ksplit = 1;
+            RT_HIP(rt::gemm_mx(g, rt::MX_F32, s));
+        } else {
+            rt::GemmArgs g{};
+            g.M = (int)m; g.N = (int)n; g.K = (int)m;
+            g.A = p->d_Y; g.a_i = m; g.a_k = 1; g.a_lower = 1;
+            g.B = A; g.b_k = lda; g.b_j = 1; g.b_gather = p->d_piv;
+            g.C = p->d_W; g.c_i = n; g.c_j = 1;
+            g.alpha = 1.0; g.ksplit = 1;
+            RT_HIP(rt::gemm_f64(g, s));
+        }
     }
     // 5. Gram X = W W^T (lower tiles, split over n, fixed-order reduction)
     {
         StageScope sc(p, 4);
-        rt::GemmArgs g{};
-        g.M = (int)m; g.N = (int)m; g.K = (int)n;
-        g.A = p->d_W; g.a_i = n; g.a_k = 1;
-        g.B = p->d_W; g.b_k = 1; g.b_j = n;
-        g.C = p->d_part; g.c_i = m; g.c_j = 1; g.c_split = m * m;
-        g.alpha = 1.0; g.c_lower = 1; g.ksplit = p->syrk_splits;
-        RT_HIP(rt::gemm_f64(g, s));
-        RT_HIP(rt::reduce_splits_f64(p->d_part, m * m, g.ksplit > 1 ? g.ksplit : 1, (int)m, (int)m, m, p->d_G, m, 1, s));
+        if (!lp) {
+            rt::GemmArgs g{};
+            g.M = (int)m; g.N = (int)m; g.K = (int)n;
+            g.A = p->d_W; g.a_i = n; g.a_k = 1;
+            g.B = p->d_W; g.b_k = 1; g.b_j = n;
+            g.C = p->d_part; g.c_i = m; g.c_j = 1; g.c_split = m * m;
+            g.alpha = 1.0; g.c_lower = 1; g.ksplit = p->syrk_splits;
+            RT_HIP(rt::gemm_f64(g, s));
+            RT_HIP(rt::reduce_splits_f64(p->d_part, m * m, g.ksplit > 1 ? g.ksplit : 1, (int)m, (int)m, m, p->d_G, m, 1,
+                                         s));
+        } else {
+            const bool bf = p->precision == RTPROJ_PREC_MIXED_BF16;
+            const int wd = p->w32 ? 0 : 1;
+            if (bf) RT_HIP(rt::row_pow2_scale(p->d_W, wd, n, (int)m, (int)n, p->d_rowscale, s));
+            rt::GemmMxArgs g{};
+            g.M = (int)m; g.N = (int)m; g.K = (int)n;
+            g.A = p->d_W; g.a_dbl = wd; g.a_i = n; g.a_k = 1; g.a_scale = bf ? p->d_rowscale : nullptr;
+            g.B = p->d_W; g.b_dbl = wd; g.b_k = 1; g.b_j = n; g.b_scale = bf ? p->d_rowscale : nullptr;
+            g.C = p->d_part; g.c_dbl = 0; g.c_i = m; g.c_j = 1; g.c_split = m * m;
+            g.alpha = 1.f; g.c_lower = 1; g.ksplit = p->syrk_splits;
+            RT_HIP(rt::gemm_mx(g, bf ? rt::MX_BF16 : rt::MX_F32, s));
+            RT_HIP(rt::reduce_f32_splits(reinterpret_cast<const float *>(p->d_part), m * m,
+                                         g.ksplit > 1 ? g.ksplit : 1, (int)m, (int)m, m,
+                                         bf ? p->d_rowscale : nullptr, bf ? p->d_rowscale : nullptr, p->d_G, m, 1, s));
+        }
     }
+    p->info.sketch_bits = (lp && !sketch64) ? 32 : 64;
+    p->info.w_bits = p->w32 ? 32 : 64;
+    p->info.gram_bits = !lp ? 64 : (p->precision == RTPROJ_PREC_MIXED_BF16 ? 16 : 32);
     // 6. Cholesky X = L L^T
     {
         StageScope sc(p, 5);
@@ -685,9 +749,41 @@ rtproj_status rtproj_precondition(rtproj_plan p, const double *A, int64_t lda)
     }
     if (st != RTPROJ_OK) return st;
     int cerr = 0;
+    double ldiag[4];
+    RT_HIP(rt::rdiag_ends_f64(p->d_L, m, (int)m, p->d_diag, s));
+    RT_HIP(hipMemcpyAsync(ldiag, p->d_diag, 32, hipMemcpyDeviceToHost, s));
     RT_HIP(hipMemcpyAsync(&cerr, p->d_err, 4, hipMemcpyDeviceToHost, s));
     RT_HIP(hipStreamSynchronize(s));
     if (cerr) return fail(RTPROJ_ERR_RANK, "Cholesky of the preconditioned Gram broke down");
+    // max/min of diag(L) bounds cond(P^{-1}A) from below (about 3 for a
+    // healthy sketch with l = 4m, Observation 3.2)
+    p->info.gram_cond_est = ldiag[2] > 0 ? ldiag[3] / ldiag[2] : INFINITY;
+    return RTPROJ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rtproj_status rtproj_precondition(rtproj_plan p, const double *A, int64_t lda)
+{
+    if (!p) return fail(RTPROJ_ERR_INVALID_ARG, "null plan");
+    if (!A) return fail(RTPROJ_ERR_INVALID_ARG, "A is NULL");
+    if (lda < p->n) return fail(RTPROJ_ERR_INVALID_ARG, "lda < n");
+    p->ready = false;
+    p->A = A;
+    p->lda = lda;
+    p->info.sketch_escalated = 0;
+    rtproj_status st = precondition_impl(p, A, lda, false);
+    // A binary32 sketch perturbs G by about 2^-24 kappa(A) relative to the
+    // small singular directions; when that shows as a poorly conditioned
+    // P^{-1}A, sketch again in binary64 (the identity holds for any G, only
+    // the conditioning matters, Lemma 2.4).
+    if (st == RTPROJ_OK && p->precision != RTPROJ_PREC_FP64 && p->info.gram_cond_est > RT_COND_ESCALATE) {
+        p->info.sketch_escalated = 1;
+        st = precondition_impl(p, A, lda, true);
+    }
+    if (st != RTPROJ_OK) return st;
     p->ready = true;
     return RTPROJ_OK;
 }

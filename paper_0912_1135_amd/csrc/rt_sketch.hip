@@ -23,11 +23,13 @@ namespace rt {
 
 namespace {
 
-struct cplx { double re, im; };
+template <typename R>
+struct cpx { R re, im; };
 
-__device__ __forceinline__ cplx cmul(cplx a, cplx b)
+template <typename R>
+__device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b)
 {
-    return cplx{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+    return cpx<R>{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
 }
 
 __device__ __forceinline__ unsigned bitrev(unsigned x, int bits)
@@ -38,7 +40,8 @@ __device__ __forceinline__ unsigned bitrev(unsigned x, int bits)
 // In-place radix-2 decimation-in-time FFT of `cols` columns of length `len`
 // stored column after column in LDS (input already in bit-reversed order).
 // tw: len/2 twiddles exp(-2 pi i j / len) in LDS.
-__device__ void lds_fft_cols(cplx *buf, int len, int cols, const cplx *tw)
+template <typename R>
+__device__ void lds_fft_cols(cpx<R> *buf, int len, int cols, const cpx<R> *tw)
 {
     const int half = len >> 1;
     for (int h = 1; h < len; h <<= 1) {
@@ -47,28 +50,31 @@ __device__ void lds_fft_cols(cplx *buf, int len, int cols, const cplx *tw)
             const int c = e / half, q = e - c * half;
             const int grp = q / h, pos = q - grp * h;
             const int i0 = grp * 2 * h + pos, i1 = i0 + h;
-            cplx *col = buf + (int64_t)c * len;
-            const cplx w = tw[pos * stride];
-            const cplx a = col[i0];
-            const cplx b = cmul(col[i1], w);
-            col[i0] = cplx{a.re + b.re, a.im + b.im};
-            col[i1] = cplx{a.re - b.re, a.im - b.im};
+            cpx<R> *col = buf + (int64_t)c * len;
+            const cpx<R> w = tw[pos * stride];
+            const cpx<R> a = col[i0];
+            const cpx<R> b = cmul(col[i1], w);
+            col[i0] = cpx<R>{a.re + b.re, a.im + b.im};
+            col[i1] = cpx<R>{a.re - b.re, a.im - b.im};
         }
         __syncthreads();
     }
 }
 
+template <typename R>
 __global__ __launch_bounds__(256) void sketch_pass1(SketchTables t, const double *A, int64_t lda, int64_t m,
-                                                    int64_t row0, cplx *zbuf, int tw_cols, int bits1)
+                                                    int64_t row0, cpx<R> *zbuf, int tw_cols, int bits1)
 {
-    extern __shared__ cplx smem[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    typedef cpx<R> cplx;
+    cplx *smem = reinterpret_cast<cplx *>(smem_raw);
     const int n1 = (int)t.n1, n2 = (int)t.n2;
     cplx *tw = smem;                 // n1/2
     cplx *buf = smem + (n1 >> 1);    // tw_cols x n1
     const int64_t pair = blockIdx.y;
     const int64_t r0 = row0 + 2 * pair, r1 = r0 + 1;
     const int u0 = blockIdx.x * tw_cols;
-    const cplx *tw1 = reinterpret_cast<const cplx *>(t.tw1);
+    const cplx *tw1 = reinterpret_cast<const cplx *>(sizeof(R) == 8 ? (const void *)t.tw1 : (const void *)t.tw1f);
     for (int e = threadIdx.x; e < (n1 >> 1); e += blockDim.x) tw[e] = tw1[e];
     const double *a0 = A + r0 * lda;
     const double *a1 = A + r1 * lda;
@@ -76,18 +82,18 @@ __global__ __launch_bounds__(256) void sketch_pass1(SketchTables t, const double
     for (int e = threadIdx.x; e < n1 * tw_cols; e += blockDim.x) {
         const int t1 = e / tw_cols, j = e - t1 * tw_cols;
         const int64_t src = (int64_t)t.sigma[t1] * n2 + u0 + j;
-        double re = 0.0, im = 0.0;
+        R re = 0, im = 0;
         if (src < t.n) {
             const double s = (double)t.sign[src];
-            re = s * a0[src];
-            if (has1) im = s * a1[src];
+            re = (R)(s * a0[src]);
+            if (has1) im = (R)(s * a1[src]);
         }
         buf[(int64_t)j * n1 + bitrev((unsigned)t1, bits1)] = cplx{re, im};
     }
     __syncthreads();
     lds_fft_cols(buf, n1, tw_cols, tw);
-    const cplx *twh = reinterpret_cast<const cplx *>(t.twh);
-    const cplx *twl = reinterpret_cast<const cplx *>(t.twl);
+    const cplx *twh = reinterpret_cast<const cplx *>(sizeof(R) == 8 ? (const void *)t.twh : (const void *)t.twhf);
+    const cplx *twl = reinterpret_cast<const cplx *>(sizeof(R) == 8 ? (const void *)t.twl : (const void *)t.twlf);
     const int tl_mask = (1 << t.tl_bits) - 1;
     cplx *zp = zbuf + pair * t.np;
     for (int e = threadIdx.x; e < n1 * tw_cols; e += blockDim.x) {
@@ -99,10 +105,13 @@ __global__ __launch_bounds__(256) void sketch_pass1(SketchTables t, const double
     }
 }
 
+template <typename R>
 __global__ __launch_bounds__(256) void sketch_pass2(SketchTables t, int64_t m, int64_t row0, int64_t npairs,
-                                                    const cplx *zbuf, double *S, int64_t lds, int cp, int bits2)
+                                                    const cpx<R> *zbuf, double *S, int64_t lds, int cp, int bits2)
 {
-    extern __shared__ cplx smem[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    typedef cpx<R> cplx;
+    cplx *smem = reinterpret_cast<cplx *>(smem_raw);
     const int n1 = (int)t.n1, n2 = (int)t.n2;
     cplx *tw = smem;               // n2/2
     cplx *buf = smem + (n2 >> 1);  // cp x 2 x n2
@@ -111,7 +120,7 @@ __global__ __launch_bounds__(256) void sketch_pass2(SketchTables t, int64_t m, i
     const int ncol = (ka == kb) ? 1 : 2;
     const int64_t p0 = (int64_t)blockIdx.y * cp;
     const int pc = (int)min<int64_t>(cp, npairs - p0);
-    const cplx *tw2 = reinterpret_cast<const cplx *>(t.tw2);
+    const cplx *tw2 = reinterpret_cast<const cplx *>(sizeof(R) == 8 ? (const void *)t.tw2 : (const void *)t.tw2f);
     for (int e = threadIdx.x; e < (n2 >> 1); e += blockDim.x) tw[e] = tw2[e];
     for (int e = threadIdx.x; e < pc * ncol * n2; e += blockDim.x) {
         const int c = e / n2, u = e - c * n2;
@@ -140,8 +149,8 @@ __global__ __launch_bounds__(256) void sketch_pass2(SketchTables t, int64_t m, i
         const cplx yp = buf[(int64_t)(p * 2 + (kp1 == ka ? 0 : 1)) * n2 + kp2];
         // spectra of the two real rows: Ya = (Y_k + conj Y_{np-k})/2,
         // Yb = (Y_k - conj Y_{np-k})/(2i)
-        const double ar = 0.5 * (y.re + yp.re), ai = 0.5 * (y.im - yp.im);
-        const double br = 0.5 * (y.im + yp.im), bi = -0.5 * (y.re - yp.re);
+        const double ar = 0.5 * ((double)y.re + (double)yp.re), ai = 0.5 * ((double)y.im - (double)yp.im);
+        const double br = 0.5 * ((double)y.im + (double)yp.im), bi = -0.5 * ((double)y.re - (double)yp.re);
         const double sc = (k == 0 || k == half) ? sc1 : sc2;
         const int64_t r0 = row0 + 2 * (p0 + p);
         S[r0 * lds + q] = sc * (part ? ai : ar);
@@ -156,38 +165,53 @@ int ilog2(int64_t v)
     return b;
 }
 
-}  // namespace
-
-hipError_t sketch_f64(const SketchTables &t, const double *A, int64_t lda, int64_t m, double *S, int64_t lds,
-                      double *zbuf, int64_t rows_chunk, hipStream_t stream)
+template <typename R>
+hipError_t sketch_run(const SketchTables &t, const double *A, int64_t lda, int64_t m, double *S, int64_t lds,
+                      void *zbuf, int64_t rows_chunk, hipStream_t stream)
 {
+    typedef cpx<R> cplx;
     const int n1 = (int)t.n1, n2 = (int)t.n2;
     const int bits1 = ilog2(n1), bits2 = ilog2(n2);
+    const int64_t csz = sizeof(cplx);
     int tw_cols = n2 < 16 ? n2 : 16;
-    while (tw_cols > 1 && (int64_t)tw_cols * n1 * 16 > 64 * 1024) tw_cols >>= 1;
-    int cp = (int)((64 * 1024) / (2 * 16 * (int64_t)n2));
+    while (tw_cols > 1 && (int64_t)tw_cols * n1 * csz > 64 * 1024) tw_cols >>= 1;
+    int cp = (int)((64 * 1024) / (2 * csz * (int64_t)n2));
     if (cp < 1) cp = 1;
     if (cp > 8) cp = 8;
-    const size_t sm1 = (size_t)((n1 >> 1) + (int64_t)tw_cols * n1) * 16;
-    const size_t sm2 = (size_t)((n2 >> 1) + (int64_t)cp * 2 * n2) * 16;
+    const size_t sm1 = (size_t)((n1 >> 1) + (int64_t)tw_cols * n1) * csz;
+    const size_t sm2 = (size_t)((n2 >> 1) + (int64_t)cp * 2 * n2) * csz;
     cplx *z = reinterpret_cast<cplx *>(zbuf);
-    hipError_t ea = hipFuncSetAttribute((const void *)sketch_pass1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm1);
+    hipError_t ea = hipFuncSetAttribute((const void *)sketch_pass1<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm1);
     if (ea != hipSuccess) return ea;
-    ea = hipFuncSetAttribute((const void *)sketch_pass2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm2);
+    ea = hipFuncSetAttribute((const void *)sketch_pass2<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm2);
     if (ea != hipSuccess) return ea;
     for (int64_t row0 = 0; row0 < m; row0 += rows_chunk) {
         const int64_t rows = std::min<int64_t>(rows_chunk, m - row0);
         const int64_t npairs = (rows + 1) / 2;
-        hipLaunchKernelGGL(sketch_pass1, dim3(n2 / tw_cols, (unsigned)npairs), dim3(256), sm1, stream, t, A, lda,
+        hipLaunchKernelGGL(sketch_pass1<R>, dim3(n2 / tw_cols, (unsigned)npairs), dim3(256), sm1, stream, t, A, lda,
                            m, row0, z, tw_cols, bits1);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(sketch_pass2, dim3(n1 / 2 + 1, (unsigned)((npairs + cp - 1) / cp)), dim3(256), sm2, stream,
+        hipLaunchKernelGGL(sketch_pass2<R>, dim3(n1 / 2 + 1, (unsigned)((npairs + cp - 1) / cp)), dim3(256), sm2, stream,
                            t, m, row0, npairs, (const cplx *)z, S, lds, cp, bits2);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t sketch_f64(const SketchTables &t, const double *A, int64_t lda, int64_t m, double *S, int64_t lds,
+                      double *zbuf, int64_t rows_chunk, hipStream_t stream)
+{
+    return sketch_run<double>(t, A, lda, m, S, lds, zbuf, rows_chunk, stream);
+}
+
+hipError_t sketch_f32(const SketchTables &t, const double *A, int64_t lda, int64_t m, double *S, int64_t lds,
+                      double *zbuf, int64_t rows_chunk, hipStream_t stream)
+{
+    return sketch_run<float>(t, A, lda, m, S, lds, zbuf, rows_chunk, stream);
 }
 
 }  // namespace rt

@@ -224,3 +224,65 @@ def test_aliasing_z_equals_b(rt):
     torch.cuda.synchronize()
     assert torch.equal(Zs, Bt)
     plan.close()
+
+
+@pytest.mark.parametrize("prec,name", [(1, "fp32"), (2, "bf16")])
+@pytest.mark.parametrize("m,n,l,kappa,k,seed", [
+    (64, 4096, 256, 1e3, 3, 31),      # P^{-1}A in binary32 (kappa_est small)
+    (100, 5000, 400, 1e8, 4, 32),     # P^{-1}A stays binary64, reduced-precision Gram
+    (130, 9000, 520, 1e10, 5, 33),
+])
+def test_mixed_precision_matches_oracle(rt, prec, name, m, n, l, kappa, k, seed):
+    A = synth.make_problem(m, n, kappa, seed)
+    B = synth.make_rhs(n, k, seed)
+    plan = rt.Plan(m, n, l, seed)
+    plan.set_precision(prec)
+    plan.precondition(torch.from_numpy(A).to(dev()))
+    Z, Y, X = plan.project_all(torch.from_numpy(B).to(dev()))
+    torch.cuda.synchronize()
+    info = plan.info()
+    assert info["sketch_bits"] == (64 if info["sketch_escalated"] else 32)
+    assert info["gram_cond_est"] < 10
+    assert info["gram_bits"] == (32 if prec == 1 else 16)
+    assert info["w_bits"] == (32 if info["kappa_est"] <= 1e5 else 64)
+    Zr, Yr, Xr, _ = oracle.project(A, B.T)
+    ez, ey, ex = errors(B, Z.cpu().numpy(), Y.cpu().numpy(), X.cpu().numpy(), Zr, Yr, Xr)
+    assert ez <= TOL and ey <= TOL and ex <= TOL, (name, ez, ey, ex, info["refine_steps"])
+    plan.close()
+
+
+def test_fp32_sketch_matches_oracle(rt):
+    m, n, l, seed = 40, 3000, 160, 9
+    A = synth.make_problem(m, n, 1e3, seed)
+    plan = rt.Plan(m, n, l, seed)
+    plan.set_precision(1)
+    plan.precondition(torch.from_numpy(A).to(dev()))
+    S = plan.export()["S"].cpu().numpy()
+    Sr = oracle.srft_sketch(A, seed, l)
+    np_ = oracle.srft_dims(n)[0]
+    tol = 64 * 2.0 ** -23 * np.log2(np_) * np.linalg.norm(A, axis=1)
+    err = np.linalg.norm(S - Sr, axis=1)
+    assert np.all(err <= tol)
+    assert np.max(err / np.linalg.norm(A, axis=1)) > 1e-12  # really binary32
+    plan.close()
+
+
+def test_bf16_gram_needs_refinement(rt):
+    """Unrefined, the bfloat16 Gram leaves errors far above binary64 rounding;
+    the refinement of Remark 4.3 brings them under the tolerance."""
+    m, n, l, k, seed = 96, 6000, 384, 3, 40
+    A = synth.make_problem(m, n, 1e6, seed)
+    B = synth.make_rhs(n, k, seed)
+    Zr, Yr, Xr, _ = oracle.project(A, B.T)
+    plan = rt.Plan(m, n, l, seed)
+    plan.set_precision(2)
+    plan.precondition(torch.from_numpy(A).to(dev()))
+    Bt = torch.from_numpy(B).to(dev())
+    plan.set_refinement(0, 0.0)
+    Z0, Y0, X0 = [t.cpu().numpy() for t in plan.project_all(Bt)]
+    plan.set_refinement(-1, 0.0)
+    Z1, Y1, X1 = [t.cpu().numpy() for t in plan.project_all(Bt)]
+    e0 = errors(B, Z0, Y0, X0, Zr, Yr, Xr)
+    e1 = errors(B, Z1, Y1, X1, Zr, Yr, Xr)
+    assert e0[2] > 1e-6 and max(e1) <= TOL, (e0, e1)
+    plan.close()
