@@ -120,20 +120,21 @@ hipError_t sketch_f32(const SketchTables &t, const double *A, int64_t lda, int64
 
 // ---------------------------------------------------------------- pivoted QR
 struct QrcpWork {
-    unsigned *counter;   // published-pivot step flag (zeroed by the launcher)
+    unsigned *counter;   // grid-barrier arrival counter (zeroed by the launcher)
     unsigned *flag;      // spare
     int *err;            // 1: wait timeout, 2: no finite pivot
-    unsigned *arrive;    // blocks: per-block arrival step (zeroed by the launcher)
     double *slots;       // 2 * blocks * 2 doubles: candidate (norm^2, column)
     double *vbuf;        // 2 * blocks * rows doubles: candidate columns
-    double *pick;        // 2 * 2 doubles: published (norm^2, column)
+    double *cols;        // null: columns kept in LDS; else blocks * 16 * rows doubles
 };
 // Column-pivoted Householder QR of M = S^T (rows = l, cols = m; column j of M
-// is row j of S, S row-major with ld lds).  R: m x m row-major (upper; the
-// strictly lower part is set to zero).  piv: m int32.
+// is row j of S, S row-major with ld lds).  R: m x m row-major, upper part
+// written (the caller clears the strictly lower part).  piv: m int32.
 hipError_t qrcp_f64(const double *S, int64_t lds, int rows, int cols, double *R, int32_t *piv,
                     const QrcpWork &w, int blocks, size_t lds_bytes_max, hipStream_t stream);
-int qrcp_max_blocks(int rows, int cols, int cu_count, size_t lds_max);
+// Number of cooperative blocks for an l x m factorization (-1: unsupported);
+// *global_cols = 1 when the columns must live in global memory (w.cols).
+int qrcp_max_blocks(int rows, int cols, int cu_count, size_t lds_max, int *global_cols);
 hipError_t zero_u32(unsigned *p, int n, hipStream_t stream);
 
 // ---------------------------------------------------------------- factor

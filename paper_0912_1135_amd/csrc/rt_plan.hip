@@ -147,7 +147,7 @@ struct rtproj_plan_s {
     double *d_G = nullptr, *d_L = nullptr, *d_Tp = nullptr, *d_DinvR = nullptr, *d_DinvL = nullptr;
     int32_t *d_piv = nullptr;
     unsigned *d_sync = nullptr;
-    double *d_slots = nullptr, *d_vbuf = nullptr, *d_scal = nullptr, *d_diag = nullptr;
+    double *d_slots = nullptr, *d_vbuf = nullptr, *d_qrcols = nullptr, *d_scal = nullptr, *d_diag = nullptr;
     int *d_err = nullptr;
     float *d_rowscale = nullptr;
     int qr_blocks = 0;
@@ -225,7 +225,7 @@ void release(rtproj_plan p)
     p->pending.clear();
     void *bufs[] = {p->d_sign, p->d_sigma, p->d_tauinv, p->d_sel_off, p->d_sel, p->d_tw1, p->d_tw2, p->d_twh,
                     p->d_twl, p->d_tw1f, p->d_tw2f, p->d_twhf, p->d_twlf, p->d_rowscale, p->d_zbuf, p->d_S, p->d_R, p->d_Y, p->d_W, p->d_part, p->d_G, p->d_L, p->d_Tp,
-                    p->d_DinvR, p->d_DinvL, p->d_piv, p->d_sync, p->d_slots, p->d_vbuf, p->d_scal, p->d_diag,
+                    p->d_DinvR, p->d_DinvL, p->d_piv, p->d_sync, p->d_slots, p->d_vbuf, p->d_qrcols, p->d_scal, p->d_diag,
                     p->d_c, p->d_tmp, p->d_xhi, p->d_xlo, p->d_d, p->d_r, p->d_ph, p->d_pl, p->d_norms, p->d_err};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -320,11 +320,14 @@ rtproj_status alloc_state(rtproj_plan p)
     RT_HIP(dalloc(&p->d_DinvL, (size_t)nblk * NB * NB));
     RT_HIP(dalloc(&p->d_piv, (size_t)m));
     RT_HIP(dalloc(&p->d_sync, 4));
-    p->qr_blocks = rt::qrcp_max_blocks((int)l, (int)m, p->cu_count, p->lds_max);
+    int gcols = 0;
+    p->qr_blocks = rt::qrcp_max_blocks((int)l, (int)m, p->cu_count, p->lds_max, &gcols);
     if (p->qr_blocks <= 0)
-        return fail(RTPROJ_ERR_UNSUPPORTED, "pivoted QR: the sketch's columns do not fit in LDS for this (m, l)");
-    RT_HIP(dalloc(&p->d_slots, (size_t)5 * p->qr_blocks));  // candidates + arrival flags
+        return fail(RTPROJ_ERR_UNSUPPORTED, "pivoted QR: more than 16 columns per compute unit, or l too large, "
+                                            "for this (m, l)");
+    RT_HIP(dalloc(&p->d_slots, (size_t)4 * p->qr_blocks));
     RT_HIP(dalloc(&p->d_vbuf, (size_t)2 * p->qr_blocks * l));
+    if (gcols) RT_HIP(dalloc(&p->d_qrcols, (size_t)p->qr_blocks * 16 * l));
     RT_HIP(dalloc(&p->d_scal, 8));
     RT_HIP(dalloc(&p->d_diag, 8));
     RT_HIP(dalloc(&p->d_err, 4));
@@ -654,10 +657,9 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
         w.counter = p->d_sync;
         w.flag = p->d_sync + 1;
         w.err = reinterpret_cast<int *>(p->d_sync + 2);
-        w.arrive = reinterpret_cast<unsigned *>(p->d_slots + 4 * p->qr_blocks);
         w.slots = p->d_slots;
         w.vbuf = p->d_vbuf;
-        w.pick = p->d_scal;
+        w.cols = p->d_qrcols;
         RT_HIP(rt::qrcp_f64(p->d_S, l, (int)l, (int)m, p->d_R, p->d_piv, w, p->qr_blocks, p->lds_max, s));
         RT_HIP(rt::rdiag_ends_f64(p->d_R, m, (int)m, p->d_diag, s));
         RT_HIP(hipMemcpyAsync(diag, p->d_diag, 32, hipMemcpyDeviceToHost, s));

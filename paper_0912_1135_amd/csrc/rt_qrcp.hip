@@ -3,8 +3,9 @@
 // remaining column with the largest trailing 2-norm (ties: lowest index).
 //
 // One cooperative launch.  Block g owns columns j = g, g + G, g + 2G, ... of
-// the input and keeps them resident in LDS for the whole factorization.  Each
-// step costs ONE grid barrier:
+// the input and keeps them for the whole factorization in LDS (or, for
+// sketches too tall for LDS, in a private slice of global memory).  Each step
+// costs ONE grid barrier:
 //   1. every block posts its best remaining column (trailing norm^2, index,
 //      and the trailing part of the column itself) to a double-buffered slot;
 //   2. grid barrier;
@@ -71,13 +72,15 @@ __device__ __forceinline__ bool spin_until(unsigned *addr, unsigned target, int 
     return true;
 }
 
-template <int NC>
+// GCOLS: the block's columns live in global memory (w.cols + g*NC*rows,
+// private to the block) instead of LDS, for sketches too tall for LDS.
+template <int NC, bool GCOLS>
 __global__ __launch_bounds__(QR_THREADS) void qrcp_kernel(const double *S, int64_t lds, int rows, int cols,
                                                           double *R, int32_t *piv, QrcpWork w, int G)
 {
     extern __shared__ double smem[];
-    double *colbuf = smem;                     // NC x rows
-    double *v = smem + (int64_t)NC * rows;     // rows
+    double *colbuf = GCOLS ? w.cols + (int64_t)blockIdx.x * NC * rows : smem;  // NC x rows
+    double *v = GCOLS ? smem : smem + (int64_t)NC * rows;                       // rows
     __shared__ double scratch[(QR_THREADS / 64) * QR_MAXCOL];
     __shared__ double nrm[QR_MAXCOL];
     __shared__ int done[QR_MAXCOL];
@@ -222,35 +225,41 @@ __global__ void zero_u32_kernel(unsigned *p, int n)
     if (i < n) p[i] = 0u;
 }
 
-template <int NC>
+template <int NC, bool GCOLS>
 hipError_t launch_qrcp(const double *S, int64_t lds, int rows, int cols, double *R, int32_t *piv, const QrcpWork &w,
                        int G, size_t shmem, hipStream_t stream)
 {
-    hipError_t e = hipFuncSetAttribute((const void *)qrcp_kernel<NC>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)shmem);
+    hipError_t e = hipFuncSetAttribute((const void *)qrcp_kernel<NC, GCOLS>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (e != hipSuccess) return e;
     QrcpWork wk = w;
     int rows_ = rows, cols_ = cols, G_ = G;
     int64_t lds_ = lds;
     void *args[] = {(void *)&S, (void *)&lds_, (void *)&rows_, (void *)&cols_, (void *)&R, (void *)&piv,
                     (void *)&wk, (void *)&G_};
-    return hipLaunchCooperativeKernel((const void *)qrcp_kernel<NC>, dim3(G), dim3(QR_THREADS), args,
+    return hipLaunchCooperativeKernel((const void *)qrcp_kernel<NC, GCOLS>, dim3(G), dim3(QR_THREADS), args,
                                       (unsigned)shmem, stream);
 }
 
 }  // namespace
 
-int qrcp_max_blocks(int rows, int cols, int cu_count, size_t lds_max)
+int qrcp_max_blocks(int rows, int cols, int cu_count, size_t lds_max, int *global_cols)
 {
     // fewest blocks (one barrier participant each) whose columns fit in LDS,
-    // at most one block per compute unit
+    // at most one block per compute unit; otherwise 16 columns per block held
+    // in global memory
+    *global_cols = 0;
     for (int ncol = QR_MAXCOL; ncol >= 1; ncol >>= 1) {
         const size_t need = ((size_t)ncol + 1) * (size_t)rows * sizeof(double) + 4096;
         if (need > lds_max) continue;
         const int G = (cols + ncol - 1) / ncol;
-        return G <= cu_count ? G : -1;
+        if (G <= cu_count) return G;
+        break;
     }
-    return -1;
+    if ((size_t)rows * sizeof(double) + 4096 > lds_max) return -1;
+    *global_cols = 1;
+    const int G = (cols + QR_MAXCOL - 1) / QR_MAXCOL;
+    return G <= cu_count ? G : -1;
 }
 
 hipError_t zero_u32(unsigned *p, int n, hipStream_t stream)
@@ -267,16 +276,19 @@ hipError_t qrcp_f64(const double *S, int64_t lds, int rows, int cols, double *R,
     int nc = 1;
     while (nc < need_cols) nc <<= 1;
     if (nc > QR_MAXCOL) return hipErrorInvalidValue;
-    const size_t shmem = ((size_t)nc + 1) * (size_t)rows * sizeof(double);
+    const bool gcols = w.cols != nullptr;
+    const size_t shmem = ((size_t)(gcols ? 0 : nc) + 1) * (size_t)rows * sizeof(double);
     if (shmem + 4096 > lds_bytes_max) return hipErrorInvalidValue;
     hipError_t e = zero_u32(w.counter, 4, stream);  // counter, flag, err
     if (e != hipSuccess) return e;
+    // the global-memory column slices are laid out for QR_MAXCOL columns per block
+    if (gcols) return launch_qrcp<QR_MAXCOL, true>(S, lds, rows, cols, R, piv, w, G, shmem, stream);
     switch (nc) {
-    case 1: return launch_qrcp<1>(S, lds, rows, cols, R, piv, w, G, shmem, stream);
-    case 2: return launch_qrcp<2>(S, lds, rows, cols, R, piv, w, G, shmem, stream);
-    case 4: return launch_qrcp<4>(S, lds, rows, cols, R, piv, w, G, shmem, stream);
-    case 8: return launch_qrcp<8>(S, lds, rows, cols, R, piv, w, G, shmem, stream);
-    default: return launch_qrcp<16>(S, lds, rows, cols, R, piv, w, G, shmem, stream);
+    case 1: return launch_qrcp<1, false>(S, lds, rows, cols, R, piv, w, G, shmem, stream);
+    case 2: return launch_qrcp<2, false>(S, lds, rows, cols, R, piv, w, G, shmem, stream);
+    case 4: return launch_qrcp<4, false>(S, lds, rows, cols, R, piv, w, G, shmem, stream);
+    case 8: return launch_qrcp<8, false>(S, lds, rows, cols, R, piv, w, G, shmem, stream);
+    default: return launch_qrcp<16, false>(S, lds, rows, cols, R, piv, w, G, shmem, stream);
     }
 }
 
