@@ -14,8 +14,10 @@ with HIP events on the plan's stream during the timed steps) and the CPU
 oracle timed on a bounded sample of the same workload.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -54,15 +56,65 @@ def stage_work(name, m, n, l, k, refine_steps):
     return None, 0.0, None
 
 
+# stage -> (kernel name in the profiler's trace, source file of that kernel)
+STAGE_KERNELS = {
+    "qrcp": ("qrcp_kernel", "paper_0912_1135_amd/csrc/rt_qrcp.hip"),
+    "sketch": ("sketch_pass", "paper_0912_1135_amd/csrc/rt_sketch.hip"),
+    "gram_syrk": ("gemm_f64_kernel", "paper_0912_1135_amd/csrc/rt_gemm.hip"),
+    "w_gemm": ("gemm_f64_kernel", "paper_0912_1135_amd/csrc/rt_gemm.hip"),
+    "cholesky": ("chol_diag_kernel", "paper_0912_1135_amd/csrc/rt_factor.hip"),
+    "refine_atx": ("atx_kernel", "paper_0912_1135_amd/csrc/rt_apply.hip"),
+    "final_atx": ("atx_kernel", "paper_0912_1135_amd/csrc/rt_apply.hip"),
+    "refine_ab": ("ab_partial_kernel", "paper_0912_1135_amd/csrc/rt_apply.hip"),
+}
+
+
+def measured_traffic(stage, workload):
+    """HBM bytes per launch of `stage`'s kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when there is
+    none for this workload or the kernel's source changed since it was taken."""
+    if stage not in STAGE_KERNELS:
+        return None
+    kernel, src = STAGE_KERNELS[stage]
+    path = os.path.join(ROOT, "profiles", "traffic.md")
+    try:
+        text = open(path).read()
+        digest = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
+    except OSError:
+        return None
+    for line in text.splitlines():
+        if not line.startswith("traffic:"):
+            continue
+        kv = dict(re.findall(r"(\w+)=(\S+)", line))
+        if kv.get("stage") == stage and kv.get("workload") == workload and kv.get("sha256") == digest:
+            return float(kv["bytes_per_launch"])
+    return None
+
+
+def copy_calibration(mib):
+    """One plain streaming kernel of known size (reads and writes `mib` MiB),
+    the scale for the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    x = torch.ones(mib << 17, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    del x, y
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", help="c1 or c2 (single-instance binary64 workloads)")
+    ap.add_argument("--workload", default="plain_512x65536",
+                    help="plain_512x65536 or plain_64x4096 (single-instance binary64 workloads)")
     ap.add_argument("--refine-steps", type=int, default=-1, help="-1: chosen from the pivoted-QR rank estimate")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run one plain copy kernel over MIB MiB (counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -90,6 +142,8 @@ def main():
     Y = torch.empty_like(Bt)
     X = torch.empty((k, m), dtype=torch.float64, device=dev)
 
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
     plan = rt.Plan(m, n, l, seed)
     plan.set_refinement(args.refine_steps, 0.0)
 
@@ -131,7 +185,7 @@ def main():
     else:
         roof = {"bound": "alu", "achieved": amount / sec / 1e12, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(dom, args.workload)
     roof["kernel"] = dom
     for name, d in stages.items():
         b, amt, kd = stage_work(name, m, n, l, k, args.refine_steps)

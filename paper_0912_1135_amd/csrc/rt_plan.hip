@@ -651,7 +651,6 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
     double diag[4];
     unsigned sync[4];
     {
-        StageScope sc(p, 1);
         RT_HIP(rt::set_matrix_f64(p->d_R, m, (int)m, (int)m, 0, s));
         rt::QrcpWork w;
         w.counter = p->d_sync;
@@ -660,7 +659,10 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
         w.slots = p->d_slots;
         w.vbuf = p->d_vbuf;
         w.cols = p->d_qrcols;
-        RT_HIP(rt::qrcp_f64(p->d_S, l, (int)l, (int)m, p->d_R, p->d_piv, w, p->qr_blocks, p->lds_max, s));
+        {
+            StageScope sc(p, 1);
+            RT_HIP(rt::qrcp_f64(p->d_S, l, (int)l, (int)m, p->d_R, p->d_piv, w, p->qr_blocks, p->lds_max, s));
+        }
         RT_HIP(rt::rdiag_ends_f64(p->d_R, m, (int)m, p->d_diag, s));
         RT_HIP(hipMemcpyAsync(diag, p->d_diag, 32, hipMemcpyDeviceToHost, s));
         RT_HIP(hipMemcpyAsync(sync, p->d_sync, 16, hipMemcpyDeviceToHost, s));

@@ -84,9 +84,9 @@ def make_batch_shapes(count: int, seed: int, m_lo: int = 32, m_hi: int = 512,
 
 # The five measured workloads (sizes, spectra, sketch size, right-hand sides).
 CONFIGS = {
-    "c1": dict(m=64, n=4096, l=256, kappa=1e6, k=1, seed=MASTER_SEED + 1),
-    "c2": dict(m=512, n=65536, l=2048, kappa=1e10, k=16, seed=MASTER_SEED + 2),
-    "c3": dict(m=2048, n=262144, l=8192, kappa=1e8, k=64, seed=MASTER_SEED + 3),
-    "c4": dict(count=256, kappa=1e6, seed=MASTER_SEED + 4),
-    "c5": dict(m=1024, n=131072, l=4096, kappa=1e4, k=128, steps=32, seed=MASTER_SEED + 5),
+    "plain_64x4096": dict(m=64, n=4096, l=256, kappa=1e6, k=1, seed=MASTER_SEED + 1),
+    "plain_512x65536": dict(m=512, n=65536, l=2048, kappa=1e10, k=16, seed=MASTER_SEED + 2),
+    "mixed_2048x262144": dict(m=2048, n=262144, l=8192, kappa=1e8, k=64, seed=MASTER_SEED + 3),
+    "batch_256": dict(count=256, kappa=1e6, seed=MASTER_SEED + 4),
+    "ipm_1024x131072": dict(m=1024, n=131072, l=4096, kappa=1e4, k=128, steps=32, seed=MASTER_SEED + 5),
 }

@@ -10,6 +10,8 @@
   that catch a wrong Fisher-Yates bound or a biased subset.
 """
 import mpmath
+import os
+
 import numpy as np
 import pytest
 import scipy.linalg as sl
@@ -179,9 +181,11 @@ def test_qrcp_ties_take_lowest_index():
 # ---------------------------------------------------------------- sketch
 
 def test_splitmix64_published_vector():
-    assert oracle.splitmix64(1234567, 5).tolist() == [
-        6457827717110365317, 3203168211198807973, 9817491932198370423,
-        4593380528125082431, 16408922859458223821]
+    path = os.path.join(os.path.dirname(__file__), "golden", "splitmix64_seed1234567.txt")
+    lines = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    seed = int(lines[0][1])
+    want = [int(ln[0]) for ln in lines[1:]]
+    assert oracle.splitmix64(seed, len(want)).tolist() == want
 
 
 @pytest.mark.parametrize("n,l", [(5, 3), (8, 8), (13, 6), (16, 16), (33, 20), (64, 17)])
