@@ -39,6 +39,10 @@ def stage_work(name, m, n, l, k, refine_steps):
         return "hbm", 8.0 * m * n + 8.0 * m * l, "bytes"          # read A, write S
     if name == "qrcp":
         return "alu", 2.0 * l * m * m - 2.0 * m ** 3 / 3, "flops"
+    if name == "qr_r0":
+        # shifted Cholesky QR: three Grams (m(m+1) l), two solves (m^2 l),
+        # three Cholesky (m^3/3) and two triangular products (m^3/3)
+        return "mfma", 3.0 * m * (m + 1) * l + 2.0 * m * m * l + 5.0 * m ** 3 / 3, "flops"
     if name == "rinv_trsm":
         return "mfma", m ** 3 / 3.0, "flops"
     if name == "w_gemm":
@@ -111,6 +115,8 @@ def main():
     ap.add_argument("--workload", default="plain_512x65536",
                     help="plain_512x65536 or plain_64x4096 (single-instance binary64 workloads)")
     ap.add_argument("--refine-steps", type=int, default=-1, help="-1: chosen from the pivoted-QR rank estimate")
+    ap.add_argument("--qr", type=int, default=0, help="pivoted-QR method: 0 auto, 1 direct, 2 two-stage, "
+                                                      "3 two-stage with a single-workgroup second stage")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -146,6 +152,7 @@ def main():
         copy_calibration(args.copy_calibration)
     plan = rt.Plan(m, n, l, seed)
     plan.set_refinement(args.refine_steps, 0.0)
+    plan.set_qr(args.qr)
 
     def step():
         plan.precondition(At)
@@ -210,6 +217,7 @@ def main():
         "stages": stages,
         "kappa_est": info["kappa_est"],
         "qrcp_blocks": info["qrcp_blocks"],
+        "qr_mode": info["qr_mode"],
     }
 
     cpu_sample = None

@@ -76,6 +76,20 @@ typedef enum {
                                    accumulation; P^{-1}A as in MIXED_FP32             */
 } rtproj_precision;
 
+/* How the pivoted QR of the sketch (eq. QR_decomp) is computed.  All modes
+ * give the same R and pivots in exact arithmetic; the two-stage modes are
+ * backward stable in the normwise sense (the QR of the small factor R0 of
+ * S^T = Q0 R0 has the same column norms as S^T at every step). */
+typedef enum {
+    RTPROJ_QR_AUTO = 0,         /* chosen by the plan from the sizes              */
+    RTPROJ_QR_DIRECT = 1,       /* Householder QRCP of S^T (l x m), one
+                                   cooperative launch                            */
+    RTPROJ_QR_TWO_STAGE = 2,    /* S^T = Q0 R0 by shifted Cholesky QR (three
+                                   Gram/Cholesky passes on MFMA, binary64), then
+                                   the cooperative QRCP of R0 (m x m)            */
+    RTPROJ_QR_TWO_STAGE_WG = 3  /* as 2, the QRCP of R0 in one workgroup         */
+} rtproj_qr_mode;
+
 typedef struct {
     int64_t m, n, l;           /* sizes of the plan                                  */
     int64_t np;                /* padded Fourier length of the sketch               */
@@ -95,9 +109,11 @@ typedef struct {
      * Stages: 0 sketch, 1 pivoted QR, 2 R^{-T} solve, 3 P^{-1}A product, 4 Gram,
      * 5 Cholesky, 6 L^{-1}R^{-T} solve, 7 A b, 8 applications of (AA^T)^{-1},
      * 9 refinement residual b - A^T x, 10 refinement product A r,
-     * 11 final A^T x and b - A^T x, 12..15 unused. */
+     * 11 final A^T x and b - A^T x, 12 the small factor R0 of the two-stage
+     * pivoted QR, 13..15 unused. */
     double t_stage_ms[16];
     int64_t stage_calls[16];
+    int qr_mode;               /* rtproj_qr_mode used by the last precondition       */
 } rtproj_info;
 
 /*
@@ -117,6 +133,11 @@ rtproj_status rtproj_plan_set_stream(rtproj_plan plan, void *hip_stream);
 /* Precision of the preconditioner (rtproj_precision).  Takes effect at the
  * next rtproj_precondition. */
 rtproj_status rtproj_plan_set_precision(rtproj_plan plan, int precision);
+
+/* Method of the pivoted QR of the sketch (rtproj_qr_mode).  Takes effect at
+ * the next rtproj_precondition; RTPROJ_ERR_UNSUPPORTED if the mode cannot
+ * handle the plan's sizes. */
+rtproj_status rtproj_plan_set_qr(rtproj_plan plan, int mode);
 
 /*
  * Iterative refinement of the least-squares solution (Remark 4.3): up to
@@ -192,6 +213,50 @@ rtproj_status rtproj_plan_export(rtproj_plan plan, double *S, int64_t lds, doubl
  */
 rtproj_status rtproj_sketch_tables(rtproj_plan plan, int64_t *dims3, int8_t *sign,
                                    int32_t *sigma, int32_t *tau, int32_t *J);
+
+/*
+ * Batches: `count` independent problems of uneven sizes (member i is an
+ * m[i] x n[i] matrix sketched to l[i] columns, 1 <= m[i] <= l[i] <= n[i],
+ * m[i] <= 2048), preconditioned and projected together with ONE grouped
+ * launch per stage of the path for all members.  The pivoted QR of member i
+ * is the two-stage form (S^T = Q0 R0 by shifted Cholesky QR, then the QRCP of
+ * R0 in one workgroup per member), so no step waits on the host: rank tests
+ * and factorization breakdowns are reported afterwards by
+ * rtproj_batch_status.  Member i's sketch seed is the first output of
+ * SplitMix64 seeded with seed XOR i.  All arithmetic is binary64 with
+ * compensated refinement residuals, as for a plan.
+ *
+ * Array arguments (A, lda, B, ldb, k, Z, ...) are HOST arrays of `count`
+ * entries; the pointers in them are device pointers with the layouts of
+ * the single-problem calls.  A[i] is borrowed as for rtproj_precondition.
+ * With rtproj_batch_set_graph(batch, 1) each entry point records its grouped
+ * launches into a HIP graph on first use and replays it while the arguments
+ * (pointers, sizes, k) stay the same.  Calls are asynchronous on the batch's
+ * stream except when new arguments must be uploaded (a short host wait).
+ */
+typedef struct rtproj_batch_s *rtproj_batch;
+
+rtproj_status rtproj_batch_create(int64_t count, const int64_t *m, const int64_t *n, const int64_t *l, uint64_t seed,
+                                  rtproj_batch *out);
+rtproj_status rtproj_batch_destroy(rtproj_batch batch);
+rtproj_status rtproj_batch_set_stream(rtproj_batch batch, void *hip_stream);
+/* Refinement steps (0..64, default 2) applied to every member: x <- x +
+ * M^{-1} A (b - A^T x) with compensated residuals (Remark 4.3). */
+rtproj_status rtproj_batch_set_refinement(rtproj_batch batch, int steps);
+/* 1: capture each entry point's launches into a HIP graph and replay it. */
+rtproj_status rtproj_batch_set_graph(rtproj_batch batch, int enable);
+rtproj_status rtproj_batch_precondition(rtproj_batch batch, const double *const *A, const int64_t *lda);
+/* As rtproj_project_all per member; Z, Y, X (or their entries) may be NULL;
+ * k[i] = 0 skips member i. */
+rtproj_status rtproj_batch_project_all(rtproj_batch batch, const double *const *B, const int64_t *ldb,
+                                       const int64_t *k, double *const *Z, const int64_t *ldz, double *const *Y,
+                                       const int64_t *ldy, double *const *X, const int64_t *ldx);
+/* Waits for the batch's stream and reports, per member (per_member may be
+ * NULL), RTPROJ_OK or RTPROJ_ERR_RANK (|R_mm| <= m 2^-52 |R_11|, a NaN in A,
+ * or a Cholesky breakdown); returns the worst. */
+rtproj_status rtproj_batch_status(rtproj_batch batch, int *per_member);
+/* Sizes and the rank estimates of member i (valid after rtproj_batch_status). */
+rtproj_status rtproj_batch_member_info(rtproj_batch batch, int64_t i, rtproj_info *out);
 
 const char *rtproj_status_string(rtproj_status status);
 const char *rtproj_last_error(void);

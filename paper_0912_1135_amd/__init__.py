@@ -38,10 +38,12 @@ class _Info(ctypes.Structure):
                 ("qrcp_blocks", ctypes.c_int), ("sketch_bits", ctypes.c_int), ("w_bits", ctypes.c_int),
                 ("gram_bits", ctypes.c_int), ("sketch_escalated", ctypes.c_int), ("gram_cond_est", ctypes.c_double),
                 ("t_stage_ms", ctypes.c_double * 16),
-                ("stage_calls", ctypes.c_int64 * 16)]
+                ("stage_calls", ctypes.c_int64 * 16),
+                ("qr_mode", ctypes.c_int)]
 
 STAGES = ["sketch", "qrcp", "rinv_trsm", "w_gemm", "gram_syrk", "cholesky", "t_trsm", "ab",
-          "minv", "refine_atx", "refine_ab", "final_atx"]
+          "minv", "refine_atx", "refine_ab", "final_atx", "qr_r0"]
+QR_AUTO, QR_DIRECT, QR_TWO_STAGE, QR_TWO_STAGE_WG = 0, 1, 2, 3
 
 
 def lib():
@@ -58,6 +60,7 @@ def lib():
         L.rtproj_plan_set_stream.argtypes = [vp, vp]
         L.rtproj_plan_set_precision.argtypes = [vp, ip]
         L.rtproj_plan_set_refinement.argtypes = [vp, ip, dp]
+        L.rtproj_plan_set_qr.argtypes = [vp, ip]
         L.rtproj_precondition.argtypes = [vp, vp, i64]
         L.rtproj_project_null.argtypes = [vp, vp, i64, i64, vp, i64]
         L.rtproj_project_row.argtypes = [vp, vp, i64, i64, vp, i64]
@@ -67,14 +70,26 @@ def lib():
         L.rtproj_plan_set_timing.argtypes = [vp, ip]
         L.rtproj_plan_export.argtypes = [vp, vp, i64, vp, vp, vp]
         L.rtproj_sketch_tables.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.rtproj_batch_create.argtypes = [i64, vp, vp, vp, u64, ctypes.POINTER(vp)]
+        L.rtproj_batch_destroy.argtypes = [vp]
+        L.rtproj_batch_set_stream.argtypes = [vp, vp]
+        L.rtproj_batch_set_refinement.argtypes = [vp, ip]
+        L.rtproj_batch_set_graph.argtypes = [vp, ip]
+        L.rtproj_batch_precondition.argtypes = [vp, vp, vp]
+        L.rtproj_batch_project_all.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.rtproj_batch_status.argtypes = [vp, vp]
+        L.rtproj_batch_member_info.argtypes = [vp, i64, ctypes.POINTER(_Info)]
         L.rtproj_status_string.argtypes = [ip]
         L.rtproj_status_string.restype = ctypes.c_char_p
         L.rtproj_last_error.restype = ctypes.c_char_p
         for name in ["rtproj_plan_create", "rtproj_plan_destroy", "rtproj_plan_set_stream",
-                     "rtproj_plan_set_precision", "rtproj_plan_set_refinement", "rtproj_precondition",
+                     "rtproj_plan_set_precision", "rtproj_plan_set_refinement", "rtproj_plan_set_qr", "rtproj_precondition",
                      "rtproj_project_null", "rtproj_project_row", "rtproj_lstsq", "rtproj_project_all",
                      "rtproj_plan_info", "rtproj_plan_export", "rtproj_sketch_tables",
-                     "rtproj_plan_set_timing"]:
+                     "rtproj_plan_set_timing", "rtproj_batch_create", "rtproj_batch_destroy",
+                     "rtproj_batch_set_stream", "rtproj_batch_set_refinement", "rtproj_batch_set_graph",
+                     "rtproj_batch_precondition", "rtproj_batch_project_all", "rtproj_batch_status",
+                     "rtproj_batch_member_info"]:
             getattr(L, name).restype = ip
         _lib = L
     return _lib
@@ -130,6 +145,10 @@ class Plan:
 
     def set_precision(self, precision: int):
         _check(lib().rtproj_plan_set_precision(self.handle, precision))
+
+    def set_qr(self, mode: int):
+        """Pivoted-QR method (QR_AUTO, QR_DIRECT, QR_TWO_STAGE, QR_TWO_STAGE_WG)."""
+        _check(lib().rtproj_plan_set_qr(self.handle, mode))
 
     def set_refinement(self, max_steps: int, rtol: float = 0.0):
         _check(lib().rtproj_plan_set_refinement(self.handle, max_steps, rtol))
@@ -213,3 +232,97 @@ class Plan:
         _check(lib().rtproj_sketch_tables(self.handle, None, sign.ctypes.data, sigma.ctypes.data,
                                           tau.ctypes.data, J.ctypes.data))
         return dict(np=np_, n1=n1, n2=n2, sign=sign, sigma=sigma, tau=tau, J=J)
+
+
+def _ptrs(ts):
+    arr = (ctypes.c_void_p * len(ts))(*[t.data_ptr() if t is not None else None for t in ts])
+    return arr
+
+
+def _i64s(vals):
+    return (ctypes.c_int64 * len(vals))(*vals)
+
+
+class Batch:
+    """Many independent problems of uneven sizes, one grouped launch per stage
+    (rtproj_batch).  Member i: an m[i] x n[i] matrix sketched to l[i] columns."""
+
+    def __init__(self, ms, ns, ls, seed: int, stream=None):
+        assert len(ms) == len(ns) == len(ls) and len(ms) > 0
+        h = ctypes.c_void_p()
+        self.count = len(ms)
+        self.ms, self.ns, self.ls = list(ms), list(ns), list(ls)
+        _check(lib().rtproj_batch_create(self.count, _i64s(self.ms), _i64s(self.ns), _i64s(self.ls), seed,
+                                         ctypes.byref(h)))
+        self.handle = h
+        self._A = None
+        self.set_stream(stream)
+
+    def close(self):
+        if self.handle:
+            lib().rtproj_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream=None):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().rtproj_batch_set_stream(self.handle, ctypes.c_void_p(s.cuda_stream)))
+
+    def set_refinement(self, steps: int):
+        _check(lib().rtproj_batch_set_refinement(self.handle, steps))
+
+    def set_graph(self, enable: bool):
+        _check(lib().rtproj_batch_set_graph(self.handle, 1 if enable else 0))
+
+    def precondition(self, As):
+        assert len(As) == self.count
+        for i, A in enumerate(As):
+            _check_tensor(A, f"A[{i}]", self.ms[i], self.ns[i])
+        _check(lib().rtproj_batch_precondition(self.handle, _ptrs(As), _i64s([A.stride(0) for A in As])))
+        self._A = list(As)  # borrowed
+
+    def project_all(self, Bs, Zs=None, Ys=None, Xs=None):
+        """Bs[i]: (k_i, n_i) float64 CUDA tensors; outputs are allocated when
+        not given (pass False to skip one kind)."""
+        import torch
+        assert len(Bs) == self.count
+        ks = []
+        for i, B in enumerate(Bs):
+            _check_tensor(B, f"B[{i}]", None, self.ns[i])
+            ks.append(B.shape[0])
+
+        def outs(given, shape_fn):
+            if given is False:
+                return None
+            if given is None:
+                return [torch.empty(shape_fn(i), dtype=torch.float64, device=Bs[i].device) for i in range(self.count)]
+            return list(given)
+
+        Z = outs(Zs, lambda i: (ks[i], self.ns[i]))
+        Y = outs(Ys, lambda i: (ks[i], self.ns[i]))
+        X = outs(Xs, lambda i: (ks[i], self.ms[i]))
+
+        def arr(ts):
+            return (_ptrs(ts), _i64s([t.stride(0) for t in ts])) if ts is not None else (None, None)
+
+        (zp, zl), (yp, yl), (xp, xl) = arr(Z), arr(Y), arr(X)
+        _check(lib().rtproj_batch_project_all(self.handle, _ptrs(Bs), _i64s([B.stride(0) for B in Bs]), _i64s(ks),
+                                              zp, zl, yp, yl, xp, xl))
+        return Z, Y, X
+
+    def status(self):
+        """Per-member status codes (waits for the batch's stream)."""
+        per = (ctypes.c_int * self.count)()
+        lib().rtproj_batch_status(self.handle, per)
+        return list(per)
+
+    def member_info(self, i: int) -> dict:
+        inf = _Info()
+        _check(lib().rtproj_batch_member_info(self.handle, i, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in _Info._fields_ if f not in ("t_stage_ms", "stage_calls")}

@@ -25,14 +25,14 @@ constexpr int AB_KJ = 16;   // right-hand sides per block
 // part[s][j][row] = sum_{t in split s} A[row][t] * B[t][j] (column-major m x k
 // per split).  dd: Dot2 accumulation, hi in part_hi and error in part_lo.
 template <bool DD>
-__global__ __launch_bounds__(256) void ab_partial_kernel(ApplyArgs a, const double *B, int64_t ldb, int splits,
-                                                         double *part_hi, double *part_lo)
+__device__ __forceinline__ void ab_partial_body(const ApplyArgs &a, const double *B, int64_t ldb, int splits,
+                                                double *part_hi, double *part_lo, int bx, int split, int bz)
 {
     __shared__ double As[AB_RB][AB_TC + 1];
     __shared__ double Bs[AB_TC][AB_KJ];
-    const int r0 = blockIdx.x * AB_RB;
-    const int split = blockIdx.y;
-    const int j0 = blockIdx.z * AB_KJ;
+    const int r0 = bx * AB_RB;
+    const int j0 = bz * AB_KJ;
+    if (r0 >= a.m || split >= splits || j0 >= a.k) return;  // whole block (grouped launches)
     const int64_t len = ((int64_t)a.n + splits - 1) / splits;
     const int64_t t0 = (int64_t)split * len;
     const int64_t t1 = min<int64_t>(a.n, t0 + len);
@@ -80,10 +80,24 @@ __global__ __launch_bounds__(256) void ab_partial_kernel(ApplyArgs a, const doub
     }
 }
 
-__global__ void ab_reduce_kernel(const double *ph, const double *pl, int m, int k, int splits, int dd, double *out,
-                                 int64_t ldo)
+template <bool DD>
+__global__ __launch_bounds__(256) void ab_partial_kernel(ApplyArgs a, const double *B, int64_t ldb, int splits,
+                                                         double *part_hi, double *part_lo)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    ab_partial_body<DD>(a, B, ldb, splits, part_hi, part_lo, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// grouped: blockIdx.z = member * kbmax + right-hand-side block
+template <bool DD>
+__global__ __launch_bounds__(256) void ab_partial_grouped(const AbGroupArgs *gs, int kbmax)
+{
+    const AbGroupArgs g = gs[blockIdx.z / kbmax];
+    ab_partial_body<DD>(g.a, g.B, g.ldb, g.splits, g.ph, g.pl, blockIdx.x, blockIdx.y, blockIdx.z % kbmax);
+}
+
+__device__ __forceinline__ void ab_reduce_body(const double *ph, const double *pl, int m, int k, int splits, int dd,
+                                               double *out, int64_t ldo, int64_t e)
+{
     if (e >= (int64_t)m * k) return;
     const int j = (int)(e / m), row = (int)(e % m);
     double s = 0.0, c = 0.0;
@@ -101,6 +115,18 @@ __global__ void ab_reduce_kernel(const double *ph, const double *pl, int m, int 
     out[(int64_t)j * ldo + row] = s + c;
 }
 
+__global__ void ab_reduce_kernel(const double *ph, const double *pl, int m, int k, int splits, int dd, double *out,
+                                 int64_t ldo)
+{
+    ab_reduce_body(ph, pl, m, k, splits, dd, out, ldo, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ void ab_reduce_grouped(const AbGroupArgs *gs, int dd)
+{
+    const AbGroupArgs g = gs[blockIdx.y];
+    ab_reduce_body(g.ph, g.pl, g.a.m, g.a.k, g.splits, dd, g.out, g.ldo, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 constexpr int ATX_T = 128;  // columns t of A per block (one per thread)
 constexpr int ATX_MC = 64;  // rows of x staged in LDS at a time
 
@@ -108,14 +134,15 @@ constexpr int ATX_MC = 64;  // rows of x staged in LDS at a time
 //   mode 0: R = round(B - y)
 //   mode 1: Y = round(y), Z = round(B - y)
 template <bool DD>
-__global__ __launch_bounds__(ATX_T) void atx_kernel(ApplyArgs a, const double *xhi, const double *xlo, int64_t ldx,
-                                                    const double *B, int64_t ldb, double *Rout, int64_t ldr,
-                                                    double *Y, int64_t ldy, double *Z, int64_t ldz)
+__device__ __forceinline__ void atx_body(const ApplyArgs &a, const double *xhi, const double *xlo, int64_t ldx,
+                                         const double *B, int64_t ldb, double *Rout, int64_t ldr, double *Y,
+                                         int64_t ldy, double *Z, int64_t ldz, int bx, int by)
 {
     __shared__ double xh[ATX_MC][AB_KJ];
     __shared__ double xl[ATX_MC][AB_KJ];
-    const int64_t t = (int64_t)blockIdx.x * ATX_T + threadIdx.x;
-    const int j0 = blockIdx.y * AB_KJ;
+    const int64_t t = (int64_t)bx * ATX_T + threadIdx.x;
+    const int j0 = by * AB_KJ;
+    if ((int64_t)bx * ATX_T >= a.n || j0 >= a.k) return;  // whole block (grouped launches)
     const int kj = min(AB_KJ, a.k - j0);
     double s[AB_KJ], c[AB_KJ];
 #pragma unroll
@@ -168,6 +195,21 @@ __global__ __launch_bounds__(ATX_T) void atx_kernel(ApplyArgs a, const double *x
     }
 }
 
+template <bool DD>
+__global__ __launch_bounds__(ATX_T) void atx_kernel(ApplyArgs a, const double *xhi, const double *xlo, int64_t ldx,
+                                                    const double *B, int64_t ldb, double *Rout, int64_t ldr,
+                                                    double *Y, int64_t ldy, double *Z, int64_t ldz)
+{
+    atx_body<DD>(a, xhi, xlo, ldx, B, ldb, Rout, ldr, Y, ldy, Z, ldz, blockIdx.x, blockIdx.y);
+}
+
+template <bool DD>
+__global__ __launch_bounds__(ATX_T) void atx_grouped(const AtxGroupArgs *gs)
+{
+    const AtxGroupArgs g = gs[blockIdx.z];
+    atx_body<DD>(g.a, g.xhi, g.xlo, g.ldx, g.B, g.ldb, g.Rout, g.ldr, g.Y, g.ldy, g.Z, g.ldz, blockIdx.x, blockIdx.y);
+}
+
 // out(i, j) = sum_r M[r*m + i] * V[r + j*ldv]  (out = M^T V, M row-major m x m)
 __global__ __launch_bounds__(256) void mtv_kernel(const double *M, int m, const double *V, int64_t ldv, double *out,
                                                   int64_t ldo)
@@ -186,8 +228,7 @@ __global__ __launch_bounds__(256) void mtv_kernel(const double *M, int m, const 
     out[(int64_t)j * ldo + i] = s0 + s1;
 }
 
-__global__ __launch_bounds__(256) void dd_update_kernel(double *xhi, double *xlo, const double *D, int total,
-                                                        double *norms)
+__device__ __forceinline__ void dd_update_body(double *xhi, double *xlo, const double *D, int total, double *norms)
 {
 #pragma clang fp contract(off)
     __shared__ double r0[256], r1[256];
@@ -219,14 +260,38 @@ __global__ __launch_bounds__(256) void dd_update_kernel(double *xhi, double *xlo
     }
 }
 
-__global__ void copy_cols_kernel(const double *src, int64_t lds, double *dst, int64_t ldd, int rows, int cols,
-                                 double *zero_out, int64_t ldz)
+__global__ __launch_bounds__(256) void dd_update_kernel(double *xhi, double *xlo, const double *D, int total,
+                                                        double *norms)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    dd_update_body(xhi, xlo, D, total, norms);
+}
+
+__global__ __launch_bounds__(256) void dd_update_grouped(const DdGroupArgs *gs)
+{
+    const DdGroupArgs g = gs[blockIdx.x];
+    dd_update_body(g.xhi, g.xlo, g.D, g.total, g.norms);
+}
+
+__device__ __forceinline__ void copy_cols_body(const double *src, int64_t lds, double *dst, int64_t ldd, int rows,
+                                               int cols, double *zero_out, int64_t ldz, int64_t e)
+{
     if (e >= (int64_t)rows * cols) return;
     const int j = (int)(e / rows), i = (int)(e % rows);
     dst[(int64_t)j * ldd + i] = src[(int64_t)j * lds + i];
     if (zero_out) zero_out[(int64_t)j * ldz + i] = 0.0;
+}
+
+__global__ void copy_cols_kernel(const double *src, int64_t lds, double *dst, int64_t ldd, int rows, int cols,
+                                 double *zero_out, int64_t ldz)
+{
+    copy_cols_body(src, lds, dst, ldd, rows, cols, zero_out, ldz, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ void copy_cols_grouped(const CopyGroupArgs *gs)
+{
+    const CopyGroupArgs g = gs[blockIdx.y];
+    copy_cols_body(g.src, g.lds, g.dst, g.ldd, g.rows, g.cols, g.zero_out, g.ldz,
+                   (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 }  // namespace
@@ -293,6 +358,47 @@ hipError_t copy_cols_f64(const double *src, int64_t lds, double *dst, int64_t ld
     if (total == 0) return hipSuccess;
     hipLaunchKernelGGL(copy_cols_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, src, lds, dst,
                        ldd, rows, cols, zero_out, ldz);
+    return hipGetLastError();
+}
+
+hipError_t ab_partial_grouped_f64(const AbGroupArgs *d, int count, int max_m, int max_k, int max_splits, int dd,
+                                  hipStream_t stream)
+{
+    if (count <= 0 || max_m <= 0 || max_k <= 0) return hipSuccess;
+    const int kb = (max_k + AB_KJ - 1) / AB_KJ;
+    dim3 grid((max_m + AB_RB - 1) / AB_RB, max_splits, count * kb);
+    if (dd) hipLaunchKernelGGL(ab_partial_grouped<true>, grid, dim3(256), 0, stream, d, kb);
+    else hipLaunchKernelGGL(ab_partial_grouped<false>, grid, dim3(256), 0, stream, d, kb);
+    return hipGetLastError();
+}
+
+hipError_t ab_reduce_grouped_f64(const AbGroupArgs *d, int count, int64_t max_mk, int dd, hipStream_t stream)
+{
+    if (count <= 0 || max_mk <= 0) return hipSuccess;
+    hipLaunchKernelGGL(ab_reduce_grouped, dim3((unsigned)((max_mk + 255) / 256), count), dim3(256), 0, stream, d, dd);
+    return hipGetLastError();
+}
+
+hipError_t atx_grouped_f64(const AtxGroupArgs *d, int count, int64_t max_n, int max_k, int dd, hipStream_t stream)
+{
+    if (count <= 0 || max_n <= 0 || max_k <= 0) return hipSuccess;
+    dim3 grid((unsigned)((max_n + ATX_T - 1) / ATX_T), (max_k + AB_KJ - 1) / AB_KJ, count);
+    if (dd) hipLaunchKernelGGL(atx_grouped<true>, grid, dim3(ATX_T), 0, stream, d);
+    else hipLaunchKernelGGL(atx_grouped<false>, grid, dim3(ATX_T), 0, stream, d);
+    return hipGetLastError();
+}
+
+hipError_t dd_update_grouped_f64(const DdGroupArgs *d, int count, hipStream_t stream)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dd_update_grouped, dim3(count), dim3(256), 0, stream, d);
+    return hipGetLastError();
+}
+
+hipError_t copy_cols_grouped_f64(const CopyGroupArgs *d, int count, int64_t max_total, hipStream_t stream)
+{
+    if (count <= 0 || max_total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(copy_cols_grouped, dim3((unsigned)((max_total + 255) / 256), count), dim3(256), 0, stream, d);
     return hipGetLastError();
 }
 

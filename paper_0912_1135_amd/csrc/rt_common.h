@@ -65,6 +65,21 @@ struct GemmArgs {
 // Launches GEMM with 64x64 or 128x128 tiles (chosen from M, N).
 hipError_t gemm_f64(const GemmArgs &g, hipStream_t stream);
 
+// Grouped GEMM: one launch over `count` problems whose GemmArgs live in
+// device memory.  Every member must share the operand layouts (a_k == 1,
+// b_k == 1) and c_lower given here; M, N and ksplit here are the maxima
+// over the members (the grid covers them; smaller members skip the tiles
+// they do not have).  64 x 64 tiles.
+struct GemmShape {
+    int M, N, ksplit;
+    int a_kc, b_kc, c_lower;
+};
+hipError_t gemm_f64_grouped(const GemmArgs *d_args, int count, const GemmShape &shape, hipStream_t stream);
+struct ReduceGroupArgs {
+    const double *part; int64_t stride; int splits, M, N; int64_t ld; double *out; int64_t ldo; int mirror;
+};
+hipError_t reduce_splits_grouped_f64(const ReduceGroupArgs *d, int count, int64_t max_total, hipStream_t stream);
+
 // out(i,j) = sum_{s<splits} part[s*stride + i*ld + j] for i,j < M x N
 // (row-major, fixed summation order); if mirror, out(j,i) = out(i,j) too and
 // only i >= j is summed.
@@ -113,6 +128,13 @@ struct SketchTables {
 // the intermediate (rows_chunk/2 x np complex binary64).
 hipError_t sketch_f64(const SketchTables &t, const double *A, int64_t lda, int64_t m,
                       double *S, int64_t lds, double *zbuf, int64_t rows_chunk, hipStream_t stream);
+// Grouped sketch over many problems (one launch pair per row chunk).
+struct SketchGroupArgs {
+    SketchTables t; const double *A; int64_t lda, m; double *S; int64_t lds;
+    double *zbuf; int64_t rows_chunk;
+};
+struct SketchGroupShape { int64_t max_n1, max_n2, max_rows_chunk; int chunks; };
+hipError_t sketch_grouped_f64(const SketchGroupArgs *d, int count, const SketchGroupShape &sh, hipStream_t stream);
 // Same sketch with the transform in binary32 (A rounded on load; S written in
 // binary64).
 hipError_t sketch_f32(const SketchTables &t, const double *A, int64_t lda, int64_t m,
@@ -137,6 +159,19 @@ hipError_t qrcp_f64(const double *S, int64_t lds, int rows, int cols, double *R,
 int qrcp_max_blocks(int rows, int cols, int cu_count, size_t lds_max, int *global_cols);
 hipError_t zero_u32(unsigned *p, int n, hipStream_t stream);
 
+// Column-pivoted QR of one matrix per workgroup (no grid synchronization):
+// M is column-major rows x cols (ld ldm) and is overwritten; R (cols x cols
+// row-major, upper part written) and piv (cols) as for qrcp_f64; *err = 2
+// when only NaN norms remain.  rows <= qrcp_wg_max_rows(), cols <=
+// qrcp_wg_max_cols().
+struct QrcpWgArgs {
+    double *M; int64_t ldm; int rows, cols;
+    double *R; int32_t *piv; int *err;
+};
+hipError_t qrcp_wg_f64(const QrcpWgArgs *d_args, int count, hipStream_t stream);
+int qrcp_wg_max_rows();
+int qrcp_wg_max_cols();
+
 // ---------------------------------------------------------------- factor
 // Inverse of each nb x nb diagonal block of the lower-triangular matrix
 // L(i,j) = T[i*t_i + j*t_j] (j <= i), m x m; Dinv: nblk blocks of nb*nb
@@ -149,6 +184,23 @@ hipError_t tri_diag_inv_f64(const double *T, int64_t t_i, int64_t t_j, int m, in
 hipError_t chol_diag_f64(const double *X, int64_t ldx, int m, int nb, int b, double *L, int64_t ldl,
                          double *Dinv, int *err, hipStream_t stream);
 // Set a row-major m x n matrix to the identity (or zero if ident = 0).
+// grouped forms of the factor kernels (one problem per blockIdx.y or .x)
+struct CholGroupArgs { const double *X; int64_t ldx; int m; double *L; int64_t ldl; double *Dinv; int *err; };
+hipError_t chol_diag_grouped_f64(const CholGroupArgs *d, int count, int nb, int b, hipStream_t stream);
+struct TriInvGroupArgs { const double *T; int64_t t_i, t_j; int m; double *Dinv; };
+hipError_t tri_diag_inv_grouped_f64(const TriInvGroupArgs *d, int count, int max_m, int nb, hipStream_t stream);
+struct MatGroupArgs { double *X; int64_t ld; int m, n; double c; const int32_t *piv; double *out; };
+// X = 0 (ident = 0) or I (ident = 1), m x n
+hipError_t set_matrix_grouped_f64(const MatGroupArgs *d, int count, int64_t max_total, int ident, hipStream_t stream);
+// X[i][i] += c * trace(X), m x m
+hipError_t shift_diag_grouped_f64(const MatGroupArgs *d, int count, hipStream_t stream);
+// out[0..3] as rdiag_ends_f64 for the m x m X
+hipError_t rdiag_grouped_f64(const MatGroupArgs *d, int count, hipStream_t stream);
+// out = [T'^T; T'] for T = X (m x m), T' = T Pi with piv
+hipError_t form_tp_grouped_f64(const MatGroupArgs *d, int count, int64_t max_total, hipStream_t stream);
+
+// G[i][i] += c * trace(G) for the m x m matrix G (one block).
+hipError_t shift_diag_f64(double *G, int64_t ld, int m, double c, hipStream_t stream);
 hipError_t set_matrix_f64(double *X, int64_t ld, int m, int n, int ident, hipStream_t stream);
 // Zero the strictly upper (upper = 1) or strictly lower part of a row-major m x m matrix.
 hipError_t zero_triangle_f64(double *X, int64_t ld, int m, int upper, hipStream_t stream);
@@ -176,6 +228,27 @@ hipError_t ab_reduce_f64(const double *part_hi, const double *part_lo, int m, in
 hipError_t atx_f64(const ApplyArgs &a, const double *Xhi, const double *Xlo, int64_t ldx,
                    const double *B, int64_t ldb, double *Rout, int64_t ldr,
                    double *Y, int64_t ldy, double *Z, int64_t ldz, int dd, hipStream_t stream);
+// ---- grouped (batched) forms: one launch over many problems whose
+// arguments live in device memory; the grid covers the largest member and
+// smaller members skip the blocks they do not have.
+struct AbGroupArgs {       // c = A B (partials + reduction)
+    ApplyArgs a; const double *B; int64_t ldb; int splits;
+    double *ph, *pl;       // splits * m * k partials
+    double *out; int64_t ldo;
+};
+hipError_t ab_partial_grouped_f64(const AbGroupArgs *d, int count, int max_m, int max_k, int max_splits, int dd,
+                                  hipStream_t stream);
+hipError_t ab_reduce_grouped_f64(const AbGroupArgs *d, int count, int64_t max_mk, int dd, hipStream_t stream);
+struct AtxGroupArgs {      // as atx_f64
+    ApplyArgs a; const double *xhi, *xlo; int64_t ldx; const double *B; int64_t ldb;
+    double *Rout; int64_t ldr; double *Y; int64_t ldy; double *Z; int64_t ldz;
+};
+hipError_t atx_grouped_f64(const AtxGroupArgs *d, int count, int64_t max_n, int max_k, int dd, hipStream_t stream);
+struct DdGroupArgs { double *xhi, *xlo; const double *D; int total; double *norms; };
+hipError_t dd_update_grouped_f64(const DdGroupArgs *d, int count, hipStream_t stream);
+struct CopyGroupArgs { const double *src; int64_t lds; double *dst; int64_t ldd; int rows, cols; double *zero_out; int64_t ldz; };
+hipError_t copy_cols_grouped_f64(const CopyGroupArgs *d, int count, int64_t max_total, hipStream_t stream);
+
 // H (m x k, col-major) = Pi^T T^T T Pi C  (the seven-step core with
 // P^{-1} = R^{-T} Pi and Y = X^{-1} = L^{-T} L^{-1} folded into T = L^{-1} R^{-T}).
 // tmp: m*k doubles.

@@ -10,44 +10,74 @@ namespace rt {
 namespace {
 
 constexpr int NBMAX = 64;
+constexpr int LDP = NBMAX + 1;                  // padded LDS row stride
+constexpr int DT = 256;                         // threads of the diagonal-block kernels
+constexpr int NTRI = NBMAX * (NBMAX + 1) / 2;   // entries of a 64 x 64 lower triangle
+constexpr int NE = (NTRI + DT - 1) / DT;        // entries owned per thread
 
-constexpr int LDP = NBMAX + 1;  // padded LDS row stride
-
-// X = L^{-1} for the NBMAX x NBMAX lower-triangular L in LDS (row stride LDP).
-// Columns are independent: four lanes own column j = tid/4 and split the dot
-// products of the forward substitution
-//   X[i][j] = -(sum_{j<=k<i} L[i][k] X[k][j]) / L[i][i],  X[j][j] = 1/L[j][j],
-// so no block barrier is needed inside.
-__device__ void lower_inverse_lds(const double *L, double *X)
+// Thread t owns the lower-triangle entries e = t + DT*s (row-wise order
+// e = i(i+1)/2 + c, c <= i) and keeps them in registers; slots past the
+// triangle get row -1 and never match.
+__device__ __forceinline__ void tri_slots(int *ri, int *ci)
 {
-    const int j = threadIdx.x >> 2, q = threadIdx.x & 3;
-    for (int i = 0; i < NBMAX; ++i) {
-        double s = 0.0;
-        if (i > j)
-            for (int k = j + q; k < i; k += 4) s += L[i * LDP + k] * X[k * LDP + j];
-        s += __shfl_xor(s, 1, 64);
-        s += __shfl_xor(s, 2, 64);
-        if (q == 0) {
-            const double d = L[i * LDP + i];
-            X[i * LDP + j] = (i > j) ? -s / d : ((i == j) ? 1.0 / d : 0.0);
-        }
-        // the four lanes of a column are in one wave: they see each other's
-        // LDS writes after a wave-level barrier
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int s = 0; s < NE; ++s) {
+        const int e = threadIdx.x + DT * s;
+        int i = (int)((__builtin_sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+        while ((i + 1) * (i + 2) / 2 <= e) ++i;
+        while (i * (i + 1) / 2 > e) --i;
+        ri[s] = e < NTRI ? i : -1;
+        ci[s] = e < NTRI ? e - i * (i + 1) / 2 : NBMAX;
     }
+}
+
+// X = L^{-1} for the lower-triangular L in LDS (row stride LDP), written to
+// X (row stride LDP; may not alias L).  Right-looking row sweep of L X = I:
+// at step k row k of X has received every update from the rows above, is
+// divided by L[k][k] and broadcast, and every lower row i > k subtracts
+// L[i][k] times it.  One block barrier per step.
+__device__ void lower_inverse_block(const double *L, double *X, const int *ri, const int *ci)
+{
+    __shared__ double rowb[2][NBMAX];
+    double x[NE];
+#pragma unroll
+    for (int s = 0; s < NE; ++s) x[s] = (ri[s] == ci[s]) ? 1.0 : 0.0;
+    for (int k = 0; k < NBMAX; ++k) {
+        const double rk = 1.0 / L[k * LDP + k];
+        double *rb = rowb[k & 1];
+#pragma unroll
+        for (int s = 0; s < NE; ++s)
+            if (ri[s] == k) {
+                x[s] *= rk;
+                rb[ci[s]] = x[s];
+            }
+        __syncthreads();
+        // branch-free update of the rows below k (entries with ci <= k < ri)
+#pragma unroll
+        for (int s = 0; s < NE; ++s) {
+            const int r = ri[s] > k ? ri[s] : k;
+            const double u = L[r * LDP + k] * rb[ci[s] <= k ? ci[s] : 0];
+            x[s] = (ri[s] > k && ci[s] <= k) ? x[s] - u : x[s];
+        }
+    }
+    for (int e = threadIdx.x; e < NBMAX * NBMAX; e += DT) X[(e / NBMAX) * LDP + (e % NBMAX)] = 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < NE; ++s)
+        if (ri[s] >= 0) X[ri[s] * LDP + ci[s]] = x[s];
     __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void tri_diag_inv_kernel(const double *T, int64_t t_i, int64_t t_j, int m, int nb,
-                                                           double *Dinv)
+__device__ __forceinline__ void tri_diag_inv_body(const double *T, int64_t t_i, int64_t t_j, int m, int nb,
+                                                  double *Dinv, int b)
 {
+    if (b * nb >= m) return;  // whole block (grouped launches)
     __shared__ double L[NBMAX * LDP];
     __shared__ double X[NBMAX * LDP];
-    const int b = blockIdx.x;
+    int ri[NE], ci[NE];
+    tri_slots(ri, ci);
     const int base = b * nb, nbb = min(nb, m - base);
-    for (int e = threadIdx.x; e < NBMAX * NBMAX; e += blockDim.x) {
+    for (int e = threadIdx.x; e < NBMAX * NBMAX; e += DT) {
         const int i = e / NBMAX, j = e % NBMAX;
         double v;
         if (i < nbb && j < nbb) v = (j <= i) ? T[(int64_t)(base + i) * t_i + (int64_t)(base + j) * t_j] : 0.0;
@@ -55,87 +85,139 @@ __global__ __launch_bounds__(256) void tri_diag_inv_kernel(const double *T, int6
         L[i * LDP + j] = v;
     }
     __syncthreads();
-    lower_inverse_lds(L, X);
+    lower_inverse_block(L, X, ri, ci);
     double *out = Dinv + (int64_t)b * nb * nb;
-    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) out[e] = X[(e / nb) * LDP + (e % nb)];
+    for (int e = threadIdx.x; e < nb * nb; e += DT) out[e] = X[(e / nb) * LDP + (e % nb)];
 }
 
-// Cholesky of one NBMAX x NBMAX diagonal block (right-looking).  Four lanes
-// own row i = tid/4 and split its columns by c mod 4.
-__global__ __launch_bounds__(256) void chol_diag_kernel(const double *Xg, int64_t ldx, int m, int nb, int b, double *Lg,
-                                                        int64_t ldl, double *Dinv, int *err)
+__global__ __launch_bounds__(DT) void tri_diag_inv_kernel(const double *T, int64_t t_i, int64_t t_j, int m, int nb,
+                                                          double *Dinv)
 {
-    __shared__ double A[NBMAX * LDP];
-    __shared__ double X[NBMAX * LDP];
-    __shared__ int bad;
+    tri_diag_inv_body(T, t_i, t_j, m, nb, Dinv, blockIdx.x);
+}
+
+__global__ __launch_bounds__(DT) void tri_diag_inv_grouped(const TriInvGroupArgs *gs, int nb)
+{
+    const TriInvGroupArgs g = gs[blockIdx.y];
+    tri_diag_inv_body(g.T, g.t_i, g.t_j, g.m, nb, g.Dinv, blockIdx.x);
+}
+
+// Cholesky of one 64 x 64 diagonal block (right-looking) and the inverse of
+// its factor.  At step j the owners of column j publish it (unscaled), every
+// thread reads the pivot d = A[j][j], finalizes its entries of column j
+// (L[i][j] = A[i][j] / sqrt(d), L[j][j] = sqrt(d)) and updates its trailing
+// entries A[i][c] -= A[i][j] A[c][j] / d.  The broadcast buffer alternates
+// between two halves, so one block barrier per step suffices.  A
+// non-positive or non-finite pivot sets *err (the outputs are then garbage).
+__device__ __forceinline__ void chol_diag_body(const double *Xg, int64_t ldx, int m, int nb, int b, double *Lg,
+                                               int64_t ldl, double *Dinv, int *err)
+{
+    if (b * nb >= m) return;  // whole block (grouped launches)
+    __shared__ double Ls[NBMAX * LDP];
+    __shared__ double Xs[NBMAX * LDP];
+    __shared__ double colb[2][NBMAX];
+    int ri[NE], ci[NE];
+    tri_slots(ri, ci);
     const int base = b * nb, nbb = min(nb, m - base);
-    for (int e = threadIdx.x; e < NBMAX * NBMAX; e += blockDim.x) {
-        const int i = e / NBMAX, j = e % NBMAX;
-        double v;
-        if (i < nbb && j < nbb) v = (j <= i) ? Xg[(int64_t)(base + i) * ldx + base + j] : 0.0;
-        else v = (i == j) ? 1.0 : 0.0;
-        A[i * LDP + j] = v;
-    }
-    if (threadIdx.x == 0) bad = 0;
-    __syncthreads();
-    __shared__ double colj[NBMAX];
-    __shared__ double diag[NBMAX];
-    const int i = threadIdx.x >> 2, q = threadIdx.x & 3;
-    for (int j = 0; j < NBMAX; ++j) {
-        const double d = A[j * LDP + j];
-        if (!(d > 0.0) || !isfinite(d)) {
-            if (threadIdx.x == 0) bad = 1;
-            break;
-        }
-        const double ljj = __builtin_sqrt(d);
-        // column j of L into its own vector, so the update below reads it
-        // without any dependence on the stores into A.  The diagonal entry is
-        // kept aside (every thread has just read A[j][j]) and stored after
-        // the loop.
-        if (q == 0 && i >= j) {
-            const double lij = (i == j) ? ljj : A[i * LDP + j] / ljj;
-            colj[i] = lij;
-            if (i == j) diag[j] = ljj;
-            else A[i * LDP + j] = lij;
-        }
-        __syncthreads();
-        if (i > j) {
-            const double lij = colj[i];
-            const int c0 = j + 1 + ((q - (j + 1)) & 3);
+    double a[NE];
 #pragma unroll
-            for (int r = 0; r < NBMAX / 4; ++r) {
-                const int c = c0 + 4 * r;
-                if (c <= i) A[i * LDP + c] -= lij * colj[c];
-            }
+    for (int s = 0; s < NE; ++s) {
+        const int i = ri[s], c = ci[s];
+        double v = 0.0;
+        if (i >= 0) {
+            if (i < nbb && c < nbb) v = Xg[(int64_t)(base + i) * ldx + base + c];
+            else v = (i == c) ? 1.0 : 0.0;
         }
+        a[s] = v;
+    }
+    bool bad = false;
+    for (int j = 0; j < NBMAX; ++j) {
+        double *cb = colb[j & 1];
+#pragma unroll
+        for (int s = 0; s < NE; ++s)
+            if (ci[s] == j) cb[ri[s]] = a[s];
+        __syncthreads();
+        const double d = cb[j];
+        bad |= !(d > 0.0 && d < INFINITY);
+        const double ljj = __builtin_sqrt(d);
+        const double rl = 1.0 / ljj;
+        const double inv_d = rl * rl;
+        // branch-free: finalize column j, update the entries right of it
+#pragma unroll
+        for (int s = 0; s < NE; ++s) {
+            const int r = ri[s] > j ? ri[s] : j, c = ci[s] > j && ci[s] < NBMAX ? ci[s] : j;
+            const double u = cb[r] * cb[c] * inv_d;
+            const double fin = (ri[s] == j) ? ljj : a[s] * rl;
+            a[s] = (ci[s] == j) ? fin : ((ci[s] > j && ri[s] >= 0) ? a[s] - u : a[s]);
+        }
+    }
+    for (int e = threadIdx.x; e < NBMAX * NBMAX; e += DT) Ls[(e / NBMAX) * LDP + (e % NBMAX)] = 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < NE; ++s)
+        if (ri[s] >= 0) Ls[ri[s] * LDP + ci[s]] = a[s];
+    __syncthreads();
+    for (int e = threadIdx.x; e < nbb * nbb; e += DT) {
+        const int r = e / nbb, c = e % nbb;
+        Lg[(int64_t)(base + r) * ldl + base + c] = Ls[r * LDP + c];
+    }
+    lower_inverse_block(Ls, Xs, ri, ci);
+    double *out = Dinv + (int64_t)b * nb * nb;
+    for (int e = threadIdx.x; e < nb * nb; e += DT) out[e] = Xs[(e / nb) * LDP + (e % nb)];
+    if (bad && threadIdx.x == 0) atomicExch(err, 1);
+}
+
+__global__ __launch_bounds__(DT) void chol_diag_kernel(const double *Xg, int64_t ldx, int m, int nb, int b, double *Lg,
+                                                       int64_t ldl, double *Dinv, int *err)
+{
+    chol_diag_body(Xg, ldx, m, nb, b, Lg, ldl, Dinv, err);
+}
+
+__global__ __launch_bounds__(DT) void chol_diag_grouped(const CholGroupArgs *gs, int nb, int b)
+{
+    const CholGroupArgs g = gs[blockIdx.x];
+    chol_diag_body(g.X, g.ldx, g.m, nb, b, g.L, g.ldl, g.Dinv, g.err);
+}
+
+__device__ __forceinline__ void shift_diag_body(double *G, int64_t ld, int m, double c)
+{
+    __shared__ double red[256];
+    double t = 0.0;
+    for (int i = threadIdx.x; i < m; i += 256) t += G[(int64_t)i * ld + i];
+    red[threadIdx.x] = t;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    __syncthreads();
-    if (bad) {
-        if (threadIdx.x == 0) atomicExch(err, 1);
-        return;
-    }
-    if (threadIdx.x < NBMAX) A[threadIdx.x * LDP + threadIdx.x] = diag[threadIdx.x];
-    for (int e = threadIdx.x; e < NBMAX * NBMAX; e += blockDim.x) {
-        const int r = e / NBMAX, c = e % NBMAX;
-        if (c > r) A[r * LDP + c] = 0.0;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < nbb * nbb; e += blockDim.x) {
-        const int r = e / nbb, c = e % nbb;
-        Lg[(int64_t)(base + r) * ldl + base + c] = A[r * LDP + c];
-    }
-    lower_inverse_lds(A, X);
-    double *out = Dinv + (int64_t)b * nb * nb;
-    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) out[e] = X[(e / nb) * LDP + (e % nb)];
+    const double sh = c * red[0];
+    for (int i = threadIdx.x; i < m; i += 256) G[(int64_t)i * ld + i] += sh;
+}
+
+__global__ void shift_diag_kernel(double *G, int64_t ld, int m, double c) { shift_diag_body(G, ld, m, c); }
+
+__global__ void shift_diag_grouped(const MatGroupArgs *gs)
+{
+    const MatGroupArgs g = gs[blockIdx.x];
+    shift_diag_body(g.X, g.ld, g.m, g.c);
+}
+
+__device__ __forceinline__ void set_matrix_body(double *X, int64_t ld, int m, int n, int ident, int64_t e)
+{
+    if (e >= (int64_t)m * n) return;
+    const int i = (int)(e / n), j = (int)(e % n);
+    X[(int64_t)i * ld + j] = (ident && i == j) ? 1.0 : 0.0;
 }
 
 __global__ void set_matrix_kernel(double *X, int64_t ld, int m, int n, int ident)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)m * n) return;
-    const int i = (int)(e / n), j = (int)(e % n);
-    X[(int64_t)i * ld + j] = (ident && i == j) ? 1.0 : 0.0;
+    set_matrix_body(X, ld, m, n, ident, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ void set_matrix_grouped(const MatGroupArgs *gs, int ident)
+{
+    const MatGroupArgs g = gs[blockIdx.y];
+    set_matrix_body(g.X, g.ld, g.m, g.n, ident, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 __global__ void zero_triangle_kernel(double *X, int64_t ld, int m, int upper)
@@ -146,7 +228,7 @@ __global__ void zero_triangle_kernel(double *X, int64_t ld, int m, int upper)
     if ((upper && j > i) || (!upper && j < i)) X[(int64_t)i * ld + j] = 0.0;
 }
 
-__global__ void rdiag_kernel(const double *R, int64_t ldr, int m, double *out)
+__device__ __forceinline__ void rdiag_body(const double *R, int64_t ldr, int m, double *out)
 {
     __shared__ double smin[256], smax[256];
     double lo = INFINITY, hi = 0.0;
@@ -174,17 +256,35 @@ __global__ void rdiag_kernel(const double *R, int64_t ldr, int m, double *out)
     }
 }
 
+__global__ void rdiag_kernel(const double *R, int64_t ldr, int m, double *out) { rdiag_body(R, ldr, m, out); }
+
+__global__ void rdiag_grouped(const MatGroupArgs *gs)
+{
+    const MatGroupArgs g = gs[blockIdx.x];
+    rdiag_body(g.X, g.ld, g.m, g.out);
+}
+
 // out[0] = T'^T and out[1] = T' (row-major m x m each) for T' = T Pi:
 // column piv[c] of T' is column c of T.
-__global__ void form_tp_kernel(const double *T, const int32_t *piv, int m, double *out)
+__device__ __forceinline__ void form_tp_body(const double *T, const int32_t *piv, int m, double *out, int64_t e)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (int64_t)m * m) return;
     const int r = (int)(e / m), c = (int)(e % m);
     const double v = T[e];
     const int pc = piv[c];
     out[(int64_t)pc * m + r] = v;
     out[(int64_t)m * m + (int64_t)r * m + pc] = v;
+}
+
+__global__ void form_tp_kernel(const double *T, const int32_t *piv, int m, double *out)
+{
+    form_tp_body(T, piv, m, out, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ void form_tp_grouped(const MatGroupArgs *gs)
+{
+    const MatGroupArgs g = gs[blockIdx.y];
+    form_tp_body(g.X, g.piv, g.m, g.out, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 }  // namespace
@@ -200,7 +300,7 @@ hipError_t tri_diag_inv_f64(const double *T, int64_t t_i, int64_t t_j, int m, in
 {
     if (nb != NBMAX) return hipErrorInvalidValue;
     const int nblk = (m + nb - 1) / nb;
-    hipLaunchKernelGGL(tri_diag_inv_kernel, dim3(nblk), dim3(256), 0, stream, T, t_i, t_j, m, nb, Dinv);
+    hipLaunchKernelGGL(tri_diag_inv_kernel, dim3(nblk), dim3(DT), 0, stream, T, t_i, t_j, m, nb, Dinv);
     return hipGetLastError();
 }
 
@@ -208,7 +308,13 @@ hipError_t chol_diag_f64(const double *X, int64_t ldx, int m, int nb, int b, dou
                          int *err, hipStream_t stream)
 {
     if (nb != NBMAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(256), 0, stream, X, ldx, m, nb, b, L, ldl, Dinv, err);
+    hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(DT), 0, stream, X, ldx, m, nb, b, L, ldl, Dinv, err);
+    return hipGetLastError();
+}
+
+hipError_t shift_diag_f64(double *G, int64_t ld, int m, double c, hipStream_t stream)
+{
+    hipLaunchKernelGGL(shift_diag_kernel, dim3(1), dim3(256), 0, stream, G, ld, m, c);
     return hipGetLastError();
 }
 
@@ -232,6 +338,51 @@ hipError_t zero_triangle_f64(double *X, int64_t ld, int m, int upper, hipStream_
 hipError_t rdiag_ends_f64(const double *R, int64_t ldr, int m, double *out, hipStream_t stream)
 {
     hipLaunchKernelGGL(rdiag_kernel, dim3(1), dim3(256), 0, stream, R, ldr, m, out);
+    return hipGetLastError();
+}
+
+hipError_t chol_diag_grouped_f64(const CholGroupArgs *d, int count, int nb, int b, hipStream_t stream)
+{
+    if (nb != NBMAX) return hipErrorInvalidValue;
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(chol_diag_grouped, dim3(count), dim3(DT), 0, stream, d, nb, b);
+    return hipGetLastError();
+}
+
+hipError_t tri_diag_inv_grouped_f64(const TriInvGroupArgs *d, int count, int max_m, int nb, hipStream_t stream)
+{
+    if (nb != NBMAX) return hipErrorInvalidValue;
+    if (count <= 0 || max_m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(tri_diag_inv_grouped, dim3((max_m + nb - 1) / nb, count), dim3(DT), 0, stream, d, nb);
+    return hipGetLastError();
+}
+
+hipError_t set_matrix_grouped_f64(const MatGroupArgs *d, int count, int64_t max_total, int ident, hipStream_t stream)
+{
+    if (count <= 0 || max_total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(set_matrix_grouped, dim3((unsigned)((max_total + 255) / 256), count), dim3(256), 0, stream, d,
+                       ident);
+    return hipGetLastError();
+}
+
+hipError_t shift_diag_grouped_f64(const MatGroupArgs *d, int count, hipStream_t stream)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(shift_diag_grouped, dim3(count), dim3(256), 0, stream, d);
+    return hipGetLastError();
+}
+
+hipError_t rdiag_grouped_f64(const MatGroupArgs *d, int count, hipStream_t stream)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(rdiag_grouped, dim3(count), dim3(256), 0, stream, d);
+    return hipGetLastError();
+}
+
+hipError_t form_tp_grouped_f64(const MatGroupArgs *d, int count, int64_t max_total, hipStream_t stream)
+{
+    if (count <= 0 || max_total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(form_tp_grouped, dim3((unsigned)((max_total + 255) / 256), count), dim3(256), 0, stream, d);
     return hipGetLastError();
 }
 

@@ -25,8 +25,11 @@ struct TileLayout {
     __device__ static int at(int mn, int k) { return KCONTIG ? mn * (KC + 1) + k : k * (T + 16) + mn; }
 };
 
+// One BM x BN output tile (bx, by) of split bz.  Tiles outside the problem
+// (possible in grouped launches, whose grid covers the largest member)
+// return at once; the whole block takes the same branch.
 template <int BM, int BN, bool A_KC, bool B_KC>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g)
+__device__ __forceinline__ void gemm_f64_tile(const GemmArgs &g, int bx, int by, int bz)
 {
     using LA = TileLayout<BM, A_KC>;
     using LB = TileLayout<BN, B_KC>;
@@ -39,21 +42,22 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g)
 
     int ti, tj;
     if (g.c_lower) {
-        const int t = blockIdx.x;
+        const int t = bx;
         ti = (int)((__builtin_sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
         while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
         while (ti * (ti + 1) / 2 > t) --ti;
         tj = t - ti * (ti + 1) / 2;
     } else {
-        ti = blockIdx.y;
-        tj = blockIdx.x;
+        ti = by;
+        tj = bx;
     }
     const int i0 = ti * BM, j0 = tj * BN;
+    if (i0 >= g.M || j0 >= g.N || bz >= (g.ksplit > 1 ? g.ksplit : 1)) return;
     int kbeg = 0, kend = g.K;
     if (g.ksplit > 1) {
         int ks = (g.K + g.ksplit - 1) / g.ksplit;
         ks = (ks + KC - 1) / KC * KC;
-        kbeg = blockIdx.z * ks;
+        kbeg = bz * ks;
         kend = min(g.K, kbeg + ks);
     }
     if (g.a_lower) kend = min(kend, i0 + BM);
@@ -135,7 +139,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g)
         buf ^= 1;
     }
 
-    double *C = g.C + (g.ksplit > 1 ? (int64_t)blockIdx.z * g.c_split : 0);
+    double *C = g.C + (g.ksplit > 1 ? (int64_t)bz * g.c_split : 0);
     const bool use_beta = (g.ksplit <= 1) && (g.beta != 0.0);
 #pragma unroll
     for (int a = 0; a < TM; ++a)
@@ -154,6 +158,20 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g)
             }
 }
 
+template <int BM, int BN, bool A_KC, bool B_KC>
+__global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g)
+{
+    gemm_f64_tile<BM, BN, A_KC, B_KC>(g, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Grouped launch: member blockIdx.z / ksmax, split blockIdx.z % ksmax.
+template <int BM, int BN, bool A_KC, bool B_KC>
+__global__ __launch_bounds__(256) void gemm_f64_grouped_kernel(const GemmArgs *gs, int ksmax)
+{
+    const GemmArgs g = gs[blockIdx.z / ksmax];
+    gemm_f64_tile<BM, BN, A_KC, B_KC>(g, blockIdx.x, blockIdx.y, blockIdx.z % ksmax);
+}
+
 template <int BM, int BN>
 hipError_t launch_tile(const GemmArgs &g, hipStream_t s)
 {
@@ -169,10 +187,9 @@ hipError_t launch_tile(const GemmArgs &g, hipStream_t s)
     return hipGetLastError();
 }
 
-__global__ void reduce_splits_kernel(const double *part, int64_t stride, int splits, int M, int N,
-                                     int64_t ld, double *out, int64_t ldo, int mirror)
+__device__ __forceinline__ void reduce_splits_body(const double *part, int64_t stride, int splits, int M, int N,
+                                                   int64_t ld, double *out, int64_t ldo, int mirror, int64_t e)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (int64_t)M * N) return;
     const int i = (int)(e / N), j = (int)(e % N);
     if (mirror && j > i) return;
@@ -180,6 +197,19 @@ __global__ void reduce_splits_kernel(const double *part, int64_t stride, int spl
     for (int p = 0; p < splits; ++p) s += part[p * stride + (int64_t)i * ld + j];
     out[(int64_t)i * ldo + j] = s;
     if (mirror) out[(int64_t)j * ldo + i] = s;
+}
+
+__global__ void reduce_splits_kernel(const double *part, int64_t stride, int splits, int M, int N,
+                                     int64_t ld, double *out, int64_t ldo, int mirror)
+{
+    reduce_splits_body(part, stride, splits, M, N, ld, out, ldo, mirror, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ void reduce_splits_grouped(const ReduceGroupArgs *gs)
+{
+    const ReduceGroupArgs g = gs[blockIdx.y];
+    reduce_splits_body(g.part, g.stride, g.splits, g.M, g.N, g.ld, g.out, g.ldo, g.mirror,
+                       (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 }  // namespace
@@ -191,6 +221,24 @@ hipError_t gemm_f64(const GemmArgs &g, hipStream_t stream)
     return launch_tile<64, 64>(g, stream);
 }
 
+hipError_t gemm_f64_grouped(const GemmArgs *d_args, int count, const GemmShape &shape, hipStream_t stream)
+{
+    if (count <= 0 || shape.M <= 0 || shape.N <= 0) return hipSuccess;
+    constexpr int BM = 64, BN = 64;
+    const int gm = (shape.M + BM - 1) / BM, gn = (shape.N + BN - 1) / BN;
+    const int ks = shape.ksplit > 1 ? shape.ksplit : 1;
+    dim3 grid = shape.c_lower ? dim3(gm * (gm + 1) / 2, 1, count * ks) : dim3(gn, gm, count * ks);
+    if (shape.a_kc && shape.b_kc)
+        hipLaunchKernelGGL((gemm_f64_grouped_kernel<BM, BN, true, true>), grid, dim3(256), 0, stream, d_args, ks);
+    else if (shape.a_kc)
+        hipLaunchKernelGGL((gemm_f64_grouped_kernel<BM, BN, true, false>), grid, dim3(256), 0, stream, d_args, ks);
+    else if (shape.b_kc)
+        hipLaunchKernelGGL((gemm_f64_grouped_kernel<BM, BN, false, true>), grid, dim3(256), 0, stream, d_args, ks);
+    else
+        hipLaunchKernelGGL((gemm_f64_grouped_kernel<BM, BN, false, false>), grid, dim3(256), 0, stream, d_args, ks);
+    return hipGetLastError();
+}
+
 hipError_t reduce_splits_f64(const double *part, int64_t stride, int splits, int M, int N, int64_t ld,
                              double *out, int64_t ldo, int mirror, hipStream_t stream)
 {
@@ -198,6 +246,13 @@ hipError_t reduce_splits_f64(const double *part, int64_t stride, int splits, int
     if (total == 0) return hipSuccess;
     hipLaunchKernelGGL(reduce_splits_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream,
                        part, stride, splits, M, N, ld, out, ldo, mirror);
+    return hipGetLastError();
+}
+
+hipError_t reduce_splits_grouped_f64(const ReduceGroupArgs *d, int count, int64_t max_total, hipStream_t stream)
+{
+    if (count <= 0 || max_total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(reduce_splits_grouped, dim3((unsigned)((max_total + 255) / 256), count), dim3(256), 0, stream, d);
     return hipGetLastError();
 }
 

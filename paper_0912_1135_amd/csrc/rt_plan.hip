@@ -14,19 +14,8 @@
 //   c = A b, x = T'^T (T' c), then refinement steps
 //   x += T'^T T' A (b - A^T x) with Dot2 residuals, then
 //   A^T x (row projection) and b - A^T x (null projection).
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
-#include <cmath>
-#include <cstdio>
-#include <cstring>
-#include <string>
-#include <vector>
-
-#include "../../include/rtproj.h"
-#include "rt_common.h"
-
-namespace {
+#include "rt_plan_state.h"
+namespace rtp {
 
 thread_local std::string g_last_error;
 
@@ -36,151 +25,17 @@ rtproj_status fail(rtproj_status s, const std::string &msg)
     return s;
 }
 
-#define RT_HIP(expr)                                                                                  \
-    do {                                                                                              \
-        hipError_t _e = (expr);                                                                       \
-        if (_e != hipSuccess)                                                                         \
-            return fail(RTPROJ_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));        \
-    } while (0)
-
-constexpr int NB = 64;  // block size of the triangular solves and the Cholesky
-// P^{-1}A is formed in binary32 only while the rank estimate of the pivoted QR
-// is at most this: its rounding error grows like 2^-24 kappa and must leave
-// the refinement a contraction well below 1.
-constexpr double RT_W32_KAPPA_MAX = 1e5;
-// Reduced-precision modes redo the sketch in binary64 when max/min diag of
-// the Gram's Cholesky factor exceeds this (a healthy preconditioner gives ~3).
-constexpr double RT_COND_ESCALATE = 10.0;
-
-// ------------------------------------------------------------ random tables
-// SplitMix64 (Steele, Lea and Flood, 2014): the state advances by the golden
-// ratio increment and each output is the finalizer of the new state.
-struct SplitMix64 {
-    uint64_t s;
-    uint64_t next()
-    {
-        s += 0x9e3779b97f4a7c15ULL;
-        uint64_t z = s;
-        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
-        z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
-        return z ^ (z >> 31);
-    }
-    // uniform in [0, range): high half of next() * range
-    uint64_t below(uint64_t range) { return (uint64_t)(((unsigned __int128)next() * range) >> 64); }
-};
-
-struct HostTables {
-    int64_t np = 0, n1 = 0, n2 = 0;
-    std::vector<int8_t> sign;
-    std::vector<int32_t> sigma, tau, J;
-};
-
-// Draw order: np signs (top bit set -> -1), Fisher-Yates of sigma over
-// [0, n1) from the top, the same for tau over [0, n2), then the sorted
-// l-subset J of [0, np) by selection sampling.
-void draw_tables(uint64_t seed, int64_t n, int64_t l, HostTables &t)
+uint64_t instance_seed(uint64_t seed, int64_t i)
 {
-    int64_t np = 4;
-    int e = 2;
-    while (np < n) { np <<= 1; ++e; }
-    t.np = np;
-    t.n2 = int64_t(1) << (e / 2);
-    t.n1 = np / t.n2;
-    SplitMix64 g{seed};
-    t.sign.resize(np);
-    for (int64_t i = 0; i < np; ++i) t.sign[i] = (g.next() >> 63) ? int8_t(-1) : int8_t(1);
-    t.sigma.resize(t.n1);
-    for (int64_t i = 0; i < t.n1; ++i) t.sigma[i] = (int32_t)i;
-    for (int64_t j = t.n1 - 1; j >= 1; --j) std::swap(t.sigma[j], t.sigma[g.below((uint64_t)j + 1)]);
-    t.tau.resize(t.n2);
-    for (int64_t i = 0; i < t.n2; ++i) t.tau[i] = (int32_t)i;
-    for (int64_t j = t.n2 - 1; j >= 1; --j) std::swap(t.tau[j], t.tau[g.below((uint64_t)j + 1)]);
-    t.J.clear();
-    t.J.reserve(l);
-    for (int64_t i = 0; i < np && (int64_t)t.J.size() < l; ++i)
-        if ((int64_t)g.below((uint64_t)(np - i)) < l - (int64_t)t.J.size()) t.J.push_back((int32_t)i);
+    SplitMix64 g{seed ^ (uint64_t)i};
+    return g.next();
 }
 
-void twiddles(int64_t len, int64_t count, int64_t step, std::vector<double> &out)
-{
-    // out[j] = exp(-2 pi i j*step / len), j < count, from long-double cos/sin
-    out.resize(2 * count);
-    const long double pi = 3.141592653589793238462643383279502884L;
-    for (int64_t j = 0; j < count; ++j) {
-        const long double ang = -2.0L * pi * (long double)((j * step) % len) / (long double)len;
-        out[2 * j] = (double)cosl(ang);
-        out[2 * j + 1] = (double)sinl(ang);
-    }
-}
+}  // namespace rtp
 
-template <class T>
-hipError_t dalloc(T **p, size_t count)
-{
-    *p = nullptr;
-    if (count == 0) count = 1;
-    return hipMalloc((void **)p, count * sizeof(T));
-}
+using namespace rtp;
 
-}  // namespace
-
-struct rtproj_plan_s {
-    int64_t m = 0, n = 0, l = 0;
-    uint64_t seed = 0;
-    int device = 0;
-    hipStream_t stream = nullptr;
-    int cu_count = 0;
-    size_t lds_max = 0;
-    int precision = RTPROJ_PREC_FP64;
-    int refine_steps = -1;  // -1: chosen from the rank estimate of the pivoted QR
-    double refine_rtol = 0.0;
-    HostTables tab;
-    // device tables
-    int8_t *d_sign = nullptr;
-    int32_t *d_sigma = nullptr, *d_tauinv = nullptr, *d_sel_off = nullptr, *d_sel = nullptr;
-    double *d_tw1 = nullptr, *d_tw2 = nullptr, *d_twh = nullptr, *d_twl = nullptr;
-    float *d_tw1f = nullptr, *d_tw2f = nullptr, *d_twhf = nullptr, *d_twlf = nullptr;
-    int tl_bits = 0;
-    // preconditioner state
-    double *d_zbuf = nullptr;
-    int64_t rows_chunk = 0;
-    double *d_S = nullptr, *d_R = nullptr, *d_Y = nullptr, *d_W = nullptr, *d_part = nullptr;
-    double *d_G = nullptr, *d_L = nullptr, *d_Tp = nullptr, *d_DinvR = nullptr, *d_DinvL = nullptr;
-    int32_t *d_piv = nullptr;
-    unsigned *d_sync = nullptr;
-    double *d_slots = nullptr, *d_vbuf = nullptr, *d_qrcols = nullptr, *d_scal = nullptr, *d_diag = nullptr;
-    int *d_err = nullptr;
-    float *d_rowscale = nullptr;
-    int qr_blocks = 0;
-    bool w32 = false;          // P^{-1}A held in binary32 by the last precondition
-    int syrk_splits = 1;
-    // projection workspace
-    int64_t kcap = 0;
-    int ab_splits = 1;
-    double *d_c = nullptr, *d_tmp = nullptr, *d_xhi = nullptr, *d_xlo = nullptr, *d_d = nullptr, *d_r = nullptr;
-    double *d_ph = nullptr, *d_pl = nullptr, *d_norms = nullptr;
-    // borrowed operand
-    const double *A = nullptr;
-    int64_t lda = 0;
-    bool ready = false;
-    rtproj_info info{};
-    // stage timing (HIP events on the plan's stream)
-    bool timing = false;
-    struct StageEvents { int stage; hipEvent_t start, stop; };
-    std::vector<StageEvents> pending;
-
-    rt::SketchTables sketch_tables() const
-    {
-        rt::SketchTables t;
-        t.n = n; t.np = tab.np; t.n1 = tab.n1; t.n2 = tab.n2; t.l = l;
-        t.sign = d_sign; t.sigma = d_sigma; t.tau_inv = d_tauinv;
-        t.tw1 = d_tw1; t.tw2 = d_tw2; t.twh = d_twh; t.twl = d_twl; t.tl_bits = tl_bits;
-        t.tw1f = d_tw1f; t.tw2f = d_tw2f; t.twhf = d_twhf; t.twlf = d_twlf;
-        t.sel_off = d_sel_off; t.sel = d_sel;
-        return t;
-    }
-};
-
-namespace {
+namespace rtp {
 
 // Records a start event on construction and a stop event on destruction
 // when the plan's stage timing is enabled.
@@ -225,7 +80,7 @@ void release(rtproj_plan p)
     p->pending.clear();
     void *bufs[] = {p->d_sign, p->d_sigma, p->d_tauinv, p->d_sel_off, p->d_sel, p->d_tw1, p->d_tw2, p->d_twh,
                     p->d_twl, p->d_tw1f, p->d_tw2f, p->d_twhf, p->d_twlf, p->d_rowscale, p->d_zbuf, p->d_S, p->d_R, p->d_Y, p->d_W, p->d_part, p->d_G, p->d_L, p->d_Tp,
-                    p->d_DinvR, p->d_DinvL, p->d_piv, p->d_sync, p->d_slots, p->d_vbuf, p->d_qrcols, p->d_scal, p->d_diag,
+                    p->d_DinvR, p->d_DinvL, p->d_piv, p->d_sync, p->d_slots, p->d_vbuf, p->d_qrcols, p->d_Yq, p->d_R0, p->d_wgargs, p->d_scal, p->d_diag,
                     p->d_c, p->d_tmp, p->d_xhi, p->d_xlo, p->d_d, p->d_r, p->d_ph, p->d_pl, p->d_norms, p->d_err};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -320,14 +175,28 @@ rtproj_status alloc_state(rtproj_plan p)
     RT_HIP(dalloc(&p->d_DinvL, (size_t)nblk * NB * NB));
     RT_HIP(dalloc(&p->d_piv, (size_t)m));
     RT_HIP(dalloc(&p->d_sync, 4));
-    int gcols = 0;
+    int gcols = 0, gcols0 = 0;
     p->qr_blocks = rt::qrcp_max_blocks((int)l, (int)m, p->cu_count, p->lds_max, &gcols);
-    if (p->qr_blocks <= 0)
+    p->qr_blocks0 = rt::qrcp_max_blocks((int)m, (int)m, p->cu_count, p->lds_max, &gcols0);
+    if (p->qr_blocks <= 0 && p->qr_blocks0 <= 0)
         return fail(RTPROJ_ERR_UNSUPPORTED, "pivoted QR: more than 16 columns per compute unit, or l too large, "
                                             "for this (m, l)");
-    RT_HIP(dalloc(&p->d_slots, (size_t)4 * p->qr_blocks));
-    RT_HIP(dalloc(&p->d_vbuf, (size_t)2 * p->qr_blocks * l));
-    if (gcols) RT_HIP(dalloc(&p->d_qrcols, (size_t)p->qr_blocks * 16 * l));
+    const int64_t gmax = std::max(p->qr_blocks, p->qr_blocks0);
+    RT_HIP(dalloc(&p->d_slots, (size_t)4 * gmax));
+    RT_HIP(dalloc(&p->d_vbuf, (size_t)2 * std::max<int64_t>(p->qr_blocks * l, p->qr_blocks0 * m)));
+    if (gcols || gcols0)
+        RT_HIP(dalloc(&p->d_qrcols, (size_t)16 * std::max<int64_t>(gcols ? p->qr_blocks * l : 0,
+                                                                     gcols0 ? p->qr_blocks0 * m : 0)));
+    // two-stage pivoted QR: iterate of the Cholesky QR and R0
+    RT_HIP(dalloc(&p->d_Yq, (size_t)m * l));
+    RT_HIP(dalloc(&p->d_R0, (size_t)m * m));
+    {
+        rt::QrcpWgArgs wa{};
+        wa.M = p->d_R0; wa.ldm = m; wa.rows = (int)m; wa.cols = (int)m;
+        wa.R = p->d_R; wa.piv = p->d_piv; wa.err = reinterpret_cast<int *>(p->d_sync + 2);
+        RT_HIP(dalloc(&p->d_wgargs, 1));
+        RT_HIP(hipMemcpy(p->d_wgargs, &wa, sizeof(wa), hipMemcpyHostToDevice));
+    }
     RT_HIP(dalloc(&p->d_scal, 8));
     RT_HIP(dalloc(&p->d_diag, 8));
     RT_HIP(dalloc(&p->d_err, 4));
@@ -389,32 +258,88 @@ rtproj_status trsm_lower(rtproj_plan p, const double *Lp, int64_t l_i, int64_t l
     return RTPROJ_OK;
 }
 
-rtproj_status cholesky(rtproj_plan p)
+// Blocked right-looking Cholesky G = L L^T of the m x m matrix G (row-major,
+// lower part read and overwritten by the trailing updates) into L; Dinv gets
+// the inverses of L's diagonal blocks.  A failed pivot is flagged in d_err.
+rtproj_status cholesky(rtproj_plan p, double *G, double *L, double *Dinv)
 {
     const int64_t m = p->m;
     const int64_t nblk = (m + NB - 1) / NB;
-    RT_HIP(rt::set_matrix_f64(p->d_L, m, (int)m, (int)m, 0, p->stream));
+    RT_HIP(rt::set_matrix_f64(L, m, (int)m, (int)m, 0, p->stream));
     for (int64_t b = 0; b < nblk; ++b) {
         const int64_t r0 = b * NB, nbb = std::min<int64_t>(NB, m - r0);
-        RT_HIP(rt::chol_diag_f64(p->d_G, m, (int)m, NB, (int)b, p->d_L, m, p->d_DinvL, p->d_err, p->stream));
+        RT_HIP(rt::chol_diag_f64(G, m, (int)m, NB, (int)b, L, m, Dinv, p->d_err, p->stream));
         const int64_t rest = m - r0 - nbb;
         if (rest <= 0) continue;
         // panel: L21 = X21 L11^{-T}
         rt::GemmArgs g{};
         g.M = (int)rest; g.N = (int)nbb; g.K = (int)nbb;
-        g.A = p->d_G + (r0 + nbb) * m + r0; g.a_i = m; g.a_k = 1;
-        g.B = p->d_DinvL + b * NB * NB; g.b_k = 1; g.b_j = NB;
-        g.C = p->d_L + (r0 + nbb) * m + r0; g.c_i = m; g.c_j = 1;
+        g.A = G + (r0 + nbb) * m + r0; g.a_i = m; g.a_k = 1;
+        g.B = Dinv + b * NB * NB; g.b_k = 1; g.b_j = NB;
+        g.C = L + (r0 + nbb) * m + r0; g.c_i = m; g.c_j = 1;
         g.alpha = 1.0; g.ksplit = 1;
         RT_HIP(rt::gemm_f64(g, p->stream));
         // trailing update: X22 -= L21 L21^T (lower tiles)
         rt::GemmArgs u{};
         u.M = (int)rest; u.N = (int)rest; u.K = (int)nbb;
-        u.A = p->d_L + (r0 + nbb) * m + r0; u.a_i = m; u.a_k = 1;
-        u.B = p->d_L + (r0 + nbb) * m + r0; u.b_k = 1; u.b_j = m;
-        u.C = p->d_G + (r0 + nbb) * m + (r0 + nbb); u.c_i = m; u.c_j = 1;
+        u.A = L + (r0 + nbb) * m + r0; u.a_i = m; u.a_k = 1;
+        u.B = L + (r0 + nbb) * m + r0; u.b_k = 1; u.b_j = m;
+        u.C = G + (r0 + nbb) * m + (r0 + nbb); u.c_i = m; u.c_j = 1;
         u.alpha = -1.0; u.beta = 1.0; u.c_lower = 1; u.ksplit = 1;
         RT_HIP(rt::gemm_f64(u, p->stream));
+    }
+    return RTPROJ_OK;
+}
+
+// G (m x m, row-major, both triangles) = A A^T for the row-major m x K
+// matrix A: lower tiles on MFMA, split over K, fixed-order reduction.
+rtproj_status gram_f64(rtproj_plan p, const double *A, int64_t lda, int64_t K, double *G)
+{
+    const int64_t m = p->m;
+    rt::GemmArgs g{};
+    g.M = (int)m; g.N = (int)m; g.K = (int)K;
+    g.A = A; g.a_i = lda; g.a_k = 1;
+    g.B = A; g.b_k = 1; g.b_j = lda;
+    g.C = p->d_part; g.c_i = m; g.c_j = 1; g.c_split = m * m;
+    g.alpha = 1.0; g.c_lower = 1;
+    g.ksplit = (int)std::max<int64_t>(1, std::min<int64_t>(p->syrk_splits, K / 256));
+    RT_HIP(rt::gemm_f64(g, p->stream));
+    RT_HIP(rt::reduce_splits_f64(p->d_part, m * m, g.ksplit, (int)m, (int)m, m, G, m, 1, p->stream));
+    return RTPROJ_OK;
+}
+
+// First stage of the two-stage pivoted QR: S^T = Q0 R0 by shifted Cholesky
+// QR (Fukaya, Kannan, Nakatsukasa, Yamamoto, Yanagisawa 2020): with X = S^T,
+//   R1^T R1 = X^T X + s I,  s = 11 (l m + m (m+1)) 2^-53 |X|_F^2,
+//   Q1 = X R1^{-1}, then two unshifted passes Q_{j+1} = Q_j R_{j+1}^{-1},
+//   R0 = R3 R2 R1.
+// Working with transposes: Y = Q^T = L^{-1} S and R0^T = L1 L2 L3 (lower),
+// which is R0 in column-major order, the layout the second stage reads.
+// Sets d_err when a Cholesky fails (then the direct method is used).
+rtproj_status r0_factor(rtproj_plan p)
+{
+    const int64_t m = p->m, l = p->l;
+    hipStream_t s = p->stream;
+    RT_HIP(hipMemcpyAsync(p->d_Yq, p->d_S, (size_t)m * l * sizeof(double), hipMemcpyDeviceToDevice, s));
+    const double shift = 11.0 * ((double)l * (double)m + (double)m * (double)(m + 1)) * std::ldexp(1.0, -53);
+    double *Ls[3] = {p->d_L, p->d_Y, p->d_Tp};  // free until the preconditioner's own factors
+    rtproj_status st;
+    for (int it = 0; it < 3; ++it) {
+        if ((st = gram_f64(p, p->d_Yq, l, l, p->d_G)) != RTPROJ_OK) return st;
+        if (it == 0) RT_HIP(rt::shift_diag_f64(p->d_G, m, (int)m, shift, s));
+        if ((st = cholesky(p, p->d_G, Ls[it], p->d_DinvL)) != RTPROJ_OK) return st;
+        if (it < 2 && (st = trsm_lower(p, Ls[it], m, 1, p->d_DinvL, p->d_Yq, l, m, l, false)) != RTPROJ_OK)
+            return st;
+    }
+    // R0^T = (L1 L2) L3, products of lower-triangular factors
+    for (int pass = 0; pass < 2; ++pass) {
+        rt::GemmArgs g{};
+        g.M = (int)m; g.N = (int)m; g.K = (int)m;
+        g.A = pass == 0 ? Ls[0] : p->d_G; g.a_i = m; g.a_k = 1; g.a_lower = 1;
+        g.B = pass == 0 ? Ls[1] : Ls[2]; g.b_k = m; g.b_j = 1;
+        g.C = pass == 0 ? p->d_G : p->d_R0; g.c_i = m; g.c_j = 1;
+        g.alpha = 1.0; g.ksplit = 1;
+        RT_HIP(rt::gemm_f64(g, s));
     }
     return RTPROJ_OK;
 }
@@ -620,6 +545,20 @@ rtproj_status rtproj_plan_set_precision(rtproj_plan p, int precision)
     return RTPROJ_OK;
 }
 
+rtproj_status rtproj_plan_set_qr(rtproj_plan p, int mode)
+{
+    if (!p) return fail(RTPROJ_ERR_INVALID_ARG, "null plan");
+    if (mode < RTPROJ_QR_AUTO || mode > RTPROJ_QR_TWO_STAGE_WG) return fail(RTPROJ_ERR_INVALID_ARG, "unknown QR mode");
+    if (mode == RTPROJ_QR_DIRECT && p->qr_blocks <= 0)
+        return fail(RTPROJ_ERR_UNSUPPORTED, "direct pivoted QR: the l x m sketch does not fit the cooperative kernel");
+    if (mode == RTPROJ_QR_TWO_STAGE && p->qr_blocks0 <= 0)
+        return fail(RTPROJ_ERR_UNSUPPORTED, "two-stage pivoted QR: R0 does not fit the cooperative kernel");
+    if (mode == RTPROJ_QR_TWO_STAGE_WG && (p->m > rt::qrcp_wg_max_rows() || p->m > rt::qrcp_wg_max_cols()))
+        return fail(RTPROJ_ERR_UNSUPPORTED, "single-workgroup pivoted QR: m too large");
+    p->qr_mode = mode;
+    return RTPROJ_OK;
+}
+
 rtproj_status rtproj_plan_set_refinement(rtproj_plan p, int max_steps, double rtol)
 {
     if (!p) return fail(RTPROJ_ERR_INVALID_ARG, "null plan");
@@ -634,6 +573,13 @@ rtproj_status rtproj_plan_set_refinement(rtproj_plan p, int max_steps, double rt
 
 namespace {
 
+// The pivoted-QR method used when the caller leaves it to the plan.
+int auto_qr_mode(rtproj_plan p)
+{
+    if (p->qr_blocks <= 0) return RTPROJ_QR_TWO_STAGE;
+    return RTPROJ_QR_DIRECT;
+}
+
 // One pass of the preconditioner; sketch64 forces the binary64 sketch.
 rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, bool sketch64)
 {
@@ -647,10 +593,18 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
         else
             RT_HIP(rt::sketch_f32(p->sketch_tables(), A, lda, m, p->d_S, l, p->d_zbuf, p->rows_chunk, s));
     }
-    // 2. pivoted QR of S^T
+    // 2. pivoted QR of S^T, directly or on the small factor R0 of S^T
     double diag[4];
     unsigned sync[4];
+    int mode = p->qr_mode;
+    if (mode == RTPROJ_QR_AUTO) mode = auto_qr_mode(p);
     {
+        RT_HIP(rt::zero_u32(reinterpret_cast<unsigned *>(p->d_err), 1, s));
+        if (mode != RTPROJ_QR_DIRECT) {
+            StageScope sc(p, 12);
+            rtproj_status st0 = r0_factor(p);
+            if (st0 != RTPROJ_OK) return st0;
+        }
         RT_HIP(rt::set_matrix_f64(p->d_R, m, (int)m, (int)m, 0, s));
         rt::QrcpWork w;
         w.counter = p->d_sync;
@@ -658,15 +612,48 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
         w.err = reinterpret_cast<int *>(p->d_sync + 2);
         w.slots = p->d_slots;
         w.vbuf = p->d_vbuf;
-        w.cols = p->d_qrcols;
         {
             StageScope sc(p, 1);
-            RT_HIP(rt::qrcp_f64(p->d_S, l, (int)l, (int)m, p->d_R, p->d_piv, w, p->qr_blocks, p->lds_max, s));
+            if (mode == RTPROJ_QR_DIRECT) {
+                int gc = 0;
+                rt::qrcp_max_blocks((int)l, (int)m, p->cu_count, p->lds_max, &gc);
+                w.cols = gc ? p->d_qrcols : nullptr;
+                RT_HIP(rt::qrcp_f64(p->d_S, l, (int)l, (int)m, p->d_R, p->d_piv, w, p->qr_blocks, p->lds_max, s));
+            } else if (mode == RTPROJ_QR_TWO_STAGE) {
+                int gc = 0;
+                rt::qrcp_max_blocks((int)m, (int)m, p->cu_count, p->lds_max, &gc);
+                w.cols = gc ? p->d_qrcols : nullptr;
+                RT_HIP(rt::qrcp_f64(p->d_R0, m, (int)m, (int)m, p->d_R, p->d_piv, w, p->qr_blocks0, p->lds_max, s));
+            } else {
+                RT_HIP(rt::zero_u32(p->d_sync, 4, s));
+                RT_HIP(rt::qrcp_wg_f64(p->d_wgargs, 1, s));
+            }
         }
         RT_HIP(rt::rdiag_ends_f64(p->d_R, m, (int)m, p->d_diag, s));
         RT_HIP(hipMemcpyAsync(diag, p->d_diag, 32, hipMemcpyDeviceToHost, s));
         RT_HIP(hipMemcpyAsync(sync, p->d_sync, 16, hipMemcpyDeviceToHost, s));
+        int r0err = 0;
+        RT_HIP(hipMemcpyAsync(&r0err, p->d_err, 4, hipMemcpyDeviceToHost, s));
+        RT_HIP(hipStreamSynchronize(s));
+        if (r0err && mode != RTPROJ_QR_DIRECT) {
+            // the Cholesky QR broke down (S^T too ill-conditioned even for the
+            // shifted first pass): factor S^T directly
+            if (p->qr_blocks <= 0) return fail(RTPROJ_ERR_RANK, "two-stage pivoted QR: Cholesky QR of the sketch failed");
+            mode = RTPROJ_QR_DIRECT;
+            RT_HIP(rt::set_matrix_f64(p->d_R, m, (int)m, (int)m, 0, s));
+            int gc = 0;
+            rt::qrcp_max_blocks((int)l, (int)m, p->cu_count, p->lds_max, &gc);
+            w.cols = gc ? p->d_qrcols : nullptr;
+            {
+                StageScope sc(p, 1);
+                RT_HIP(rt::qrcp_f64(p->d_S, l, (int)l, (int)m, p->d_R, p->d_piv, w, p->qr_blocks, p->lds_max, s));
+            }
+            RT_HIP(rt::rdiag_ends_f64(p->d_R, m, (int)m, p->d_diag, s));
+            RT_HIP(hipMemcpyAsync(diag, p->d_diag, 32, hipMemcpyDeviceToHost, s));
+            RT_HIP(hipMemcpyAsync(sync, p->d_sync, 16, hipMemcpyDeviceToHost, s));
+        }
     }
+    p->info.qr_mode = mode;
     RT_HIP(hipStreamSynchronize(s));
     if (sync[2] == 2) return fail(RTPROJ_ERR_RANK, "pivoted QR: no finite pivot (A contains NaN or Inf)");
     if (sync[2] != 0) return fail(RTPROJ_ERR_DEVICE, "pivoted QR: cooperative barrier timed out");
@@ -742,7 +729,7 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
     {
         StageScope sc(p, 5);
         RT_HIP(rt::zero_u32(reinterpret_cast<unsigned *>(p->d_err), 1, s));
-        st = cholesky(p);
+        st = cholesky(p, p->d_G, p->d_L, p->d_DinvL);
     }
     if (st != RTPROJ_OK) return st;
     // 7. T = L^{-1} R^{-T} (in place in d_Y), T' = T Pi

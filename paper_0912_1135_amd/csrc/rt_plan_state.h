@@ -1,0 +1,184 @@
+// Internal state of a plan, shared by the single-problem runtime (rt_plan.hip)
+// and the batched runtime (rt_batch.hip).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rtproj.h"
+#include "rt_common.h"
+
+namespace rtp {
+
+
+// Records the message returned by rtproj_last_error() and returns s.
+rtproj_status fail(rtproj_status s, const std::string &msg);
+extern thread_local std::string g_last_error;
+
+#define RT_HIP(expr)                                                                                  \
+    do {                                                                                              \
+        hipError_t _e = (expr);                                                                       \
+        if (_e != hipSuccess)                                                                         \
+            return fail(RTPROJ_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));        \
+    } while (0)
+
+constexpr int NB = 64;  // block size of the triangular solves and the Cholesky
+// P^{-1}A is formed in binary32 only while the rank estimate of the pivoted QR
+// is at most this: its rounding error grows like 2^-24 kappa and must leave
+// the refinement a contraction well below 1.
+constexpr double RT_W32_KAPPA_MAX = 1e5;
+// Reduced-precision modes redo the sketch in binary64 when max/min diag of
+// the Gram's Cholesky factor exceeds this (a healthy preconditioner gives ~3).
+constexpr double RT_COND_ESCALATE = 10.0;
+
+// ------------------------------------------------------------ random tables
+// SplitMix64 (Steele, Lea and Flood, 2014): the state advances by the golden
+// ratio increment and each output is the finalizer of the new state.
+struct SplitMix64 {
+    uint64_t s;
+    uint64_t next()
+    {
+        s += 0x9e3779b97f4a7c15ULL;
+        uint64_t z = s;
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+        return z ^ (z >> 31);
+    }
+    // uniform in [0, range): high half of next() * range
+    uint64_t below(uint64_t range) { return (uint64_t)(((unsigned __int128)next() * range) >> 64); }
+};
+
+struct HostTables {
+    int64_t np = 0, n1 = 0, n2 = 0;
+    std::vector<int8_t> sign;
+    std::vector<int32_t> sigma, tau, J;
+};
+
+// Draw order: np signs (top bit set -> -1), Fisher-Yates of sigma over
+// [0, n1) from the top, the same for tau over [0, n2), then the sorted
+// l-subset J of [0, np) by selection sampling.
+inline void draw_tables(uint64_t seed, int64_t n, int64_t l, HostTables &t)
+{
+    int64_t np = 4;
+    int e = 2;
+    while (np < n) { np <<= 1; ++e; }
+    t.np = np;
+    t.n2 = int64_t(1) << (e / 2);
+    t.n1 = np / t.n2;
+    SplitMix64 g{seed};
+    t.sign.resize(np);
+    for (int64_t i = 0; i < np; ++i) t.sign[i] = (g.next() >> 63) ? int8_t(-1) : int8_t(1);
+    t.sigma.resize(t.n1);
+    for (int64_t i = 0; i < t.n1; ++i) t.sigma[i] = (int32_t)i;
+    for (int64_t j = t.n1 - 1; j >= 1; --j) std::swap(t.sigma[j], t.sigma[g.below((uint64_t)j + 1)]);
+    t.tau.resize(t.n2);
+    for (int64_t i = 0; i < t.n2; ++i) t.tau[i] = (int32_t)i;
+    for (int64_t j = t.n2 - 1; j >= 1; --j) std::swap(t.tau[j], t.tau[g.below((uint64_t)j + 1)]);
+    t.J.clear();
+    t.J.reserve(l);
+    for (int64_t i = 0; i < np && (int64_t)t.J.size() < l; ++i)
+        if ((int64_t)g.below((uint64_t)(np - i)) < l - (int64_t)t.J.size()) t.J.push_back((int32_t)i);
+}
+
+inline void twiddles(int64_t len, int64_t count, int64_t step, std::vector<double> &out)
+{
+    // out[j] = exp(-2 pi i j*step / len), j < count, from long-double cos/sin
+    out.resize(2 * count);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int64_t j = 0; j < count; ++j) {
+        const long double ang = -2.0L * pi * (long double)((j * step) % len) / (long double)len;
+        out[2 * j] = (double)cosl(ang);
+        out[2 * j + 1] = (double)sinl(ang);
+    }
+}
+
+template <class T>
+hipError_t dalloc(T **p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc((void **)p, count * sizeof(T));
+}
+
+
+}  // namespace rtp
+
+struct rtproj_plan_s {
+    int64_t m = 0, n = 0, l = 0;
+    uint64_t seed = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int cu_count = 0;
+    size_t lds_max = 0;
+    int precision = RTPROJ_PREC_FP64;
+    int refine_steps = -1;  // -1: chosen from the rank estimate of the pivoted QR
+    double refine_rtol = 0.0;
+    rtp::HostTables tab;
+    // device tables
+    int8_t *d_sign = nullptr;
+    int32_t *d_sigma = nullptr, *d_tauinv = nullptr, *d_sel_off = nullptr, *d_sel = nullptr;
+    double *d_tw1 = nullptr, *d_tw2 = nullptr, *d_twh = nullptr, *d_twl = nullptr;
+    float *d_tw1f = nullptr, *d_tw2f = nullptr, *d_twhf = nullptr, *d_twlf = nullptr;
+    int tl_bits = 0;
+    // preconditioner state
+    double *d_zbuf = nullptr;
+    int64_t rows_chunk = 0;
+    double *d_S = nullptr, *d_R = nullptr, *d_Y = nullptr, *d_W = nullptr, *d_part = nullptr;
+    double *d_G = nullptr, *d_L = nullptr, *d_Tp = nullptr, *d_DinvR = nullptr, *d_DinvL = nullptr;
+    int32_t *d_piv = nullptr;
+    unsigned *d_sync = nullptr;
+    double *d_slots = nullptr, *d_vbuf = nullptr, *d_qrcols = nullptr, *d_scal = nullptr, *d_diag = nullptr;
+    int *d_err = nullptr;
+    float *d_rowscale = nullptr;
+    int qr_blocks = 0;         // cooperative blocks for the l x m QRCP (direct mode)
+    int qr_blocks0 = 0;        // cooperative blocks for the m x m QRCP of R0
+    int qr_mode = RTPROJ_QR_AUTO;
+    double *d_Yq = nullptr;    // two-stage: the m x l iterate of the Cholesky QR
+    double *d_R0 = nullptr;    // two-stage: R0^T (lower, row-major m x m)
+    rt::QrcpWgArgs *d_wgargs = nullptr;
+    bool w32 = false;          // P^{-1}A held in binary32 by the last precondition
+    int syrk_splits = 1;
+    // projection workspace
+    int64_t kcap = 0;
+    int ab_splits = 1;
+    double *d_c = nullptr, *d_tmp = nullptr, *d_xhi = nullptr, *d_xlo = nullptr, *d_d = nullptr, *d_r = nullptr;
+    double *d_ph = nullptr, *d_pl = nullptr, *d_norms = nullptr;
+    // borrowed operand
+    const double *A = nullptr;
+    int64_t lda = 0;
+    bool ready = false;
+    rtproj_info info{};
+    // stage timing (HIP events on the plan's stream)
+    bool timing = false;
+    struct StageEvents { int stage; hipEvent_t start, stop; };
+    std::vector<StageEvents> pending;
+
+    rt::SketchTables sketch_tables() const
+    {
+        rt::SketchTables t;
+        t.n = n; t.np = tab.np; t.n1 = tab.n1; t.n2 = tab.n2; t.l = l;
+        t.sign = d_sign; t.sigma = d_sigma; t.tau_inv = d_tauinv;
+        t.tw1 = d_tw1; t.tw2 = d_tw2; t.twh = d_twh; t.twl = d_twl; t.tl_bits = tl_bits;
+        t.tw1f = d_tw1f; t.tw2f = d_tw2f; t.twhf = d_twhf; t.twlf = d_twlf;
+        t.sel_off = d_sel_off; t.sel = d_sel;
+        return t;
+    }
+};
+
+namespace rtp {
+
+// Grows the projection workspace of p to k right-hand sides.
+rtproj_status ensure_k(rtproj_plan p, int64_t k);
+// Refinement steps chosen from the rank estimate (see rtproj_plan_set_refinement).
+int auto_refine_steps(double kappa_est, int precision, bool w32, double cond_w);
+// First output of SplitMix64 seeded with seed XOR i: the sketch seed of
+// member i of a batch.
+uint64_t instance_seed(uint64_t seed, int64_t i);
+
+}  // namespace rtp

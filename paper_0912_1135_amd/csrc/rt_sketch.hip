@@ -61,9 +61,37 @@ __device__ void lds_fft_cols(cpx<R> *buf, int len, int cols, const cpx<R> *tw)
     }
 }
 
+// Shared launch geometry of the two passes for one problem.
+struct SketchGeom {
+    int tw_cols, bits1, cp, bits2;
+};
+
+__host__ __device__ inline int ilog2(int64_t v)
+{
+    int b = 0;
+    while ((int64_t(1) << b) < v) ++b;
+    return b;
+}
+
 template <typename R>
-__global__ __launch_bounds__(256) void sketch_pass1(SketchTables t, const double *A, int64_t lda, int64_t m,
-                                                    int64_t row0, cpx<R> *zbuf, int tw_cols, int bits1)
+__host__ __device__ inline SketchGeom sketch_geom(const SketchTables &t)
+{
+    const int64_t csz = sizeof(cpx<R>);
+    SketchGeom g;
+    g.tw_cols = t.n2 < 16 ? (int)t.n2 : 16;
+    while (g.tw_cols > 1 && (int64_t)g.tw_cols * t.n1 * csz > 64 * 1024) g.tw_cols >>= 1;
+    g.cp = (int)((64 * 1024) / (2 * csz * t.n2));
+    if (g.cp < 1) g.cp = 1;
+    if (g.cp > 8) g.cp = 8;
+    g.bits1 = ilog2(t.n1);
+    g.bits2 = ilog2(t.n2);
+    return g;
+}
+
+template <typename R>
+__device__ __forceinline__ void sketch_pass1_body(const SketchTables &t, const double *A, int64_t lda, int64_t m,
+                                                  int64_t row0, cpx<R> *zbuf, int tw_cols, int bits1, int bx,
+                                                  int64_t pair)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     typedef cpx<R> cplx;
@@ -71,9 +99,9 @@ __global__ __launch_bounds__(256) void sketch_pass1(SketchTables t, const double
     const int n1 = (int)t.n1, n2 = (int)t.n2;
     cplx *tw = smem;                 // n1/2
     cplx *buf = smem + (n1 >> 1);    // tw_cols x n1
-    const int64_t pair = blockIdx.y;
     const int64_t r0 = row0 + 2 * pair, r1 = r0 + 1;
-    const int u0 = blockIdx.x * tw_cols;
+    const int u0 = bx * tw_cols;
+    if (u0 >= n2 || r0 >= m) return;  // whole block (grouped launches)
     const cplx *tw1 = reinterpret_cast<const cplx *>(sizeof(R) == 8 ? (const void *)t.tw1 : (const void *)t.tw1f);
     for (int e = threadIdx.x; e < (n1 >> 1); e += blockDim.x) tw[e] = tw1[e];
     const double *a0 = A + r0 * lda;
@@ -106,8 +134,16 @@ __global__ __launch_bounds__(256) void sketch_pass1(SketchTables t, const double
 }
 
 template <typename R>
-__global__ __launch_bounds__(256) void sketch_pass2(SketchTables t, int64_t m, int64_t row0, int64_t npairs,
-                                                    const cpx<R> *zbuf, double *S, int64_t lds, int cp, int bits2)
+__global__ __launch_bounds__(256) void sketch_pass1(SketchTables t, const double *A, int64_t lda, int64_t m,
+                                                    int64_t row0, cpx<R> *zbuf, int tw_cols, int bits1)
+{
+    sketch_pass1_body<R>(t, A, lda, m, row0, zbuf, tw_cols, bits1, blockIdx.x, blockIdx.y);
+}
+
+template <typename R>
+__device__ __forceinline__ void sketch_pass2_body(const SketchTables &t, int64_t m, int64_t row0, int64_t npairs,
+                                                  const cpx<R> *zbuf, double *S, int64_t lds, int cp, int bits2,
+                                                  int w, int64_t by)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     typedef cpx<R> cplx;
@@ -115,10 +151,11 @@ __global__ __launch_bounds__(256) void sketch_pass2(SketchTables t, int64_t m, i
     const int n1 = (int)t.n1, n2 = (int)t.n2;
     cplx *tw = smem;               // n2/2
     cplx *buf = smem + (n2 >> 1);  // cp x 2 x n2
-    const int w = blockIdx.x;      // k1-pair index: ka = w, kb = (n1 - w) % n1
+    // w: k1-pair index, ka = w, kb = (n1 - w) % n1
     const int ka = w, kb = (n1 - w) % n1;
     const int ncol = (ka == kb) ? 1 : 2;
-    const int64_t p0 = (int64_t)blockIdx.y * cp;
+    const int64_t p0 = by * cp;
+    if (w > n1 / 2 || p0 >= npairs) return;  // whole block (grouped launches)
     const int pc = (int)min<int64_t>(cp, npairs - p0);
     const cplx *tw2 = reinterpret_cast<const cplx *>(sizeof(R) == 8 ? (const void *)t.tw2 : (const void *)t.tw2f);
     for (int e = threadIdx.x; e < (n2 >> 1); e += blockDim.x) tw[e] = tw2[e];
@@ -158,11 +195,37 @@ __global__ __launch_bounds__(256) void sketch_pass2(SketchTables t, int64_t m, i
     }
 }
 
-int ilog2(int64_t v)
+template <typename R>
+__global__ __launch_bounds__(256) void sketch_pass2(SketchTables t, int64_t m, int64_t row0, int64_t npairs,
+                                                    const cpx<R> *zbuf, double *S, int64_t lds, int cp, int bits2)
 {
-    int b = 0;
-    while ((int64_t(1) << b) < v) ++b;
-    return b;
+    sketch_pass2_body<R>(t, m, row0, npairs, zbuf, S, lds, cp, bits2, blockIdx.x, blockIdx.y);
+}
+
+// Grouped passes: member blockIdx.z; chunk c covers rows [c*rows_chunk, ...).
+template <typename R>
+__global__ __launch_bounds__(256) void sketch_pass1_grouped(const SketchGroupArgs *gs, int chunk)
+{
+    const SketchGroupArgs g = gs[blockIdx.z];
+    const int64_t row0 = (int64_t)chunk * g.rows_chunk;
+    if (row0 >= g.m) return;
+    const int64_t rows = min(g.rows_chunk, g.m - row0);
+    if ((int64_t)blockIdx.y >= (rows + 1) / 2) return;  // pairs of this member's chunk only
+    const SketchGeom geo = sketch_geom<R>(g.t);
+    sketch_pass1_body<R>(g.t, g.A, g.lda, g.m, row0, reinterpret_cast<cpx<R> *>(g.zbuf), geo.tw_cols, geo.bits1,
+                         blockIdx.x, blockIdx.y);
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void sketch_pass2_grouped(const SketchGroupArgs *gs, int chunk)
+{
+    const SketchGroupArgs g = gs[blockIdx.z];
+    const int64_t row0 = (int64_t)chunk * g.rows_chunk;
+    if (row0 >= g.m) return;
+    const int64_t rows = min(g.rows_chunk, g.m - row0);
+    const SketchGeom geo = sketch_geom<R>(g.t);
+    sketch_pass2_body<R>(g.t, g.m, row0, (rows + 1) / 2, reinterpret_cast<const cpx<R> *>(g.zbuf), g.S, g.lds, geo.cp,
+                         geo.bits2, blockIdx.x, blockIdx.y);
 }
 
 template <typename R>
@@ -171,13 +234,9 @@ hipError_t sketch_run(const SketchTables &t, const double *A, int64_t lda, int64
 {
     typedef cpx<R> cplx;
     const int n1 = (int)t.n1, n2 = (int)t.n2;
-    const int bits1 = ilog2(n1), bits2 = ilog2(n2);
+    const SketchGeom geo = sketch_geom<R>(t);
+    const int bits1 = geo.bits1, bits2 = geo.bits2, tw_cols = geo.tw_cols, cp = geo.cp;
     const int64_t csz = sizeof(cplx);
-    int tw_cols = n2 < 16 ? n2 : 16;
-    while (tw_cols > 1 && (int64_t)tw_cols * n1 * csz > 64 * 1024) tw_cols >>= 1;
-    int cp = (int)((64 * 1024) / (2 * csz * (int64_t)n2));
-    if (cp < 1) cp = 1;
-    if (cp > 8) cp = 8;
     const size_t sm1 = (size_t)((n1 >> 1) + (int64_t)tw_cols * n1) * csz;
     const size_t sm2 = (size_t)((n2 >> 1) + (int64_t)cp * 2 * n2) * csz;
     cplx *z = reinterpret_cast<cplx *>(zbuf);
@@ -200,7 +259,48 @@ hipError_t sketch_run(const SketchTables &t, const double *A, int64_t lda, int64
     return hipSuccess;
 }
 
+template <typename R>
+hipError_t sketch_grouped_run(const SketchGroupArgs *d, int count, const SketchGroupShape &sh, hipStream_t stream)
+{
+    if (count <= 0) return hipSuccess;
+    typedef cpx<R> cplx;
+    const int64_t csz = sizeof(cplx);
+    // launch geometry covering every member: the largest n1, n2 and pairs
+    SketchTables tmax{};
+    tmax.n1 = sh.max_n1; tmax.n2 = sh.max_n2;
+    size_t sm1 = 0, sm2 = 0;
+    int gx1 = 0, gx2 = 0;
+    for (int64_t n1 = 1; n1 <= sh.max_n1; n1 <<= 1)
+        for (int64_t n2 = 1; n2 <= sh.max_n2; n2 <<= 1) {
+            SketchTables tt{};
+            tt.n1 = n1; tt.n2 = n2;
+            const SketchGeom g = sketch_geom<R>(tt);
+            sm1 = std::max(sm1, (size_t)((n1 >> 1) + (int64_t)g.tw_cols * n1) * csz);
+            sm2 = std::max(sm2, (size_t)((n2 >> 1) + (int64_t)g.cp * 2 * n2) * csz);
+            gx1 = std::max(gx1, (int)(n2 / g.tw_cols));
+            gx2 = std::max(gx2, (int)(n1 / 2 + 1));
+        }
+    hipError_t e = hipFuncSetAttribute((const void *)sketch_pass1_grouped<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)sm1);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)sketch_pass2_grouped<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm2);
+    if (e != hipSuccess) return e;
+    const int64_t max_pairs = (sh.max_rows_chunk + 1) / 2;
+    for (int c = 0; c < sh.chunks; ++c) {
+        hipLaunchKernelGGL(sketch_pass1_grouped<R>, dim3(gx1, (unsigned)max_pairs, count), dim3(256), sm1, stream, d, c);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(sketch_pass2_grouped<R>, dim3(gx2, (unsigned)max_pairs, count), dim3(256), sm2, stream, d, c);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 }  // namespace
+
+hipError_t sketch_grouped_f64(const SketchGroupArgs *d, int count, const SketchGroupShape &sh, hipStream_t stream)
+{
+    return sketch_grouped_run<double>(d, count, sh, stream);
+}
 
 hipError_t sketch_f64(const SketchTables &t, const double *A, int64_t lda, int64_t m, double *S, int64_t lds,
                       double *zbuf, int64_t rows_chunk, hipStream_t stream)

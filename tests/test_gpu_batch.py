@@ -1,0 +1,112 @@
+"""Batched path (grouped launches, optional HIP graph) vs the CPU oracle,
+member by member, through the C ABI (marker: gpu).  Same tolerance as a
+single plan: <= 1e-10 relative for z, the row projection and x."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_0912_1135_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def rt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0912_1135_amd as rt
+    rt.lib()
+    return rt
+
+
+def dev():
+    return torch.device("cuda", 0)
+
+
+def members(count, seed, m_lo=8, m_hi=160, j_lo=4, j_hi=24, k_hi=9):
+    shp = synth.make_batch_shapes(count, seed, m_lo=m_lo, m_hi=m_hi, j_lo=j_lo, j_hi=j_hi, k_lo=1, k_hi=k_hi)
+    return shp
+
+
+def check_member(A, B, Z, Y, X):
+    Zr, Yr, Xr, _ = oracle.project(A, B.T)
+    nb = np.linalg.norm(B, axis=1)
+    ez = np.max(np.linalg.norm(Z - Zr.T, axis=1) / nb)
+    ey = np.max(np.linalg.norm(Y - Yr.T, axis=1) / nb)
+    ex = np.max(np.linalg.norm(X - Xr.T, axis=1) / np.linalg.norm(Xr.T, axis=1))
+    return ez, ey, ex
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_matches_oracle(rt, graph):
+    shp = members(10, 71)
+    As = [synth.make_problem(m, n, 1e6, 100 + i) for i, (m, n) in enumerate(zip(shp.m, shp.n))]
+    Bs = [synth.make_rhs(n, k, 200 + i) for i, (n, k) in enumerate(zip(shp.n, shp.k))]
+    bt = rt.Batch(shp.m, shp.n, shp.l, 5)
+    bt.set_graph(graph)
+    At = [torch.from_numpy(A).to(dev()) for A in As]
+    Bt = [torch.from_numpy(B).to(dev()) for B in Bs]
+    bt.precondition(At)
+    Z, Y, X = bt.project_all(Bt)
+    assert bt.status() == [0] * len(As)
+    for i in range(len(As)):
+        e = check_member(As[i], Bs[i], Z[i].cpu().numpy(), Y[i].cpu().numpy(), X[i].cpu().numpy())
+        assert max(e) <= TOL, (i, shp.m[i], shp.n[i], e)
+    bt.close()
+
+
+def test_batch_graph_replay_sees_new_data(rt):
+    """Two preconditions and projections with the same buffers: the second
+    call replays the captured graphs and must see the new contents."""
+    shp = members(6, 72, m_hi=96)
+    bt = rt.Batch(shp.m, shp.n, shp.l, 9)
+    bt.set_graph(True)
+    At = [torch.empty((m, n), dtype=torch.float64, device=dev()) for m, n in zip(shp.m, shp.n)]
+    Bt = [torch.empty((k, n), dtype=torch.float64, device=dev()) for n, k in zip(shp.n, shp.k)]
+    Z = [torch.empty_like(B) for B in Bt]
+    Y = [torch.empty_like(B) for B in Bt]
+    X = [torch.empty((k, m), dtype=torch.float64, device=dev()) for m, k in zip(shp.m, shp.k)]
+    for rep in range(3):
+        As = [synth.make_problem(m, n, 1e4, 300 + 10 * rep + i) for i, (m, n) in enumerate(zip(shp.m, shp.n))]
+        Bs = [synth.make_rhs(n, k, 400 + 10 * rep + i) for i, (n, k) in enumerate(zip(shp.n, shp.k))]
+        for t, a in zip(At, As):
+            t.copy_(torch.from_numpy(a))
+        for t, b in zip(Bt, Bs):
+            t.copy_(torch.from_numpy(b))
+        torch.cuda.synchronize()
+        bt.precondition(At)
+        bt.project_all(Bt, Z, Y, X)
+        torch.cuda.synchronize()
+        assert bt.status() == [0] * len(As)
+        for i in range(len(As)):
+            e = check_member(As[i], Bs[i], Z[i].cpu().numpy(), Y[i].cpu().numpy(), X[i].cpu().numpy())
+            assert max(e) <= TOL, (rep, i, e)
+    bt.close()
+
+
+def test_batch_status_flags_rank_deficient_member(rt):
+    shp = members(4, 73, m_hi=64)
+    As = [synth.make_problem(m, n, 1e3, 500 + i) for i, (m, n) in enumerate(zip(shp.m, shp.n))]
+    As[2][-1] = As[2][0]  # duplicate row: rank m - 1
+    bt = rt.Batch(shp.m, shp.n, shp.l, 3)
+    bt.precondition([torch.from_numpy(A).to(dev()) for A in As])
+    st = bt.status()
+    assert st[2] == 5 and st[0] == st[1] == st[3] == 0, st
+    bt.close()
+
+
+def test_batch_member_equals_single_plan(rt):
+    """A batch of one equals the same problem through a plan (both binary64,
+    same sketch seed derivation, same refinement count)."""
+    m, n, l, k, seed = 48, 3000, 192, 3, 11
+    A = synth.make_problem(m, n, 1e6, 1)
+    B = synth.make_rhs(n, k, 1)
+    bt = rt.Batch([m], [n], [l], seed)
+    bt.precondition([torch.from_numpy(A).to(dev())])
+    Z, Y, X = bt.project_all([torch.from_numpy(B).to(dev())])
+    e = check_member(A, B, Z[0].cpu().numpy(), Y[0].cpu().numpy(), X[0].cpu().numpy())
+    assert max(e) <= TOL, e
+    bt.close()

@@ -108,6 +108,7 @@ def test_sketch_matches_oracle(rt, m, n, l, seed):
 def test_qrcp_matches_oracle(rt, m, n, l, kappa, seed):
     A = synth.make_problem(m, n, kappa, seed)
     plan = rt.Plan(m, n, l, seed)
+    plan.set_qr(rt.QR_DIRECT)  # Householder QRCP of S^T itself, as the oracle
     plan.precondition(torch.from_numpy(A).to(dev()))
     if l == 4096:
         assert plan.info()["qrcp_blocks"] == (m + 15) // 16  # global-memory column mode
@@ -289,4 +290,58 @@ def test_bf16_gram_needs_refinement(rt):
     e0 = errors(B, Z0, Y0, X0, Zr, Yr, Xr)
     e1 = errors(B, Z1, Y1, X1, Zr, Yr, Xr)
     assert e0[2] > 1e-6 and max(e1) <= TOL, (e0, e1)
+    plan.close()
+
+
+# ------------------------------------------------------------ two-stage QR
+
+@pytest.mark.parametrize("mode", ["two_stage", "two_stage_wg"])
+@pytest.mark.parametrize("m,n,l,kappa,seed", [(64, 4096, 256, 1e6, 1), (200, 8192, 800, 1e8, 3),
+                                               (130, 9000, 520, 1e10, 4), (600, 8192, 4096, 1e6, 7)])
+def test_two_stage_qrcp_is_backward_stable(rt, mode, m, n, l, kappa, seed):
+    """R and piv of the two-stage pivoted QR: R^T R = Pi^T S S^T Pi up to a
+    normwise rounding error c u |S|^2 (kappa-independent), the pivoting
+    property |R_kk| >= |R[k:, j]| (j > k) within c u |S|, and a
+    preconditioner as good as the direct one (Lemma 2.4)."""
+    code = {"two_stage": rt.QR_TWO_STAGE, "two_stage_wg": rt.QR_TWO_STAGE_WG}[mode]
+    A = synth.make_problem(m, n, kappa, seed)
+    plan = rt.Plan(m, n, l, seed)
+    plan.set_qr(code)
+    plan.precondition(torch.from_numpy(A).to(dev()))
+    assert plan.info()["qr_mode"] == code
+    ex = plan.export()
+    R, piv = ex["R"].cpu().numpy(), ex["piv"].cpu().numpy()
+    assert sorted(piv.tolist()) == list(range(m))
+    assert np.allclose(np.tril(R, -1), 0)
+    Sr = oracle.srft_sketch(A, seed, l)
+    nS = np.linalg.norm(Sr)
+    u = 2.0 ** -53
+    c = 8.0 * (l * m) ** 0.5 * m
+    M = Sr[piv]                       # rows of S in pivot order = columns of S^T Pi
+    assert np.max(np.abs(R.T @ R - M @ M.T)) <= c * u * nS ** 2
+    for k in range(m - 1):
+        tail = np.linalg.norm(R[k:, k + 1:], axis=0)
+        assert np.all(tail <= abs(R[k, k]) * (1 + 1e-8) + c * u * nS), k
+    W = np.linalg.solve(R.T, A[piv])  # P^{-1} A = R^{-T} Pi A
+    sv = np.linalg.svd(W, compute_uv=False)
+    assert sv[0] / sv[-1] < 10
+    plan.close()
+
+
+@pytest.mark.parametrize("mode", ["direct", "two_stage", "two_stage_wg"])
+@pytest.mark.parametrize("m,n,l,kappa,k,seed", [(100, 5000, 400, 1e8, 5, 2), (130, 9000, 520, 1e10, 3, 3),
+                                                 (1, 50, 1, 1e0, 2, 4), (12, 12, 12, 1e3, 2, 5)])
+def test_projection_matches_oracle_all_qr_modes(rt, mode, m, n, l, kappa, k, seed):
+    code = {"direct": rt.QR_DIRECT, "two_stage": rt.QR_TWO_STAGE, "two_stage_wg": rt.QR_TWO_STAGE_WG}[mode]
+    A = synth.make_problem(m, n, kappa, seed)
+    B = synth.make_rhs(n, k, seed)
+    plan = rt.Plan(m, n, l, seed)
+    plan.set_qr(code)
+    At = torch.from_numpy(A).to(dev())
+    Bt = torch.from_numpy(B).to(dev())
+    plan.precondition(At)
+    Z, Y, X = plan.project_all(Bt)
+    Zr, Yr, Xr, _ = oracle.project(A, B.T)
+    ez, ey, ex = errors(B, Z.cpu().numpy(), Y.cpu().numpy(), X.cpu().numpy(), Zr, Yr, Xr)
+    assert ez <= TOL and ey <= TOL and ex <= TOL, (ez, ey, ex)
     plan.close()

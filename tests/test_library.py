@@ -18,7 +18,8 @@ def declared_symbols():
 def test_header_declares_the_boundary():
     names = declared_symbols()
     for need in ["rtproj_plan_create", "rtproj_precondition", "rtproj_project_null", "rtproj_project_row",
-                 "rtproj_lstsq", "rtproj_project_all", "rtproj_plan_destroy"]:
+                 "rtproj_lstsq", "rtproj_project_all", "rtproj_plan_destroy", "rtproj_batch_create",
+                 "rtproj_batch_precondition", "rtproj_batch_project_all", "rtproj_batch_status"]:
         assert need in names
 
 
@@ -53,3 +54,17 @@ def test_binding_rejects_bad_arguments_before_device_work():
     assert rt.lib().rtproj_plan_create(4, 10, 3, 0, ctypes.byref(h)) == 1
     assert not h.value
     assert rt.lib().rtproj_project_null(None, None, 0, 1, None, 0) == 1
+
+
+def test_batch_rejects_bad_sizes_before_device_work():
+    import paper_0912_1135_amd as rt
+    if not os.path.exists(rt.LIB_PATH):
+        pytest.skip("library not built")
+    L = rt.lib()
+    h = ctypes.c_void_p()
+    i64 = lambda v: (ctypes.c_int64 * len(v))(*v)
+    assert L.rtproj_batch_create(0, i64([1]), i64([4]), i64([2]), 1, ctypes.byref(h)) == 1
+    assert L.rtproj_batch_create(2, i64([4, 5]), i64([8, 8]), i64([2, 5]), 1, ctypes.byref(h)) == 1   # l < m
+    assert L.rtproj_batch_create(1, i64([4]), i64([3]), i64([4]), 1, ctypes.byref(h)) == 1            # n < m
+    assert L.rtproj_batch_create(1, i64([4096]), i64([9000]), i64([8192]), 1, ctypes.byref(h)) == 7  # m too large
+    assert not h.value
