@@ -1,17 +1,25 @@
 #!/usr/bin/env python3
 """Throughput of the randomized orthogonal projection on one MI355X.
 
-One step = the whole path on one batch: precondition A (sketch, pivoted QR,
-R^{-T}, P^{-1}A, Gram, Cholesky) and project k right-hand sides (least squares
-x, row projection A^T x, null projection b - A^T x, with the double-binary64
-refinement), all through the C ABI.  The default workload is the binary64
-one: m = 512, n = 65536, singular values log-spaced 1 -> 1e-10, l = 2048,
-k = 16 Gaussian right-hand sides.
+One step = the whole path on one batch of work: precondition A (sketch,
+pivoted QR, R^{-T}, P^{-1}A, Gram, Cholesky) and project k right-hand sides
+(least-squares x, row projection A^T x, null projection b - A^T x, with the
+compensated refinement), all through the C ABI.
 
-value = projections per second = k / (seconds per step), inputs resident in
-HBM.  Prints one JSON line with the roofline of the dominant kernel (timed
-with HIP events on the plan's stream during the timed steps) and the CPU
-oracle timed on a bounded sample of the same workload.
+Workloads (seeded synthetic inputs, A = U diag(sigma) V^T with Haar factors):
+  plain_512x65536 (default)  m=512, n=65536, sigma 1 -> 1e-10, l=2048, k=16;
+                             binary64, plus the mixed forms on the same inputs
+  plain_64x4096              m=64, n=4096, sigma 1 -> 1e-6, l=256, k=1
+  mixed_2048x262144          m=2048, n=262144, sigma 1 -> 1e-8, l=8192, k=64;
+                             binary32 / bfloat16 forms against binary64
+  batch_256                  256 members, m ~ U{32..512}, n = m U{16..64},
+                             l = 4m, k ~ U{1..64}, sigma 1 -> 1e-6; grouped
+                             launches in a HIP graph against a loop of plans
+
+value = projections per second = (right-hand sides) / (seconds per step),
+inputs resident in HBM.  Prints one JSON line with the roofline of the
+dominant stage (timed with HIP events on the plan's stream during the timed
+steps) and the CPU oracle timed on a bounded sample of the same workload.
 """
 import argparse
 import hashlib
@@ -26,38 +34,61 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "projections/sec (Zb, k RHS) mixed vs FP64 at ≤1e-10 rel err; % HBM/MFMA peak"
+TOL = 1e-10
 
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6          # matrix and vector (FMA = 2 flops)
+PEAK_FP32_TFLOPS = 157.3         # MFMA binary32
+PEAK_BF16_TFLOPS = 2500.0        # MFMA bfloat16, dense
 PEAK_FP64_VALU_TOPS = 39.3       # FP64 VALU instructions/s: 256 CU x 64 lanes x 2.4 GHz
 
+PRECISIONS = {"fp64": 0, "mixed_fp32": 1, "mixed_bf16": 2}
 
-def stage_work(name, m, n, l, k, refine_steps):
-    """Algorithmic work per launch of a stage: (bound, amount, unit-kind)."""
-    if name == "sketch":
-        return "hbm", 8.0 * m * n + 8.0 * m * l, "bytes"          # read A, write S
+
+def log(msg):
+    """Progress on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def stage_work(name, dims, prec="fp64", w_bits=64):
+    """Algorithmic work per launch of a stage summed over the problems in
+    `dims` (a list of (m, n, l, k)): (bound, amount, kind, peak)."""
+    tot = 0.0
+    for (m, n, l, k) in dims:
+        if name == "sketch":
+            tot += 8.0 * m * n + 8.0 * m * l                               # read A, write S
+        elif name == "qrcp":
+            tot += 2.0 * l * m * m - 2.0 * m ** 3 / 3
+        elif name == "qr_r0":
+            # shifted Cholesky QR: three Grams m(m+1)l, two solves m^2 l,
+            # three Cholesky m^3/3 and two triangular products m^3/3
+            tot += 3.0 * m * (m + 1) * l + 2.0 * m * m * l + 5.0 * m ** 3 / 3
+        elif name in ("rinv_trsm", "cholesky", "t_trsm"):
+            tot += m ** 3 / 3.0
+        elif name == "w_gemm":
+            tot += 1.0 * m * m * n                                          # triangular: m^2 n
+        elif name == "gram_syrk":
+            tot += 1.0 * m * (m + 1) * n
+        elif name == "ab":
+            tot += 8.0 * m * n + 8.0 * n * k                                # read A and B
+        elif name in ("refine_atx", "refine_ab", "final_atx"):
+            tot += 10.0 * m * n * k                                         # Dot2: 10 FP64 ops per term
+        else:
+            return None, 0.0, None, None
+    if name in ("sketch", "ab"):
+        return "hbm", tot, "bytes", PEAK_HBM_GBS
     if name == "qrcp":
-        return "alu", 2.0 * l * m * m - 2.0 * m ** 3 / 3, "flops"
-    if name == "qr_r0":
-        # shifted Cholesky QR: three Grams (m(m+1) l), two solves (m^2 l),
-        # three Cholesky (m^3/3) and two triangular products (m^3/3)
-        return "mfma", 3.0 * m * (m + 1) * l + 2.0 * m * m * l + 5.0 * m ** 3 / 3, "flops"
-    if name == "rinv_trsm":
-        return "mfma", m ** 3 / 3.0, "flops"
-    if name == "w_gemm":
-        return "mfma", 1.0 * m * m * n, "flops"                    # triangular: m^2 n
-    if name == "gram_syrk":
-        return "mfma", 1.0 * m * (m + 1) * n, "flops"
-    if name == "cholesky":
-        return "mfma", m ** 3 / 3.0, "flops"
-    if name == "t_trsm":
-        return "mfma", m ** 3 / 3.0, "flops"
-    if name == "ab":
-        return "hbm", 8.0 * m * n + 8.0 * n * k, "bytes"           # read A and B
+        return "alu", tot, "flops", PEAK_FP64_TFLOPS
     if name in ("refine_atx", "refine_ab", "final_atx"):
-        return "alu", 10.0 * m * n * k, "ops"                      # Dot2: 10 FP64 ops per term
-    return None, 0.0, None
+        return "alu", tot, "ops", PEAK_FP64_VALU_TOPS
+    if name == "gram_syrk" and prec == "mixed_bf16":
+        return "mfma", tot, "flops", PEAK_BF16_TFLOPS
+    if name == "gram_syrk" and prec == "mixed_fp32":
+        return "mfma", tot, "flops", PEAK_FP32_TFLOPS
+    if name == "w_gemm" and w_bits == 32:
+        return "mfma", tot, "flops", PEAK_FP32_TFLOPS
+    return "mfma", tot, "flops", PEAK_FP64_TFLOPS
 
 
 # stage -> (kernel name in the profiler's trace, source file of that kernel)
@@ -107,13 +138,288 @@ def copy_calibration(mib):
     del x, y
 
 
+def stage_table(info, steps, dims, prec, w_bits):
+    stages = {}
+    for name, tot in info["stage_ms"].items():
+        calls = info["stage_calls"][name]
+        if not calls:
+            continue
+        d = {"ms_per_step": tot / steps, "ms_per_launch": tot / calls, "launches_per_step": calls / steps}
+        bound, amt, kind, peak = stage_work(name, dims, prec, w_bits)
+        if bound is not None:
+            sec = d["ms_per_launch"] / 1e3
+            if bound == "hbm":
+                d["achieved"], d["unit"] = amt / sec / 1e9, "GB/s"
+            else:
+                d["achieved"], d["unit"] = amt / sec / 1e12, ("TOP/s" if kind == "ops" else "TFLOP/s")
+            d["bound"], d["peak"], d["frac"] = bound, peak, d["achieved"] / peak
+        stages[name] = d
+    return stages
+
+
+def roofline(stages, workload):
+    dom = max(stages, key=lambda s: stages[s]["ms_per_step"])
+    d = stages[dom]
+    if "bound" not in d:
+        return {"bound": None, "achieved": None, "peak": None, "unit": None, "frac": None, "traffic": None,
+                "kernel": dom}
+    return {"bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"], "unit": d["unit"],
+            "frac": d["frac"], "traffic": measured_traffic(dom, workload), "kernel": dom}
+
+
+def rel_errors(B, Z, Y, X, Zr, Yr, Xr):
+    """max over right-hand sides (rows) of |z - z*|/|b|, |p - p*|/|b|, |x - x*|/|x*|."""
+    import numpy as np
+    nb = np.linalg.norm(B, axis=1)
+    return (float(np.max(np.linalg.norm(Z - Zr, axis=1) / nb)),
+            float(np.max(np.linalg.norm(Y - Yr, axis=1) / nb)),
+            float(np.max(np.linalg.norm(X - Xr, axis=1) / np.linalg.norm(Xr, axis=1))))
+
+
+def time_plan(plan, At, Bt, Z, Y, X, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        plan.precondition(At)
+        plan.project_all(Bt, Z, Y, X)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        plan.precondition(At)
+        plan.project_all(Bt, Z, Y, X)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    info = plan.info()
+    plan.set_timing(False)
+    return (t2 - t1) * 1e3 / steps, info
+
+
+def run_single(args, rt, synth, np, torch):
+    c = synth.CONFIGS[args.workload]
+    m, n, l, k, kappa, seed = c["m"], c["n"], c["l"], c["k"], c["kappa"], c["seed"]
+    t0 = time.time()
+    log(f"generating {args.workload}: {m} x {n}")
+    A = synth.make_problem(m, n, kappa, seed)
+    B = synth.make_rhs(n, k, seed)
+    gen_s = time.time() - t0
+    log(f"inputs ready in {gen_s:.1f} s")
+    dev = torch.device("cuda", 0)
+    At = torch.from_numpy(A).to(dev)
+    Bt = torch.from_numpy(B).to(dev)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+    mixed_wl = args.workload.startswith("mixed")
+    main_prec = args.precision or ("mixed_fp32" if mixed_wl else "fp64")
+    forms_to_run = [main_prec] + ([] if args.no_forms else [p for p in PRECISIONS if p != main_prec])
+    dims = [(m, n, l, k)]
+    forms, outputs, main = {}, {}, None
+    for prec in forms_to_run:
+        plan = rt.Plan(m, n, l, seed)
+        plan.set_precision(PRECISIONS[prec])
+        plan.set_refinement(args.refine_steps, 0.0)
+        plan.set_qr(args.qr)
+        Z, Y = torch.empty_like(Bt), torch.empty_like(Bt)
+        X = torch.empty((k, m), dtype=torch.float64, device=dev)
+        steps = args.steps if prec == main_prec else min(args.steps, args.form_steps)
+        ms, info = time_plan(plan, At, Bt, Z, Y, X, steps, args.warmup)
+        log(f"{prec}: {ms:.3f} ms per step")
+        plan.close()
+        stages = stage_table(info, steps, dims, prec, info["w_bits"])
+        outputs[prec] = (Z.cpu().numpy(), Y.cpu().numpy(), X.cpu().numpy())
+        forms[prec] = {"value": k / (ms / 1e3), "ms_per_step": ms, "steps": steps,
+                       "refine_steps": info["refine_steps"], "sketch_bits": info["sketch_bits"],
+                       "w_bits": info["w_bits"], "gram_bits": info["gram_bits"],
+                       "sketch_escalated": info["sketch_escalated"], "kappa_est": info["kappa_est"],
+                       "gram_cond_est": info["gram_cond_est"], "qr_mode": info["qr_mode"],
+                       "stage_ms": {s: round(d["ms_per_step"], 4) for s, d in stages.items()}}
+        if prec == main_prec:
+            main = (ms, info, stages, steps)
+        del Z, Y, X
+    ms_per_step, info, stages, steps = main
+    value = k / (ms_per_step / 1e3)
+    bits = {"fp64": "f64", "mixed_fp32": "f64+f32", "mixed_bf16": "f64+bf16"}[main_prec]
+    result = {
+        "metric": METRIC, "value": value, "unit": "projections/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": bits, "data": "synthetic",
+        "config": {"workload": f"{args.workload}: A = U diag(sigma) V^T (Haar U, V), m={m}, n={n}, "
+                               f"sigma log-spaced 1..1/{kappa:g}, l={l}, k={k} Gaussian right-hand sides, "
+                               f"{main_prec}", "m": m, "n": n, "l": l, "k": k, "kappa": kappa,
+                   "precision": main_prec, "refine_steps": info["refine_steps"], "parallelism": "single GPU"},
+        "roofline": roofline(stages, args.workload),
+        "stages": stages,
+        "forms": forms,
+        "kappa_est": info["kappa_est"],
+        "qrcp_blocks": info["qrcp_blocks"],
+        "qr_mode": info["qr_mode"],
+    }
+    # parity of every form: against the oracle on a bounded set of columns, or,
+    # at sizes the oracle cannot finish in seconds, against the binary64 form
+    # plus A z = 0 (a property that holds at any size)
+    cpu_sample = None
+    oracle_ok = m * n <= 512 * 65536 and not args.no_parity
+    if oracle_ok or not args.no_cpu_baseline:
+        import oracle
+        threads = oracle.num_threads()
+        ks = min(k, threads) if m * n <= 512 * 65536 else min(k, 2)
+        log(f"oracle on {ks} right-hand sides")
+        t3 = time.perf_counter()
+        Zr, Yr, Xr, _ = oracle.project(A, B[:ks].T)
+        t4 = time.perf_counter()
+        log(f"oracle done in {t4 - t3:.1f} s")
+        if oracle_ok:
+            for prec, (Zg, Yg, Xg) in outputs.items():
+                ez, ep, ex = rel_errors(B[:ks], Zg[:ks], Yg[:ks], Xg[:ks], Zr.T, Yr.T, Xr.T)
+                forms[prec].update({"e_z": ez, "e_p": ep, "e_x": ex, "parity": "oracle", "columns_checked": ks,
+                                    "pass": max(ez, ep, ex) <= TOL})
+        if not args.no_cpu_baseline:
+            cpu_sample = {"value": ks / (t4 - t3), "unit": "projections/s", "cores": threads, "kind": "oracle",
+                          "sample": f"Householder QR of A^T plus binary128 refinement for {ks} of the {k} "
+                                    f"right-hand sides of the same {m} x {n} workload ({t4 - t3:.1f} s)"}
+    if not oracle_ok and not args.no_parity and "fp64" in outputs:
+        Z64, Y64, X64 = outputs["fp64"]
+        nA = float(np.linalg.norm(A, 2))
+        for prec, (Zg, Yg, Xg) in outputs.items():
+            ez, ep, ex = rel_errors(B, Zg, Yg, Xg, Z64, Y64, X64)
+            az = float(np.max(np.linalg.norm(A @ Zg.T, axis=0) / (nA * np.linalg.norm(B, axis=1))))
+            forms[prec].update({"e_z_vs_fp64": ez, "e_p_vs_fp64": ep, "e_x_vs_fp64": ex, "rel_Az": az,
+                                "parity": "against the binary64 GPU form and A z = 0",
+                                "pass": max(ez, ep, ex) <= TOL})
+    result["cpu_baseline"] = cpu_sample
+    result["parity"] = {p: {key: forms[p][key] for key in ("e_z", "e_p", "e_x", "e_z_vs_fp64", "e_p_vs_fp64",
+                                                           "e_x_vs_fp64", "rel_Az", "pass") if key in forms[p]}
+                        for p in forms}
+    result["input_generation_s"] = gen_s
+    return result
+
+
+def run_batch(args, rt, synth, np, torch):
+    c = synth.CONFIGS[args.workload]
+    count, kappa, seed = c["count"], c["kappa"], c["seed"]
+    shp = synth.make_batch_shapes(count, seed)
+    t0 = time.time()
+    log(f"generating {count} members")
+    As = []
+    for i, (m, n) in enumerate(zip(shp.m, shp.n)):
+        As.append(synth.make_problem(m, n, kappa, seed + 1000 + i))
+        if i % 64 == 63:
+            log(f"  {i + 1} members")
+    Bs = [synth.make_rhs(n, k, seed + 5000 + i) for i, (n, k) in enumerate(zip(shp.n, shp.k))]
+    gen_s = time.time() - t0
+    log(f"inputs ready in {gen_s:.1f} s")
+    dev = torch.device("cuda", 0)
+    At = [torch.from_numpy(A).to(dev) for A in As]
+    Bt = [torch.from_numpy(B).to(dev) for B in Bs]
+    Z = [torch.empty_like(b) for b in Bt]
+    Y = [torch.empty_like(b) for b in Bt]
+    X = [torch.empty((k, m), dtype=torch.float64, device=dev) for m, k in zip(shp.m, shp.k)]
+    ksum = int(sum(shp.k))
+    dims = list(zip(shp.m, shp.n, shp.l, shp.k))
+    bt = rt.Batch(shp.m, shp.n, shp.l, seed)
+    bt.set_refinement(2)
+    # per-stage times from eager (ungraphed) steps
+    bt.set_graph(False)
+    bt.precondition(At)
+    bt.project_all(Bt, Z, Y, X)
+    torch.cuda.synchronize()
+    bt.set_timing(True)
+    tsteps = 2
+    for _ in range(tsteps):
+        bt.precondition(At)
+        bt.project_all(Bt, Z, Y, X)
+    torch.cuda.synchronize()
+    binfo = bt.info()
+    bt.set_timing(False)
+    stages = stage_table(binfo, tsteps, dims, "fp64", 64)
+    # the timed steps replay the captured graphs
+    bt.set_graph(True)
+    for _ in range(args.warmup):
+        bt.precondition(At)
+        bt.project_all(Bt, Z, Y, X)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        bt.precondition(At)
+        bt.project_all(Bt, Z, Y, X)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    status = bt.status()
+    ms_per_step = (t2 - t1) * 1e3 / args.steps
+    log(f"batch (graph): {ms_per_step:.3f} ms per step")
+    value = ksum / (ms_per_step / 1e3)
+    # baseline on the same GPU: one binary64 plan per member, one after another
+    plans = [rt.Plan(m, n, l, 0) for m, n, l in zip(shp.m, shp.n, shp.l)]
+    Zl = [torch.empty_like(b) for b in Bt]
+    for p, a, b, z in zip(plans, At, Bt, Zl):  # warm-up
+        p.precondition(a)
+        p.project_all(b, z, None, None, want=(True, False, False))
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    for p, a, b, z in zip(plans, At, Bt, Zl):
+        p.precondition(a)
+        p.project_all(b, z, None, None, want=(True, False, False))
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    for p in plans:
+        p.close()
+    loop_value = ksum / (t4 - t3)
+    log(f"loop of plans: {(t4 - t3) * 1e3:.3f} ms per step")
+    result = {
+        "metric": METRIC, "value": value, "unit": "projections/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {count} members, m ~ U{{32..512}}, n = m U{{16..64}}, l = 4m, "
+                               f"k ~ U{{1..64}}, sigma log-spaced 1..1/{kappa:g}; grouped launches replayed from "
+                               "a HIP graph", "members": count, "sum_k": ksum,
+                   "sum_mn": int(sum(m * n for m, n in zip(shp.m, shp.n))), "precision": "fp64",
+                   "refine_steps": 2, "parallelism": "single GPU"},
+        "roofline": roofline(stages, args.workload),
+        "stages": stages,
+        "forms": {"batch_graph": {"value": value, "ms_per_step": ms_per_step},
+                  "loop_of_plans": {"value": loop_value, "ms_per_step": (t4 - t3) * 1e3}},
+        "member_status_nonzero": [i for i, s in enumerate(status) if s != 0],
+    }
+    cpu_sample = None
+    if not (args.no_parity and args.no_cpu_baseline):
+        import oracle
+        threads = oracle.num_threads()
+        order = np.argsort(np.array(shp.m) * np.array(shp.n))
+        pick = sorted(set([int(order[0]), int(order[len(order) // 2]), int(order[-1])] +
+                          [int(i) for i in np.linspace(0, count - 1, 5).astype(int)]))
+        worst = [0.0, 0.0, 0.0]
+        t5 = time.perf_counter()
+        kdone = 0
+        log(f"oracle on members {pick}")
+        for i in pick:
+            Zr, Yr, Xr, _ = oracle.project(As[i], Bs[i].T)
+            kdone += Bs[i].shape[0]
+            e = rel_errors(Bs[i], Z[i].cpu().numpy(), Y[i].cpu().numpy(), X[i].cpu().numpy(), Zr.T, Yr.T, Xr.T)
+            worst = [max(a, b) for a, b in zip(worst, e)]
+        t6 = time.perf_counter()
+        result["parity"] = {"members_checked": pick, "e_z": worst[0], "e_p": worst[1], "e_x": worst[2],
+                            "tol": TOL, "pass": max(worst) <= TOL}
+        if not args.no_cpu_baseline:
+            cpu_sample = {"value": kdone / (t6 - t5), "unit": "projections/s", "cores": threads, "kind": "oracle",
+                          "sample": f"members {pick} of the same batch (all their right-hand sides, "
+                                    f"{kdone} projections, {t6 - t5:.1f} s)"}
+    result["cpu_baseline"] = cpu_sample
+    result["input_generation_s"] = gen_s
+    bt.close()
+    return result
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="plain_512x65536",
-                    help="plain_512x65536 or plain_64x4096 (single-instance binary64 workloads)")
+                    choices=["plain_512x65536", "plain_64x4096", "mixed_2048x262144", "batch_256"])
+    ap.add_argument("--precision", default=None, choices=list(PRECISIONS),
+                    help="form of the main line (default: fp64, or mixed_fp32 for the mixed workload)")
+    ap.add_argument("--no-forms", action="store_true", help="time only the main precision")
+    ap.add_argument("--form-steps", type=int, default=10, help="timed steps of the other precision forms")
     ap.add_argument("--refine-steps", type=int, default=-1, help="-1: chosen from the pivoted-QR rank estimate")
     ap.add_argument("--qr", type=int, default=0, help="pivoted-QR method: 0 auto, 1 direct, 2 two-stage, "
                                                       "3 two-stage with a single-workgroup second stage")
@@ -135,115 +441,10 @@ def main():
     import paper_0912_1135_amd as rt
     from paper_0912_1135_amd import synth
 
-    c = synth.CONFIGS[args.workload]
-    m, n, l, k, kappa, seed = c["m"], c["n"], c["l"], c["k"], c["kappa"], c["seed"]
-    t0 = time.time()
-    A = synth.make_problem(m, n, kappa, seed)
-    B = synth.make_rhs(n, k, seed)
-    gen_s = time.time() - t0
-    dev = torch.device("cuda", 0)
-    At = torch.from_numpy(A).to(dev)
-    Bt = torch.from_numpy(B).to(dev)
-    Z = torch.empty_like(Bt)
-    Y = torch.empty_like(Bt)
-    X = torch.empty((k, m), dtype=torch.float64, device=dev)
-
-    if args.copy_calibration:
-        copy_calibration(args.copy_calibration)
-    plan = rt.Plan(m, n, l, seed)
-    plan.set_refinement(args.refine_steps, 0.0)
-    plan.set_qr(args.qr)
-
-    def step():
-        plan.precondition(At)
-        plan.project_all(Bt, Z, Y, X)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    plan.set_timing(True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    info = plan.info()
-    plan.set_timing(False)
-    ms_per_step = (t2 - t1) * 1e3 / args.steps
-    value = k / (ms_per_step / 1e3)
-
-    # per-stage device time per step and the dominant stage's roofline
-    stages = {}
-    for name, tot in info["stage_ms"].items():
-        calls = info["stage_calls"][name]
-        if calls:
-            stages[name] = {"ms_per_step": tot / args.steps, "ms_per_launch": tot / calls,
-                            "launches_per_step": calls / args.steps}
-    dom = max(stages, key=lambda s: stages[s]["ms_per_step"])
-    bound, amount, kind = stage_work(dom, m, n, l, k, args.refine_steps)
-    sec = stages[dom]["ms_per_launch"] / 1e3
-    if bound == "hbm":
-        roof = {"bound": "hbm", "achieved": amount / sec / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
-    elif bound == "mfma":
-        roof = {"bound": "mfma", "achieved": amount / sec / 1e12, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s"}
-    elif kind == "ops":
-        roof = {"bound": "alu", "achieved": amount / sec / 1e12, "peak": PEAK_FP64_VALU_TOPS, "unit": "TFLOP/s"}
+    if args.workload == "batch_256":
+        result = run_batch(args, rt, synth, np, torch)
     else:
-        roof = {"bound": "alu", "achieved": amount / sec / 1e12, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic(dom, args.workload)
-    roof["kernel"] = dom
-    for name, d in stages.items():
-        b, amt, kd = stage_work(name, m, n, l, k, args.refine_steps)
-        if b is None:
-            continue
-        s = d["ms_per_launch"] / 1e3
-        if b == "hbm":
-            d["achieved"], d["unit"], d["frac"] = amt / s / 1e9, "GB/s", amt / s / 1e9 / PEAK_HBM_GBS
-        elif kd == "ops":
-            d["achieved"], d["unit"], d["frac"] = amt / s / 1e12, "TOP/s", amt / s / 1e12 / PEAK_FP64_VALU_TOPS
-        else:
-            d["achieved"], d["unit"], d["frac"] = amt / s / 1e12, "TFLOP/s", amt / s / 1e12 / PEAK_FP64_TFLOPS
-
-    result = {
-        "metric": METRIC, "value": value, "unit": "projections/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"fp64 plain: A = U diag(sigma) V^T, m={m}, n={n}, sigma log-spaced 1..1/{kappa:g}, "
-                               f"l={l}, k={k} Gaussian RHS", "m": m, "n": n, "l": l, "k": k, "kappa": kappa,
-                   "precision": "fp64", "refine_steps": info["refine_steps"], "parallelism": "single GPU"},
-        "roofline": roof,
-        "stages": stages,
-        "kappa_est": info["kappa_est"],
-        "qrcp_blocks": info["qrcp_blocks"],
-        "qr_mode": info["qr_mode"],
-    }
-
-    cpu_sample = None
-    if not args.no_parity or not args.no_cpu_baseline:
-        import oracle
-        threads = oracle.num_threads()
-        ks = min(k, threads)
-        Zg, Yg, Xg = Z[:ks].cpu().numpy(), Y[:ks].cpu().numpy(), X[:ks].cpu().numpy()
-        t3 = time.perf_counter()
-        Zr, Yr, Xr, oinfo = oracle.project(A, B[:ks].T)
-        t4 = time.perf_counter()
-        nb = np.linalg.norm(B[:ks], axis=1)
-        result["parity"] = {
-            "columns_checked": ks,
-            "e_z": float(np.max(np.linalg.norm(Zg - Zr.T, axis=1) / nb)),
-            "e_p": float(np.max(np.linalg.norm(Yg - Yr.T, axis=1) / nb)),
-            "e_x": float(np.max(np.linalg.norm(Xg - Xr.T, axis=1) / np.linalg.norm(Xr.T, axis=1))),
-            "tol": 1e-10,
-        }
-        if not args.no_cpu_baseline:
-            cpu_sample = {"value": ks / (t4 - t3), "unit": "projections/s", "cores": threads, "kind": "oracle",
-                          "sample": f"Householder QR of A^T plus binary128 refinement for {ks} of the {k} "
-                                    f"right-hand sides of the same {m} x {n} workload ({t4 - t3:.1f} s)"}
-    result["cpu_baseline"] = cpu_sample
-    result["input_generation_s"] = gen_s
-    plan.close()
+        result = run_single(args, rt, synth, np, torch)
     print(json.dumps(result))
 
 

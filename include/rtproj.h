@@ -255,6 +255,12 @@ rtproj_status rtproj_batch_project_all(rtproj_batch batch, const double *const *
  * NULL), RTPROJ_OK or RTPROJ_ERR_RANK (|R_mm| <= m 2^-52 |R_11|, a NaN in A,
  * or a Cholesky breakdown); returns the worst. */
 rtproj_status rtproj_batch_status(rtproj_batch batch, int *per_member);
+/* Per-stage device time of the batch (stage indices as in rtproj_info),
+ * accumulated while enabled; only eager (non-graph) calls are timed, and a
+ * timed call waits for its stream. */
+rtproj_status rtproj_batch_set_timing(rtproj_batch batch, int enable);
+/* Batch totals: largest m, n, l; refinement steps; stage times. */
+rtproj_status rtproj_batch_info(rtproj_batch batch, rtproj_info *out);
 /* Sizes and the rank estimates of member i (valid after rtproj_batch_status). */
 rtproj_status rtproj_batch_member_info(rtproj_batch batch, int64_t i, rtproj_info *out);
 

@@ -79,6 +79,8 @@ def lib():
         L.rtproj_batch_project_all.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.rtproj_batch_status.argtypes = [vp, vp]
         L.rtproj_batch_member_info.argtypes = [vp, i64, ctypes.POINTER(_Info)]
+        L.rtproj_batch_set_timing.argtypes = [vp, ip]
+        L.rtproj_batch_info.argtypes = [vp, ctypes.POINTER(_Info)]
         L.rtproj_status_string.argtypes = [ip]
         L.rtproj_status_string.restype = ctypes.c_char_p
         L.rtproj_last_error.restype = ctypes.c_char_p
@@ -89,7 +91,7 @@ def lib():
                      "rtproj_plan_set_timing", "rtproj_batch_create", "rtproj_batch_destroy",
                      "rtproj_batch_set_stream", "rtproj_batch_set_refinement", "rtproj_batch_set_graph",
                      "rtproj_batch_precondition", "rtproj_batch_project_all", "rtproj_batch_status",
-                     "rtproj_batch_member_info"]:
+                     "rtproj_batch_member_info", "rtproj_batch_set_timing", "rtproj_batch_info"]:
             getattr(L, name).restype = ip
         _lib = L
     return _lib
@@ -321,6 +323,17 @@ class Batch:
         per = (ctypes.c_int * self.count)()
         lib().rtproj_batch_status(self.handle, per)
         return list(per)
+
+    def set_timing(self, enable: bool):
+        _check(lib().rtproj_batch_set_timing(self.handle, 1 if enable else 0))
+
+    def info(self) -> dict:
+        inf = _Info()
+        _check(lib().rtproj_batch_info(self.handle, ctypes.byref(inf)))
+        d = {f: getattr(inf, f) for f, _ in _Info._fields_ if f not in ("t_stage_ms", "stage_calls")}
+        d["stage_ms"] = {name: inf.t_stage_ms[i] for i, name in enumerate(STAGES)}
+        d["stage_calls"] = {name: inf.stage_calls[i] for i, name in enumerate(STAGES)}
+        return d
 
     def member_info(self, i: int) -> dict:
         inf = _Info()

@@ -33,11 +33,18 @@ struct Op {
     rt::SketchGroupShape ss{};
     int64_t total = 0;  // element counts for the elementwise ops
     int i0 = 0, i1 = 0, i2 = 0, dd = 0;
+    int stage = -1;     // rtproj_info stage index the op is accounted to
 };
 
 struct Program {
     std::vector<unsigned char> bytes;
     std::vector<Op> ops;
+    int stage = -1;  // stage of the ops recorded next
+    void push(Op o)
+    {
+        o.stage = stage;
+        ops.push_back(o);
+    }
     template <class T>
     size_t add(const std::vector<T> &v)
     {
@@ -64,6 +71,9 @@ struct rtproj_batch_s {
     hipStream_t cap_stream = nullptr;  // graph capture (the null stream cannot be captured)
     int refine_steps = 2;
     int use_graph = 0;
+    int timing = 0;                 // per-stage HIP events (eager mode only)
+    double t_stage_ms[16] = {};
+    int64_t stage_calls[16] = {};
     int64_t max_m = 0, max_n = 0, max_l = 0;
     double *d_diag_all = nullptr;  // count x 8: |R| ends of R (4), of the Gram factor (4)
     bool ready = false;
@@ -104,21 +114,21 @@ void rec_gemm(Program &P, const std::vector<rt::GemmArgs> &v)
 {
     Op o{OP_GEMM, P.add(v), (int)v.size()};
     o.gs = shape_of(v);
-    P.ops.push_back(o);
+    P.push(o);
 }
 
 void rec_reduce(Program &P, const std::vector<rt::ReduceGroupArgs> &v)
 {
     Op o{OP_REDUCE, P.add(v), (int)v.size()};
     for (const auto &r : v) o.total = std::max<int64_t>(o.total, (int64_t)r.M * r.N);
-    P.ops.push_back(o);
+    P.push(o);
 }
 
 void rec_mat(Program &P, OpKind kind, const std::vector<rt::MatGroupArgs> &v)
 {
     Op o{kind, P.add(v), (int)v.size()};
     for (const auto &r : v) o.total = std::max<int64_t>(o.total, (int64_t)r.m * std::max(r.n, r.m));
-    P.ops.push_back(o);
+    P.push(o);
 }
 
 // C (m x m, both triangles) = X X^T for each member's row-major m x K X.
@@ -162,7 +172,7 @@ void rec_cholesky(Program &P, rtproj_batch b, const std::vector<double *> &C, co
     for (int64_t bk = 0; bk < nblk; ++bk) {
         Op o{OP_CHOL, choff, (int)cnt};
         o.i0 = (int)bk;
-        P.ops.push_back(o);
+        P.push(o);
         std::vector<rt::GemmArgs> pan(cnt), upd(cnt);
         for (int64_t i = 0; i < cnt; ++i) {
             rtproj_plan p = b->sub[i];
@@ -229,6 +239,7 @@ void build_precondition(Program &P, rtproj_batch b, const double *const *A, cons
 {
     const int64_t cnt = b->count;
     // 1. sketches
+    P.stage = 0;
     {
         std::vector<rt::SketchGroupArgs> v(cnt);
         Op o{OP_SKETCH, 0, (int)cnt};
@@ -241,7 +252,7 @@ void build_precondition(Program &P, rtproj_batch b, const double *const *A, cons
             o.ss.chunks = std::max<int>(o.ss.chunks, (int)((p->m + p->rows_chunk - 1) / p->rows_chunk));
         }
         o.off = P.add(v);
-        P.ops.push_back(o);
+        P.push(o);
     }
     std::vector<double *> G(cnt), Yq(cnt), L1(cnt), L2(cnt), L3(cnt), R0(cnt), S(cnt), Rm(cnt), Ym(cnt), Lm(cnt);
     std::vector<const double *> cYq(cnt);
@@ -262,9 +273,10 @@ void build_precondition(Program &P, rtproj_batch b, const double *const *A, cons
         }
         o.off = P.add(flags);
         o.count = (int)flags.size();
-        P.ops.push_back(o);
+        P.push(o);
     }
     // 2a. R0 by shifted Cholesky QR
+    P.stage = 12;
     {
         std::vector<rt::CopyGroupArgs> c(cnt);
         int64_t tot = 0;
@@ -275,7 +287,7 @@ void build_precondition(Program &P, rtproj_batch b, const double *const *A, cons
         }
         Op o{OP_COPY, P.add(c), (int)cnt};
         o.total = tot;
-        P.ops.push_back(o);
+        P.push(o);
     }
     std::vector<double *> Ls[3] = {L1, L2, L3};
     std::vector<const double *> Dl(cnt);
@@ -311,6 +323,7 @@ void build_precondition(Program &P, rtproj_batch b, const double *const *A, cons
         rec_gemm(P, g);
     }
     // 2b. pivoted QR of R0, one workgroup per member
+    P.stage = 1;
     {
         std::vector<rt::MatGroupArgs> z(cnt);
         for (int64_t i = 0; i < cnt; ++i) z[i] = rt::MatGroupArgs{Rm[i], mm[i], (int)mm[i], (int)mm[i], 0.0, nullptr, nullptr};
@@ -321,19 +334,20 @@ void build_precondition(Program &P, rtproj_batch b, const double *const *A, cons
             q[i] = rt::QrcpWgArgs{p->d_R0, p->m, (int)p->m, (int)p->m, p->d_R, p->d_piv,
                                   reinterpret_cast<int *>(p->d_sync + 2)};
         }
-        P.ops.push_back(Op{OP_QRCPWG, P.add(q), (int)cnt});
+        P.push(Op{OP_QRCPWG, P.add(q), (int)cnt});
         std::vector<rt::MatGroupArgs> rd(cnt);
         for (int64_t i = 0; i < cnt; ++i)
             rd[i] = rt::MatGroupArgs{Rm[i], mm[i], (int)mm[i], (int)mm[i], 0.0, nullptr, b->d_diag_all + 8 * i};
         rec_mat(P, OP_RDIAG, rd);
     }
     // 3. R^{-T} in d_Y: diagonal-block inverses, identity, blocked solve
+    P.stage = 2;
     {
         std::vector<rt::TriInvGroupArgs> t(cnt);
         for (int64_t i = 0; i < cnt; ++i) t[i] = rt::TriInvGroupArgs{Rm[i], 1, mm[i], (int)mm[i], b->sub[i]->d_DinvR};
         Op o{OP_TRIINV, P.add(t), (int)cnt};
         o.i0 = (int)b->max_m;
-        P.ops.push_back(o);
+        P.push(o);
         std::vector<rt::MatGroupArgs> id(cnt);
         for (int64_t i = 0; i < cnt; ++i) id[i] = rt::MatGroupArgs{Ym[i], mm[i], (int)mm[i], (int)mm[i], 0.0, nullptr, nullptr};
         rec_mat(P, OP_SET1, id);
@@ -342,6 +356,7 @@ void build_precondition(Program &P, rtproj_batch b, const double *const *A, cons
         rec_trsm(P, b, Rc, 0, 1, Dr, Ym, mm, mm, true);
     }
     // 4. W = R^{-T} (Pi A)
+    P.stage = 3;
     {
         std::vector<rt::GemmArgs> g(cnt);
         for (int64_t i = 0; i < cnt; ++i) {
@@ -360,10 +375,13 @@ void build_precondition(Program &P, rtproj_batch b, const double *const *A, cons
         std::vector<const double *> W(cnt);
         std::vector<int64_t> nn(cnt);
         for (int64_t i = 0; i < cnt; ++i) { W[i] = b->sub[i]->d_W; nn[i] = b->sub[i]->n; }
+        P.stage = 4;
         rec_gram(P, b, W, nn, nn, G);
+        P.stage = 5;
         rec_cholesky(P, b, G, Lm);
     }
     // 7. T = L^{-1} R^{-T} (in d_Y), T' = T Pi
+    P.stage = 6;
     {
         std::vector<const double *> Lc(cnt);
         for (int64_t i = 0; i < cnt; ++i) Lc[i] = Lm[i];
@@ -422,10 +440,10 @@ void rec_ab(Program &P, rtproj_batch b, const std::vector<int64_t> &k, const dou
         o.total = std::max<int64_t>(o.total, p->m * k[i]);
     }
     o.off = P.add(v);
-    P.ops.push_back(o);
+    P.push(o);
     Op r = o;
     r.kind = OP_ABRED;
-    P.ops.push_back(r);
+    P.push(r);
 }
 
 void rec_atx(Program &P, rtproj_batch b, const std::vector<rt::AtxGroupArgs> &v, int dd)
@@ -437,7 +455,7 @@ void rec_atx(Program &P, rtproj_batch b, const std::vector<rt::AtxGroupArgs> &v,
         o.i1 = std::max(o.i1, a.a.k);
     }
     (void)b;
-    P.ops.push_back(o);
+    P.push(o);
 }
 
 void build_project(Program &P, rtproj_batch b, const double *const *A, const int64_t *lda, const double *const *B,
@@ -453,7 +471,9 @@ void build_project(Program &P, rtproj_batch b, const double *const *A, const int
         c[i] = p->d_c; r[i] = p->d_r; xhi[i] = p->d_xhi; dd[i] = p->d_d; nn[i] = p->n; mm[i] = p->m;
     }
     // c = A b; x = M^{-1} c; xlo = 0
+    P.stage = 7;
     rec_ab(P, b, kk, A, lda, Bv, lb, 0);
+    P.stage = 8;
     rec_minv(P, b, kk, c, xhi);
     {
         std::vector<rt::MatGroupArgs> z(cnt);
@@ -467,16 +487,20 @@ void build_project(Program &P, rtproj_batch b, const double *const *A, const int
             a[i] = rt::AtxGroupArgs{rt::ApplyArgs{(int)p->m, (int)p->n, (int)kk[i], A[i], lda[i]}, p->d_xhi, p->d_xlo,
                                     p->m, B[i], ldb[i], p->d_r, p->n, nullptr, 0, nullptr, 0};
         }
+        P.stage = 9;
         rec_atx(P, b, a, 1);
+        P.stage = 10;
         rec_ab(P, b, kk, A, lda, r, nn, 1);
+        P.stage = 8;
         rec_minv(P, b, kk, c, dd);
         std::vector<rt::DdGroupArgs> u(cnt);
         for (int64_t i = 0; i < cnt; ++i) {
             rtproj_plan p = b->sub[i];
             u[i] = rt::DdGroupArgs{p->d_xhi, p->d_xlo, p->d_d, (int)(p->m * kk[i]), p->d_norms};
         }
-        P.ops.push_back(Op{OP_DDUPD, P.add(u), (int)cnt});
+        P.push(Op{OP_DDUPD, P.add(u), (int)cnt});
     }
+    P.stage = 11;
     {
         std::vector<rt::AtxGroupArgs> a(cnt);
         for (int64_t i = 0; i < cnt; ++i) {
@@ -499,7 +523,7 @@ void build_project(Program &P, rtproj_batch b, const double *const *A, const int
         }
         Op o{OP_COPY, P.add(cp), (int)cnt};
         o.total = tot;
-        P.ops.push_back(o);
+        P.push(o);
     }
 }
 
@@ -557,7 +581,37 @@ rtproj_status run_program(rtproj_batch b, rtproj_batch_s::Slot &slot, const Prog
         a.shadow = P.bytes;
     }
     if (!b->use_graph) {
-        for (const Op &o : P.ops) RT_HIP(run_op(o, a.d, s));
+        if (!b->timing) {
+            for (const Op &o : P.ops) RT_HIP(run_op(o, a.d, s));
+            return RTPROJ_OK;
+        }
+        // per-stage events around each run of ops of one stage
+        struct Ev { int stage; hipEvent_t e0, e1; };
+        std::vector<Ev> evs;
+        size_t i = 0;
+        hipError_t err = hipSuccess;
+        while (i < P.ops.size() && err == hipSuccess) {
+            const int st = P.ops[i].stage;
+            Ev ev{st, nullptr, nullptr};
+            (void)hipEventCreate(&ev.e0);
+            (void)hipEventCreate(&ev.e1);
+            (void)hipEventRecord(ev.e0, s);
+            for (; i < P.ops.size() && P.ops[i].stage == st; ++i)
+                if ((err = run_op(P.ops[i], a.d, s)) != hipSuccess) break;
+            (void)hipEventRecord(ev.e1, s);
+            evs.push_back(ev);
+        }
+        (void)hipStreamSynchronize(s);
+        for (Ev &ev : evs) {
+            float ms = 0.f;
+            if (ev.stage >= 0 && ev.stage < 16 && hipEventElapsedTime(&ms, ev.e0, ev.e1) == hipSuccess) {
+                b->t_stage_ms[ev.stage] += ms;
+                b->stage_calls[ev.stage] += 1;
+            }
+            (void)hipEventDestroy(ev.e0);
+            (void)hipEventDestroy(ev.e1);
+        }
+        RT_HIP(err);
         return RTPROJ_OK;
     }
     if (!slot.exec || slot.graph_key != P.bytes) {
@@ -655,6 +709,25 @@ rtproj_status rtproj_batch_set_graph(rtproj_batch b, int enable)
 {
     if (!b) return fail(RTPROJ_ERR_INVALID_ARG, "null batch");
     b->use_graph = enable ? 1 : 0;
+    return RTPROJ_OK;
+}
+
+rtproj_status rtproj_batch_set_timing(rtproj_batch b, int enable)
+{
+    if (!b) return fail(RTPROJ_ERR_INVALID_ARG, "null batch");
+    b->timing = enable ? 1 : 0;
+    for (int s = 0; s < 16; ++s) { b->t_stage_ms[s] = 0.0; b->stage_calls[s] = 0; }
+    return RTPROJ_OK;
+}
+
+rtproj_status rtproj_batch_info(rtproj_batch b, rtproj_info *out)
+{
+    if (!b || !out) return fail(RTPROJ_ERR_INVALID_ARG, "null batch or output");
+    std::memset(out, 0, sizeof(*out));
+    out->m = b->max_m; out->n = b->max_n; out->l = b->max_l;
+    out->refine_steps = b->refine_steps;
+    out->qr_mode = RTPROJ_QR_TWO_STAGE_WG;
+    for (int s = 0; s < 16; ++s) { out->t_stage_ms[s] = b->t_stage_ms[s]; out->stage_calls[s] = b->stage_calls[s]; }
     return RTPROJ_OK;
 }
 
