@@ -22,7 +22,7 @@ namespace {
 
 enum OpKind {
     OP_GEMM, OP_REDUCE, OP_SKETCH, OP_COPY, OP_SET0, OP_SET1, OP_SHIFT, OP_CHOL, OP_TRIINV, OP_QRCPWG, OP_RDIAG,
-    OP_FORMTP, OP_ZERO, OP_AB, OP_ABRED, OP_ATX, OP_DDUPD
+    OP_FORMTP, OP_ZERO, OP_AB, OP_ABRED, OP_ATX, OP_DDUPD, OP_IOTA
 };
 
 struct Op {
@@ -325,9 +325,16 @@ void build_precondition(Program &P, rtproj_batch b, const double *const *A, cons
     // 2b. pivoted QR of R0, one workgroup per member
     P.stage = 1;
     {
-        std::vector<rt::MatGroupArgs> z(cnt);
-        for (int64_t i = 0; i < cnt; ++i) z[i] = rt::MatGroupArgs{Rm[i], mm[i], (int)mm[i], (int)mm[i], 0.0, nullptr, nullptr};
+        std::vector<rt::MatGroupArgs> z(cnt), pv(cnt);
+        for (int64_t i = 0; i < cnt; ++i) {
+            z[i] = rt::MatGroupArgs{Rm[i], mm[i], (int)mm[i], (int)mm[i], 0.0, nullptr, nullptr};
+            pv[i] = rt::MatGroupArgs{nullptr, 0, (int)mm[i], 0, 0.0, b->sub[i]->d_piv, nullptr};
+        }
         rec_mat(P, OP_SET0, z);
+        // valid pivots even if a member's QR stops early on non-finite data
+        Op io{OP_IOTA, P.add(pv), (int)cnt};
+        io.i0 = (int)b->max_m;
+        P.push(io);
         std::vector<rt::QrcpWgArgs> q(cnt);
         for (int64_t i = 0; i < cnt; ++i) {
             rtproj_plan p = b->sub[i];
@@ -557,6 +564,7 @@ hipError_t run_op(const Op &o, const unsigned char *arena, hipStream_t s)
     case OP_ABRED: return rt::ab_reduce_grouped_f64((const rt::AbGroupArgs *)d, o.count, o.total, o.dd, s);
     case OP_ATX: return rt::atx_grouped_f64((const rt::AtxGroupArgs *)d, o.count, o.total, o.i1, o.dd, s);
     case OP_DDUPD: return rt::dd_update_grouped_f64((const rt::DdGroupArgs *)d, o.count, s);
+    case OP_IOTA: return rt::iota_grouped_i32((const rt::MatGroupArgs *)d, o.count, o.i0, s);
     }
     return hipErrorInvalidValue;
 }

@@ -158,6 +158,12 @@ hipError_t qrcp_f64(const double *S, int64_t lds, int rows, int cols, double *R,
 // *global_cols = 1 when the columns must live in global memory (w.cols).
 int qrcp_max_blocks(int rows, int cols, int cu_count, size_t lds_max, int *global_cols);
 hipError_t zero_u32(unsigned *p, int n, hipStream_t stream);
+// Register-resident cooperative form (512 threads per block; rows <= 8192).
+// Block count from qrcp_reg_shape; the workspace is that of qrcp_f64 with
+// G blocks (slots 4 G doubles, vbuf 2 G rows doubles).
+bool qrcp_reg_shape(int rows, int cols, int cu_count, int *nc, int *rpt, int *blocks);
+hipError_t qrcp_reg_f64(const double *S, int64_t lds, int rows, int cols, double *R, int32_t *piv,
+                        const QrcpWork &w, int cu_count, hipStream_t stream);
 
 // Column-pivoted QR of one matrix per workgroup (no grid synchronization):
 // M is column-major rows x cols (ld ldm) and is overwritten; R (cols x cols
@@ -192,6 +198,9 @@ hipError_t tri_diag_inv_grouped_f64(const TriInvGroupArgs *d, int count, int max
 struct MatGroupArgs { double *X; int64_t ld; int m, n; double c; const int32_t *piv; double *out; };
 // X = 0 (ident = 0) or I (ident = 1), m x n
 hipError_t set_matrix_grouped_f64(const MatGroupArgs *d, int count, int64_t max_total, int ident, hipStream_t stream);
+// piv[i] = i, i < m (the pivot vector given as MatGroupArgs::piv)
+hipError_t iota_grouped_i32(const MatGroupArgs *d, int count, int max_m, hipStream_t stream);
+hipError_t iota_f64piv(int32_t *piv, int m, hipStream_t stream);
 // X[i][i] += c * trace(X), m x m
 hipError_t shift_diag_grouped_f64(const MatGroupArgs *d, int count, hipStream_t stream);
 // out[0..3] as rdiag_ends_f64 for the m x m X

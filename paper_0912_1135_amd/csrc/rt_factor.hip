@@ -196,6 +196,21 @@ __device__ __forceinline__ void shift_diag_body(double *G, int64_t ld, int m, do
 
 __global__ void shift_diag_kernel(double *G, int64_t ld, int m, double c) { shift_diag_body(G, ld, m, c); }
 
+// piv[i] = i: the pivot vector is valid (in range) even when a pivoted QR
+// stops early on non-finite input, so later gathers through it stay in bounds.
+__global__ void iota_grouped(const MatGroupArgs *gs)
+{
+    const MatGroupArgs g = gs[blockIdx.y];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < g.m) const_cast<int32_t *>(g.piv)[i] = i;
+}
+
+__global__ void iota_kernel(int32_t *piv, int m)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) piv[i] = i;
+}
+
 __global__ void shift_diag_grouped(const MatGroupArgs *gs)
 {
     const MatGroupArgs g = gs[blockIdx.x];
@@ -362,6 +377,20 @@ hipError_t set_matrix_grouped_f64(const MatGroupArgs *d, int count, int64_t max_
     if (count <= 0 || max_total <= 0) return hipSuccess;
     hipLaunchKernelGGL(set_matrix_grouped, dim3((unsigned)((max_total + 255) / 256), count), dim3(256), 0, stream, d,
                        ident);
+    return hipGetLastError();
+}
+
+hipError_t iota_f64piv(int32_t *piv, int m, hipStream_t stream)
+{
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(iota_kernel, dim3((m + 255) / 256), dim3(256), 0, stream, piv, m);
+    return hipGetLastError();
+}
+
+hipError_t iota_grouped_i32(const MatGroupArgs *d, int count, int max_m, hipStream_t stream)
+{
+    if (count <= 0 || max_m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(iota_grouped, dim3((max_m + 255) / 256, count), dim3(256), 0, stream, d);
     return hipGetLastError();
 }
 

@@ -178,12 +178,18 @@ rtproj_status alloc_state(rtproj_plan p)
     int gcols = 0, gcols0 = 0;
     p->qr_blocks = rt::qrcp_max_blocks((int)l, (int)m, p->cu_count, p->lds_max, &gcols);
     p->qr_blocks0 = rt::qrcp_max_blocks((int)m, (int)m, p->cu_count, p->lds_max, &gcols0);
-    if (p->qr_blocks <= 0 && p->qr_blocks0 <= 0)
+    if (p->qr_blocks <= 0 && p->qr_blocks0 <= 0 && m > rt::qrcp_wg_max_cols())
         return fail(RTPROJ_ERR_UNSUPPORTED, "pivoted QR: more than 16 columns per compute unit, or l too large, "
                                             "for this (m, l)");
-    const int64_t gmax = std::max(p->qr_blocks, p->qr_blocks0);
+    // register-resident form where the shapes allow it (rows <= 8192)
+    int nc_, rpt_;
+    if (!rt::qrcp_reg_shape((int)l, (int)m, p->cu_count, &nc_, &rpt_, &p->qr_reg_l)) p->qr_reg_l = 0;
+    if (!rt::qrcp_reg_shape((int)m, (int)m, p->cu_count, &nc_, &rpt_, &p->qr_reg_m)) p->qr_reg_m = 0;
+    const int64_t gmax = std::max({(int64_t)p->qr_blocks, (int64_t)p->qr_blocks0, (int64_t)p->qr_reg_l,
+                                   (int64_t)p->qr_reg_m});
     RT_HIP(dalloc(&p->d_slots, (size_t)4 * gmax));
-    RT_HIP(dalloc(&p->d_vbuf, (size_t)2 * std::max<int64_t>(p->qr_blocks * l, p->qr_blocks0 * m)));
+    RT_HIP(dalloc(&p->d_vbuf, (size_t)2 * std::max({(int64_t)p->qr_blocks * l, (int64_t)p->qr_blocks0 * m,
+                                                     (int64_t)p->qr_reg_l * l, (int64_t)p->qr_reg_m * m})));
     if (gcols || gcols0)
         RT_HIP(dalloc(&p->d_qrcols, (size_t)16 * std::max<int64_t>(gcols ? p->qr_blocks * l : 0,
                                                                      gcols0 ? p->qr_blocks0 * m : 0)));
@@ -549,9 +555,9 @@ rtproj_status rtproj_plan_set_qr(rtproj_plan p, int mode)
 {
     if (!p) return fail(RTPROJ_ERR_INVALID_ARG, "null plan");
     if (mode < RTPROJ_QR_AUTO || mode > RTPROJ_QR_TWO_STAGE_WG) return fail(RTPROJ_ERR_INVALID_ARG, "unknown QR mode");
-    if (mode == RTPROJ_QR_DIRECT && p->qr_blocks <= 0)
+    if (mode == RTPROJ_QR_DIRECT && p->qr_blocks <= 0 && p->qr_reg_l <= 0)
         return fail(RTPROJ_ERR_UNSUPPORTED, "direct pivoted QR: the l x m sketch does not fit the cooperative kernel");
-    if (mode == RTPROJ_QR_TWO_STAGE && p->qr_blocks0 <= 0)
+    if (mode == RTPROJ_QR_TWO_STAGE && p->qr_blocks0 <= 0 && p->qr_reg_m <= 0)
         return fail(RTPROJ_ERR_UNSUPPORTED, "two-stage pivoted QR: R0 does not fit the cooperative kernel");
     if (mode == RTPROJ_QR_TWO_STAGE_WG && (p->m > rt::qrcp_wg_max_rows() || p->m > rt::qrcp_wg_max_cols()))
         return fail(RTPROJ_ERR_UNSUPPORTED, "single-workgroup pivoted QR: m too large");
@@ -573,10 +579,29 @@ rtproj_status rtproj_plan_set_refinement(rtproj_plan p, int max_steps, double rt
 
 namespace {
 
+// Cooperative pivoted QR of the rows x m matrix whose columns are the rows
+// of M (ld ldm): the register-resident form when it applies (reg_blocks >
+// 0), else the LDS / global-memory form with lds_blocks blocks.
+hipError_t qrcp_any(rtproj_plan p, const double *M, int64_t ldm, int rows, rt::QrcpWork w, int reg_blocks,
+                    int lds_blocks)
+{
+    const int m = (int)p->m;
+    if (reg_blocks > 0) {
+        w.cols = nullptr;
+        p->info.qrcp_blocks = reg_blocks;
+        return rt::qrcp_reg_f64(M, ldm, rows, m, p->d_R, p->d_piv, w, p->cu_count, p->stream);
+    }
+    int gc = 0;
+    rt::qrcp_max_blocks(rows, m, p->cu_count, p->lds_max, &gc);
+    w.cols = gc ? p->d_qrcols : nullptr;
+    p->info.qrcp_blocks = lds_blocks;
+    return rt::qrcp_f64(M, ldm, rows, m, p->d_R, p->d_piv, w, lds_blocks, p->lds_max, p->stream);
+}
+
 // The pivoted-QR method used when the caller leaves it to the plan.
 int auto_qr_mode(rtproj_plan p)
 {
-    if (p->qr_blocks <= 0) return RTPROJ_QR_TWO_STAGE;
+    if (p->qr_blocks <= 0 && p->qr_reg_l <= 0) return RTPROJ_QR_TWO_STAGE;
     return RTPROJ_QR_DIRECT;
 }
 
@@ -606,6 +631,7 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
             if (st0 != RTPROJ_OK) return st0;
         }
         RT_HIP(rt::set_matrix_f64(p->d_R, m, (int)m, (int)m, 0, s));
+        RT_HIP(rt::iota_f64piv(p->d_piv, (int)m, s));  // valid pivots even if the QR stops early
         rt::QrcpWork w;
         w.counter = p->d_sync;
         w.flag = p->d_sync + 1;
@@ -615,15 +641,9 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
         {
             StageScope sc(p, 1);
             if (mode == RTPROJ_QR_DIRECT) {
-                int gc = 0;
-                rt::qrcp_max_blocks((int)l, (int)m, p->cu_count, p->lds_max, &gc);
-                w.cols = gc ? p->d_qrcols : nullptr;
-                RT_HIP(rt::qrcp_f64(p->d_S, l, (int)l, (int)m, p->d_R, p->d_piv, w, p->qr_blocks, p->lds_max, s));
+                RT_HIP(qrcp_any(p, p->d_S, l, (int)l, w, p->qr_reg_l, p->qr_blocks));
             } else if (mode == RTPROJ_QR_TWO_STAGE) {
-                int gc = 0;
-                rt::qrcp_max_blocks((int)m, (int)m, p->cu_count, p->lds_max, &gc);
-                w.cols = gc ? p->d_qrcols : nullptr;
-                RT_HIP(rt::qrcp_f64(p->d_R0, m, (int)m, (int)m, p->d_R, p->d_piv, w, p->qr_blocks0, p->lds_max, s));
+                RT_HIP(qrcp_any(p, p->d_R0, m, (int)m, w, p->qr_reg_m, p->qr_blocks0));
             } else {
                 RT_HIP(rt::zero_u32(p->d_sync, 4, s));
                 RT_HIP(rt::qrcp_wg_f64(p->d_wgargs, 1, s));
@@ -638,15 +658,14 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
         if (r0err && mode != RTPROJ_QR_DIRECT) {
             // the Cholesky QR broke down (S^T too ill-conditioned even for the
             // shifted first pass): factor S^T directly
-            if (p->qr_blocks <= 0) return fail(RTPROJ_ERR_RANK, "two-stage pivoted QR: Cholesky QR of the sketch failed");
+            if (p->qr_blocks <= 0 && p->qr_reg_l <= 0)
+                return fail(RTPROJ_ERR_RANK, "two-stage pivoted QR: Cholesky QR of the sketch failed");
             mode = RTPROJ_QR_DIRECT;
             RT_HIP(rt::set_matrix_f64(p->d_R, m, (int)m, (int)m, 0, s));
-            int gc = 0;
-            rt::qrcp_max_blocks((int)l, (int)m, p->cu_count, p->lds_max, &gc);
-            w.cols = gc ? p->d_qrcols : nullptr;
+            RT_HIP(rt::iota_f64piv(p->d_piv, (int)m, s));
             {
                 StageScope sc(p, 1);
-                RT_HIP(rt::qrcp_f64(p->d_S, l, (int)l, (int)m, p->d_R, p->d_piv, w, p->qr_blocks, p->lds_max, s));
+                RT_HIP(qrcp_any(p, p->d_S, l, (int)l, w, p->qr_reg_l, p->qr_blocks));
             }
             RT_HIP(rt::rdiag_ends_f64(p->d_R, m, (int)m, p->d_diag, s));
             RT_HIP(hipMemcpyAsync(diag, p->d_diag, 32, hipMemcpyDeviceToHost, s));

@@ -138,6 +138,7 @@ struct rtproj_plan_s {
     float *d_rowscale = nullptr;
     int qr_blocks = 0;         // cooperative blocks for the l x m QRCP (direct mode)
     int qr_blocks0 = 0;        // cooperative blocks for the m x m QRCP of R0
+    int qr_reg_l = 0, qr_reg_m = 0;  // blocks of the register-resident form (0: not applicable)
     int qr_mode = RTPROJ_QR_AUTO;
     double *d_Yq = nullptr;    // two-stage: the m x l iterate of the Cholesky QR
     double *d_R0 = nullptr;    // two-stage: R0^T (lower, row-major m x m)

@@ -38,10 +38,10 @@ __device__ __forceinline__ unsigned bitrev(unsigned x, int bits)
 }
 
 // In-place radix-2 decimation-in-time FFT of `cols` columns of length `len`
-// stored column after column in LDS (input already in bit-reversed order).
-// tw: len/2 twiddles exp(-2 pi i j / len) in LDS.
+// stored column after column in LDS with column stride ld (input already in
+// bit-reversed order).  tw: len/2 twiddles exp(-2 pi i j / len) in LDS.
 template <typename R>
-__device__ void lds_fft_cols(cpx<R> *buf, int len, int cols, const cpx<R> *tw)
+__device__ void lds_fft_cols(cpx<R> *buf, int len, int ld, int cols, const cpx<R> *tw)
 {
     const int half = len >> 1;
     for (int h = 1; h < len; h <<= 1) {
@@ -50,7 +50,7 @@ __device__ void lds_fft_cols(cpx<R> *buf, int len, int cols, const cpx<R> *tw)
             const int c = e / half, q = e - c * half;
             const int grp = q / h, pos = q - grp * h;
             const int i0 = grp * 2 * h + pos, i1 = i0 + h;
-            cpx<R> *col = buf + (int64_t)c * len;
+            cpx<R> *col = buf + (int64_t)c * ld;
             const cpx<R> w = tw[pos * stride];
             const cpx<R> a = col[i0];
             const cpx<R> b = cmul(col[i1], w);
@@ -88,6 +88,27 @@ __host__ __device__ inline SketchGeom sketch_geom(const SketchTables &t)
     return g;
 }
 
+// Dynamic LDS of pass 1 (bytes), in this order: n1/2 twiddles of the
+// n1-point FFT, the tw_cols x n1 columns, the two-level twiddle tables of
+// the np-point product (np/tl and tl entries), sigma (n1) and the tw_cols
+// in-block indices.  Pass 2: n2/2 twiddles, cp x 2 x n2 columns, tau^{-1} (n2).
+template <typename R>
+__host__ __device__ inline size_t pass1_smem(int64_t n1, int64_t n2, int tw_cols)
+{
+    const int64_t np = n1 * n2;
+    const int tl_bits = (ilog2(np) + 1) / 2;
+    const int64_t c = (n1 >> 1) + (int64_t)tw_cols * (n1 + 1) + (np >> tl_bits) + (int64_t(1) << tl_bits);
+    return (size_t)(c * (int64_t)sizeof(cpx<R>) + (n1 + tw_cols) * 4);
+}
+
+template <typename R>
+__host__ __device__ inline size_t pass2_smem(int64_t n2, int cp)
+{
+    return (size_t)(((n2 >> 1) + (int64_t)cp * 2 * (n2 + 1)) * (int64_t)sizeof(cpx<R>) + n2 * 4);
+}
+
+constexpr int SK_U = 8;  // gathers in flight per thread
+
 template <typename R>
 __device__ __forceinline__ void sketch_pass1_body(const SketchTables &t, const double *A, int64_t lda, int64_t m,
                                                   int64_t row0, cpx<R> *zbuf, int tw_cols, int bits1, int bx,
@@ -97,39 +118,64 @@ __device__ __forceinline__ void sketch_pass1_body(const SketchTables &t, const d
     typedef cpx<R> cplx;
     cplx *smem = reinterpret_cast<cplx *>(smem_raw);
     const int n1 = (int)t.n1, n2 = (int)t.n2;
-    cplx *tw = smem;                 // n1/2
-    cplx *buf = smem + (n1 >> 1);    // tw_cols x n1
+    const int nh = (int)(t.np >> t.tl_bits), nl = 1 << t.tl_bits;
+    cplx *tw = smem;                           // n1/2
+    const int ld1 = n1 + 1;                    // padded column stride (no bank conflicts across columns)
+    cplx *buf = tw + (n1 >> 1);                // tw_cols x ld1
+    cplx *th = buf + (int64_t)tw_cols * ld1;   // np / tl
+    cplx *tlo = th + nh;                       // tl
+    int *s_sigma = reinterpret_cast<int *>(tlo + nl);
+    int *s_tinv = s_sigma + n1;
     const int64_t r0 = row0 + 2 * pair, r1 = r0 + 1;
     const int u0 = bx * tw_cols;
     if (u0 >= n2 || r0 >= m) return;  // whole block (grouped launches)
     const cplx *tw1 = reinterpret_cast<const cplx *>(sizeof(R) == 8 ? (const void *)t.tw1 : (const void *)t.tw1f);
+    const cplx *twh = reinterpret_cast<const cplx *>(sizeof(R) == 8 ? (const void *)t.twh : (const void *)t.twhf);
+    const cplx *twl = reinterpret_cast<const cplx *>(sizeof(R) == 8 ? (const void *)t.twl : (const void *)t.twlf);
+    // stage the small tables once, so no gather below waits on a table load
     for (int e = threadIdx.x; e < (n1 >> 1); e += blockDim.x) tw[e] = tw1[e];
+    for (int e = threadIdx.x; e < nh; e += blockDim.x) th[e] = twh[e];
+    for (int e = threadIdx.x; e < nl; e += blockDim.x) tlo[e] = twl[e];
+    for (int e = threadIdx.x; e < n1; e += blockDim.x) s_sigma[e] = t.sigma[e];
+    for (int e = threadIdx.x; e < tw_cols; e += blockDim.x) s_tinv[e] = t.tau_inv[u0 + e];
+    __syncthreads();
     const double *a0 = A + r0 * lda;
     const double *a1 = A + r1 * lda;
     const bool has1 = r1 < m;
-    for (int e = threadIdx.x; e < n1 * tw_cols; e += blockDim.x) {
-        const int t1 = e / tw_cols, j = e - t1 * tw_cols;
-        const int64_t src = (int64_t)t.sigma[t1] * n2 + u0 + j;
-        R re = 0, im = 0;
-        if (src < t.n) {
-            const double s = (double)t.sign[src];
-            re = (R)(s * a0[src]);
-            if (has1) im = (R)(s * a1[src]);
+    const int total = n1 * tw_cols;
+    // gathers: SK_U independent loads per thread in flight at a time; each
+    // run of tw_cols consecutive elements of a row is read contiguously
+    for (int base = threadIdx.x; base < total; base += SK_U * blockDim.x) {
+        double v0[SK_U], v1[SK_U], sg[SK_U];
+        int dst[SK_U];
+#pragma unroll
+        for (int q = 0; q < SK_U; ++q) {
+            const int e = base + q * blockDim.x;
+            v0[q] = 0.0; v1[q] = 0.0; sg[q] = 0.0; dst[q] = -1;
+            if (e < total) {
+                const int t1 = e / tw_cols, j = e - t1 * tw_cols;
+                const int64_t src = (int64_t)s_sigma[t1] * n2 + u0 + j;
+                dst[q] = j * ld1 + (int)bitrev((unsigned)t1, bits1);
+                if (src < t.n) {
+                    sg[q] = (double)t.sign[src];
+                    v0[q] = a0[src];
+                    if (has1) v1[q] = a1[src];
+                }
+            }
         }
-        buf[(int64_t)j * n1 + bitrev((unsigned)t1, bits1)] = cplx{re, im};
+#pragma unroll
+        for (int q = 0; q < SK_U; ++q)
+            if (dst[q] >= 0) buf[dst[q]] = cplx{(R)(sg[q] * v0[q]), (R)(sg[q] * v1[q])};
     }
     __syncthreads();
-    lds_fft_cols(buf, n1, tw_cols, tw);
-    const cplx *twh = reinterpret_cast<const cplx *>(sizeof(R) == 8 ? (const void *)t.twh : (const void *)t.twhf);
-    const cplx *twl = reinterpret_cast<const cplx *>(sizeof(R) == 8 ? (const void *)t.twl : (const void *)t.twlf);
-    const int tl_mask = (1 << t.tl_bits) - 1;
+    lds_fft_cols(buf, n1, ld1, tw_cols, tw);
+    const int tl_mask = nl - 1;
     cplx *zp = zbuf + pair * t.np;
-    for (int e = threadIdx.x; e < n1 * tw_cols; e += blockDim.x) {
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
         const int k1 = e / tw_cols, j = e - k1 * tw_cols;
-        const int t2 = t.tau_inv[u0 + j];
-        const int idx = t2 * k1;  // < np, no reduction needed
-        const cplx w = cmul(twh[idx >> t.tl_bits], twl[idx & tl_mask]);
-        zp[(int64_t)k1 * n2 + u0 + j] = cmul(buf[(int64_t)j * n1 + k1], w);
+        const int idx = s_tinv[j] * k1;  // < np, no reduction needed
+        const cplx w = cmul(th[idx >> t.tl_bits], tlo[idx & tl_mask]);
+        zp[(int64_t)k1 * n2 + u0 + j] = cmul(buf[(int64_t)j * ld1 + k1], w);
     }
 }
 
@@ -150,26 +196,44 @@ __device__ __forceinline__ void sketch_pass2_body(const SketchTables &t, int64_t
     cplx *smem = reinterpret_cast<cplx *>(smem_raw);
     const int n1 = (int)t.n1, n2 = (int)t.n2;
     cplx *tw = smem;               // n2/2
-    cplx *buf = smem + (n2 >> 1);  // cp x 2 x n2
+    const int ld2 = n2 + 1;        // padded column stride
+    cplx *buf = smem + (n2 >> 1);  // cp x 2 x ld2
     // w: k1-pair index, ka = w, kb = (n1 - w) % n1
     const int ka = w, kb = (n1 - w) % n1;
     const int ncol = (ka == kb) ? 1 : 2;
     const int64_t p0 = by * cp;
     if (w > n1 / 2 || p0 >= npairs) return;  // whole block (grouped launches)
     const int pc = (int)min<int64_t>(cp, npairs - p0);
+    int *s_tinv = reinterpret_cast<int *>(buf + (int64_t)cp * 2 * ld2);
     const cplx *tw2 = reinterpret_cast<const cplx *>(sizeof(R) == 8 ? (const void *)t.tw2 : (const void *)t.tw2f);
     for (int e = threadIdx.x; e < (n2 >> 1); e += blockDim.x) tw[e] = tw2[e];
-    for (int e = threadIdx.x; e < pc * ncol * n2; e += blockDim.x) {
-        const int c = e / n2, u = e - c * n2;
-        const int p = c / ncol, col = c - p * ncol;
-        const int k1 = col == 0 ? ka : kb;
-        const int t2 = t.tau_inv[u];
-        buf[(int64_t)(p * 2 + col) * n2 + bitrev((unsigned)t2, bits2)] = zbuf[(p0 + p) * t.np + (int64_t)k1 * n2 + u];
+    for (int e = threadIdx.x; e < n2; e += blockDim.x) s_tinv[e] = t.tau_inv[e];
+    __syncthreads();
+    const int total = pc * ncol * n2;
+    for (int base = threadIdx.x; base < total; base += SK_U * blockDim.x) {
+        cplx v[SK_U];
+        int dst[SK_U];
+#pragma unroll
+        for (int q = 0; q < SK_U; ++q) {
+            const int e = base + q * blockDim.x;
+            dst[q] = -1;
+            v[q] = cplx{0, 0};
+            if (e < total) {
+                const int c = e / n2, u = e - c * n2;
+                const int p = c / ncol, col = c - p * ncol;
+                const int k1 = col == 0 ? ka : kb;
+                dst[q] = (p * 2 + col) * ld2 + (int)bitrev((unsigned)s_tinv[u], bits2);
+                v[q] = zbuf[(p0 + p) * t.np + (int64_t)k1 * n2 + u];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < SK_U; ++q)
+            if (dst[q] >= 0) buf[dst[q]] = v[q];
     }
     __syncthreads();
     // FFT every loaded column; columns are laid out p*2 + col, so transform
     // 2*pc columns (an unused second column is harmless zero work when ncol = 1).
-    lds_fft_cols(buf, n2, pc * 2, tw);
+    lds_fft_cols(buf, n2, ld2, pc * 2, tw);
     const int beg = t.sel_off[w], cnt = t.sel_off[w + 1] - beg;
     const double sc1 = 1.0 / __builtin_sqrt((double)t.l);
     const double sc2 = __builtin_sqrt(2.0) * sc1;
@@ -182,8 +246,8 @@ __device__ __forceinline__ void sketch_pass2_body(const SketchTables &t, int64_t
         const int k1 = (int)(k % n1), k2 = (int)(k / n1);
         const int64_t kp = (t.np - k) % t.np;
         const int kp1 = (int)(kp % n1), kp2 = (int)(kp / n1);
-        const cplx y = buf[(int64_t)(p * 2 + (k1 == ka ? 0 : 1)) * n2 + k2];
-        const cplx yp = buf[(int64_t)(p * 2 + (kp1 == ka ? 0 : 1)) * n2 + kp2];
+        const cplx y = buf[(int64_t)(p * 2 + (k1 == ka ? 0 : 1)) * ld2 + k2];
+        const cplx yp = buf[(int64_t)(p * 2 + (kp1 == ka ? 0 : 1)) * ld2 + kp2];
         // spectra of the two real rows: Ya = (Y_k + conj Y_{np-k})/2,
         // Yb = (Y_k - conj Y_{np-k})/(2i)
         const double ar = 0.5 * ((double)y.re + (double)yp.re), ai = 0.5 * ((double)y.im - (double)yp.im);
@@ -237,8 +301,9 @@ hipError_t sketch_run(const SketchTables &t, const double *A, int64_t lda, int64
     const SketchGeom geo = sketch_geom<R>(t);
     const int bits1 = geo.bits1, bits2 = geo.bits2, tw_cols = geo.tw_cols, cp = geo.cp;
     const int64_t csz = sizeof(cplx);
-    const size_t sm1 = (size_t)((n1 >> 1) + (int64_t)tw_cols * n1) * csz;
-    const size_t sm2 = (size_t)((n2 >> 1) + (int64_t)cp * 2 * n2) * csz;
+    (void)csz;
+    const size_t sm1 = pass1_smem<R>(n1, n2, tw_cols);
+    const size_t sm2 = pass2_smem<R>(n2, cp);
     cplx *z = reinterpret_cast<cplx *>(zbuf);
     hipError_t ea = hipFuncSetAttribute((const void *)sketch_pass1<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm1);
     if (ea != hipSuccess) return ea;
@@ -275,8 +340,8 @@ hipError_t sketch_grouped_run(const SketchGroupArgs *d, int count, const SketchG
             SketchTables tt{};
             tt.n1 = n1; tt.n2 = n2;
             const SketchGeom g = sketch_geom<R>(tt);
-            sm1 = std::max(sm1, (size_t)((n1 >> 1) + (int64_t)g.tw_cols * n1) * csz);
-            sm2 = std::max(sm2, (size_t)((n2 >> 1) + (int64_t)g.cp * 2 * n2) * csz);
+            sm1 = std::max(sm1, pass1_smem<R>(n1, n2, g.tw_cols));
+            sm2 = std::max(sm2, pass2_smem<R>(n2, g.cp));
             gx1 = std::max(gx1, (int)(n2 / g.tw_cols));
             gx2 = std::max(gx2, (int)(n1 / 2 + 1));
         }
