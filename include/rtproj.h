@@ -148,8 +148,11 @@ rtproj_status rtproj_plan_set_qr(rtproj_plan plan, int mode);
  * to-host read per step); rtol = 0 runs exactly max_steps steps without any
  * host synchronisation.  max_steps = 0 returns the unrefined projection
  * (the seven steps of Sec. 4 in binary64); max_steps = -1 (the default)
- * chooses the count from the rank estimate of the pivoted QR: with
- * rho = 16 u kappa_est the fewest steps s >= 1 with rho^(s+1) <= 1e-14.
+ * chooses the schedule from the rank estimate of the pivoted QR: with
+ * contraction rho ~ 16 u_W kappa_est + (the Gram's rounding), steps whose
+ * residuals are plain binary64 while the error is above their floor
+ * 16 u kappa_est, then compensated steps until rho^s times the error is
+ * <= 1e-14.  An explicit max_steps runs compensated steps only.
  */
 rtproj_status rtproj_plan_set_refinement(rtproj_plan plan, int max_steps, double rtol);
 

@@ -357,7 +357,13 @@ bool ld_ok(int64_t ld, int64_t need) { return ld >= need && ld > 0; }
 // max|R_ii| / min|R_ii| from the pivoted QR and a safety factor c = 16, take
 // the fewest steps s >= 1 with rho^(s+1) <= 1e-14 (binary64 accuracy of x
 // with margin), at most 12.
-int auto_refine_steps(double kappa_est, int precision, bool w32, double cond_w)
+// Refinement schedule when none was requested.  The contraction of a step
+// is rho ~ 16 u_W kappa + (the Gram's rounding); a residual evaluated in
+// plain binary64 stalls at the floor ~16 u kappa (relative error of x), so
+// plain steps are taken while the error is above that floor and compensated
+// (Dot2) steps after it, until rho^s * error <= 1e-14.  kappa is the rank
+// estimate of the pivoted QR; cond_w the Gram factor's diagonal ratio.
+void auto_refine_plan(double kappa_est, int precision, bool w32, double cond_w, int *plain, int *comp)
 {
     // W's error ~ u_W kappa; the Gram's own rounding adds ~16 u_G (binary32)
     // or a few units of 2^-8 (bfloat16 inputs, binary32 accumulation)
@@ -366,10 +372,25 @@ int auto_refine_steps(double kappa_est, int precision, bool w32, double cond_w)
     const double c2 = std::max(1.0, cond_w * cond_w / 9.0);  // relative to a healthy cond ~ 3
     if (precision == RTPROJ_PREC_MIXED_FP32) gram = 16.0 * std::ldexp(1.0, -23) * c2;
     if (precision == RTPROJ_PREC_MIXED_BF16) gram = 4e-3 * c2;
-    const double rho = std::min(0.5, 16.0 * uw * std::max(1.0, kappa_est) + gram);
-    int s = 1;
-    while (s < 12 && std::pow(rho, s + 1) > 1e-14) ++s;
-    return s;
+    const double k = std::max(1.0, kappa_est);
+    const double rho = std::min(0.5, 16.0 * uw * k + gram);
+    const double floor64 = std::min(0.5, 16.0 * std::ldexp(1.0, -52) * k);
+    // error after the first solve ~ rho; plain steps while above the floor
+    int np_ = 0;
+    double e = rho;
+    while (np_ < 12 && e * rho > floor64) { e *= rho; ++np_; }
+    e = std::max(e, floor64);
+    int nc = 1;
+    while (nc < 12 && e * std::pow(rho, nc) > 1e-14) ++nc;
+    *plain = np_;
+    *comp = nc;
+}
+
+int auto_refine_steps(double kappa_est, int precision, bool w32, double cond_w)
+{
+    int a, b;
+    auto_refine_plan(kappa_est, precision, w32, cond_w, &a, &b);
+    return a + b;
 }
 
 // H = T'^T (T' C) = (A A^T)^{-1} C for an m x k column-major block C: two
@@ -429,18 +450,22 @@ rtproj_status project(rtproj_plan p, const double *B, int64_t ldb, int64_t k, do
     }
     int steps = 0;
     double ratio = 0.0;
-    const int nsteps = p->refine_steps >= 0 ? p->refine_steps
-                                            : auto_refine_steps(p->info.kappa_est, p->precision, p->w32,
-                                                                p->info.gram_cond_est);
+    int nplain = 0, ncomp = p->refine_steps;
+    if (p->refine_steps < 0)
+        auto_refine_plan(p->info.kappa_est, p->precision, p->w32, p->info.gram_cond_est, &nplain, &ncomp);
+    const int nsteps = nplain + ncomp;
     for (int it = 0; it < nsteps; ++it) {
+        // plain binary64 residuals while the error is above their floor,
+        // compensated (Dot2) ones for the last steps
+        const int dd = it >= nplain ? 1 : 0;
         {
             StageScope sc(p, 9);
-            RT_HIP(rt::atx_f64(a, p->d_xhi, p->d_xlo, m, B, ldb, p->d_r, n, nullptr, 0, nullptr, 0, 1, s));
+            RT_HIP(rt::atx_f64(a, p->d_xhi, p->d_xlo, m, B, ldb, p->d_r, n, nullptr, 0, nullptr, 0, dd, s));
         }
         {
             StageScope sc(p, 10);
-            RT_HIP(rt::ab_partial_f64(a, p->d_r, n, p->ab_splits, p->d_ph, p->d_pl, 1, s));
-            RT_HIP(rt::ab_reduce_f64(p->d_ph, p->d_pl, (int)m, (int)k, p->ab_splits, 1, p->d_c, m, s));
+            RT_HIP(rt::ab_partial_f64(a, p->d_r, n, p->ab_splits, p->d_ph, p->d_pl, dd, s));
+            RT_HIP(rt::ab_reduce_f64(p->d_ph, p->d_pl, (int)m, (int)k, p->ab_splits, dd, p->d_c, m, s));
         }
         {
             StageScope sc(p, 8);
@@ -601,8 +626,12 @@ hipError_t qrcp_any(rtproj_plan p, const double *M, int64_t ldm, int rows, rt::Q
 // The pivoted-QR method used when the caller leaves it to the plan.
 int auto_qr_mode(rtproj_plan p)
 {
-    if (p->qr_blocks <= 0 && p->qr_reg_l <= 0) return RTPROJ_QR_TWO_STAGE;
-    return RTPROJ_QR_DIRECT;
+    // the register-resident form on S^T when it applies; otherwise (sketches
+    // taller than 8192 rows, or too many columns for one block per compute
+    // unit) on the m x m factor R0 of the two-stage form
+    if (p->qr_reg_l > 0) return RTPROJ_QR_DIRECT;
+    if (p->qr_reg_m > 0) return RTPROJ_QR_TWO_STAGE;
+    return p->qr_blocks > 0 ? RTPROJ_QR_DIRECT : RTPROJ_QR_TWO_STAGE;
 }
 
 // One pass of the preconditioner; sketch64 forces the binary64 sketch.

@@ -176,7 +176,9 @@ namespace rtp {
 
 // Grows the projection workspace of p to k right-hand sides.
 rtproj_status ensure_k(rtproj_plan p, int64_t k);
-// Refinement steps chosen from the rank estimate (see rtproj_plan_set_refinement).
+// Refinement steps chosen from the rank estimate (see rtproj_plan_set_refinement):
+// *plain steps with binary64 residuals, then *comp compensated ones.
+void auto_refine_plan(double kappa_est, int precision, bool w32, double cond_w, int *plain, int *comp);
 int auto_refine_steps(double kappa_est, int precision, bool w32, double cond_w);
 // First output of SplitMix64 seeded with seed XOR i: the sketch seed of
 // member i of a batch.
