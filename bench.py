@@ -15,6 +15,9 @@ Workloads (seeded synthetic inputs, A = U diag(sigma) V^T with Haar factors):
   batch_256                  256 members, m ~ U{32..512}, n = m U{16..64},
                              l = 4m, k ~ U{1..64}, sigma 1 -> 1e-6; grouped
                              launches in a HIP graph against a loop of plans
+  ipm_1024x131072            A (1024 x 131072, sigma 1 -> 1e-4) rescaled as
+                             A D_t for 32 steps, l=4096, k=128 per step, all
+                             steps batched against a step-by-step loop
 
 value = projections per second = (right-hand sides) / (seconds per step),
 inputs resident in HBM.  Prints one JSON line with the roofline of the
@@ -317,7 +320,6 @@ def run_batch(args, rt, synth, np, torch):
     ksum = int(sum(shp.k))
     dims = list(zip(shp.m, shp.n, shp.l, shp.k))
     bt = rt.Batch(shp.m, shp.n, shp.l, seed)
-    bt.set_refinement(2)
     # per-stage times from eager (ungraphed) steps
     bt.set_graph(False)
     bt.precondition(At)
@@ -373,7 +375,7 @@ def run_batch(args, rt, synth, np, torch):
                                f"k ~ U{{1..64}}, sigma log-spaced 1..1/{kappa:g}; grouped launches replayed from "
                                "a HIP graph", "members": count, "sum_k": ksum,
                    "sum_mn": int(sum(m * n for m, n in zip(shp.m, shp.n))), "precision": "fp64",
-                   "refine_steps": 2, "parallelism": "single GPU"},
+                   "refine_steps": binfo["refine_steps"], "parallelism": "single GPU"},
         "roofline": roofline(stages, args.workload),
         "stages": stages,
         "forms": {"batch_graph": {"value": value, "ms_per_step": ms_per_step},
@@ -409,13 +411,123 @@ def run_batch(args, rt, synth, np, torch):
     return result
 
 
+def run_ipm(args, rt, synth, np, torch):
+    """Interior-point-shaped sequence: a fixed A rescaled as A D_t for every
+    step t, preconditioner rebuilt and k right-hand sides projected per step,
+    all steps in one batch (grouped launches, HIP graph) against a loop over
+    the steps with one binary64 plan."""
+    c = synth.CONFIGS[args.workload]
+    m, n, l, k, steps, kappa, seed = c["m"], c["n"], c["l"], c["k"], c["steps"], c["kappa"], c["seed"]
+    log(f"generating {args.workload}: base {m} x {n}, {steps} scalings, {k} right-hand sides per step")
+    t0 = time.time()
+    A = synth.make_problem(m, n, kappa, seed)
+    D = synth.make_scalings(n, steps, seed)
+    dev = torch.device("cuda", 0)
+    At = torch.from_numpy(A).to(dev)
+    Dt = [torch.from_numpy(np.ascontiguousarray(D[t])).to(dev) for t in range(steps)]
+    Bt = [torch.from_numpy(synth.make_rhs(n, k, seed + 100 + t)).to(dev) for t in range(steps)]
+    gen_s = time.time() - t0
+    log(f"inputs ready in {gen_s:.1f} s")
+    Z = [torch.empty_like(b) for b in Bt]
+    Y = [torch.empty_like(b) for b in Bt]
+    X = [torch.empty((k, m), dtype=torch.float64, device=dev) for _ in range(steps)]
+    dims = [(m, n, l, k)] * steps
+    bt = rt.Batch([m] * steps, [n] * steps, [l] * steps, seed)
+    bt.set_graph(False)
+    bt.precondition([At] * steps, Dt)
+    bt.project_all(Bt, Z, Y, X)
+    torch.cuda.synchronize()
+    bt.set_timing(True)
+    bt.precondition([At] * steps, Dt)
+    bt.project_all(Bt, Z, Y, X)
+    torch.cuda.synchronize()
+    binfo = bt.info()
+    stages = stage_table(binfo, 1, dims, "fp64", 64)
+    bt.set_timing(False)
+    bt.set_graph(True)
+    for _ in range(args.warmup):
+        bt.precondition([At] * steps, Dt)
+        bt.project_all(Bt, Z, Y, X)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        bt.precondition([At] * steps, Dt)
+        bt.project_all(Bt, Z, Y, X)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    status = bt.status()
+    ms_per_step = (t2 - t1) * 1e3 / args.steps
+    value = steps * k / (ms_per_step / 1e3)
+    log(f"batch of {steps} steps (graph): {ms_per_step:.1f} ms")
+    # the sequential loop: one plan, A D_t formed on the device, step by step
+    plan = rt.Plan(m, n, l, seed)
+    Ad = torch.empty_like(At)
+    Zl = torch.empty_like(Bt[0])
+    torch.mul(At, Dt[0][None, :], out=Ad)
+    plan.precondition(Ad)
+    plan.project_all(Bt[0], Zl, None, None, want=(True, False, False))
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    for t in range(steps):
+        torch.mul(At, Dt[t][None, :], out=Ad)
+        plan.precondition(Ad)
+        plan.project_all(Bt[t], Zl, None, None, want=(True, False, False))
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    plan.close()
+    loop_value = steps * k / (t4 - t3)
+    log(f"loop of steps: {(t4 - t3) * 1e3:.1f} ms")
+    result = {
+        "metric": METRIC, "value": value, "unit": "projections/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: base A = U diag(sigma) V^T, m={m}, n={n}, sigma log-spaced "
+                               f"1..1/{kappa:g}, rescaled A D_t for {steps} steps with D_t = diag(10^U(-6,6)); "
+                               f"l={l}, k={k} right-hand sides per step; all steps batched, HIP graph",
+                   "m": m, "n": n, "l": l, "k": k, "ipm_steps": steps, "precision": "fp64",
+                   "refine_steps": binfo["refine_steps"],
+                   "parallelism": "single GPU"},
+        "roofline": roofline(stages, args.workload),
+        "stages": stages,
+        "forms": {"batch_graph": {"value": value, "ms_per_step": ms_per_step},
+                  "loop_of_steps": {"value": loop_value, "ms_per_step": (t4 - t3) * 1e3}},
+        "member_status_nonzero": [i for i, s_ in enumerate(status) if s_ != 0],
+    }
+    cpu_sample = None
+    if not (args.no_parity and args.no_cpu_baseline):
+        import oracle
+        threads = oracle.num_threads()
+        worst = [0.0, 0.0, 0.0]
+        t5 = time.perf_counter()
+        pick = [0, steps - 1]
+        for t in pick:
+            log(f"oracle on step {t}")
+            As = A * D[t][None, :]
+            Bs = Bt[t][:2].cpu().numpy()
+            Zr, Yr, Xr, _ = oracle.project(As, Bs.T)
+            e = rel_errors(Bs, Z[t][:2].cpu().numpy(), Y[t][:2].cpu().numpy(), X[t][:2].cpu().numpy(),
+                           Zr.T, Yr.T, Xr.T)
+            worst = [max(a, b) for a, b in zip(worst, e)]
+        t6 = time.perf_counter()
+        result["parity"] = {"steps_checked": pick, "columns_per_step": 2, "e_z": worst[0], "e_p": worst[1],
+                            "e_x": worst[2], "tol": TOL, "pass": max(worst) <= TOL}
+        if not args.no_cpu_baseline:
+            cpu_sample = {"value": 2 * len(pick) / (t6 - t5), "unit": "projections/s", "cores": threads,
+                          "kind": "oracle", "sample": f"2 right-hand sides of steps {pick} ({t6 - t5:.1f} s)"}
+    result["cpu_baseline"] = cpu_sample
+    result["input_generation_s"] = gen_s
+    bt.close()
+    return result
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="plain_512x65536",
-                    choices=["plain_512x65536", "plain_64x4096", "mixed_2048x262144", "batch_256"])
+                    choices=["plain_512x65536", "plain_64x4096", "mixed_2048x262144", "batch_256",
+                             "ipm_1024x131072"])
     ap.add_argument("--precision", default=None, choices=list(PRECISIONS),
                     help="form of the main line (default: fp64, or mixed_fp32 for the mixed workload)")
     ap.add_argument("--no-forms", action="store_true", help="time only the main precision")
@@ -443,6 +555,8 @@ def main():
 
     if args.workload == "batch_256":
         result = run_batch(args, rt, synth, np, torch)
+    elif args.workload == "ipm_1024x131072":
+        result = run_ipm(args, rt, synth, np, torch)
     else:
         result = run_single(args, rt, synth, np, torch)
     print(json.dumps(result))

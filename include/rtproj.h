@@ -243,12 +243,23 @@ rtproj_status rtproj_batch_create(int64_t count, const int64_t *m, const int64_t
                                   rtproj_batch *out);
 rtproj_status rtproj_batch_destroy(rtproj_batch batch);
 rtproj_status rtproj_batch_set_stream(rtproj_batch batch, void *hip_stream);
-/* Refinement steps (0..64, default 2) applied to every member: x <- x +
- * M^{-1} A (b - A^T x) with compensated residuals (Remark 4.3). */
+/* Refinement of every member (Remark 4.3): steps >= 0 compensated steps
+ * x <- x + M^{-1} A (b - A^T x); -1 (the default) the schedule of
+ * rtproj_plan_set_refinement for the least favourable member's rank
+ * estimate (plain binary64 residuals above their floor, compensated after),
+ * which reads the estimates once per projection call (a short host wait). */
 rtproj_status rtproj_batch_set_refinement(rtproj_batch batch, int steps);
 /* 1: capture each entry point's launches into a HIP graph and replay it. */
 rtproj_status rtproj_batch_set_graph(rtproj_batch batch, int enable);
 rtproj_status rtproj_batch_precondition(rtproj_batch batch, const double *const *A, const int64_t *lda);
+/* As rtproj_batch_precondition for the column-scaled matrices A[i] diag(d[i])
+ * (an interior-point step rescales a fixed A by a positive diagonal):
+ * col_scale[i] points to n[i] doubles on the device, or is NULL for an
+ * unscaled member.  Scaled members are copied once per call into a buffer the
+ * batch owns (m[i] n[i] doubles), which the projections then use; A[i] and
+ * col_scale[i] need not outlive the call. */
+rtproj_status rtproj_batch_precondition_scaled(rtproj_batch batch, const double *const *A, const int64_t *lda,
+                                              const double *const *col_scale);
 /* As rtproj_project_all per member; Z, Y, X (or their entries) may be NULL;
  * k[i] = 0 skips member i. */
 rtproj_status rtproj_batch_project_all(rtproj_batch batch, const double *const *B, const int64_t *ldb,

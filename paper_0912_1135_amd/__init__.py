@@ -76,6 +76,7 @@ def lib():
         L.rtproj_batch_set_refinement.argtypes = [vp, ip]
         L.rtproj_batch_set_graph.argtypes = [vp, ip]
         L.rtproj_batch_precondition.argtypes = [vp, vp, vp]
+        L.rtproj_batch_precondition_scaled.argtypes = [vp, vp, vp, vp]
         L.rtproj_batch_project_all.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.rtproj_batch_status.argtypes = [vp, vp]
         L.rtproj_batch_member_info.argtypes = [vp, i64, ctypes.POINTER(_Info)]
@@ -91,7 +92,8 @@ def lib():
                      "rtproj_plan_set_timing", "rtproj_batch_create", "rtproj_batch_destroy",
                      "rtproj_batch_set_stream", "rtproj_batch_set_refinement", "rtproj_batch_set_graph",
                      "rtproj_batch_precondition", "rtproj_batch_project_all", "rtproj_batch_status",
-                     "rtproj_batch_member_info", "rtproj_batch_set_timing", "rtproj_batch_info"]:
+                     "rtproj_batch_member_info", "rtproj_batch_set_timing", "rtproj_batch_info",
+                     "rtproj_batch_precondition_scaled"]:
             getattr(L, name).restype = ip
         _lib = L
     return _lib
@@ -282,11 +284,23 @@ class Batch:
     def set_graph(self, enable: bool):
         _check(lib().rtproj_batch_set_graph(self.handle, 1 if enable else 0))
 
-    def precondition(self, As):
+    def precondition(self, As, col_scales=None):
+        """As[i]: (m_i, n_i) float64 CUDA tensors; col_scales[i] (optional):
+        (n_i,) float64 CUDA tensors, member i then works on A[i] diag(d[i])."""
         assert len(As) == self.count
         for i, A in enumerate(As):
             _check_tensor(A, f"A[{i}]", self.ms[i], self.ns[i])
-        _check(lib().rtproj_batch_precondition(self.handle, _ptrs(As), _i64s([A.stride(0) for A in As])))
+        if col_scales is None:
+            _check(lib().rtproj_batch_precondition(self.handle, _ptrs(As), _i64s([A.stride(0) for A in As])))
+        else:
+            import torch
+            assert len(col_scales) == self.count
+            for i, d in enumerate(col_scales):
+                if d is not None and (not isinstance(d, torch.Tensor) or d.dtype != torch.float64 or not d.is_cuda
+                                      or d.dim() != 1 or d.shape[0] != self.ns[i] or d.stride(0) != 1):
+                    raise ValueError(f"col_scales[{i}] must be a contiguous float64 CUDA vector of length n")
+            _check(lib().rtproj_batch_precondition_scaled(self.handle, _ptrs(As), _i64s([A.stride(0) for A in As]),
+                                                          _ptrs(col_scales)))
         self._A = list(As)  # borrowed
 
     def project_all(self, Bs, Zs=None, Ys=None, Xs=None):

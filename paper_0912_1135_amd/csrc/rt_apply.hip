@@ -20,25 +20,27 @@ namespace {
 
 constexpr int AB_RB = 32;   // rows of A per block
 constexpr int AB_TC = 64;   // columns of A per LDS stage
-constexpr int AB_KJ = 16;   // right-hand sides per block
 
 // part[s][j][row] = sum_{t in split s} A[row][t] * B[t][j] (column-major m x k
 // per split).  dd: Dot2 accumulation, hi in part_hi and error in part_lo.
-template <bool DD>
+template <bool DD, int KJ>
 __device__ __forceinline__ void ab_partial_body(const ApplyArgs &a, const double *B, int64_t ldb, int splits,
                                                 double *part_hi, double *part_lo, int bx, int split, int bz)
 {
+    constexpr int NO = AB_RB * KJ / 256;  // outputs per thread
     __shared__ double As[AB_RB][AB_TC + 1];
-    __shared__ double Bs[AB_TC][AB_KJ];
+    __shared__ double Bs[AB_TC][KJ];
     const int r0 = bx * AB_RB;
-    const int j0 = bz * AB_KJ;
+    const int j0 = bz * KJ;
     if (r0 >= a.m || split >= splits || j0 >= a.k) return;  // whole block (grouped launches)
     const int64_t len = ((int64_t)a.n + splits - 1) / splits;
     const int64_t t0 = (int64_t)split * len;
     const int64_t t1 = min<int64_t>(a.n, t0 + len);
     const int tid = threadIdx.x;
-    // two outputs per thread: (row, j) = (o / 16, o % 16), o = tid, tid + 256
-    double s[2] = {0.0, 0.0}, c[2] = {0.0, 0.0};
+    // NO outputs per thread: (row, j) = (o / KJ, o % KJ), o = tid + 256 q
+    double s[NO], c[NO];
+#pragma unroll
+    for (int q = 0; q < NO; ++q) { s[q] = 0.0; c[q] = 0.0; }
     for (int64_t tb = t0; tb < t1; tb += AB_TC) {
         for (int e = tid; e < AB_RB * AB_TC; e += 256) {
             const int rr = e / AB_TC, tt = e % AB_TC;
@@ -46,7 +48,7 @@ __device__ __forceinline__ void ab_partial_body(const ApplyArgs &a, const double
             const int row = r0 + rr;
             As[rr][tt] = (row < a.m && t < t1) ? a.A[(int64_t)row * a.lda + t] : 0.0;
         }
-        for (int e = tid; e < AB_TC * AB_KJ; e += 256) {
+        for (int e = tid; e < AB_TC * KJ; e += 256) {
             const int jj = e / AB_TC, tt = e % AB_TC;
             const int64_t t = tb + tt;
             const int j = j0 + jj;
@@ -54,9 +56,9 @@ __device__ __forceinline__ void ab_partial_body(const ApplyArgs &a, const double
         }
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
+        for (int q = 0; q < NO; ++q) {
             const int o = tid + 256 * q;
-            const int rr = o >> 4, jj = o & 15;
+            const int rr = o / KJ, jj = o % KJ;
             double sq = s[q], cq = c[q];
 #pragma unroll 8
             for (int tt = 0; tt < AB_TC; ++tt) {
@@ -69,9 +71,9 @@ __device__ __forceinline__ void ab_partial_body(const ApplyArgs &a, const double
         __syncthreads();
     }
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < NO; ++q) {
         const int o = tid + 256 * q;
-        const int row = r0 + (o >> 4), j = j0 + (o & 15);
+        const int row = r0 + o / KJ, j = j0 + o % KJ;
         if (row < a.m && j < a.k) {
             const int64_t idx = (int64_t)split * a.m * a.k + (int64_t)j * a.m + row;
             part_hi[idx] = s[q];
@@ -80,20 +82,24 @@ __device__ __forceinline__ void ab_partial_body(const ApplyArgs &a, const double
     }
 }
 
-template <bool DD>
+template <bool DD, int KJ>
 __global__ __launch_bounds__(256) void ab_partial_kernel(ApplyArgs a, const double *B, int64_t ldb, int splits,
                                                          double *part_hi, double *part_lo)
 {
-    ab_partial_body<DD>(a, B, ldb, splits, part_hi, part_lo, blockIdx.x, blockIdx.y, blockIdx.z);
+    ab_partial_body<DD, KJ>(a, B, ldb, splits, part_hi, part_lo, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // grouped: blockIdx.z = member * kbmax + right-hand-side block
-template <bool DD>
+template <bool DD, int KJ>
 __global__ __launch_bounds__(256) void ab_partial_grouped(const AbGroupArgs *gs, int kbmax)
 {
     const AbGroupArgs g = gs[blockIdx.z / kbmax];
-    ab_partial_body<DD>(g.a, g.B, g.ldb, g.splits, g.ph, g.pl, blockIdx.x, blockIdx.y, blockIdx.z % kbmax);
+    ab_partial_body<DD, KJ>(g.a, g.B, g.ldb, g.splits, g.ph, g.pl, blockIdx.x, blockIdx.y, blockIdx.z % kbmax);
 }
+
+// right-hand sides per block of the A B pass: every block reads its panel of
+// A once for KJ columns of B (compensated accumulators need twice the registers)
+inline int ab_kj(int k, int dd) { return k > 32 && !dd ? 64 : (k > 16 ? 32 : 16); }
 
 __device__ __forceinline__ void ab_reduce_body(const double *ph, const double *pl, int m, int k, int splits, int dd,
                                                double *out, int64_t ldo, int64_t e)
@@ -133,28 +139,28 @@ constexpr int ATX_MC = 64;  // rows of x staged in LDS at a time
 // y(t, j) = sum_i A[i][t] (xhi[i][j] + xlo[i][j]); then
 //   mode 0: R = round(B - y)
 //   mode 1: Y = round(y), Z = round(B - y)
-template <bool DD>
+template <bool DD, int KJ>
 __device__ __forceinline__ void atx_body(const ApplyArgs &a, const double *xhi, const double *xlo, int64_t ldx,
                                          const double *B, int64_t ldb, double *Rout, int64_t ldr, double *Y,
                                          int64_t ldy, double *Z, int64_t ldz, int bx, int by)
 {
-    __shared__ double xh[ATX_MC][AB_KJ];
-    __shared__ double xl[ATX_MC][AB_KJ];
+    __shared__ double xh[ATX_MC][KJ];
+    __shared__ double xl[DD ? ATX_MC : 1][KJ];
     const int64_t t = (int64_t)bx * ATX_T + threadIdx.x;
-    const int j0 = by * AB_KJ;
+    const int j0 = by * KJ;
     if ((int64_t)bx * ATX_T >= a.n || j0 >= a.k) return;  // whole block (grouped launches)
-    const int kj = min(AB_KJ, a.k - j0);
-    double s[AB_KJ], c[AB_KJ];
+    const int kj = min(KJ, a.k - j0);
+    double s[KJ], c[KJ];
 #pragma unroll
-    for (int j = 0; j < AB_KJ; ++j) { s[j] = 0.0; c[j] = 0.0; }
+    for (int j = 0; j < KJ; ++j) { s[j] = 0.0; c[j] = 0.0; }
     const bool active = t < a.n;
     for (int i0 = 0; i0 < a.m; i0 += ATX_MC) {
         const int mc = min(ATX_MC, a.m - i0);
-        for (int e = threadIdx.x; e < ATX_MC * AB_KJ; e += ATX_T) {
-            const int ii = e / AB_KJ, jj = e % AB_KJ;
+        for (int e = threadIdx.x; e < ATX_MC * KJ; e += ATX_T) {
+            const int ii = e / KJ, jj = e % KJ;
             const bool ok = ii < mc && jj < kj;
             xh[ii][jj] = ok ? xhi[(int64_t)(j0 + jj) * ldx + i0 + ii] : 0.0;
-            xl[ii][jj] = (ok && DD && xlo) ? xlo[(int64_t)(j0 + jj) * ldx + i0 + ii] : 0.0;
+            if (DD) xl[ii][jj] = (ok && xlo) ? xlo[(int64_t)(j0 + jj) * ldx + i0 + ii] : 0.0;
         }
         __syncthreads();
         if (active) {
@@ -167,7 +173,7 @@ __device__ __forceinline__ void atx_body(const ApplyArgs &a, const double *xhi, 
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
 #pragma unroll
-                    for (int j = 0; j < AB_KJ; ++j) {
+                    for (int j = 0; j < KJ; ++j) {
                         if (DD) {
                             dot2_acc(av[u], xh[ii + u][j], s[j], c[j]);
                             c[j] = __builtin_fma(av[u], xl[ii + u][j], c[j]);
@@ -195,20 +201,26 @@ __device__ __forceinline__ void atx_body(const ApplyArgs &a, const double *xhi, 
     }
 }
 
-template <bool DD>
+template <bool DD, int KJ>
 __global__ __launch_bounds__(ATX_T) void atx_kernel(ApplyArgs a, const double *xhi, const double *xlo, int64_t ldx,
                                                     const double *B, int64_t ldb, double *Rout, int64_t ldr,
                                                     double *Y, int64_t ldy, double *Z, int64_t ldz)
 {
-    atx_body<DD>(a, xhi, xlo, ldx, B, ldb, Rout, ldr, Y, ldy, Z, ldz, blockIdx.x, blockIdx.y);
+    atx_body<DD, KJ>(a, xhi, xlo, ldx, B, ldb, Rout, ldr, Y, ldy, Z, ldz, blockIdx.x, blockIdx.y);
 }
 
-template <bool DD>
+template <bool DD, int KJ>
 __global__ __launch_bounds__(ATX_T) void atx_grouped(const AtxGroupArgs *gs)
 {
     const AtxGroupArgs g = gs[blockIdx.z];
-    atx_body<DD>(g.a, g.xhi, g.xlo, g.ldx, g.B, g.ldb, g.Rout, g.ldr, g.Y, g.ldy, g.Z, g.ldz, blockIdx.x, blockIdx.y);
+    atx_body<DD, KJ>(g.a, g.xhi, g.xlo, g.ldx, g.B, g.ldb, g.Rout, g.ldr, g.Y, g.ldy, g.Z, g.ldz, blockIdx.x,
+                     blockIdx.y);
 }
+
+// right-hand sides per block of the A^T x pass (accumulators per thread)
+// (the compensated form keeps 16: twice the accumulators cost more in
+// occupancy than the extra pass over A)
+inline int atx_kj(int k, int dd) { return dd ? 16 : (k > 32 ? 64 : (k > 16 ? 32 : 16)); }
 
 // out(i, j) = sum_r M[r*m + i] * V[r + j*ldv]  (out = M^T V, M row-major m x m)
 __global__ __launch_bounds__(256) void mtv_kernel(const double *M, int m, const double *V, int64_t ldv, double *out,
@@ -299,9 +311,14 @@ __global__ void copy_cols_grouped(const CopyGroupArgs *gs)
 hipError_t ab_partial_f64(const ApplyArgs &a, const double *B, int64_t ldb, int splits, double *part_hi,
                           double *part_lo, int dd, hipStream_t stream)
 {
-    dim3 grid((a.m + AB_RB - 1) / AB_RB, splits, (a.k + AB_KJ - 1) / AB_KJ);
-    if (dd) hipLaunchKernelGGL(ab_partial_kernel<true>, grid, dim3(256), 0, stream, a, B, ldb, splits, part_hi, part_lo);
-    else hipLaunchKernelGGL(ab_partial_kernel<false>, grid, dim3(256), 0, stream, a, B, ldb, splits, part_hi, part_lo);
+    const int kj = ab_kj(a.k, dd);
+    dim3 grid((a.m + AB_RB - 1) / AB_RB, splits, (a.k + kj - 1) / kj);
+#define AB_CASE(DD_, KJ_)                                                                                            \
+    if (!!dd == DD_ && kj == KJ_)                                                                                    \
+        hipLaunchKernelGGL((ab_partial_kernel<DD_, KJ_>), grid, dim3(256), 0, stream, a, B, ldb, splits, part_hi, \
+                           part_lo);
+    AB_CASE(true, 16) AB_CASE(true, 32) AB_CASE(false, 16) AB_CASE(false, 32) AB_CASE(false, 64)
+#undef AB_CASE
     return hipGetLastError();
 }
 
@@ -318,13 +335,14 @@ hipError_t atx_f64(const ApplyArgs &a, const double *Xhi, const double *Xlo, int
                    int64_t ldb, double *Rout, int64_t ldr, double *Y, int64_t ldy, double *Z, int64_t ldz, int dd,
                    hipStream_t stream)
 {
-    dim3 grid((unsigned)((a.n + ATX_T - 1) / ATX_T), (a.k + AB_KJ - 1) / AB_KJ);
-    if (dd)
-        hipLaunchKernelGGL(atx_kernel<true>, grid, dim3(ATX_T), 0, stream, a, Xhi, Xlo, ldx, B, ldb, Rout, ldr, Y, ldy,
-                           Z, ldz);
-    else
-        hipLaunchKernelGGL(atx_kernel<false>, grid, dim3(ATX_T), 0, stream, a, Xhi, Xlo, ldx, B, ldb, Rout, ldr, Y,
-                           ldy, Z, ldz);
+    const int kj = atx_kj(a.k, dd);
+    dim3 grid((unsigned)((a.n + ATX_T - 1) / ATX_T), (a.k + kj - 1) / kj);
+#define ATX_CASE(DD_, KJ_)                                                                                          \
+    if (!!dd == DD_ && kj == KJ_)                                                                                   \
+        hipLaunchKernelGGL((atx_kernel<DD_, KJ_>), grid, dim3(ATX_T), 0, stream, a, Xhi, Xlo, ldx, B, ldb, Rout, ldr, \
+                           Y, ldy, Z, ldz);
+    ATX_CASE(true, 16) ATX_CASE(false, 16) ATX_CASE(false, 32) ATX_CASE(false, 64)
+#undef ATX_CASE
     return hipGetLastError();
 }
 
@@ -361,14 +379,40 @@ hipError_t copy_cols_f64(const double *src, int64_t lds, double *dst, int64_t ld
     return hipGetLastError();
 }
 
+namespace {
+
+// out (m x n, ld ldo) = A diag(d): row i of out is row i of A times d
+// element by element (one problem per blockIdx.y).
+__global__ __launch_bounds__(256) void scale_cols_grouped(const ScaleGroupArgs *gs)
+{
+    const ScaleGroupArgs g = gs[blockIdx.y];
+    const int64_t total = (int64_t)g.m * g.n;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const int64_t i = e / g.n, j = e - i * g.n;
+        g.out[i * g.ldo + j] = g.A[i * g.lda + j] * g.d[j];
+    }
+}
+
+}  // namespace
+
+hipError_t scale_cols_grouped_f64(const ScaleGroupArgs *d, int count, hipStream_t stream)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scale_cols_grouped, dim3(2048, count), dim3(256), 0, stream, d);
+    return hipGetLastError();
+}
+
 hipError_t ab_partial_grouped_f64(const AbGroupArgs *d, int count, int max_m, int max_k, int max_splits, int dd,
                                   hipStream_t stream)
 {
     if (count <= 0 || max_m <= 0 || max_k <= 0) return hipSuccess;
-    const int kb = (max_k + AB_KJ - 1) / AB_KJ;
+    const int kj = ab_kj(max_k, dd);
+    const int kb = (max_k + kj - 1) / kj;
     dim3 grid((max_m + AB_RB - 1) / AB_RB, max_splits, count * kb);
-    if (dd) hipLaunchKernelGGL(ab_partial_grouped<true>, grid, dim3(256), 0, stream, d, kb);
-    else hipLaunchKernelGGL(ab_partial_grouped<false>, grid, dim3(256), 0, stream, d, kb);
+#define AB_CASE(DD_, KJ_) \
+    if (!!dd == DD_ && kj == KJ_) hipLaunchKernelGGL((ab_partial_grouped<DD_, KJ_>), grid, dim3(256), 0, stream, d, kb);
+    AB_CASE(true, 16) AB_CASE(true, 32) AB_CASE(false, 16) AB_CASE(false, 32) AB_CASE(false, 64)
+#undef AB_CASE
     return hipGetLastError();
 }
 
@@ -382,9 +426,12 @@ hipError_t ab_reduce_grouped_f64(const AbGroupArgs *d, int count, int64_t max_mk
 hipError_t atx_grouped_f64(const AtxGroupArgs *d, int count, int64_t max_n, int max_k, int dd, hipStream_t stream)
 {
     if (count <= 0 || max_n <= 0 || max_k <= 0) return hipSuccess;
-    dim3 grid((unsigned)((max_n + ATX_T - 1) / ATX_T), (max_k + AB_KJ - 1) / AB_KJ, count);
-    if (dd) hipLaunchKernelGGL(atx_grouped<true>, grid, dim3(ATX_T), 0, stream, d);
-    else hipLaunchKernelGGL(atx_grouped<false>, grid, dim3(ATX_T), 0, stream, d);
+    const int kj = atx_kj(max_k, dd);
+    dim3 grid((unsigned)((max_n + ATX_T - 1) / ATX_T), (max_k + kj - 1) / kj, count);
+#define ATX_CASE(DD_, KJ_) \
+    if (!!dd == DD_ && kj == KJ_) hipLaunchKernelGGL((atx_grouped<DD_, KJ_>), grid, dim3(ATX_T), 0, stream, d);
+    ATX_CASE(true, 16) ATX_CASE(false, 16) ATX_CASE(false, 32) ATX_CASE(false, 64)
+#undef ATX_CASE
     return hipGetLastError();
 }
 

@@ -22,7 +22,7 @@ namespace {
 
 enum OpKind {
     OP_GEMM, OP_REDUCE, OP_SKETCH, OP_COPY, OP_SET0, OP_SET1, OP_SHIFT, OP_CHOL, OP_TRIINV, OP_QRCPWG, OP_RDIAG,
-    OP_FORMTP, OP_ZERO, OP_AB, OP_ABRED, OP_ATX, OP_DDUPD, OP_IOTA
+    OP_FORMTP, OP_ZERO, OP_AB, OP_ABRED, OP_ATX, OP_DDUPD, OP_IOTA, OP_SCALE
 };
 
 struct Op {
@@ -69,13 +69,15 @@ struct rtproj_batch_s {
     std::vector<rtproj_plan> sub;
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;  // graph capture (the null stream cannot be captured)
-    int refine_steps = 2;
+    int refine_steps = -1;  // -1: schedule from the members' rank estimates
+    int plain_steps = 0, comp_steps = 2;  // schedule of the last projection
     int use_graph = 0;
     int timing = 0;                 // per-stage HIP events (eager mode only)
     double t_stage_ms[16] = {};
     int64_t stage_calls[16] = {};
     int64_t max_m = 0, max_n = 0, max_l = 0;
     double *d_diag_all = nullptr;  // count x 8: |R| ends of R (4), of the Gram factor (4)
+    std::vector<double *> scaled;  // per member: A diag(d) when a column scaling is given
     bool ready = false;
     // one program and arena per entry point, plus its captured graph
     struct Slot {
@@ -434,6 +436,27 @@ void rec_ab(Program &P, rtproj_batch b, const std::vector<int64_t> &k, const dou
             const std::vector<const double *> &B, const std::vector<int64_t> &ldb, int dd)
 {
     const int64_t cnt = b->count;
+    const int64_t kmax = *std::max_element(k.begin(), k.end());
+    if (!dd && kmax >= RT_MFMA_KMIN) {
+        // plain product with many right-hand sides: MFMA GEMM split over n
+        std::vector<rt::GemmArgs> g(cnt);
+        std::vector<rt::ReduceGroupArgs> r(cnt);
+        for (int64_t i = 0; i < cnt; ++i) {
+            rtproj_plan p = b->sub[i];
+            const int64_t m = p->m;
+            rt::GemmArgs &a = g[i];
+            a.M = (int)m; a.N = (int)k[i]; a.K = (int)p->n;
+            a.A = A[i]; a.a_i = lda[i]; a.a_k = 1;
+            a.B = B[i]; a.b_k = 1; a.b_j = ldb[i];
+            a.C = p->d_ph; a.c_i = 1; a.c_j = m; a.c_split = m * k[i];
+            a.alpha = 1.0; a.ksplit = p->ab_splits;
+            r[i] = rt::ReduceGroupArgs{p->d_ph, m * k[i], p->ab_splits, (int)k[i], (int)m, m, p->d_c, m, 0};
+            if (k[i] == 0) { a.M = 0; r[i].M = 0; }
+        }
+        rec_gemm(P, g);
+        rec_reduce(P, r);
+        return;
+    }
     std::vector<rt::AbGroupArgs> v(cnt);
     Op o{OP_AB, 0, (int)cnt};
     o.dd = dd;
@@ -487,7 +510,9 @@ void build_project(Program &P, rtproj_batch b, const double *const *A, const int
         for (int64_t i = 0; i < cnt; ++i) z[i] = rt::MatGroupArgs{b->sub[i]->d_xlo, mm[i], (int)kk[i], (int)mm[i], 0.0, nullptr, nullptr};
         rec_mat(P, OP_SET0, z);
     }
-    for (int it = 0; it < b->refine_steps; ++it) {
+    const int nsteps = b->plain_steps + b->comp_steps;
+    for (int it = 0; it < nsteps; ++it) {
+        const int comp = it >= b->plain_steps ? 1 : 0;  // plain residuals first, compensated last
         std::vector<rt::AtxGroupArgs> a(cnt);
         for (int64_t i = 0; i < cnt; ++i) {
             rtproj_plan p = b->sub[i];
@@ -495,9 +520,33 @@ void build_project(Program &P, rtproj_batch b, const double *const *A, const int
                                     p->m, B[i], ldb[i], p->d_r, p->n, nullptr, 0, nullptr, 0};
         }
         P.stage = 9;
-        rec_atx(P, b, a, 1);
+        if (comp || *std::max_element(kk.begin(), kk.end()) < RT_MFMA_KMIN) {
+            rec_atx(P, b, a, comp);
+        } else {
+            // plain residual r = b - A^T x_hi with many right-hand sides:
+            // copy b, then the MFMA GEMM with alpha = -1, beta = 1
+            std::vector<rt::CopyGroupArgs> cp(cnt);
+            std::vector<rt::GemmArgs> g(cnt);
+            int64_t tot = 0;
+            for (int64_t i = 0; i < cnt; ++i) {
+                rtproj_plan p = b->sub[i];
+                cp[i] = rt::CopyGroupArgs{B[i], ldb[i], p->d_r, p->n, (int)p->n, (int)kk[i], nullptr, 0};
+                tot = std::max(tot, p->n * kk[i]);
+                rt::GemmArgs &q = g[i];
+                q.M = (int)p->n; q.N = (int)kk[i]; q.K = (int)p->m;
+                q.A = A[i]; q.a_i = 1; q.a_k = lda[i];
+                q.B = p->d_xhi; q.b_k = 1; q.b_j = p->m;
+                q.C = p->d_r; q.c_i = 1; q.c_j = p->n;
+                q.alpha = -1.0; q.beta = 1.0; q.ksplit = 1;
+                if (kk[i] == 0) q.M = 0;
+            }
+            Op o{OP_COPY, P.add(cp), (int)cnt};
+            o.total = tot;
+            P.push(o);
+            rec_gemm(P, g);
+        }
         P.stage = 10;
-        rec_ab(P, b, kk, A, lda, r, nn, 1);
+        rec_ab(P, b, kk, A, lda, r, nn, comp);
         P.stage = 8;
         rec_minv(P, b, kk, c, dd);
         std::vector<rt::DdGroupArgs> u(cnt);
@@ -517,7 +566,7 @@ void build_project(Program &P, rtproj_batch b, const double *const *A, const int
                                     Z ? Z[i] : nullptr, Z ? ldz[i] : 0};
             if (!(Y && Y[i]) && !(Z && Z[i])) a[i].a.k = 0;
         }
-        rec_atx(P, b, a, b->refine_steps > 0 ? 1 : 0);
+        rec_atx(P, b, a, nsteps > 0 ? 1 : 0);
     }
     if (X) {
         std::vector<rt::CopyGroupArgs> cp(cnt);
@@ -565,6 +614,7 @@ hipError_t run_op(const Op &o, const unsigned char *arena, hipStream_t s)
     case OP_ATX: return rt::atx_grouped_f64((const rt::AtxGroupArgs *)d, o.count, o.total, o.i1, o.dd, s);
     case OP_DDUPD: return rt::dd_update_grouped_f64((const rt::DdGroupArgs *)d, o.count, s);
     case OP_IOTA: return rt::iota_grouped_i32((const rt::MatGroupArgs *)d, o.count, o.i0, s);
+    case OP_SCALE: return rt::scale_cols_grouped_f64((const rt::ScaleGroupArgs *)d, o.count, s);
     }
     return hipErrorInvalidValue;
 }
@@ -692,6 +742,8 @@ rtproj_status rtproj_batch_destroy(rtproj_batch b)
     for (rtproj_plan p : b->sub)
         if (p) rtproj_plan_destroy(p);
     if (b->d_diag_all) (void)hipFree(b->d_diag_all);
+    for (double *q : b->scaled)
+        if (q) (void)hipFree(q);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     delete b;
     return RTPROJ_OK;
@@ -708,7 +760,7 @@ rtproj_status rtproj_batch_set_stream(rtproj_batch b, void *stream)
 rtproj_status rtproj_batch_set_refinement(rtproj_batch b, int steps)
 {
     if (!b) return fail(RTPROJ_ERR_INVALID_ARG, "null batch");
-    if (steps < 0 || steps > 64) return fail(RTPROJ_ERR_INVALID_ARG, "steps outside [0, 64]");
+    if (steps < -1 || steps > 64) return fail(RTPROJ_ERR_INVALID_ARG, "steps outside [-1, 64]");
     b->refine_steps = steps;
     return RTPROJ_OK;
 }
@@ -733,13 +785,14 @@ rtproj_status rtproj_batch_info(rtproj_batch b, rtproj_info *out)
     if (!b || !out) return fail(RTPROJ_ERR_INVALID_ARG, "null batch or output");
     std::memset(out, 0, sizeof(*out));
     out->m = b->max_m; out->n = b->max_n; out->l = b->max_l;
-    out->refine_steps = b->refine_steps;
+    out->refine_steps = b->plain_steps + b->comp_steps;
     out->qr_mode = RTPROJ_QR_TWO_STAGE_WG;
     for (int s = 0; s < 16; ++s) { out->t_stage_ms[s] = b->t_stage_ms[s]; out->stage_calls[s] = b->stage_calls[s]; }
     return RTPROJ_OK;
 }
 
-rtproj_status rtproj_batch_precondition(rtproj_batch b, const double *const *A, const int64_t *lda)
+rtproj_status rtproj_batch_precondition_scaled(rtproj_batch b, const double *const *A, const int64_t *lda,
+                                              const double *const *col_scale)
 {
     if (!b) return fail(RTPROJ_ERR_INVALID_ARG, "null batch");
     if (!A || !lda) return fail(RTPROJ_ERR_INVALID_ARG, "A or lda is NULL");
@@ -748,16 +801,40 @@ rtproj_status rtproj_batch_precondition(rtproj_batch b, const double *const *A, 
         if (lda[i] < b->sub[i]->n) return fail(RTPROJ_ERR_INVALID_ARG, "member " + std::to_string(i) + ": lda < n");
     }
     b->ready = false;
+    // members with a column scaling work on their own copy A diag(d)
+    std::vector<const double *> Aw(A, A + b->count);
+    std::vector<int64_t> lw(lda, lda + b->count);
+    std::vector<rt::ScaleGroupArgs> sc;
+    if (col_scale) {
+        if (b->scaled.empty()) b->scaled.assign(b->count, nullptr);
+        for (int64_t i = 0; i < b->count; ++i) {
+            if (!col_scale[i]) continue;
+            rtproj_plan p = b->sub[i];
+            if (!b->scaled[i]) RT_HIP(hipMalloc((void **)&b->scaled[i], (size_t)p->m * p->n * sizeof(double)));
+            sc.push_back(rt::ScaleGroupArgs{A[i], lda[i], col_scale[i], b->scaled[i], p->n, (int)p->m, (int)p->n});
+            Aw[i] = b->scaled[i];
+            lw[i] = p->n;
+        }
+    }
     Program P;
-    build_precondition(P, b, A, lda);
+    if (!sc.empty()) {
+        P.stage = 0;
+        P.push(Op{OP_SCALE, P.add(sc), (int)sc.size()});
+    }
+    build_precondition(P, b, Aw.data(), lw.data());
     rtproj_status st = run_program(b, b->pre, P);
     if (st != RTPROJ_OK) return st;
     for (int64_t i = 0; i < b->count; ++i) {
-        b->sub[i]->A = A[i];
-        b->sub[i]->lda = lda[i];
+        b->sub[i]->A = Aw[i];
+        b->sub[i]->lda = lw[i];
     }
     b->ready = true;
     return RTPROJ_OK;
+}
+
+rtproj_status rtproj_batch_precondition(rtproj_batch b, const double *const *A, const int64_t *lda)
+{
+    return rtproj_batch_precondition_scaled(b, A, lda, nullptr);
 }
 
 rtproj_status rtproj_batch_project_all(rtproj_batch b, const double *const *B, const int64_t *ldb, const int64_t *k,
@@ -782,6 +859,30 @@ rtproj_status rtproj_batch_project_all(rtproj_batch b, const double *const *B, c
     for (int64_t i = 0; i < b->count; ++i) {
         rtproj_status st = ensure_k(b->sub[i], std::max<int64_t>(1, k[i]));
         if (st != RTPROJ_OK) return st;
+    }
+    if (b->refine_steps >= 0) {
+        b->plain_steps = 0;
+        b->comp_steps = b->refine_steps;
+    } else {
+        // one schedule for all members (one program): the most demanding one,
+        // from the rank estimates the preconditioner left on the device
+        std::vector<double> diag((size_t)b->count * 8);
+        RT_HIP(hipMemcpyAsync(diag.data(), b->d_diag_all, diag.size() * sizeof(double), hipMemcpyDeviceToHost,
+                              b->stream));
+        RT_HIP(hipStreamSynchronize(b->stream));
+        int pl = 0, cp = 1;
+        for (int64_t i = 0; i < b->count; ++i) {
+            const double *d = diag.data() + 8 * i;
+            const double kap = d[2] > 0 ? d[3] / d[2] : 1e16;
+            const double cw = d[6] > 0 ? d[7] / d[6] : 1e3;
+            int a, c;
+            auto_refine_plan(std::isfinite(kap) ? kap : 1e16, RTPROJ_PREC_FP64, false, std::isfinite(cw) ? cw : 1e3,
+                             &a, &c);
+            pl = std::max(pl, a);
+            cp = std::max(cp, c);
+        }
+        b->plain_steps = pl;
+        b->comp_steps = cp;
     }
     std::vector<const double *> A(b->count);
     std::vector<int64_t> lda(b->count);
@@ -824,7 +925,7 @@ rtproj_status rtproj_batch_member_info(rtproj_batch b, int64_t i, rtproj_info *o
     if (!b || !out || i < 0 || i >= b->count) return fail(RTPROJ_ERR_INVALID_ARG, "bad batch, member or output");
     *out = b->sub[i]->info;
     out->m = b->sub[i]->m; out->n = b->sub[i]->n; out->l = b->sub[i]->l; out->np = b->sub[i]->tab.np;
-    out->refine_steps = b->refine_steps;
+    out->refine_steps = b->plain_steps + b->comp_steps;
     out->qr_mode = RTPROJ_QR_TWO_STAGE_WG;
     return RTPROJ_OK;
 }

@@ -255,6 +255,9 @@ struct AtxGroupArgs {      // as atx_f64
 hipError_t atx_grouped_f64(const AtxGroupArgs *d, int count, int64_t max_n, int max_k, int dd, hipStream_t stream);
 struct DdGroupArgs { double *xhi, *xlo; const double *D; int total; double *norms; };
 hipError_t dd_update_grouped_f64(const DdGroupArgs *d, int count, hipStream_t stream);
+struct ScaleGroupArgs { const double *A; int64_t lda; const double *d; double *out; int64_t ldo; int m, n; };
+// out = A diag(d) per problem (column scaling)
+hipError_t scale_cols_grouped_f64(const ScaleGroupArgs *d, int count, hipStream_t stream);
 struct CopyGroupArgs { const double *src; int64_t lds; double *dst; int64_t ldd; int rows, cols; double *zero_out; int64_t ldz; };
 hipError_t copy_cols_grouped_f64(const CopyGroupArgs *d, int count, int64_t max_total, hipStream_t stream);
 

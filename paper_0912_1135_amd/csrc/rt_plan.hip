@@ -218,7 +218,7 @@ rtproj_status ensure_k(rtproj_plan p, int64_t k)
         if (*b) { (void)hipFree(*b); *b = nullptr; }
     p->kcap = 0;
     const int64_t m = p->m, n = p->n;
-    const int64_t rb = (m + 31) / 32, kb = (k + 15) / 16;
+    const int64_t rb = (m + 31) / 32, kb = (k + 31) / 32;  // row blocks x right-hand-side blocks of the A B pass
     p->ab_splits = (int)std::max<int64_t>(1, std::min<int64_t>(n / 256, (4 * p->cu_count + rb * kb - 1) / (rb * kb)));
     RT_HIP(dalloc(&p->d_c, (size_t)m * k));
     RT_HIP(dalloc(&p->d_tmp, (size_t)m * k));
@@ -416,6 +416,48 @@ rtproj_status apply_minv(rtproj_plan p, const double *C, int64_t ldc, double *H,
     return RTPROJ_OK;
 }
 
+// d_c (m x k, column-major) = A B in plain binary64: the MFMA GEMM (split
+// over n, fixed-order reduction) from RT_MFMA_KMIN right-hand sides on, where
+// the product has enough columns to be a contraction; below that one pass
+// over A on the vector units (bound by reading A).
+hipError_t ab_plain(rtproj_plan p, const double *B, int64_t ldb, int64_t k, hipStream_t s)
+{
+    const int64_t m = p->m, n = p->n;
+    if (k < RT_MFMA_KMIN) {
+        rt::ApplyArgs a{(int)m, (int)n, (int)k, p->A, p->lda};
+        hipError_t e = rt::ab_partial_f64(a, B, ldb, p->ab_splits, p->d_ph, p->d_pl, 0, s);
+        return e != hipSuccess ? e : rt::ab_reduce_f64(p->d_ph, p->d_pl, (int)m, (int)k, p->ab_splits, 0, p->d_c, m, s);
+    }
+    rt::GemmArgs g{};
+    g.M = (int)m; g.N = (int)k; g.K = (int)n;
+    g.A = p->A; g.a_i = p->lda; g.a_k = 1;
+    g.B = B; g.b_k = 1; g.b_j = ldb;
+    g.C = p->d_ph; g.c_i = 1; g.c_j = m; g.c_split = m * k;
+    g.alpha = 1.0; g.ksplit = p->ab_splits;
+    hipError_t e = rt::gemm_f64(g, s);
+    return e != hipSuccess ? e : rt::reduce_splits_f64(p->d_ph, m * k, p->ab_splits, (int)k, (int)m, m, p->d_c, m, 0, s);
+}
+
+// d_r (n x k) = B - A^T x_hi in plain binary64 (refinement steps above the
+// binary64 floor): B copied, then the MFMA GEMM with alpha = -1, beta = 1.
+hipError_t resid_plain(rtproj_plan p, const double *B, int64_t ldb, int64_t k, hipStream_t s)
+{
+    const int64_t m = p->m, n = p->n;
+    if (k < RT_MFMA_KMIN) {
+        rt::ApplyArgs a{(int)m, (int)n, (int)k, p->A, p->lda};
+        return rt::atx_f64(a, p->d_xhi, p->d_xlo, m, B, ldb, p->d_r, n, nullptr, 0, nullptr, 0, 0, s);
+    }
+    hipError_t e = rt::copy_cols_f64(B, ldb, p->d_r, n, (int)n, (int)k, nullptr, 0, s);
+    if (e != hipSuccess) return e;
+    rt::GemmArgs g{};
+    g.M = (int)n; g.N = (int)k; g.K = (int)m;
+    g.A = p->A; g.a_i = 1; g.a_k = p->lda;
+    g.B = p->d_xhi; g.b_k = 1; g.b_j = m;
+    g.C = p->d_r; g.c_i = 1; g.c_j = n;
+    g.alpha = -1.0; g.beta = 1.0; g.ksplit = 1;
+    return rt::gemm_f64(g, s);
+}
+
 rtproj_status project(rtproj_plan p, const double *B, int64_t ldb, int64_t k, double *Z, int64_t ldz, double *Y,
                       int64_t ldy, double *X, int64_t ldx)
 {
@@ -438,8 +480,7 @@ rtproj_status project(rtproj_plan p, const double *B, int64_t ldb, int64_t k, do
     // step 1: c = A b
     {
         StageScope sc(p, 7);
-        RT_HIP(rt::ab_partial_f64(a, B, ldb, p->ab_splits, p->d_ph, p->d_pl, 0, s));
-        RT_HIP(rt::ab_reduce_f64(p->d_ph, p->d_pl, (int)m, (int)k, p->ab_splits, 0, p->d_c, m, s));
+        RT_HIP(ab_plain(p, B, ldb, k, s));
     }
     // steps 2-6: x = Pi^T R^{-1} Y R^{-T} Pi c
     {
@@ -460,12 +501,17 @@ rtproj_status project(rtproj_plan p, const double *B, int64_t ldb, int64_t k, do
         const int dd = it >= nplain ? 1 : 0;
         {
             StageScope sc(p, 9);
-            RT_HIP(rt::atx_f64(a, p->d_xhi, p->d_xlo, m, B, ldb, p->d_r, n, nullptr, 0, nullptr, 0, dd, s));
+            if (dd) RT_HIP(rt::atx_f64(a, p->d_xhi, p->d_xlo, m, B, ldb, p->d_r, n, nullptr, 0, nullptr, 0, 1, s));
+            else RT_HIP(resid_plain(p, B, ldb, k, s));
         }
         {
             StageScope sc(p, 10);
-            RT_HIP(rt::ab_partial_f64(a, p->d_r, n, p->ab_splits, p->d_ph, p->d_pl, dd, s));
-            RT_HIP(rt::ab_reduce_f64(p->d_ph, p->d_pl, (int)m, (int)k, p->ab_splits, dd, p->d_c, m, s));
+            if (dd) {
+                RT_HIP(rt::ab_partial_f64(a, p->d_r, n, p->ab_splits, p->d_ph, p->d_pl, 1, s));
+                RT_HIP(rt::ab_reduce_f64(p->d_ph, p->d_pl, (int)m, (int)k, p->ab_splits, 1, p->d_c, m, s));
+            } else {
+                RT_HIP(ab_plain(p, p->d_r, n, k, s));
+            }
         }
         {
             StageScope sc(p, 8);

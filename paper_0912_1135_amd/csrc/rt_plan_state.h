@@ -29,6 +29,8 @@ extern thread_local std::string g_last_error;
     } while (0)
 
 constexpr int NB = 64;  // block size of the triangular solves and the Cholesky
+// right-hand sides from which the plain binary64 A-passes run as MFMA GEMMs
+constexpr int64_t RT_MFMA_KMIN = 32;
 // P^{-1}A is formed in binary32 only while the rank estimate of the pivoted QR
 // is at most this: its rounding error grows like 2^-24 kappa and must leave
 // the refinement a contraction well below 1.

@@ -40,9 +40,9 @@ def check_member(A, B, Z, Y, X):
     return ez, ey, ex
 
 
-@pytest.mark.parametrize("graph", [False, True])
-def test_batch_matches_oracle(rt, graph):
-    shp = members(10, 71)
+@pytest.mark.parametrize("graph,k_hi", [(False, 9), (True, 9), (True, 40)])
+def test_batch_matches_oracle(rt, graph, k_hi):
+    shp = members(10, 71, k_hi=k_hi)
     As = [synth.make_problem(m, n, 1e6, 100 + i) for i, (m, n) in enumerate(zip(shp.m, shp.n))]
     Bs = [synth.make_rhs(n, k, 200 + i) for i, (n, k) in enumerate(zip(shp.n, shp.k))]
     bt = rt.Batch(shp.m, shp.n, shp.l, 5)
@@ -109,4 +109,25 @@ def test_batch_member_equals_single_plan(rt):
     Z, Y, X = bt.project_all([torch.from_numpy(B).to(dev())])
     e = check_member(A, B, Z[0].cpu().numpy(), Y[0].cpu().numpy(), X[0].cpu().numpy())
     assert max(e) <= TOL, e
+    bt.close()
+
+
+def test_batch_column_scaled_members_match_oracle(rt):
+    """Interior-point shape: one base A, member t works on A diag(d_t) with
+    d_t = 10^U(-6, 6); each member against the oracle on the scaled matrix."""
+    m, n, l, steps = 40, 1500, 160, 4
+    A = synth.make_problem(m, n, 1e4, 77)
+    D = synth.make_scalings(n, steps, 77)
+    Bs = [synth.make_rhs(n, 3, 900 + t) for t in range(steps)]
+    bt = rt.Batch([m] * steps, [n] * steps, [l] * steps, 13)
+    bt.set_graph(True)
+    At = torch.from_numpy(A).to(dev())
+    Dt = [torch.from_numpy(np.ascontiguousarray(D[t])).to(dev()) for t in range(steps)]
+    for rep in range(2):  # the second call replays the captured graphs
+        bt.precondition([At] * steps, Dt)
+        Z, Y, X = bt.project_all([torch.from_numpy(B).to(dev()) for B in Bs])
+        assert bt.status() == [0] * steps
+        for t in range(steps):
+            e = check_member(A * D[t][None, :], Bs[t], Z[t].cpu().numpy(), Y[t].cpu().numpy(), X[t].cpu().numpy())
+            assert max(e) <= TOL, (rep, t, e)
     bt.close()

@@ -66,6 +66,7 @@ def errors(B, Z, Y, X, Zr, Yr, Xr):
     (33, 500, 33, 1e6, 4, 6),              # l = m
     (600, 8192, 4096, 1e6, 2, 7),          # tall sketch: register-resident QR, 8 rows per thread
     (600, 16384, 9000, 1e6, 2, 8),         # taller than the register form: QR columns in global memory
+    (200, 6000, 800, 1e6, 40, 9),          # k >= 32: the plain A B pass on MFMA
 ])
 def test_projection_matches_oracle(rt, m, n, l, kappa, k, seed):
     A = synth.make_problem(m, n, kappa, seed)
@@ -238,6 +239,7 @@ def test_aliasing_z_equals_b(rt):
     (64, 4096, 256, 1e3, 3, 31),      # P^{-1}A in binary32 (kappa_est small)
     (100, 5000, 400, 1e8, 4, 32),     # P^{-1}A stays binary64, reduced-precision Gram
     (130, 9000, 520, 1e10, 5, 33),
+    (150, 6000, 600, 1e6, 36, 34),    # k >= 32: plain refinement steps and A B on MFMA
 ])
 def test_mixed_precision_matches_oracle(rt, prec, name, m, n, l, kappa, k, seed):
     A = synth.make_problem(m, n, kappa, seed)
