@@ -62,11 +62,13 @@ __device__ __forceinline__ double group_sum(double v, double *scratch)
 __device__ __forceinline__ bool spin_until(unsigned *addr, unsigned target, int *err)
 {
     long spins = 0;
-    // relaxed polling (no cache invalidation per poll); the caller issues one
-    // acquire fence after the wait
+    // relaxed device-scope polling (no cache maintenance per poll); the error
+    // word is looked at only every 256 polls so that a poll is one load
     while (__hip_atomic_load(addr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
         __builtin_amdgcn_s_sleep(1);
-        if (++spins > SPIN_LIMIT || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        ++spins;
+        if (spins > SPIN_LIMIT ||
+            ((spins & 255) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
             __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return false;
         }
@@ -225,40 +227,165 @@ __global__ __launch_bounds__(QR_THREADS) void qrcp_kernel(const double *S, int64
 // Register-resident form (the default): 512 threads, block g keeps its NC
 // columns in registers, thread t owning rows t, t + 512, ..., so that each
 // thread reads the reflector's entries for its rows once and applies them to
-// all NC columns; dot products and trailing norms are block reductions.  The
-// pivot column is read straight from its owner's posted copy.
+// all NC columns.  A step is a chain of dependent latencies (post, barrier,
+// candidate headers, pivot column), so everything between them is kept short:
+//   - reductions run inside the wave on DPP lane moves (quad permutes, row
+//     mirrors, row broadcasts) and lane reads, one LDS exchange per block;
+//   - the pivot choice and the broadcast of sums stay in registers;
+//   - posted data (headers and candidate columns) is written and read with
+//     device-scope accesses, which are coherent across the L2 slices of the
+//     XCDs without flushing or invalidating them; a block announces its
+//     arrival only after its posting stores have completed.
 constexpr int RQ_T = 512;
 constexpr int RQ_W = RQ_T / 64;
 
+__device__ __forceinline__ double u64_to_d(unsigned lo, unsigned hi)
+{
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// DPP move of a double (two 32-bit lane moves); lanes of rows outside
+// ROW_MASK receive 0.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ double dpp_d(double v)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROW_MASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROW_MASK, 0xF, false);
+    return u64_to_d((unsigned)lo, (unsigned)hi);
+}
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)(unsigned)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+    return u64_to_d((unsigned)lo, (unsigned)hi);
+}
+
+constexpr int DPP_QUAD_XOR1 = 0xB1;  // quad_perm [1,0,3,2]
+constexpr int DPP_QUAD_XOR2 = 0x4E;  // quad_perm [2,3,0,1]
+constexpr int DPP_ROW_MIRROR = 0x140;
+constexpr int DPP_ROW_HALF_MIRROR = 0x141;
+constexpr int DPP_ROW_BCAST15 = 0x142;
+constexpr int DPP_ROW_BCAST31 = 0x143;
+
+// Sum over the wave, returned uniformly.  Butterflies inside each 16-lane row
+// leave the row sum in every lane of the row; two row broadcasts then
+// accumulate rows 0..3 into lane 63.
+__device__ __forceinline__ double wave_total(double v)
+{
+    v += dpp_d<DPP_QUAD_XOR1>(v);
+    v += dpp_d<DPP_QUAD_XOR2>(v);
+    v += dpp_d<DPP_ROW_HALF_MIRROR>(v);
+    v += dpp_d<DPP_ROW_MIRROR>(v);
+    v += dpp_d<DPP_ROW_BCAST15, 0xA>(v);
+    v += dpp_d<DPP_ROW_BCAST31, 0xC>(v);
+    return readlane_d(v, 63);
+}
+
+// Candidate order: larger norm^2 first, then the lower column index.  Every
+// candidate carries a norm >= -1 (never NaN), so the order is total.
+__device__ __forceinline__ bool cand_better(double n2, int c2, double n, int c)
+{
+    return n2 > n || (n2 == n && c2 < c);
+}
+
+template <int CTRL>
+__device__ __forceinline__ void amax_step(double &n, int &c)
+{
+    const double n2 = dpp_d<CTRL>(n);
+    const int c2 = dpp_i<CTRL>(c);
+    if (cand_better(n2, c2, n, c)) { n = n2; c = c2; }
+}
+
+// Best candidate of the wave, returned uniformly.
+__device__ __forceinline__ void wave_best(double &n, int &c)
+{
+    amax_step<DPP_QUAD_XOR1>(n, c);
+    amax_step<DPP_QUAD_XOR2>(n, c);
+    amax_step<DPP_ROW_HALF_MIRROR>(n, c);
+    amax_step<DPP_ROW_MIRROR>(n, c);
+    double bn = readlane_d(n, 0);
+    int bc = __builtin_amdgcn_readlane(c, 0);
+#pragma unroll
+    for (int r = 1; r < 4; ++r) {
+        const double n2 = readlane_d(n, 16 * r);
+        const int c2 = __builtin_amdgcn_readlane(c, 16 * r);
+        if (cand_better(n2, c2, bn, bc)) { bn = n2; bc = c2; }
+    }
+    n = bn;
+    c = bc;
+}
+
+__device__ __forceinline__ void st_dev(double *p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_dev(const double *p)
+{
+    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Wait until this thread's outstanding memory operations (the posting
+// stores) have completed.
+__device__ __forceinline__ void wait_mem()
+{
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Block-wide column sums of the per-thread partials p[0..NC): wave totals go
+// through LDS (red, NC x RQ_W), then lane c of every wave adds column c's
+// wave totals in a fixed order.  Returns lane c's column sum (0 for c >= NC);
+// identical in every wave.  One block barrier.
 template <int NC>
-__device__ __forceinline__ void block_sums(double (&v)[NC], double (*red)[NC], double *out)
+__device__ __forceinline__ double block_col_sums(const double (&p)[NC], double (*red)[RQ_W])
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) v[c] = wave_sum(v[c]);
-    if (lane == 0)
-#pragma unroll
-        for (int c = 0; c < NC; ++c) red[wave][c] = v[c];
-    __syncthreads();
-    if (threadIdx.x < NC) {
-        double s = 0.0;
-#pragma unroll
-        for (int w = 0; w < RQ_W; ++w) s += red[w][threadIdx.x];
-        out[threadIdx.x] = s;
+    for (int c = 0; c < NC; ++c) {
+        const double t = wave_total(p[c]);
+        if (lane == 0) red[c][wave] = t;
     }
     __syncthreads();
+    double s = 0.0;
+    if (lane < NC)
+#pragma unroll
+        for (int w = 0; w < RQ_W; ++w) s += red[lane][w];
+    return s;
+}
+
+// Local candidate from lane c's trailing norm^2 s: the largest norm among the
+// block's remaining columns (lowest local index on ties); -1 when none is
+// left (or only NaN norms are).
+template <int NC>
+__device__ __forceinline__ void local_best(double s, int ncol, unsigned done, double &bn, int &bc)
+{
+    const int lane = threadIdx.x & 63;
+    const bool ok = lane < ncol && !((done >> lane) & 1u) && s >= 0.0;
+    double n = ok ? s : -1.0;
+    int c = ok ? lane : 0x7fffffff;
+    wave_best(n, c);
+    bn = n;
+    bc = n >= 0.0 ? c : -1;
 }
 
 template <int NC, int RPT>
 __global__ __launch_bounds__(RQ_T) void qrcp_reg_kernel(const double *S, int64_t lds, int rows, int cols, double *R,
                                                         int32_t *piv, QrcpWork w, int G)
 {
-    __shared__ double red[RQ_W][NC];
-    __shared__ double s_dot[NC], nrm[NC];
-    __shared__ int done[NC];
-    __shared__ int s_p, s_abort, s_best;
+    static_assert(NC <= 32, "done mask and lane-per-column sums");
+    __shared__ double red[2][NC][RQ_W];
     __shared__ double s_pn;
-    const int g = blockIdx.x, tid = threadIdx.x;
+    __shared__ int s_p, s_abort;
+    const int g = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
     int ncol = 0;
     while (ncol < NC && g + G * ncol < cols) ++ncol;
     double *hdr = w.slots;  // 2 x G x 2: candidate (norm^2, column)
@@ -272,8 +399,10 @@ __global__ __launch_bounds__(RQ_T) void qrcp_reg_kernel(const double *S, int64_t
             const int i = tid + RQ_T * r;
             x[c][r] = (c < ncol && i < rows) ? S[(int64_t)(g + G * c) * lds + i] : 0.0;
         }
-    if (tid < NC) done[tid] = (tid < ncol) ? 0 : 1;
     if (tid == 0) s_abort = 0;
+    unsigned done = 0;  // bit c: local column c retired (uniform)
+    double bn;
+    int bc;
     {
         double part[NC];
 #pragma unroll
@@ -282,60 +411,50 @@ __global__ __launch_bounds__(RQ_T) void qrcp_reg_kernel(const double *S, int64_t
 #pragma unroll
             for (int r = 0; r < RPT; ++r) part[c] += x[c][r] * x[c][r];
         }
-        block_sums<NC>(part, red, nrm);
+        local_best<NC>(block_col_sums<NC>(part, red[1]), ncol, done, bn, bc);
     }
 
     for (int k = 0; k < cols; ++k) {
         const int buf = k & 1;
-        // 1. post the local candidate (header and rows >= k of its column)
-        if (tid == 0) {
-            double bn = -1.0;
-            int bc = -1;
-            for (int c = 0; c < ncol; ++c)
-                if (!done[c] && nrm[c] > bn) { bn = nrm[c]; bc = c; }
-            s_best = bc;
-            hdr[(buf * G + g) * 2 + 0] = bn;
-            hdr[(buf * G + g) * 2 + 1] = bc >= 0 ? (double)(g + G * bc) : -1.0;
-        }
-        __syncthreads();
-        const int best = s_best;
-        if (best >= 0) {
+        // 1. post the local candidate: header, and rows >= k of its column
+        if (bc >= 0) {
             double *dst = cand + ((int64_t)buf * G + g) * rows;
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
                 const int i = tid + RQ_T * r;
                 double val = 0.0;
 #pragma unroll
-                for (int c = 0; c < NC; ++c) val = (c == best) ? x[c][r] : val;
-                if (i >= k && i < rows) dst[i] = val;
+                for (int c = 0; c < NC; ++c) val = (c == bc) ? x[c][r] : val;
+                if (i >= k && i < rows) st_dev(dst + i, val);
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        if (tid == 0) {
+            st_dev(hdr + (buf * G + g) * 2 + 0, bn);
+            st_dev(hdr + (buf * G + g) * 2 + 1, bc >= 0 ? (double)(g + G * bc) : -1.0);
+        }
+        wait_mem();
         __syncthreads();
         // 2. grid barrier (arrival counter is monotonic across steps)
         if (tid == 0) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __hip_atomic_fetch_add(w.counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (!spin_until(w.counter, (unsigned)(k + 1) * (unsigned)G, w.err)) s_abort = 1;
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         __syncthreads();
         if (s_abort) return;
-        // 3. agree on the pivot (wave 0 scans the G candidates)
+        // 3. agree on the pivot (wave 0 scans the G candidate headers)
         if (tid < 64) {
-            double bn = -2.0;
-            int bj = 0x7fffffff;
-            for (int q = tid; q < G; q += 64) {
-                const double n = hdr[(buf * G + q) * 2 + 0];
-                const int j = (int)hdr[(buf * G + q) * 2 + 1];
-                if (j >= 0 && (n > bn || (n == bn && j < bj))) { bn = n; bj = j; }
+            double n = -2.0;
+            int j = 0x7fffffff;
+            for (int q = lane; q < G; q += 64) {
+                const double qn = ld_dev(hdr + (buf * G + q) * 2 + 0);
+                const int qj = (int)ld_dev(hdr + (buf * G + q) * 2 + 1);
+                if (qj >= 0 && cand_better(qn, qj, n, j)) { n = qn; j = qj; }
             }
-            for (int o = 32; o > 0; o >>= 1) {
-                const double on = __shfl_xor(bn, o, 64);
-                const int oj = __shfl_xor(bj, o, 64);
-                if (on > bn || (on == bn && oj < bj)) { bn = on; bj = oj; }
+            wave_best(n, j);
+            if (tid == 0) {
+                s_p = n >= 0.0 ? j : -1;
+                s_pn = n;
             }
-            if (tid == 0) { s_p = bj; s_pn = bn; }
         }
         __syncthreads();
         const int p = s_p;
@@ -345,7 +464,13 @@ __global__ __launch_bounds__(RQ_T) void qrcp_reg_kernel(const double *S, int64_t
         }
         // 4. reflector entries for this thread's rows, from the posted column
         const double *xp = cand + ((int64_t)buf * G + (p % G)) * rows;
-        const double alpha = xp[k];
+        const double alpha = ld_dev(xp + k);
+        double v[RPT];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int i = tid + RQ_T * r;
+            v[r] = (i > k && i < rows) ? ld_dev(xp + i) : 0.0;
+        }
         const double xnorm = __builtin_sqrt(s_pn);
         double beta, tau, inv;
         if (xnorm == 0.0) { beta = 0.0; tau = 0.0; inv = 0.0; }
@@ -354,12 +479,8 @@ __global__ __launch_bounds__(RQ_T) void qrcp_reg_kernel(const double *S, int64_t
             tau = (beta - alpha) / beta;
             inv = 1.0 / (alpha - beta);
         }
-        double v[RPT];
 #pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            const int i = tid + RQ_T * r;
-            v[r] = (i == k) ? 1.0 : ((i > k && i < rows) ? xp[i] * inv : 0.0);
-        }
+        for (int r = 0; r < RPT; ++r) v[r] = (tid + RQ_T * r == k) ? 1.0 : v[r] * inv;
         // 5. owner: column k of R and piv[k]
         if (p % G == g) {
             const int c = p / G;
@@ -374,27 +495,28 @@ __global__ __launch_bounds__(RQ_T) void qrcp_reg_kernel(const double *S, int64_t
             if (tid == 0) {
                 R[(int64_t)k * cols + k] = beta;
                 piv[k] = p;
-                done[c] = 1;
             }
+            done |= 1u << c;
         }
-        // 6. dot products v . x_c (block sums), then the update and the next
-        //    trailing norms
+        // 6. dot products v . x_c, then the update and the next trailing norms
+        double d[NC];
         {
-            double d[NC];
+            double part[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                d[c] = 0.0;
+                part[c] = 0.0;
 #pragma unroll
-                for (int r = 0; r < RPT; ++r) d[c] += v[r] * x[c][r];
+                for (int r = 0; r < RPT; ++r) part[c] += v[r] * x[c][r];
             }
-            block_sums<NC>(d, red, s_dot);
+            const double s = block_col_sums<NC>(part, red[0]);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) d[c] = readlane_d(s, c);
         }
         {
             double nn[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                const bool act = !done[c];
-                const double f = act ? tau * s_dot[c] : 0.0;
+                const double f = ((done >> c) & 1u) ? 0.0 : tau * d[c];
                 nn[c] = 0.0;
 #pragma unroll
                 for (int r = 0; r < RPT; ++r) {
@@ -404,7 +526,7 @@ __global__ __launch_bounds__(RQ_T) void qrcp_reg_kernel(const double *S, int64_t
                     if (i > k) nn[c] += nx * nx;
                 }
             }
-            block_sums<NC>(nn, red, nrm);
+            local_best<NC>(block_col_sums<NC>(nn, red[1]), ncol, done, bn, bc);
         }
     }
 }
