@@ -2,7 +2,7 @@
 """Throughput of the randomized orthogonal projection on one MI355X.
 
 One step = the whole path on one batch of work: precondition A (sketch,
-pivoted QR, R^{-T}, P^{-1}A, Gram, Cholesky) and project k right-hand sides
+pivoted QR, R^{-T}, P^{-1}A, Gram, its inverse) and project k right-hand sides
 (least-squares x, row projection A^T x, null projection b - A^T x, with the
 compensated refinement), all through the C ABI.
 
@@ -54,10 +54,12 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def stage_work(name, dims, prec="fp64", w_bits=64):
+def stage_work(name, dims, prec="fp64", w_bits=64, inv=(2, 0)):
     """Algorithmic work per launch of a stage summed over the problems in
-    `dims` (a list of (m, n, l, k)): (bound, amount, kind, peak)."""
+    `dims` (a list of (m, n, l, k)): (bound, amount, kind, peak).  `inv` is
+    (method, iterations) of the Gram's inverse: 1 Newton-Schulz, 2 Cholesky."""
     tot = 0.0
+    ns = inv[0] == 1
     for (m, n, l, k) in dims:
         if name == "sketch":
             tot += 8.0 * m * n + 8.0 * m * l                               # read A, write S
@@ -67,8 +69,12 @@ def stage_work(name, dims, prec="fp64", w_bits=64):
             # shifted Cholesky QR: three Grams m(m+1)l, two solves m^2 l,
             # three Cholesky m^3/3 and two triangular products m^3/3
             tot += 3.0 * m * (m + 1) * l + 2.0 * m * m * l + 5.0 * m ** 3 / 3
-        elif name in ("rinv_trsm", "cholesky", "t_trsm"):
+        elif name == "rinv_trsm":
             tot += m ** 3 / 3.0
+        elif name == "gram_inv":
+            tot += 4.0 * m ** 3 * inv[1] if ns else m ** 3 / 3.0        # two m^3 products per step
+        elif name == "minv_form":
+            tot += 24.0 * m * m if ns else m ** 3 / 3.0                  # R^{-T} Pi and its transpose
         elif name == "w_gemm":
             tot += 1.0 * m * m * n                                          # triangular: m^2 n
         elif name == "gram_syrk":
@@ -79,7 +85,7 @@ def stage_work(name, dims, prec="fp64", w_bits=64):
             tot += 10.0 * m * n * k                                         # Dot2: 10 FP64 ops per term
         else:
             return None, 0.0, None, None
-    if name in ("sketch", "ab"):
+    if name in ("sketch", "ab") or (name == "minv_form" and ns):
         return "hbm", tot, "bytes", PEAK_HBM_GBS
     if name == "qrcp":
         return "alu", tot, "flops", PEAK_FP64_TFLOPS
@@ -100,7 +106,7 @@ STAGE_KERNELS = {
     "sketch": ("sketch_pass", "paper_0912_1135_amd/csrc/rt_sketch.hip"),
     "gram_syrk": ("gemm_f64_kernel", "paper_0912_1135_amd/csrc/rt_gemm.hip"),
     "w_gemm": ("gemm_f64_kernel", "paper_0912_1135_amd/csrc/rt_gemm.hip"),
-    "cholesky": ("chol_diag_kernel", "paper_0912_1135_amd/csrc/rt_factor.hip"),
+    "gram_inv": ("gemm_f64_kernel", "paper_0912_1135_amd/csrc/rt_gemm.hip"),
     "refine_atx": ("atx_kernel", "paper_0912_1135_amd/csrc/rt_apply.hip"),
     "final_atx": ("atx_kernel", "paper_0912_1135_amd/csrc/rt_apply.hip"),
     "refine_ab": ("ab_partial_kernel", "paper_0912_1135_amd/csrc/rt_apply.hip"),
@@ -148,7 +154,8 @@ def stage_table(info, steps, dims, prec, w_bits):
         if not calls:
             continue
         d = {"ms_per_step": tot / steps, "ms_per_launch": tot / calls, "launches_per_step": calls / steps}
-        bound, amt, kind, peak = stage_work(name, dims, prec, w_bits)
+        bound, amt, kind, peak = stage_work(name, dims, prec, w_bits,
+                                            (info.get("inverse", 2), info.get("inverse_iters", 0)))
         if bound is not None:
             sec = d["ms_per_launch"] / 1e3
             if bound == "hbm":
@@ -222,6 +229,7 @@ def run_single(args, rt, synth, np, torch):
         plan.set_precision(PRECISIONS[prec])
         plan.set_refinement(args.refine_steps, 0.0)
         plan.set_qr(args.qr)
+        plan.set_inverse(args.inverse)
         Z, Y = torch.empty_like(Bt), torch.empty_like(Bt)
         X = torch.empty((k, m), dtype=torch.float64, device=dev)
         steps = args.steps if prec == main_prec else min(args.steps, args.form_steps)
@@ -235,6 +243,8 @@ def run_single(args, rt, synth, np, torch):
                        "w_bits": info["w_bits"], "gram_bits": info["gram_bits"],
                        "sketch_escalated": info["sketch_escalated"], "kappa_est": info["kappa_est"],
                        "gram_cond_est": info["gram_cond_est"], "qr_mode": info["qr_mode"],
+                       "inverse": info["inverse"], "inverse_iters": info["inverse_iters"],
+                       "inverse_resid": info["inverse_resid"],
                        "stage_ms": {s: round(d["ms_per_step"], 4) for s, d in stages.items()}}
         if prec == main_prec:
             main = (ms, info, stages, steps)
@@ -535,6 +545,7 @@ def main():
     ap.add_argument("--refine-steps", type=int, default=-1, help="-1: chosen from the pivoted-QR rank estimate")
     ap.add_argument("--qr", type=int, default=0, help="pivoted-QR method: 0 auto, 1 direct, 2 two-stage, "
                                                       "3 two-stage with a single-workgroup second stage")
+    ap.add_argument("--inverse", type=int, default=0, help="Gram inverse: 0 auto, 1 Newton-Schulz, 2 Cholesky")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",

@@ -58,19 +58,21 @@ typedef enum {
     RTPROJ_ERR_DEVICE = 3,      /* HIP runtime or kernel failure                 */
     RTPROJ_ERR_STATE = 4,       /* projection requested before preconditioning   */
     RTPROJ_ERR_RANK = 5,        /* A (numerically) rank deficient: the pivoted QR
-                                   of the sketch or the Cholesky of the Gram failed */
+                                   of the sketch failed, or the Gram's inverse
+                                   (Cholesky breakdown, or no Newton-Schulz
+                                   convergence)                                  */
     RTPROJ_ERR_NOCONV = 6,      /* refinement did not contract                   */
     RTPROJ_ERR_UNSUPPORTED = 7  /* size or mode this build does not handle       */
 } rtproj_status;
 
 /* Arithmetic used by the preconditioner (the projection's residuals, the
- * solves with R and Pi, and the Cholesky are always binary64). */
+ * solves with R and Pi, and the Gram's inverse are always binary64). */
 typedef enum {
     RTPROJ_PREC_FP64 = 0,       /* sketch, P^{-1}A and its Gram in binary64           */
     RTPROJ_PREC_MIXED_FP32 = 1, /* binary32 sketch and Gram (binary32 MFMA); P^{-1}A
                                    in binary32 when kappa_est <= 1e5, else binary64;
-                                   the sketch is redone in binary64 when the Gram's
-                                   Cholesky shows cond(P^{-1}A) > 10                 */
+                                   the sketch is redone in binary64 when the Gram
+                                   shows cond(P^{-1}A) > 10 (gram_cond_est)           */
     RTPROJ_PREC_MIXED_BF16 = 2  /* binary32 sketch; Gram from row-scaled (powers of
                                    two) bfloat16 P^{-1}A on MFMA with binary32
                                    accumulation; P^{-1}A as in MIXED_FP32             */
@@ -90,6 +92,19 @@ typedef enum {
     RTPROJ_QR_TWO_STAGE_WG = 3  /* as 2, the QRCP of R0 in one workgroup         */
 } rtproj_qr_mode;
 
+/* How Y = X^{-1} of the Gram X = (P^{-1}A)(P^{-1}A)^* (eq. inversion) enters
+ * the projections.  Both give (A A^*)^{-1} up to rounding; the refinement
+ * removes what is left. */
+typedef enum {
+    RTPROJ_INV_AUTO = 0,           /* Newton-Schulz for m <= 1024, else Cholesky   */
+    RTPROJ_INV_NEWTON_SCHULZ = 1,  /* Y_{k+1} = Y_k (2I - X Y_k), Y_0 = I/|X|_inf,
+                                      iterated until |I - X Y_k|_F <= 1e-6 (then
+                                      one more step); applications use
+                                      T'^T (Y (T' c)) with T' = R^{-T} Pi         */
+    RTPROJ_INV_CHOLESKY = 2        /* X = L L^T (blocked, binary64); applications
+                                      use T' = L^{-1} R^{-T} Pi, T'^T (T' c)      */
+} rtproj_inverse;
+
 typedef struct {
     int64_t m, n, l;           /* sizes of the plan                                  */
     int64_t np;                /* padded Fourier length of the sketch               */
@@ -102,18 +117,28 @@ typedef struct {
     int sketch_bits, w_bits, gram_bits; /* precisions used by the last precondition:
                                    64 binary64, 32 binary32, 16 bfloat16             */
     int sketch_escalated;      /* 1 if a binary32 sketch was redone in binary64      */
-    double gram_cond_est;      /* max/min diag of the Gram's Cholesky factor, a lower
-                                   bound on cond(P^{-1}A)                            */
+    double gram_cond_est;      /* a lower bound on cond(P^{-1}A): Newton-Schulz
+                                   sqrt(max_i X_ii max_i Y_ii); Cholesky max/min
+                                   of diag(L)                                        */
     /* Per-stage device time, accumulated since rtproj_plan_set_timing(plan, 1),
      * measured with HIP events on the plan's stream (zero while timing is off).
      * Stages: 0 sketch, 1 pivoted QR, 2 R^{-T} solve, 3 P^{-1}A product, 4 Gram,
-     * 5 Cholesky, 6 L^{-1}R^{-T} solve, 7 A b, 8 applications of (AA^T)^{-1},
+     * 5 inverse of the Gram (Newton-Schulz iterations, or the Cholesky),
+     * 6 the factor T' of M^{-1} (Newton-Schulz: R^{-T} Pi; Cholesky: the
+     * solve L^{-1}R^{-T}), 7 A b, 8 applications of (AA^T)^{-1},
      * 9 refinement residual b - A^T x, 10 refinement product A r,
      * 11 final A^T x and b - A^T x, 12 the small factor R0 of the two-stage
      * pivoted QR, 13..15 unused. */
     double t_stage_ms[16];
     int64_t stage_calls[16];
     int qr_mode;               /* rtproj_qr_mode used by the last precondition       */
+    int inverse;               /* rtproj_inverse used by the last precondition
+                                  (1 or 2)                                          */
+    int inverse_iters;         /* Newton-Schulz iterations (0 for Cholesky)          */
+    double inverse_resid;      /* Newton-Schulz: |I - X Y_k|_F of the last iterate
+                                  before the final step (the final residual is
+                                  about its square, down to rounding); 0 for
+                                  Cholesky                                          */
 } rtproj_info;
 
 /*
@@ -138,6 +163,10 @@ rtproj_status rtproj_plan_set_precision(rtproj_plan plan, int precision);
  * the next rtproj_precondition; RTPROJ_ERR_UNSUPPORTED if the mode cannot
  * handle the plan's sizes. */
 rtproj_status rtproj_plan_set_qr(rtproj_plan plan, int mode);
+
+/* Method of the Gram's inverse (rtproj_inverse).  Takes effect at the next
+ * rtproj_precondition; RTPROJ_ERR_INVALID_ARG for an unknown value. */
+rtproj_status rtproj_plan_set_inverse(rtproj_plan plan, int method);
 
 /*
  * Iterative refinement of the least-squares solution (Remark 4.3): up to
@@ -202,11 +231,12 @@ rtproj_status rtproj_plan_info(rtproj_plan plan, rtproj_info *out);
  *   S    m x l row-major sketch (lds >= l; NULL to skip)
  *   R    m x m row-major upper-triangular factor of the pivoted QR (NULL to skip)
  *   piv  m int32: column k of S^T Pi^T is column piv[k] of S^T (NULL to skip)
- *   L    m x m row-major lower Cholesky factor of the Gram X (NULL to skip)
+ *   Minv m x m row-major M^{-1} = (P^*)^{-1} Y P^{-1}, the approximation of
+ *        (A A^*)^{-1} the projections apply (NULL to skip)
  * RTPROJ_ERR_STATE before preconditioning.
  */
 rtproj_status rtproj_plan_export(rtproj_plan plan, double *S, int64_t lds, double *R,
-                                 int32_t *piv, double *L);
+                                 int32_t *piv, double *Minv);
 
 /*
  * Host copies of the plan's random sketch tables (for inspection):

@@ -39,11 +39,13 @@ class _Info(ctypes.Structure):
                 ("gram_bits", ctypes.c_int), ("sketch_escalated", ctypes.c_int), ("gram_cond_est", ctypes.c_double),
                 ("t_stage_ms", ctypes.c_double * 16),
                 ("stage_calls", ctypes.c_int64 * 16),
-                ("qr_mode", ctypes.c_int)]
+                ("qr_mode", ctypes.c_int), ("inverse", ctypes.c_int), ("inverse_iters", ctypes.c_int),
+                ("inverse_resid", ctypes.c_double)]
 
-STAGES = ["sketch", "qrcp", "rinv_trsm", "w_gemm", "gram_syrk", "cholesky", "t_trsm", "ab",
+STAGES = ["sketch", "qrcp", "rinv_trsm", "w_gemm", "gram_syrk", "gram_inv", "minv_form", "ab",
           "minv", "refine_atx", "refine_ab", "final_atx", "qr_r0"]
 QR_AUTO, QR_DIRECT, QR_TWO_STAGE, QR_TWO_STAGE_WG = 0, 1, 2, 3
+INV_AUTO, INV_NEWTON_SCHULZ, INV_CHOLESKY = 0, 1, 2
 
 
 def lib():
@@ -61,6 +63,7 @@ def lib():
         L.rtproj_plan_set_precision.argtypes = [vp, ip]
         L.rtproj_plan_set_refinement.argtypes = [vp, ip, dp]
         L.rtproj_plan_set_qr.argtypes = [vp, ip]
+        L.rtproj_plan_set_inverse.argtypes = [vp, ip]
         L.rtproj_precondition.argtypes = [vp, vp, i64]
         L.rtproj_project_null.argtypes = [vp, vp, i64, i64, vp, i64]
         L.rtproj_project_row.argtypes = [vp, vp, i64, i64, vp, i64]
@@ -86,7 +89,8 @@ def lib():
         L.rtproj_status_string.restype = ctypes.c_char_p
         L.rtproj_last_error.restype = ctypes.c_char_p
         for name in ["rtproj_plan_create", "rtproj_plan_destroy", "rtproj_plan_set_stream",
-                     "rtproj_plan_set_precision", "rtproj_plan_set_refinement", "rtproj_plan_set_qr", "rtproj_precondition",
+                     "rtproj_plan_set_precision", "rtproj_plan_set_refinement", "rtproj_plan_set_qr", "rtproj_plan_set_inverse",
+                     "rtproj_precondition",
                      "rtproj_project_null", "rtproj_project_row", "rtproj_lstsq", "rtproj_project_all",
                      "rtproj_plan_info", "rtproj_plan_export", "rtproj_sketch_tables",
                      "rtproj_plan_set_timing", "rtproj_batch_create", "rtproj_batch_destroy",
@@ -154,6 +158,10 @@ class Plan:
         """Pivoted-QR method (QR_AUTO, QR_DIRECT, QR_TWO_STAGE, QR_TWO_STAGE_WG)."""
         _check(lib().rtproj_plan_set_qr(self.handle, mode))
 
+    def set_inverse(self, method: int):
+        """Gram inverse (INV_AUTO, INV_NEWTON_SCHULZ, INV_CHOLESKY)."""
+        _check(lib().rtproj_plan_set_inverse(self.handle, method))
+
     def set_refinement(self, max_steps: int, rtol: float = 0.0):
         _check(lib().rtproj_plan_set_refinement(self.handle, max_steps, rtol))
 
@@ -214,15 +222,16 @@ class Plan:
         return d
 
     def export(self):
-        """Device copies of S (m x l), R (m x m), piv (m), L (m x m)."""
+        """Device copies of S (m x l), R (m x m), piv (m) and Minv (m x m), the
+        approximation of (A A^T)^{-1} that the projections apply."""
         import torch
         dev = torch.device("cuda", torch.cuda.current_device())
         S = torch.empty((self.m, self.l), dtype=torch.float64, device=dev)
         R = torch.empty((self.m, self.m), dtype=torch.float64, device=dev)
         piv = torch.empty(self.m, dtype=torch.int32, device=dev)
-        L = torch.empty((self.m, self.m), dtype=torch.float64, device=dev)
-        _check(lib().rtproj_plan_export(self.handle, _ptr(S), self.l, _ptr(R), _ptr(piv), _ptr(L)))
-        return dict(S=S, R=R, piv=piv, L=L)
+        Mi = torch.empty((self.m, self.m), dtype=torch.float64, device=dev)
+        _check(lib().rtproj_plan_export(self.handle, _ptr(S), self.l, _ptr(R), _ptr(piv), _ptr(Mi)))
+        return dict(S=S, R=R, piv=piv, Minv=Mi)
 
     def sketch_tables(self) -> dict:
         import numpy as np

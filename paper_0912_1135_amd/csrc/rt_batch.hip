@@ -913,6 +913,8 @@ rtproj_status rtproj_batch_status(rtproj_batch b, int *per_member)
         p->info.kappa_est = d[2] > 0 ? d[3] / d[2] : INFINITY;
         p->info.rdiag_min = d[2];
         p->info.gram_cond_est = d[6] > 0 ? d[7] / d[6] : INFINITY;
+        p->info.inverse = RTPROJ_INV_CHOLESKY;
+        p->inv_used = RTPROJ_INV_CHOLESKY;
         if (per_member) per_member[i] = st;
         if (st != RTPROJ_OK) worst = st;
     }

@@ -60,9 +60,11 @@ struct GemmArgs {
     double *C; int64_t c_i, c_j; int64_t c_split;
     double alpha, beta;
     int a_lower, c_lower, ksplit;
+    int small_tiles;  // 1: 64 x 64 tiles whatever M, N (more blocks for small products)
 };
 
-// Launches GEMM with 64x64 or 128x128 tiles (chosen from M, N).
+// Launches GEMM with 64x64 or 128x128 tiles (chosen from M, N unless
+// small_tiles is set).
 hipError_t gemm_f64(const GemmArgs &g, hipStream_t stream);
 
 // Grouped GEMM: one launch over `count` problems whose GemmArgs live in
@@ -217,6 +219,20 @@ hipError_t zero_triangle_f64(double *X, int64_t ld, int m, int upper, hipStream_
 hipError_t form_tp_f64(const double *T, const int32_t *piv, int m, double *out, hipStream_t stream);
 // |R_11| and |R_mm| of the row-major R (for the rank test), written to out[0..1].
 hipError_t rdiag_ends_f64(const double *R, int64_t ldr, int m, double *out, hipStream_t stream);
+
+// Newton-Schulz inverse of the SPD Gram (row-major m x m, both triangles).
+// slots[0] = |X|_inf and slots[1] = max_i X_ii as bit patterns of
+// non-negative doubles (atomic maxima; the caller clears the two slots).
+hipError_t ns_norms_f64(const double *X, int m, unsigned long long *slots, hipStream_t stream);
+// Y = 2 a I - a^2 X with a = 1 / slots[0]: the first iterate from Y_0 = a I.
+hipError_t ns_start_f64(const double *X, int m, const unsigned long long *slots, double *Y, hipStream_t stream);
+// out = scale * sum_s part[s] + diag * I for splits partials of an m x m
+// matrix (stride apart); with bsum, block b also writes the sum of squares of
+// (out - I) over its 256 entries to bsum[b] (ceil(m^2 / 256) blocks).
+hipError_t reduce_affine_f64(const double *part, int64_t stride, int splits, int m, double *out, double scale,
+                             double diag, double *bsum, hipStream_t stream);
+// out[0] = sqrt(sum of bsum[0..nb)), summed in a fixed order (one block).
+hipError_t sum_blocks_sqrt_f64(const double *bsum, int nb, double *out, hipStream_t stream);
 
 // ---------------------------------------------------------------- apply
 // C (m x k, column-major, ldc) partials: P[s] = A(:, split s) * B(split s, :)

@@ -302,6 +302,74 @@ __global__ void form_tp_grouped(const MatGroupArgs *gs)
     form_tp_body(g.X, g.piv, g.m, g.out, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
+
+// ---------------------------------------------------------------------------
+// Newton-Schulz inverse of the Gram.  One wave per row for the norms; the
+// affine reduction also yields the Frobenius norm of (out - I) in block
+// partials, combined in a fixed order.
+
+__global__ __launch_bounds__(256) void ns_norms_kernel(const double *X, int m, unsigned long long *slots)
+{
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (row >= m) return;  // the whole wave
+    const double *x = X + (int64_t)row * m;
+    double s = 0.0;
+    for (int j = lane; j < m; j += 64) s += fabs(x[j]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) {
+        // non-negative doubles order like their bit patterns (NaN above all)
+        atomicMax(slots + 0, (unsigned long long)__double_as_longlong(s));
+        const double d = x[row];
+        atomicMax(slots + 1, (unsigned long long)__double_as_longlong(d > 0.0 ? d : 0.0));
+    }
+}
+
+__global__ void ns_start_kernel(const double *X, int m, const unsigned long long *slots, double *Y)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)m * m) return;
+    const double a = 1.0 / __longlong_as_double((long long)slots[0]);
+    const int i = (int)(e / m), j = (int)(e % m);
+    Y[e] = (i == j ? 2.0 * a : 0.0) - a * a * X[e];
+}
+
+__global__ __launch_bounds__(256) void reduce_affine_kernel(const double *part, int64_t stride, int splits, int m,
+                                                            double *out, double scale, double diag, double *bsum)
+{
+    __shared__ double red[4];
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double q = 0.0;
+    if (e < (int64_t)m * m) {
+        double s = 0.0;
+        for (int p = 0; p < splits; ++p) s += part[p * stride + e];
+        const double id = ((int)(e / m) == (int)(e % m)) ? 1.0 : 0.0;
+        const double v = scale * s + diag * id;
+        out[e] = v;
+        q = (v - id) * (v - id);
+    }
+    if (!bsum) return;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) q += __shfl_xor(q, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = q;
+    __syncthreads();
+    if (threadIdx.x == 0) bsum[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void sum_blocks_sqrt_kernel(const double *bsum, int nb, double *out)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) s += bsum[b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = __builtin_sqrt(red[0]);
+}
+
 }  // namespace
 
 hipError_t form_tp_f64(const double *T, const int32_t *piv, int m, double *out, hipStream_t stream)
@@ -412,6 +480,37 @@ hipError_t form_tp_grouped_f64(const MatGroupArgs *d, int count, int64_t max_tot
 {
     if (count <= 0 || max_total <= 0) return hipSuccess;
     hipLaunchKernelGGL(form_tp_grouped, dim3((unsigned)((max_total + 255) / 256), count), dim3(256), 0, stream, d);
+    return hipGetLastError();
+}
+
+hipError_t ns_norms_f64(const double *X, int m, unsigned long long *slots, hipStream_t stream)
+{
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(ns_norms_kernel, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, stream, X, m, slots);
+    return hipGetLastError();
+}
+
+hipError_t ns_start_f64(const double *X, int m, const unsigned long long *slots, double *Y, hipStream_t stream)
+{
+    const int64_t total = (int64_t)m * m;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(ns_start_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, X, m, slots, Y);
+    return hipGetLastError();
+}
+
+hipError_t reduce_affine_f64(const double *part, int64_t stride, int splits, int m, double *out, double scale,
+                             double diag, double *bsum, hipStream_t stream)
+{
+    const int64_t total = (int64_t)m * m;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(reduce_affine_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, part,
+                       stride, splits, m, out, scale, diag, bsum);
+    return hipGetLastError();
+}
+
+hipError_t sum_blocks_sqrt_f64(const double *bsum, int nb, double *out, hipStream_t stream)
+{
+    hipLaunchKernelGGL(sum_blocks_sqrt_kernel, dim3(1), dim3(256), 0, stream, bsum, nb, out);
     return hipGetLastError();
 }
 

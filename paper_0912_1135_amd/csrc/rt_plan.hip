@@ -81,7 +81,7 @@ void release(rtproj_plan p)
     void *bufs[] = {p->d_sign, p->d_sigma, p->d_tauinv, p->d_sel_off, p->d_sel, p->d_tw1, p->d_tw2, p->d_twh,
                     p->d_twl, p->d_tw1f, p->d_tw2f, p->d_twhf, p->d_twlf, p->d_rowscale, p->d_zbuf, p->d_S, p->d_R, p->d_Y, p->d_W, p->d_part, p->d_G, p->d_L, p->d_Tp,
                     p->d_DinvR, p->d_DinvL, p->d_piv, p->d_sync, p->d_slots, p->d_vbuf, p->d_qrcols, p->d_Yq, p->d_R0, p->d_wgargs, p->d_scal, p->d_diag,
-                    p->d_c, p->d_tmp, p->d_xhi, p->d_xlo, p->d_d, p->d_r, p->d_ph, p->d_pl, p->d_norms, p->d_err};
+                    p->d_bsum, p->d_c, p->d_tmp, p->d_xhi, p->d_xlo, p->d_d, p->d_r, p->d_ph, p->d_pl, p->d_norms, p->d_err};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
 }
@@ -170,6 +170,7 @@ rtproj_status alloc_state(rtproj_plan p)
     RT_HIP(dalloc(&p->d_G, (size_t)m * m));
     RT_HIP(dalloc(&p->d_L, (size_t)m * m));
     RT_HIP(dalloc(&p->d_Tp, (size_t)2 * m * m));
+    RT_HIP(dalloc(&p->d_bsum, (size_t)((m * m + 255) / 256)));
     const int64_t nblk = (m + NB - 1) / NB;
     RT_HIP(dalloc(&p->d_DinvR, (size_t)nblk * NB * NB));
     RT_HIP(dalloc(&p->d_DinvL, (size_t)nblk * NB * NB));
@@ -314,6 +315,95 @@ rtproj_status gram_f64(rtproj_plan p, const double *A, int64_t lda, int64_t K, d
     return RTPROJ_OK;
 }
 
+// One Newton-Schulz step on row-major m x m matrices: U = 2I - X Yc (with the
+// block sums of |U - I|^2 in d_bsum), then Yn = Yc U.  64 x 64 tiles, K split
+// so that a product spans about two blocks per compute unit.
+int ns_splits(rtproj_plan p)
+{
+    const int64_t m = p->m, tiles = ((m + 63) / 64) * ((m + 63) / 64);
+    const int64_t want = (2 * p->cu_count + tiles - 1) / tiles;
+    return (int)std::max<int64_t>(1, std::min<int64_t>({want, m / 128, (int64_t)p->syrk_splits}));
+}
+
+rtproj_status ns_product(rtproj_plan p, const double *Am, const double *Bm, double *out, double scale, double diag,
+                         double *bsum)
+{
+    const int64_t m = p->m;
+    const int ks = ns_splits(p);
+    rt::GemmArgs g{};
+    g.M = (int)m; g.N = (int)m; g.K = (int)m;
+    g.A = Am; g.a_i = m; g.a_k = 1;
+    g.B = Bm; g.b_k = m; g.b_j = 1;
+    g.C = p->d_part; g.c_i = m; g.c_j = 1; g.c_split = m * m;
+    g.alpha = 1.0; g.ksplit = ks; g.small_tiles = 1;
+    RT_HIP(rt::gemm_f64(g, p->stream));
+    RT_HIP(rt::reduce_affine_f64(p->d_part, m * m, ks, (int)m, out, scale, diag, bsum, p->stream));
+    return RTPROJ_OK;
+}
+
+// Y = X^{-1} (eq. inversion) for the SPD Gram X (d_G) by the Newton-Schulz
+// iteration Y_{k+1} = Y_k (2I - X Y_k) from Y_0 = a I, a = 1 / |X|_inf: the
+// spectrum of a X lies in (0, 1], the iterates are polynomials in X, and
+// I - X Y_{k+1} = (I - X Y_k)^2, so the error squares at every step once
+// below one.  Rounds of steps run on the stream; after each round the host
+// reads e = |I - X Y_k|_F of the last U and sizes the next round so that
+// e^(2^j) <= RT_NS_DONE (the step after such a U is the final one).  A
+// residual that stops squaring above RT_NS_DONE is the rounding floor of an
+// ill-conditioned X and is accepted; no convergence within RT_NS_MAX_IT
+// steps (singular or indefinite X, NaN) is RTPROJ_ERR_RANK.  Y alternates
+// between d_L and d_Tp's first half with U in its second half; rounds have
+// an even number of steps, so Y ends in d_L.  d_scal slots: 0 |X|_inf,
+// 1 max X_ii, 2..3 the same for Y (filled later), 4 e.
+rtproj_status gram_inverse_ns(rtproj_plan p)
+{
+    const int64_t m = p->m;
+    hipStream_t s = p->stream;
+    unsigned long long *slots = reinterpret_cast<unsigned long long *>(p->d_scal);
+    RT_HIP(rt::zero_u32(reinterpret_cast<unsigned *>(slots), 8, s));
+    RT_HIP(rt::ns_norms_f64(p->d_G, (int)m, slots, s));
+    double *Ya = p->d_L, *Yb = p->d_Tp, *U = p->d_Tp + m * m;
+    RT_HIP(rt::ns_start_f64(p->d_G, (int)m, slots, Ya, s));
+    const int nbs = (int)((m * m + 255) / 256);
+    int it = 0, round = RT_NS_FIRST;
+    double e = INFINITY, eprev = INFINITY;
+    rtproj_status st;
+    for (;;) {
+        for (int j = 0; j < round; ++j, ++it) {
+            double *Yc = (it & 1) ? Yb : Ya, *Yn = (it & 1) ? Ya : Yb;
+            if ((st = ns_product(p, p->d_G, Yc, U, -1.0, 2.0, p->d_bsum)) != RTPROJ_OK) return st;
+            if ((st = ns_product(p, Yc, U, Yn, 1.0, 0.0, nullptr)) != RTPROJ_OK) return st;
+        }
+        RT_HIP(rt::sum_blocks_sqrt_f64(p->d_bsum, nbs, p->d_scal + 4, s));
+        RT_HIP(hipMemcpyAsync(&e, p->d_scal + 4, 8, hipMemcpyDeviceToHost, s));
+        RT_HIP(hipStreamSynchronize(s));
+        p->info.inverse_iters = it;
+        p->info.inverse_resid = e;
+        if (!std::isfinite(e)) return fail(RTPROJ_ERR_RANK, "Newton-Schulz inverse of the Gram diverged");
+        if (e <= RT_NS_DONE || (e < 1e-2 && e > 0.5 * eprev)) return RTPROJ_OK;
+        if (it >= RT_NS_MAX_IT)
+            return fail(RTPROJ_ERR_RANK, "Newton-Schulz inverse of the Gram did not converge (singular Gram)");
+        int j = 6;
+        if (e < 0.5) {
+            j = 1;
+            while (std::pow(e, std::ldexp(1.0, j)) > RT_NS_DONE) ++j;
+        }
+        round = (j + 1) / 2 * 2;
+        eprev = e;
+    }
+}
+
+// Factors of M^{-1} = Pi^T R^{-1} Y R^{-T} Pi = T'^T Y T' with T' = R^{-T} Pi
+// (d_Y holds R^{-T}): T'^T and T' by form_tp into d_Tp; Y stays in d_L.  Then
+// max_i Y_ii into slot 3 for the conditioning estimate.
+rtproj_status form_factors_ns(rtproj_plan p)
+{
+    const int64_t m = p->m;
+    hipStream_t s = p->stream;
+    RT_HIP(rt::form_tp_f64(p->d_Y, p->d_piv, (int)m, p->d_Tp, s));
+    RT_HIP(rt::ns_norms_f64(p->d_L, (int)m, reinterpret_cast<unsigned long long *>(p->d_scal) + 2, s));
+    return RTPROJ_OK;
+}
+
 // First stage of the two-stage pivoted QR: S^T = Q0 R0 by shifted Cholesky
 // QR (Fukaya, Kannan, Nakatsukasa, Yamamoto, Yanagisawa 2020): with X = S^T,
 //   R1^T R1 = X^T X + s I,  s = 11 (l m + m (m+1)) 2^-53 |X|_F^2,
@@ -393,13 +483,37 @@ int auto_refine_steps(double kappa_est, int precision, bool w32, double cond_w)
     return a + b;
 }
 
-// H = T'^T (T' C) = (A A^T)^{-1} C for an m x k column-major block C: two
-// MFMA GEMMs with the K = m contraction split over blocks and reduced in a
-// fixed order.  d_Tp holds T'^T (row-major) followed by T' (row-major).
+// H = M^{-1} C = (A A^T)^{-1} C for an m x k column-major block C, applied
+// in factored form so that only the well-conditioned Y is explicit (Sec. 4,
+// steps 2-6): Newton-Schulz route H = T'^T (Y (T' C)), Cholesky route
+// H = T'^T (T' C), with d_Tp holding T'^T (row-major) followed by T'.  MFMA
+// GEMMs with the K = m contraction split over blocks and reduced in a fixed
+// order.  H must not alias C.
 rtproj_status apply_minv(rtproj_plan p, const double *C, int64_t ldc, double *H, int64_t ldh, int64_t k)
 {
     const int64_t m = p->m;
     const int splits = (int)std::max<int64_t>(1, std::min<int64_t>(p->ab_splits, (m + 63) / 64));
+    if (p->inv_used == RTPROJ_INV_NEWTON_SCHULZ) {
+        // H = T' C;  d_tmp = Y H;  H = T'^T d_tmp
+        const double *As[3] = {p->d_Tp + m * m, p->d_L, p->d_Tp};
+        const double *Bs[3] = {C, H, p->d_tmp};
+        const int64_t ldbs[3] = {ldc, ldh, m};
+        double *outs[3] = {H, p->d_tmp, H};
+        const int64_t ldos[3] = {ldh, m, ldh};
+        for (int pass = 0; pass < 3; ++pass) {
+            rt::GemmArgs g{};
+            g.M = (int)m; g.N = (int)k; g.K = (int)m;
+            g.A = As[pass]; g.a_i = m; g.a_k = 1;
+            g.B = Bs[pass]; g.b_k = 1; g.b_j = ldbs[pass];
+            g.C = p->d_ph; g.c_i = 1; g.c_j = m; g.c_split = m * k;
+            g.alpha = 1.0; g.ksplit = splits;
+            RT_HIP(rt::gemm_f64(g, p->stream));
+            // partial s is column-major m x k, i.e. row-major k x m
+            RT_HIP(rt::reduce_splits_f64(p->d_ph, m * k, splits, (int)k, (int)m, m, outs[pass], ldos[pass], 0,
+                                         p->stream));
+        }
+        return RTPROJ_OK;
+    }
     for (int pass = 0; pass < 2; ++pass) {
         rt::GemmArgs g{};
         g.M = (int)m; g.N = (int)k; g.K = (int)m;
@@ -636,6 +750,15 @@ rtproj_status rtproj_plan_set_qr(rtproj_plan p, int mode)
     return RTPROJ_OK;
 }
 
+rtproj_status rtproj_plan_set_inverse(rtproj_plan p, int method)
+{
+    if (!p) return fail(RTPROJ_ERR_INVALID_ARG, "null plan");
+    if (method < RTPROJ_INV_AUTO || method > RTPROJ_INV_CHOLESKY)
+        return fail(RTPROJ_ERR_INVALID_ARG, "unknown inverse method");
+    p->inv_method = method;
+    return RTPROJ_OK;
+}
+
 rtproj_status rtproj_plan_set_refinement(rtproj_plan p, int max_steps, double rtol)
 {
     if (!p) return fail(RTPROJ_ERR_INVALID_ARG, "null plan");
@@ -819,6 +942,33 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
     p->info.sketch_bits = (lp && !sketch64) ? 32 : 64;
     p->info.w_bits = p->w32 ? 32 : 64;
     p->info.gram_bits = !lp ? 64 : (p->precision == RTPROJ_PREC_MIXED_BF16 ? 16 : 32);
+    // 6-7. Y = X^{-1} (eq. inversion) and the form of M^{-1} the projections apply
+    p->inv_used = p->inv_method != RTPROJ_INV_AUTO ? p->inv_method
+                  : (m <= RT_NS_MAX_M ? RTPROJ_INV_NEWTON_SCHULZ : RTPROJ_INV_CHOLESKY);
+    p->info.inverse = p->inv_used;
+    p->info.inverse_iters = 0;
+    p->info.inverse_resid = 0.0;
+    if (p->inv_used == RTPROJ_INV_NEWTON_SCHULZ) {
+        {
+            StageScope sc(p, 5);
+            st = gram_inverse_ns(p);
+        }
+        if (st != RTPROJ_OK) return st;
+        {
+            StageScope sc(p, 6);
+            st = form_factors_ns(p);
+        }
+        if (st != RTPROJ_OK) return st;
+        unsigned long long sl[4];
+        RT_HIP(hipMemcpyAsync(sl, p->d_scal, 32, hipMemcpyDeviceToHost, s));
+        RT_HIP(hipStreamSynchronize(s));
+        double dx, dy;
+        std::memcpy(&dx, &sl[1], 8);
+        std::memcpy(&dy, &sl[3], 8);
+        // X_ii <= lambda_max(X) and Y_ii <= 1 / lambda_min(X)
+        p->info.gram_cond_est = (dx > 0 && dy > 0 && std::isfinite(dx * dy)) ? std::sqrt(dx * dy) : INFINITY;
+        return RTPROJ_OK;
+    }
     // 6. Cholesky X = L L^T
     {
         StageScope sc(p, 5);
@@ -918,7 +1068,7 @@ rtproj_status rtproj_plan_info(rtproj_plan p, rtproj_info *out)
     return RTPROJ_OK;
 }
 
-rtproj_status rtproj_plan_export(rtproj_plan p, double *S, int64_t lds, double *R, int32_t *piv, double *L)
+rtproj_status rtproj_plan_export(rtproj_plan p, double *S, int64_t lds, double *R, int32_t *piv, double *Minv)
 {
     if (!p) return fail(RTPROJ_ERR_INVALID_ARG, "null plan");
     if (!p->ready) return fail(RTPROJ_ERR_STATE, "plan not preconditioned");
@@ -928,7 +1078,21 @@ rtproj_status rtproj_plan_export(rtproj_plan p, double *S, int64_t lds, double *
         RT_HIP(hipMemcpy2DAsync(S, lds * 8, p->d_S, p->l * 8, p->l * 8, m, hipMemcpyDeviceToDevice, p->stream));
     if (R) RT_HIP(hipMemcpyAsync(R, p->d_R, m * m * 8, hipMemcpyDeviceToDevice, p->stream));
     if (piv) RT_HIP(hipMemcpyAsync(piv, p->d_piv, m * 4, hipMemcpyDeviceToDevice, p->stream));
-    if (L) RT_HIP(hipMemcpyAsync(L, p->d_L, m * m * 8, hipMemcpyDeviceToDevice, p->stream));
+    if (Minv) {
+        // T'^T T' (Cholesky) or T'^T (Y T') with Y T' staged in d_G, whose
+        // Gram is no longer needed (Newton-Schulz), from d_Tp = [T'^T; T']
+        const bool ns = p->inv_used == RTPROJ_INV_NEWTON_SCHULZ;
+        rt::GemmArgs g{};
+        g.M = (int)m; g.N = (int)m; g.K = (int)m;
+        g.a_i = m; g.a_k = 1; g.b_k = m; g.b_j = 1; g.c_i = m; g.c_j = 1;
+        g.alpha = 1.0; g.ksplit = 1;
+        if (ns) {
+            g.A = p->d_L; g.B = p->d_Tp + m * m; g.C = p->d_G;
+            RT_HIP(rt::gemm_f64(g, p->stream));
+        }
+        g.A = p->d_Tp; g.B = ns ? p->d_G : p->d_Tp + m * m; g.C = Minv;
+        RT_HIP(rt::gemm_f64(g, p->stream));
+    }
     RT_HIP(hipStreamSynchronize(p->stream));
     return RTPROJ_OK;
 }

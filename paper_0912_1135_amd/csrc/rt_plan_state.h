@@ -38,6 +38,16 @@ constexpr double RT_W32_KAPPA_MAX = 1e5;
 // Reduced-precision modes redo the sketch in binary64 when max/min diag of
 // the Gram's Cholesky factor exceeds this (a healthy preconditioner gives ~3).
 constexpr double RT_COND_ESCALATE = 10.0;
+// Automatic choice of the Gram inverse: Newton-Schulz (about a dozen pairs of
+// m^3 products, latency-light) up to this m, the blocked Cholesky (m^3 / 3,
+// but a chain of small diagonal steps) above it.
+constexpr int64_t RT_NS_MAX_M = 1024;
+// Newton-Schulz: iterations of the first round (Y_0 = I / |X|_inf converges
+// within it for |X|_inf / lambda_min(X) up to about 100), the residual
+// |I - X Y_k|_F below which Y_{k+1} is final, and the iteration cap.
+constexpr int RT_NS_FIRST = 12;
+constexpr double RT_NS_DONE = 1e-6;
+constexpr int RT_NS_MAX_IT = 64;
 
 // ------------------------------------------------------------ random tables
 // SplitMix64 (Steele, Lea and Flood, 2014): the state advances by the golden
@@ -142,6 +152,9 @@ struct rtproj_plan_s {
     int qr_blocks0 = 0;        // cooperative blocks for the m x m QRCP of R0
     int qr_reg_l = 0, qr_reg_m = 0;  // blocks of the register-resident form (0: not applicable)
     int qr_mode = RTPROJ_QR_AUTO;
+    int inv_method = RTPROJ_INV_AUTO;  // inverse of the Gram requested
+    int inv_used = 0;          // RTPROJ_INV_NEWTON_SCHULZ or RTPROJ_INV_CHOLESKY, last precondition
+    double *d_bsum = nullptr;  // block partial sums of squares (ceil(m^2 / 256))
     double *d_Yq = nullptr;    // two-stage: the m x l iterate of the Cholesky QR
     double *d_R0 = nullptr;    // two-stage: R0^T (lower, row-major m x m)
     rt::QrcpWgArgs *d_wgargs = nullptr;

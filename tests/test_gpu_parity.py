@@ -349,3 +349,68 @@ def test_projection_matches_oracle_all_qr_modes(rt, mode, m, n, l, kappa, k, see
     ez, ey, ex = errors(B, Z.cpu().numpy(), Y.cpu().numpy(), X.cpu().numpy(), Zr, Yr, Xr)
     assert ez <= TOL and ey <= TOL and ex <= TOL, (ez, ey, ex)
     plan.close()
+
+
+# ------------------------------------------------------- inverse of the Gram
+
+@pytest.mark.parametrize("method", ["newton_schulz", "cholesky"])
+@pytest.mark.parametrize("m,n,l,kappa,k,seed", [
+    (1, 50, 1, 1e0, 2, 41),            # 1 x 1 Gram
+    (12, 12, 12, 1e3, 2, 42),          # square A, l = m
+    (64, 4096, 68, 1e6, 3, 43),        # l = m + 4: a poorer preconditioner, more steps
+    (300, 9000, 1200, 1e8, 4, 44),     # ragged 64-tiles, K split in two
+    (600, 8192, 2400, 1e10, 5, 45),    # K split in four
+])
+def test_projection_matches_oracle_both_inverses(rt, method, m, n, l, kappa, k, seed):
+    code = {"newton_schulz": rt.INV_NEWTON_SCHULZ, "cholesky": rt.INV_CHOLESKY}[method]
+    A = synth.make_problem(m, n, kappa, seed)
+    B = synth.make_rhs(n, k, seed)
+    plan = rt.Plan(m, n, l, seed)
+    plan.set_inverse(code)
+    plan.precondition(torch.from_numpy(A).to(dev()))
+    Z, Y, X = plan.project_all(torch.from_numpy(B).to(dev()))
+    torch.cuda.synchronize()
+    info = plan.info()
+    assert info["inverse"] == code
+    if code == rt.INV_NEWTON_SCHULZ:
+        # rounds have an even number of steps; the last measured residual is
+        # past the quadratic phase (or at the rounding floor)
+        assert info["inverse_iters"] >= 2 and info["inverse_iters"] % 2 == 0
+        assert info["inverse_resid"] <= 1e-2
+    else:
+        assert info["inverse_iters"] == 0
+    assert 1.0 <= info["gram_cond_est"] < 100
+    Zr, Yr, Xr, _ = oracle.project(A, B.T)
+    ez, ey, ex = errors(B, Z.cpu().numpy(), Y.cpu().numpy(), X.cpu().numpy(), Zr, Yr, Xr)
+    assert ez <= TOL and ey <= TOL and ex <= TOL, (method, ez, ey, ex, info["refine_steps"])
+    plan.close()
+
+
+@pytest.mark.parametrize("method", ["newton_schulz", "cholesky"])
+def test_exported_minv_inverts_the_normal_matrix(rt, method):
+    """M^{-1} = (P^*)^{-1} Y P^{-1} is (A A^T)^{-1} up to rounding for a well
+    conditioned A (eq. basic_precond with Y = X^{-1}); both routes agree."""
+    code = {"newton_schulz": rt.INV_NEWTON_SCHULZ, "cholesky": rt.INV_CHOLESKY}[method]
+    m, n, l, seed = 200, 6000, 800, 46
+    A = synth.make_problem(m, n, 1e2, seed)
+    plan = rt.Plan(m, n, l, seed)
+    plan.set_inverse(code)
+    plan.precondition(torch.from_numpy(A).to(dev()))
+    Mi = plan.export()["Minv"].cpu().numpy()
+    N = A @ A.T
+    E = Mi @ N - np.eye(m)
+    assert np.linalg.norm(E, 2) <= 1e-10, np.linalg.norm(E, 2)
+    assert np.max(np.abs(Mi - Mi.T)) <= 1e-8 * np.max(np.abs(Mi))
+    plan.close()
+
+
+def test_inverse_method_argument_checks(rt):
+    plan = rt.Plan(8, 100, 32, 0)
+    with pytest.raises(rt.RtprojError) as e:
+        plan.set_inverse(3)
+    assert e.value.status == 1
+    plan.set_inverse(rt.INV_AUTO)
+    A = synth.make_problem(8, 100, 10.0, 1)
+    plan.precondition(torch.from_numpy(A).to(dev()))
+    assert plan.info()["inverse"] == rt.INV_NEWTON_SCHULZ   # m <= 1024
+    plan.close()
