@@ -104,6 +104,8 @@ rt::GemmShape shape_of(const std::vector<rt::GemmArgs> &v)
     s.a_kc = v.empty() ? 1 : (v[0].a_k == 1);
     s.b_kc = v.empty() ? 1 : (v[0].b_k == 1);
     s.c_lower = v.empty() ? 0 : v[0].c_lower;
+    // the members of one recorded product all gather B's rows or none do
+    s.b_gather = v.empty() ? 0 : (v[0].b_gather != nullptr);
     for (const auto &g : v) {
         s.M = std::max(s.M, g.M);
         s.N = std::max(s.N, g.N);

@@ -75,6 +75,7 @@ hipError_t gemm_f64(const GemmArgs &g, hipStream_t stream);
 struct GemmShape {
     int M, N, ksplit;
     int a_kc, b_kc, c_lower;
+    int b_gather;  // 1 when the members gather B's rows (all or none do)
 };
 hipError_t gemm_f64_grouped(const GemmArgs *d_args, int count, const GemmShape &shape, hipStream_t stream);
 struct ReduceGroupArgs {

@@ -25,10 +25,27 @@ struct TileLayout {
     __device__ static int at(int mn, int k) { return KCONTIG ? mn * (KC + 1) + k : k * (T + 16) + mn; }
 };
 
+// Chunks of K in flight: the loads of chunk t + RING - 1 are issued before
+// chunk t is multiplied, so RING - 1 chunk products hide a load's latency.
+// Two slots (one chunk ahead, LDS double buffered): deeper rings defeat the
+// compiler's memory counters at the loop back edge (it then waits for every
+// load before issuing the next), so small products get their latency hiding
+// from more resident blocks instead (more K splits).
+template <int BM>
+struct Ring { static constexpr int value = 2; };
+
 // One BM x BN output tile (bx, by) of split bz.  Tiles outside the problem
 // (possible in grouped launches, whose grid covers the largest member)
 // return at once; the whole block takes the same branch.
-template <int BM, int BN, bool A_KC, bool B_KC>
+//
+// Operand chunks travel global -> registers (a ring of RING slots) -> LDS
+// (double buffered).  Every load is issued unconditionally from a clamped
+// address and zeroed by a select when out of range, so the loads stay
+// straight-line and the compiler's counters let RING - 1 chunks remain in
+// flight.  A row gather of B (along K) reads its indices one chunk ahead of
+// the data they address, in a ring of their own; a row gather of A (along M)
+// is resolved once.
+template <int BM, int BN, bool A_KC, bool B_KC, bool GB>
 __device__ __forceinline__ void gemm_f64_tile(const GemmArgs &g, int bx, int by, int bz)
 {
     using LA = TileLayout<BM, A_KC>;
@@ -36,7 +53,8 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmArgs &g, int bx, int by,
     __shared__ double As[2][LA::size];
     __shared__ double Bs[2][LB::size];
     constexpr int TM = BM / 32, TN = BN / 32;
-    constexpr int NA = BM * KC / 256, NB = BN * KC / 256;  // elements per thread
+    constexpr int NA = BM * KC / 256, NB = BN * KC / 256;  // elements per thread and chunk
+    constexpr int R = Ring<BM>::value;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
 
@@ -61,43 +79,70 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmArgs &g, int bx, int by,
         kend = min(g.K, kbeg + ks);
     }
     if (g.a_lower) kend = min(kend, i0 + BM);
+    const int nch = kend > kbeg ? (kend - kbeg + KC - 1) / KC : 0;
 
-    // element e of this thread's share: (mn, k) of the tile, consecutive
-    // threads along the operand's contiguous dimension
-    auto a_coord = [&](int e, int &ii, int &kk) {
+    // per-element coordinates (consecutive threads along the operand's
+    // contiguous dimension) and the loop-invariant parts of the addresses
+    int a_ii[NA], a_kk[NA], b_jj[NB], b_kk[NB];
+    int64_t a_row[NA], b_col[NB];
+    bool a_in[NA], b_in[NB];
+#pragma unroll
+    for (int e = 0; e < NA; ++e) {
         const int x = tid + 256 * e;
-        if (A_KC) { ii = x / KC; kk = x % KC; } else { ii = x % BM; kk = x / BM; }
-    };
-    auto b_coord = [&](int e, int &jj, int &kk) {
+        a_ii[e] = A_KC ? x / KC : x % BM;
+        a_kk[e] = A_KC ? x % KC : x / BM;
+        const int i = i0 + a_ii[e];
+        a_in[e] = i < g.M;
+        const int ic = a_in[e] ? i : g.M - 1;
+        a_row[e] = (g.a_gather ? (int64_t)g.a_gather[ic] : (int64_t)ic) * g.a_i;
+    }
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
         const int x = tid + 256 * e;
-        if (B_KC) { jj = x / KC; kk = x % KC; } else { jj = x % BN; kk = x / BN; }
+        b_jj[e] = B_KC ? x / KC : x % BN;
+        b_kk[e] = B_KC ? x % KC : x / BN;
+        const int j = j0 + b_jj[e];
+        b_in[e] = j < g.N;
+        b_col[e] = (int64_t)(b_in[e] ? j : g.N - 1) * g.b_j;
+    }
+
+    double ra[R][NA], rb[R][NB];
+    int gi[R][NB];
+    (void)gi;
+    auto load_idx = [&](int s, int c) {
+        if constexpr (GB) {
+#pragma unroll
+            for (int e = 0; e < NB; ++e) {
+                const int k = kbeg + c * KC + b_kk[e];
+                gi[s][e] = g.b_gather[k < kend ? k : kend - 1];
+            }
+        }
     };
-    double ra[NA], rb[NB];
-    auto load = [&](int k0) {
+    auto load = [&](int s, int c) {
+        const int k0 = kbeg + c * KC;
 #pragma unroll
         for (int e = 0; e < NA; ++e) {
-            int ii, kk;
-            a_coord(e, ii, kk);
-            const int i = i0 + ii, k = k0 + kk;
-            double v = 0.0;
-            if (i < g.M && k < kend && !(g.a_lower && k > i)) {
-                const int64_t gi = g.a_gather ? (int64_t)g.a_gather[i] : (int64_t)i;
-                v = g.A[gi * g.a_i + (int64_t)k * g.a_k];
-            }
-            ra[e] = v;
+            const int k = k0 + a_kk[e];
+            const bool ok = a_in[e] && k < kend && !(g.a_lower && k > i0 + a_ii[e]);
+            const double v = g.A[a_row[e] + (int64_t)(k < kend ? k : kend - 1) * g.a_k];
+            ra[s][e] = ok ? v : 0.0;
         }
 #pragma unroll
         for (int e = 0; e < NB; ++e) {
-            int jj, kk;
-            b_coord(e, jj, kk);
-            const int j = j0 + jj, k = k0 + kk;
-            double v = 0.0;
-            if (j < g.N && k < kend) {
-                const int64_t gk = g.b_gather ? (int64_t)g.b_gather[k] : (int64_t)k;
-                v = g.B[gk * g.b_k + (int64_t)j * g.b_j];
-            }
-            rb[e] = v;
+            const int k = k0 + b_kk[e];
+            const bool ok = b_in[e] && k < kend;
+            int64_t kr;
+            if constexpr (GB) kr = gi[s][e];
+            else kr = k < kend ? k : kend - 1;
+            const double v = g.B[kr * g.b_k + b_col[e]];
+            rb[s][e] = ok ? v : 0.0;
         }
+    };
+    auto stage = [&](int s, int buf) {
+#pragma unroll
+        for (int e = 0; e < NA; ++e) As[buf][LA::at(a_ii[e], a_kk[e])] = ra[s][e];
+#pragma unroll
+        for (int e = 0; e < NB; ++e) Bs[buf][LB::at(b_jj[e], b_kk[e])] = rb[s][e];
     };
 
     double4v acc[TM][TN];
@@ -106,37 +151,42 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmArgs &g, int bx, int by,
 #pragma unroll
         for (int b = 0; b < TN; ++b) acc[a][b] = double4v{0.0, 0.0, 0.0, 0.0};
 
-    int buf = 0;
-    if (kbeg < kend) load(kbeg);
-    for (int k0 = kbeg; k0 < kend; k0 += KC) {
+    if (nch > 0) {
+        // prologue: indices of chunks 0..R-1, data of chunks 0..R-2, chunk 0 staged
 #pragma unroll
-        for (int e = 0; e < NA; ++e) {
-            int ii, kk;
-            a_coord(e, ii, kk);
-            As[buf][LA::at(ii, kk)] = ra[e];
-        }
+        for (int s = 0; s < R; ++s) load_idx(s, s);
 #pragma unroll
-        for (int e = 0; e < NB; ++e) {
-            int jj, kk;
-            b_coord(e, jj, kk);
-            Bs[buf][LB::at(jj, kk)] = rb[e];
-        }
+        for (int s = 0; s < R - 1; ++s) load(s, s);
+        stage(0, 0);
         __syncthreads();
-        if (k0 + KC < kend) load(k0 + KC);  // next chunk in flight during the MFMAs
+    }
+    for (int t0 = 0; t0 < nch; t0 += R) {
 #pragma unroll
-        for (int kk = 0; kk < KC; kk += 4) {
-            double av[TM], bv[TN];
+        for (int u = 0; u < R; ++u) {
+            const int t = t0 + u;
+            if (t >= nch) break;
+            // indices of chunk t + R (slot u held chunk t's), data of chunk t + R - 1
+            load_idx(u, t + R);
+            load((u + R - 1) % R, t + R - 1);
+            const int buf = t & 1;
 #pragma unroll
-            for (int a = 0; a < TM; ++a) av[a] = As[buf][LA::at(wm * (BM / 2) + a * 16 + (lane & 15), kk + (lane >> 4))];
+            for (int kk = 0; kk < KC; kk += 4) {
+                double av[TM], bv[TN];
 #pragma unroll
-            for (int b = 0; b < TN; ++b) bv[b] = Bs[buf][LB::at(wn * (BN / 2) + b * 16 + (lane & 15), kk + (lane >> 4))];
-#pragma unroll
-            for (int a = 0; a < TM; ++a)
+                for (int a = 0; a < TM; ++a)
+                    av[a] = As[buf][LA::at(wm * (BM / 2) + a * 16 + (lane & 15), kk + (lane >> 4))];
 #pragma unroll
                 for (int b = 0; b < TN; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+                    bv[b] = Bs[buf][LB::at(wn * (BN / 2) + b * 16 + (lane & 15), kk + (lane >> 4))];
+#pragma unroll
+                for (int a = 0; a < TM; ++a)
+#pragma unroll
+                    for (int b = 0; b < TN; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+            }
+            if (t + 1 < nch) stage((u + 1) % R, buf ^ 1);
+            __syncthreads();
         }
-        buf ^= 1;
     }
 
     double *C = g.C + (g.ksplit > 1 ? (int64_t)bz * g.c_split : 0);
@@ -158,33 +208,39 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmArgs &g, int bx, int by,
             }
 }
 
-template <int BM, int BN, bool A_KC, bool B_KC>
+template <int BM, int BN, bool A_KC, bool B_KC, bool GB>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g)
 {
-    gemm_f64_tile<BM, BN, A_KC, B_KC>(g, blockIdx.x, blockIdx.y, blockIdx.z);
+    gemm_f64_tile<BM, BN, A_KC, B_KC, GB>(g, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // Grouped launch: member blockIdx.z / ksmax, split blockIdx.z % ksmax.
-template <int BM, int BN, bool A_KC, bool B_KC>
+template <int BM, int BN, bool A_KC, bool B_KC, bool GB>
 __global__ __launch_bounds__(256) void gemm_f64_grouped_kernel(const GemmArgs *gs, int ksmax)
 {
     const GemmArgs g = gs[blockIdx.z / ksmax];
-    gemm_f64_tile<BM, BN, A_KC, B_KC>(g, blockIdx.x, blockIdx.y, blockIdx.z % ksmax);
+    gemm_f64_tile<BM, BN, A_KC, B_KC, GB>(g, blockIdx.x, blockIdx.y, blockIdx.z % ksmax);
+}
+
+template <int BM, int BN, bool GB>
+hipError_t launch_tile_g(const GemmArgs &g, dim3 grid, hipStream_t s)
+{
+    const bool akc = (g.a_k == 1), bkc = (g.b_k == 1);
+    if (akc && bkc) hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, true, true, GB>), grid, dim3(256), 0, s, g);
+    else if (akc) hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, true, false, GB>), grid, dim3(256), 0, s, g);
+    else if (bkc) hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, false, true, GB>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, false, false, GB>), grid, dim3(256), 0, s, g);
+    return hipGetLastError();
 }
 
 template <int BM, int BN>
 hipError_t launch_tile(const GemmArgs &g, hipStream_t s)
 {
-    dim3 grid, block(256);
+    dim3 grid;
     const int gm = (g.M + BM - 1) / BM, gn = (g.N + BN - 1) / BN;
     if (g.c_lower) grid = dim3(gm * (gm + 1) / 2, 1, g.ksplit > 1 ? g.ksplit : 1);
     else grid = dim3(gn, gm, g.ksplit > 1 ? g.ksplit : 1);
-    const bool akc = (g.a_k == 1), bkc = (g.b_k == 1);
-    if (akc && bkc) hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, true, true>), grid, block, 0, s, g);
-    else if (akc) hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, true, false>), grid, block, 0, s, g);
-    else if (bkc) hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, false, true>), grid, block, 0, s, g);
-    else hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, false, false>), grid, block, 0, s, g);
-    return hipGetLastError();
+    return g.b_gather ? launch_tile_g<BM, BN, true>(g, grid, s) : launch_tile_g<BM, BN, false>(g, grid, s);
 }
 
 __device__ __forceinline__ void reduce_splits_body(const double *part, int64_t stride, int splits, int M, int N,
@@ -221,6 +277,21 @@ hipError_t gemm_f64(const GemmArgs &g, hipStream_t stream)
     return launch_tile<64, 64>(g, stream);
 }
 
+template <bool GB>
+void launch_grouped(const GemmArgs *d_args, const GemmShape &shape, dim3 grid, int ks, hipStream_t stream)
+{
+    constexpr int BM = 64, BN = 64;
+    if (shape.a_kc && shape.b_kc)
+        hipLaunchKernelGGL((gemm_f64_grouped_kernel<BM, BN, true, true, GB>), grid, dim3(256), 0, stream, d_args, ks);
+    else if (shape.a_kc)
+        hipLaunchKernelGGL((gemm_f64_grouped_kernel<BM, BN, true, false, GB>), grid, dim3(256), 0, stream, d_args, ks);
+    else if (shape.b_kc)
+        hipLaunchKernelGGL((gemm_f64_grouped_kernel<BM, BN, false, true, GB>), grid, dim3(256), 0, stream, d_args, ks);
+    else
+        hipLaunchKernelGGL((gemm_f64_grouped_kernel<BM, BN, false, false, GB>), grid, dim3(256), 0, stream, d_args,
+                           ks);
+}
+
 hipError_t gemm_f64_grouped(const GemmArgs *d_args, int count, const GemmShape &shape, hipStream_t stream)
 {
     if (count <= 0 || shape.M <= 0 || shape.N <= 0) return hipSuccess;
@@ -228,14 +299,8 @@ hipError_t gemm_f64_grouped(const GemmArgs *d_args, int count, const GemmShape &
     const int gm = (shape.M + BM - 1) / BM, gn = (shape.N + BN - 1) / BN;
     const int ks = shape.ksplit > 1 ? shape.ksplit : 1;
     dim3 grid = shape.c_lower ? dim3(gm * (gm + 1) / 2, 1, count * ks) : dim3(gn, gm, count * ks);
-    if (shape.a_kc && shape.b_kc)
-        hipLaunchKernelGGL((gemm_f64_grouped_kernel<BM, BN, true, true>), grid, dim3(256), 0, stream, d_args, ks);
-    else if (shape.a_kc)
-        hipLaunchKernelGGL((gemm_f64_grouped_kernel<BM, BN, true, false>), grid, dim3(256), 0, stream, d_args, ks);
-    else if (shape.b_kc)
-        hipLaunchKernelGGL((gemm_f64_grouped_kernel<BM, BN, false, true>), grid, dim3(256), 0, stream, d_args, ks);
-    else
-        hipLaunchKernelGGL((gemm_f64_grouped_kernel<BM, BN, false, false>), grid, dim3(256), 0, stream, d_args, ks);
+    if (shape.b_gather) launch_grouped<true>(d_args, shape, grid, ks, stream);
+    else launch_grouped<false>(d_args, shape, grid, ks, stream);
     return hipGetLastError();
 }
 

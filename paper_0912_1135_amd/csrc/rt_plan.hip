@@ -317,12 +317,13 @@ rtproj_status gram_f64(rtproj_plan p, const double *A, int64_t lda, int64_t K, d
 
 // One Newton-Schulz step on row-major m x m matrices: U = 2I - X Yc (with the
 // block sums of |U - I|^2 in d_bsum), then Yn = Yc U.  64 x 64 tiles, K split
-// so that a product spans about two blocks per compute unit.
+// so that a product spans about four blocks per compute unit (chunks of 64
+// or more), whose interleaving hides the load latency.
 int ns_splits(rtproj_plan p)
 {
     const int64_t m = p->m, tiles = ((m + 63) / 64) * ((m + 63) / 64);
     const int64_t want = (2 * p->cu_count + tiles - 1) / tiles;
-    return (int)std::max<int64_t>(1, std::min<int64_t>({want, m / 128, (int64_t)p->syrk_splits}));
+    return (int)std::max<int64_t>(1, std::min<int64_t>({2 * want, m / 64, (int64_t)p->syrk_splits}));
 }
 
 rtproj_status ns_product(rtproj_plan p, const double *Am, const double *Bm, double *out, double scale, double diag,
