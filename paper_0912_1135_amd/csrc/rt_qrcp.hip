@@ -229,8 +229,9 @@ __global__ __launch_bounds__(QR_THREADS) void qrcp_kernel(const double *S, int64
 // thread reads the reflector's entries for its rows once and applies them to
 // all NC columns.  A step is a chain of dependent latencies (post, barrier,
 // candidate headers, pivot column), so everything between them is kept short:
-//   - reductions run inside the wave on DPP lane moves (quad permutes, row
-//     mirrors, row broadcasts) and lane reads, one LDS exchange per block;
+//   - the column sums (dot products, trailing norms) transpose the columns
+//     across lanes while adding them (DPP quad permutes, row mirror and
+//     rotation), with one LDS exchange per block;
 //   - the pivot choice and the broadcast of sums stay in registers;
 //   - posted data (headers and candidate columns) is written and read with
 //     device-scope accesses, which are coherent across the L2 slices of the
@@ -273,22 +274,6 @@ constexpr int DPP_QUAD_XOR1 = 0xB1;  // quad_perm [1,0,3,2]
 constexpr int DPP_QUAD_XOR2 = 0x4E;  // quad_perm [2,3,0,1]
 constexpr int DPP_ROW_MIRROR = 0x140;
 constexpr int DPP_ROW_HALF_MIRROR = 0x141;
-constexpr int DPP_ROW_BCAST15 = 0x142;
-constexpr int DPP_ROW_BCAST31 = 0x143;
-
-// Sum over the wave, returned uniformly.  Butterflies inside each 16-lane row
-// leave the row sum in every lane of the row; two row broadcasts then
-// accumulate rows 0..3 into lane 63.
-__device__ __forceinline__ double wave_total(double v)
-{
-    v += dpp_d<DPP_QUAD_XOR1>(v);
-    v += dpp_d<DPP_QUAD_XOR2>(v);
-    v += dpp_d<DPP_ROW_HALF_MIRROR>(v);
-    v += dpp_d<DPP_ROW_MIRROR>(v);
-    v += dpp_d<DPP_ROW_BCAST15, 0xA>(v);
-    v += dpp_d<DPP_ROW_BCAST31, 0xC>(v);
-    return readlane_d(v, 63);
-}
 
 // Candidate order: larger norm^2 first, then the lower column index.  Every
 // candidate carries a norm >= -1 (never NaN), so the order is total.
@@ -341,24 +326,66 @@ __device__ __forceinline__ void wait_mem()
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-// Block-wide column sums of the per-thread partials p[0..NC): wave totals go
-// through LDS (red, NC x RQ_W), then lane c of every wave adds column c's
-// wave totals in a fixed order.  Returns lane c's column sum (0 for c >= NC);
-// identical in every wave.  One block barrier.
+constexpr int DPP_ROW_ROR8 = 0x128;  // row_ror:8, i.e. lane i <-> i ^ 8 within a row
+
+// One level of the transposing reduction: the partner differs from this lane
+// in bit BIT.  With N > 1 values the lane keeps the half selected by that bit
+// and adds the partner's copy of the same half (the partner sends the half it
+// does not keep); with one value left it adds the partner's, and only the lane
+// with the bit clear remains the representative of the duplicate pair.
+template <int CTRL, int BIT, int N, int NC>
+__device__ __forceinline__ void red_level(double (&v)[NC], int lane, int &off, bool &rep)
+{
+    const bool kb = (lane >> BIT) & 1;
+    if constexpr (N > 1) {
+        constexpr int H = N / 2;
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            const double mine = kb ? v[j + H] : v[j];
+            const double other = kb ? v[j] : v[j + H];
+            v[j] = mine + dpp_d<CTRL>(other);
+        }
+        if (kb) off += H;
+    } else {
+        v[0] += dpp_d<CTRL>(v[0]);
+        if (kb) rep = false;
+    }
+}
+
+// Block-wide column sums of the per-thread partials p[0..NC) (NC a power of
+// two).  Inside each 16-lane row the NC values are transposed while being
+// added: four DPP levels (partners i <-> 7-i within 8 lanes, i <-> i^2,
+// i <-> i^1, i <-> i^8) halve the values per lane while any remain, so a lane
+// ends with the row sums of max(1, NC/16) consecutive columns starting at
+// `off` (set by its lane bits).  The representatives write these row sums to
+// LDS (red: NC x 4 RQ_W, one slot per wave and row); after one block barrier
+// lane c of every wave adds column c's 4 RQ_W partials in a fixed order.
+// Returns that sum in lane c (0 for c >= NC), identical in every wave.
 template <int NC>
-__device__ __forceinline__ double block_col_sums(const double (&p)[NC], double (*red)[RQ_W])
+__device__ __forceinline__ double block_col_sums(const double (&p)[NC], double (*red)[4 * RQ_W])
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double v[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        const double t = wave_total(p[c]);
-        if (lane == 0) red[c][wave] = t;
-    }
+    for (int c = 0; c < NC; ++c) v[c] = p[c];
+    int off = 0;
+    bool rep = true;
+    red_level<DPP_ROW_HALF_MIRROR, 2, NC, NC>(v, lane, off, rep);
+    red_level<DPP_QUAD_XOR2, 1, (NC > 2 ? NC / 2 : 1), NC>(v, lane, off, rep);
+    red_level<DPP_QUAD_XOR1, 0, (NC > 4 ? NC / 4 : 1), NC>(v, lane, off, rep);
+    red_level<DPP_ROW_ROR8, 3, (NC > 8 ? NC / 8 : 1), NC>(v, lane, off, rep);
+    constexpr int NF = NC > 16 ? NC / 16 : 1;
+    if (rep)
+#pragma unroll
+        for (int j = 0; j < NF; ++j) red[off + j][wave * 4 + (lane >> 4)] = v[j];
     __syncthreads();
     double s = 0.0;
-    if (lane < NC)
+    if (lane < NC) {
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int w = 0; w < RQ_W; ++w) s += red[lane][w];
+        for (int q = 0; q < 4 * RQ_W; ++q) a[q & 3] += red[lane][q];
+        s = (a[0] + a[1]) + (a[2] + a[3]);
+    }
     return s;
 }
 
@@ -381,8 +408,8 @@ template <int NC, int RPT>
 __global__ __launch_bounds__(RQ_T) void qrcp_reg_kernel(const double *S, int64_t lds, int rows, int cols, double *R,
                                                         int32_t *piv, QrcpWork w, int G)
 {
-    static_assert(NC <= 32, "done mask and lane-per-column sums");
-    __shared__ double red[2][NC][RQ_W];
+    static_assert(NC <= 32 && (NC & (NC - 1)) == 0, "done mask, lane-per-column sums, power of two");
+    __shared__ double red[2][NC][4 * RQ_W];
     __shared__ double s_pn;
     __shared__ int s_p, s_abort;
     const int g = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
