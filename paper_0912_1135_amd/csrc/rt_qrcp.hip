@@ -358,11 +358,12 @@ __device__ __forceinline__ void red_level(double (&v)[NC], int lane, int &off, b
 // i <-> i^1, i <-> i^8) halve the values per lane while any remain, so a lane
 // ends with the row sums of max(1, NC/16) consecutive columns starting at
 // `off` (set by its lane bits).  The representatives write these row sums to
-// LDS (red: NC x 4 RQ_W, one slot per wave and row); after one block barrier
+// LDS (red: 4 RQ_W x NC, one row per wave and lane row, columns contiguous so
+// that the lanes reading them hit distinct banks); after one block barrier
 // lane c of every wave adds column c's 4 RQ_W partials in a fixed order.
 // Returns that sum in lane c (0 for c >= NC), identical in every wave.
 template <int NC>
-__device__ __forceinline__ double block_col_sums(const double (&p)[NC], double (*red)[4 * RQ_W])
+__device__ __forceinline__ double block_col_sums(const double (&p)[NC], double (*red)[NC])
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double v[NC];
@@ -377,13 +378,13 @@ __device__ __forceinline__ double block_col_sums(const double (&p)[NC], double (
     constexpr int NF = NC > 16 ? NC / 16 : 1;
     if (rep)
 #pragma unroll
-        for (int j = 0; j < NF; ++j) red[off + j][wave * 4 + (lane >> 4)] = v[j];
+        for (int j = 0; j < NF; ++j) red[wave * 4 + (lane >> 4)][off + j] = v[j];
     __syncthreads();
     double s = 0.0;
     if (lane < NC) {
         double a[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int q = 0; q < 4 * RQ_W; ++q) a[q & 3] += red[lane][q];
+        for (int q = 0; q < 4 * RQ_W; ++q) a[q & 3] += red[q][lane];
         s = (a[0] + a[1]) + (a[2] + a[3]);
     }
     return s;
@@ -409,7 +410,7 @@ __global__ __launch_bounds__(RQ_T) void qrcp_reg_kernel(const double *S, int64_t
                                                         int32_t *piv, QrcpWork w, int G)
 {
     static_assert(NC <= 32 && (NC & (NC - 1)) == 0, "done mask, lane-per-column sums, power of two");
-    __shared__ double red[2][NC][4 * RQ_W];
+    __shared__ double red[2][4 * RQ_W][NC];
     __shared__ double s_pn;
     __shared__ int s_p, s_abort;
     const int g = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
