@@ -349,8 +349,8 @@ rtproj_status ns_product(rtproj_plan p, const double *Am, const double *Bm, doub
 // below one.  Rounds of steps run on the stream; after each round the host
 // reads e = |I - X Y_k|_F of the last U and sizes the next round so that
 // e^(2^j) <= RT_NS_DONE (the step after such a U is the final one).  A
-// residual that stops squaring above RT_NS_DONE is the rounding floor of an
-// ill-conditioned X and is accepted; no convergence within RT_NS_MAX_IT
+// residual that stops squaring between RT_NS_DONE and RT_NS_FLOOR is the
+// rounding floor of an ill-conditioned X and is accepted; no convergence within RT_NS_MAX_IT
 // steps (singular or indefinite X, NaN) is RTPROJ_ERR_RANK.  Y alternates
 // between d_L and d_Tp's first half with U in its second half; rounds have
 // an even number of steps, so Y ends in d_L.  d_scal slots: 0 |X|_inf,
@@ -380,7 +380,7 @@ rtproj_status gram_inverse_ns(rtproj_plan p)
         p->info.inverse_iters = it;
         p->info.inverse_resid = e;
         if (!std::isfinite(e)) return fail(RTPROJ_ERR_RANK, "Newton-Schulz inverse of the Gram diverged");
-        if (e <= RT_NS_DONE || (e < 1e-2 && e > 0.5 * eprev)) return RTPROJ_OK;
+        if (e <= RT_NS_DONE || (e < RT_NS_FLOOR && e > 0.5 * eprev)) return RTPROJ_OK;
         if (it >= RT_NS_MAX_IT)
             return fail(RTPROJ_ERR_RANK, "Newton-Schulz inverse of the Gram did not converge (singular Gram)");
         int j = 6;

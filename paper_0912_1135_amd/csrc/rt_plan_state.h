@@ -44,9 +44,14 @@ constexpr double RT_COND_ESCALATE = 10.0;
 constexpr int64_t RT_NS_MAX_M = 1024;
 // Newton-Schulz: iterations of the first round (Y_0 = I / |X|_inf converges
 // within it for |X|_inf / lambda_min(X) up to about 100), the residual
-// |I - X Y_k|_F below which Y_{k+1} is final, and the iteration cap.
+// |I - X Y_k|_F below which Y_{k+1} is final, the largest residual accepted
+// as a rounding floor once it stops squaring, and the iteration cap.  The
+// iterates are used as computed, never symmetrised: I - X Y_{k+1} =
+// (I - X Y_k)^2 holds for any Y_k, while a symmetrised product drifts when the
+// computed Y_k does not commute with X.
 constexpr int RT_NS_FIRST = 12;
 constexpr double RT_NS_DONE = 1e-6;
+constexpr double RT_NS_FLOOR = 1e-4;
 constexpr int RT_NS_MAX_IT = 64;
 
 // ------------------------------------------------------------ random tables

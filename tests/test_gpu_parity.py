@@ -358,6 +358,7 @@ def test_projection_matches_oracle_all_qr_modes(rt, mode, m, n, l, kappa, k, see
     (1, 50, 1, 1e0, 2, 41),            # 1 x 1 Gram
     (12, 12, 12, 1e3, 2, 42),          # square A, l = m
     (64, 4096, 68, 1e6, 3, 43),        # l = m + 4: a poorer preconditioner, more steps
+    (33, 500, 33, 1e6, 2, 6),          # l = m: cond(X) near 3e3
     (300, 9000, 1200, 1e8, 4, 44),     # ragged 64-tiles, K split in two
     (600, 8192, 2400, 1e10, 5, 45),    # K split in four
 ])
@@ -376,7 +377,7 @@ def test_projection_matches_oracle_both_inverses(rt, method, m, n, l, kappa, k, 
         # rounds have an even number of steps; the last measured residual is
         # past the quadratic phase (or at the rounding floor)
         assert info["inverse_iters"] >= 2 and info["inverse_iters"] % 2 == 0
-        assert info["inverse_resid"] <= 1e-2
+        assert info["inverse_resid"] <= 1e-4
     else:
         assert info["inverse_iters"] == 0
     assert 1.0 <= info["gram_cond_est"] < 100
