@@ -102,7 +102,7 @@ def stage_work(name, dims, prec="fp64", w_bits=64, inv=(2, 0)):
 
 # stage -> (kernel name in the profiler's trace, source file of that kernel)
 STAGE_KERNELS = {
-    "qrcp": ("qrcp_kernel", "paper_0912_1135_amd/csrc/rt_qrcp.hip"),
+    "qrcp": ("qrcp_reg_kernel", "paper_0912_1135_amd/csrc/rt_qrcp.hip"),
     "sketch": ("sketch_pass", "paper_0912_1135_amd/csrc/rt_sketch.hip"),
     "gram_syrk": ("gemm_f64_kernel", "paper_0912_1135_amd/csrc/rt_gemm.hip"),
     "w_gemm": ("gemm_f64_kernel", "paper_0912_1135_amd/csrc/rt_gemm.hip"),
