@@ -26,7 +26,20 @@ struct Lay32 {
     __device__ static int at(int mn, int k) { return KCONTIG ? mn * (KC32 + 1) + k : k * (T + 32) + mn; }
 };
 
-template <int BM, int BN, bool A_KC, bool B_KC>
+// Element of binary64 (DBL) or binary32 storage, widened to binary64.
+template <bool DBL>
+__device__ __forceinline__ double ld_st(const void *p, int64_t idx)
+{
+    if constexpr (DBL) return static_cast<const double *>(p)[idx];
+    else return (double)static_cast<const float *>(p)[idx];
+}
+
+// As the binary64 GEMM: every load is issued from a clamped address and
+// zeroed by a select (straight-line loads, one chunk in flight behind the
+// MFMAs), the loop-invariant address parts and scales are hoisted, and a
+// gather of B's rows reads its indices one chunk ahead.  DBL: binary64
+// storage of both operands (else binary32).
+template <int BM, int BN, bool A_KC, bool B_KC, bool DBL, bool GB>
 __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmMxArgs g)
 {
     using LA = Lay32<BM, A_KC>;
@@ -58,41 +71,64 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmMxArgs g)
         kend = min(g.K, kbeg + ks);
     }
     if (g.a_lower) kend = min(kend, i0 + BM);
-    auto a_coord = [&](int e, int &ii, int &kk) {
+    const int nch = kend > kbeg ? (kend - kbeg + KC32 - 1) / KC32 : 0;
+
+    int a_ii[NA], a_kk[NA], b_jj[NB], b_kk[NB];
+    int64_t a_row[NA], b_col[NB];
+    bool a_in[NA], b_in[NB];
+    double a_sc[NA], b_sc[NB];
+#pragma unroll
+    for (int e = 0; e < NA; ++e) {
         const int x = tid + 256 * e;
-        if (A_KC) { ii = x / KC32; kk = x % KC32; } else { ii = x % BM; kk = x / BM; }
-    };
-    auto b_coord = [&](int e, int &jj, int &kk) {
+        a_ii[e] = A_KC ? x / KC32 : x % BM;
+        a_kk[e] = A_KC ? x % KC32 : x / BM;
+        const int i = i0 + a_ii[e];
+        a_in[e] = i < g.M;
+        const int ic = a_in[e] ? i : g.M - 1;
+        a_row[e] = (g.a_gather ? (int64_t)g.a_gather[ic] : (int64_t)ic) * g.a_i;
+        a_sc[e] = g.a_scale ? (double)g.a_scale[ic] : 1.0;
+    }
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
         const int x = tid + 256 * e;
-        if (B_KC) { jj = x / KC32; kk = x % KC32; } else { jj = x % BN; kk = x / BN; }
-    };
+        b_jj[e] = B_KC ? x / KC32 : x % BN;
+        b_kk[e] = B_KC ? x % KC32 : x / BN;
+        const int j = j0 + b_jj[e];
+        b_in[e] = j < g.N;
+        const int jc = b_in[e] ? j : g.N - 1;
+        b_col[e] = (int64_t)jc * g.b_j;
+        b_sc[e] = g.b_scale ? (double)g.b_scale[jc] : 1.0;
+    }
     float ra[NA], rb[NB];
-    auto load = [&](int k0) {
+    int gi[NB];
+    (void)gi;
+    auto load_idx = [&](int c) {
+        if constexpr (GB) {
+#pragma unroll
+            for (int e = 0; e < NB; ++e) {
+                const int k = kbeg + c * KC32 + b_kk[e];
+                gi[e] = g.b_gather[k < kend ? k : kend - 1];
+            }
+        }
+    };
+    auto load = [&](int c) {
+        const int k0 = kbeg + c * KC32;
 #pragma unroll
         for (int e = 0; e < NA; ++e) {
-            int ii, kk;
-            a_coord(e, ii, kk);
-            const int i = i0 + ii, k = k0 + kk;
-            double v = 0.0;
-            if (i < g.M && k < kend && !(g.a_lower && k > i)) {
-                const int64_t gi = g.a_gather ? (int64_t)g.a_gather[i] : (int64_t)i;
-                v = ld_any(g.A, g.a_dbl, gi * g.a_i + (int64_t)k * g.a_k);
-                if (g.a_scale) v *= (double)g.a_scale[i];
-            }
-            ra[e] = (float)v;
+            const int k = k0 + a_kk[e];
+            const bool ok = a_in[e] && k < kend && !(g.a_lower && k > i0 + a_ii[e]);
+            const double v = ld_st<DBL>(g.A, a_row[e] + (int64_t)(k < kend ? k : kend - 1) * g.a_k) * a_sc[e];
+            ra[e] = ok ? (float)v : 0.f;
         }
 #pragma unroll
         for (int e = 0; e < NB; ++e) {
-            int jj, kk;
-            b_coord(e, jj, kk);
-            const int j = j0 + jj, k = k0 + kk;
-            double v = 0.0;
-            if (j < g.N && k < kend) {
-                const int64_t gk = g.b_gather ? (int64_t)g.b_gather[k] : (int64_t)k;
-                v = ld_any(g.B, g.b_dbl, gk * g.b_k + (int64_t)j * g.b_j);
-                if (g.b_scale) v *= (double)g.b_scale[j];
-            }
-            rb[e] = (float)v;
+            const int k = k0 + b_kk[e];
+            const bool ok = b_in[e] && k < kend;
+            int64_t kr;
+            if constexpr (GB) kr = gi[e];
+            else kr = k < kend ? k : kend - 1;
+            const double v = ld_st<DBL>(g.B, kr * g.b_k + b_col[e]) * b_sc[e];
+            rb[e] = ok ? (float)v : 0.f;
         }
     };
     f4 acc[TM][TN];
@@ -100,23 +136,22 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmMxArgs g)
     for (int a = 0; a < TM; ++a)
 #pragma unroll
         for (int b = 0; b < TN; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
-    int buf = 0;
-    if (kbeg < kend) load(kbeg);
-    for (int k0 = kbeg; k0 < kend; k0 += KC32) {
+    if (nch > 0) {
+        load_idx(0);
+        load(0);
+        load_idx(1);
+    }
+    for (int t = 0; t < nch; ++t) {
+        const int buf = t & 1;
 #pragma unroll
-        for (int e = 0; e < NA; ++e) {
-            int ii, kk;
-            a_coord(e, ii, kk);
-            As[buf][LA::at(ii, kk)] = ra[e];
-        }
+        for (int e = 0; e < NA; ++e) As[buf][LA::at(a_ii[e], a_kk[e])] = ra[e];
 #pragma unroll
-        for (int e = 0; e < NB; ++e) {
-            int jj, kk;
-            b_coord(e, jj, kk);
-            Bs[buf][LB::at(jj, kk)] = rb[e];
-        }
+        for (int e = 0; e < NB; ++e) Bs[buf][LB::at(b_jj[e], b_kk[e])] = rb[e];
         __syncthreads();
-        if (k0 + KC32 < kend) load(k0 + KC32);
+        // next chunk's data (its indices were read a chunk ago), then the
+        // indices of the chunk after it
+        load(t + 1);
+        load_idx(t + 2);
 #pragma unroll
         for (int kk = 0; kk < KC32; kk += 4) {
             float av[TM], bv[TN];
@@ -130,7 +165,6 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmMxArgs g)
                 for (int b = 0; b < TN; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
         }
-        buf ^= 1;
     }
     const int64_t coff = g.ksplit > 1 ? (int64_t)blockIdx.z * g.c_split : 0;
 #pragma unroll
@@ -157,7 +191,7 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmMxArgs g)
 // and 16 lanes at 16 consecutive rows hit 64 distinct banks.
 constexpr int KB = 32;
 
-template <int BM, int BN>
+template <int BM, int BN, bool DBL>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmMxArgs g)
 {
     typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
@@ -188,33 +222,48 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmMxArgs g)
         kbeg = blockIdx.z * ks;
         kend = min(g.K, kbeg + ks);
     }
-    // group e of this thread: row (x / 4), k-offset 8 * (x % 4), x = tid + 256 e
+    // group e of this thread: row (x / 4), k-offset 8 * (x % 4), x = tid + 256 e;
+    // row offsets and scales hoisted, loads from clamped addresses zeroed by
+    // a select (straight-line, one chunk in flight)
+    int64_t a_row[NA], b_row[NB];
+    float a_sc[NA], b_sc[NB];
+    bool a_in[NA], b_in[NB];
+#pragma unroll
+    for (int e = 0; e < NA; ++e) {
+        const int x = tid + 256 * e, i = i0 + (x >> 2);
+        a_in[e] = i < g.M;
+        const int ic = a_in[e] ? i : g.M - 1;
+        a_row[e] = (int64_t)ic * g.a_i;
+        a_sc[e] = g.a_scale ? g.a_scale[ic] : 1.f;
+    }
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+        const int x = tid + 256 * e, j = j0 + (x >> 2);
+        b_in[e] = j < g.N;
+        const int jc = b_in[e] ? j : g.N - 1;
+        b_row[e] = (int64_t)jc * g.b_j;
+        b_sc[e] = g.b_scale ? g.b_scale[jc] : 1.f;
+    }
     bf8 ra[NA], rb[NB];
     auto load = [&](int k0) {
 #pragma unroll
         for (int e = 0; e < NA; ++e) {
-            const int x = tid + 256 * e, ii = x >> 2, kk = 8 * (x & 3);
-            const int i = i0 + ii;
-            const float sc = (i < g.M && g.a_scale) ? g.a_scale[i] : 1.f;
+            const int kk = 8 * ((tid + 256 * e) & 3);
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int k = k0 + kk + u;
-                double v = 0.0;
-                if (i < g.M && k < kend) v = ld_any(g.A, g.a_dbl, (int64_t)i * g.a_i + (int64_t)k * g.a_k) * sc;
-                ra[e][u] = (__bf16)(float)v;
+                const double v = ld_st<DBL>(g.A, a_row[e] + (int64_t)(k < kend ? k : kend - 1) * g.a_k) * a_sc[e];
+                ra[e][u] = (a_in[e] && k < kend) ? (__bf16)(float)v : (__bf16)0.f;
             }
         }
 #pragma unroll
         for (int e = 0; e < NB; ++e) {
-            const int x = tid + 256 * e, jj = x >> 2, kk = 8 * (x & 3);
-            const int j = j0 + jj;
-            const float sc = (j < g.N && g.b_scale) ? g.b_scale[j] : 1.f;
+            const int kk = 8 * ((tid + 256 * e) & 3);
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int k = k0 + kk + u;
-                double v = 0.0;
-                if (j < g.N && k < kend) v = ld_any(g.B, g.b_dbl, (int64_t)k * g.b_k + (int64_t)j * g.b_j) * sc;
-                rb[e][u] = (__bf16)(float)v;
+                const double v = ld_st<DBL>(g.B, (int64_t)(k < kend ? k : kend - 1) * g.b_k + b_row[e]) * b_sc[e];
+                rb[e][u] = (b_in[e] && k < kend) ? (__bf16)(float)v : (__bf16)0.f;
             }
         }
     };
@@ -270,18 +319,34 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmMxArgs g)
             }
 }
 
+template <int BM, int BN, bool DBL>
+hipError_t launch32_st(const GemmMxArgs &g, dim3 grid, hipStream_t s)
+{
+    const bool akc = g.a_k == 1, bkc = g.b_k == 1;
+    if (g.b_gather) {
+        // the gathered product P^{-1}A: A K-contiguous, B's rows gathered
+        if (!akc || bkc) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, true, false, DBL, true>), grid, dim3(256), 0, s, g);
+    } else if (akc && bkc) {
+        hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, true, true, DBL, false>), grid, dim3(256), 0, s, g);
+    } else if (akc) {
+        hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, true, false, DBL, false>), grid, dim3(256), 0, s, g);
+    } else if (bkc) {
+        hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, false, true, DBL, false>), grid, dim3(256), 0, s, g);
+    } else {
+        hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, false, false, DBL, false>), grid, dim3(256), 0, s, g);
+    }
+    return hipGetLastError();
+}
+
 template <int BM, int BN>
 hipError_t launch32(const GemmMxArgs &g, hipStream_t s)
 {
     const int gm = (g.M + BM - 1) / BM, gn = (g.N + BN - 1) / BN;
     dim3 grid = g.c_lower ? dim3(gm * (gm + 1) / 2, 1, g.ksplit > 1 ? g.ksplit : 1)
                           : dim3(gn, gm, g.ksplit > 1 ? g.ksplit : 1);
-    const bool akc = g.a_k == 1, bkc = g.b_k == 1;
-    if (akc && bkc) hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, true, true>), grid, dim3(256), 0, s, g);
-    else if (akc) hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, true, false>), grid, dim3(256), 0, s, g);
-    else if (bkc) hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, false, true>), grid, dim3(256), 0, s, g);
-    else hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, false, false>), grid, dim3(256), 0, s, g);
-    return hipGetLastError();
+    if (g.a_dbl != g.b_dbl) return hipErrorInvalidValue;  // operands share their storage type
+    return g.a_dbl ? launch32_st<BM, BN, true>(g, grid, s) : launch32_st<BM, BN, false>(g, grid, s);
 }
 
 // out(i, j) = sum_s part[s][i][j] / (sa[i] sb[j]) in binary64 (fixed order);
@@ -342,9 +407,12 @@ hipError_t gemm_mx(const GemmMxArgs &g, int mode, hipStream_t stream)
         const int gm = (g.M + 127) / 128, gn = (g.N + 127) / 128;
         dim3 grid = g.c_lower ? dim3(gm * (gm + 1) / 2, 1, g.ksplit > 1 ? g.ksplit : 1)
                               : dim3(gn, gm, g.ksplit > 1 ? g.ksplit : 1);
-        hipLaunchKernelGGL((gemm_bf16_kernel<128, 128>), grid, dim3(256), 0, stream, g);
+        if (g.a_dbl != g.b_dbl) return hipErrorInvalidValue;
+        if (g.a_dbl) hipLaunchKernelGGL((gemm_bf16_kernel<128, 128, true>), grid, dim3(256), 0, stream, g);
+        else hipLaunchKernelGGL((gemm_bf16_kernel<128, 128, false>), grid, dim3(256), 0, stream, g);
         return hipGetLastError();
     }
+    // triangular A (P^{-1}A): 64-row tiles measured faster than 128-row ones
     if (g.M >= 128 && g.N >= 128 && !g.a_lower) return launch32<128, 128>(g, stream);
     return launch32<64, 64>(g, stream);
 }
