@@ -12,14 +12,18 @@ namespace rt {
 
 namespace {
 
-constexpr int KC = 16;
+// K per chunk: 16 for 64 x 64 tiles, 32 for 128 x 128 tiles (each measured
+// faster for its tile: the larger tile has the MFMA work to cover the deeper
+// loads, the smaller one keeps two blocks per compute unit).
+template <int BM>
+struct Chunk { static constexpr int value = BM >= 128 ? 32 : 16; };
 
 // LDS layout of an operand tile with MN extent T: a K-contiguous operand is
 // kept MN-major ([T][KC+1], k fastest, as loaded), an MN-contiguous one
 // K-major ([KC][T+16]); both paddings make the coalesced stores and the MFMA
 // operand reads (16 consecutive MN indices x 4 consecutive k per wave)
 // bank-conflict free.
-template <int T, bool KCONTIG>
+template <int T, bool KCONTIG, int KC>
 struct TileLayout {
     static constexpr int size = KCONTIG ? T * (KC + 1) : KC * (T + 16);
     __device__ static int at(int mn, int k) { return KCONTIG ? mn * (KC + 1) + k : k * (T + 16) + mn; }
@@ -48,8 +52,9 @@ struct Ring { static constexpr int value = 2; };
 template <int BM, int BN, bool A_KC, bool B_KC, bool GB>
 __device__ __forceinline__ void gemm_f64_tile(const GemmArgs &g, int bx, int by, int bz)
 {
-    using LA = TileLayout<BM, A_KC>;
-    using LB = TileLayout<BN, B_KC>;
+    constexpr int KC = Chunk<BM>::value;
+    using LA = TileLayout<BM, A_KC, KC>;
+    using LB = TileLayout<BN, B_KC, KC>;
     __shared__ double As[2][LA::size];
     __shared__ double Bs[2][LB::size];
     constexpr int TM = BM / 32, TN = BN / 32;
