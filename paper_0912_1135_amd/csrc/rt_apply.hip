@@ -217,6 +217,82 @@ __global__ __launch_bounds__(ATX_T) void atx_grouped(const AtxGroupArgs *gs)
                      blockIdx.y);
 }
 
+// Compensated A^T x with x in scalar registers.  x (hi and lo) is packed per
+// block of 8 right-hand sides as xpk[jb][i][0..8) = hi and [8..16) = lo, rows
+// padded with zeros to a multiple of 8 (m8).  The packed addresses are
+// uniform across the wave, so they are read with scalar loads and the Dot2
+// updates take x as scalar operands: the pass reads no LDS, and its rate is
+// set by the vector FP64 instructions.  One thread per column t of A; A is
+// read once per block of 8 right-hand sides.
+constexpr int ATS_T = 256;
+constexpr int ATS_KJ = 8;
+
+__global__ void pack_x_kernel(const double *xhi, const double *xlo, int64_t ldx, int m, int m8, int k, double *xpk)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int kb = (k + ATS_KJ - 1) / ATS_KJ;
+    if (e >= (int64_t)kb * m8 * 2 * ATS_KJ) return;
+    const int w = (int)(e % (2 * ATS_KJ));
+    const int64_t r = e / (2 * ATS_KJ);
+    const int i = (int)(r % m8), jb = (int)(r / m8);
+    const int j = jb * ATS_KJ + (w % ATS_KJ);
+    double v = 0.0;
+    if (i < m && j < k) {
+        if (w < ATS_KJ) v = xhi[(int64_t)j * ldx + i];
+        else if (xlo) v = xlo[(int64_t)j * ldx + i];
+    }
+    xpk[e] = v;
+}
+
+__global__ __launch_bounds__(ATS_T) void atx_dd_sx_kernel(int m, int m8, int n, int k, const double *__restrict__ A,
+                                                          int64_t lda, const double *__restrict__ xpk,
+                                                          const double *__restrict__ B, int64_t ldb,
+                                                          double *__restrict__ Rout, int64_t ldr,
+                                                          double *__restrict__ Y, int64_t ldy,
+                                                          double *__restrict__ Z, int64_t ldz)
+{
+    const int64_t t = (int64_t)blockIdx.x * ATS_T + threadIdx.x;
+    const int jb = blockIdx.y, j0 = jb * ATS_KJ;
+    const int kj = min(ATS_KJ, k - j0);
+    const double *xp = xpk + (int64_t)jb * m8 * 2 * ATS_KJ;
+    const bool active = t < n;
+    const double *ap = A + (active ? t : 0);
+    double s[ATS_KJ], c[ATS_KJ];
+#pragma unroll
+    for (int j = 0; j < ATS_KJ; ++j) { s[j] = 0.0; c[j] = 0.0; }
+    for (int i0 = 0; i0 < m8; i0 += 8) {
+        double av[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u;
+            const double v = ap[(int64_t)(i < m ? i : m - 1) * lda];
+            av[u] = i < m ? v : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double *xr = xp + (int64_t)(i0 + u) * 2 * ATS_KJ;
+#pragma unroll
+            for (int j = 0; j < ATS_KJ; ++j) {
+                dot2_acc(av[u], xr[j], s[j], c[j]);
+                c[j] = __builtin_fma(av[u], xr[ATS_KJ + j], c[j]);
+            }
+        }
+    }
+    if (!active) return;
+    for (int j = 0; j < kj; ++j) {
+        const int col = j0 + j;
+        double zr = 0.0;
+        if (B) {
+            double d, e;
+            two_sum(B[(int64_t)col * ldb + t], -s[j], d, e);
+            zr = d + (e - c[j]);
+        }
+        if (Rout) Rout[(int64_t)col * ldr + t] = zr;
+        if (Y) Y[(int64_t)col * ldy + t] = s[j] + c[j];
+        if (Z) Z[(int64_t)col * ldz + t] = zr;
+    }
+}
+
 // right-hand sides per block of the A^T x pass (accumulators per thread)
 // (the compensated form keeps 16: twice the accumulators cost more in
 // occupancy than the extra pass over A)
@@ -333,8 +409,20 @@ hipError_t ab_reduce_f64(const double *part_hi, const double *part_lo, int m, in
 
 hipError_t atx_f64(const ApplyArgs &a, const double *Xhi, const double *Xlo, int64_t ldx, const double *B,
                    int64_t ldb, double *Rout, int64_t ldr, double *Y, int64_t ldy, double *Z, int64_t ldz, int dd,
-                   hipStream_t stream)
+                   hipStream_t stream, double *xpk)
 {
+    if (dd && xpk) {
+        const int m8 = (a.m + 7) / 8 * 8, kb = (a.k + ATS_KJ - 1) / ATS_KJ;
+        const int64_t total = (int64_t)kb * m8 * 2 * ATS_KJ;
+        hipLaunchKernelGGL(pack_x_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, Xhi, Xlo, ldx,
+                           a.m, m8, a.k, xpk);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        dim3 grid((unsigned)((a.n + ATS_T - 1) / ATS_T), kb);
+        hipLaunchKernelGGL(atx_dd_sx_kernel, grid, dim3(ATS_T), 0, stream, a.m, m8, a.n, a.k, a.A, a.lda, xpk, B,
+                           ldb, Rout, ldr, Y, ldy, Z, ldz);
+        return hipGetLastError();
+    }
     const int kj = atx_kj(a.k, dd);
     dim3 grid((unsigned)((a.n + ATX_T - 1) / ATX_T), (a.k + kj - 1) / kj);
 #define ATX_CASE(DD_, KJ_)                                                                                          \

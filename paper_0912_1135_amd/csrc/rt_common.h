@@ -250,10 +250,13 @@ hipError_t ab_reduce_f64(const double *part_hi, const double *part_lo, int m, in
 // R = B - A^T (Xhi + Xlo) (n x k, col-major), Dot2 over m; mode 0: write
 // r = round(B - A^T x) to Rout; mode 1: write Y = round(A^T x) and
 // Z = round(B - A^T x) (either may be NULL); dd = 0 uses plain binary64 and
-// ignores Xlo.
+// ignores Xlo.  With dd and a workspace xpk of atx_pack_size(m, k) doubles,
+// x is packed for scalar loads and the pass reads no LDS.
 hipError_t atx_f64(const ApplyArgs &a, const double *Xhi, const double *Xlo, int64_t ldx,
                    const double *B, int64_t ldb, double *Rout, int64_t ldr,
-                   double *Y, int64_t ldy, double *Z, int64_t ldz, int dd, hipStream_t stream);
+                   double *Y, int64_t ldy, double *Z, int64_t ldz, int dd, hipStream_t stream,
+                   double *xpk = nullptr);
+inline int64_t atx_pack_size(int64_t m, int64_t k) { return (k + 7) / 8 * ((m + 7) / 8 * 8) * 16; }
 // ---- grouped (batched) forms: one launch over many problems whose
 // arguments live in device memory; the grid covers the largest member and
 // smaller members skip the blocks they do not have.

@@ -81,7 +81,8 @@ void release(rtproj_plan p)
     void *bufs[] = {p->d_sign, p->d_sigma, p->d_tauinv, p->d_sel_off, p->d_sel, p->d_tw1, p->d_tw2, p->d_twh,
                     p->d_twl, p->d_tw1f, p->d_tw2f, p->d_twhf, p->d_twlf, p->d_rowscale, p->d_zbuf, p->d_S, p->d_R, p->d_Y, p->d_W, p->d_part, p->d_G, p->d_L, p->d_Tp,
                     p->d_DinvR, p->d_DinvL, p->d_piv, p->d_sync, p->d_slots, p->d_vbuf, p->d_qrcols, p->d_Yq, p->d_R0, p->d_wgargs, p->d_scal, p->d_diag,
-                    p->d_bsum, p->d_c, p->d_tmp, p->d_xhi, p->d_xlo, p->d_d, p->d_r, p->d_ph, p->d_pl, p->d_norms, p->d_err};
+                    p->d_bsum, p->d_c, p->d_tmp, p->d_xhi, p->d_xlo, p->d_d, p->d_r, p->d_ph, p->d_pl, p->d_norms, p->d_xpk,
+                    p->d_err};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
 }
@@ -214,7 +215,8 @@ rtproj_status alloc_state(rtproj_plan p)
 rtproj_status ensure_k(rtproj_plan p, int64_t k)
 {
     if (k <= p->kcap) return RTPROJ_OK;
-    double **bufs[] = {&p->d_c, &p->d_tmp, &p->d_xhi, &p->d_xlo, &p->d_d, &p->d_r, &p->d_ph, &p->d_pl, &p->d_norms};
+    double **bufs[] = {&p->d_c, &p->d_tmp, &p->d_xhi, &p->d_xlo, &p->d_d, &p->d_r, &p->d_ph, &p->d_pl, &p->d_norms,
+                       &p->d_xpk};
     for (double **b : bufs)
         if (*b) { (void)hipFree(*b); *b = nullptr; }
     p->kcap = 0;
@@ -230,6 +232,7 @@ rtproj_status ensure_k(rtproj_plan p, int64_t k)
     RT_HIP(dalloc(&p->d_ph, (size_t)p->ab_splits * m * k));
     RT_HIP(dalloc(&p->d_pl, (size_t)p->ab_splits * m * k));
     RT_HIP(dalloc(&p->d_norms, 4));
+    RT_HIP(dalloc(&p->d_xpk, (size_t)rt::atx_pack_size(m, k)));
     p->kcap = k;
     return RTPROJ_OK;
 }
@@ -616,7 +619,8 @@ rtproj_status project(rtproj_plan p, const double *B, int64_t ldb, int64_t k, do
         const int dd = it >= nplain ? 1 : 0;
         {
             StageScope sc(p, 9);
-            if (dd) RT_HIP(rt::atx_f64(a, p->d_xhi, p->d_xlo, m, B, ldb, p->d_r, n, nullptr, 0, nullptr, 0, 1, s));
+            if (dd) RT_HIP(rt::atx_f64(a, p->d_xhi, p->d_xlo, m, B, ldb, p->d_r, n, nullptr, 0, nullptr, 0, 1, s,
+                                       p->d_xpk));
             else RT_HIP(resid_plain(p, B, ldb, k, s));
         }
         {
@@ -646,7 +650,8 @@ rtproj_status project(rtproj_plan p, const double *B, int64_t ldb, int64_t k, do
     // step 7: b~ = A^T x, z = b - b~
     if (Z || Y) {
         StageScope sc(p, 11);
-        RT_HIP(rt::atx_f64(a, p->d_xhi, p->d_xlo, m, B, ldb, nullptr, 0, Y, ldy, Z, ldz, steps > 0 ? 1 : 0, s));
+        RT_HIP(rt::atx_f64(a, p->d_xhi, p->d_xlo, m, B, ldb, nullptr, 0, Y, ldy, Z, ldz, steps > 0 ? 1 : 0, s,
+                           p->d_xpk));
     }
     if (X) RT_HIP(rt::copy_cols_f64(p->d_xhi, m, X, ldx, (int)m, (int)k, nullptr, 0, s));
     p->info.refine_steps = steps;
