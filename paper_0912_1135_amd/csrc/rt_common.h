@@ -161,10 +161,10 @@ hipError_t qrcp_f64(const double *S, int64_t lds, int rows, int cols, double *R,
 // *global_cols = 1 when the columns must live in global memory (w.cols).
 int qrcp_max_blocks(int rows, int cols, int cu_count, size_t lds_max, int *global_cols);
 hipError_t zero_u32(unsigned *p, int n, hipStream_t stream);
-// Register-resident cooperative form (512 threads per block; rows <= 8192).
+// Register-resident cooperative form (256 or 512 threads per block; rows <= 8192).
 // Block count from qrcp_reg_shape; the workspace is that of qrcp_f64 with
 // G blocks (slots 4 G doubles, vbuf 2 G rows doubles).
-bool qrcp_reg_shape(int rows, int cols, int cu_count, int *nc, int *rpt, int *blocks);
+bool qrcp_reg_shape(int rows, int cols, int cu_count, int *nc, int *rpt, int *blocks, int *threads);
 hipError_t qrcp_reg_f64(const double *S, int64_t lds, int rows, int cols, double *R, int32_t *piv,
                         const QrcpWork &w, int cu_count, hipStream_t stream);
 

@@ -185,8 +185,9 @@ rtproj_status alloc_state(rtproj_plan p)
                                             "for this (m, l)");
     // register-resident form where the shapes allow it (rows <= 8192)
     int nc_, rpt_;
-    if (!rt::qrcp_reg_shape((int)l, (int)m, p->cu_count, &nc_, &rpt_, &p->qr_reg_l)) p->qr_reg_l = 0;
-    if (!rt::qrcp_reg_shape((int)m, (int)m, p->cu_count, &nc_, &rpt_, &p->qr_reg_m)) p->qr_reg_m = 0;
+    int tt_;
+    if (!rt::qrcp_reg_shape((int)l, (int)m, p->cu_count, &nc_, &rpt_, &p->qr_reg_l, &tt_)) p->qr_reg_l = 0;
+    if (!rt::qrcp_reg_shape((int)m, (int)m, p->cu_count, &nc_, &rpt_, &p->qr_reg_m, &tt_)) p->qr_reg_m = 0;
     const int64_t gmax = std::max({(int64_t)p->qr_blocks, (int64_t)p->qr_blocks0, (int64_t)p->qr_reg_l,
                                    (int64_t)p->qr_reg_m});
     RT_HIP(dalloc(&p->d_slots, (size_t)4 * gmax));

@@ -224,8 +224,8 @@ __global__ __launch_bounds__(QR_THREADS) void qrcp_kernel(const double *S, int64
 }
 
 // ---------------------------------------------------------------------------
-// Register-resident form (the default): 512 threads, block g keeps its NC
-// columns in registers, thread t owning rows t, t + 512, ..., so that each
+// Register-resident form (the default): TT = 256 or 512 threads, block g keeps its NC
+// columns in registers, thread t owning rows t, t + TT, ..., so that each
 // thread reads the reflector's entries for its rows once and applies them to
 // all NC columns.  A step is a chain of dependent latencies (post, barrier,
 // candidate headers, pivot column), so everything between them is kept short:
@@ -237,8 +237,8 @@ __global__ __launch_bounds__(QR_THREADS) void qrcp_kernel(const double *S, int64
 //     device-scope accesses, which are coherent across the L2 slices of the
 //     XCDs without flushing or invalidating them; a block announces its
 //     arrival only after its posting stores have completed.
-constexpr int RQ_T = 512;
-constexpr int RQ_W = RQ_T / 64;
+// Threads per block: 256 or 512 (template parameter TT, TW = TT / 64 waves).
+
 
 __device__ __forceinline__ double u64_to_d(unsigned lo, unsigned hi)
 {
@@ -358,11 +358,11 @@ __device__ __forceinline__ void red_level(double (&v)[NC], int lane, int &off, b
 // i <-> i^1, i <-> i^8) halve the values per lane while any remain, so a lane
 // ends with the row sums of max(1, NC/16) consecutive columns starting at
 // `off` (set by its lane bits).  The representatives write these row sums to
-// LDS (red: 4 RQ_W x NC, one row per wave and lane row, columns contiguous so
+// LDS (red: 4 TW x NC, one row per wave and lane row, columns contiguous so
 // that the lanes reading them hit distinct banks); after one block barrier
-// lane c of every wave adds column c's 4 RQ_W partials in a fixed order.
+// lane c of every wave adds column c's 4 TW partials in a fixed order.
 // Returns that sum in lane c (0 for c >= NC), identical in every wave.
-template <int NC>
+template <int NC, int TW>
 __device__ __forceinline__ double block_col_sums(const double (&p)[NC], double (*red)[NC])
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -384,7 +384,7 @@ __device__ __forceinline__ double block_col_sums(const double (&p)[NC], double (
     if (lane < NC) {
         double a[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int q = 0; q < 4 * RQ_W; ++q) a[q & 3] += red[q][lane];
+        for (int q = 0; q < 4 * TW; ++q) a[q & 3] += red[q][lane];
         s = (a[0] + a[1]) + (a[2] + a[3]);
     }
     return s;
@@ -405,12 +405,13 @@ __device__ __forceinline__ void local_best(double s, int ncol, unsigned done, do
     bc = n >= 0.0 ? c : -1;
 }
 
-template <int NC, int RPT>
-__global__ __launch_bounds__(RQ_T) void qrcp_reg_kernel(const double *S, int64_t lds, int rows, int cols, double *R,
+template <int NC, int RPT, int TT>
+__global__ __launch_bounds__(TT) void qrcp_reg_kernel(const double *S, int64_t lds, int rows, int cols, double *R,
                                                         int32_t *piv, QrcpWork w, int G)
 {
     static_assert(NC <= 32 && (NC & (NC - 1)) == 0, "done mask, lane-per-column sums, power of two");
-    __shared__ double red[2][4 * RQ_W][NC];
+    constexpr int TW = TT / 64;
+    __shared__ double red[2][4 * TW][NC];
     __shared__ double s_pn;
     __shared__ int s_p, s_abort;
     const int g = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
@@ -424,7 +425,7 @@ __global__ __launch_bounds__(RQ_T) void qrcp_reg_kernel(const double *S, int64_t
     for (int c = 0; c < NC; ++c)
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            const int i = tid + RQ_T * r;
+            const int i = tid + TT * r;
             x[c][r] = (c < ncol && i < rows) ? S[(int64_t)(g + G * c) * lds + i] : 0.0;
         }
     if (tid == 0) s_abort = 0;
@@ -439,7 +440,7 @@ __global__ __launch_bounds__(RQ_T) void qrcp_reg_kernel(const double *S, int64_t
 #pragma unroll
             for (int r = 0; r < RPT; ++r) part[c] += x[c][r] * x[c][r];
         }
-        local_best<NC>(block_col_sums<NC>(part, red[1]), ncol, done, bn, bc);
+        local_best<NC>(block_col_sums<NC, TW>(part, red[1]), ncol, done, bn, bc);
     }
 
     for (int k = 0; k < cols; ++k) {
@@ -449,7 +450,7 @@ __global__ __launch_bounds__(RQ_T) void qrcp_reg_kernel(const double *S, int64_t
             double *dst = cand + ((int64_t)buf * G + g) * rows;
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
-                const int i = tid + RQ_T * r;
+                const int i = tid + TT * r;
                 double val = 0.0;
 #pragma unroll
                 for (int c = 0; c < NC; ++c) val = (c == bc) ? x[c][r] : val;
@@ -496,7 +497,7 @@ __global__ __launch_bounds__(RQ_T) void qrcp_reg_kernel(const double *S, int64_t
         double v[RPT];
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            const int i = tid + RQ_T * r;
+            const int i = tid + TT * r;
             v[r] = (i > k && i < rows) ? ld_dev(xp + i) : 0.0;
         }
         const double xnorm = __builtin_sqrt(s_pn);
@@ -508,13 +509,13 @@ __global__ __launch_bounds__(RQ_T) void qrcp_reg_kernel(const double *S, int64_t
             inv = 1.0 / (alpha - beta);
         }
 #pragma unroll
-        for (int r = 0; r < RPT; ++r) v[r] = (tid + RQ_T * r == k) ? 1.0 : v[r] * inv;
+        for (int r = 0; r < RPT; ++r) v[r] = (tid + TT * r == k) ? 1.0 : v[r] * inv;
         // 5. owner: column k of R and piv[k]
         if (p % G == g) {
             const int c = p / G;
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
-                const int i = tid + RQ_T * r;
+                const int i = tid + TT * r;
                 double val = 0.0;
 #pragma unroll
                 for (int cc = 0; cc < NC; ++cc) val = (cc == c) ? x[cc][r] : val;
@@ -536,7 +537,7 @@ __global__ __launch_bounds__(RQ_T) void qrcp_reg_kernel(const double *S, int64_t
 #pragma unroll
                 for (int r = 0; r < RPT; ++r) part[c] += v[r] * x[c][r];
             }
-            const double s = block_col_sums<NC>(part, red[0]);
+            const double s = block_col_sums<NC, TW>(part, red[0]);
 #pragma unroll
             for (int c = 0; c < NC; ++c) d[c] = readlane_d(s, c);
         }
@@ -548,18 +549,18 @@ __global__ __launch_bounds__(RQ_T) void qrcp_reg_kernel(const double *S, int64_t
                 nn[c] = 0.0;
 #pragma unroll
                 for (int r = 0; r < RPT; ++r) {
-                    const int i = tid + RQ_T * r;
+                    const int i = tid + TT * r;
                     const double nx = x[c][r] - f * v[r];
                     x[c][r] = nx;
                     if (i > k) nn[c] += nx * nx;
                 }
             }
-            local_best<NC>(block_col_sums<NC>(nn, red[1]), ncol, done, bn, bc);
+            local_best<NC>(block_col_sums<NC, TW>(nn, red[1]), ncol, done, bn, bc);
         }
     }
 }
 
-template <int NC, int RPT>
+template <int NC, int RPT, int TT>
 hipError_t launch_reg(const double *S, int64_t lds, int rows, int cols, double *R, int32_t *piv, const QrcpWork &w,
                       int G, hipStream_t stream)
 {
@@ -568,7 +569,8 @@ hipError_t launch_reg(const double *S, int64_t lds, int rows, int cols, double *
     int64_t lds_ = lds;
     void *args[] = {(void *)&S, (void *)&lds_, (void *)&rows_, (void *)&cols_, (void *)&R, (void *)&piv,
                     (void *)&wk, (void *)&G_};
-    return hipLaunchCooperativeKernel((const void *)qrcp_reg_kernel<NC, RPT>, dim3(G), dim3(RQ_T), args, 0, stream);
+    return hipLaunchCooperativeKernel((const void *)qrcp_reg_kernel<NC, RPT, TT>, dim3(G), dim3(TT), args, 0,
+                                      stream);
 }
 
 __global__ void zero_u32_kernel(unsigned *p, int n)
@@ -614,12 +616,14 @@ int qrcp_max_blocks(int rows, int cols, int cu_count, size_t lds_max, int *globa
     return G <= cu_count ? G : -1;
 }
 
-// Register form: rows per thread RPT = 1, 2, 4, 8 or 16 (rows <= 8192) and
-// NC columns per block with NC * RPT <= 64, NC aimed at about 64 blocks.
-bool qrcp_reg_shape(int rows, int cols, int cu_count, int *nc_out, int *rpt_out, int *g_out)
+// Register form: TT threads per block, rows per thread RPT = 1, 2, 4, 8 or 16
+// and NC columns per block with NC * RPT <= 64 (registers), NC aimed at
+// about 64 blocks.  256 threads when that still gives at most 64 blocks (fewer
+// waves to combine per step: measured faster), else 512 (rows <= 8192).
+static bool reg_shape_for(int tt, int rows, int cols, int cu_count, int *nc_out, int *rpt_out, int *g_out)
 {
     int rpt = 1;
-    while (rpt * RQ_T < rows) rpt <<= 1;
+    while (rpt * tt < rows) rpt <<= 1;
     if (rpt > 16) return false;
     const int cap = rpt == 1 ? 32 : (rpt == 2 ? 16 : 64 / rpt);
     int want = (cols + 63) / 64, nc = 4;
@@ -633,15 +637,27 @@ bool qrcp_reg_shape(int rows, int cols, int cu_count, int *nc_out, int *rpt_out,
     return true;
 }
 
+bool qrcp_reg_shape(int rows, int cols, int cu_count, int *nc_out, int *rpt_out, int *g_out, int *tt_out)
+{
+    if (reg_shape_for(256, rows, cols, cu_count, nc_out, rpt_out, g_out) && *g_out <= 64) {
+        *tt_out = 256;
+        return true;
+    }
+    *tt_out = 512;
+    return reg_shape_for(512, rows, cols, cu_count, nc_out, rpt_out, g_out);
+}
+
 hipError_t qrcp_reg_f64(const double *S, int64_t lds, int rows, int cols, double *R, int32_t *piv, const QrcpWork &w,
                         int cu_count, hipStream_t stream)
 {
-    int nc, rpt, G;
-    if (!qrcp_reg_shape(rows, cols, cu_count, &nc, &rpt, &G)) return hipErrorInvalidValue;
+    int nc, rpt, G, tt;
+    if (!qrcp_reg_shape(rows, cols, cu_count, &nc, &rpt, &G, &tt)) return hipErrorInvalidValue;
     hipError_t e = zero_u32(w.counter, 4, stream);
     if (e != hipSuccess) return e;
-#define RQ_CASE(NC_, RPT_) \
-    if (nc == NC_ && rpt == RPT_) return launch_reg<NC_, RPT_>(S, lds, rows, cols, R, piv, w, G, stream);
+#define RQ_CASE(NC_, RPT_)                                                                                        \
+    if (nc == NC_ && rpt == RPT_)                                                                                 \
+        return tt == 256 ? launch_reg<NC_, RPT_, 256>(S, lds, rows, cols, R, piv, w, G, stream)                   \
+                         : launch_reg<NC_, RPT_, 512>(S, lds, rows, cols, R, piv, w, G, stream);
     RQ_CASE(4, 1) RQ_CASE(8, 1) RQ_CASE(16, 1) RQ_CASE(32, 1)
     RQ_CASE(4, 2) RQ_CASE(8, 2) RQ_CASE(16, 2)
     RQ_CASE(4, 4) RQ_CASE(8, 4) RQ_CASE(16, 4)
