@@ -216,6 +216,9 @@ hipError_t shift_diag_f64(double *G, int64_t ld, int m, double c, hipStream_t st
 hipError_t set_matrix_f64(double *X, int64_t ld, int m, int n, int ident, hipStream_t stream);
 // Zero the strictly upper (upper = 1) or strictly lower part of a row-major m x m matrix.
 hipError_t zero_triangle_f64(double *X, int64_t ld, int m, int upper, hipStream_t stream);
+// X's diagonal nb-blocks (row-major, ld ldx) from the inverted blocks Dinv of
+// tri_diag_inv_f64; the rest of X is untouched.
+hipError_t place_diag_blocks_f64(const double *Dinv, int m, int nb, double *X, int64_t ldx, hipStream_t stream);
 // out = [T'^T ; T'] (two row-major m x m blocks) with T' = T Pi.
 hipError_t form_tp_f64(const double *T, const int32_t *piv, int m, double *out, hipStream_t stream);
 // |R_11| and |R_mm| of the row-major R (for the rank test), written to out[0..1].

@@ -303,6 +303,17 @@ __global__ void form_tp_grouped(const MatGroupArgs *gs)
 }
 
 
+// X's diagonal 64-blocks from the inverted blocks Dinv (nb x nb row-major
+// each, block b at Dinv + b nb^2); the rest of X is left as it is.
+__global__ void place_diag_blocks_kernel(const double *Dinv, int m, int nb, double *X, int64_t ldx)
+{
+    const int b = blockIdx.y, base = b * nb, nbb = min(nb, m - base);
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nbb * nbb; e += gridDim.x * blockDim.x) {
+        const int i = e / nbb, j = e % nbb;
+        X[(int64_t)(base + i) * ldx + base + j] = Dinv[(int64_t)b * nb * nb + (int64_t)i * nb + j];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Newton-Schulz inverse of the Gram.  One wave per row for the norms; the
 // affine reduction also yields the Frobenius norm of (out - I) in block
@@ -511,6 +522,14 @@ hipError_t reduce_affine_f64(const double *part, int64_t stride, int splits, int
 hipError_t sum_blocks_sqrt_f64(const double *bsum, int nb, double *out, hipStream_t stream)
 {
     hipLaunchKernelGGL(sum_blocks_sqrt_kernel, dim3(1), dim3(256), 0, stream, bsum, nb, out);
+    return hipGetLastError();
+}
+
+hipError_t place_diag_blocks_f64(const double *Dinv, int m, int nb, double *X, int64_t ldx, hipStream_t stream)
+{
+    const int nblk = (m + nb - 1) / nb;
+    if (nblk <= 0) return hipSuccess;
+    hipLaunchKernelGGL(place_diag_blocks_kernel, dim3(4, nblk), dim3(256), 0, stream, Dinv, m, nb, X, ldx);
     return hipGetLastError();
 }
 

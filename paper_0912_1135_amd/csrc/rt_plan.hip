@@ -80,7 +80,7 @@ void release(rtproj_plan p)
     p->pending.clear();
     void *bufs[] = {p->d_sign, p->d_sigma, p->d_tauinv, p->d_sel_off, p->d_sel, p->d_tw1, p->d_tw2, p->d_twh,
                     p->d_twl, p->d_tw1f, p->d_tw2f, p->d_twhf, p->d_twlf, p->d_rowscale, p->d_zbuf, p->d_S, p->d_R, p->d_Y, p->d_W, p->d_part, p->d_G, p->d_L, p->d_Tp,
-                    p->d_DinvR, p->d_DinvL, p->d_piv, p->d_sync, p->d_slots, p->d_vbuf, p->d_qrcols, p->d_Yq, p->d_R0, p->d_wgargs, p->d_scal, p->d_diag,
+                    p->d_DinvR, p->d_DinvL, p->d_piv, p->d_sync, p->d_slots, p->d_vbuf, p->d_qrcols, p->d_Yq, p->d_R0, p->d_wgargs, p->d_rinv_args, p->d_scal, p->d_diag,
                     p->d_bsum, p->d_c, p->d_tmp, p->d_xhi, p->d_xlo, p->d_d, p->d_r, p->d_ph, p->d_pl, p->d_norms, p->d_xpk,
                     p->d_err};
     for (void *b : bufs)
@@ -210,6 +210,46 @@ rtproj_status alloc_state(rtproj_plan p)
     RT_HIP(dalloc(&p->d_diag, 8));
     RT_HIP(dalloc(&p->d_err, 4));
     RT_HIP(dalloc(&p->d_rowscale, (size_t)m));
+    // recursive-doubling inverse of R^T: level s joins pairs of inverted
+    // diagonal blocks of size S = NB 2^s: for the pair at rows/cols c0..c0+S
+    // (X11) and r0 = c0 + S .. r0 + s2 (X22), T = L21 X11 goes to d_L's block
+    // (r0, c0), then X21 = -X22 T to the same block of d_Y.  L = R^T, read as
+    // L(i, j) = R[j m + i].
+    {
+        std::vector<rt::GemmArgs> all;
+        for (int64_t S = NB; S < m; S *= 2) {
+            std::vector<rt::GemmArgs> g1, g2;
+            for (int64_t c0 = 0; c0 + S < m; c0 += 2 * S) {
+                const int64_t r0 = c0 + S, s1 = S, s2 = std::min<int64_t>(S, m - r0);
+                rt::GemmArgs a{};
+                a.M = (int)s2; a.N = (int)s1; a.K = (int)s1;
+                a.A = p->d_R + c0 * m + r0; a.a_i = 1; a.a_k = m;
+                a.B = p->d_Y + c0 * m + c0; a.b_k = m; a.b_j = 1;
+                a.C = p->d_L + r0 * m + c0; a.c_i = m; a.c_j = 1;
+                a.alpha = 1.0; a.ksplit = 1;
+                g1.push_back(a);
+                rt::GemmArgs b{};
+                b.M = (int)s2; b.N = (int)s1; b.K = (int)s2;
+                b.A = p->d_Y + r0 * m + r0; b.a_i = m; b.a_k = 1;
+                b.B = p->d_L + r0 * m + c0; b.b_k = m; b.b_j = 1;
+                b.C = p->d_Y + r0 * m + c0; b.c_i = m; b.c_j = 1;
+                b.alpha = -1.0; b.ksplit = 1;
+                g2.push_back(b);
+            }
+            rt::GemmShape h1{}, h2{};
+            h1.M = h2.M = (int)S; h1.N = h2.N = (int)S; h1.ksplit = h2.ksplit = 1;
+            h1.a_kc = 0; h1.b_kc = 0; h2.a_kc = 1; h2.b_kc = 0;
+            p->rinv_count.push_back((int)g1.size());
+            p->rinv_shape1.push_back(h1);
+            p->rinv_shape2.push_back(h2);
+            all.insert(all.end(), g1.begin(), g1.end());
+            all.insert(all.end(), g2.begin(), g2.end());
+        }
+        if (!all.empty()) {
+            RT_HIP(hipMalloc(&p->d_rinv_args, all.size() * sizeof(rt::GemmArgs)));
+            RT_HIP(hipMemcpy(p->d_rinv_args, all.data(), all.size() * sizeof(rt::GemmArgs), hipMemcpyHostToDevice));
+        }
+    }
     return RTPROJ_OK;
 }
 
@@ -885,15 +925,23 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
     p->info.kappa_est = diag[2] > 0 ? diag[3] / diag[2] : INFINITY;
     if (!(diag[2] > (double)m * std::ldexp(1.0, -52) * diag[3]))
         return fail(RTPROJ_ERR_RANK, "pivoted QR of the sketch: |R_mm| <= m eps |R_11| (rank deficient A)");
-    // 3. R^{-T} (lower) by forward substitution on the identity
-    rtproj_status st;
+    // 3. R^{-T} (lower): inverted 64 x 64 diagonal blocks, then recursive
+    //    doubling over block pairs, X21 = -X22 L21 X11 (two grouped MFMA
+    //    products per level, log2(m / 64) levels)
+    rtproj_status st = RTPROJ_OK;
     {
         StageScope sc(p, 2);
         RT_HIP(rt::tri_diag_inv_f64(p->d_R, 1, m, (int)m, NB, p->d_DinvR, s));
-        RT_HIP(rt::set_matrix_f64(p->d_Y, m, (int)m, (int)m, 1, s));
-        st = trsm_lower(p, p->d_R, 1, m, p->d_DinvR, p->d_Y, m, m, m, true);
+        RT_HIP(rt::set_matrix_f64(p->d_Y, m, (int)m, (int)m, 0, s));
+        RT_HIP(rt::place_diag_blocks_f64(p->d_DinvR, (int)m, NB, p->d_Y, m, s));
+        size_t off = 0;
+        for (size_t lv = 0; lv < p->rinv_count.size(); ++lv) {
+            const int cnt = p->rinv_count[lv];
+            RT_HIP(rt::gemm_f64_grouped(p->d_rinv_args + off, cnt, p->rinv_shape1[lv], s));
+            RT_HIP(rt::gemm_f64_grouped(p->d_rinv_args + off + cnt, cnt, p->rinv_shape2[lv], s));
+            off += 2 * (size_t)cnt;
+        }
     }
-    if (st != RTPROJ_OK) return st;
     // 4. W = R^{-T} (Pi A), binary32 when the rank estimate allows it
     const bool lp = p->precision != RTPROJ_PREC_FP64;
     p->w32 = lp && p->info.kappa_est <= RT_W32_KAPPA_MAX;

@@ -163,6 +163,12 @@ struct rtproj_plan_s {
     double *d_Yq = nullptr;    // two-stage: the m x l iterate of the Cholesky QR
     double *d_R0 = nullptr;    // two-stage: R0^T (lower, row-major m x m)
     rt::QrcpWgArgs *d_wgargs = nullptr;
+    // R^{-T} by recursive doubling: per level, the grouped products
+    // T = L21 X11 and X21 = -X22 T over all block pairs (device argument
+    // arrays built at plan creation)
+    rt::GemmArgs *d_rinv_args = nullptr;
+    std::vector<int> rinv_count;                 // pairs per level
+    std::vector<rt::GemmShape> rinv_shape1, rinv_shape2;
     bool w32 = false;          // P^{-1}A held in binary32 by the last precondition
     int syrk_splits = 1;
     // projection workspace

@@ -40,22 +40,58 @@ __device__ __forceinline__ unsigned bitrev(unsigned x, int bits)
 // In-place radix-2 decimation-in-time FFT of `cols` columns of length `len`
 // stored column after column in LDS with column stride ld (input already in
 // bit-reversed order).  tw: len/2 twiddles exp(-2 pi i j / len) in LDS.
+//
+// Up to four consecutive radix-2 stages (half-sizes h, 2h, 4h, 8h) run in
+// registers: a thread loads the 2^B elements base + j h (base = blk 2^B h +
+// pos, pos < h) that those stages combine, applies the same butterflies the
+// stage-by-stage form would (so the result is bitwise the same), and writes
+// them back; one block barrier per group of stages instead of one per stage.
+// Consecutive threads take consecutive columns, whose stride ld = len + 1
+// puts their accesses on distinct banks.
+template <typename R, int B>
+__device__ __forceinline__ void fft_stage_group(cpx<R> *buf, int len, int ld, int cols, const cpx<R> *tw, int h)
+{
+    constexpr int G = 1 << B;
+    const int tasks = (len / G) * cols;
+    for (int t = threadIdx.x; t < tasks; t += blockDim.x) {
+        const int c = t % cols, gi = t / cols;
+        const int pos = gi % h, blk = gi / h;
+        const int base = blk * G * h + pos;
+        cpx<R> *col = buf + (int64_t)c * ld;
+        cpx<R> x[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) x[j] = col[base + j * h];
+#pragma unroll
+        for (int st = 0; st < B; ++st) {
+            const int hs = h << st;              // half-size of this stage
+            const int tstep = len / (2 * hs);    // twiddle index step
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                if ((j >> st) & 1) continue;
+                const int pj = pos + (j & ((1 << st) - 1)) * h;  // position inside the 2 hs block
+                const cpx<R> w = tw[pj * tstep];
+                const cpx<R> a = x[j];
+                const cpx<R> b = cmul(x[j + (1 << st)], w);
+                x[j] = cpx<R>{a.re + b.re, a.im + b.im};
+                x[j + (1 << st)] = cpx<R>{a.re - b.re, a.im - b.im};
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < G; ++j) col[base + j * h] = x[j];
+    }
+}
+
 template <typename R>
 __device__ void lds_fft_cols(cpx<R> *buf, int len, int ld, int cols, const cpx<R> *tw)
 {
-    const int half = len >> 1;
-    for (int h = 1; h < len; h <<= 1) {
-        const int stride = half / h;  // twiddle index step: len / (2h)
-        for (int e = threadIdx.x; e < half * cols; e += blockDim.x) {
-            const int c = e / half, q = e - c * half;
-            const int grp = q / h, pos = q - grp * h;
-            const int i0 = grp * 2 * h + pos, i1 = i0 + h;
-            cpx<R> *col = buf + (int64_t)c * ld;
-            const cpx<R> w = tw[pos * stride];
-            const cpx<R> a = col[i0];
-            const cpx<R> b = cmul(col[i1], w);
-            col[i0] = cpx<R>{a.re + b.re, a.im + b.im};
-            col[i1] = cpx<R>{a.re - b.re, a.im - b.im};
+    for (int h = 1; h < len;) {
+        int rem = 0;
+        while ((h << rem) < len) ++rem;  // stages left
+        switch (rem < 4 ? rem : 4) {
+        case 4: fft_stage_group<R, 4>(buf, len, ld, cols, tw, h); h <<= 4; break;
+        case 3: fft_stage_group<R, 3>(buf, len, ld, cols, tw, h); h <<= 3; break;
+        case 2: fft_stage_group<R, 2>(buf, len, ld, cols, tw, h); h <<= 2; break;
+        default: fft_stage_group<R, 1>(buf, len, ld, cols, tw, h); h <<= 1; break;
         }
         __syncthreads();
     }
