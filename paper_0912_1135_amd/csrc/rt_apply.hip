@@ -14,6 +14,8 @@
 // right-hand-side blocks are small and staged through LDS.
 #include "rt_common.h"
 
+#include <algorithm>
+
 namespace rt {
 
 namespace {
@@ -293,6 +295,135 @@ __global__ __launch_bounds__(ATS_T) void atx_dd_sx_kernel(int m, int m8, int n, 
     }
 }
 
+// Plain binary64 A B with B in scalar registers.  B is packed as
+// bpk[jb][t][16] (16 right-hand sides per block jb, zero past n and k), so
+// the 16 values of one t are uniform across the wave and are read with scalar
+// loads.  A block is
+// four waves on one 64-row strip of A and one split of the columns t; the
+// split is cut into chunks of 16 columns dealt to the waves in turn.  A wave
+// loads its chunk (64 rows x 16 doubles) with coalesced pair loads, one
+// chunk ahead, into a tile of its own in LDS, and each lane reads back its
+// row: one LDS read per 16 FMAs, so the pass is bound by reading A.  The
+// four waves' sums are combined in LDS in wave order and written as
+// part[split][j][row].  (A compensated form of this kernel, 8 right-hand
+// sides per block to fit the accumulator pairs, measured slower than the
+// LDS-staged Dot2 pass above, which the refinement keeps.)
+constexpr int ABS_RH = 16;           // right-hand sides per block (packed width)
+constexpr int ABS_TC = 16;           // columns of A per chunk
+constexpr int ABS_LD = ABS_TC + 1;   // LDS row stride in doubles: row reads free of bank conflicts
+constexpr int ABS_WAVES = 4;
+
+__global__ void pack_rhs_kernel(const double *B, int64_t ldb, int n, int k, int64_t tpad, double *bpk)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int kb = (k + ABS_RH - 1) / ABS_RH;
+    if (e >= (int64_t)kb * tpad * ABS_RH) return;
+    const int jj = (int)(e % ABS_RH);
+    const int64_t r = e / ABS_RH;
+    const int64_t t = r % tpad;
+    const int j = (int)(r / tpad) * ABS_RH + jj;
+    bpk[e] = (t < n && j < k) ? B[(int64_t)j * ldb + t] : 0.0;
+}
+
+// V2: A 16-byte aligned with even lda, so full chunks load as double pairs
+template <bool V2>
+__global__ __launch_bounds__(256) void ab_sx_kernel(int m, int n, int k, const double *__restrict__ A, int64_t lda,
+                                                    const double *__restrict__ bpk, int64_t tpad, int splits,
+                                                    double *__restrict__ part)
+{
+    constexpr int RH = ABS_RH;
+    constexpr int TILE = 64 * ABS_LD;
+    constexpr int RED = (ABS_WAVES - 1) * RH * 64;
+    __shared__ double lds[ABS_WAVES * TILE > RED ? ABS_WAVES * TILE : RED];
+    // the wave index through readfirstlane, so that chunk and B addresses are
+    // known to be uniform and B is read with scalar loads
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int r0 = blockIdx.x * 64, split = blockIdx.y, jb = blockIdx.z;
+    const int64_t nch = (n + ABS_TC - 1) / ABS_TC;
+    const int64_t per = (nch + splits - 1) / splits;
+    const int64_t c0 = (int64_t)split * per, c1 = min(nch, c0 + per);
+    double *tile = lds + w * TILE;
+    const double *bp = bpk + (int64_t)jb * tpad * RH;
+
+    // loader: lane (rsub, seg) takes columns 2 seg, 2 seg + 1 of rows
+    // rsub + 8 q, q = 0..7 (rows past m are clamped and read as zero)
+    const int seg = lane & 7, rsub = lane >> 3;
+    int64_t roff[8];
+    bool rok[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int row = r0 + rsub + 8 * q;
+        rok[q] = row < m;
+        roff[q] = (int64_t)(rok[q] ? row : m - 1) * lda;
+    }
+    double2 nx[8];
+    auto load = [&](int64_t ch) {
+        const int64_t t = ch * ABS_TC + 2 * seg;
+        if (V2 && (ch + 1) * ABS_TC <= n) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const double2 v = *reinterpret_cast<const double2 *>(A + roff[q] + t);
+                nx[q].x = rok[q] ? v.x : 0.0;
+                nx[q].y = rok[q] ? v.y : 0.0;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const double v0 = A[roff[q] + (t < n ? t : n - 1)];
+                const double v1 = A[roff[q] + (t + 1 < n ? t + 1 : n - 1)];
+                nx[q].x = (rok[q] && t < n) ? v0 : 0.0;
+                nx[q].y = (rok[q] && t + 1 < n) ? v1 : 0.0;
+            }
+        }
+    };
+
+    double s[RH];
+#pragma unroll
+    for (int j = 0; j < RH; ++j) s[j] = 0.0;
+    int64_t ch = c0 + w;
+    if (ch < c1) load(ch);
+    for (; ch < c1; ch += ABS_WAVES) {
+        // one wave writes and reads its own tile, in program order: no barrier
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            tile[(rsub + 8 * q) * ABS_LD + 2 * seg] = nx[q].x;
+            tile[(rsub + 8 * q) * ABS_LD + 2 * seg + 1] = nx[q].y;
+        }
+        if (ch + ABS_WAVES < c1) load(ch + ABS_WAVES);
+        double a[ABS_TC];
+#pragma unroll
+        for (int tt = 0; tt < ABS_TC; ++tt) a[tt] = tile[lane * ABS_LD + tt];
+        const double *bt = bp + ch * ABS_TC * RH;
+#pragma unroll
+        for (int tt = 0; tt < ABS_TC; ++tt) {
+#pragma unroll
+            for (int j = 0; j < RH; ++j) s[j] = __builtin_fma(a[tt], bt[tt * RH + j], s[j]);
+        }
+    }
+    // combine the four waves in order 0, 1, 2, 3
+    __syncthreads();
+    if (w > 0) {
+        double *rp = lds + (w - 1) * RH * 64;
+#pragma unroll
+        for (int j = 0; j < RH; ++j) rp[j * 64 + lane] = s[j];
+    }
+    __syncthreads();
+    if (w != 0) return;
+    for (int v = 0; v < ABS_WAVES - 1; ++v) {
+        const double *rp = lds + v * RH * 64;
+#pragma unroll
+        for (int j = 0; j < RH; ++j) s[j] += rp[j * 64 + lane];
+    }
+    const int row = r0 + lane;
+    if (row >= m) return;
+    const int64_t base = (int64_t)split * m * k;
+#pragma unroll
+    for (int j = 0; j < RH; ++j) {
+        const int col = jb * RH + j;
+        if (col < k) part[base + (int64_t)col * m + row] = s[j];
+    }
+}
+
 // right-hand sides per block of the A^T x pass (accumulators per thread)
 // (the compensated form keeps 16: twice the accumulators cost more in
 // occupancy than the extra pass over A)
@@ -395,6 +526,38 @@ hipError_t ab_partial_f64(const ApplyArgs &a, const double *B, int64_t ldb, int 
                            part_lo);
     AB_CASE(true, 16) AB_CASE(true, 32) AB_CASE(false, 16) AB_CASE(false, 32) AB_CASE(false, 64)
 #undef AB_CASE
+    return hipGetLastError();
+}
+
+int ab_sx_splits(int64_t m, int64_t n, int64_t k, int cu_count)
+{
+    // about two blocks per compute unit, at least four chunks per wave
+    const int64_t tiles = ((m + 63) / 64) * ((k + ABS_RH - 1) / ABS_RH);
+    const int64_t nch = (n + ABS_TC - 1) / ABS_TC;
+    const int64_t want = (2 * (int64_t)cu_count + tiles - 1) / tiles;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(want, nch / (4 * ABS_WAVES)));
+}
+
+hipError_t ab_sx_f64(const ApplyArgs &a, const double *B, int64_t ldb, double *bpk, int splits, double *part,
+                     hipStream_t stream)
+{
+    if (a.m <= 0 || a.n <= 0 || a.k <= 0) return hipSuccess;
+    if (splits < 1) return hipErrorInvalidValue;
+    const int64_t tpad = (a.n + ABS_TC - 1) / ABS_TC * ABS_TC;
+    const int kb = (a.k + ABS_RH - 1) / ABS_RH;
+    const int64_t total = (int64_t)kb * tpad * ABS_RH;
+    hipLaunchKernelGGL(pack_rhs_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, B, ldb, a.n, a.k,
+                       tpad, bpk);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const bool v2 = (a.lda % 2 == 0) && (reinterpret_cast<uintptr_t>(a.A) % 16 == 0);
+    const dim3 grid((unsigned)((a.m + 63) / 64), (unsigned)splits, (unsigned)kb);
+    if (v2)
+        hipLaunchKernelGGL((ab_sx_kernel<true>), grid, dim3(64 * ABS_WAVES), 0, stream, a.m, a.n, a.k, a.A, a.lda,
+                           bpk, tpad, splits, part);
+    else
+        hipLaunchKernelGGL((ab_sx_kernel<false>), grid, dim3(64 * ABS_WAVES), 0, stream, a.m, a.n, a.k, a.A, a.lda,
+                           bpk, tpad, splits, part);
     return hipGetLastError();
 }
 

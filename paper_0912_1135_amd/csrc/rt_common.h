@@ -247,6 +247,14 @@ struct ApplyArgs {
 };
 hipError_t ab_partial_f64(const ApplyArgs &a, const double *B, int64_t ldb, int splits,
                           double *part_hi, double *part_lo, int dd, hipStream_t stream);
+// The same partials in plain binary64 with B in scalar registers: B is first
+// packed into bpk (ab_pack_size(n, k) doubles) as [block of 16 right-hand
+// sides][t][16], zero past n and k; each wave streams a 64-row strip of A
+// through its own LDS tile.  splits comes from ab_sx_splits.
+hipError_t ab_sx_f64(const ApplyArgs &a, const double *B, int64_t ldb, double *bpk, int splits,
+                     double *part, hipStream_t stream);
+inline int64_t ab_pack_size(int64_t n, int64_t k) { return (k + 15) / 16 * ((n + 15) / 16 * 16) * 16; }
+int ab_sx_splits(int64_t m, int64_t n, int64_t k, int cu_count);
 // out (m x k, col-major ldo) = sum of partials (dd: compensated, rounded once).
 hipError_t ab_reduce_f64(const double *part_hi, const double *part_lo, int m, int k, int splits,
                          int dd, double *out, int64_t ldo, hipStream_t stream);

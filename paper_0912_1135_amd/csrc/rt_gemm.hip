@@ -213,10 +213,38 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmArgs &g, int bx, int by,
             }
 }
 
+// One-dimensional grid.  Tiles that read the same operand panel form a
+// group (the M tiles of one N tile and K split, which share B; or all lower
+// tiles of one K split, which share the panels of W).  In the plain order
+// block b runs tile b: N tile fastest, then M tile, then split (lower tiles,
+// then split, for a triangular C).  In the XCD order the tiles, numbered
+// t = group * members + member, are cut into runs of `chunk` consecutive
+// numbers and block b runs position (b / 8) % chunk of run
+// ((b / 8) / chunk) * 8 + b % 8: the device deals consecutive workgroups
+// round-robin to its 8 XCDs, each with its own L2, so each run executes on
+// one XCD and reuses its panels from that XCD's L2.  chunk is the group size,
+// or smaller when there are too few groups to occupy every XCD.
+constexpr int XCDS = 8;
+
+struct TileMap {
+    int members, total, chunk, gn, gm, xcd;
+};
+
 template <int BM, int BN, bool A_KC, bool B_KC, bool GB>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g)
+__global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g, TileMap tm)
 {
-    gemm_f64_tile<BM, BN, A_KC, B_KC, GB>(g, blockIdx.x, blockIdx.y, blockIdx.z);
+    const int b = blockIdx.x, q = b / XCDS;
+    const int t = tm.xcd ? ((q / tm.chunk) * XCDS + b % XCDS) * tm.chunk + q % tm.chunk : b;
+    if (t >= tm.total) return;
+    if (g.c_lower) {
+        gemm_f64_tile<BM, BN, A_KC, B_KC, GB>(g, t % tm.members, 0, t / tm.members);
+    } else if (tm.xcd) {
+        const int group = t / tm.members;
+        gemm_f64_tile<BM, BN, A_KC, B_KC, GB>(g, group % tm.gn, t % tm.members, group / tm.gn);
+    } else {
+        const int r = t / tm.gn;
+        gemm_f64_tile<BM, BN, A_KC, B_KC, GB>(g, t % tm.gn, r % tm.gm, r / tm.gm);
+    }
 }
 
 // Grouped launch: member blockIdx.z / ksmax, split blockIdx.z % ksmax.
@@ -228,24 +256,39 @@ __global__ __launch_bounds__(256) void gemm_f64_grouped_kernel(const GemmArgs *g
 }
 
 template <int BM, int BN, bool GB>
-hipError_t launch_tile_g(const GemmArgs &g, dim3 grid, hipStream_t s)
+hipError_t launch_tile_g(const GemmArgs &g, const TileMap &tm, hipStream_t s)
 {
+    const int64_t runs = (tm.total + tm.chunk - 1) / tm.chunk;
+    const int64_t nb = tm.xcd ? (int64_t)tm.chunk * ((runs + XCDS - 1) / XCDS) * XCDS : tm.total;
+    if (nb > INT32_MAX) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)nb);
     const bool akc = (g.a_k == 1), bkc = (g.b_k == 1);
-    if (akc && bkc) hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, true, true, GB>), grid, dim3(256), 0, s, g);
-    else if (akc) hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, true, false, GB>), grid, dim3(256), 0, s, g);
-    else if (bkc) hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, false, true, GB>), grid, dim3(256), 0, s, g);
-    else hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, false, false, GB>), grid, dim3(256), 0, s, g);
+    if (akc && bkc) hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, true, true, GB>), grid, dim3(256), 0, s, g, tm);
+    else if (akc) hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, true, false, GB>), grid, dim3(256), 0, s, g, tm);
+    else if (bkc) hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, false, true, GB>), grid, dim3(256), 0, s, g, tm);
+    else hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, false, false, GB>), grid, dim3(256), 0, s, g, tm);
     return hipGetLastError();
 }
 
 template <int BM, int BN>
 hipError_t launch_tile(const GemmArgs &g, hipStream_t s)
 {
-    dim3 grid;
     const int gm = (g.M + BM - 1) / BM, gn = (g.N + BN - 1) / BN;
-    if (g.c_lower) grid = dim3(gm * (gm + 1) / 2, 1, g.ksplit > 1 ? g.ksplit : 1);
-    else grid = dim3(gn, gm, g.ksplit > 1 ? g.ksplit : 1);
-    return g.b_gather ? launch_tile_g<BM, BN, true>(g, grid, s) : launch_tile_g<BM, BN, false>(g, grid, s);
+    const int ks = g.ksplit > 1 ? g.ksplit : 1;
+    // groups sharing a panel: lower tiles of one split, or the M tiles of one
+    // (N tile, split)
+    TileMap tm;
+    tm.members = g.c_lower ? gm * (gm + 1) / 2 : gm;
+    const int ngroups = g.c_lower ? ks : gn * ks;
+    tm.total = tm.members * ngroups;
+    tm.gn = gn;
+    tm.gm = gm;
+    tm.chunk = ngroups >= XCDS ? tm.members : (tm.total + XCDS - 1) / XCDS;
+    // measured: the XCD order pays for a triangular C and for 16 or more M
+    // tiles per panel; with 8 M tiles (a 512-row product) the plain order
+    // runs the same product about 20% faster
+    tm.xcd = (g.c_lower || gm >= 16) ? 1 : 0;
+    return g.b_gather ? launch_tile_g<BM, BN, true>(g, tm, s) : launch_tile_g<BM, BN, false>(g, tm, s);
 }
 
 __device__ __forceinline__ void reduce_splits_body(const double *part, int64_t stride, int splits, int M, int N,

@@ -81,7 +81,7 @@ void release(rtproj_plan p)
     void *bufs[] = {p->d_sign, p->d_sigma, p->d_tauinv, p->d_sel_off, p->d_sel, p->d_tw1, p->d_tw2, p->d_twh,
                     p->d_twl, p->d_tw1f, p->d_tw2f, p->d_twhf, p->d_twlf, p->d_rowscale, p->d_zbuf, p->d_S, p->d_R, p->d_Y, p->d_W, p->d_part, p->d_G, p->d_L, p->d_Tp,
                     p->d_DinvR, p->d_DinvL, p->d_piv, p->d_sync, p->d_slots, p->d_vbuf, p->d_qrcols, p->d_Yq, p->d_R0, p->d_wgargs, p->d_rinv_args, p->d_scal, p->d_diag,
-                    p->d_bsum, p->d_c, p->d_tmp, p->d_xhi, p->d_xlo, p->d_d, p->d_r, p->d_ph, p->d_pl, p->d_norms, p->d_xpk,
+                    p->d_bsum, p->d_c, p->d_tmp, p->d_xhi, p->d_xlo, p->d_d, p->d_r, p->d_ph, p->d_pl, p->d_norms, p->d_xpk, p->d_bpk,
                     p->d_err};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -257,7 +257,7 @@ rtproj_status ensure_k(rtproj_plan p, int64_t k)
 {
     if (k <= p->kcap) return RTPROJ_OK;
     double **bufs[] = {&p->d_c, &p->d_tmp, &p->d_xhi, &p->d_xlo, &p->d_d, &p->d_r, &p->d_ph, &p->d_pl, &p->d_norms,
-                       &p->d_xpk};
+                       &p->d_xpk, &p->d_bpk};
     for (double **b : bufs)
         if (*b) { (void)hipFree(*b); *b = nullptr; }
     p->kcap = 0;
@@ -270,8 +270,11 @@ rtproj_status ensure_k(rtproj_plan p, int64_t k)
     RT_HIP(dalloc(&p->d_xlo, (size_t)m * k));
     RT_HIP(dalloc(&p->d_d, (size_t)m * k));
     RT_HIP(dalloc(&p->d_r, (size_t)n * k));
-    RT_HIP(dalloc(&p->d_ph, (size_t)p->ab_splits * m * k));
-    RT_HIP(dalloc(&p->d_pl, (size_t)p->ab_splits * m * k));
+    p->ab_sx_splits = rt::ab_sx_splits(m, n, k, p->cu_count);
+    const int64_t psplits = std::max<int64_t>(p->ab_splits, p->ab_sx_splits);
+    RT_HIP(dalloc(&p->d_ph, (size_t)(psplits * m * k)));
+    RT_HIP(dalloc(&p->d_pl, (size_t)(psplits * m * k)));
+    RT_HIP(dalloc(&p->d_bpk, (size_t)rt::ab_pack_size(n, k)));
     RT_HIP(dalloc(&p->d_norms, 4));
     RT_HIP(dalloc(&p->d_xpk, (size_t)rt::atx_pack_size(m, k)));
     p->kcap = k;
@@ -584,8 +587,9 @@ hipError_t ab_plain(rtproj_plan p, const double *B, int64_t ldb, int64_t k, hipS
     const int64_t m = p->m, n = p->n;
     if (k < RT_MFMA_KMIN) {
         rt::ApplyArgs a{(int)m, (int)n, (int)k, p->A, p->lda};
-        hipError_t e = rt::ab_partial_f64(a, B, ldb, p->ab_splits, p->d_ph, p->d_pl, 0, s);
-        return e != hipSuccess ? e : rt::ab_reduce_f64(p->d_ph, p->d_pl, (int)m, (int)k, p->ab_splits, 0, p->d_c, m, s);
+        hipError_t e = rt::ab_sx_f64(a, B, ldb, p->d_bpk, p->ab_sx_splits, p->d_ph, s);
+        return e != hipSuccess ? e
+                               : rt::ab_reduce_f64(p->d_ph, p->d_pl, (int)m, (int)k, p->ab_sx_splits, 0, p->d_c, m, s);
     }
     rt::GemmArgs g{};
     g.M = (int)m; g.N = (int)k; g.K = (int)n;

@@ -176,6 +176,8 @@ struct rtproj_plan_s {
     int ab_splits = 1;
     double *d_c = nullptr, *d_tmp = nullptr, *d_xhi = nullptr, *d_xlo = nullptr, *d_d = nullptr, *d_r = nullptr;
     double *d_ph = nullptr, *d_pl = nullptr, *d_norms = nullptr;
+    double *d_bpk = nullptr;   // right-hand sides packed for the scalar-load A B pass (ab_pack_size(n, k))
+    int ab_sx_splits = 1;      // column splits of that pass
     double *d_xpk = nullptr;   // x packed for the scalar-load A^T x pass (atx_pack_size(m, k))
     // borrowed operand
     const double *A = nullptr;

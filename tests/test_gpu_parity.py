@@ -78,6 +78,32 @@ def test_projection_matches_oracle(rt, m, n, l, kappa, k, seed):
     plan.close()
 
 
+@pytest.mark.parametrize("m,n,l,kappa,k,seed", [
+    (70, 3001, 300, 1e8, 17, 10),   # odd n and row stride, A not 16-byte aligned
+    (64, 4099, 256, 1e6, 9, 11),
+])
+def test_projection_with_strided_unaligned_a(rt, m, n, l, kappa, k, seed):
+    # A and B as views into wider buffers: odd row strides and a start 8 bytes
+    # past an allocation, so the passes over A take their unaligned paths
+    A = synth.make_problem(m, n, kappa, seed)
+    B = synth.make_rhs(n, k, seed)
+    abuf = torch.zeros(m, n + 2 + (n + 1) % 2, dtype=torch.float64, device=dev())   # odd row stride
+    abuf[:, 1:n + 1] = torch.from_numpy(A).to(dev())
+    At = abuf[:, 1:n + 1]
+    bbuf = torch.zeros(k, n + 5, dtype=torch.float64, device=dev())
+    bbuf[:, 3:n + 3] = torch.from_numpy(np.ascontiguousarray(B)).to(dev())
+    Bt = bbuf[:, 3:n + 3]
+    assert At.stride(0) % 2 == 1 and At.data_ptr() % 16 == 8
+    plan = rt.Plan(m, n, l, seed)
+    plan.precondition(At)
+    Z, Y, X = plan.project_all(Bt)
+    torch.cuda.synchronize()
+    Zr, Yr, Xr, _ = oracle.project(A, B.T)
+    ez, ey, ex = errors(B, Z.cpu().numpy(), Y.cpu().numpy(), X.cpu().numpy(), Zr, Yr, Xr)
+    assert ez <= TOL and ey <= TOL and ex <= TOL, (ez, ey, ex)
+    plan.close()
+
+
 def test_tables_match_oracle(rt):
     for (m, n, l, seed) in [(8, 100, 40, 3), (64, 4096, 256, 9), (16, 544, 64, 11)]:
         plan = rt.Plan(m, n, l, seed)
