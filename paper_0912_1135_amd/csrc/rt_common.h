@@ -67,6 +67,14 @@ struct GemmArgs {
 // small_tiles is set).
 hipError_t gemm_f64(const GemmArgs &g, hipStream_t stream);
 
+// out = scale (A B) + diag I for row-major m x m A, B, out (leading dimension
+// m; out must not alias A or B), one wave per 16 x 16 tile over the whole K.
+// With bsum (sq_mm_blocks(m) doubles), bsum[tile] = sum over the tile of
+// (out - I)^2.
+hipError_t sq_mm_f64(int m, const double *A, const double *B, double *out, double scale, double diag, double *bsum,
+                     hipStream_t stream);
+inline int64_t sq_mm_blocks(int64_t m) { return ((m + 15) / 16) * ((m + 15) / 16); }
+
 // Grouped GEMM: one launch over `count` problems whose GemmArgs live in
 // device memory.  Every member must share the operand layouts (a_k == 1,
 // b_k == 1) and c_lower given here; M, N and ksplit here are the maxima

@@ -316,7 +316,120 @@ __global__ void reduce_splits_grouped(const ReduceGroupArgs *gs)
                        (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
+// Square products of the Newton-Schulz iteration: out = scale (A B) +
+// diag I for row-major m x m A, B and out.  One wave per 16 x 16 output tile
+// over the whole of K: no split, hence no partials to write and reduce.  The
+// operands (a few MB) are read straight from L2, k = k0 + 4 u + (lane / 16)
+// for k-step u, so an A load covers 16 rows x 4 consecutive k and a B load
+// 4 rows x 16 consecutive columns; the loads of the next 64 k are in flight
+// while the 16 MFMAs of the current 64 run, alternating two accumulators.
+// Groups inside the matrix run in a straight-line two-slot pipeline of
+// unmasked loads (masked loads get turned into branches that wait for each
+// load, and a conditional prefetch makes the compiler wait for it before
+// the other slot's products); ragged groups follow one at a time, masked.
+// With bsum the wave also writes the sum over its tile of (out - I)^2 to
+// bsum[tile], tile = ti * ceil(m / 16) + tj.
+constexpr int SQ_U = 16;  // k-steps of 4 per group
+
+__device__ __forceinline__ void sq_load_full(double (&av)[SQ_U], double (&bv)[SQ_U], const double *ap,
+                                             const double *bp, int m, int k0, int q)
+{
+#pragma unroll
+    for (int u = 0; u < SQ_U; ++u) {
+        const int k = k0 + 4 * u + q;
+        av[u] = ap[k];
+        bv[u] = bp[(int64_t)k * m];
+    }
+}
+
+__device__ __forceinline__ void sq_load(double (&av)[SQ_U], double (&bv)[SQ_U], const double *ap, const double *bp,
+                                        bool aok, bool bok, int m, int k0, int q)
+{
+#pragma unroll
+    for (int u = 0; u < SQ_U; ++u) {
+        const int k = k0 + 4 * u + q;
+        const int kc = k < m ? k : m - 1;
+        const double x = ap[kc];
+        const double y = bp[(int64_t)kc * m];
+        av[u] = (aok && k < m) ? x : 0.0;
+        bv[u] = (bok && k < m) ? y : 0.0;
+    }
+}
+
+__device__ __forceinline__ void sq_mma(const double (&av)[SQ_U], const double (&bv)[SQ_U], double4v &acc0,
+                                       double4v &acc1)
+{
+#pragma unroll
+    for (int u = 0; u < SQ_U; u += 2) {
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u + 1], bv[u + 1], acc1, 0, 0, 0);
+    }
+}
+
+__global__ __launch_bounds__(64) void sq_mm_kernel(int m, const double *__restrict__ A, const double *__restrict__ B,
+                                                   double *__restrict__ out, double scale, double diag,
+                                                   double *__restrict__ bsum)
+{
+    const int tiles = (m + 15) / 16;
+    const int ti = blockIdx.x / tiles, tj = blockIdx.x % tiles;
+    const int lane = threadIdx.x, r = lane & 15, q = lane >> 4;
+    const int ia = ti * 16 + r, jb = tj * 16 + r;
+    const bool aok = ia < m, bok = jb < m;
+    const double *ap = A + (int64_t)(aok ? ia : m - 1) * m;
+    const double *bp = B + (bok ? jb : m - 1);
+    double4v acc0 = double4v{0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+    double a0[SQ_U], b0[SQ_U], a1[SQ_U], b1[SQ_U];
+    constexpr int KG = 4 * SQ_U;
+    const int groups = (m + KG - 1) / KG;
+    // groups with every k inside m, for a tile with every row and column inside
+    const int full_groups = (ti * 16 + 16 <= m && tj * 16 + 16 <= m) ? m / KG : 0;
+    int gi = 0;
+    if (full_groups > 0) {
+        sq_load_full(a0, b0, ap, bp, m, 0, q);
+        for (; gi + 2 <= full_groups; gi += 2) {
+            sq_load_full(a1, b1, ap, bp, m, (gi + 1) * KG, q);
+            sq_mma(a0, b0, acc0, acc1);
+            // the last pair reloads its final group instead of branching
+            sq_load_full(a0, b0, ap, bp, m, min(gi + 2, full_groups - 1) * KG, q);
+            sq_mma(a1, b1, acc0, acc1);
+        }
+        if (gi < full_groups) {  // odd count: slot 0 holds the last full group
+            sq_mma(a0, b0, acc0, acc1);
+            ++gi;
+        }
+    }
+    for (; gi < groups; ++gi) {
+        sq_load(a0, b0, ap, bp, aok, bok, m, gi * KG, q);
+        sq_mma(a0, b0, acc0, acc1);
+    }
+    double qs = 0.0;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+        const int i = ti * 16 + mfma16_row(lane, rr), j = tj * 16 + mfma16_col(lane);
+        if (i < m && j < m) {
+            const double id = (i == j) ? 1.0 : 0.0;
+            const double v = scale * (acc0[rr] + acc1[rr]) + diag * id;
+            out[(int64_t)i * m + j] = v;
+            qs += (v - id) * (v - id);
+        }
+    }
+    if (!bsum) return;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) qs += __shfl_xor(qs, o, 64);
+    if (lane == 0) bsum[blockIdx.x] = qs;
+}
+
 }  // namespace
+
+hipError_t sq_mm_f64(int m, const double *A, const double *B, double *out, double scale, double diag, double *bsum,
+                     hipStream_t stream)
+{
+    if (m <= 0) return hipSuccess;
+    const int64_t nb = sq_mm_blocks(m);
+    if (nb > INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(sq_mm_kernel, dim3((unsigned)nb), dim3(64), 0, stream, m, A, B, out, scale, diag, bsum);
+    return hipGetLastError();
+}
 
 hipError_t gemm_f64(const GemmArgs &g, hipStream_t stream)
 {

@@ -153,6 +153,10 @@ rtproj_status upload_tables(rtproj_plan p)
     return RTPROJ_OK;
 }
 
+// Newton-Schulz residual block sums: one per 16 x 16 tile of the fused
+// products, one per 256 elements of the split ones' affine reduction.
+int64_t ns_bsum_count(int64_t m) { return m <= RT_NS_FUSED_MAX_M ? rt::sq_mm_blocks(m) : (m * m + 255) / 256; }
+
 rtproj_status alloc_state(rtproj_plan p)
 {
     const int64_t m = p->m, n = p->n, l = p->l, np = p->tab.np;
@@ -171,7 +175,7 @@ rtproj_status alloc_state(rtproj_plan p)
     RT_HIP(dalloc(&p->d_G, (size_t)m * m));
     RT_HIP(dalloc(&p->d_L, (size_t)m * m));
     RT_HIP(dalloc(&p->d_Tp, (size_t)2 * m * m));
-    RT_HIP(dalloc(&p->d_bsum, (size_t)((m * m + 255) / 256)));
+    RT_HIP(dalloc(&p->d_bsum, (size_t)ns_bsum_count(m)));
     const int64_t nblk = (m + NB - 1) / NB;
     RT_HIP(dalloc(&p->d_DinvR, (size_t)nblk * NB * NB));
     RT_HIP(dalloc(&p->d_DinvL, (size_t)nblk * NB * NB));
@@ -362,10 +366,13 @@ rtproj_status gram_f64(rtproj_plan p, const double *A, int64_t lda, int64_t K, d
     return RTPROJ_OK;
 }
 
-// One Newton-Schulz step on row-major m x m matrices: U = 2I - X Yc (with the
-// block sums of |U - I|^2 in d_bsum), then Yn = Yc U.  64 x 64 tiles, K split
-// so that a product spans about four blocks per compute unit (chunks of 64
-// or more), whose interleaving hides the load latency.
+// One product of a Newton-Schulz step on row-major m x m matrices:
+// out = scale (Am Bm) + diag I, with block sums of |out - I|^2 in bsum
+// (U = 2I - X Yc, then Yn = Yc U).  Up to RT_NS_FUSED_MAX_M one launch with
+// one wave per 16 x 16 tile over the whole K and the affine epilogue fused
+// (small products are launch latency); above it, whose fused form would
+// read about m^3 bytes from L2, 64 x 64 tiles with K split so that a product
+// spans about four blocks per compute unit, then the affine reduction.
 int ns_splits(rtproj_plan p)
 {
     const int64_t m = p->m, tiles = ((m + 63) / 64) * ((m + 63) / 64);
@@ -377,6 +384,10 @@ rtproj_status ns_product(rtproj_plan p, const double *Am, const double *Bm, doub
                          double *bsum)
 {
     const int64_t m = p->m;
+    if (m <= RT_NS_FUSED_MAX_M) {
+        RT_HIP(rt::sq_mm_f64((int)m, Am, Bm, out, scale, diag, bsum, p->stream));
+        return RTPROJ_OK;
+    }
     const int ks = ns_splits(p);
     rt::GemmArgs g{};
     g.M = (int)m; g.N = (int)m; g.K = (int)m;
@@ -411,7 +422,7 @@ rtproj_status gram_inverse_ns(rtproj_plan p)
     RT_HIP(rt::ns_norms_f64(p->d_G, (int)m, slots, s));
     double *Ya = p->d_L, *Yb = p->d_Tp, *U = p->d_Tp + m * m;
     RT_HIP(rt::ns_start_f64(p->d_G, (int)m, slots, Ya, s));
-    const int nbs = (int)((m * m + 255) / 256);
+    const int nbs = (int)ns_bsum_count(m);
     int it = 0, round = RT_NS_FIRST;
     double e = INFINITY, eprev = INFINITY;
     rtproj_status st;

@@ -43,7 +43,9 @@ constexpr double RT_COND_ESCALATE = 10.0;
 // but a chain of small diagonal steps) above it.
 constexpr int64_t RT_NS_MAX_M = 1024;
 // Newton-Schulz: iterations of the first round (Y_0 = I / |X|_inf converges
-// within it for |X|_inf / lambda_min(X) up to about 100), the residual
+// within it for |X|_inf / lambda_min(X) up to about 100; a Gram sketched at
+// l = 4m has |X|_inf about 5 lambda_max and condition about 8.5, and needs
+// 11 steps), the residual
 // |I - X Y_k|_F below which Y_{k+1} is final, the largest residual accepted
 // as a rounding floor once it stops squaring, and the iteration cap.  The
 // iterates are used as computed, never symmetrised: I - X Y_{k+1} =
@@ -53,6 +55,9 @@ constexpr int RT_NS_FIRST = 12;
 constexpr double RT_NS_DONE = 1e-6;
 constexpr double RT_NS_FLOOR = 1e-4;
 constexpr int RT_NS_MAX_IT = 64;
+// Largest m whose Newton-Schulz products run as one fused launch per product
+// (one wave per 16 x 16 tile, whole K; its L2 reads grow as m^3).
+constexpr int64_t RT_NS_FUSED_MAX_M = 256;
 
 // ------------------------------------------------------------ random tables
 // SplitMix64 (Steele, Lea and Flood, 2014): the state advances by the golden
@@ -159,7 +164,7 @@ struct rtproj_plan_s {
     int qr_mode = RTPROJ_QR_AUTO;
     int inv_method = RTPROJ_INV_AUTO;  // inverse of the Gram requested
     int inv_used = 0;          // RTPROJ_INV_NEWTON_SCHULZ or RTPROJ_INV_CHOLESKY, last precondition
-    double *d_bsum = nullptr;  // block partial sums of squares (ceil(m^2 / 256))
+    double *d_bsum = nullptr;  // block sums of squares of the Newton-Schulz residual (ns_bsum_count(m))
     double *d_Yq = nullptr;    // two-stage: the m x l iterate of the Cholesky QR
     double *d_R0 = nullptr;    // two-stage: R0^T (lower, row-major m x m)
     rt::QrcpWgArgs *d_wgargs = nullptr;
