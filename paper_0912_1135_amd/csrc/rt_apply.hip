@@ -23,13 +23,23 @@ namespace {
 constexpr int AB_RB = 32;   // rows of A per block
 constexpr int AB_TC = 64;   // columns of A per LDS stage
 
+// Zero read in place of an operand element outside the problem: the staging
+// loads pick their address, not their value, so that every load is issued
+// unconditionally (a load whose value is selected afterwards is compiled
+// into a branch that waits for it).
+__device__ double g_zero = 0.0;
+
 // part[s][j][row] = sum_{t in split s} A[row][t] * B[t][j] (column-major m x k
 // per split).  dd: Dot2 accumulation, hi in part_hi and error in part_lo.
+// The next stage's A and B elements are loaded into registers while the
+// current stage is multiplied out of LDS.
 template <bool DD, int KJ>
 __device__ __forceinline__ void ab_partial_body(const ApplyArgs &a, const double *B, int64_t ldb, int splits,
                                                 double *part_hi, double *part_lo, int bx, int split, int bz)
 {
-    constexpr int NO = AB_RB * KJ / 256;  // outputs per thread
+    constexpr int NO = AB_RB * KJ / 256;      // outputs per thread
+    constexpr int NA = AB_RB * AB_TC / 256;   // staged elements of A per thread
+    constexpr int NB = AB_TC * KJ / 256;      // staged elements of B per thread
     __shared__ double As[AB_RB][AB_TC + 1];
     __shared__ double Bs[AB_TC][KJ];
     const int r0 = bx * AB_RB;
@@ -39,24 +49,42 @@ __device__ __forceinline__ void ab_partial_body(const ApplyArgs &a, const double
     const int64_t t0 = (int64_t)split * len;
     const int64_t t1 = min<int64_t>(a.n, t0 + len);
     const int tid = threadIdx.x;
+    // staged element e = tid + 256 q: A (rr, tt) = (e / AB_TC, e % AB_TC),
+    // B (jj, tt) likewise; consecutive threads read consecutive t
+    const int tt = tid % AB_TC;
+    const double *arow[NA];
+    const double *bcol[NB];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+        const int row = r0 + (tid + 256 * q) / AB_TC;
+        arow[q] = row < a.m ? a.A + (int64_t)row * a.lda : nullptr;
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int j = j0 + (tid + 256 * q) / AB_TC;
+        bcol[q] = j < a.k ? B + (int64_t)j * ldb : nullptr;
+    }
+    double ra[NA], rb[NB];
+    auto load = [&](int64_t tb) {
+        const int64_t t = tb + tt;
+        const bool tin = t < t1;
+#pragma unroll
+        for (int q = 0; q < NA; ++q) ra[q] = *((arow[q] && tin) ? arow[q] + t : &g_zero);
+#pragma unroll
+        for (int q = 0; q < NB; ++q) rb[q] = *((bcol[q] && tin) ? bcol[q] + t : &g_zero);
+    };
     // NO outputs per thread: (row, j) = (o / KJ, o % KJ), o = tid + 256 q
     double s[NO], c[NO];
 #pragma unroll
     for (int q = 0; q < NO; ++q) { s[q] = 0.0; c[q] = 0.0; }
+    load(t0);
     for (int64_t tb = t0; tb < t1; tb += AB_TC) {
-        for (int e = tid; e < AB_RB * AB_TC; e += 256) {
-            const int rr = e / AB_TC, tt = e % AB_TC;
-            const int64_t t = tb + tt;
-            const int row = r0 + rr;
-            As[rr][tt] = (row < a.m && t < t1) ? a.A[(int64_t)row * a.lda + t] : 0.0;
-        }
-        for (int e = tid; e < AB_TC * KJ; e += 256) {
-            const int jj = e / AB_TC, tt = e % AB_TC;
-            const int64_t t = tb + tt;
-            const int j = j0 + jj;
-            Bs[tt][jj] = (j < a.k && t < t1) ? B[(int64_t)j * ldb + t] : 0.0;
-        }
+#pragma unroll
+        for (int q = 0; q < NA; ++q) As[(tid + 256 * q) / AB_TC][tt] = ra[q];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) Bs[tt][(tid + 256 * q) / AB_TC] = rb[q];
         __syncthreads();
+        load(tb + AB_TC);  // past t1 every address is the zero
 #pragma unroll
         for (int q = 0; q < NO; ++q) {
             const int o = tid + 256 * q;
@@ -262,14 +290,7 @@ __global__ __launch_bounds__(ATS_T) void atx_dd_sx_kernel(int m, int m8, int n, 
     double s[ATS_KJ], c[ATS_KJ];
 #pragma unroll
     for (int j = 0; j < ATS_KJ; ++j) { s[j] = 0.0; c[j] = 0.0; }
-    for (int i0 = 0; i0 < m8; i0 += 8) {
-        double av[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int i = i0 + u;
-            const double v = ap[(int64_t)(i < m ? i : m - 1) * lda];
-            av[u] = i < m ? v : 0.0;
-        }
+    auto update = [&](const double (&av)[8], int i0) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const double *xr = xp + (int64_t)(i0 + u) * 2 * ATS_KJ;
@@ -279,6 +300,43 @@ __global__ __launch_bounds__(ATS_T) void atx_dd_sx_kernel(int m, int m8, int n, 
                 c[j] = __builtin_fma(av[u], xr[ATS_KJ + j], c[j]);
             }
         }
+    };
+    // Groups of 8 rows inside m: straight-line, two register slots taken in
+    // turn, the next group's loads in flight during this group's updates (the
+    // last pair reloads its final group rather than branch: a conditional or
+    // masked load is compiled into a branch that waits for it, and a copy
+    // between slots waits at the loop's back edge).  Then the ragged group,
+    // masked.
+    const int full = m / 8;
+    auto load8 = [&](double (&av)[8], int g) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) av[u] = ap[(int64_t)(8 * g + u) * lda];
+    };
+    int g = 0;
+    if (full > 0) {
+        double a0[8], a1[8];
+        load8(a0, 0);
+        for (; g + 2 <= full; g += 2) {
+            load8(a1, g + 1);
+            update(a0, 8 * g);
+            load8(a0, min(g + 2, full - 1));
+            update(a1, 8 * g + 8);
+        }
+        if (g < full) {  // odd count: slot 0 holds the last full group
+            update(a0, 8 * g);
+            ++g;
+        }
+    }
+    const int i0 = 8 * g;
+    if (i0 < m8) {
+        double av[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u;
+            const double v = ap[(int64_t)(i < m ? i : m - 1) * lda];
+            av[u] = i < m ? v : 0.0;
+        }
+        update(av, i0);
     }
     if (!active) return;
     for (int j = 0; j < kj; ++j) {
