@@ -40,6 +40,7 @@ __device__ __forceinline__ void ab_partial_body(const ApplyArgs &a, const double
     constexpr int NO = AB_RB * KJ / 256;      // outputs per thread
     constexpr int NA = AB_RB * AB_TC / 256;   // staged elements of A per thread
     constexpr int NB = AB_TC * KJ / 256;      // staged elements of B per thread
+    static_assert(256 % KJ == 0 && 256 % AB_TC == 0, "thread coordinates assume these divide the block");
     __shared__ double As[AB_RB][AB_TC + 1];
     __shared__ double Bs[AB_TC][KJ];
     const int r0 = bx * AB_RB;
@@ -85,18 +86,18 @@ __device__ __forceinline__ void ab_partial_body(const ApplyArgs &a, const double
         for (int q = 0; q < NB; ++q) Bs[tt][(tid + 256 * q) / AB_TC] = rb[q];
         __syncthreads();
         load(tb + AB_TC);  // past t1 every address is the zero
-#pragma unroll
-        for (int q = 0; q < NO; ++q) {
-            const int o = tid + 256 * q;
-            const int rr = o / KJ, jj = o % KJ;
-            double sq = s[q], cq = c[q];
+        // a thread's outputs share their column jj (256 is a multiple of
+        // KJ): one LDS read of B per t serves all of them
+        const int jj = tid % KJ;
 #pragma unroll 8
-            for (int tt = 0; tt < AB_TC; ++tt) {
-                if (DD) dot2_acc(As[rr][tt], Bs[tt][jj], sq, cq);
-                else sq = __builtin_fma(As[rr][tt], Bs[tt][jj], sq);
+        for (int t2 = 0; t2 < AB_TC; ++t2) {
+            const double bv = Bs[t2][jj];
+#pragma unroll
+            for (int q = 0; q < NO; ++q) {
+                const double av = As[(tid + 256 * q) / KJ][t2];
+                if (DD) dot2_acc(av, bv, s[q], c[q]);
+                else s[q] = __builtin_fma(av, bv, s[q]);
             }
-            s[q] = sq;
-            c[q] = cq;
         }
         __syncthreads();
     }
