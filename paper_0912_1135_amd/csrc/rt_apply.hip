@@ -506,39 +506,66 @@ __global__ __launch_bounds__(256) void mtv_kernel(const double *M, int m, const 
     out[(int64_t)j * ldo + i] = s0 + s1;
 }
 
-__device__ __forceinline__ void dd_update_body(double *xhi, double *xlo, const double *D, int total, double *norms)
+// x = (xhi, xlo) + d in double-double, and norms = (|d|^2, |x_hi|^2), by one
+// block (any multiple of 64 threads, at most 1024).  Each thread loads U
+// elements' operands before any arithmetic; indices past total are clamped
+// for the loads and masked out of the stores and the norms.
+__device__ __forceinline__ void dd_update_body(double *__restrict__ xhi, double *__restrict__ xlo,
+                                               const double *__restrict__ D, int total, double *norms)
 {
 #pragma clang fp contract(off)
-    __shared__ double r0[256], r1[256];
+    constexpr int U = 4;
+    __shared__ double red[2][16];
+    const int nt = blockDim.x;
     double nd = 0.0, nx = 0.0;
-    for (int e = threadIdx.x; e < total; e += 256) {
-        const double d = D[e];
-        double s, err;
-        two_sum(xhi[e], d, s, err);
-        const double lo = xlo[e] + err;
-        const double hi = s + lo;
-        xlo[e] = lo - (hi - s);
-        xhi[e] = hi;
-        nd += d * d;
-        nx += hi * hi;
-    }
-    r0[threadIdx.x] = nd;
-    r1[threadIdx.x] = nx;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-            r0[threadIdx.x] += r0[threadIdx.x + s];
-            r1[threadIdx.x] += r1[threadIdx.x + s];
+    for (int e0 = threadIdx.x; e0 < total; e0 += U * nt) {
+        double d[U], h[U], l[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = min(e0 + u * nt, total - 1);
+            d[u] = D[e];
+            h[u] = xhi[e];
+            l[u] = xlo[e];
         }
-        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * nt;
+            double sm, err;
+            two_sum(h[u], d[u], sm, err);
+            const double lo = l[u] + err;
+            const double hi = sm + lo;
+            const double in = e < total ? 1.0 : 0.0;
+            nd += in * (d[u] * d[u]);
+            nx += in * (hi * hi);
+            if (e < total) {
+                xlo[e] = lo - (hi - sm);
+                xhi[e] = hi;
+            }
+        }
     }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        nd += __shfl_xor(nd, o, 64);
+        nx += __shfl_xor(nx, o, 64);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][w] = nd;
+        red[1][w] = nx;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        norms[0] = r0[0];
-        norms[1] = r1[0];
+        double a = 0.0, b = 0.0;
+        for (int v = 0; v < nt / 64; ++v) {
+            a += red[0][v];
+            b += red[1][v];
+        }
+        norms[0] = a;
+        norms[1] = b;
     }
 }
 
-__global__ __launch_bounds__(256) void dd_update_kernel(double *xhi, double *xlo, const double *D, int total,
+__global__ __launch_bounds__(1024) void dd_update_kernel(double *xhi, double *xlo, const double *D, int total,
                                                         double *norms)
 {
     dd_update_body(xhi, xlo, D, total, norms);
@@ -675,7 +702,7 @@ hipError_t apply_minv_f64(const double *T, int64_t ldt, const int32_t *piv, int 
 
 hipError_t dd_update_f64(double *Xhi, double *Xlo, const double *D, int m, int k, double *norms, hipStream_t stream)
 {
-    hipLaunchKernelGGL(dd_update_kernel, dim3(1), dim3(256), 0, stream, Xhi, Xlo, D, m * k, norms);
+    hipLaunchKernelGGL(dd_update_kernel, dim3(1), dim3(1024), 0, stream, Xhi, Xlo, D, m * k, norms);
     return hipGetLastError();
 }
 
