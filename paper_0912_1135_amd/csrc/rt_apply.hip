@@ -132,21 +132,35 @@ __global__ __launch_bounds__(256) void ab_partial_grouped(const AbGroupArgs *gs,
 // A once for KJ columns of B (compensated accumulators need twice the registers)
 inline int ab_kj(int k, int dd) { return k > 32 && !dd ? 64 : (k > 16 ? 32 : 16); }
 
+// Sum of the split partials in split order; the loads of eight splits are
+// issued before they are added (clamped indices, unconditional loads).
 __device__ __forceinline__ void ab_reduce_body(const double *ph, const double *pl, int m, int k, int splits, int dd,
                                                double *out, int64_t ldo, int64_t e)
 {
-    if (e >= (int64_t)m * k) return;
+    const int64_t mk = (int64_t)m * k;
+    if (e >= mk) return;
     const int j = (int)(e / m), row = (int)(e % m);
+    constexpr int U = 8;
     double s = 0.0, c = 0.0;
-    for (int p = 0; p < splits; ++p) {
-        const int64_t idx = (int64_t)p * m * k + e;
-        if (dd) {
-            double t, err;
-            two_sum(s, ph[idx], t, err);
-            s = t;
-            c += err + pl[idx];
-        } else {
-            s += ph[idx];
+    for (int p0 = 0; p0 < splits; p0 += U) {
+        double vh[U], vl[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t idx = (int64_t)min(p0 + u, splits - 1) * mk + e;
+            vh[u] = ph[idx];
+            vl[u] = dd ? pl[idx] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (p0 + u >= splits) break;
+            if (dd) {
+                double t, err;
+                two_sum(s, vh[u], t, err);
+                s = t;
+                c += err + vl[u];
+            } else {
+                s += vh[u];
+            }
         }
     }
     out[(int64_t)j * ldo + row] = s + c;
@@ -651,8 +665,9 @@ hipError_t ab_reduce_f64(const double *part_hi, const double *part_lo, int m, in
                          int64_t ldo, hipStream_t stream)
 {
     const int64_t total = (int64_t)m * k;
-    hipLaunchKernelGGL(ab_reduce_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, part_hi, part_lo,
-                       m, k, splits, dd, out, ldo);
+    // 64-thread blocks: m k is small (thousands), so spread it over more CUs
+    hipLaunchKernelGGL(ab_reduce_kernel, dim3((unsigned)((total + 63) / 64)), dim3(64), 0, stream, part_hi, part_lo, m,
+                       k, splits, dd, out, ldo);
     return hipGetLastError();
 }
 
