@@ -75,6 +75,12 @@ hipError_t sq_mm_f64(int m, const double *A, const double *B, double *out, doubl
                      hipStream_t stream);
 inline int64_t sq_mm_blocks(int64_t m) { return ((m + 15) / 16) * ((m + 15) / 16); }
 
+// out(i, j) = sum_r A[i lda + r] B[j ldb + r], i < M, j < N, r < K: A
+// row-major, B and out column-major (out[j ldo + i]; out must not alias A or
+// B).  One launch, one block per 16 x 16 tile of out, K split over its waves.
+hipError_t skinny_mm_f64(int M, int N, int K, const double *A, int64_t lda, const double *B, int64_t ldb, double *out,
+                         int64_t ldo, hipStream_t stream);
+
 // Grouped GEMM: one launch over `count` problems whose GemmArgs live in
 // device memory.  Every member must share the operand layouts (a_k == 1,
 // b_k == 1) and c_lower given here; M, N and ksplit here are the maxima

@@ -419,7 +419,95 @@ __global__ __launch_bounds__(64) void sq_mm_kernel(int m, const double *__restri
     if (lane == 0) bsum[blockIdx.x] = qs;
 }
 
+// Skinny products of the M^{-1} application: out(i, j) = sum_r A[i lda + r]
+// B[j ldb + r] for i < M, j < N (A row-major, B and out column-major, out[j
+// ldo + i]), N a block of right-hand sides.  One block of 4 waves per 16 x 16
+// tile of out; the waves take quarters of K and add their tiles through LDS
+// in wave order, so one launch does the whole product.  Elements outside the
+// problem are read from a shared zero (the address is selected, not the
+// value), so every load is unconditional and the two register slots of 64 k
+// stay in flight in turn.
+__device__ double g_zero_mm = 0.0;
+
+constexpr int SK_U = 16;  // k-steps of 4 per slot
+
+__device__ __forceinline__ void skinny_load(double (&av)[SK_U], double (&bv)[SK_U], const double *ap,
+                                            const double *bp, bool iok, bool jok, int k0, int ke, int q)
+{
+#pragma unroll
+    for (int u = 0; u < SK_U; ++u) {
+        const int k = k0 + 4 * u + q;
+        const bool kin = k < ke;
+        av[u] = *((iok && kin) ? ap + k : &g_zero_mm);
+        bv[u] = *((jok && kin) ? bp + k : &g_zero_mm);
+    }
+}
+
+__global__ __launch_bounds__(256) void skinny_mm_kernel(int M, int N, int K, const double *__restrict__ A,
+                                                        int64_t lda, const double *__restrict__ B, int64_t ldb,
+                                                        double *__restrict__ out, int64_t ldo)
+{
+    __shared__ double red[3][4][64];
+    const int tm = (M + 15) / 16;
+    const int ti = blockIdx.x % tm, tj = blockIdx.x / tm;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r = lane & 15, q = lane >> 4;
+    const int i = ti * 16 + r, j = tj * 16 + r;
+    const bool iok = i < M, jok = j < N;
+    const double *ap = A + (int64_t)(iok ? i : 0) * lda;
+    const double *bp = B + (int64_t)(jok ? j : 0) * ldb;
+    constexpr int KG = 4 * SK_U;
+    const int kq = ((K + 3) / 4 + KG - 1) / KG * KG;  // this wave's quarter, whole slots
+    const int kb = w * kq, ke = min(K, kb + kq);
+    double4v acc0 = double4v{0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+    double a0[SK_U], b0[SK_U], a1[SK_U], b1[SK_U];
+    skinny_load(a0, b0, ap, bp, iok, jok, kb, ke, q);
+    for (int k0 = kb; k0 < ke; k0 += 2 * KG) {
+        skinny_load(a1, b1, ap, bp, iok, jok, k0 + KG, ke, q);
+#pragma unroll
+        for (int u = 0; u < SK_U; u += 2) {
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], b0[u], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u + 1], b0[u + 1], acc1, 0, 0, 0);
+        }
+        skinny_load(a0, b0, ap, bp, iok, jok, k0 + 2 * KG, ke, q);
+#pragma unroll
+        for (int u = 0; u < SK_U; u += 2) {
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], b1[u], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u + 1], b1[u + 1], acc1, 0, 0, 0);
+        }
+    }
+    double v[4];
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) v[rr] = acc0[rr] + acc1[rr];
+    if (w > 0) {
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) red[w - 1][rr][lane] = v[rr];
+    }
+    __syncthreads();
+    if (w != 0) return;
+#pragma unroll
+    for (int x = 0; x < 3; ++x)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) v[rr] += red[x][rr][lane];
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+        const int oi = ti * 16 + mfma16_row(lane, rr), oj = tj * 16 + mfma16_col(lane);
+        if (oi < M && oj < N) out[(int64_t)oj * ldo + oi] = v[rr];
+    }
+}
+
 }  // namespace
+
+hipError_t skinny_mm_f64(int M, int N, int K, const double *A, int64_t lda, const double *B, int64_t ldb, double *out,
+                         int64_t ldo, hipStream_t stream)
+{
+    if (M <= 0 || N <= 0) return hipSuccess;
+    if (K <= 0) return hipErrorInvalidValue;
+    const int64_t nb = (int64_t)((M + 15) / 16) * ((N + 15) / 16);
+    if (nb > INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(skinny_mm_kernel, dim3((unsigned)nb), dim3(256), 0, stream, M, N, K, A, lda, B, ldb, out, ldo);
+    return hipGetLastError();
+}
 
 hipError_t sq_mm_f64(int m, const double *A, const double *B, double *out, double scale, double diag, double *bsum,
                      hipStream_t stream)

@@ -550,10 +550,25 @@ int auto_refine_steps(double kappa_est, int precision, bool w32, double cond_w)
 // steps 2-6): Newton-Schulz route H = T'^T (Y (T' C)), Cholesky route
 // H = T'^T (T' C), with d_Tp holding T'^T (row-major) followed by T'.  MFMA
 // GEMMs with the K = m contraction split over blocks and reduced in a fixed
-// order.  H must not alias C.
+// order, or (up to RT_SKINNY_KMAX right-hand sides) one launch per product
+// with K split over the waves of each block.  H must not alias C.
 rtproj_status apply_minv(rtproj_plan p, const double *C, int64_t ldc, double *H, int64_t ldh, int64_t k)
 {
     const int64_t m = p->m;
+    if (k <= RT_SKINNY_KMAX) {
+        // one launch per product: blocks of 16 x 16 output tiles, K split
+        // over the waves of a block
+        const bool ns = p->inv_used == RTPROJ_INV_NEWTON_SCHULZ;
+        const double *Tp = p->d_Tp + m * m, *TpT = p->d_Tp;  // T' and T'^T, row-major
+        if (ns) {
+            RT_HIP(rt::skinny_mm_f64((int)m, (int)k, (int)m, Tp, m, C, ldc, H, ldh, p->stream));
+            RT_HIP(rt::skinny_mm_f64((int)m, (int)k, (int)m, p->d_L, m, H, ldh, p->d_tmp, m, p->stream));
+        } else {
+            RT_HIP(rt::skinny_mm_f64((int)m, (int)k, (int)m, Tp, m, C, ldc, p->d_tmp, m, p->stream));
+        }
+        RT_HIP(rt::skinny_mm_f64((int)m, (int)k, (int)m, TpT, m, p->d_tmp, m, H, ldh, p->stream));
+        return RTPROJ_OK;
+    }
     const int splits = (int)std::max<int64_t>(1, std::min<int64_t>(p->ab_splits, (m + 63) / 64));
     if (p->inv_used == RTPROJ_INV_NEWTON_SCHULZ) {
         // H = T' C;  d_tmp = Y H;  H = T'^T d_tmp

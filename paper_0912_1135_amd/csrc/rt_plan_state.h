@@ -58,6 +58,9 @@ constexpr int RT_NS_MAX_IT = 64;
 // Largest m whose Newton-Schulz products run as one fused launch per product
 // (one wave per 16 x 16 tile, whole K; its L2 reads grow as m^3).
 constexpr int64_t RT_NS_FUSED_MAX_M = 256;
+// Largest block of right-hand sides whose M^{-1} products run as one launch
+// each (skinny product kernel) instead of a split GEMM and its reduction.
+constexpr int64_t RT_SKINNY_KMAX = 64;
 
 // ------------------------------------------------------------ random tables
 // SplitMix64 (Steele, Lea and Flood, 2014): the state advances by the golden
