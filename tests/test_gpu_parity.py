@@ -67,6 +67,7 @@ def errors(B, Z, Y, X, Zr, Yr, Xr):
     (600, 8192, 4096, 1e6, 2, 7),          # tall sketch: register-resident QR, 8 rows per thread
     (600, 16384, 9000, 1e6, 2, 8),         # taller than the register form: QR columns in global memory
     (200, 6000, 800, 1e6, 40, 9),          # k >= 32: the plain A B pass on MFMA
+    (96, 3000, 384, 1e6, 70, 12),          # k > 64: M^{-1} by split GEMMs, not the skinny products
 ])
 def test_projection_matches_oracle(rt, m, n, l, kappa, k, seed):
     A = synth.make_problem(m, n, kappa, seed)
