@@ -42,16 +42,17 @@ constexpr double RT_COND_ESCALATE = 10.0;
 // m^3 products, latency-light) up to this m, the blocked Cholesky (m^3 / 3,
 // but a chain of small diagonal steps) above it.
 constexpr int64_t RT_NS_MAX_M = 1024;
-// Newton-Schulz: iterations of the first round (Y_0 = I / |X|_inf converges
-// within it for |X|_inf / lambda_min(X) up to about 100; a Gram sketched at
-// l = 4m has |X|_inf about 5 lambda_max and condition about 8.5, and needs
-// 11 steps), the residual
+// Newton-Schulz: iterations of the first round, after the first step from
+// a I (a = 1 / |X|_inf) that the start kernel forms elementwise (a Gram
+// sketched at l = 4m has |X|_inf about 5 lambda_max and condition about 8.5;
+// its residual is below 1e-10 after these; harder Grams take further rounds
+// sized from the measured residual), the residual
 // |I - X Y_k|_F below which Y_{k+1} is final, the largest residual accepted
 // as a rounding floor once it stops squaring, and the iteration cap.  The
 // iterates are used as computed, never symmetrised: I - X Y_{k+1} =
 // (I - X Y_k)^2 holds for any Y_k, while a symmetrised product drifts when the
 // computed Y_k does not commute with X.
-constexpr int RT_NS_FIRST = 12;
+constexpr int RT_NS_FIRST = 10;
 constexpr double RT_NS_DONE = 1e-6;
 constexpr double RT_NS_FLOOR = 1e-4;
 constexpr int RT_NS_MAX_IT = 64;
