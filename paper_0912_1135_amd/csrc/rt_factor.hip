@@ -319,20 +319,44 @@ __global__ void place_diag_blocks_kernel(const double *Dinv, int m, int nb, doub
 // affine reduction also yields the Frobenius norm of (out - I) in block
 // partials, combined in a fixed order.
 
+// 16 rows per block, 4 per wave: the row maxima meet in LDS and one thread
+// per block posts them, so the two slots see two atomics per block rather
+// than two per row.
+constexpr int NSN_ROWS_PER_WAVE = 4;
+
 __global__ __launch_bounds__(256) void ns_norms_kernel(const double *X, int m, unsigned long long *slots)
 {
-    const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-    if (row >= m) return;  // the whole wave
-    const double *x = X + (int64_t)row * m;
-    double s = 0.0;
-    for (int j = lane; j < m; j += 64) s += fabs(x[j]);
+    __shared__ double wmax[2][4];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r0 = (blockIdx.x * 4 + w) * NSN_ROWS_PER_WAVE;
+    double rs = 0.0, dg = 0.0;  // largest absolute row sum and positive diagonal entry of this wave
+    for (int r = 0; r < NSN_ROWS_PER_WAVE; ++r) {
+        const int row = r0 + r;
+        if (row >= m) break;  // uniform across the wave
+        const double *x = X + (int64_t)row * m;
+        double s = 0.0;
+        for (int j = lane; j < m; j += 64) s += fabs(x[j]);
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if (lane == 0) {
-        // non-negative doubles order like their bit patterns (NaN above all)
-        atomicMax(slots + 0, (unsigned long long)__double_as_longlong(s));
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        // fmax drops a NaN operand: keep NaN row sums by comparing as below
+        rs = (s > rs || s != s) ? s : rs;
         const double d = x[row];
-        atomicMax(slots + 1, (unsigned long long)__double_as_longlong(d > 0.0 ? d : 0.0));
+        dg = d > dg ? d : dg;
+    }
+    if (lane == 0) {
+        wmax[0][w] = rs;
+        wmax[1][w] = dg;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = wmax[0][0], b = wmax[1][0];
+        for (int v = 1; v < 4; ++v) {
+            a = (wmax[0][v] > a || wmax[0][v] != wmax[0][v]) ? wmax[0][v] : a;
+            b = wmax[1][v] > b ? wmax[1][v] : b;
+        }
+        // non-negative doubles order like their bit patterns (NaN above all)
+        atomicMax(slots + 0, (unsigned long long)__double_as_longlong(a));
+        atomicMax(slots + 1, (unsigned long long)__double_as_longlong(b));
     }
 }
 
@@ -497,7 +521,9 @@ hipError_t form_tp_grouped_f64(const MatGroupArgs *d, int count, int64_t max_tot
 hipError_t ns_norms_f64(const double *X, int m, unsigned long long *slots, hipStream_t stream)
 {
     if (m <= 0) return hipSuccess;
-    hipLaunchKernelGGL(ns_norms_kernel, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, stream, X, m, slots);
+    const int rows_per_block = 4 * NSN_ROWS_PER_WAVE;
+    hipLaunchKernelGGL(ns_norms_kernel, dim3((unsigned)((m + rows_per_block - 1) / rows_per_block)), dim3(256), 0,
+                       stream, X, m, slots);
     return hipGetLastError();
 }
 
