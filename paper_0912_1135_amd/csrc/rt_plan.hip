@@ -85,6 +85,8 @@ void release(rtproj_plan p)
                     p->d_err};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
+    if (p->h_scal) (void)hipHostFree(p->h_scal);
+    p->h_scal = nullptr;
 }
 
 rtproj_status upload_tables(rtproj_plan p)
@@ -214,6 +216,7 @@ rtproj_status alloc_state(rtproj_plan p)
         RT_HIP(hipMemcpy(p->d_wgargs, &wa, sizeof(wa), hipMemcpyHostToDevice));
     }
     RT_HIP(dalloc(&p->d_scal, 8));
+    RT_HIP(hipHostMalloc((void **)&p->h_scal, 4 * sizeof(unsigned long long), hipHostMallocDefault));
     RT_HIP(dalloc(&p->d_diag, 8));
     RT_HIP(dalloc(&p->d_err, 4));
     RT_HIP(dalloc(&p->d_rowscale, (size_t)m));
@@ -543,6 +546,19 @@ int auto_refine_steps(double kappa_est, int precision, bool w32, double cond_w)
     int a, b;
     auto_refine_plan(kappa_est, precision, w32, cond_w, &a, &b);
     return a + b;
+}
+
+// Conditioning estimate of the Newton-Schulz route from the norm slots
+// copied to h_scal (the stream must have passed that copy): X_ii <=
+// lambda_max(X) and Y_ii <= 1 / lambda_min(X).
+void resolve_cond(rtproj_plan p)
+{
+    if (!p->cond_pending) return;
+    double dx, dy;
+    std::memcpy(&dx, &p->h_scal[1], 8);
+    std::memcpy(&dy, &p->h_scal[3], 8);
+    p->info.gram_cond_est = (dx > 0 && dy > 0 && std::isfinite(dx * dy)) ? std::sqrt(dx * dy) : INFINITY;
+    p->cond_pending = false;
 }
 
 // H = M^{-1} C = (A A^T)^{-1} C for an m x k column-major block C, applied
@@ -1036,6 +1052,7 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
     p->info.inverse = p->inv_used;
     p->info.inverse_iters = 0;
     p->info.inverse_resid = 0.0;
+    p->cond_pending = false;
     if (p->inv_used == RTPROJ_INV_NEWTON_SCHULZ) {
         {
             StageScope sc(p, 5);
@@ -1047,14 +1064,14 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
             st = form_factors_ns(p);
         }
         if (st != RTPROJ_OK) return st;
-        unsigned long long sl[4];
-        RT_HIP(hipMemcpyAsync(sl, p->d_scal, 32, hipMemcpyDeviceToHost, s));
-        RT_HIP(hipStreamSynchronize(s));
-        double dx, dy;
-        std::memcpy(&dx, &sl[1], 8);
-        std::memcpy(&dy, &sl[3], 8);
-        // X_ii <= lambda_max(X) and Y_ii <= 1 / lambda_min(X)
-        p->info.gram_cond_est = (dx > 0 && dy > 0 && std::isfinite(dx * dy)) ? std::sqrt(dx * dy) : INFINITY;
+        RT_HIP(hipMemcpyAsync(p->h_scal, p->d_scal, 32, hipMemcpyDeviceToHost, s));
+        p->cond_pending = true;
+        // the mixed forms decide on a re-sketch from the estimate now; at
+        // binary64 nothing before rtproj_plan_info needs it
+        if (p->precision != RTPROJ_PREC_FP64) {
+            RT_HIP(hipStreamSynchronize(s));
+            resolve_cond(p);
+        }
         return RTPROJ_OK;
     }
     // 6. Cholesky X = L L^T
@@ -1151,6 +1168,7 @@ rtproj_status rtproj_plan_info(rtproj_plan p, rtproj_info *out)
 {
     if (!p || !out) return fail(RTPROJ_ERR_INVALID_ARG, "null argument");
     RT_HIP(hipStreamSynchronize(p->stream));
+    resolve_cond(p);
     collect_timing(p);
     *out = p->info;
     return RTPROJ_OK;

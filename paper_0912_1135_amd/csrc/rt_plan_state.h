@@ -193,6 +193,11 @@ struct rtproj_plan_s {
     int64_t lda = 0;
     bool ready = false;
     rtproj_info info{};
+    // binary64 preconditions copy the Newton-Schulz norm slots here without
+    // waiting (the refinement planner does not use the conditioning estimate
+    // at binary64); rtproj_plan_info waits on the stream and derives it
+    unsigned long long *h_scal = nullptr;  // pinned, 4 slots
+    bool cond_pending = false;
     // stage timing (HIP events on the plan's stream)
     bool timing = false;
     struct StageEvents { int stage; hipEvent_t start, stop; };
