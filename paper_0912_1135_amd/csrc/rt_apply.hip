@@ -1,17 +1,17 @@
-// The projection: the seven steps of Sec. 4 applied to blocks of k right-hand
-// sides, and the refinement of the least-squares solution (Remark 4.3).
+// The passes over A of the projection (Sec. 4, steps 1 and 7) and of the
+// refinement of the least-squares solution (Remark 4.3); the m x m products
+// of steps 2-6 (x = M^{-1} c) are GEMMs issued by the plan.
 //
-//   c = A b                          ab_partial + ab_reduce   (step 1)
-//   h = Pi^T R^{-1} L^{-T} L^{-1} R^{-T} Pi c                (steps 2-6)
-//                                    apply_minv, with T' = L^{-1} R^{-T} Pi
-//                                    stored explicitly: h = T'^T (T' c)
-//   b~ = A^T h, z = b - b~           atx                      (step 7)
+//   c = A b                 ab_sx (plain, b in scalar registers) or
+//                           ab_partial (LDS-staged; Dot2), then ab_reduce
+//   b~ = A^T x, z = b - b~  atx_dd_sx (Dot2, x in scalar registers) or atx
 //
 // Refinement: r = b - A^T x and s = A r are accumulated with Dot2 (error-free
 // products and sums, i.e. about twice binary64 precision) and x is kept as an
 // unevaluated pair (x_hi, x_lo).  The contractions over the long dimension n
-// are VALU kernels that stream A once per pass with coalesced loads; the
-// right-hand-side blocks are small and staged through LDS.
+// are VALU kernels that stream A once per pass (or per block of right-hand
+// sides) with coalesced loads kept in flight; the right-hand-side blocks are
+// small and read from scalar registers or LDS.
 #include "rt_common.h"
 
 #include <algorithm>
@@ -502,24 +502,6 @@ __global__ __launch_bounds__(256) void ab_sx_kernel(int m, int n, int k, const d
 // occupancy than the extra pass over A)
 inline int atx_kj(int k, int dd) { return dd ? 16 : (k > 32 ? 64 : (k > 16 ? 32 : 16)); }
 
-// out(i, j) = sum_r M[r*m + i] * V[r + j*ldv]  (out = M^T V, M row-major m x m)
-__global__ __launch_bounds__(256) void mtv_kernel(const double *M, int m, const double *V, int64_t ldv, double *out,
-                                                  int64_t ldo)
-{
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    const int j = blockIdx.y;
-    if (i >= m) return;
-    const double *v = V + (int64_t)j * ldv;
-    double s0 = 0.0, s1 = 0.0;
-    int r = 0;
-    for (; r + 1 < m; r += 2) {
-        s0 = __builtin_fma(M[(int64_t)r * m + i], v[r], s0);
-        s1 = __builtin_fma(M[(int64_t)(r + 1) * m + i], v[r + 1], s1);
-    }
-    if (r < m) s0 = __builtin_fma(M[(int64_t)r * m + i], v[r], s0);
-    out[(int64_t)j * ldo + i] = s0 + s1;
-}
-
 // x = (xhi, xlo) + d in double-double, and norms = (|d|^2, |x_hi|^2), by one
 // block (any multiple of 64 threads, at most 1024).  Each thread loads U
 // elements' operands before any arithmetic; indices past total are clamped
@@ -695,23 +677,6 @@ hipError_t atx_f64(const ApplyArgs &a, const double *Xhi, const double *Xlo, int
                            Y, ldy, Z, ldz);
     ATX_CASE(true, 16) ATX_CASE(false, 16) ATX_CASE(false, 32) ATX_CASE(false, 64)
 #undef ATX_CASE
-    return hipGetLastError();
-}
-
-hipError_t apply_minv_f64(const double *T, int64_t ldt, const int32_t *piv, int m, int k, const double *C, int64_t ldc,
-                          double *tmp, double *H, int64_t ldh, hipStream_t stream)
-{
-    // T holds T'^T (row-major), i.e. T'(i, r) = T[r*m + i]; H = T'^T (T' C).
-    // tmp = T' C: tmp(i, j) = sum_r T'(i, r) C(r, j) = sum_r T[r*m + i] C(r, j)
-    (void)ldt;
-    (void)piv;
-    dim3 grid((m + 255) / 256, k);
-    hipLaunchKernelGGL(mtv_kernel, grid, dim3(256), 0, stream, T, m, C, ldc, tmp, (int64_t)m);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    // H(i, j) = sum_r T'(r, i) tmp(r, j) = sum_r T'[r*m + i] ...: needs T' row-major,
-    // which is stored right after T'^T.
-    hipLaunchKernelGGL(mtv_kernel, grid, dim3(256), 0, stream, T + (int64_t)m * m, m, tmp, (int64_t)m, H, ldh);
     return hipGetLastError();
 }
 

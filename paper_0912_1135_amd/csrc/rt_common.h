@@ -306,12 +306,6 @@ hipError_t scale_cols_grouped_f64(const ScaleGroupArgs *d, int count, hipStream_
 struct CopyGroupArgs { const double *src; int64_t lds; double *dst; int64_t ldd; int rows, cols; double *zero_out; int64_t ldz; };
 hipError_t copy_cols_grouped_f64(const CopyGroupArgs *d, int count, int64_t max_total, hipStream_t stream);
 
-// H (m x k, col-major) = Pi^T T^T T Pi C  (the seven-step core with
-// P^{-1} = R^{-T} Pi and Y = X^{-1} = L^{-T} L^{-1} folded into T = L^{-1} R^{-T}).
-// tmp: m*k doubles.
-hipError_t apply_minv_f64(const double *T, int64_t ldt, const int32_t *piv, int m, int k,
-                          const double *C, int64_t ldc, double *tmp, double *H, int64_t ldh,
-                          hipStream_t stream);
 // (Xhi, Xlo) += D (double-binary64 update); norms[0] = |D|_F^2, norms[1] = |Xhi|_F^2.
 hipError_t dd_update_f64(double *Xhi, double *Xlo, const double *D, int m, int k, double *norms,
                          hipStream_t stream);
