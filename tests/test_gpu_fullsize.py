@@ -1,0 +1,114 @@
+"""GPU path at the full sizes of the measured workloads (marker: gpu).
+
+* 512 x 65536 (k = 16, kappa = 1e10), the plan exactly as the throughput
+  bench runs it (default pivoted QR, inverse and refinement plan): every
+  column is projected, and sampled columns are compared element by element
+  with the oracle, <= 1e-10 relative (z and the row projection relative to
+  |b|, x relative to |x|).
+* 2048 x 262144 (k = 64, kappa = 1e8), too large for the oracle within a
+  test: properties that hold at any size, with the products taken by torch
+  (not by this library's kernels): z orthogonal to the rows of A, z + p = b,
+  |z|^2 + |p|^2 = |b|^2, and z within 1e-6 of b - V V^T b for the
+  generator's own V (the rounding of the stored A tilts its row space away
+  from span(V) by about 2^-53 |A| / sigma_min = 1e-8, so this reference is
+  independent but loose).  The binary32-Gram form must agree with the
+  binary64 form to 1e-10.
+
+A^T x is not checked by a plain product here: with kappa >= 1e8, |x| is of
+order kappa |b| and a binary64 product loses kappa times the unit roundoff
+to cancellation, which is why the library forms it compensated.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_0912_1135_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def rt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0912_1135_amd as rt
+    rt.lib()
+    return rt
+
+
+def dev():
+    return torch.device("cuda", 0)
+
+
+@pytest.mark.timeout(400)
+def test_plain_512x65536_sampled_columns_match_oracle(rt):
+    c = synth.CONFIGS["plain_512x65536"]
+    m, n, l, k = c["m"], c["n"], c["l"], c["k"]
+    A, _, sv, _ = synth.make_problem(m, n, c["kappa"], c["seed"], with_factors=True)
+    B = synth.make_rhs(n, k, c["seed"])
+    plan = rt.Plan(m, n, l, c["seed"])
+    At = torch.from_numpy(A).to(dev())
+    Bt = torch.from_numpy(B).to(dev())
+    plan.precondition(At)
+    Z, Y, X = plan.project_all(Bt)
+    torch.cuda.synchronize()
+    Z, Y, X = Z.cpu().numpy(), Y.cpu().numpy(), X.cpu().numpy()
+    cols = [0, 11]
+    Zr, Yr, Xr, _ = oracle.project(A, B[cols].T)
+    for i, j in enumerate(cols):
+        nb = np.linalg.norm(B[j])
+        ez = np.linalg.norm(Z[j] - Zr[:, i]) / nb
+        ey = np.linalg.norm(Y[j] - Yr[:, i]) / nb
+        ex = np.linalg.norm(X[j] - Xr[:, i]) / np.linalg.norm(Xr[:, i])
+        assert ez <= TOL and ey <= TOL and ex <= TOL, (j, ez, ey, ex)
+    # every column, not only the sampled ones: z + p = b and z orthogonal to
+    # the rows of A, with the product taken in numpy
+    nbs = np.linalg.norm(B, axis=1)
+    assert np.max(np.linalg.norm(B - Z - Y, axis=1) / nbs) <= 1e-14
+    na = sv[0]  # |A|_2, the generator's largest singular value
+    assert np.max(np.linalg.norm(Z @ A.T, axis=1) / (na * np.linalg.norm(Z, axis=1))) <= 1e-12
+    plan.close()
+
+
+def _properties(A, na, B, Z, Y, Zv):
+    """Largest relative residuals of the defining properties over the columns."""
+    nb = torch.linalg.vector_norm(B, dim=1)
+    az = torch.linalg.vector_norm(Z @ A.T, dim=1) / (na * torch.linalg.vector_norm(Z, dim=1))
+    split = torch.linalg.vector_norm(B - Z - Y, dim=1) / nb
+    pyth = (torch.linalg.vector_norm(Z, dim=1) ** 2 + torch.linalg.vector_norm(Y, dim=1) ** 2 - nb ** 2).abs() / nb ** 2
+    vref = torch.linalg.vector_norm(Z - Zv, dim=1) / nb
+    return az.max().item(), split.max().item(), pyth.max().item(), vref.max().item()
+
+
+@pytest.mark.timeout(600)
+def test_mixed_2048x262144_properties(rt):
+    c = synth.CONFIGS["mixed_2048x262144"]
+    m, n, l, k = c["m"], c["n"], c["l"], c["k"]
+    A, _, sv, V = synth.make_problem(m, n, c["kappa"], c["seed"], with_factors=True)
+    At = torch.from_numpy(A).to(dev())
+    Vt = torch.from_numpy(V).to(dev())
+    del A, V
+    Bt = torch.from_numpy(synth.make_rhs(n, k, c["seed"])).to(dev())
+    Zv = Bt - (Bt @ Vt) @ Vt.T   # b - V V^T b, one row per right-hand side
+    del Vt
+    na = float(sv[0])  # |A|_2, the generator's largest singular value
+    out = {}
+    for prec in (rt.PREC_FP64, rt.PREC_MIXED_FP32):
+        plan = rt.Plan(m, n, l, c["seed"])
+        plan.set_precision(prec)
+        plan.precondition(At)
+        out[prec] = plan.project_all(Bt)
+        torch.cuda.synchronize()
+        plan.close()
+    for prec, (Z, Y, X) in out.items():
+        az, split, pyth, vref = _properties(At, na, Bt, Z, Y, Zv)
+        assert az <= 1e-12 and split <= 1e-14 and pyth <= 1e-12 and vref <= 1e-6, (prec, az, split, pyth, vref)
+    (Z0, Y0, X0), (Z1, Y1, X1) = out[rt.PREC_FP64], out[rt.PREC_MIXED_FP32]
+    nb = torch.linalg.vector_norm(Bt, dim=1)
+    ez = (torch.linalg.vector_norm(Z1 - Z0, dim=1) / nb).max().item()
+    ey = (torch.linalg.vector_norm(Y1 - Y0, dim=1) / nb).max().item()
+    ex = (torch.linalg.vector_norm(X1 - X0, dim=1) / torch.linalg.vector_norm(X0, dim=1)).max().item()
+    assert ez <= TOL and ey <= TOL and ex <= TOL, (ez, ey, ex)
