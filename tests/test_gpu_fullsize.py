@@ -13,6 +13,8 @@
   from span(V) by about 2^-53 |A| / sigma_min = 1e-8, so this reference is
   independent but loose).  The binary32-Gram form must agree with the
   binary64 form to 1e-10.
+* the 256-member batch (uneven shapes), recorded and replayed from a HIP
+  graph: sampled members, the largest among them, against the oracle.
 
 A^T x is not checked by a plain product here: with kappa >= 1e8, |x| is of
 order kappa |b| and a binary64 product loses kappa times the unit roundoff
@@ -112,3 +114,36 @@ def test_mixed_2048x262144_properties(rt):
     ey = (torch.linalg.vector_norm(Y1 - Y0, dim=1) / nb).max().item()
     ex = (torch.linalg.vector_norm(X1 - X0, dim=1) / torch.linalg.vector_norm(X0, dim=1)).max().item()
     assert ez <= TOL and ey <= TOL and ex <= TOL, (ez, ey, ex)
+
+
+@pytest.mark.timeout(600)
+def test_batch_256_sampled_members_match_oracle(rt):
+    # the 256 uneven members as the bench builds them, two graph replays (the
+    # first records, the second replays on the same data)
+    c = synth.CONFIGS["batch_256"]
+    count, kappa, seed = c["count"], c["kappa"], c["seed"]
+    shp = synth.make_batch_shapes(count, seed)
+    As = [synth.make_problem(m, n, kappa, seed + 1000 + i) for i, (m, n) in enumerate(zip(shp.m, shp.n))]
+    Bs = [synth.make_rhs(n, k, seed + 5000 + i) for i, (n, k) in enumerate(zip(shp.n, shp.k))]
+    At = [torch.from_numpy(A).to(dev()) for A in As]
+    Bt = [torch.from_numpy(B).to(dev()) for B in Bs]
+    Z = [torch.empty_like(b) for b in Bt]
+    Y = [torch.empty_like(b) for b in Bt]
+    X = [torch.empty((k, m), dtype=torch.float64, device=dev()) for m, k in zip(shp.m, shp.k)]
+    bt = rt.Batch(shp.m, shp.n, shp.l, seed)
+    bt.set_graph(True)
+    for _ in range(2):
+        bt.precondition(At)
+        bt.project_all(Bt, Z, Y, X)
+    torch.cuda.synchronize()
+    assert all(s == 0 for s in bt.status())
+    big = int(np.argmax(np.asarray(shp.m) * np.asarray(shp.n)))
+    for i in sorted({0, 97, 200, count - 1, big}):
+        Zr, Yr, Xr, _ = oracle.project(As[i], Bs[i].T)
+        Zi, Yi, Xi = Z[i].cpu().numpy(), Y[i].cpu().numpy(), X[i].cpu().numpy()
+        nb = np.linalg.norm(Bs[i], axis=1)
+        ez = np.max(np.linalg.norm(Zi - Zr.T, axis=1) / nb)
+        ey = np.max(np.linalg.norm(Yi - Yr.T, axis=1) / nb)
+        ex = np.max(np.linalg.norm(Xi - Xr.T, axis=1) / np.linalg.norm(Xr.T, axis=1))
+        assert ez <= TOL and ey <= TOL and ex <= TOL, (i, ez, ey, ex)
+    bt.close()
