@@ -15,6 +15,9 @@
   binary64 form to 1e-10.
 * the 256-member batch (uneven shapes), recorded and replayed from a HIP
   graph: sampled members, the largest among them, against the oracle.
+* the 32-step interior-point sequence A D_t at 1024 x 131072 (k = 128),
+  batched and graph-replayed: steps 0 and 31, two right-hand sides each,
+  against the oracle on A D_t.
 
 A^T x is not checked by a plain product here: with kappa >= 1e8, |x| is of
 order kappa |b| and a binary64 product loses kappa times the unit roundoff
@@ -146,4 +149,39 @@ def test_batch_256_sampled_members_match_oracle(rt):
         ey = np.max(np.linalg.norm(Yi - Yr.T, axis=1) / nb)
         ex = np.max(np.linalg.norm(Xi - Xr.T, axis=1) / np.linalg.norm(Xr.T, axis=1))
         assert ez <= TOL and ey <= TOL and ex <= TOL, (i, ez, ey, ex)
+    bt.close()
+
+
+@pytest.mark.timeout(600)
+def test_ipm_1024x131072_sampled_steps_match_oracle(rt):
+    # the 32 rescaled problems A D_t as the bench batches them (graph replay);
+    # steps 0 and 31, two right-hand sides each, against the oracle on A D_t
+    c = synth.CONFIGS["ipm_1024x131072"]
+    m, n, l, k, steps, kappa, seed = c["m"], c["n"], c["l"], c["k"], c["steps"], c["kappa"], c["seed"]
+    A = synth.make_problem(m, n, kappa, seed)
+    D = synth.make_scalings(n, steps, seed)
+    At = torch.from_numpy(A).to(dev())
+    Dt = [torch.from_numpy(np.ascontiguousarray(D[t])).to(dev()) for t in range(steps)]
+    Bs = [synth.make_rhs(n, k, seed + 100 + t) for t in range(steps)]
+    Bt = [torch.from_numpy(B).to(dev()) for B in Bs]
+    Z = [torch.empty_like(b) for b in Bt]
+    Y = [torch.empty_like(b) for b in Bt]
+    X = [torch.empty((k, m), dtype=torch.float64, device=dev()) for _ in range(steps)]
+    bt = rt.Batch([m] * steps, [n] * steps, [l] * steps, seed)
+    bt.set_graph(True)
+    for _ in range(2):
+        bt.precondition([At] * steps, Dt)
+        bt.project_all(Bt, Z, Y, X)
+    torch.cuda.synchronize()
+    assert all(s == 0 for s in bt.status())
+    cols = [0, k - 1]
+    for t in (0, steps - 1):
+        AD = A * D[t][None, :]
+        Zr, Yr, Xr, _ = oracle.project(AD, Bs[t][cols].T)
+        Zt, Yt, Xt = Z[t].cpu().numpy()[cols], Y[t].cpu().numpy()[cols], X[t].cpu().numpy()[cols]
+        nb = np.linalg.norm(Bs[t][cols], axis=1)
+        ez = np.max(np.linalg.norm(Zt - Zr.T, axis=1) / nb)
+        ey = np.max(np.linalg.norm(Yt - Yr.T, axis=1) / nb)
+        ex = np.max(np.linalg.norm(Xt - Xr.T, axis=1) / np.linalg.norm(Xr.T, axis=1))
+        assert ez <= TOL and ey <= TOL and ex <= TOL, (t, ez, ey, ex)
     bt.close()
