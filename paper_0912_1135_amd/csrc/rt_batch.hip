@@ -16,6 +16,8 @@
 // R0, one workgroup per member) so that no step needs a grid-wide barrier.
 #include "rt_plan_state.h"
 
+#include <map>
+
 using namespace rtp;
 
 namespace {
@@ -242,21 +244,28 @@ void rec_trsm(Program &P, rtproj_batch b, const std::vector<const double *> &Lp,
 void build_precondition(Program &P, rtproj_batch b, const double *const *A, const int64_t *lda)
 {
     const int64_t cnt = b->count;
-    // 1. sketches
+    // 1. sketches: one grouped launch pair per padded Fourier length and band
+    // of 128 rows, so that each grid (sized for the largest member it covers)
+    // wastes few blocks on smaller transforms or fewer row pairs
     P.stage = 0;
     {
-        std::vector<rt::SketchGroupArgs> v(cnt);
-        Op o{OP_SKETCH, 0, (int)cnt};
-        for (int64_t i = 0; i < cnt; ++i) {
-            rtproj_plan p = b->sub[i];
-            v[i] = rt::SketchGroupArgs{p->sketch_tables(), A[i], lda[i], p->m, p->d_S, p->l, p->d_zbuf, p->rows_chunk};
-            o.ss.max_n1 = std::max(o.ss.max_n1, p->tab.n1);
-            o.ss.max_n2 = std::max(o.ss.max_n2, p->tab.n2);
-            o.ss.max_rows_chunk = std::max(o.ss.max_rows_chunk, p->rows_chunk);
-            o.ss.chunks = std::max<int>(o.ss.chunks, (int)((p->m + p->rows_chunk - 1) / p->rows_chunk));
+        std::map<std::pair<int64_t, int64_t>, std::vector<int64_t>> by_np;
+        for (int64_t i = 0; i < cnt; ++i) by_np[{b->sub[i]->tab.np, (b->sub[i]->m + 127) / 128}].push_back(i);
+        for (const auto &cls : by_np) {
+            std::vector<rt::SketchGroupArgs> v;
+            Op o{OP_SKETCH, 0, (int)cls.second.size()};
+            for (int64_t i : cls.second) {
+                rtproj_plan p = b->sub[i];
+                v.push_back(rt::SketchGroupArgs{p->sketch_tables(), A[i], lda[i], p->m, p->d_S, p->l, p->d_zbuf,
+                                                p->rows_chunk});
+                o.ss.max_n1 = std::max(o.ss.max_n1, p->tab.n1);
+                o.ss.max_n2 = std::max(o.ss.max_n2, p->tab.n2);
+                o.ss.max_rows_chunk = std::max(o.ss.max_rows_chunk, p->rows_chunk);
+                o.ss.chunks = std::max<int>(o.ss.chunks, (int)((p->m + p->rows_chunk - 1) / p->rows_chunk));
+            }
+            o.off = P.add(v);
+            P.push(o);
         }
-        o.off = P.add(v);
-        P.push(o);
     }
     std::vector<double *> G(cnt), Yq(cnt), L1(cnt), L2(cnt), L3(cnt), R0(cnt), S(cnt), Rm(cnt), Ym(cnt), Lm(cnt);
     std::vector<const double *> cYq(cnt);
