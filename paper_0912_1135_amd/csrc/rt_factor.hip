@@ -32,39 +32,35 @@ __device__ __forceinline__ void tri_slots(int *ri, int *ci)
 }
 
 // X = L^{-1} for the lower-triangular L in LDS (row stride LDP), written to
-// X (row stride LDP; may not alias L).  Right-looking row sweep of L X = I:
-// at step k row k of X has received every update from the rows above, is
-// divided by L[k][k] and broadcast, and every lower row i > k subtracts
-// L[i][k] times it.  One block barrier per step.
-__device__ void lower_inverse_block(const double *L, double *X, const int *ri, const int *ci)
+// X (row stride LDP; may not alias L).  Column j of X solves L x = e_j by
+// forward substitution, x_i = (delta_ij - sum_{c<i} L_ic x_c) / L_ii for
+// i = 0..63 in turn, and the 64 columns are independent: four lanes of one
+// wave share a column (lanes 4j..4j+3), each summing the terms c = q mod 4
+// before two shuffles add the four parts, so no block barrier is needed
+// between rows (a wave's LDS accesses complete in order).  Rows above j come
+// out as exact zeros.  The reciprocals 1 / L_ii are formed once.
+__device__ void lower_inverse_block(const double *L, double *X)
 {
-    __shared__ double rowb[2][NBMAX];
-    double x[NE];
-#pragma unroll
-    for (int s = 0; s < NE; ++s) x[s] = (ri[s] == ci[s]) ? 1.0 : 0.0;
-    for (int k = 0; k < NBMAX; ++k) {
-        const double rk = 1.0 / L[k * LDP + k];
-        double *rb = rowb[k & 1];
-#pragma unroll
-        for (int s = 0; s < NE; ++s)
-            if (ri[s] == k) {
-                x[s] *= rk;
-                rb[ci[s]] = x[s];
-            }
-        __syncthreads();
-        // branch-free update of the rows below k (entries with ci <= k < ri)
-#pragma unroll
-        for (int s = 0; s < NE; ++s) {
-            const int r = ri[s] > k ? ri[s] : k;
-            const double u = L[r * LDP + k] * rb[ci[s] <= k ? ci[s] : 0];
-            x[s] = (ri[s] > k && ci[s] <= k) ? x[s] - u : x[s];
-        }
-    }
+    static_assert(DT == 4 * NBMAX, "four lanes per column of the block");
+    __shared__ double invd[NBMAX];
     for (int e = threadIdx.x; e < NBMAX * NBMAX; e += DT) X[(e / NBMAX) * LDP + (e % NBMAX)] = 0.0;
+    if (threadIdx.x < NBMAX) invd[threadIdx.x] = 1.0 / L[threadIdx.x * LDP + threadIdx.x];
     __syncthreads();
-#pragma unroll
-    for (int s = 0; s < NE; ++s)
-        if (ri[s] >= 0) X[ri[s] * LDP + ci[s]] = x[s];
+    const int j = threadIdx.x >> 2, q = threadIdx.x & 3;
+    for (int i = 0; i < NBMAX; ++i) {
+        const double *li = L + i * LDP;
+        double sq = 0.0;
+        for (int c0 = 0; c0 < i; c0 += 4) {
+            const int c = c0 + q;
+            const double t = li[c < i ? c : 0] * X[(c < i ? c : 0) * LDP + j];
+            sq += c < i ? t : 0.0;
+        }
+        sq += __shfl_xor(sq, 1, 64);
+        sq += __shfl_xor(sq, 2, 64);
+        const double xi = ((i == j ? 1.0 : 0.0) - sq) * invd[i];
+        if (q == 0) X[i * LDP + j] = xi;
+        __builtin_amdgcn_wave_barrier();
+    }
     __syncthreads();
 }
 
@@ -74,8 +70,6 @@ __device__ __forceinline__ void tri_diag_inv_body(const double *T, int64_t t_i, 
     if (b * nb >= m) return;  // whole block (grouped launches)
     __shared__ double L[NBMAX * LDP];
     __shared__ double X[NBMAX * LDP];
-    int ri[NE], ci[NE];
-    tri_slots(ri, ci);
     const int base = b * nb, nbb = min(nb, m - base);
     for (int e = threadIdx.x; e < NBMAX * NBMAX; e += DT) {
         const int i = e / NBMAX, j = e % NBMAX;
@@ -85,7 +79,7 @@ __device__ __forceinline__ void tri_diag_inv_body(const double *T, int64_t t_i, 
         L[i * LDP + j] = v;
     }
     __syncthreads();
-    lower_inverse_block(L, X, ri, ci);
+    lower_inverse_block(L, X);
     double *out = Dinv + (int64_t)b * nb * nb;
     for (int e = threadIdx.x; e < nb * nb; e += DT) out[e] = X[(e / nb) * LDP + (e % nb)];
 }
@@ -161,7 +155,7 @@ __device__ __forceinline__ void chol_diag_body(const double *Xg, int64_t ldx, in
         const int r = e / nbb, c = e % nbb;
         Lg[(int64_t)(base + r) * ldl + base + c] = Ls[r * LDP + c];
     }
-    lower_inverse_block(Ls, Xs, ri, ci);
+    lower_inverse_block(Ls, Xs);
     double *out = Dinv + (int64_t)b * nb * nb;
     for (int e = threadIdx.x; e < nb * nb; e += DT) out[e] = Xs[(e / nb) * LDP + (e % nb)];
     if (bad && threadIdx.x == 0) atomicExch(err, 1);
