@@ -62,7 +62,7 @@ typedef enum {
                                    (Cholesky breakdown, or no Newton-Schulz
                                    convergence)                                  */
     RTPROJ_ERR_NOCONV = 6,      /* refinement did not contract                   */
-    RTPROJ_ERR_UNSUPPORTED = 7  /* size or mode this build does not handle       */
+    RTPROJ_ERR_UNSUPPORTED = 7  /* size or mode the library does not handle      */
 } rtproj_status;
 
 /* Arithmetic used by the preconditioner (the projection's residuals, the
