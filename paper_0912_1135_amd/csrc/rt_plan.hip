@@ -378,12 +378,14 @@ rtproj_status gram_f64(rtproj_plan p, const double *A, int64_t lda, int64_t K, d
 // one wave per 16 x 16 tile over the whole K and the affine epilogue fused
 // (small products are launch latency); above it, whose fused form would
 // read about m^3 bytes from L2, 64 x 64 tiles with K split so that a product
-// spans about four blocks per compute unit, then the affine reduction.
+// spans about one block per compute unit, then the affine reduction.
 int ns_splits(rtproj_plan p)
 {
+    // about one block per compute unit, at least 4 splits (measured at
+    // m = 512: 4 splits 0.57 ms per inverse, 8 splits 0.59, 2 splits 0.74)
     const int64_t m = p->m, tiles = ((m + 63) / 64) * ((m + 63) / 64);
-    const int64_t want = (2 * p->cu_count + tiles - 1) / tiles;
-    return (int)std::max<int64_t>(1, std::min<int64_t>({2 * want, m / 64, (int64_t)p->syrk_splits}));
+    const int64_t want = std::max<int64_t>(4, (p->cu_count + tiles - 1) / tiles);
+    return (int)std::max<int64_t>(1, std::min<int64_t>({want, m / 64, (int64_t)p->syrk_splits}));
 }
 
 rtproj_status ns_product(rtproj_plan p, const double *Am, const double *Bm, double *out, double scale, double diag,
