@@ -8,6 +8,11 @@ shares no code with the GPU library.
                       column b (Sec. 1 items 1-3, Remark 4.1, eq.
                       basic_identity); Householder QR of A^T plus binary128
                       refinement (Remark 4.3).  Written in C (``oracle.c``).
+* ``project_lapack`` -- the same outputs with the Householder QR of A^T
+                      taken from LAPACK (numpy.linalg.qr, R only, as a
+                      library step), x started at 0 and refined by the same
+                      binary128 iteration; for sizes where the unblocked
+                      factorization of ``project`` takes minutes.
 * ``qrcp``         -- Businger-Golub column-pivoted Householder QR
                       (Sec. 4, eq. QR_decomp).
 * ``srft_tables``  -- SplitMix64 draws of the sketch's random tables.
@@ -53,6 +58,8 @@ def bind(path: str):
     lib.orc_qrcp.restype = ip
     lib.orc_project.argtypes = [i64, i64, dp, i64, i64, dp, i64, dp, i64, dp, i64, dp, i64, ip, dp]
     lib.orc_project.restype = ip
+    lib.orc_project_r.argtypes = [i64, i64, dp, i64, dp, i64, i64, dp, i64, dp, i64, dp, i64, dp, i64, ip, dp]
+    lib.orc_project_r.restype = ip
     lib.orc_num_threads.restype = ip
     return lib
 
@@ -132,6 +139,31 @@ def project(A: np.ndarray, B: np.ndarray, maxit: int = 8, lib=None):
                              _ptr(X), m, maxit, _ptr(info))
     if rc != 0:
         raise ValueError(f"orc_project failed ({rc})")
+    if vec:
+        return Z[:, 0], P[:, 0], X[:, 0], info
+    return Z, P, X, info
+
+
+def project_lapack(A: np.ndarray, B: np.ndarray, maxit: int = 12, lib=None):
+    """As ``project``, with R from LAPACK's Householder QR of A^T.
+
+    The semi-normal solve x1 = R^{-1} R^{-T} A b (the first refinement step
+    from x = 0) is refined in binary128 exactly as in ``project``, so both
+    routes converge to the same x, p and z (to the final rounding)."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    m, n = A.shape
+    R = np.ascontiguousarray(np.linalg.qr(A.T, mode="r")[:m, :m])
+    vec = B.ndim == 1
+    Bc = np.asfortranarray(B.reshape(n, -1), dtype=np.float64)
+    k = Bc.shape[1]
+    Z = np.zeros((n, k), order="F")
+    P = np.zeros((n, k), order="F")
+    X = np.zeros((m, k), order="F")
+    info = np.zeros(2)
+    rc = (lib or _load()).orc_project_r(m, n, _ptr(A), n, _ptr(R), m, k, _ptr(Bc), n, _ptr(Z), n, _ptr(P), n,
+                                        _ptr(X), m, maxit, _ptr(info))
+    if rc != 0:
+        raise ValueError(f"orc_project_r failed ({rc})")
     if vec:
         return Z[:, 0], P[:, 0], X[:, 0], info
     return Z, P, X, info

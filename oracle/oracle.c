@@ -24,6 +24,9 @@
  *                        Evaluated by Householder QR of A^T plus iterative
  *                        refinement (the refinement of Remark 4.3) with the
  *                        residuals in binary128.
+ *   orc_project_r        The same outputs from a triangular factor of A^T
+ *                        supplied by the caller (LAPACK's Householder QR
+ *                        as a library step), refined the same way.
  *
  * Conventions
  *   A is row-major m x n with leading dimension lda (element (i,j) at
@@ -228,25 +231,103 @@ static void householder_at(int64_t m, int64_t n, double *H, double *tau, double 
     }
 }
 
-/* R of A^T: R[i][j] = H[j][i] for i < j, diagonal Rd. Solve R y = c. */
-static void solve_r(int64_t m, int64_t n, const double *H, const double *Rd, double *y)
+/* Triangular solves with an upper-triangular m x m R addressed through
+ * strides: R[i][j] = Rp[i*ri + j*rj] for i <= j (the diagonal included).   */
+
+/* Solve R y = c (back substitution), y overwritten. */
+static void solve_r(int64_t m, const double *Rp, int64_t ri, int64_t rj, double *y)
 {
     for (int64_t i = m - 1; i >= 0; --i) {
         double s = y[i];
-        for (int64_t j = i + 1; j < m; ++j) s -= H[j * n + i] * y[j];
-        y[i] = s / Rd[i];
+        for (int64_t j = i + 1; j < m; ++j) s -= Rp[i * ri + j * rj] * y[j];
+        y[i] = s / Rp[i * ri + i * rj];
     }
 }
 
-/* Solve R^T y = c (forward substitution). */
-static void solve_rt(int64_t m, int64_t n, const double *H, const double *Rd, double *y)
+/* Solve R^T y = c (forward substitution), y overwritten. */
+static void solve_rt(int64_t m, const double *Rp, int64_t ri, int64_t rj, double *y)
 {
     for (int64_t i = 0; i < m; ++i) {
         double s = y[i];
-        const double *col = H + i * n; /* column i of R above the diagonal: H[i][0..i-1] */
-        for (int64_t j = 0; j < i; ++j) s -= col[j] * y[j];
-        y[i] = s / Rd[i];
+        for (int64_t j = 0; j < i; ++j) s -= Rp[j * ri + i * rj] * y[j];
+        y[i] = s / Rp[i * ri + i * rj];
     }
+}
+
+/*
+ * Refinement (Remark 4.3) of the k least-squares solutions x (binary128,
+ * m x k column-major, in: the starting point) and the outputs formed from
+ * them.  For each column b:
+ *   r = b - A^T x and s = A r in binary128 (s rounded once to double),
+ *   d = R^{-1} R^{-T} s in double (R from a Householder QR of A^T, so that
+ *   R^T R = A A^T up to rounding), x += d kept in binary128;
+ *   stop when |d| <= 1e-22 |x|, when |d| stops decreasing, or after maxit
+ *   steps.  Then p = A^T x and z = b - A^T x in binary128, rounded once.
+ * The columns are taken one after another; inside a column the loops over
+ * independent entries (t for r, i for s) run in parallel, and every entry is
+ * accumulated in the same order as a sequential loop would.
+ */
+static int refine_and_form(int64_t m, int64_t n, const double *A, int64_t lda,
+                           const double *Rp, int64_t ri, int64_t rj, int64_t k,
+                           const double *B, int64_t ldb, quad *xq, double *Z, int64_t ldz,
+                           double *P, int64_t ldp, double *X, int64_t ldx, int maxit, double *info)
+{
+    quad *r = (quad *)malloc(sizeof(quad) * (size_t)n);
+    double *d = (double *)malloc(sizeof(double) * (size_t)m);
+    if (!r || !d) { free(r); free(d); return 3; }
+    int steps_max = 0;
+    double last_ratio = 0.0;
+    for (int64_t c = 0; c < k; ++c) {
+        const double *b = B + c * ldb;
+        quad *x = xq + c * m;
+        double prev = INFINITY, ratio = 0.0;
+        int steps = 0;
+        for (int it = 0; it < maxit; ++it) {
+            /* r = b - A^T x in binary128: entry t subtracts a_it x_i for i = 0..m-1 */
+            #pragma omp parallel for schedule(static)
+            for (int64_t t = 0; t < n; ++t) {
+                quad acc = (quad)b[t];
+                for (int64_t i = 0; i < m; ++i) acc -= (quad)A[i * lda + t] * x[i];
+                r[t] = acc;
+            }
+            /* s = A r in binary128, rounded once to double */
+            #pragma omp parallel for schedule(static)
+            for (int64_t i = 0; i < m; ++i) {
+                const double *a = A + i * lda;
+                quad s = 0;
+                for (int64_t t = 0; t < n; ++t) s += (quad)a[t] * r[t];
+                d[i] = (double)s;
+            }
+            solve_rt(m, Rp, ri, rj, d);
+            solve_r(m, Rp, ri, rj, d);
+            double dn = 0.0, xn = 0.0;
+            for (int64_t i = 0; i < m; ++i) {
+                x[i] += (quad)d[i];
+                dn += d[i] * d[i];
+                double xd = (double)x[i];
+                xn += xd * xd;
+            }
+            dn = sqrt(dn); xn = sqrt(xn);
+            ++steps;
+            ratio = xn > 0.0 ? dn / xn : 0.0;
+            if (dn <= 1e-22 * xn || dn >= prev) break;
+            prev = dn;
+        }
+        /* p = A^T x and z = b - A^T x in binary128 */
+        #pragma omp parallel for schedule(static)
+        for (int64_t t = 0; t < n; ++t) {
+            quad acc = 0;
+            for (int64_t i = 0; i < m; ++i) acc += (quad)A[i * lda + t] * x[i];
+            if (P) P[c * ldp + t] = (double)acc;
+            if (Z) Z[c * ldz + t] = (double)((quad)b[t] - acc);
+        }
+        if (X) for (int64_t i = 0; i < m; ++i) X[c * ldx + i] = (double)x[i];
+        if (steps > steps_max) steps_max = steps;
+        if (ratio > last_ratio) last_ratio = ratio;
+    }
+    if (info) { info[0] = steps_max; info[1] = last_ratio; }
+    free(r); free(d);
+    return 0;
 }
 
 /*
@@ -254,11 +335,8 @@ static void solve_rt(int64_t m, int64_t n, const double *H, const double *Rd, do
  *   x = argmin_h |A^T h - b|        (written to X if X != NULL)
  *   p = A^T x                       (row-space projection, to P if != NULL)
  *   z = b - A^T x                   (null-space projection, to Z if != NULL)
- * Start: x0 from the Householder QR of A^T (x0 = R^{-1} [Q^T b]_{0:m}).
- * Refinement (Remark 4.3): r = b - A^T x and s = A r evaluated in binary128,
- * correction d = R^{-1} R^{-T} s in double, x += d kept in binary128; stop
- * when |d| <= 1e-22 |x|, when |d| stops decreasing, or after maxit steps.
- * z and p are formed from the binary128 x in binary128 and rounded once.
+ * Start: x0 from the Householder QR of A^T (x0 = R^{-1} [Q^T b]_{0:m}),
+ * then the binary128 refinement of refine_and_form.
  * info (length >= 2, may be NULL): info[0] = refinement steps taken,
  * info[1] = |d|/|x| of the last step (maximum over columns).
  */
@@ -275,16 +353,14 @@ int orc_project(int64_t m, int64_t n, const double *A, int64_t lda, int64_t k,
     for (int64_t i = 0; i < m; ++i) memcpy(H + i * n, A + i * lda, sizeof(double) * (size_t)n);
     householder_at(m, n, H, tau, Rd);
 
-    int steps_max = 0;
-    double last_ratio = 0.0;
-    #pragma omp parallel for schedule(dynamic, 1) reduction(max:steps_max, last_ratio)
+    /* x0 per column: apply H_0 .. H_{m-1} to b, then back-substitute with R,
+     * whose entries are R[i][j] = H[j*n + i] (i <= j; the diagonal is beta) */
+    int bad = 0;
+    #pragma omp parallel for schedule(dynamic, 1) reduction(|:bad)
     for (int64_t c = 0; c < k; ++c) {
         const double *b = B + c * ldb;
         double *w = (double *)malloc(sizeof(double) * (size_t)n);
-        quad *r = (quad *)malloc(sizeof(quad) * (size_t)n);
-        double *d = (double *)malloc(sizeof(double) * (size_t)m);
-        quad *x = xq + c * m;
-        /* x0: apply H_0 .. H_{m-1} to b, then back-substitute with R */
+        if (!w) { bad = 1; continue; }
         memcpy(w, b, sizeof(double) * (size_t)n);
         for (int64_t j = 0; j < m; ++j) {
             const double *v = H + j * n;
@@ -294,58 +370,33 @@ int orc_project(int64_t m, int64_t n, const double *A, int64_t lda, int64_t k,
             w[j] -= s;
             for (int64_t i = j + 1; i < n; ++i) w[i] -= s * v[i];
         }
-        memcpy(d, w, sizeof(double) * (size_t)m);
-        solve_r(m, n, H, Rd, d);
-        for (int64_t i = 0; i < m; ++i) x[i] = (quad)d[i];
-        double prev = INFINITY, ratio = 0.0;
-        int steps = 0;
-        for (int it = 0; it < maxit; ++it) {
-            /* r = b - A^T x in binary128 */
-            for (int64_t t = 0; t < n; ++t) r[t] = (quad)b[t];
-            for (int64_t i = 0; i < m; ++i) {
-                const double *a = A + i * lda;
-                quad xi = x[i];
-                for (int64_t t = 0; t < n; ++t) r[t] -= (quad)a[t] * xi;
-            }
-            /* s = A r in binary128, rounded once to double */
-            for (int64_t i = 0; i < m; ++i) {
-                const double *a = A + i * lda;
-                quad s = 0;
-                for (int64_t t = 0; t < n; ++t) s += (quad)a[t] * r[t];
-                d[i] = (double)s;
-            }
-            solve_rt(m, n, H, Rd, d);
-            solve_r(m, n, H, Rd, d);
-            double dn = 0.0, xn = 0.0;
-            for (int64_t i = 0; i < m; ++i) {
-                x[i] += (quad)d[i];
-                dn += d[i] * d[i];
-                double xd = (double)x[i];
-                xn += xd * xd;
-            }
-            dn = sqrt(dn); xn = sqrt(xn);
-            ++steps;
-            ratio = xn > 0.0 ? dn / xn : 0.0;
-            if (dn <= 1e-22 * xn || dn >= prev) break;
-            prev = dn;
-        }
-        /* p = A^T x and z = b - A^T x in binary128 */
-        for (int64_t t = 0; t < n; ++t) r[t] = 0;
-        for (int64_t i = 0; i < m; ++i) {
-            const double *a = A + i * lda;
-            quad xi = x[i];
-            for (int64_t t = 0; t < n; ++t) r[t] += (quad)a[t] * xi;
-        }
-        if (P) for (int64_t t = 0; t < n; ++t) P[c * ldp + t] = (double)r[t];
-        if (Z) for (int64_t t = 0; t < n; ++t) Z[c * ldz + t] = (double)((quad)b[t] - r[t]);
-        if (X) for (int64_t i = 0; i < m; ++i) X[c * ldx + i] = (double)x[i];
-        if (steps > steps_max) steps_max = steps;
-        if (ratio > last_ratio) last_ratio = ratio;
-        free(w); free(r); free(d);
+        solve_r(m, H, 1, n, w);
+        for (int64_t i = 0; i < m; ++i) xq[c * m + i] = (quad)w[i];
+        free(w);
     }
-    if (info) { info[0] = steps_max; info[1] = last_ratio; }
+    int rc = bad ? 3 : refine_and_form(m, n, A, lda, H, 1, n, k, B, ldb, xq, Z, ldz, P, ldp, X, ldx, maxit, info);
     free(H); free(tau); free(Rd); free(xq);
-    return 0;
+    return rc;
+}
+
+/*
+ * As orc_project, with the triangular factor of the Householder QR of A^T
+ * supplied by the caller (R, m x m upper triangular, row-major, ld ldr;
+ * e.g. LAPACK's): x starts at 0, so the first refinement step is the
+ * semi-normal solve x1 = R^{-1} R^{-T} A b, and the binary128 refinement of
+ * refine_and_form continues from there (it contracts by about u cond(A)
+ * per step for any backward-stable R).
+ */
+int orc_project_r(int64_t m, int64_t n, const double *A, int64_t lda, const double *R, int64_t ldr,
+                  int64_t k, const double *B, int64_t ldb, double *Z, int64_t ldz,
+                  double *P, int64_t ldp, double *X, int64_t ldx, int maxit, double *info)
+{
+    if (m < 1 || n < m || lda < n || ldr < m || k < 0 || (k > 0 && ldb < n)) return 1;
+    quad *xq = (quad *)calloc((size_t)(m * (k > 0 ? k : 1)), sizeof(quad));
+    if (!xq) return 3;
+    int rc = refine_and_form(m, n, A, lda, R, ldr, 1, k, B, ldb, xq, Z, ldz, P, ldp, X, ldx, maxit, info);
+    free(xq);
+    return rc;
 }
 
 /* Number of OpenMP threads the oracle runs with. */

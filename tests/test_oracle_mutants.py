@@ -23,12 +23,20 @@ SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
 
 PROJECTION_MUTANTS = {
     "householder tau sign": ("t = (beta - alpha) / beta;", "t = (alpha - beta) / beta;"),
-    "residual product rounded to double": ("r[t] -= (quad)a[t] * xi;", "r[t] -= (quad)(a[t] * (double)xi);"),
-    "R^T solve reads R row": ("s -= col[j] * y[j];", "s -= H[j * n + i] * y[j];"),
+    "residual product rounded to double": ("acc -= (quad)A[i * lda + t] * x[i];",
+                                           "acc -= (quad)(A[i * lda + t] * (double)x[i]);"),
+    "R^T solve reads R row": ("s -= Rp[j * ri + i * rj] * y[j];", "s -= Rp[i * ri + j * rj] * y[j];"),
     "A r contraction index shifted": ("s += (quad)a[t] * r[t];", "s += (quad)a[t] * r[(t + 1) % n];"),
-    "null projection sign": ("(double)((quad)b[t] - r[t])", "(double)((quad)b[t] + r[t])"),
+    "null projection sign": ("(double)((quad)b[t] - acc)", "(double)((quad)b[t] + acc)"),
     "correction dropped": ("x[i] += (quad)d[i];", "x[i] += (quad)(0.5 * d[i]);"),
-    "z uses rounded x": ("r[t] += (quad)a[t] * xi;", "r[t] += (quad)(a[t] * (double)xi);"),
+    "z uses rounded x": ("acc += (quad)A[i * lda + t] * x[i];", "acc += (quad)(A[i * lda + t] * (double)x[i]);"),
+}
+
+# mistakes in the route that takes R from LAPACK (orc_project_r)
+PROJECT_R_MUTANTS = {
+    "R read transposed": ("R, ldr, 1, k, B, ldb, xq", "R, 1, ldr, k, B, ldb, xq"),
+    "too few refinement steps": ("xq, Z, ldz, P, ldp, X, ldx, maxit, info);\n    free(xq);",
+                                 "xq, Z, ldz, P, ldp, X, ldx, 1, info);\n    free(xq);"),
 }
 
 QRCP_MUTANTS = {
@@ -65,6 +73,19 @@ def projection_pins_pass(lib):
     return True
 
 
+def project_r_pins_pass(lib):
+    for m, n, kappa, seed in [(3, 12, 1e6, 3), (5, 24, 1e10, 5), (6, 40, 1e10, 7)]:
+        A = synth.make_problem(m, n, kappa, seed)
+        b = synth.make_rhs(n, 1, seed)[0]
+        z, p, x, _ = oracle.project_lapack(A, b, lib=lib)
+        zt, pt, xt = mp_truth(A, b)
+        nb = np.linalg.norm(b)
+        if not (np.linalg.norm(z - zt) <= 1e-15 * nb and np.linalg.norm(p - pt) <= 1e-15 * nb
+                and np.linalg.norm(x - xt) <= 1e-15 * np.linalg.norm(xt)):
+            return False
+    return True
+
+
 def qrcp_pins_pass(lib):
     for rows, cols, seed in [(40, 10, 1), (100, 37, 3)]:
         M = graded(rows, cols, seed)
@@ -81,13 +102,19 @@ def qrcp_pins_pass(lib):
 
 def test_unmutated_copy_passes(tmp_path):
     lib = build_mutant(tmp_path, "int orc_num_threads(void)", "int orc_num_threads(void)")
-    assert projection_pins_pass(lib) and qrcp_pins_pass(lib)
+    assert projection_pins_pass(lib) and qrcp_pins_pass(lib) and project_r_pins_pass(lib)
 
 
 @pytest.mark.parametrize("name", sorted(PROJECTION_MUTANTS))
 def test_projection_mutant_is_caught(tmp_path, name):
     lib = build_mutant(tmp_path, *PROJECTION_MUTANTS[name])
     assert not projection_pins_pass(lib), name
+
+
+@pytest.mark.parametrize("name", sorted(PROJECT_R_MUTANTS))
+def test_project_r_mutant_is_caught(tmp_path, name):
+    lib = build_mutant(tmp_path, *PROJECT_R_MUTANTS[name])
+    assert not project_r_pins_pass(lib), name
 
 
 @pytest.mark.parametrize("name", sorted(QRCP_MUTANTS))
