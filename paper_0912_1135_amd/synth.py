@@ -5,8 +5,16 @@ same generators feed the GPU path, the CPU oracle, the tests and the
 benchmark.
 
 * A = U diag(sigma) V^T with U (m x m) and V (n x m) Haar-distributed
-  orthonormal (QR of a Gaussian matrix, columns multiplied by the signs of
-  R's diagonal), sigma log-spaced from 1 down to 1/kappa.
+  orthonormal, sigma log-spaced from 1 down to 1/kappa.  U, and V when n <
+  8m, is the QR of a Gaussian matrix with its columns multiplied by the
+  signs of R's diagonal (Mezzadri).  For n >= 8m, V is the orthonormal polar
+  factor G (G^T G)^{-1/2} of an n x m Gaussian G: for any orthogonal Q, QG
+  has the law of G and its polar factor is Q times that of G, so the law of
+  V is invariant under rotations, i.e. Haar.  G is then well conditioned
+  (cond <= (1 + sqrt(m/n)) / (1 - sqrt(m/n)) < 2.1 up to fluctuations), so
+  the polar factor formed from G^T G is orthonormal to a few units of
+  rounding, at a tenth of the cost of a QR of G (262144 x 2048: 15 s
+  against 110 s on 8 cores).
 * Right-hand sides: i.i.d. N(0, 1), stored as a (k, n) C-contiguous array,
   i.e. column-major n x k (column c is row c of the array).
 * Batched workload: instance sizes m_i ~ U{32..512}, n_i = m_i * U{16..64},
@@ -37,6 +45,16 @@ def haar(rows: int, cols: int, rng: np.random.Generator) -> np.ndarray:
     return q * d[None, :]
 
 
+def haar_tall(rows: int, cols: int, rng: np.random.Generator) -> np.ndarray:
+    """rows x cols Haar orthonormal columns; the polar factor of a Gaussian
+    matrix when rows >= 8 cols, else ``haar``."""
+    if rows < 8 * cols:
+        return haar(rows, cols, rng)
+    g = rng.standard_normal((rows, cols))
+    lam, w = np.linalg.eigh(g.T @ g)
+    return g @ ((w / np.sqrt(lam)[None, :]) @ w.T)
+
+
 def log_spaced(m: int, kappa: float) -> np.ndarray:
     if m == 1:
         return np.ones(1)
@@ -46,7 +64,7 @@ def log_spaced(m: int, kappa: float) -> np.ndarray:
 def make_problem(m: int, n: int, kappa: float, seed: int, with_factors: bool = False):
     """A (m x n, row-major float64) with singular values log-spaced 1 -> 1/kappa."""
     U = haar(m, m, rng_for(seed, 0))
-    V = haar(n, m, rng_for(seed, 1))
+    V = haar_tall(n, m, rng_for(seed, 1))
     s = log_spaced(m, kappa)
     A = np.ascontiguousarray((U * s[None, :]) @ V.T)
     if with_factors:
