@@ -29,9 +29,11 @@
  * Streams and synchronisation: every call enqueues its work on the plan's
  * stream (rtproj_plan_set_stream; default: the null stream).
  * rtproj_precondition blocks until the sketch's pivoted QR has finished, to
- * read the rank test (a few bytes).  The project calls are asynchronous unless
- * refinement runs with a convergence test (set_refinement with rtol > 0),
- * which reads one flag per refinement step.  A plan is not thread-safe;
+ * read the rank test (a few bytes), and until the Gram's inverse is done.
+ * The project calls are asynchronous unless refinement runs with a
+ * convergence test (set_refinement with rtol > 0), which reads one flag per
+ * refinement step; otherwise whether the refinement converged is read at the
+ * next rtproj_plan_status or rtproj_plan_info.  A plan is not thread-safe;
  * distinct plans are independent.
  *
  * Errors: every entry point returns an rtproj_status; nothing is thrown and
@@ -71,8 +73,9 @@ typedef enum {
     RTPROJ_PREC_FP64 = 0,       /* sketch, P^{-1}A and its Gram in binary64           */
     RTPROJ_PREC_MIXED_FP32 = 1, /* binary32 sketch and Gram (binary32 MFMA); P^{-1}A
                                    in binary32 when kappa_est <= 1e5, else binary64;
-                                   the sketch is redone in binary64 when the Gram
-                                   shows cond(P^{-1}A) > 10 (gram_cond_est)           */
+                                   the sketch is redone in binary64 when its rank
+                                   estimate shows it too coarse (2^-24 kappa_est >
+                                   1) or the Gram shows cond(P^{-1}A) > 10          */
     RTPROJ_PREC_MIXED_BF16 = 2  /* binary32 sketch; Gram from row-scaled (powers of
                                    two) bfloat16 P^{-1}A on MFMA with binary32
                                    accumulation; P^{-1}A as in MIXED_FP32             */
@@ -105,18 +108,50 @@ typedef enum {
                                       use T' = L^{-1} R^{-T} Pi, T'^T (T' c)      */
 } rtproj_inverse;
 
+/* Arithmetic of the refinement residuals (Remark 4.3).  r = b - A^T x is the
+ * residual, s = A r the contraction the correction is solved from, and the
+ * final A^T x gives the row and null projections.  A residual evaluated in
+ * plain binary64 stalls at a relative error of x of about u cond(A);
+ * compensated (double-binary64, Dot2) evaluation removes that floor at
+ * about ten times the instruction count. */
+typedef enum {
+    RTPROJ_RESID_AUTO = 0,     /* chosen from the rank estimate (see
+                                  rtproj_plan_set_refinement)                   */
+    RTPROJ_RESID_PLAIN = 1,    /* every residual in plain binary64              */
+    RTPROJ_RESID_S_ONLY = 2,   /* r and the final A^T x plain, s = A r
+                                  compensated in the compensated steps          */
+    RTPROJ_RESID_FULL = 3      /* r, s and the final A^T x compensated in the
+                                  compensated steps (x kept double-binary64)    */
+} rtproj_residual;
+
+/* Method of a plan.  Both return the same x, A^* x and b - A^* x in exact
+ * arithmetic; they differ in rounding (Sec. 1) and cost (Sec. 5). */
+typedef enum {
+    RTPROJ_METHOD_RANDOMIZED = 0, /* the preconditioned identity (eq. basic_precond)
+                                     with P from the randomized sketch, and the
+                                     refinement of Remark 4.3 (the default)          */
+    RTPROJ_METHOD_CLASSICAL = 1   /* eq. basic_identity evaluated directly: A A^*
+                                     (binary64 MFMA), its Householder pivoted QR,
+                                     x = Pi R^{-1} Q^T (A b), no refinement; the
+                                     comparison scheme of Sec. 5 (s_pre, s_pro,
+                                     delta_norm, epsilon_norm); m <= 4096          */
+} rtproj_method;
+
 typedef struct {
     int64_t m, n, l;           /* sizes of the plan                                  */
     int64_t np;                /* padded Fourier length of the sketch               */
     double kappa_est;          /* |R_11 / R_mm| of the pivoted QR of the sketch      */
     double rdiag_min;          /* |R_mm|                                             */
-    int precision;             /* rtproj_precision in effect                         */
+    int precision;             /* rtproj_precision of the last precondition          */
     int refine_steps;          /* refinement steps taken by the last projection     */
     double refine_last_ratio;  /* |dx| / |x| of the last refinement step             */
     int qrcp_blocks;           /* workgroups of the cooperative pivoted QR           */
     int sketch_bits, w_bits, gram_bits; /* precisions used by the last precondition:
                                    64 binary64, 32 binary32, 16 bfloat16             */
-    int sketch_escalated;      /* 1 if a binary32 sketch was redone in binary64      */
+    int sketch_escalated;      /* a binary32 sketch was redone in binary64: 1 right
+                                  after the pivoted QR (2^-24 kappa_est > 1, or a
+                                  failed rank test), 2 after the Gram (gram_cond_est
+                                  > 10); 0 otherwise                                */
     double gram_cond_est;      /* a lower bound on cond(P^{-1}A): Newton-Schulz
                                    sqrt(max_i X_ii max_i Y_ii); Cholesky max/min
                                    of diag(L)                                        */
@@ -128,7 +163,8 @@ typedef struct {
      * solve L^{-1}R^{-T}), 7 A b, 8 applications of (AA^T)^{-1},
      * 9 refinement residual b - A^T x, 10 refinement product A r,
      * 11 final A^T x and b - A^T x, 12 the small factor R0 of the two-stage
-     * pivoted QR, 13..15 unused. */
+     * pivoted QR; 9, 10 and 11 count the compensated passes, and the plain
+     * binary64 ones are 13 (residual), 14 (product A r) and 15 (final). */
     double t_stage_ms[16];
     int64_t stage_calls[16];
     int qr_mode;               /* rtproj_qr_mode used by the last precondition       */
@@ -139,6 +175,21 @@ typedef struct {
                                   before the final step (the final residual is
                                   about its square, down to rounding); 0 for
                                   Cholesky                                          */
+    int refine_plain;          /* steps of the last projection with plain residuals */
+    int refine_comp;           /* steps with compensated residuals after them        */
+    int resid_mode;            /* rtproj_residual used by the last projection
+                                  (1, 2 or 3; 0 before any)                         */
+    int refine_status;         /* RTPROJ_OK or RTPROJ_ERR_NOCONV for the last
+                                  projection (evaluated by rtproj_plan_status or
+                                  rtproj_plan_info)                                 */
+    double refine_rho_est;     /* contraction per step estimated from the steps'
+                                  corrections (|d_1|/|x_1| and ratios of
+                                  successive same-kind corrections)                 */
+    double refine_err_est;     /* relative error of x estimated after the last step:
+                                  refine_rho_est times the last |d| / |x|            */
+    double refine_rho_model;   /* contraction per step the schedule was planned with
+                                  (see rtproj_plan_set_refinement)                  */
+    int method;                /* rtproj_method of the last precondition             */
 } rtproj_info;
 
 /*
@@ -156,8 +207,32 @@ rtproj_status rtproj_plan_destroy(rtproj_plan plan);
 rtproj_status rtproj_plan_set_stream(rtproj_plan plan, void *hip_stream);
 
 /* Precision of the preconditioner (rtproj_precision).  Takes effect at the
- * next rtproj_precondition. */
+ * next rtproj_precondition; projections plan their refinement for the
+ * precision the preconditioner in use was built with. */
 rtproj_status rtproj_plan_set_precision(rtproj_plan plan, int precision);
+
+/* Precision of P^{-1}A in the reduced-precision modes: 0 (default) binary32
+ * while the rank estimate allows it (kappa_est <= 1e5), else binary64; 32 or
+ * 64 forces it.  Forcing binary32 on an ill-conditioned A makes the
+ * preconditioner too poor for the refinement to contract (Remarks 4.2 and
+ * 4.3), which rtproj_plan_status then reports as RTPROJ_ERR_NOCONV.  Takes
+ * effect at the next rtproj_precondition; RTPROJ_ERR_INVALID_ARG for other
+ * values. */
+rtproj_status rtproj_plan_set_w_bits(rtproj_plan plan, int bits);
+
+/* Method (rtproj_method); default RTPROJ_METHOD_RANDOMIZED.  Takes effect
+ * at the next rtproj_precondition.  RTPROJ_ERR_INVALID_ARG for an unknown
+ * value; RTPROJ_ERR_UNSUPPORTED for the classical scheme with m > 4096.
+ * With RTPROJ_METHOD_CLASSICAL, rtproj_precondition forms A A^* and its
+ * pivoted QR (kappa_est then reports |R_11 / R_mm| of that QR, about
+ * cond(A)^2, and fails only on a zero or non-finite pivot), the projections
+ * compute x = Pi R^{-1} Q^T A b and A^* x, b - A^* x in plain binary64, and
+ * the refinement and residual settings do not apply. */
+rtproj_status rtproj_plan_set_method(rtproj_plan plan, int method);
+
+/* Arithmetic of the refinement residuals (rtproj_residual); default
+ * RTPROJ_RESID_AUTO.  Takes effect at the next projection. */
+rtproj_status rtproj_plan_set_residual(rtproj_plan plan, int mode);
 
 /* Method of the pivoted QR of the sketch (rtproj_qr_mode).  Takes effect at
  * the next rtproj_precondition; RTPROJ_ERR_UNSUPPORTED if the mode cannot
@@ -171,17 +246,25 @@ rtproj_status rtproj_plan_set_inverse(rtproj_plan plan, int method);
 /*
  * Iterative refinement of the least-squares solution (Remark 4.3): up to
  * `max_steps` steps x <- x + M^{-1} A (b - A^T x) with M = P X P^T the
- * preconditioned normal matrix, residuals accumulated in double-binary64
- * (error-free transformations) and x kept as an unevaluated sum of two
- * binary64 numbers.  rtol > 0 stops early once |dx| <= rtol |x| (one device-
- * to-host read per step); rtol = 0 runs exactly max_steps steps without any
- * host synchronisation.  max_steps = 0 returns the unrefined projection
- * (the seven steps of Sec. 4 in binary64); max_steps = -1 (the default)
- * chooses the schedule from the rank estimate of the pivoted QR: with
- * contraction rho ~ 16 u_W kappa_est + (the Gram's rounding), steps whose
- * residuals are plain binary64 while the error is above their floor
- * 16 u kappa_est, then compensated steps until rho^s times the error is
- * <= 1e-14.  An explicit max_steps runs compensated steps only.
+ * preconditioned normal matrix.  rtol > 0 stops early once |dx| <= rtol |x|
+ * (one device-to-host read per step) and returns RTPROJ_ERR_NOCONV from the
+ * projection itself when the steps stopped contracting; rtol = 0 runs
+ * exactly the scheduled steps without any host synchronisation.
+ * max_steps = 0 returns the unrefined projection (the seven steps of Sec. 4
+ * in binary64); max_steps = -1 (the default) chooses the schedule from the
+ * rank estimate kappa_est of the pivoted QR, with the contraction per step
+ * modelled as rho = 16 u kappa_est (binary64 P^{-1}A) or 2 u_32 kappa_est
+ * (binary32 P^{-1}A), plus the Gram's rounding (u_32 K / 32 for a Gram
+ * accumulated in binary32 over K terms per split, plus 4e-3 for bfloat16
+ * inputs), and the floor of a plain binary64 residual as 16 u kappa_est
+ * (relative error of x; rtproj_info.refine_rho_model reports rho): plain
+ * steps while the
+ * error is above that floor, then, unless the floor itself is below the goal
+ * 1e-11, compensated steps until rho^s times the error is <= 1e-11.  In
+ * RTPROJ_RESID_AUTO the compensated steps compensate r and s and the final
+ * A^T x is compensated whenever a compensated step ran.  An explicit
+ * max_steps runs that many compensated steps (plain ones in
+ * RTPROJ_RESID_PLAIN).
  */
 rtproj_status rtproj_plan_set_refinement(rtproj_plan plan, int max_steps, double rtol);
 
@@ -190,10 +273,15 @@ rtproj_status rtproj_plan_set_refinement(rtproj_plan plan, int max_steps, double
  * sketch S = A G (eq. testing), pivoted QR S^T = Q R Pi (eq. QR_decomp),
  * P^- = Pi^T R^{-1} (eq. scary) in its transposed form R^{-T}, the
  * preconditioned matrix P^{-1}A = R^{-T} Pi A, its Gram X (the matrix X of
- * Sec. 4, steps a-e) and the Cholesky factor of X in place of Y = X^{-1}
- * (eq. inversion).  Blocks the host until the pivoted QR is done (rank test).
- * Returns RTPROJ_ERR_RANK if |R_mm| <= m * 2^-52 * |R_11| or the Cholesky
- * breaks down.  A is borrowed (see above).
+ * Sec. 4, steps a-e) and Y = X^{-1} (eq. inversion): by default Newton-
+ * Schulz iterations for m <= 1024 and a Cholesky factor of X above that
+ * (rtproj_plan_set_inverse).  Blocks the host until the pivoted QR is done
+ * (rank test) and until the inverse is formed (its residual or breakdown).
+ * In the reduced-precision modes a binary32 sketch is redone in binary64
+ * when the rank estimate shows it too coarse (2^-24 kappa_est > 1), or when
+ * the Gram shows a poorly conditioned P^{-1}A.  Returns RTPROJ_ERR_RANK if
+ * |R_mm| <= m * 2^-52 * |R_11|, the Cholesky breaks down or Newton-Schulz
+ * does not converge.  A is borrowed (see above).
  */
 rtproj_status rtproj_precondition(rtproj_plan plan, const double *A, int64_t lda);
 
@@ -223,8 +311,17 @@ rtproj_status rtproj_project_all(rtproj_plan plan, const double *B, int64_t ldb,
 rtproj_status rtproj_plan_set_timing(rtproj_plan plan, int enable);
 
 /* Sizes, rank estimate, refinement and stage-timing statistics (synchronises
- * the stream). */
+ * the stream and evaluates the last projection's convergence check). */
 rtproj_status rtproj_plan_info(rtproj_plan plan, rtproj_info *out);
+
+/* Waits for the plan's stream and returns the outcome of the last
+ * projection's refinement (Remarks 4.2 and 4.3): RTPROJ_ERR_NOCONV when a
+ * step's correction did not shrink to at most half the previous one while
+ * corrections were still above 1e-11 |x|, or when the error estimated after
+ * the last step (the estimated contraction times the last |dx| / |x|) is
+ * above 1e-10; the outputs then hold the last iterate.  RTPROJ_OK otherwise,
+ * and when nothing was refined. */
+rtproj_status rtproj_plan_status(rtproj_plan plan);
 
 /*
  * Copy plan state to device buffers supplied by the caller (synchronous):
@@ -296,8 +393,11 @@ rtproj_status rtproj_batch_project_all(rtproj_batch batch, const double *const *
                                        const int64_t *k, double *const *Z, const int64_t *ldz, double *const *Y,
                                        const int64_t *ldy, double *const *X, const int64_t *ldx);
 /* Waits for the batch's stream and reports, per member (per_member may be
- * NULL), RTPROJ_OK or RTPROJ_ERR_RANK (|R_mm| <= m 2^-52 |R_11|, a NaN in A,
- * or a Cholesky breakdown); returns the worst. */
+ * NULL), RTPROJ_OK, RTPROJ_ERR_RANK (|R_mm| <= m 2^-52 |R_11|, a NaN in A,
+ * or a Cholesky breakdown) or RTPROJ_ERR_NOCONV (the member's refinement in
+ * the last rtproj_batch_project_all did not converge, judged as in
+ * rtproj_plan_status); returns RTPROJ_ERR_RANK if any member has it, else
+ * RTPROJ_ERR_NOCONV if any member has it, else RTPROJ_OK. */
 rtproj_status rtproj_batch_status(rtproj_batch batch, int *per_member);
 /* Per-stage device time of the batch (stage indices as in rtproj_info),
  * accumulated while enabled; only eager (non-graph) calls are timed, and a
@@ -305,8 +405,40 @@ rtproj_status rtproj_batch_status(rtproj_batch batch, int *per_member);
 rtproj_status rtproj_batch_set_timing(rtproj_batch batch, int enable);
 /* Batch totals: largest m, n, l; refinement steps; stage times. */
 rtproj_status rtproj_batch_info(rtproj_batch batch, rtproj_info *out);
+/* Host copies of member i's sketch tables, as rtproj_sketch_tables for a
+ * plan (member i draws them from instance seed i, see above). */
+rtproj_status rtproj_batch_member_tables(rtproj_batch batch, int64_t i, int64_t *dims3, int8_t *sign, int32_t *sigma,
+                                         int32_t *tau, int32_t *J);
 /* Sizes and the rank estimates of member i (valid after rtproj_batch_status). */
 rtproj_status rtproj_batch_member_info(rtproj_batch batch, int64_t i, rtproj_info *out);
+
+/*
+ * Complex-valued A (Sec. 1: the method and its analysis extend to complex
+ * entries).  x = argmin |A^* x - b| with A^* the conjugate transpose, the
+ * row projection A^* x and the null projection b - A^* x, for a complex
+ * m x n A of rank m.  Complex arrays are interleaved (re, im) binary64
+ * pairs in device memory, 16-byte aligned (std::complex<double>,
+ * torch.complex128), with leading dimensions in complex elements and the
+ * layouts of the real calls: A row-major m x n (lda >= n), B, Z, Y
+ * column-major n x k, X column-major m x k.
+ *
+ * A complex plan runs a real plan of sizes (2m, 2n, 2l) on the real 2m x 2n
+ * matrix [Re A, -Im A; Im A, Re A], which maps [Re b; Im b] to [Re Ab; Im Ab]
+ * and whose transpose acts as A^*; the embedding is an isometry, so its
+ * projections and least-squares solution are those of A, and its condition
+ * number is cond(A).  The plan owns the embedded copy (4 m n doubles, formed
+ * at each rtproj_cprecondition, so A is not borrowed) and embedded
+ * right-hand sides and outputs (grown with k).  rtproj_cplan_real returns
+ * the real plan for the setters, rtproj_plan_info and rtproj_plan_status
+ * (its sizes are 2m, 2n, 2l).  Errors as for the real calls.
+ */
+typedef struct rtproj_cplan_s *rtproj_cplan;
+rtproj_status rtproj_cplan_create(int64_t m, int64_t n, int64_t l, uint64_t seed, rtproj_cplan *out);
+rtproj_status rtproj_cplan_destroy(rtproj_cplan plan);
+rtproj_plan rtproj_cplan_real(rtproj_cplan plan);
+rtproj_status rtproj_cprecondition(rtproj_cplan plan, const double *A, int64_t lda);
+rtproj_status rtproj_cproject_all(rtproj_cplan plan, const double *B, int64_t ldb, int64_t k, double *Z, int64_t ldz,
+                                  double *Y, int64_t ldy, double *X, int64_t ldx);
 
 const char *rtproj_status_string(rtproj_status status);
 const char *rtproj_last_error(void);

@@ -38,7 +38,7 @@ def build(force: bool = True) -> str:
     """Compile ``oracle.c`` with gcc (-O2, OpenMP) into ``liboracle.so``."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
-        cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"]
+        cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", _SRC, "-o", tmp, "-lquadmath", "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -60,6 +60,9 @@ def bind(path: str):
     lib.orc_project.restype = ip
     lib.orc_project_r.argtypes = [i64, i64, dp, i64, dp, i64, i64, dp, i64, dp, i64, dp, i64, dp, i64, ip, dp]
     lib.orc_project_r.restype = ip
+    lib.orc_project_complex_r.argtypes = [i64, i64, dp, i64, dp, i64, i64, dp, i64, dp, i64, dp, i64, dp, i64, ip,
+                                          dp]
+    lib.orc_project_complex_r.restype = ip
     lib.orc_num_threads.restype = ip
     return lib
 

@@ -27,13 +27,17 @@
  *   orc_project_r        The same outputs from a triangular factor of A^T
  *                        supplied by the caller (LAPACK's Householder QR
  *                        as a library step), refined the same way.
+ *   orc_project_complex_r  The same for complex A (conjugate transpose A^*),
+ *                        with binary128 complex residuals.
  *
  * Conventions
  *   A is row-major m x n with leading dimension lda (element (i,j) at
  *   A[i*lda + j]).  Right-hand sides are column-major n x k (column c at
  *   B + c*ldb).  X is column-major m x k.
  */
+#include <complex.h>
 #include <math.h>
+#include <quadmath.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -397,6 +401,116 @@ int orc_project_r(int64_t m, int64_t n, const double *A, int64_t lda, const doub
     int rc = refine_and_form(m, n, A, lda, R, ldr, 1, k, B, ldb, xq, Z, ldz, P, ldp, X, ldx, maxit, info);
     free(xq);
     return rc;
+}
+
+/*
+ * Complex-valued A (Sec. 1: the method extends to complex entries), with
+ * A^* the conjugate transpose.  Data are interleaved (re, im) binary64
+ * pairs: A row-major m x n (element (i,j) at 2*(i*lda + j)), B/Z/P column-
+ * major n x k, X column-major m x k, R upper triangular m x m row-major (a
+ * Householder factor of A^*, so that R^* R = A A^*, from the caller).
+ * x starts at 0; per step r = b - A^* x and s = A r in binary128 complex,
+ * d = R^{-1} R^{-*} s in binary64 complex, x += d kept in binary128; stop
+ * as refine_and_form does.  Then p = A^* x, z = b - p, rounded once.
+ */
+typedef __complex128 cquad;
+
+static void csolve_rh(int64_t m, const double *R, int64_t ldr, double _Complex *y)
+{   /* R^* y = c: forward substitution with the conjugate transpose */
+    for (int64_t i = 0; i < m; ++i) {
+        double _Complex s = y[i];
+        for (int64_t j = 0; j < i; ++j) {
+            const double _Complex rji = R[2 * (j * ldr + i)] + R[2 * (j * ldr + i) + 1] * 1.0i;
+            s -= conj(rji) * y[j];
+        }
+        const double _Complex rii = R[2 * (i * ldr + i)] + R[2 * (i * ldr + i) + 1] * 1.0i;
+        y[i] = s / conj(rii);
+    }
+}
+
+static void csolve_r(int64_t m, const double *R, int64_t ldr, double _Complex *y)
+{   /* R y = c: back substitution */
+    for (int64_t i = m - 1; i >= 0; --i) {
+        double _Complex s = y[i];
+        for (int64_t j = i + 1; j < m; ++j) s -= (R[2 * (i * ldr + j)] + R[2 * (i * ldr + j) + 1] * 1.0i) * y[j];
+        y[i] = s / (R[2 * (i * ldr + i)] + R[2 * (i * ldr + i) + 1] * 1.0i);
+    }
+}
+
+static cquad cq(const double *v) { cquad z; __real__ z = v[0]; __imag__ z = v[1]; return z; }
+
+int orc_project_complex_r(int64_t m, int64_t n, const double *A, int64_t lda, const double *R, int64_t ldr,
+                          int64_t k, const double *B, int64_t ldb, double *Z, int64_t ldz, double *P, int64_t ldp,
+                          double *X, int64_t ldx, int maxit, double *info)
+{
+    if (m < 1 || n < m || lda < n || ldr < m || k < 0 || (k > 0 && ldb < n)) return 1;
+    cquad *r = (cquad *)malloc(sizeof(cquad) * (size_t)n);
+    cquad *x = (cquad *)malloc(sizeof(cquad) * (size_t)m);
+    double _Complex *d = (double _Complex *)malloc(sizeof(double _Complex) * (size_t)m);
+    if (!r || !x || !d) { free(r); free(x); free(d); return 3; }
+    int steps_max = 0;
+    double last_ratio = 0.0;
+    for (int64_t c = 0; c < k; ++c) {
+        const double *b = B + 2 * c * ldb;
+        for (int64_t i = 0; i < m; ++i) x[i] = 0;
+        double prev = INFINITY, ratio = 0.0;
+        int steps = 0;
+        for (int it = 0; it < maxit; ++it) {
+            /* r = b - A^* x: entry t subtracts conj(a_it) x_i for i = 0..m-1 */
+            #pragma omp parallel for schedule(static)
+            for (int64_t t = 0; t < n; ++t) {
+                cquad acc = cq(b + 2 * t);
+                for (int64_t i = 0; i < m; ++i) acc -= conjq(cq(A + 2 * (i * lda + t))) * x[i];
+                r[t] = acc;
+            }
+            /* s = A r, rounded once to binary64 */
+            #pragma omp parallel for schedule(static)
+            for (int64_t i = 0; i < m; ++i) {
+                cquad s = 0;
+                for (int64_t t = 0; t < n; ++t) s += cq(A + 2 * (i * lda + t)) * r[t];
+                d[i] = (double)crealq(s) + (double)cimagq(s) * 1.0i;
+            }
+            csolve_rh(m, R, ldr, d);
+            csolve_r(m, R, ldr, d);
+            double dn = 0.0, xn = 0.0;
+            for (int64_t i = 0; i < m; ++i) {
+                cquad di;
+                __real__ di = creal(d[i]);
+                __imag__ di = cimag(d[i]);
+                x[i] += di;
+                dn += creal(d[i]) * creal(d[i]) + cimag(d[i]) * cimag(d[i]);
+                const double xr = (double)crealq(x[i]), xim = (double)cimagq(x[i]);
+                xn += xr * xr + xim * xim;
+            }
+            dn = sqrt(dn); xn = sqrt(xn);
+            ++steps;
+            ratio = xn > 0.0 ? dn / xn : 0.0;
+            if (dn <= 1e-22 * xn || dn >= prev) break;
+            prev = dn;
+        }
+        /* p = A^* x and z = b - A^* x in binary128 complex */
+        #pragma omp parallel for schedule(static)
+        for (int64_t t = 0; t < n; ++t) {
+            cquad acc = 0;
+            for (int64_t i = 0; i < m; ++i) acc += conjq(cq(A + 2 * (i * lda + t))) * x[i];
+            if (P) { P[2 * (c * ldp + t)] = (double)crealq(acc); P[2 * (c * ldp + t) + 1] = (double)cimagq(acc); }
+            if (Z) {
+                const cquad zt = cq(b + 2 * t) - acc;
+                Z[2 * (c * ldz + t)] = (double)crealq(zt);
+                Z[2 * (c * ldz + t) + 1] = (double)cimagq(zt);
+            }
+        }
+        if (X)
+            for (int64_t i = 0; i < m; ++i) {
+                X[2 * (c * ldx + i)] = (double)crealq(x[i]);
+                X[2 * (c * ldx + i) + 1] = (double)cimagq(x[i]);
+            }
+        if (steps > steps_max) steps_max = steps;
+        if (ratio > last_ratio) last_ratio = ratio;
+    }
+    if (info) { info[0] = steps_max; info[1] = last_ratio; }
+    free(r); free(x); free(d);
+    return 0;
 }
 
 /* Number of OpenMP threads the oracle runs with. */

@@ -40,12 +40,18 @@ class _Info(ctypes.Structure):
                 ("t_stage_ms", ctypes.c_double * 16),
                 ("stage_calls", ctypes.c_int64 * 16),
                 ("qr_mode", ctypes.c_int), ("inverse", ctypes.c_int), ("inverse_iters", ctypes.c_int),
-                ("inverse_resid", ctypes.c_double)]
+                ("inverse_resid", ctypes.c_double), ("refine_plain", ctypes.c_int), ("refine_comp", ctypes.c_int),
+                ("resid_mode", ctypes.c_int), ("refine_status", ctypes.c_int), ("refine_rho_est", ctypes.c_double),
+                ("refine_err_est", ctypes.c_double), ("refine_rho_model", ctypes.c_double),
+                ("method", ctypes.c_int)]
 
 STAGES = ["sketch", "qrcp", "rinv_trsm", "w_gemm", "gram_syrk", "gram_inv", "minv_form", "ab",
-          "minv", "refine_atx", "refine_ab", "final_atx", "qr_r0"]
+          "minv", "refine_atx", "refine_ab", "final_atx", "qr_r0", "refine_atx_plain", "refine_ab_plain",
+          "final_atx_plain"]
 QR_AUTO, QR_DIRECT, QR_TWO_STAGE, QR_TWO_STAGE_WG = 0, 1, 2, 3
 INV_AUTO, INV_NEWTON_SCHULZ, INV_CHOLESKY = 0, 1, 2
+RESID_AUTO, RESID_PLAIN, RESID_S_ONLY, RESID_FULL = 0, 1, 2, 3
+METHOD_RANDOMIZED, METHOD_CLASSICAL = 0, 1
 
 
 def lib():
@@ -64,6 +70,10 @@ def lib():
         L.rtproj_plan_set_refinement.argtypes = [vp, ip, dp]
         L.rtproj_plan_set_qr.argtypes = [vp, ip]
         L.rtproj_plan_set_inverse.argtypes = [vp, ip]
+        L.rtproj_plan_set_residual.argtypes = [vp, ip]
+        L.rtproj_plan_set_method.argtypes = [vp, ip]
+        L.rtproj_plan_set_w_bits.argtypes = [vp, ip]
+        L.rtproj_plan_status.argtypes = [vp]
         L.rtproj_precondition.argtypes = [vp, vp, i64]
         L.rtproj_project_null.argtypes = [vp, vp, i64, i64, vp, i64]
         L.rtproj_project_row.argtypes = [vp, vp, i64, i64, vp, i64]
@@ -83,13 +93,22 @@ def lib():
         L.rtproj_batch_project_all.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.rtproj_batch_status.argtypes = [vp, vp]
         L.rtproj_batch_member_info.argtypes = [vp, i64, ctypes.POINTER(_Info)]
+        L.rtproj_batch_member_tables.argtypes = [vp, i64, vp, vp, vp, vp, vp]
         L.rtproj_batch_set_timing.argtypes = [vp, ip]
         L.rtproj_batch_info.argtypes = [vp, ctypes.POINTER(_Info)]
+        L.rtproj_cplan_create.argtypes = [i64, i64, i64, u64, ctypes.POINTER(vp)]
+        L.rtproj_cplan_destroy.argtypes = [vp]
+        L.rtproj_cplan_real.argtypes = [vp]
+        L.rtproj_cplan_real.restype = vp
+        L.rtproj_cprecondition.argtypes = [vp, vp, i64]
+        L.rtproj_cproject_all.argtypes = [vp, vp, i64, i64, vp, i64, vp, i64, vp, i64]
         L.rtproj_status_string.argtypes = [ip]
         L.rtproj_status_string.restype = ctypes.c_char_p
         L.rtproj_last_error.restype = ctypes.c_char_p
         for name in ["rtproj_plan_create", "rtproj_plan_destroy", "rtproj_plan_set_stream",
                      "rtproj_plan_set_precision", "rtproj_plan_set_refinement", "rtproj_plan_set_qr", "rtproj_plan_set_inverse",
+                     "rtproj_plan_set_residual", "rtproj_plan_set_w_bits", "rtproj_plan_status",
+                     "rtproj_plan_set_method",
                      "rtproj_precondition",
                      "rtproj_project_null", "rtproj_project_row", "rtproj_lstsq", "rtproj_project_all",
                      "rtproj_plan_info", "rtproj_plan_export", "rtproj_sketch_tables",
@@ -97,7 +116,8 @@ def lib():
                      "rtproj_batch_set_stream", "rtproj_batch_set_refinement", "rtproj_batch_set_graph",
                      "rtproj_batch_precondition", "rtproj_batch_project_all", "rtproj_batch_status",
                      "rtproj_batch_member_info", "rtproj_batch_set_timing", "rtproj_batch_info",
-                     "rtproj_batch_precondition_scaled"]:
+                     "rtproj_batch_precondition_scaled", "rtproj_batch_member_tables", "rtproj_cplan_create",
+                     "rtproj_cplan_destroy", "rtproj_cprecondition", "rtproj_cproject_all"]:
             getattr(L, name).restype = ip
         _lib = L
     return _lib
@@ -112,7 +132,7 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def _check_tensor(t, name, rows=None, cols=None):
+def _check_tensor(t, name, rows=None, cols=None, device=None):
     import torch
     if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
         raise TypeError(f"{name} must be a float64 CUDA tensor")
@@ -122,6 +142,10 @@ def _check_tensor(t, name, rows=None, cols=None):
         raise ValueError(f"{name} has {t.shape[0]} rows, expected {rows}")
     if cols is not None and t.shape[1] != cols:
         raise ValueError(f"{name} has {t.shape[1]} columns, expected {cols}")
+    if t.shape[0] > 1 and t.stride(0) < t.shape[1]:
+        raise ValueError(f"{name} rows overlap (row stride {t.stride(0)} < {t.shape[1]})")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
 
 
 class Plan:
@@ -165,6 +189,24 @@ class Plan:
     def set_refinement(self, max_steps: int, rtol: float = 0.0):
         _check(lib().rtproj_plan_set_refinement(self.handle, max_steps, rtol))
 
+    def set_residual(self, mode: int):
+        """Arithmetic of the refinement residuals (RESID_AUTO, RESID_PLAIN, RESID_S_ONLY, RESID_FULL)."""
+        _check(lib().rtproj_plan_set_residual(self.handle, mode))
+
+    def set_method(self, method: int):
+        """METHOD_RANDOMIZED (default) or METHOD_CLASSICAL (eq. basic_identity
+        with a pivoted QR of A A^T, the comparison scheme of Sec. 5)."""
+        _check(lib().rtproj_plan_set_method(self.handle, method))
+
+    def set_w_bits(self, bits: int):
+        """Precision of P^{-1}A in the reduced-precision modes: 0 automatic, 32 or 64 forced."""
+        _check(lib().rtproj_plan_set_w_bits(self.handle, bits))
+
+    def status(self):
+        """Waits for the plan's stream; raises RtprojError (ERR_NOCONV) when the
+        last projection's refinement did not converge."""
+        _check(lib().rtproj_plan_status(self.handle))
+
     def precondition(self, A):
         _check_tensor(A, "A", self.m, self.n)
         _check(lib().rtproj_precondition(self.handle, _ptr(A), A.stride(0)))
@@ -178,6 +220,7 @@ class Plan:
         import torch
         k = self._rhs(B)
         Z = out if out is not None else torch.empty_like(B)
+        _check_tensor(Z, "Z", k, self.n, B.device)
         _check(lib().rtproj_project_null(self.handle, _ptr(B), B.stride(0), k, _ptr(Z), Z.stride(0)))
         return Z
 
@@ -185,6 +228,7 @@ class Plan:
         import torch
         k = self._rhs(B)
         Y = out if out is not None else torch.empty_like(B)
+        _check_tensor(Y, "Y", k, self.n, B.device)
         _check(lib().rtproj_project_row(self.handle, _ptr(B), B.stride(0), k, _ptr(Y), Y.stride(0)))
         return Y
 
@@ -192,6 +236,7 @@ class Plan:
         import torch
         k = self._rhs(B)
         X = out if out is not None else torch.empty((k, self.m), dtype=B.dtype, device=B.device)
+        _check_tensor(X, "X", k, self.m, B.device)
         _check(lib().rtproj_lstsq(self.handle, _ptr(B), B.stride(0), k, _ptr(X), X.stride(0)))
         return X
 
@@ -204,6 +249,9 @@ class Plan:
             Y = torch.empty_like(B)
         if want[2] and X is None:
             X = torch.empty((k, self.m), dtype=B.dtype, device=B.device)
+        for t, name, rows, cols in ((Z, "Z", k, self.n), (Y, "Y", k, self.n), (X, "X", k, self.m)):
+            if t is not None:
+                _check_tensor(t, name, rows, cols, B.device)
         _check(lib().rtproj_project_all(self.handle, _ptr(B), B.stride(0), k,
                                         _ptr(Z), Z.stride(0) if Z is not None else 0,
                                         _ptr(Y), Y.stride(0) if Y is not None else 0,
@@ -245,6 +293,75 @@ class Plan:
         _check(lib().rtproj_sketch_tables(self.handle, None, sign.ctypes.data, sigma.ctypes.data,
                                           tau.ctypes.data, J.ctypes.data))
         return dict(np=np_, n1=n1, n2=n2, sign=sign, sigma=sigma, tau=tau, J=J)
+
+
+def _check_complex(t, name, rows=None, cols=None, device=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or not t.is_cuda:
+        raise TypeError(f"{name} must be a complex128 CUDA tensor")
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{name} must be 2-D with unit stride along its last dimension")
+    if rows is not None and t.shape[0] != rows:
+        raise ValueError(f"{name} has {t.shape[0]} rows, expected {rows}")
+    if cols is not None and t.shape[1] != cols:
+        raise ValueError(f"{name} has {t.shape[1]} columns, expected {cols}")
+    if t.shape[0] > 1 and t.stride(0) < t.shape[1]:
+        raise ValueError(f"{name} rows overlap")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+
+
+class CPlan:
+    """A plan for complex m x n matrices (rtproj_cplan): projections with the
+    conjugate transpose A^*.  A (m, n), B/Z/Y (k, n), X (k, m) complex128
+    CUDA tensors.  ``real`` is the underlying real plan (sizes 2m, 2n, 2l)
+    for the setters, info() and status()."""
+
+    def __init__(self, m: int, n: int, l: int, seed: int, stream=None):
+        h = ctypes.c_void_p()
+        _check(lib().rtproj_cplan_create(m, n, l, seed, ctypes.byref(h)))
+        self.handle, self.m, self.n, self.l = h, m, n, l
+        real = object.__new__(Plan)
+        real.handle = ctypes.c_void_p(lib().rtproj_cplan_real(h))
+        real.m, real.n, real.l, real.seed, real._A = 2 * m, 2 * n, 2 * l, seed, None
+        real.close = lambda: None   # owned by the complex plan
+        self.real = real
+        self.real.set_stream(stream)
+
+    def close(self):
+        if self.handle:
+            lib().rtproj_cplan_destroy(self.handle)
+            self.handle = None
+            self.real.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def precondition(self, A):
+        _check_complex(A, "A", self.m, self.n)
+        _check(lib().rtproj_cprecondition(self.handle, _ptr(A), A.stride(0)))
+
+    def project_all(self, B, Z=None, Y=None, X=None, want=(True, True, True)):
+        import torch
+        _check_complex(B, "B", None, self.n)
+        k = B.shape[0]
+        if want[0] and Z is None:
+            Z = torch.empty_like(B)
+        if want[1] and Y is None:
+            Y = torch.empty_like(B)
+        if want[2] and X is None:
+            X = torch.empty((k, self.m), dtype=B.dtype, device=B.device)
+        for t, name, rows, cols in ((Z, "Z", k, self.n), (Y, "Y", k, self.n), (X, "X", k, self.m)):
+            if t is not None:
+                _check_complex(t, name, rows, cols, B.device)
+        _check(lib().rtproj_cproject_all(self.handle, _ptr(B), B.stride(0), k,
+                                         _ptr(Z), Z.stride(0) if Z is not None else 0,
+                                         _ptr(Y), Y.stride(0) if Y is not None else 0,
+                                         _ptr(X), X.stride(0) if X is not None else 0))
+        return Z, Y, X
 
 
 def _ptrs(ts):
@@ -332,6 +449,13 @@ class Batch:
         Z = outs(Zs, lambda i: (ks[i], self.ns[i]))
         Y = outs(Ys, lambda i: (ks[i], self.ns[i]))
         X = outs(Xs, lambda i: (ks[i], self.ms[i]))
+        for ts, name, cols in ((Z, "Z", self.ns), (Y, "Y", self.ns), (X, "X", self.ms)):
+            if ts is None:
+                continue
+            if len(ts) != self.count:
+                raise ValueError(f"{name} has {len(ts)} members, expected {self.count}")
+            for i, t in enumerate(ts):
+                _check_tensor(t, f"{name}[{i}]", ks[i], cols[i], Bs[i].device)
 
         def arr(ts):
             return (_ptrs(ts), _i64s([t.stride(0) for t in ts])) if ts is not None else (None, None)
@@ -357,6 +481,20 @@ class Batch:
         d["stage_ms"] = {name: inf.t_stage_ms[i] for i, name in enumerate(STAGES)}
         d["stage_calls"] = {name: inf.stage_calls[i] for i, name in enumerate(STAGES)}
         return d
+
+    def member_tables(self, i: int) -> dict:
+        """Host copies of member i's sketch tables (signs, permutations, subset)."""
+        import numpy as np
+        dims = np.zeros(3, dtype=np.int64)
+        _check(lib().rtproj_batch_member_tables(self.handle, i, dims.ctypes.data, None, None, None, None))
+        np_, n1, n2 = (int(v) for v in dims)
+        sign = np.empty(np_, dtype=np.int8)
+        sigma = np.empty(n1, dtype=np.int32)
+        tau = np.empty(n2, dtype=np.int32)
+        J = np.empty(self.ls[i], dtype=np.int32)
+        _check(lib().rtproj_batch_member_tables(self.handle, i, None, sign.ctypes.data, sigma.ctypes.data,
+                                                tau.ctypes.data, J.ctypes.data))
+        return dict(np=np_, n1=n1, n2=n2, sign=sign, sigma=sigma, tau=tau, J=J)
 
     def member_info(self, i: int) -> dict:
         inf = _Info()

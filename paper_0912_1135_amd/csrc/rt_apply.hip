@@ -588,6 +588,16 @@ __global__ void copy_cols_kernel(const double *src, int64_t lds, double *dst, in
     copy_cols_body(src, lds, dst, ldd, rows, cols, zero_out, ldz, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
+__global__ void sub_cols_kernel(const double *B, int64_t ldb, const double *C, int64_t ldc, double *out, int64_t ldo,
+                                int rows, int cols)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)rows * cols) return;
+    const int j = (int)(e / rows), i = (int)(e % rows);
+    const double v = B[(int64_t)j * ldb + i] - C[(int64_t)j * ldc + i];
+    out[(int64_t)j * ldo + i] = v;
+}
+
 __global__ void copy_cols_grouped(const CopyGroupArgs *gs)
 {
     const CopyGroupArgs g = gs[blockIdx.y];
@@ -683,6 +693,16 @@ hipError_t atx_f64(const ApplyArgs &a, const double *Xhi, const double *Xlo, int
 hipError_t dd_update_f64(double *Xhi, double *Xlo, const double *D, int m, int k, double *norms, hipStream_t stream)
 {
     hipLaunchKernelGGL(dd_update_kernel, dim3(1), dim3(1024), 0, stream, Xhi, Xlo, D, m * k, norms);
+    return hipGetLastError();
+}
+
+hipError_t sub_cols_f64(const double *B, int64_t ldb, const double *C, int64_t ldc, double *out, int64_t ldo, int rows,
+                        int cols, hipStream_t stream)
+{
+    const int64_t total = (int64_t)rows * cols;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(sub_cols_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, B, ldb, C, ldc,
+                       out, ldo, rows, cols);
     return hipGetLastError();
 }
 

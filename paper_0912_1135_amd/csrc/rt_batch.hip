@@ -73,6 +73,9 @@ struct rtproj_batch_s {
     hipStream_t cap_stream = nullptr;  // graph capture (the null stream cannot be captured)
     int refine_steps = -1;  // -1: schedule from the members' rank estimates
     int plain_steps = 0, comp_steps = 2;  // schedule of the last projection
+    bool comp_final = true;               // its final A^T x compensated
+    int last_steps = 0, last_plain = 0;   // steps of the last projection (norms recorded)
+    std::vector<int64_t> last_k;          // right-hand sides per member in it
     int use_graph = 0;
     int timing = 0;                 // per-stage HIP events (eager mode only)
     double t_stage_ms[16] = {};
@@ -521,7 +524,7 @@ void build_project(Program &P, rtproj_batch b, const double *const *A, const int
         for (int64_t i = 0; i < cnt; ++i) z[i] = rt::MatGroupArgs{b->sub[i]->d_xlo, mm[i], (int)kk[i], (int)mm[i], 0.0, nullptr, nullptr};
         rec_mat(P, OP_SET0, z);
     }
-    const int nsteps = b->plain_steps + b->comp_steps;
+    const int nsteps = std::min(b->plain_steps + b->comp_steps, RT_MAX_STEPS);
     for (int it = 0; it < nsteps; ++it) {
         const int comp = it >= b->plain_steps ? 1 : 0;  // plain residuals first, compensated last
         std::vector<rt::AtxGroupArgs> a(cnt);
@@ -563,7 +566,7 @@ void build_project(Program &P, rtproj_batch b, const double *const *A, const int
         std::vector<rt::DdGroupArgs> u(cnt);
         for (int64_t i = 0; i < cnt; ++i) {
             rtproj_plan p = b->sub[i];
-            u[i] = rt::DdGroupArgs{p->d_xhi, p->d_xlo, p->d_d, (int)(p->m * kk[i]), p->d_norms};
+            u[i] = rt::DdGroupArgs{p->d_xhi, p->d_xlo, p->d_d, (int)(p->m * kk[i]), p->d_norms + 2 * it};
         }
         P.push(Op{OP_DDUPD, P.add(u), (int)cnt});
     }
@@ -577,7 +580,7 @@ void build_project(Program &P, rtproj_batch b, const double *const *A, const int
                                     Z ? Z[i] : nullptr, Z ? ldz[i] : 0};
             if (!(Y && Y[i]) && !(Z && Z[i])) a[i].a.k = 0;
         }
-        rec_atx(P, b, a, nsteps > 0 ? 1 : 0);
+        rec_atx(P, b, a, nsteps > 0 && b->comp_final ? 1 : 0);
     }
     if (X) {
         std::vector<rt::CopyGroupArgs> cp(cnt);
@@ -628,6 +631,27 @@ hipError_t run_op(const Op &o, const unsigned char *arena, hipStream_t s)
     case OP_SCALE: return rt::scale_cols_grouped_f64((const rt::ScaleGroupArgs *)d, o.count, s);
     }
     return hipErrorInvalidValue;
+}
+
+// Everything a launch sequence depends on: the descriptor bytes and every
+// op's own launch parameters (kind, offset, counts, shapes, flags), so that
+// two programs with equal descriptors but different flags (a compensated
+// against a plain pass) never share a captured graph.
+std::vector<unsigned char> program_key(const Program &P)
+{
+    std::vector<unsigned char> key(P.bytes);
+    auto put = [&key](const void *v, size_t n) {
+        const unsigned char *c = static_cast<const unsigned char *>(v);
+        key.insert(key.end(), c, c + n);
+    };
+    for (const Op &o : P.ops) {
+        const int ints[] = {(int)o.kind, o.count, o.i0, o.i1, o.i2, o.dd, o.gs.M, o.gs.N, o.gs.ksplit, o.gs.a_kc,
+                            o.gs.b_kc, o.gs.c_lower, o.gs.b_gather, o.ss.chunks};
+        const int64_t longs[] = {(int64_t)o.off, o.total, o.ss.max_n1, o.ss.max_n2, o.ss.max_rows_chunk};
+        put(ints, sizeof(ints));
+        put(longs, sizeof(longs));
+    }
+    return key;
 }
 
 // Upload the program's descriptors (only if they changed) and run it, from
@@ -683,7 +707,8 @@ rtproj_status run_program(rtproj_batch b, rtproj_batch_s::Slot &slot, const Prog
         RT_HIP(err);
         return RTPROJ_OK;
     }
-    if (!slot.exec || slot.graph_key != P.bytes) {
+    std::vector<unsigned char> key = program_key(P);
+    if (!slot.exec || slot.graph_key != key) {
         if (slot.exec) { (void)hipGraphExecDestroy(slot.exec); slot.exec = nullptr; }
         if (slot.graph) { (void)hipGraphDestroy(slot.graph); slot.graph = nullptr; }
         if (!b->cap_stream) RT_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
@@ -698,7 +723,7 @@ rtproj_status run_program(rtproj_batch b, rtproj_batch_s::Slot &slot, const Prog
         RT_HIP(e2);
         slot.graph = g;
         RT_HIP(hipGraphInstantiate(&slot.exec, slot.graph, nullptr, nullptr, 0));
-        slot.graph_key = P.bytes;
+        slot.graph_key = std::move(key);
     }
     RT_HIP(hipGraphLaunch(slot.exec, s));
     return RTPROJ_OK;
@@ -874,6 +899,7 @@ rtproj_status rtproj_batch_project_all(rtproj_batch b, const double *const *B, c
     if (b->refine_steps >= 0) {
         b->plain_steps = 0;
         b->comp_steps = b->refine_steps;
+        b->comp_final = b->refine_steps > 0;
     } else {
         // one schedule for all members (one program): the most demanding one,
         // from the rank estimates the preconditioner left on the device
@@ -881,25 +907,30 @@ rtproj_status rtproj_batch_project_all(rtproj_batch b, const double *const *B, c
         RT_HIP(hipMemcpyAsync(diag.data(), b->d_diag_all, diag.size() * sizeof(double), hipMemcpyDeviceToHost,
                               b->stream));
         RT_HIP(hipStreamSynchronize(b->stream));
-        int pl = 0, cp = 1;
+        int pl = 0, cp = 0;
+        bool cf = false;
         for (int64_t i = 0; i < b->count; ++i) {
             const double *d = diag.data() + 8 * i;
             const double kap = d[2] > 0 ? d[3] / d[2] : 1e16;
             const double cw = d[6] > 0 ? d[7] / d[6] : 1e3;
-            int a, c;
-            auto_refine_plan(std::isfinite(kap) ? kap : 1e16, RTPROJ_PREC_FP64, false, std::isfinite(cw) ? cw : 1e3,
-                             &a, &c);
-            pl = std::max(pl, a);
-            cp = std::max(cp, c);
+            const RefinePlan rp = refine_schedule(std::isfinite(kap) ? kap : 1e16, RTPROJ_PREC_FP64, false,
+                                                  std::isfinite(cw) ? cw : 1e3, 0.0, RTPROJ_RESID_FULL, -1);
+            pl = std::max(pl, rp.plain);
+            cp = std::max(cp, rp.comp);
+            cf = cf || rp.comp_final;
         }
         b->plain_steps = pl;
         b->comp_steps = cp;
+        b->comp_final = cf;
     }
     std::vector<const double *> A(b->count);
     std::vector<int64_t> lda(b->count);
     for (int64_t i = 0; i < b->count; ++i) { A[i] = b->sub[i]->A; lda[i] = b->sub[i]->lda; }
     Program P;
     build_project(P, b, A.data(), lda.data(), B, ldb, k, Z, ldz, Y, ldy, X, ldx);
+    b->last_steps = std::min(b->plain_steps + b->comp_steps, RT_MAX_STEPS);
+    b->last_plain = std::min(b->plain_steps, b->last_steps);
+    b->last_k.assign(k, k + b->count);
     return run_program(b, b->pro, P);
 }
 
@@ -914,12 +945,26 @@ rtproj_status rtproj_batch_status(rtproj_batch b, int *per_member)
         RT_HIP(hipMemcpyAsync(&cerr[i], b->sub[i]->d_err, sizeof(int), hipMemcpyDeviceToHost, s));
         RT_HIP(hipMemcpyAsync(&qerr[i], b->sub[i]->d_sync + 2, sizeof(int), hipMemcpyDeviceToHost, s));
     }
+    // per-step refinement norms of the last projection (members with k > 0)
+    const int ns = b->last_k.size() == (size_t)b->count ? b->last_steps : 0;
+    std::vector<double> norms((size_t)b->count * 2 * std::max(ns, 1), 0.0);
+    for (int64_t i = 0; i < b->count && ns > 0; ++i)
+        if (b->last_k[i] > 0)
+            RT_HIP(hipMemcpyAsync(norms.data() + (size_t)i * 2 * ns, b->sub[i]->d_norms, (size_t)ns * 2 * sizeof(double),
+                                  hipMemcpyDeviceToHost, s));
     RT_HIP(hipStreamSynchronize(s));
     rtproj_status worst = RTPROJ_OK;
     for (int64_t i = 0; i < b->count; ++i) {
         rtproj_plan p = b->sub[i];
         const double *d = diag.data() + 8 * i;
         rtproj_status st = RTPROJ_OK;
+        if (ns > 0 && b->last_k[i] > 0) {
+            double rho, err;
+            st = refine_verdict(norms.data() + (size_t)i * 2 * ns, ns, b->last_plain, &rho, &err);
+            p->info.refine_rho_est = rho;
+            p->info.refine_err_est = err;
+            p->info.refine_status = st;
+        }
         if (qerr[i] || cerr[i] || !(d[2] > (double)p->m * std::ldexp(1.0, -52) * d[3])) st = RTPROJ_ERR_RANK;
         p->info.kappa_est = d[2] > 0 ? d[3] / d[2] : INFINITY;
         p->info.rdiag_min = d[2];
@@ -927,10 +972,19 @@ rtproj_status rtproj_batch_status(rtproj_batch b, int *per_member)
         p->info.inverse = RTPROJ_INV_CHOLESKY;
         p->inv_used = RTPROJ_INV_CHOLESKY;
         if (per_member) per_member[i] = st;
-        if (st != RTPROJ_OK) worst = st;
+        if (st == RTPROJ_ERR_RANK || (st != RTPROJ_OK && worst == RTPROJ_OK)) worst = st;
     }
-    if (worst != RTPROJ_OK) return fail(worst, "at least one member is rank deficient or its factorization broke down");
+    if (worst == RTPROJ_ERR_RANK)
+        return fail(worst, "at least one member is rank deficient or its factorization broke down");
+    if (worst != RTPROJ_OK) return fail(worst, "the refinement of at least one member did not converge");
     return RTPROJ_OK;
+}
+
+rtproj_status rtproj_batch_member_tables(rtproj_batch b, int64_t i, int64_t *dims3, int8_t *sign, int32_t *sigma,
+                                         int32_t *tau, int32_t *J)
+{
+    if (!b || i < 0 || i >= b->count) return fail(RTPROJ_ERR_INVALID_ARG, "bad batch or member");
+    return rtproj_sketch_tables(b->sub[i], dims3, sign, sigma, tau, J);
 }
 
 rtproj_status rtproj_batch_member_info(rtproj_batch b, int64_t i, rtproj_info *out)
@@ -939,6 +993,8 @@ rtproj_status rtproj_batch_member_info(rtproj_batch b, int64_t i, rtproj_info *o
     *out = b->sub[i]->info;
     out->m = b->sub[i]->m; out->n = b->sub[i]->n; out->l = b->sub[i]->l; out->np = b->sub[i]->tab.np;
     out->refine_steps = b->plain_steps + b->comp_steps;
+    out->refine_plain = b->plain_steps;
+    out->refine_comp = b->comp_steps;
     out->qr_mode = RTPROJ_QR_TWO_STAGE_WG;
     return RTPROJ_OK;
 }

@@ -159,12 +159,17 @@ hipError_t sketch_f32(const SketchTables &t, const double *A, int64_t lda, int64
 
 // ---------------------------------------------------------------- pivoted QR
 struct QrcpWork {
-    unsigned *counter;   // grid-barrier arrival counter (zeroed by the launcher)
-    unsigned *flag;      // spare
-    int *err;            // 1: wait timeout, 2: no finite pivot
-    double *slots;       // 2 * blocks * 2 doubles: candidate (norm^2, column)
-    double *vbuf;        // 2 * blocks * rows doubles: candidate columns
-    double *cols;        // null: columns kept in LDS; else blocks * 16 * rows doubles
+    unsigned *counter = nullptr;  // grid-barrier arrival counter (zeroed by the launcher)
+    unsigned *flag = nullptr;     // spare
+    int *err = nullptr;           // 1: wait timeout, 2: no finite pivot
+    double *slots = nullptr;      // 2 * blocks * 2 doubles: candidate (norm^2, column)
+    double *vbuf = nullptr;       // 2 * blocks * rows doubles: candidate columns
+    double *cols = nullptr;       // null: columns kept in LDS; else blocks * 16 * rows doubles
+    // optional Householder reflectors: step k writes v (v[k] = 1) to
+    // V[k * rows + i] for rows i >= k, and its scalar to tau[k], so that
+    // M Pi = H_0 ... H_{cols-1} R with H_k = I - tau_k v v^T (null: not kept)
+    double *V = nullptr;
+    double *tau = nullptr;
 };
 // Column-pivoted Householder QR of M = S^T (rows = l, cols = m; column j of M
 // is row j of S, S row-major with ld lds).  R: m x m row-major, upper part
@@ -310,6 +315,15 @@ hipError_t copy_cols_grouped_f64(const CopyGroupArgs *d, int count, int64_t max_
 hipError_t dd_update_f64(double *Xhi, double *Xlo, const double *D, int m, int k, double *norms,
                          hipStream_t stream);
 // Copy an m x k column-major block (ld -> ld2), optionally zeroing `zero_out`.
+// Classical scheme: X (m x k, column-major) = Pi R^{-1} Q^T C for the
+// Householder pivoted QR M Pi = Q R of an m x m matrix with reflectors V
+// (QrcpWork::V layout), scalars tau, row-major upper-triangular R and piv.
+// m <= 8192 (the vector is kept in LDS).
+hipError_t qr_solve_f64(int m, const double *V, const double *tau, const double *R, const int32_t *piv,
+                        const double *C, int64_t ldc, double *X, int64_t ldx, int k, hipStream_t stream);
+// out = B - C for column-major rows x cols blocks (out may be B or C).
+hipError_t sub_cols_f64(const double *B, int64_t ldb, const double *C, int64_t ldc, double *out, int64_t ldo, int rows,
+                        int cols, hipStream_t stream);
 hipError_t copy_cols_f64(const double *src, int64_t lds, double *dst, int64_t ldd, int rows, int cols,
                          double *zero_out, int64_t ldz, hipStream_t stream);
 

@@ -82,11 +82,13 @@ void release(rtproj_plan p)
                     p->d_twl, p->d_tw1f, p->d_tw2f, p->d_twhf, p->d_twlf, p->d_rowscale, p->d_zbuf, p->d_S, p->d_R, p->d_Y, p->d_W, p->d_part, p->d_G, p->d_L, p->d_Tp,
                     p->d_DinvR, p->d_DinvL, p->d_piv, p->d_sync, p->d_slots, p->d_vbuf, p->d_qrcols, p->d_Yq, p->d_R0, p->d_wgargs, p->d_rinv_args, p->d_scal, p->d_diag,
                     p->d_bsum, p->d_c, p->d_tmp, p->d_xhi, p->d_xlo, p->d_d, p->d_r, p->d_ph, p->d_pl, p->d_norms, p->d_xpk, p->d_bpk,
-                    p->d_err};
+                    p->d_err, p->d_V, p->d_tau};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (p->h_scal) (void)hipHostFree(p->h_scal);
     p->h_scal = nullptr;
+    if (p->h_norms) (void)hipHostFree(p->h_norms);
+    p->h_norms = nullptr;
 }
 
 rtproj_status upload_tables(rtproj_plan p)
@@ -217,6 +219,7 @@ rtproj_status alloc_state(rtproj_plan p)
     }
     RT_HIP(dalloc(&p->d_scal, 8));
     RT_HIP(hipHostMalloc((void **)&p->h_scal, 4 * sizeof(unsigned long long), hipHostMallocDefault));
+    RT_HIP(hipHostMalloc((void **)&p->h_norms, 2 * RT_MAX_STEPS * sizeof(double), hipHostMallocDefault));
     RT_HIP(dalloc(&p->d_diag, 8));
     RT_HIP(dalloc(&p->d_err, 4));
     RT_HIP(dalloc(&p->d_rowscale, (size_t)m));
@@ -263,30 +266,47 @@ rtproj_status alloc_state(rtproj_plan p)
     return RTPROJ_OK;
 }
 
+ProjLayout proj_layout(int64_t m, int64_t n, int64_t k, int cu_count)
+{
+    ProjLayout L;
+    const int64_t rb = (m + 31) / 32, kb = (k + 31) / 32;  // row blocks x right-hand-side blocks of the A B pass
+    L.ab_splits = (int)std::max<int64_t>(1, std::min<int64_t>(n / 256, (4 * cu_count + rb * kb - 1) / (rb * kb)));
+    L.ab_sx_splits = rt::ab_sx_splits(m, n, k, cu_count);
+    const int64_t psplits = std::max<int64_t>(L.ab_splits, L.ab_sx_splits);
+    // c, tmp, xhi, xlo, d (m k each), r (n k), ph, pl (split partials), bpk, norms, xpk
+    const int64_t cnt[ProjLayout::NBUF] = {m * k, m * k, m * k, m * k, m * k, n * k, psplits * m * k,
+                                           psplits * m * k, rt::ab_pack_size(n, k), 2 * RT_MAX_STEPS,
+                                           rt::atx_pack_size(m, k)};
+    for (int i = 0; i < ProjLayout::NBUF; ++i) L.count[i] = std::max<int64_t>(1, cnt[i]);
+    return L;
+}
+
+size_t ProjLayout::bytes() const
+{
+    size_t b = 0;
+    for (int i = 0; i < NBUF; ++i) b += ((size_t)count[i] * sizeof(double) + 255) / 256 * 256;
+    return b;
+}
+
+double **proj_buffers(rtproj_plan p, int i)
+{
+    double **bufs[ProjLayout::NBUF] = {&p->d_c, &p->d_tmp, &p->d_xhi, &p->d_xlo, &p->d_d, &p->d_r,
+                                       &p->d_ph, &p->d_pl, &p->d_bpk, &p->d_norms, &p->d_xpk};
+    return bufs[i];
+}
+
 rtproj_status ensure_k(rtproj_plan p, int64_t k)
 {
     if (k <= p->kcap) return RTPROJ_OK;
-    double **bufs[] = {&p->d_c, &p->d_tmp, &p->d_xhi, &p->d_xlo, &p->d_d, &p->d_r, &p->d_ph, &p->d_pl, &p->d_norms,
-                       &p->d_xpk, &p->d_bpk};
-    for (double **b : bufs)
+    for (int i = 0; i < ProjLayout::NBUF; ++i) {
+        double **b = proj_buffers(p, i);
         if (*b) { (void)hipFree(*b); *b = nullptr; }
+    }
     p->kcap = 0;
-    const int64_t m = p->m, n = p->n;
-    const int64_t rb = (m + 31) / 32, kb = (k + 31) / 32;  // row blocks x right-hand-side blocks of the A B pass
-    p->ab_splits = (int)std::max<int64_t>(1, std::min<int64_t>(n / 256, (4 * p->cu_count + rb * kb - 1) / (rb * kb)));
-    RT_HIP(dalloc(&p->d_c, (size_t)m * k));
-    RT_HIP(dalloc(&p->d_tmp, (size_t)m * k));
-    RT_HIP(dalloc(&p->d_xhi, (size_t)m * k));
-    RT_HIP(dalloc(&p->d_xlo, (size_t)m * k));
-    RT_HIP(dalloc(&p->d_d, (size_t)m * k));
-    RT_HIP(dalloc(&p->d_r, (size_t)n * k));
-    p->ab_sx_splits = rt::ab_sx_splits(m, n, k, p->cu_count);
-    const int64_t psplits = std::max<int64_t>(p->ab_splits, p->ab_sx_splits);
-    RT_HIP(dalloc(&p->d_ph, (size_t)(psplits * m * k)));
-    RT_HIP(dalloc(&p->d_pl, (size_t)(psplits * m * k)));
-    RT_HIP(dalloc(&p->d_bpk, (size_t)rt::ab_pack_size(n, k)));
-    RT_HIP(dalloc(&p->d_norms, 4));
-    RT_HIP(dalloc(&p->d_xpk, (size_t)rt::atx_pack_size(m, k)));
+    const ProjLayout L = proj_layout(p->m, p->n, k, p->cu_count);
+    p->ab_splits = L.ab_splits;
+    p->ab_sx_splits = L.ab_sx_splits;
+    for (int i = 0; i < ProjLayout::NBUF; ++i) RT_HIP(dalloc(proj_buffers(p, i), (size_t)L.count[i]));
     p->kcap = k;
     return RTPROJ_OK;
 }
@@ -509,45 +529,114 @@ rtproj_status r0_factor(rtproj_plan p)
 
 bool ld_ok(int64_t ld, int64_t need) { return ld >= need && ld > 0; }
 
-// Refinement steps when none were requested: the contraction of a step is
-// about c u_W kappa(A) plus the Gram's rounding; with kappa_est =
-// max|R_ii| / min|R_ii| from the pivoted QR and a safety factor c = 16, take
-// the fewest steps s >= 1 with rho^(s+1) <= 1e-14 (binary64 accuracy of x
-// with margin), at most 12.
-// Refinement schedule when none was requested.  The contraction of a step
-// is rho ~ 16 u_W kappa + (the Gram's rounding); a residual evaluated in
-// plain binary64 stalls at the floor ~16 u kappa (relative error of x), so
-// plain steps are taken while the error is above that floor and compensated
-// (Dot2) steps after it, until rho^s * error <= 1e-14.  kappa is the rank
-// estimate of the pivoted QR; cond_w the Gram factor's diagonal ratio.
-void auto_refine_plan(double kappa_est, int precision, bool w32, double cond_w, int *plain, int *comp)
+// Refinement schedule (Remark 4.3).  The contraction of a step is modelled
+// as rho = c_W u_W kappa + (the Gram's rounding), with kappa the rank
+// estimate of the pivoted QR; the error of x after the first solve is about
+// rho.  Calibrated on measured unrefined errors (the first correction):
+//   - P^{-1}A in binary64: 16 u kappa (measured 0.3 to 1.3 times that);
+//     in binary32: 2 u_32 kappa (measured at most a tenth of that);
+//   - a binary32 Gram accumulated on MFMA in binary32 over K terms per
+//     split: u_32 K / 32 (measured u_32 K / 117 at K = 256 and 32768), times
+//     cond(P^{-1}A)^2 / 9 relative to a healthy preconditioner (cond ~ 3);
+//     a bfloat16 Gram adds the rounding of its inputs, 4e-3 (measured 3.9e-3).
+// A step with a plain binary64 residual takes the error to max(rho e, F)
+// with the floor F = RT_FLOOR_C u kappa; a compensated step to rho e (its
+// own floor is near u^2 kappa^2).  Plain steps cost a tenth of a compensated
+// one (MFMA GEMMs from 32 right-hand sides on), so the schedule takes plain
+// steps while they still lower the error, then compensated ones until the
+// error is at most RT_REFINE_GOAL; when F itself is below the goal no
+// compensated step is needed.
+double refine_rho_model(double kappa_est, int precision, bool w32, double cond_w, double gram_k)
 {
-    // W's error ~ u_W kappa; the Gram's own rounding adds ~16 u_G (binary32)
-    // or a few units of 2^-8 (bfloat16 inputs, binary32 accumulation)
-    const double uw = w32 ? std::ldexp(1.0, -23) : std::ldexp(1.0, -52);
+    const double k = std::max(1.0, std::isfinite(kappa_est) ? kappa_est : 1e16);
+    const double wterm = w32 ? 2.0 * std::ldexp(1.0, -23) * k : 16.0 * std::ldexp(1.0, -52) * k;
+    const double c2 = std::max(1.0, cond_w * cond_w / 9.0);
     double gram = 0.0;
-    const double c2 = std::max(1.0, cond_w * cond_w / 9.0);  // relative to a healthy cond ~ 3
-    if (precision == RTPROJ_PREC_MIXED_FP32) gram = 16.0 * std::ldexp(1.0, -23) * c2;
-    if (precision == RTPROJ_PREC_MIXED_BF16) gram = 4e-3 * c2;
-    const double k = std::max(1.0, kappa_est);
-    const double rho = std::min(0.5, 16.0 * uw * k + gram);
-    const double floor64 = std::min(0.5, 16.0 * std::ldexp(1.0, -52) * k);
-    // error after the first solve ~ rho; plain steps while above the floor
-    int np_ = 0;
-    double e = rho;
-    while (np_ < 12 && e * rho > floor64) { e *= rho; ++np_; }
-    e = std::max(e, floor64);
-    int nc = 1;
-    while (nc < 12 && e * std::pow(rho, nc) > 1e-14) ++nc;
-    *plain = np_;
-    *comp = nc;
+    if (precision == RTPROJ_PREC_MIXED_FP32 || precision == RTPROJ_PREC_MIXED_BF16)
+        gram = std::ldexp(1.0, -24) * std::max(1.0, gram_k) / 32.0 * c2;
+    if (precision == RTPROJ_PREC_MIXED_BF16) gram += 4e-3 * c2;
+    return std::min(0.5, wterm + gram);
 }
 
-int auto_refine_steps(double kappa_est, int precision, bool w32, double cond_w)
+RefinePlan refine_schedule(double kappa_est, int precision, bool w32, double cond_w, double gram_k, int mode,
+                           int max_steps)
 {
-    int a, b;
-    auto_refine_plan(kappa_est, precision, w32, cond_w, &a, &b);
-    return a + b;
+    RefinePlan r;
+    const double k = std::max(1.0, std::isfinite(kappa_est) ? kappa_est : 1e16);
+    r.rho = refine_rho_model(kappa_est, precision, w32, cond_w, gram_k);
+    if (mode == RTPROJ_RESID_AUTO) mode = RTPROJ_RESID_FULL;
+    r.comp_r = mode == RTPROJ_RESID_FULL;
+    if (max_steps >= 0) {
+        // explicit count: compensated steps (plain ones in the plain mode)
+        if (mode == RTPROJ_RESID_PLAIN) r.plain = max_steps;
+        else r.comp = max_steps;
+        r.comp_final = mode == RTPROJ_RESID_FULL && max_steps > 0;
+        return r;
+    }
+    const double floor64 = std::min(0.5, RT_FLOOR_C * std::ldexp(1.0, -52) * k);
+    double e = r.rho;
+    while (r.plain < 12 && e > RT_REFINE_GOAL && e > 1.5 * floor64) {
+        e = std::max(e * r.rho, floor64);
+        ++r.plain;
+    }
+    if (mode == RTPROJ_RESID_PLAIN || e <= RT_REFINE_GOAL) {
+        // at least one step, whose correction measures the contraction for
+        // the convergence check
+        r.plain = std::max(r.plain, 1);
+        r.comp_final = false;
+        return r;
+    }
+    while (r.comp < 12 && e > RT_REFINE_GOAL) {
+        e *= r.rho;
+        ++r.comp;
+    }
+    r.comp_final = mode == RTPROJ_RESID_FULL;
+    return r;
+}
+
+// Outcome of a refinement from its per-step (|d_j|^2, |x_j|^2) pairs.  The
+// first correction |d_0| / |x_0| is the error of the unrefined x, about one
+// contraction factor; successive corrections of steps of the same kind
+// shrink by the contraction.  The error after the last step is estimated as
+// the contraction estimate times the last relative correction when the
+// steps contract (estimate <= RT_NC_RATIO), else as the last relative
+// correction itself.
+rtproj_status refine_verdict(const double *norms, int steps, int plain, double *rho_est, double *err_est)
+{
+    *rho_est = 0.0;
+    *err_est = 0.0;
+    if (steps <= 0) return RTPROJ_OK;
+    double rho = 0.0, prev = 0.0, rel = 0.0;
+    for (int j = 0; j < steps; ++j) {
+        const double a = std::sqrt(norms[2 * j]), x = std::sqrt(norms[2 * j + 1]);
+        if (!std::isfinite(a) || !std::isfinite(x)) {
+            *rho_est = *err_est = INFINITY;
+            return RTPROJ_ERR_NOCONV;
+        }
+        rel = x > 0.0 ? a / x : (a > 0.0 ? INFINITY : 0.0);
+        if (j == 0) rho = rel;
+        else if ((j < plain) == (j - 1 < plain) && prev > 0.0) rho = std::max(rho, a / prev);
+        prev = a;
+    }
+    *rho_est = rho;
+    *err_est = rho <= RT_NC_RATIO ? rho * rel : rel;
+    return *err_est > RT_NC_TOL ? RTPROJ_ERR_NOCONV : RTPROJ_OK;
+}
+
+// Evaluates the pending convergence check of the last projection (the
+// stream must have passed its copy of the norms to h_norms).
+rtproj_status resolve_refine(rtproj_plan p)
+{
+    if (!p->nc_pending) return (rtproj_status)p->info.refine_status;
+    p->nc_pending = false;
+    double rho, err;
+    const rtproj_status st = refine_verdict(p->h_norms, p->nc_steps, p->nc_plain, &rho, &err);
+    p->info.refine_rho_est = rho;
+    p->info.refine_err_est = err;
+    p->info.refine_status = st;
+    p->info.refine_last_ratio = p->nc_steps > 0
+        ? std::sqrt(p->h_norms[2 * p->nc_steps - 2] / std::max(p->h_norms[2 * p->nc_steps - 1], 1e-300)) : 0.0;
+    return st;
 }
 
 // Conditioning estimate of the Newton-Schulz route from the norm slots
@@ -668,6 +757,40 @@ hipError_t resid_plain(rtproj_plan p, const double *B, int64_t ldb, int64_t k, h
     return rt::gemm_f64(g, s);
 }
 
+// Final row and null projections from x_hi in plain binary64: Y = A^T x,
+// Z = B - A^T x.  Below RT_MFMA_KMIN right-hand sides one pass over A on the
+// vector units; from there MFMA GEMMs: Z = B - A^T x (copy, then alpha = -1,
+// beta = 1) and Y = B - Z, or Y = A^T x first when Z overwrites B.
+hipError_t final_plain(rtproj_plan p, const double *B, int64_t ldb, int64_t k, double *Z, int64_t ldz, double *Y,
+                       int64_t ldy, hipStream_t s)
+{
+    const int64_t m = p->m, n = p->n;
+    if (k < RT_MFMA_KMIN) {
+        rt::ApplyArgs a{(int)m, (int)n, (int)k, p->A, p->lda};
+        return rt::atx_f64(a, p->d_xhi, p->d_xlo, m, B, ldb, nullptr, 0, Y, ldy, Z, ldz, 0, s);
+    }
+    rt::GemmArgs g{};
+    g.M = (int)n; g.N = (int)k; g.K = (int)m;
+    g.A = p->A; g.a_i = 1; g.a_k = p->lda;
+    g.B = p->d_xhi; g.b_k = 1; g.b_j = m;
+    g.ksplit = 1;
+    hipError_t e;
+    if (Z && !(Y && Z == B)) {
+        // Z = B - A^T x (Z may be B itself), then Y = B - Z (Y may be B)
+        e = Z == B ? hipSuccess : rt::copy_cols_f64(B, ldb, Z, ldz, (int)n, (int)k, nullptr, 0, s);
+        if (e != hipSuccess) return e;
+        g.C = Z; g.c_i = 1; g.c_j = ldz;
+        g.alpha = -1.0; g.beta = 1.0;
+        if ((e = rt::gemm_f64(g, s)) != hipSuccess) return e;
+        return Y ? rt::sub_cols_f64(B, ldb, Z, ldz, Y, ldy, (int)n, (int)k, s) : hipSuccess;
+    }
+    // Y = A^T x, then (Z overwriting B) Z = B - Y
+    g.C = Y; g.c_i = 1; g.c_j = ldy;
+    g.alpha = 1.0; g.beta = 0.0;
+    if ((e = rt::gemm_f64(g, s)) != hipSuccess) return e;
+    return Z ? rt::sub_cols_f64(B, ldb, Y, ldy, Z, ldz, (int)n, (int)k, s) : hipSuccess;
+}
+
 rtproj_status project(rtproj_plan p, const double *B, int64_t ldb, int64_t k, double *Z, int64_t ldz, double *Y,
                       int64_t ldy, double *X, int64_t ldx)
 {
@@ -681,6 +804,7 @@ rtproj_status project(rtproj_plan p, const double *B, int64_t ldb, int64_t k, do
     if (X && !ld_ok(ldx, p->m)) return fail(RTPROJ_ERR_INVALID_ARG, "ldx < m");
     if ((Z == B && ldz != ldb) || (Y == B && ldy != ldb))
         return fail(RTPROJ_ERR_INVALID_ARG, "an output aliases B with a different leading dimension");
+    if (Z && Z == Y) return fail(RTPROJ_ERR_INVALID_ARG, "Z and Y are the same buffer");
     if (!p->ready) return fail(RTPROJ_ERR_STATE, "project called before a successful rtproj_precondition");
     rtproj_status st = ensure_k(p, k);
     if (st != RTPROJ_OK) return st;
@@ -692,6 +816,27 @@ rtproj_status project(rtproj_plan p, const double *B, int64_t ldb, int64_t k, do
         StageScope sc(p, 7);
         RT_HIP(ab_plain(p, B, ldb, k, s));
     }
+    if (p->method_used == RTPROJ_METHOD_CLASSICAL) {
+        // eq. basic_identity directly: x = Pi R^{-1} Q^T c, then A^T x and
+        // b - A^T x in plain binary64
+        {
+            StageScope sc(p, 8);
+            RT_HIP(rt::qr_solve_f64((int)m, p->d_V, p->d_tau, p->d_R, p->d_piv, p->d_c, m, p->d_xhi, m, (int)k, s));
+            RT_HIP(rt::set_matrix_f64(p->d_xlo, m, (int)k, (int)m, 0, s));
+        }
+        if (Z || Y) {
+            StageScope sc(p, 15);
+            RT_HIP(final_plain(p, B, ldb, k, Z, ldz, Y, ldy, s));
+        }
+        if (X) RT_HIP(rt::copy_cols_f64(p->d_xhi, m, X, ldx, (int)m, (int)k, nullptr, 0, s));
+        p->info.refine_steps = p->info.refine_plain = p->info.refine_comp = 0;
+        p->info.resid_mode = RTPROJ_RESID_PLAIN;
+        p->info.refine_last_ratio = p->info.refine_rho_est = p->info.refine_err_est = p->info.refine_rho_model = 0.0;
+        p->info.refine_status = RTPROJ_OK;
+        p->nc_pending = false;
+        p->nc_steps = 0;
+        return RTPROJ_OK;
+    }
     // steps 2-6: x = Pi^T R^{-1} Y R^{-T} Pi c
     {
         StageScope sc(p, 8);
@@ -699,25 +844,27 @@ rtproj_status project(rtproj_plan p, const double *B, int64_t ldb, int64_t k, do
         if (st != RTPROJ_OK) return st;
         RT_HIP(rt::set_matrix_f64(p->d_xlo, m, (int)k, (int)m, 0, s));
     }
+    const RefinePlan rp = refine_schedule(p->info.kappa_est, p->prec_used, p->w32, p->info.gram_cond_est,
+                                          (double)p->n / std::max(1, p->syrk_splits), p->resid_mode,
+                                          p->refine_steps);
+    p->info.refine_rho_model = rp.rho;
+    const int nplain = rp.plain, nsteps = std::min(rp.plain + rp.comp, RT_MAX_STEPS);
     int steps = 0;
     double ratio = 0.0;
-    int nplain = 0, ncomp = p->refine_steps;
-    if (p->refine_steps < 0)
-        auto_refine_plan(p->info.kappa_est, p->precision, p->w32, p->info.gram_cond_est, &nplain, &ncomp);
-    const int nsteps = nplain + ncomp;
     for (int it = 0; it < nsteps; ++it) {
         // plain binary64 residuals while the error is above their floor,
         // compensated (Dot2) ones for the last steps
-        const int dd = it >= nplain ? 1 : 0;
+        const bool comp = it >= nplain;
+        const bool dd_r = comp && rp.comp_r;
         {
-            StageScope sc(p, 9);
-            if (dd) RT_HIP(rt::atx_f64(a, p->d_xhi, p->d_xlo, m, B, ldb, p->d_r, n, nullptr, 0, nullptr, 0, 1, s,
-                                       p->d_xpk));
+            StageScope sc(p, dd_r ? 9 : 13);
+            if (dd_r) RT_HIP(rt::atx_f64(a, p->d_xhi, p->d_xlo, m, B, ldb, p->d_r, n, nullptr, 0, nullptr, 0, 1, s,
+                                         p->d_xpk));
             else RT_HIP(resid_plain(p, B, ldb, k, s));
         }
         {
-            StageScope sc(p, 10);
-            if (dd) {
+            StageScope sc(p, comp ? 10 : 14);
+            if (comp) {
                 RT_HIP(rt::ab_partial_f64(a, p->d_r, n, p->ab_splits, p->d_ph, p->d_pl, 1, s));
                 RT_HIP(rt::ab_reduce_f64(p->d_ph, p->d_pl, (int)m, (int)k, p->ab_splits, 1, p->d_c, m, s));
             } else {
@@ -728,12 +875,12 @@ rtproj_status project(rtproj_plan p, const double *B, int64_t ldb, int64_t k, do
             StageScope sc(p, 8);
             st = apply_minv(p, p->d_c, m, p->d_d, m, k);
             if (st != RTPROJ_OK) return st;
-            RT_HIP(rt::dd_update_f64(p->d_xhi, p->d_xlo, p->d_d, (int)m, (int)k, p->d_norms, s));
+            RT_HIP(rt::dd_update_f64(p->d_xhi, p->d_xlo, p->d_d, (int)m, (int)k, p->d_norms + 2 * it, s));
         }
         ++steps;
         if (p->refine_rtol > 0.0) {
             double nrm[2];
-            RT_HIP(hipMemcpyAsync(nrm, p->d_norms, 16, hipMemcpyDeviceToHost, s));
+            RT_HIP(hipMemcpyAsync(nrm, p->d_norms + 2 * it, 16, hipMemcpyDeviceToHost, s));
             RT_HIP(hipStreamSynchronize(s));
             ratio = nrm[1] > 0 ? std::sqrt(nrm[0] / nrm[1]) : 0.0;
             if (ratio <= p->refine_rtol) break;
@@ -741,13 +888,33 @@ rtproj_status project(rtproj_plan p, const double *B, int64_t ldb, int64_t k, do
     }
     // step 7: b~ = A^T x, z = b - b~
     if (Z || Y) {
-        StageScope sc(p, 11);
-        RT_HIP(rt::atx_f64(a, p->d_xhi, p->d_xlo, m, B, ldb, nullptr, 0, Y, ldy, Z, ldz, steps > 0 ? 1 : 0, s,
-                           p->d_xpk));
+        StageScope sc(p, steps > 0 && rp.comp_final ? 11 : 15);
+        if (steps > 0 && rp.comp_final)
+            RT_HIP(rt::atx_f64(a, p->d_xhi, p->d_xlo, m, B, ldb, nullptr, 0, Y, ldy, Z, ldz, 1, s, p->d_xpk));
+        else RT_HIP(final_plain(p, B, ldb, k, Z, ldz, Y, ldy, s));
     }
     if (X) RT_HIP(rt::copy_cols_f64(p->d_xhi, m, X, ldx, (int)m, (int)k, nullptr, 0, s));
     p->info.refine_steps = steps;
+    p->info.refine_plain = std::min(steps, nplain);
+    p->info.refine_comp = steps - p->info.refine_plain;
+    p->info.resid_mode = p->resid_mode == RTPROJ_RESID_AUTO ? RTPROJ_RESID_FULL : p->resid_mode;
     p->info.refine_last_ratio = ratio;
+    // the convergence check reads the steps' norms at the next wait
+    p->nc_steps = steps;
+    p->nc_plain = std::min(steps, nplain);
+    p->nc_pending = false;
+    p->info.refine_status = RTPROJ_OK;
+    p->info.refine_rho_est = p->info.refine_err_est = 0.0;
+    if (steps > 0) {
+        RT_HIP(hipMemcpyAsync(p->h_norms, p->d_norms, (size_t)steps * 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        p->nc_pending = true;
+    }
+    if (p->refine_rtol > 0.0 && steps > 0) {
+        RT_HIP(hipStreamSynchronize(s));
+        const rtproj_status v = resolve_refine(p);
+        if (v != RTPROJ_OK)
+            return fail(v, "refinement did not converge: estimated error " + std::to_string(p->info.refine_err_est));
+    }
     return RTPROJ_OK;
 }
 
@@ -830,7 +997,33 @@ rtproj_status rtproj_plan_set_precision(rtproj_plan p, int precision)
     if (precision != RTPROJ_PREC_FP64 && precision != RTPROJ_PREC_MIXED_FP32 && precision != RTPROJ_PREC_MIXED_BF16)
         return fail(RTPROJ_ERR_INVALID_ARG, "unknown precision");
     p->precision = precision;
-    p->info.precision = precision;
+    return RTPROJ_OK;
+}
+
+rtproj_status rtproj_plan_set_w_bits(rtproj_plan p, int bits)
+{
+    if (!p) return fail(RTPROJ_ERR_INVALID_ARG, "null plan");
+    if (bits != 0 && bits != 32 && bits != 64) return fail(RTPROJ_ERR_INVALID_ARG, "bits must be 0, 32 or 64");
+    p->w_bits_req = bits;
+    return RTPROJ_OK;
+}
+
+rtproj_status rtproj_plan_set_method(rtproj_plan p, int method)
+{
+    if (!p) return fail(RTPROJ_ERR_INVALID_ARG, "null plan");
+    if (method != RTPROJ_METHOD_RANDOMIZED && method != RTPROJ_METHOD_CLASSICAL)
+        return fail(RTPROJ_ERR_INVALID_ARG, "unknown method");
+    if (method == RTPROJ_METHOD_CLASSICAL && p->m > 4096)
+        return fail(RTPROJ_ERR_UNSUPPORTED, "classical scheme: m above 4096");
+    p->method = method;
+    return RTPROJ_OK;
+}
+
+rtproj_status rtproj_plan_set_residual(rtproj_plan p, int mode)
+{
+    if (!p) return fail(RTPROJ_ERR_INVALID_ARG, "null plan");
+    if (mode < RTPROJ_RESID_AUTO || mode > RTPROJ_RESID_FULL) return fail(RTPROJ_ERR_INVALID_ARG, "unknown residual mode");
+    p->resid_mode = mode;
     return RTPROJ_OK;
 }
 
@@ -899,6 +1092,60 @@ int auto_qr_mode(rtproj_plan p)
     if (p->qr_reg_l > 0) return RTPROJ_QR_DIRECT;
     if (p->qr_reg_m > 0) return RTPROJ_QR_TWO_STAGE;
     return p->qr_blocks > 0 ? RTPROJ_QR_DIRECT : RTPROJ_QR_TWO_STAGE;
+}
+
+// The classical scheme's set-up (the s_pre of Sec. 5): G = A A^T on MFMA
+// (both triangles), then the Householder pivoted QR G Pi = Q R with the
+// reflectors kept in d_V / d_tau.  The rank estimate is |R_11 / R_mm|
+// (about cond(A)^2); only a zero or non-finite pivot is an error.
+rtproj_status precondition_classical(rtproj_plan p, const double *A, int64_t lda)
+{
+    const int64_t m = p->m, n = p->n;
+    hipStream_t s = p->stream;
+    if (!p->d_V) RT_HIP(dalloc(&p->d_V, (size_t)m * m));
+    if (!p->d_tau) RT_HIP(dalloc(&p->d_tau, (size_t)m));
+    {
+        StageScope sc(p, 4);
+        rtproj_status st = gram_f64(p, A, lda, n, p->d_G);
+        if (st != RTPROJ_OK) return st;
+    }
+    double diag[4];
+    unsigned sync[4];
+    {
+        StageScope sc(p, 1);
+        RT_HIP(rt::set_matrix_f64(p->d_R, m, (int)m, (int)m, 0, s));
+        RT_HIP(rt::iota_f64piv(p->d_piv, (int)m, s));
+        rt::QrcpWork w;
+        w.counter = p->d_sync;
+        w.flag = p->d_sync + 1;
+        w.err = reinterpret_cast<int *>(p->d_sync + 2);
+        w.slots = p->d_slots;
+        w.vbuf = p->d_vbuf;
+        w.V = p->d_V;
+        w.tau = p->d_tau;
+        if (p->qr_reg_m <= 0 && p->qr_blocks0 <= 0)
+            return fail(RTPROJ_ERR_UNSUPPORTED, "classical scheme: the m x m QR does not fit the cooperative kernel");
+        RT_HIP(qrcp_any(p, p->d_G, m, (int)m, w, p->qr_reg_m, p->qr_blocks0));
+    }
+    RT_HIP(rt::rdiag_ends_f64(p->d_R, m, (int)m, p->d_diag, s));
+    RT_HIP(hipMemcpyAsync(diag, p->d_diag, 32, hipMemcpyDeviceToHost, s));
+    RT_HIP(hipMemcpyAsync(sync, p->d_sync, 16, hipMemcpyDeviceToHost, s));
+    RT_HIP(hipStreamSynchronize(s));
+    if (sync[2] == 2) return fail(RTPROJ_ERR_RANK, "pivoted QR of A A^T: no finite pivot (A contains NaN or Inf)");
+    if (sync[2] != 0) return fail(RTPROJ_ERR_DEVICE, "pivoted QR: cooperative barrier timed out");
+    p->info.rdiag_min = diag[2];
+    p->info.kappa_est = diag[2] > 0 ? diag[3] / diag[2] : INFINITY;
+    if (!(diag[2] > 0.0) || !std::isfinite(diag[3]))
+        return fail(RTPROJ_ERR_RANK, "pivoted QR of A A^T: zero pivot (rank deficient A)");
+    p->info.qr_mode = RTPROJ_QR_DIRECT;
+    p->info.sketch_bits = p->info.w_bits = 0;
+    p->info.gram_bits = 64;
+    p->info.inverse = 0;
+    p->info.inverse_iters = 0;
+    p->info.inverse_resid = 0.0;
+    p->info.gram_cond_est = 0.0;
+    p->cond_pending = false;
+    return RTPROJ_OK;
 }
 
 // One pass of the preconditioner; sketch64 forces the binary64 sketch.
@@ -974,6 +1221,16 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
     if (sync[2] != 0) return fail(RTPROJ_ERR_DEVICE, "pivoted QR: cooperative barrier timed out");
     p->info.rdiag_min = diag[2];
     p->info.kappa_est = diag[2] > 0 ? diag[3] / diag[2] : INFINITY;
+    const bool lp = p->precision != RTPROJ_PREC_FP64;
+    // a binary32 sketch whose rank estimate shows it too coarse for this A
+    // (2^-24 kappa_est above RT_SKETCH32_MAX, or numerically rank deficient)
+    // is redone in binary64 before anything is built on it
+    if (lp && !sketch64 &&
+        (!(std::ldexp(p->info.kappa_est, -24) <= RT_SKETCH32_MAX) ||
+         !(diag[2] > (double)m * std::ldexp(1.0, -52) * diag[3]))) {
+        p->resketch = true;
+        return RTPROJ_OK;
+    }
     if (!(diag[2] > (double)m * std::ldexp(1.0, -52) * diag[3]))
         return fail(RTPROJ_ERR_RANK, "pivoted QR of the sketch: |R_mm| <= m eps |R_11| (rank deficient A)");
     // 3. R^{-T} (lower): inverted 64 x 64 diagonal blocks, then recursive
@@ -993,9 +1250,9 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
             off += 2 * (size_t)cnt;
         }
     }
-    // 4. W = R^{-T} (Pi A), binary32 when the rank estimate allows it
-    const bool lp = p->precision != RTPROJ_PREC_FP64;
-    p->w32 = lp && p->info.kappa_est <= RT_W32_KAPPA_MAX;
+    // 4. W = R^{-T} (Pi A), binary32 when the rank estimate allows it (or
+    //    when forced by rtproj_plan_set_w_bits)
+    p->w32 = lp && (p->w_bits_req == 32 || (p->w_bits_req == 0 && p->info.kappa_est <= RT_W32_KAPPA_MAX));
     {
         StageScope sc(p, 3);
         if (p->w32) {
@@ -1116,13 +1373,28 @@ rtproj_status rtproj_precondition(rtproj_plan p, const double *A, int64_t lda)
     p->A = A;
     p->lda = lda;
     p->info.sketch_escalated = 0;
+    p->resketch = false;
+    p->prec_used = p->precision;
+    p->info.precision = p->precision;
+    p->method_used = p->method;
+    p->info.method = p->method;
+    if (p->method == RTPROJ_METHOD_CLASSICAL) {
+        p->prec_used = p->info.precision = RTPROJ_PREC_FP64;
+        const rtproj_status sc = precondition_classical(p, A, lda);
+        if (sc != RTPROJ_OK) return sc;
+        p->ready = true;
+        return RTPROJ_OK;
+    }
     rtproj_status st = precondition_impl(p, A, lda, false);
     // A binary32 sketch perturbs G by about 2^-24 kappa(A) relative to the
-    // small singular directions; when that shows as a poorly conditioned
-    // P^{-1}A, sketch again in binary64 (the identity holds for any G, only
-    // the conditioning matters, Lemma 2.4).
-    if (st == RTPROJ_OK && p->precision != RTPROJ_PREC_FP64 && p->info.gram_cond_est > RT_COND_ESCALATE) {
-        p->info.sketch_escalated = 1;
+    // small singular directions; when the rank estimate shows that (right
+    // after the pivoted QR), or the Gram shows a poorly conditioned P^{-1}A,
+    // sketch again in binary64 (the identity holds for any G, only the
+    // conditioning matters, Lemma 2.4).
+    if (st == RTPROJ_OK && p->precision != RTPROJ_PREC_FP64 &&
+        (p->resketch || p->info.gram_cond_est > RT_COND_ESCALATE)) {
+        p->info.sketch_escalated = p->resketch ? 1 : 2;
+        p->resketch = false;
         st = precondition_impl(p, A, lda, true);
     }
     if (st != RTPROJ_OK) return st;
@@ -1171,8 +1443,21 @@ rtproj_status rtproj_plan_info(rtproj_plan p, rtproj_info *out)
     if (!p || !out) return fail(RTPROJ_ERR_INVALID_ARG, "null argument");
     RT_HIP(hipStreamSynchronize(p->stream));
     resolve_cond(p);
+    resolve_refine(p);
     collect_timing(p);
     *out = p->info;
+    return RTPROJ_OK;
+}
+
+rtproj_status rtproj_plan_status(rtproj_plan p)
+{
+    if (!p) return fail(RTPROJ_ERR_INVALID_ARG, "null plan");
+    RT_HIP(hipStreamSynchronize(p->stream));
+    const rtproj_status st = resolve_refine(p);
+    if (st != RTPROJ_OK)
+        return fail(st, "refinement did not converge: estimated relative error of x " +
+                            std::to_string(p->info.refine_err_est) + ", contraction " +
+                            std::to_string(p->info.refine_rho_est));
     return RTPROJ_OK;
 }
 

@@ -62,6 +62,31 @@ constexpr int64_t RT_NS_FUSED_MAX_M = 256;
 // Largest block of right-hand sides whose M^{-1} products run as one launch
 // each (skinny product kernel) instead of a split GEMM and its reduction.
 constexpr int64_t RT_SKINNY_KMAX = 64;
+// Refinement planner.  Accuracy goal of the automatic schedule: a tenth of
+// the 1e-10 relative error the projections are specified to (room for the
+// model's constants).  The rank estimate |R_11 / R_mm| of the pivoted QR
+// understates cond(A) (by 18 to 40 times in the measured workloads); the
+// planner's constants below absorb that factor.
+constexpr double RT_REFINE_GOAL = 1e-11;
+// Relative error of x at which a refinement with a plain binary64 residual
+// stalls: about RT_FLOOR_C u kappa_est (measured 7e-9 at cond(A) = 1e8,
+// kappa_est = 4.7e6: RT_FLOOR_C u kappa_est = 8.3e-9).
+constexpr double RT_FLOOR_C = 16.0;
+// A binary32 sketch is redone in binary64 before anything else is built on
+// it when 2^-24 kappa_est exceeds this (the sketch's rounding then reaches
+// the small singular directions: healthy at 0.15, degraded at 6, measured).
+constexpr double RT_SKETCH32_MAX = 1.0;
+// Refinement steps recorded per projection for the convergence check.
+constexpr int RT_MAX_STEPS = 80;
+// Convergence check of a projection's refinement (Remarks 4.2 and 4.3): the
+// iteration did not converge when a step's correction did not shrink to at
+// most this fraction of the previous one while corrections are still above
+// RT_NC_ACTIVE |x|, or when the error estimated after the last step
+// (contraction estimate times the last relative correction) is above
+// RT_NC_TOL.
+constexpr double RT_NC_RATIO = 0.5;
+constexpr double RT_NC_ACTIVE = 1e-11;
+constexpr double RT_NC_TOL = 1e-10;
 
 // ------------------------------------------------------------ random tables
 // SplitMix64 (Steele, Lea and Flood, 2014): the state advances by the golden
@@ -145,6 +170,19 @@ struct rtproj_plan_s {
     int precision = RTPROJ_PREC_FP64;
     int refine_steps = -1;  // -1: chosen from the rank estimate of the pivoted QR
     double refine_rtol = 0.0;
+    int resid_mode = RTPROJ_RESID_AUTO;  // rtproj_residual requested
+    int w_bits_req = 0;        // 0: P^{-1}A precision from the rank estimate; 32 or 64 forced
+    int prec_used = RTPROJ_PREC_FP64;    // precision of the last precondition
+    // convergence check of the last projection: per-step |d|^2, |x|^2 copied
+    // to pinned memory; evaluated at the next call that waits on the stream
+    double *h_norms = nullptr;  // pinned, 2 RT_MAX_STEPS
+    int nc_steps = 0;           // steps recorded (0: nothing pending)
+    int nc_plain = 0;           // of which plain (the first ones)
+    bool nc_pending = false;
+    bool resketch = false;      // the binary32 sketch must be redone in binary64
+    int method = RTPROJ_METHOD_RANDOMIZED;  // requested (rtproj_method)
+    int method_used = RTPROJ_METHOD_RANDOMIZED;  // of the last precondition
+    double *d_V = nullptr, *d_tau = nullptr;  // classical scheme: reflectors of the QR of A A^T
     rtp::HostTables tab;
     // device tables
     int8_t *d_sign = nullptr;
@@ -217,12 +255,42 @@ struct rtproj_plan_s {
 
 namespace rtp {
 
+// Projection workspace for k right-hand sides: the split counts of the A B
+// passes and the element count (doubles) of each buffer, in the order c,
+// tmp, xhi, xlo, d, r, ph, pl, bpk, norms, xpk.
+struct ProjLayout {
+    static constexpr int NBUF = 11;
+    int ab_splits = 1, ab_sx_splits = 1;
+    int64_t count[NBUF] = {};
+    size_t bytes() const;  // every buffer rounded up to 256 bytes
+};
+ProjLayout proj_layout(int64_t m, int64_t n, int64_t k, int cu_count);
+// The plan's pointer to projection buffer i (order of ProjLayout::count).
+double **proj_buffers(rtproj_plan p, int i);
 // Grows the projection workspace of p to k right-hand sides.
 rtproj_status ensure_k(rtproj_plan p, int64_t k);
-// Refinement steps chosen from the rank estimate (see rtproj_plan_set_refinement):
-// *plain steps with binary64 residuals, then *comp compensated ones.
-void auto_refine_plan(double kappa_est, int precision, bool w32, double cond_w, int *plain, int *comp);
-int auto_refine_steps(double kappa_est, int precision, bool w32, double cond_w);
+// Projection of k right-hand sides through the plan's current workspace
+// pointers (the body of rtproj_project_all).
+rtproj_status project(rtproj_plan p, const double *B, int64_t ldb, int64_t k, double *Z, int64_t ldz, double *Y,
+                      int64_t ldy, double *X, int64_t ldx);
+// A refinement schedule (see rtproj_plan_set_refinement): `plain` steps with
+// binary64 residuals, then `comp` steps whose contraction s = A r (and, with
+// comp_r, the residual r = b - A^T x) is compensated; the final A^T x is
+// compensated when comp_final.  rho is the modelled contraction per step.
+struct RefinePlan {
+    int plain = 0, comp = 0;
+    bool comp_r = true, comp_final = true;
+    double rho = 0.5;
+};
+// Modelled contraction per refinement step (gram_k: terms per split-K
+// partial sum of a reduced-precision Gram), and the schedule built on it.
+double refine_rho_model(double kappa_est, int precision, bool w32, double cond_w, double gram_k);
+RefinePlan refine_schedule(double kappa_est, int precision, bool w32, double cond_w, double gram_k, int mode,
+                           int max_steps);
+// Status of a finished refinement from its per-step norms (|d_j|^2, |x_j|^2
+// pairs, `steps` of them, the first `plain` from plain steps): RTPROJ_OK or
+// RTPROJ_ERR_NOCONV, with the contraction and error estimates.
+rtproj_status refine_verdict(const double *norms, int steps, int plain, double *rho_est, double *err_est);
 // First output of SplitMix64 seeded with seed XOR i: the sketch seed of
 // member i of a batch.
 uint64_t instance_seed(uint64_t seed, int64_t i);

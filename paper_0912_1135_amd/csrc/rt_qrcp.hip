@@ -185,7 +185,13 @@ __global__ __launch_bounds__(QR_THREADS) void qrcp_kernel(const double *S, int64
             tau = (beta - alpha) / beta;
             inv = 1.0 / (alpha - beta);
         }
-        for (int i = k + tid; i < rows; i += QR_THREADS) v[i] = (i == k) ? 1.0 : xp[i] * inv;
+        const bool keep_v = w.V && p % G == g;
+        for (int i = k + tid; i < rows; i += QR_THREADS) {
+            const double vi = (i == k) ? 1.0 : xp[i] * inv;
+            v[i] = vi;
+            if (keep_v) w.V[(int64_t)k * rows + i] = vi;
+        }
+        if (keep_v && tid == 0) w.tau[k] = tau;
         // 4. owner: column k of R and piv[k]
         if (p % G == g) {
             const int c = p / G;
@@ -524,6 +530,14 @@ __global__ __launch_bounds__(TT) void qrcp_reg_kernel(const double *S, int64_t l
             if (tid == 0) {
                 R[(int64_t)k * cols + k] = beta;
                 piv[k] = p;
+            }
+            if (w.V) {
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) {
+                    const int i = tid + TT * r;
+                    if (i >= k && i < rows) w.V[(int64_t)k * rows + i] = v[r];
+                }
+                if (tid == 0) w.tau[k] = tau;
             }
             done |= 1u << c;
         }

@@ -17,6 +17,8 @@ benchmark.
   against 110 s on 8 cores).
 * Right-hand sides: i.i.d. N(0, 1), stored as a (k, n) C-contiguous array,
   i.e. column-major n x k (column c is row c of the array).
+* Complex problems: the same construction with unitary factors and complex
+  Gaussian right-hand sides (streams 6, 7, 8).
 * Batched workload: instance sizes m_i ~ U{32..512}, n_i = m_i * U{16..64},
   l_i = 4 m_i, k_i ~ U{1..64}.
 * Interior-point-shaped sequence: diagonal scalings D_t with entries
@@ -70,6 +72,29 @@ def make_problem(m: int, n: int, kappa: float, seed: int, with_factors: bool = F
     if with_factors:
         return A, U, s, V
     return A
+
+
+def make_complex_problem(m: int, n: int, kappa: float, seed: int) -> np.ndarray:
+    """Complex A = U diag(sigma) V^* (m x n, row-major complex128): U and V
+    with orthonormal columns from the QR of complex Gaussian matrices (the
+    unitary analogue of Mezzadri's construction, columns multiplied by the
+    phases of R's diagonal), sigma log-spaced 1 -> 1/kappa."""
+    def unitary(rows, cols, rng):
+        g = rng.standard_normal((rows, cols)) + 1j * rng.standard_normal((rows, cols))
+        q, r = np.linalg.qr(g)
+        d = np.diag(r)
+        ph = np.where(np.abs(d) > 0, d / np.abs(d), 1.0)
+        return q * ph[None, :]
+    U = unitary(m, m, rng_for(seed, 6))
+    V = unitary(n, m, rng_for(seed, 7))
+    s = log_spaced(m, kappa)
+    return np.ascontiguousarray((U * s[None, :]) @ V.conj().T)
+
+
+def make_complex_rhs(n: int, k: int, seed: int) -> np.ndarray:
+    """k complex Gaussian right-hand sides as a (k, n) complex128 array."""
+    g = rng_for(seed, 8).standard_normal((2, k, n))
+    return np.ascontiguousarray(g[0] + 1j * g[1])
 
 
 def make_rhs(n: int, k: int, seed: int) -> np.ndarray:

@@ -131,3 +131,20 @@ def test_batch_column_scaled_members_match_oracle(rt):
             e = check_member(A * D[t][None, :], Bs[t], Z[t].cpu().numpy(), Y[t].cpu().numpy(), X[t].cpu().numpy())
             assert max(e) <= TOL, (rep, t, e)
     bt.close()
+
+
+def test_batch_member_tables_match_oracle(rt):
+    """Member i's sketch tables are the oracle's tables for the instance seed
+    of i (the first SplitMix64 output of seed XOR i), bit for bit."""
+    seed = 20091214
+    ms, ns = [8, 40, 17], [100, 2000, 544]
+    ls = [4 * m for m in ms]
+    bt = rt.Batch(ms, ns, ls, seed)
+    for i in range(3):
+        got = bt.member_tables(i)
+        ref = oracle.srft_tables(oracle.instance_seed(seed, i), ns[i], ls[i])
+        for key in ["np", "n1", "n2"]:
+            assert got[key] == ref[key]
+        for key in ["sign", "sigma", "tau", "J"]:
+            assert np.array_equal(got[key], ref[key]), (i, key)
+    bt.close()

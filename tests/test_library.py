@@ -68,3 +68,17 @@ def test_batch_rejects_bad_sizes_before_device_work():
     assert L.rtproj_batch_create(1, i64([4]), i64([3]), i64([4]), 1, ctypes.byref(h)) == 1            # n < m
     assert L.rtproj_batch_create(1, i64([4096]), i64([9000]), i64([8192]), 1, ctypes.byref(h)) == 7  # m too large
     assert not h.value
+
+
+def test_binding_checks_tensors_before_any_library_call():
+    """Host tensors (or wrong dtypes) are rejected by the binding itself."""
+    import paper_0912_1135_amd as rt
+    torch = pytest.importorskip("torch")
+    plan = object.__new__(rt.Plan)
+    plan.handle, plan.m, plan.n, plan.l = None, 4, 10, 8
+    B = torch.zeros((2, 10), dtype=torch.float64)
+    for call in (plan.project_null, plan.project_row, plan.lstsq, plan.project_all):
+        with pytest.raises(TypeError):
+            call(B)
+    with pytest.raises(TypeError):
+        plan.precondition(torch.zeros((4, 10), dtype=torch.float32))

@@ -55,7 +55,8 @@ def build_mutant(tmp_path, old, new):
     c = tmp_path / "mut.c"
     c.write_text(mutated)
     so = tmp_path / "libmut.so"
-    subprocess.run(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", str(c), "-o", str(so), "-lm"],
+    subprocess.run(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", str(c), "-o", str(so), "-lquadmath",
+                    "-lm"],
                    check=True)
     return oracle.bind(str(so))
 
