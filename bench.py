@@ -252,6 +252,7 @@ def run_single(args, rt, synth, np, torch):
         plan.set_refinement(args.refine_steps, 0.0)
         plan.set_qr(args.qr)
         plan.set_inverse(args.inverse)
+        plan.set_autotune(not args.no_autotune)  # new shapes are tuned in the warm-up steps
         Z, Y = torch.empty_like(Bt), torch.empty_like(Bt)
         X = torch.empty((k, m), dtype=torch.float64, device=dev)
         steps = args.steps if prec == main_prec else min(args.steps, args.form_steps)
@@ -279,6 +280,7 @@ def run_single(args, rt, synth, np, torch):
         del Z, Y, X
     ms_per_step, info, stages, steps = main
     value = k / (ms_per_step / 1e3)
+    paper = None if args.no_forms else paper_columns(rt, torch, np, At, Bt, m, n, l, k, seed, kappa, main_prec)
     bits = {"fp64": "f64", "mixed_fp32": "f64+f32", "mixed_bf16": "f64+bf16"}[main_prec]
     result = {
         "metric": METRIC, "value": value, "unit": "projections/s", "n_gpus": 1, "steps": steps,
@@ -297,6 +299,13 @@ def run_single(args, rt, synth, np, torch):
     }
     if main_prec != "fp64" and "fp64" in forms:
         result["mixed_vs_fp64"] = forms[main_prec]["value"] / forms["fp64"]["value"]
+    if paper is not None:
+        result["paper_columns"] = paper
+    if not args.no_autotune:
+        import tempfile
+        with tempfile.TemporaryDirectory() as td:
+            rt.autotune_save(os.path.join(td, "tune.txt"))
+            result["autotune"] = [ln.split() for ln in open(os.path.join(td, "tune.txt")) if ln.strip()]
     # parity of every form against the oracle on the sampled right-hand sides
     # (refined and unrefined results); the oracle's time on that sample is the
     # CPU baseline.  Above 512 x 65536 the oracle takes R from LAPACK's
@@ -337,6 +346,162 @@ def run_single(args, rt, synth, np, torch):
                         for p in forms}
     result["input_generation_s"] = gen_s
     return result
+
+
+def paper_columns(rt, torch, np, At, Bt, m, n, l, k, seed, kappa, main_prec):
+    """The columns of the paper's tables (Sec. 5) on this workload: s_pre and
+    s_pro of the classical scheme (A A^T, its pivoted QR, then eq.
+    basic_identity per right-hand side), t_pre and t_pro of the randomized
+    method, and delta = max |A z|, epsilon = max |Z z - z| over 8 random unit
+    vectors b, divided by cond(A) as the tables report them."""
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps
+    Bu = Bt[:8] / torch.linalg.vector_norm(Bt[:8], dim=1, keepdim=True)
+    out = {}
+    for name, method, prec, steps in [("classical", rt.METHOD_CLASSICAL, "fp64", -1),
+                                      ("randomized_unrefined", rt.METHOD_RANDOMIZED, "fp64", 0),
+                                      ("randomized", rt.METHOD_RANDOMIZED, main_prec, -1),
+                                      ("randomized_krylov", rt.METHOD_KRYLOV, "fp64", -1)]:
+        plan = rt.Plan(m, n, l, seed)
+        plan.set_method(method)
+        plan.set_precision(PRECISIONS[prec])
+        plan.set_refinement(steps, 0.0)
+        t_pre = timed(lambda: plan.precondition(At))
+        Z = torch.empty_like(Bt)
+        t_pro = timed(lambda: plan.project_null(Bt, out=Z)) / k
+        Zu = plan.project_null(Bu)
+        ZZ = plan.project_null(Zu)
+        torch.cuda.synchronize()
+        delta = torch.linalg.vector_norm(Zu @ At.T, dim=1).max().item()
+        eps = torch.linalg.vector_norm(ZZ - Zu, dim=1).max().item()
+        out[name] = {"pre_s": t_pre, "pro_s": t_pro, "delta_over_kappa": delta / kappa,
+                     "epsilon_over_kappa": eps / kappa, "precision": prec}
+        log(f"{name}: pre {t_pre * 1e3:.2f} ms, pro {t_pro * 1e6:.1f} us per rhs, "
+            f"delta/kappa {delta / kappa:.2e}, epsilon/kappa {eps / kappa:.2e}")
+        plan.close()
+    return out
+
+
+def run_paper(args, rt, synth, np, torch):
+    """The paper's Table 1 / Table 2 workload (Sec. 5, eq. test_mat): A =
+    U [B ... B] V with m = 400, n = 1e6, l = 404, cond(A) = 1e8, G drawn as
+    lagged-Fibonacci uniform [-1, 1] (passed in), k = 8 random unit vectors.
+    Both schemes' columns: s_pre, s_pro (classical), t_pre, t_pro
+    (randomized), delta / kappa and epsilon / kappa; z and A^T x against the
+    exact block-average projection for every right-hand side."""
+    from oracle.paper_forms import block_average_projection
+    c = synth.CONFIGS[args.workload]
+    m, n, l, k, kappa, seed = c["m"], c["n"], c["l"], c["k"], c["kappa"], c["seed"]
+    log(f"generating {args.workload}")
+    t0 = time.time()
+    A, rp, cp = synth.make_paper_matrix(m, n, kappa, seed)
+    G = synth.make_lfg_sketch(n, l, seed)
+    B = synth.make_rhs(n, k, seed)
+    B /= np.linalg.norm(B, axis=1, keepdims=True)
+    gen_s = time.time() - t0
+    log(f"inputs ready in {gen_s:.1f} s")
+    dev = torch.device("cuda", 0)
+    At, Gt, Bt = (torch.from_numpy(x).to(dev) for x in (A, G, B))
+    Zc, Pc = block_average_projection(m, cp, B.T)
+    nb = np.linalg.norm(B, axis=1)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps
+    rows = {}
+    for name, method, sketch in [("classical", rt.METHOD_CLASSICAL, None), ("randomized_lfg", rt.METHOD_RANDOMIZED, Gt),
+                                 ("randomized_srft", rt.METHOD_RANDOMIZED, None)]:
+        plan = rt.Plan(m, n, l, seed)
+        plan.set_method(method)
+        if sketch is not None:
+            plan.set_sketch_matrix(sketch)
+        pre = timed(lambda: plan.precondition(At), args.steps)
+        Z = torch.empty_like(Bt)
+        pro = timed(lambda: plan.project_null(Bt, out=Z), args.steps) / k
+        ZZ = plan.project_null(Z)
+        torch.cuda.synchronize()
+        delta = torch.linalg.vector_norm(Z @ At.T, dim=1).max().item()
+        eps = torch.linalg.vector_norm(ZZ - Z, dim=1).max().item()
+        ez = float(np.max(np.linalg.norm(Z.cpu().numpy() - Zc.T, axis=1) / nb))
+        rows[name] = {"pre_s": pre, "pro_s": pro, "delta_over_kappa": delta / kappa, "epsilon_over_kappa": eps / kappa,
+                      "e_z_vs_closed_form": ez, "kappa_est": plan.info()["kappa_est"]}
+        log(f"{name}: pre {pre * 1e3:.2f} ms, pro {pro * 1e6:.1f} us per vector, delta/kappa {delta / kappa:.2e}, "
+            f"epsilon/kappa {eps / kappa:.2e}, e_z {ez:.2e}")
+        plan.close()
+    r = rows["randomized_lfg"]
+    ms = (r["pre_s"] + k * r["pro_s"]) * 1e3
+    value = k / (ms / 1e3)
+    return {
+        "metric": METRIC, "value": value, "unit": "projections/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 1, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: A = U [B ... B] V (eq. test_mat), m={m}, n={n}, l={l}, "
+                               f"cond {kappa:g}, lagged-Fibonacci G, {k} random unit vectors",
+                   "m": m, "n": n, "l": l, "k": k, "kappa": kappa, "parallelism": "single GPU"},
+        "paper_columns": rows,
+        "parity": {"e_z_vs_closed_form": r["e_z_vs_closed_form"], "pass": r["e_z_vs_closed_form"] <= TOL},
+        "cpu_baseline": None,
+        "input_generation_s": gen_s,
+    }
+
+
+def run_complex(args, rt, synth, np, torch):
+    """Complex A (the paper's extension to complex entries, Sec. 1): a
+    complex m x n A = U diag(sigma) V^* projected through the real embedding
+    (rtproj_cplan_*), against the complex oracle on two right-hand sides."""
+    from oracle import complex_oracle
+    c = synth.CONFIGS[args.workload]
+    m, n, l, k, kappa, seed = c["m"], c["n"], c["l"], c["k"], c["kappa"], c["seed"]
+    log(f"generating {args.workload}")
+    A = synth.make_complex_problem(m, n, kappa, seed)
+    B = synth.make_complex_rhs(n, k, seed)
+    dev = torch.device("cuda", 0)
+    At, Bt = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+    plan = rt.CPlan(m, n, l, seed)
+    Z, Y, X = torch.empty_like(Bt), torch.empty_like(Bt), torch.empty((k, m), dtype=Bt.dtype, device=dev)
+    for _ in range(args.warmup):
+        plan.precondition(At)
+        plan.project_all(Bt, Z, Y, X)
+    torch.cuda.synchronize()
+    plan.real.set_timing(True)
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.precondition(At)
+        plan.project_all(Bt, Z, Y, X)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t1) * 1e3 / args.steps
+    info = plan.real.info()
+    plan.real.status()
+    stages = stage_table(info, args.steps, [(2 * m, 2 * n, 2 * l, k)], "fp64", 64)
+    t3 = time.perf_counter()
+    Zr, Yr, Xr, _ = complex_oracle.project_complex(A, B[:2].T)
+    t4 = time.perf_counter()
+    ez, ep, ex = rel_errors(B[:2], Z[:2].cpu().numpy(), Y[:2].cpu().numpy(), X[:2].cpu().numpy(), Zr.T, Yr.T, Xr.T)
+    plan.close()
+    return {
+        "metric": METRIC, "value": k / (ms / 1e3), "unit": "projections/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c128 (as f64 real embedding)", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: complex A = U diag(sigma) V^*, m={m}, n={n}, l={l}, "
+                               f"sigma 1..1/{kappa:g}, k={k}; real 2m x 2n embedding", "m": m, "n": n, "l": l,
+                   "k": k, "kappa": kappa, "parallelism": "single GPU"},
+        "roofline": roofline(stages, args.workload), "stages": stages,
+        "parity": {"e_z": ez, "e_p": ep, "e_x": ex, "columns_checked": 2, "pass": max(ez, ep, ex) <= TOL},
+        "cpu_baseline": {"value": 2 / (t4 - t3), "unit": "projections/s", "cores": len(os.sched_getaffinity(0)),
+                         "kind": "oracle", "cpu_model": cpu_model(),
+                         "sample": f"complex oracle on 2 of the {k} right-hand sides ({t4 - t3:.1f} s)"},
+    }
 
 
 def run_batch(args, rt, synth, np, torch):
@@ -391,6 +556,20 @@ def run_batch(args, rt, synth, np, torch):
     status = bt.status()
     ms_per_step = (t2 - t1) * 1e3 / args.steps
     log(f"batch (graph): {ms_per_step:.3f} ms per step")
+    # the same batch with the binary32 grouped Gram
+    bt.set_precision(1)
+    for _ in range(args.warmup):
+        bt.precondition(At)
+        bt.project_all(Bt, Z, Y, X)
+    torch.cuda.synchronize()
+    t1b = time.perf_counter()
+    for _ in range(args.steps):
+        bt.precondition(At)
+        bt.project_all(Bt, Z, Y, X)
+    torch.cuda.synchronize()
+    ms32 = (time.perf_counter() - t1b) * 1e3 / args.steps
+    status32 = bt.status()
+    log(f"batch (graph, binary32 Gram): {ms32:.3f} ms per step")
     value = ksum / (ms_per_step / 1e3)
     # baseline on the same GPU: one binary64 plan per member, one after another
     plans = [rt.Plan(m, n, l, 0) for m, n, l in zip(shp.m, shp.n, shp.l)]
@@ -421,6 +600,8 @@ def run_batch(args, rt, synth, np, torch):
         "roofline": roofline(stages, args.workload),
         "stages": stages,
         "forms": {"batch_graph": {"value": value, "ms_per_step": ms_per_step},
+                  "batch_graph_fp32_gram": {"value": ksum / (ms32 / 1e3), "ms_per_step": ms32,
+                                            "member_status_nonzero": [i for i, s in enumerate(status32) if s != 0]},
                   "loop_of_plans": {"value": loop_value, "ms_per_step": (t4 - t3) * 1e3}},
         "member_status_nonzero": [i for i, s in enumerate(status) if s != 0],
     }
@@ -442,7 +623,7 @@ def run_batch(args, rt, synth, np, torch):
             worst = [max(a, b) for a, b in zip(worst, e)]
         t6 = time.perf_counter()
         result["parity"] = {"members_checked": pick, "e_z": worst[0], "e_p": worst[1], "e_x": worst[2],
-                            "tol": TOL, "pass": max(worst) <= TOL}
+                            "tol": TOL, "pass": max(worst) <= TOL, "form": "batch_graph_fp32_gram (last run)"}
         if not args.no_cpu_baseline:
             cpu_sample = {"value": kdone / (t6 - t5), "unit": "projections/s", "cores": threads, "kind": "oracle",
                           "sample": f"members {pick} of the same batch (all their right-hand sides, "
@@ -569,7 +750,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="mixed_2048x262144",
                     choices=["plain_512x65536", "plain_64x4096", "mixed_2048x262144", "batch_256",
-                             "ipm_1024x131072"])
+                             "ipm_1024x131072", "paper_400x1000000", "complex_512x32768"])
     ap.add_argument("--precision", default=None, choices=list(PRECISIONS),
                     help="form of the main line (default: fp64, or mixed_fp32 for the mixed workload)")
     ap.add_argument("--no-forms", action="store_true", help="time only the main precision")
@@ -578,6 +759,7 @@ def main():
     ap.add_argument("--qr", type=int, default=0, help="pivoted-QR method: 0 auto, 1 direct, 2 two-stage, "
                                                       "3 two-stage with a single-workgroup second stage")
     ap.add_argument("--inverse", type=int, default=0, help="Gram inverse: 0 auto, 1 Newton-Schulz, 2 Cholesky")
+    ap.add_argument("--no-autotune", action="store_true", help="built-in GEMM configurations only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -598,6 +780,10 @@ def main():
 
     if args.workload == "batch_256":
         result = run_batch(args, rt, synth, np, torch)
+    elif args.workload.startswith("paper_"):
+        result = run_paper(args, rt, synth, np, torch)
+    elif args.workload.startswith("complex_"):
+        result = run_complex(args, rt, synth, np, torch)
     elif args.workload == "ipm_1024x131072":
         result = run_ipm(args, rt, synth, np, torch)
     else:

@@ -130,11 +130,22 @@ typedef enum {
     RTPROJ_METHOD_RANDOMIZED = 0, /* the preconditioned identity (eq. basic_precond)
                                      with P from the randomized sketch, and the
                                      refinement of Remark 4.3 (the default)          */
-    RTPROJ_METHOD_CLASSICAL = 1   /* eq. basic_identity evaluated directly: A A^*
+    RTPROJ_METHOD_CLASSICAL = 1,  /* eq. basic_identity evaluated directly: A A^*
                                      (binary64 MFMA), its Householder pivoted QR,
                                      x = Pi R^{-1} Q^T (A b), no refinement; the
                                      comparison scheme of Sec. 5 (s_pre, s_pro,
                                      delta_norm, epsilon_norm); m <= 4096          */
+    RTPROJ_METHOD_KRYLOV = 2      /* the iterative variant (Sec. 1: a
+                                     preconditioned iterative approach is also
+                                     feasible): the sketch, its pivoted QR and
+                                     R^{-T} only (no P^{-1}A, Gram or inverse);
+                                     every solve with A A^* = P (W W^*) P^* runs
+                                     conjugate gradients on the well-conditioned
+                                     W W^*, W = P^{-1}A, applying W and W^* as
+                                     R^{-T} Pi A and A^* Pi^T R^{-1} (two passes
+                                     over A per iteration; the iteration count is
+                                     set by rtproj_plan_set_krylov), inside the
+                                     refinement of Remark 4.3                      */
 } rtproj_method;
 
 typedef struct {
@@ -229,6 +240,42 @@ rtproj_status rtproj_plan_set_w_bits(rtproj_plan plan, int bits);
  * compute x = Pi R^{-1} Q^T A b and A^* x, b - A^* x in plain binary64, and
  * the refinement and residual settings do not apply. */
 rtproj_status rtproj_plan_set_method(rtproj_plan plan, int method);
+
+/* Sketch with the caller's dense n x l matrix G (device, row-major, element
+ * (t, j) at G[t*ldg + j], ldg >= l) in place of the subsampled randomized
+ * Fourier transform: S = A G (eq. testing) in binary64 on MFMA, as the
+ * paper's experiments draw G (i.i.d. Gaussian, or lagged Fibonacci uniform
+ * on [-1, 1]; Sec. 5).  G is borrowed from the next rtproj_precondition
+ * until G is replaced or cleared (G = NULL restores the SRFT).  The
+ * projections do not depend on G (eq. basic_precond is an identity); only
+ * the conditioning of P^{-1}A does (Lemma 2.4).  Costs 2 m n l flops per
+ * precondition. */
+rtproj_status rtproj_plan_set_sketch_matrix(rtproj_plan plan, const double *G, int64_t ldg);
+
+/* Conjugate-gradient iterations per solve of the iterative method
+ * (RTPROJ_METHOD_KRYLOV); default 30, which takes the error of a solve to
+ * about 2 (0.6)^30 = 4e-7 when cond(P^{-1}A) <= 4 (Observation 3.2 with
+ * l = 4m); 1 to 500, else RTPROJ_ERR_INVALID_ARG.  Takes effect at the next
+ * projection. */
+rtproj_status rtproj_plan_set_krylov(rtproj_plan plan, int iters);
+
+/* Autotuning of the preconditioner's large contractions (1 on, 0 off, the
+ * default).  When on, the first rtproj_precondition of a shape times every
+ * candidate configuration of the product P^{-1}A (64 or 128 square tiles,
+ * plain or XCD-grouped tile order) and of its Gram (split-K counts, tile
+ * size) on the plan's stream with the real operands, keeps the fastest in a
+ * process-wide table keyed by operation, number type and sizes, and uses it
+ * for every later preconditioning of that shape (on any plan with autotuning
+ * on).  The tuning precondition takes the candidates' extra time and waits
+ * on the stream once per candidate. */
+rtproj_status rtproj_plan_set_autotune(rtproj_plan plan, int enable);
+/* Save or load the autotuner's table (text, one entry per line: key and
+ * integers).  Loading adds to (and overrides entries of) the table in
+ * memory; RTPROJ_ERR_INVALID_ARG for an unreadable file or a malformed line. */
+rtproj_status rtproj_autotune_save(const char *path);
+rtproj_status rtproj_autotune_load(const char *path);
+/* Entries in the autotuner's table. */
+int rtproj_autotune_entries(void);
 
 /* Arithmetic of the refinement residuals (rtproj_residual); default
  * RTPROJ_RESID_AUTO.  Takes effect at the next projection. */
@@ -353,8 +400,9 @@ rtproj_status rtproj_sketch_tables(rtproj_plan plan, int64_t *dims3, int8_t *sig
  * R0 in one workgroup per member), so no step waits on the host: rank tests
  * and factorization breakdowns are reported afterwards by
  * rtproj_batch_status.  Member i's sketch seed is the first output of
- * SplitMix64 seeded with seed XOR i.  All arithmetic is binary64 with
- * compensated refinement residuals, as for a plan.
+ * SplitMix64 seeded with seed XOR i.  Arithmetic is binary64 with
+ * compensated refinement residuals, as for a plan, except for a binary32
+ * Gram with rtproj_batch_set_precision.
  *
  * Array arguments (A, lda, B, ldb, k, Z, ...) are HOST arrays of `count`
  * entries; the pointers in them are device pointers with the layouts of
@@ -376,6 +424,14 @@ rtproj_status rtproj_batch_set_stream(rtproj_batch batch, void *hip_stream);
  * estimate (plain binary64 residuals above their floor, compensated after),
  * which reads the estimates once per projection call (a short host wait). */
 rtproj_status rtproj_batch_set_refinement(rtproj_batch batch, int steps);
+/* Precision of every member's preconditioner: RTPROJ_PREC_FP64 (default)
+ * or RTPROJ_PREC_MIXED_FP32, whose Gram of P^{-1}A runs on binary32 MFMA
+ * (grouped over the members) with binary64 operands and reduction; the
+ * sketch, P^{-1}A, the factorizations and the refinement residuals stay
+ * binary64, and the refinement schedule accounts for the binary32 Gram
+ * (Remark 4.3).  RTPROJ_ERR_UNSUPPORTED for RTPROJ_PREC_MIXED_BF16.  Takes
+ * effect at the next rtproj_batch_precondition. */
+rtproj_status rtproj_batch_set_precision(rtproj_batch batch, int precision);
 /* 1: capture each entry point's launches into a HIP graph and replay it. */
 rtproj_status rtproj_batch_set_graph(rtproj_batch batch, int enable);
 rtproj_status rtproj_batch_precondition(rtproj_batch batch, const double *const *A, const int64_t *lda);

@@ -51,7 +51,7 @@ STAGES = ["sketch", "qrcp", "rinv_trsm", "w_gemm", "gram_syrk", "gram_inv", "min
 QR_AUTO, QR_DIRECT, QR_TWO_STAGE, QR_TWO_STAGE_WG = 0, 1, 2, 3
 INV_AUTO, INV_NEWTON_SCHULZ, INV_CHOLESKY = 0, 1, 2
 RESID_AUTO, RESID_PLAIN, RESID_S_ONLY, RESID_FULL = 0, 1, 2, 3
-METHOD_RANDOMIZED, METHOD_CLASSICAL = 0, 1
+METHOD_RANDOMIZED, METHOD_CLASSICAL, METHOD_KRYLOV = 0, 1, 2
 
 
 def lib():
@@ -72,6 +72,12 @@ def lib():
         L.rtproj_plan_set_inverse.argtypes = [vp, ip]
         L.rtproj_plan_set_residual.argtypes = [vp, ip]
         L.rtproj_plan_set_method.argtypes = [vp, ip]
+        L.rtproj_plan_set_sketch_matrix.argtypes = [vp, vp, i64]
+        L.rtproj_plan_set_krylov.argtypes = [vp, ip]
+        L.rtproj_plan_set_autotune.argtypes = [vp, ip]
+        L.rtproj_autotune_save.argtypes = [ctypes.c_char_p]
+        L.rtproj_autotune_load.argtypes = [ctypes.c_char_p]
+        L.rtproj_autotune_entries.restype = ip
         L.rtproj_plan_set_w_bits.argtypes = [vp, ip]
         L.rtproj_plan_status.argtypes = [vp]
         L.rtproj_precondition.argtypes = [vp, vp, i64]
@@ -88,6 +94,7 @@ def lib():
         L.rtproj_batch_set_stream.argtypes = [vp, vp]
         L.rtproj_batch_set_refinement.argtypes = [vp, ip]
         L.rtproj_batch_set_graph.argtypes = [vp, ip]
+        L.rtproj_batch_set_precision.argtypes = [vp, ip]
         L.rtproj_batch_precondition.argtypes = [vp, vp, vp]
         L.rtproj_batch_precondition_scaled.argtypes = [vp, vp, vp, vp]
         L.rtproj_batch_project_all.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -108,12 +115,14 @@ def lib():
         for name in ["rtproj_plan_create", "rtproj_plan_destroy", "rtproj_plan_set_stream",
                      "rtproj_plan_set_precision", "rtproj_plan_set_refinement", "rtproj_plan_set_qr", "rtproj_plan_set_inverse",
                      "rtproj_plan_set_residual", "rtproj_plan_set_w_bits", "rtproj_plan_status",
-                     "rtproj_plan_set_method",
+                     "rtproj_plan_set_method", "rtproj_plan_set_sketch_matrix", "rtproj_plan_set_krylov",
+                     "rtproj_plan_set_autotune", "rtproj_autotune_save", "rtproj_autotune_load",
                      "rtproj_precondition",
                      "rtproj_project_null", "rtproj_project_row", "rtproj_lstsq", "rtproj_project_all",
                      "rtproj_plan_info", "rtproj_plan_export", "rtproj_sketch_tables",
                      "rtproj_plan_set_timing", "rtproj_batch_create", "rtproj_batch_destroy",
                      "rtproj_batch_set_stream", "rtproj_batch_set_refinement", "rtproj_batch_set_graph",
+                     "rtproj_batch_set_precision",
                      "rtproj_batch_precondition", "rtproj_batch_project_all", "rtproj_batch_status",
                      "rtproj_batch_member_info", "rtproj_batch_set_timing", "rtproj_batch_info",
                      "rtproj_batch_precondition_scaled", "rtproj_batch_member_tables", "rtproj_cplan_create",
@@ -194,9 +203,28 @@ class Plan:
         _check(lib().rtproj_plan_set_residual(self.handle, mode))
 
     def set_method(self, method: int):
-        """METHOD_RANDOMIZED (default) or METHOD_CLASSICAL (eq. basic_identity
-        with a pivoted QR of A A^T, the comparison scheme of Sec. 5)."""
+        """METHOD_RANDOMIZED (default), METHOD_CLASSICAL (eq. basic_identity
+        with a pivoted QR of A A^T, the comparison scheme of Sec. 5) or
+        METHOD_KRYLOV (conjugate gradients on P^{-1}A, the iterative variant)."""
         _check(lib().rtproj_plan_set_method(self.handle, method))
+
+    def set_autotune(self, enable: bool):
+        """Time candidate configurations of P^{-1}A and its Gram for new shapes."""
+        _check(lib().rtproj_plan_set_autotune(self.handle, 1 if enable else 0))
+
+    def set_krylov(self, iters: int):
+        """Conjugate-gradient iterations per solve of METHOD_KRYLOV."""
+        _check(lib().rtproj_plan_set_krylov(self.handle, iters))
+
+    def set_sketch_matrix(self, G=None):
+        """Sketch with a dense (n, l) float64 CUDA tensor G (S = A G) instead
+        of the randomized Fourier transform; None restores the latter."""
+        if G is None:
+            _check(lib().rtproj_plan_set_sketch_matrix(self.handle, None, 0))
+        else:
+            _check_tensor(G, "G", self.n, self.l)
+            _check(lib().rtproj_plan_set_sketch_matrix(self.handle, _ptr(G), G.stride(0)))
+        self._G = G  # the plan borrows G
 
     def set_w_bits(self, bits: int):
         """Precision of P^{-1}A in the reduced-precision modes: 0 automatic, 32 or 64 forced."""
@@ -364,6 +392,18 @@ class CPlan:
         return Z, Y, X
 
 
+def autotune_save(path: str):
+    _check(lib().rtproj_autotune_save(path.encode()))
+
+
+def autotune_load(path: str):
+    _check(lib().rtproj_autotune_load(path.encode()))
+
+
+def autotune_entries() -> int:
+    return int(lib().rtproj_autotune_entries())
+
+
 def _ptrs(ts):
     arr = (ctypes.c_void_p * len(ts))(*[t.data_ptr() if t is not None else None for t in ts])
     return arr
@@ -409,6 +449,10 @@ class Batch:
 
     def set_graph(self, enable: bool):
         _check(lib().rtproj_batch_set_graph(self.handle, 1 if enable else 0))
+
+    def set_precision(self, precision: int):
+        """PREC_FP64 (default) or PREC_MIXED_FP32 (binary32 Gram on MFMA)."""
+        _check(lib().rtproj_batch_set_precision(self.handle, precision))
 
     def precondition(self, As, col_scales=None):
         """As[i]: (m_i, n_i) float64 CUDA tensors; col_scales[i] (optional):

@@ -24,7 +24,7 @@ namespace {
 
 enum OpKind {
     OP_GEMM, OP_REDUCE, OP_SKETCH, OP_COPY, OP_SET0, OP_SET1, OP_SHIFT, OP_CHOL, OP_TRIINV, OP_QRCPWG, OP_RDIAG,
-    OP_FORMTP, OP_ZERO, OP_AB, OP_ABRED, OP_ATX, OP_DDUPD, OP_IOTA, OP_SCALE
+    OP_FORMTP, OP_ZERO, OP_AB, OP_ABRED, OP_ATX, OP_DDUPD, OP_IOTA, OP_SCALE, OP_GEMM32, OP_RED32
 };
 
 struct Op {
@@ -72,6 +72,8 @@ struct rtproj_batch_s {
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;  // graph capture (the null stream cannot be captured)
     int refine_steps = -1;  // -1: schedule from the members' rank estimates
+    int precision = RTPROJ_PREC_FP64;  // the preconditioner's Gram: binary64 or binary32 (MIXED_FP32)
+    int prec_used = RTPROJ_PREC_FP64;  // of the last precondition
     int plain_steps = 0, comp_steps = 2;  // schedule of the last projection
     bool comp_final = true;               // its final A^T x compensated
     int last_steps = 0, last_plain = 0;   // steps of the last projection (norms recorded)
@@ -141,6 +143,37 @@ void rec_mat(Program &P, OpKind kind, const std::vector<rt::MatGroupArgs> &v)
 }
 
 // C (m x m, both triangles) = X X^T for each member's row-major m x K X.
+// Binary32 Gram on MFMA of the binary64 X (lower 64 x 64 tiles, split over
+// K), reduced in binary64 into both triangles of C.
+void rec_gram32(Program &P, rtproj_batch b, const std::vector<const double *> &X, const std::vector<int64_t> &ldx,
+                const std::vector<int64_t> &K, const std::vector<double *> &C)
+{
+    std::vector<rt::GemmMxArgs> g(b->count);
+    std::vector<rt::ReduceF32GroupArgs> r(b->count);
+    int ksmax = 1, mmax = 0;
+    for (int64_t i = 0; i < b->count; ++i) {
+        rtproj_plan p = b->sub[i];
+        const int64_t m = p->m;
+        rt::GemmMxArgs &a = g[i];
+        a.M = (int)m; a.N = (int)m; a.K = (int)K[i];
+        a.A = X[i]; a.a_dbl = 1; a.a_i = ldx[i]; a.a_k = 1;
+        a.B = X[i]; a.b_dbl = 1; a.b_k = 1; a.b_j = ldx[i];
+        a.C = p->d_part; a.c_dbl = 0; a.c_i = m; a.c_j = 1; a.c_split = m * m;
+        a.alpha = 1.f; a.c_lower = 1;
+        a.ksplit = (int)std::max<int64_t>(1, std::min<int64_t>(p->syrk_splits, K[i] / 256));
+        r[i] = rt::ReduceF32GroupArgs{reinterpret_cast<const float *>(p->d_part), m * m, a.ksplit, (int)m, C[i]};
+        ksmax = std::max(ksmax, a.ksplit);
+        mmax = std::max<int>(mmax, (int)m);
+    }
+    Op o{OP_GEMM32, P.add(g), (int)b->count};
+    o.i0 = mmax;
+    o.i1 = ksmax;
+    P.push(o);
+    Op q{OP_RED32, P.add(r), (int)b->count};
+    q.i0 = mmax;
+    P.push(q);
+}
+
 void rec_gram(Program &P, rtproj_batch b, const std::vector<const double *> &X, const std::vector<int64_t> &ldx,
               const std::vector<int64_t> &K, const std::vector<double *> &C)
 {
@@ -399,7 +432,8 @@ void build_precondition(Program &P, rtproj_batch b, const double *const *A, cons
         std::vector<int64_t> nn(cnt);
         for (int64_t i = 0; i < cnt; ++i) { W[i] = b->sub[i]->d_W; nn[i] = b->sub[i]->n; }
         P.stage = 4;
-        rec_gram(P, b, W, nn, nn, G);
+        if (b->prec_used == RTPROJ_PREC_MIXED_FP32) rec_gram32(P, b, W, nn, nn, G);
+        else rec_gram(P, b, W, nn, nn, G);
         P.stage = 5;
         rec_cholesky(P, b, G, Lm);
     }
@@ -629,6 +663,8 @@ hipError_t run_op(const Op &o, const unsigned char *arena, hipStream_t s)
     case OP_DDUPD: return rt::dd_update_grouped_f64((const rt::DdGroupArgs *)d, o.count, s);
     case OP_IOTA: return rt::iota_grouped_i32((const rt::MatGroupArgs *)d, o.count, o.i0, s);
     case OP_SCALE: return rt::scale_cols_grouped_f64((const rt::ScaleGroupArgs *)d, o.count, s);
+    case OP_GEMM32: return rt::gemm_f32_grouped_lower((const rt::GemmMxArgs *)d, o.count, o.i0, o.i1, s);
+    case OP_RED32: return rt::reduce_f32_grouped((const rt::ReduceF32GroupArgs *)d, o.count, o.i0, s);
     }
     return hipErrorInvalidValue;
 }
@@ -801,6 +837,16 @@ rtproj_status rtproj_batch_set_refinement(rtproj_batch b, int steps)
     return RTPROJ_OK;
 }
 
+rtproj_status rtproj_batch_set_precision(rtproj_batch b, int precision)
+{
+    if (!b) return fail(RTPROJ_ERR_INVALID_ARG, "null batch");
+    if (precision != RTPROJ_PREC_FP64 && precision != RTPROJ_PREC_MIXED_FP32)
+        return fail(precision == RTPROJ_PREC_MIXED_BF16 ? RTPROJ_ERR_UNSUPPORTED : RTPROJ_ERR_INVALID_ARG,
+                    "batches take RTPROJ_PREC_FP64 or RTPROJ_PREC_MIXED_FP32");
+    b->precision = precision;
+    return RTPROJ_OK;
+}
+
 rtproj_status rtproj_batch_set_graph(rtproj_batch b, int enable)
 {
     if (!b) return fail(RTPROJ_ERR_INVALID_ARG, "null batch");
@@ -852,6 +898,7 @@ rtproj_status rtproj_batch_precondition_scaled(rtproj_batch b, const double *con
             lw[i] = p->n;
         }
     }
+    b->prec_used = b->precision;
     Program P;
     if (!sc.empty()) {
         P.stage = 0;
@@ -913,8 +960,10 @@ rtproj_status rtproj_batch_project_all(rtproj_batch b, const double *const *B, c
             const double *d = diag.data() + 8 * i;
             const double kap = d[2] > 0 ? d[3] / d[2] : 1e16;
             const double cw = d[6] > 0 ? d[7] / d[6] : 1e3;
-            const RefinePlan rp = refine_schedule(std::isfinite(kap) ? kap : 1e16, RTPROJ_PREC_FP64, false,
-                                                  std::isfinite(cw) ? cw : 1e3, 0.0, RTPROJ_RESID_FULL, -1);
+            rtproj_plan p = b->sub[i];
+            const double gram_k = (double)p->n / std::max<int64_t>(1, std::min<int64_t>(p->syrk_splits, p->n / 256));
+            const RefinePlan rp = refine_schedule(std::isfinite(kap) ? kap : 1e16, b->prec_used, false,
+                                                  std::isfinite(cw) ? cw : 1e3, gram_k, RTPROJ_RESID_FULL, -1);
             pl = std::max(pl, rp.plain);
             cp = std::max(cp, rp.comp);
             cf = cf || rp.comp_final;
@@ -971,6 +1020,9 @@ rtproj_status rtproj_batch_status(rtproj_batch b, int *per_member)
         p->info.gram_cond_est = d[6] > 0 ? d[7] / d[6] : INFINITY;
         p->info.inverse = RTPROJ_INV_CHOLESKY;
         p->inv_used = RTPROJ_INV_CHOLESKY;
+        p->info.precision = b->prec_used;
+        p->info.gram_bits = b->prec_used == RTPROJ_PREC_MIXED_FP32 ? 32 : 64;
+        p->info.sketch_bits = p->info.w_bits = 64;
         if (per_member) per_member[i] = st;
         if (st == RTPROJ_ERR_RANK || (st != RTPROJ_OK && worst == RTPROJ_OK)) worst = st;
     }

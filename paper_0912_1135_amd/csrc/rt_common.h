@@ -61,6 +61,8 @@ struct GemmArgs {
     double alpha, beta;
     int a_lower, c_lower, ksplit;
     int small_tiles;  // 1: 64 x 64 tiles whatever M, N (more blocks for small products)
+    int tile;         // 0: chosen from the shape; 64 or 128 forces the square tile size
+    int order;        // 0: tile order chosen from the shape; 1 plain; 2 XCD-grouped
 };
 
 // Launches GEMM with 64x64 or 128x128 tiles (chosen from M, N unless
@@ -116,8 +118,17 @@ struct GemmMxArgs {
     void *C; int c_dbl; int64_t c_i, c_j, c_split;
     float alpha;
     int a_lower, c_lower, ksplit;
+    int tile;         // binary32: 0 chosen from the shape; 64 or 128 forces it
 };
 hipError_t gemm_mx(const GemmMxArgs &g, int mode, hipStream_t stream);
+// Grouped binary32 Gram of binary64 operands (batches): the lower 64 x 64
+// tiles of each member's C = A B (A, B K-contiguous), K split ksmax ways
+// (members with fewer splits skip the extra ones); then the binary64
+// reduction of each member's binary32 partials into both triangles of its
+// m x m output.
+hipError_t gemm_f32_grouped_lower(const GemmMxArgs *d_args, int count, int max_m, int ksmax, hipStream_t stream);
+struct ReduceF32GroupArgs { const float *part; int64_t stride; int splits; int m; double *out; };
+hipError_t reduce_f32_grouped(const ReduceF32GroupArgs *d, int count, int max_m, hipStream_t stream);
 // out(i,j) = sum_s part[s*stride + i*ld + j] / (sa[i] sb[j]) in binary64.
 hipError_t reduce_f32_splits(const float *part, int64_t stride, int splits, int M, int N, int64_t ld,
                              const float *sa, const float *sb, double *out, int64_t ldo, int mirror,
@@ -321,6 +332,12 @@ hipError_t dd_update_f64(double *Xhi, double *Xlo, const double *D, int m, int k
 // m <= 8192 (the vector is kept in LDS).
 hipError_t qr_solve_f64(int m, const double *V, const double *tau, const double *R, const int32_t *piv,
                         const double *C, int64_t ldc, double *X, int64_t ldx, int k, hipStream_t stream);
+// Conjugate gradients on k columns (m x k column-major blocks, ld m): init
+// r = t, pp = t, u = 0, gamma = r.r; step with q = (operator) pp.
+hipError_t cg_init_f64(int m, int k, const double *t, double *u, double *r, double *pp, double *gamma,
+                       hipStream_t stream);
+hipError_t cg_step_f64(int m, int k, double *u, double *r, double *pp, const double *q, double *gamma,
+                       hipStream_t stream);
 // out = B - C for column-major rows x cols blocks (out may be B or C).
 hipError_t sub_cols_f64(const double *B, int64_t ldb, const double *C, int64_t ldc, double *out, int64_t ldo, int rows,
                         int cols, hipStream_t stream);

@@ -97,77 +97,81 @@ __global__ __launch_bounds__(DT) void tri_diag_inv_grouped(const TriInvGroupArgs
 }
 
 // Cholesky of one 64 x 64 diagonal block (right-looking) and the inverse of
-// its factor.  At step j the owners of column j publish it (unscaled), every
-// thread reads the pivot d = A[j][j], finalizes its entries of column j
-// (L[i][j] = A[i][j] / sqrt(d), L[j][j] = sqrt(d)) and updates its trailing
-// entries A[i][c] -= A[i][j] A[c][j] / d.  The broadcast buffer alternates
-// between two halves, so one block barrier per step suffices.  A
-// non-positive or non-finite pivot sets *err (the outputs are then garbage).
+// its factor, by one wave.  A non-positive or non-finite pivot sets *err
+// (the outputs are then garbage).
+__device__ __forceinline__ double lane_value(double v, int src)
+{
+    const unsigned long long bits = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = __builtin_amdgcn_readlane((unsigned)bits, src);
+    const unsigned hi = __builtin_amdgcn_readlane((unsigned)(bits >> 32), src);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// One wave: lane i keeps row i of the block (a[c], c <= i) in registers.
+// Step j: the pivot d = A[j][j] is read from lane j, every lane finalizes its
+// entry of column j (L[j][j] = sqrt(d), L[i][j] = A[i][j] / sqrt(d) below),
+// publishes it in LDS, and updates its row, A[i][c] -= L[i][j] L[c][j] for
+// c > j.  Then L goes to LDS and lane i solves L x = e_i for column i of
+// X = L^{-1}.  A wave's LDS accesses complete in order, so no barrier is
+// needed between the steps.
 __device__ __forceinline__ void chol_diag_body(const double *Xg, int64_t ldx, int m, int nb, int b, double *Lg,
                                                int64_t ldl, double *Dinv, int *err)
 {
     if (b * nb >= m) return;  // whole block (grouped launches)
+    __shared__ double pub[NBMAX];
     __shared__ double Ls[NBMAX * LDP];
-    __shared__ double Xs[NBMAX * LDP];
-    __shared__ double colb[2][NBMAX];
-    int ri[NE], ci[NE];
-    tri_slots(ri, ci);
+    const int i = threadIdx.x;
     const int base = b * nb, nbb = min(nb, m - base);
-    double a[NE];
+    double a[NBMAX];
 #pragma unroll
-    for (int s = 0; s < NE; ++s) {
-        const int i = ri[s], c = ci[s];
-        double v = 0.0;
-        if (i >= 0) {
-            if (i < nbb && c < nbb) v = Xg[(int64_t)(base + i) * ldx + base + c];
-            else v = (i == c) ? 1.0 : 0.0;
-        }
-        a[s] = v;
+    for (int c = 0; c < NBMAX; ++c) {
+        double v = (i == c) ? 1.0 : 0.0;
+        if (i < nbb && c < nbb && c <= i) v = Xg[(int64_t)(base + i) * ldx + base + c];
+        a[c] = v;
     }
     bool bad = false;
-    for (int j = 0; j < NBMAX; ++j) {
-        double *cb = colb[j & 1];
 #pragma unroll
-        for (int s = 0; s < NE; ++s)
-            if (ci[s] == j) cb[ri[s]] = a[s];
-        __syncthreads();
-        const double d = cb[j];
+    for (int j = 0; j < NBMAX; ++j) {
+        const double d = lane_value(a[j], j);
         bad |= !(d > 0.0 && d < INFINITY);
         const double ljj = __builtin_sqrt(d);
-        const double rl = 1.0 / ljj;
-        const double inv_d = rl * rl;
-        // branch-free: finalize column j, update the entries right of it
+        const double lij = (i == j) ? ljj : (i > j ? a[j] / ljj : 0.0);
+        a[j] = lij;
+        pub[i] = lij;
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int s = 0; s < NE; ++s) {
-            const int r = ri[s] > j ? ri[s] : j, c = ci[s] > j && ci[s] < NBMAX ? ci[s] : j;
-            const double u = cb[r] * cb[c] * inv_d;
-            const double fin = (ri[s] == j) ? ljj : a[s] * rl;
-            a[s] = (ci[s] == j) ? fin : ((ci[s] > j && ri[s] >= 0) ? a[s] - u : a[s]);
-        }
+        for (int c = j + 1; c < NBMAX; ++c) a[c] -= lij * pub[c];
+        __builtin_amdgcn_wave_barrier();
     }
-    for (int e = threadIdx.x; e < NBMAX * NBMAX; e += DT) Ls[(e / NBMAX) * LDP + (e % NBMAX)] = 0.0;
-    __syncthreads();
+    if (i < nbb)
+        for (int c = 0; c < nbb; ++c) Lg[(int64_t)(base + i) * ldl + base + c] = c <= i ? a[c] : 0.0;
+    // X = L^{-1} by forward substitution, lane i solving for column i of X:
+    // x[r] = (delta_ri - sum_{p<r} L[r][p] x[p]) / L[r][r], with L read from
+    // LDS (the same address in every lane)
 #pragma unroll
-    for (int s = 0; s < NE; ++s)
-        if (ri[s] >= 0) Ls[ri[s] * LDP + ci[s]] = a[s];
-    __syncthreads();
-    for (int e = threadIdx.x; e < nbb * nbb; e += DT) {
-        const int r = e / nbb, c = e % nbb;
-        Lg[(int64_t)(base + r) * ldl + base + c] = Ls[r * LDP + c];
+    for (int c = 0; c < NBMAX; ++c) Ls[i * LDP + c] = c <= i ? a[c] : 0.0;
+    __builtin_amdgcn_wave_barrier();
+    double x[NBMAX];
+#pragma unroll
+    for (int r = 0; r < NBMAX; ++r) {
+        double t = (r == i) ? 1.0 : 0.0;
+#pragma unroll
+        for (int p = 0; p < r; ++p) t -= Ls[r * LDP + p] * x[p];
+        x[r] = t / Ls[r * LDP + r];
     }
-    lower_inverse_block(Ls, Xs);
     double *out = Dinv + (int64_t)b * nb * nb;
-    for (int e = threadIdx.x; e < nb * nb; e += DT) out[e] = Xs[(e / nb) * LDP + (e % nb)];
-    if (bad && threadIdx.x == 0) atomicExch(err, 1);
+    if (i < nb)
+        for (int r = 0; r < nb; ++r) out[(int64_t)r * nb + i] = x[r];
+    if (bad && i == 0) atomicExch(err, 1);
 }
 
-__global__ __launch_bounds__(DT) void chol_diag_kernel(const double *Xg, int64_t ldx, int m, int nb, int b, double *Lg,
-                                                       int64_t ldl, double *Dinv, int *err)
+__global__ __launch_bounds__(NBMAX) void chol_diag_kernel(const double *Xg, int64_t ldx, int m, int nb, int b,
+                                                          double *Lg, int64_t ldl, double *Dinv, int *err)
 {
     chol_diag_body(Xg, ldx, m, nb, b, Lg, ldl, Dinv, err);
 }
 
-__global__ __launch_bounds__(DT) void chol_diag_grouped(const CholGroupArgs *gs, int nb, int b)
+__global__ __launch_bounds__(NBMAX) void chol_diag_grouped(const CholGroupArgs *gs, int nb, int b)
 {
     const CholGroupArgs g = gs[blockIdx.x];
     chol_diag_body(g.X, g.ldx, g.m, nb, b, g.L, g.ldl, g.Dinv, g.err);
@@ -420,7 +424,7 @@ hipError_t chol_diag_f64(const double *X, int64_t ldx, int m, int nb, int b, dou
                          int *err, hipStream_t stream)
 {
     if (nb != NBMAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(DT), 0, stream, X, ldx, m, nb, b, L, ldl, Dinv, err);
+    hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(NBMAX), 0, stream, X, ldx, m, nb, b, L, ldl, Dinv, err);
     return hipGetLastError();
 }
 
@@ -457,7 +461,7 @@ hipError_t chol_diag_grouped_f64(const CholGroupArgs *d, int count, int nb, int 
 {
     if (nb != NBMAX) return hipErrorInvalidValue;
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(chol_diag_grouped, dim3(count), dim3(DT), 0, stream, d, nb, b);
+    hipLaunchKernelGGL(chol_diag_grouped, dim3(count), dim3(NBMAX), 0, stream, d, nb, b);
     return hipGetLastError();
 }
 

@@ -288,6 +288,8 @@ hipError_t launch_tile(const GemmArgs &g, hipStream_t s)
     // tiles per panel; with 8 M tiles (a 512-row product) the plain order
     // runs the same product about 20% faster
     tm.xcd = (g.c_lower || gm >= 16) ? 1 : 0;
+    if (g.order == 1 && !g.c_lower) tm.xcd = 0;
+    if (g.order == 2) tm.xcd = 1;
     return g.b_gather ? launch_tile_g<BM, BN, true>(g, tm, s) : launch_tile_g<BM, BN, false>(g, tm, s);
 }
 
@@ -522,6 +524,8 @@ hipError_t sq_mm_f64(int m, const double *A, const double *B, double *out, doubl
 hipError_t gemm_f64(const GemmArgs &g, hipStream_t stream)
 {
     if (g.M <= 0 || g.N <= 0) return hipSuccess;
+    if (g.tile == 128) return launch_tile<128, 128>(g, stream);
+    if (g.tile == 64) return launch_tile<64, 64>(g, stream);
     // triangular A (P^{-1}A): 64-row tiles measured faster than 128-row ones
     if (g.M >= 128 && g.N >= 128 && !g.a_lower && !g.small_tiles) return launch_tile<128, 128>(g, stream);
     return launch_tile<64, 64>(g, stream);

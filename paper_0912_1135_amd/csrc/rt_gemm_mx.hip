@@ -40,7 +40,7 @@ __device__ __forceinline__ double ld_st(const void *p, int64_t idx)
 // gather of B's rows reads its indices one chunk ahead.  DBL: binary64
 // storage of both operands (else binary32).
 template <int BM, int BN, bool A_KC, bool B_KC, bool DBL, bool GB>
-__global__ __launch_bounds__(256) void gemm_f32_kernel(GemmMxArgs g)
+__device__ __forceinline__ void gemm_f32_tile(const GemmMxArgs &g, int bx, int by, int bz)
 {
     using LA = Lay32<BM, A_KC>;
     using LB = Lay32<BN, B_KC>;
@@ -53,21 +53,23 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmMxArgs g)
     const int wm = wave >> 1, wn = wave & 1;
     int ti, tj;
     if (g.c_lower) {
-        const int t = blockIdx.x;
+        const int t = bx;
         ti = (int)((__builtin_sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
         while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
         while (ti * (ti + 1) / 2 > t) --ti;
         tj = t - ti * (ti + 1) / 2;
     } else {
-        ti = blockIdx.y;
-        tj = blockIdx.x;
+        ti = by;
+        tj = bx;
     }
     const int i0 = ti * BM, j0 = tj * BN;
+    // tiles outside the problem (grouped launches cover the largest member)
+    if (i0 >= g.M || j0 >= g.N || bz >= (g.ksplit > 1 ? g.ksplit : 1)) return;
     int kbeg = 0, kend = g.K;
     if (g.ksplit > 1) {
         int ks = (g.K + g.ksplit - 1) / g.ksplit;
         ks = (ks + KC32 - 1) / KC32 * KC32;
-        kbeg = blockIdx.z * ks;
+        kbeg = bz * ks;
         kend = min(g.K, kbeg + ks);
     }
     if (g.a_lower) kend = min(kend, i0 + BM);
@@ -166,7 +168,7 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmMxArgs g)
                     acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
         }
     }
-    const int64_t coff = g.ksplit > 1 ? (int64_t)blockIdx.z * g.c_split : 0;
+    const int64_t coff = g.ksplit > 1 ? (int64_t)bz * g.c_split : 0;
 #pragma unroll
     for (int a = 0; a < TM; ++a)
 #pragma unroll
@@ -183,6 +185,20 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmMxArgs g)
                     else static_cast<float *>(g.C)[idx] = v;
                 }
             }
+}
+
+template <int BM, int BN, bool A_KC, bool B_KC, bool DBL, bool GB>
+__global__ __launch_bounds__(256) void gemm_f32_kernel(GemmMxArgs g)
+{
+    gemm_f32_tile<BM, BN, A_KC, B_KC, DBL, GB>(g, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Grouped launch (batches): member blockIdx.z / ksmax, split blockIdx.z % ksmax.
+template <int BM, int BN, bool A_KC, bool B_KC, bool DBL>
+__global__ __launch_bounds__(256) void gemm_f32_grouped_kernel(const GemmMxArgs *gs, int ksmax)
+{
+    const GemmMxArgs g = gs[blockIdx.z / ksmax];
+    gemm_f32_tile<BM, BN, A_KC, B_KC, DBL, false>(g, blockIdx.x, blockIdx.y, blockIdx.z % ksmax);
 }
 
 // ---------------------------------------------------------------- bfloat16
@@ -412,9 +428,41 @@ hipError_t gemm_mx(const GemmMxArgs &g, int mode, hipStream_t stream)
         else hipLaunchKernelGGL((gemm_bf16_kernel<128, 128, false>), grid, dim3(256), 0, stream, g);
         return hipGetLastError();
     }
+    if (g.tile == 128) return launch32<128, 128>(g, stream);
+    if (g.tile == 64) return launch32<64, 64>(g, stream);
     // triangular A (P^{-1}A): 64-row tiles measured faster than 128-row ones
     if (g.M >= 128 && g.N >= 128 && !g.a_lower) return launch32<128, 128>(g, stream);
     return launch32<64, 64>(g, stream);
+}
+
+hipError_t gemm_f32_grouped_lower(const GemmMxArgs *d_args, int count, int max_m, int ksmax, hipStream_t stream)
+{
+    if (count <= 0 || max_m <= 0) return hipSuccess;
+    const int gm = (max_m + 63) / 64;
+    const dim3 grid((unsigned)(gm * (gm + 1) / 2), 1, (unsigned)(count * ksmax));
+    hipLaunchKernelGGL((gemm_f32_grouped_kernel<64, 64, true, true, true>), grid, dim3(256), 0, stream, d_args, ksmax);
+    return hipGetLastError();
+}
+
+__global__ void reduce_f32_grouped_kernel(const ReduceF32GroupArgs *gs)
+{
+    const ReduceF32GroupArgs g = gs[blockIdx.y];
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)g.m * g.m) return;
+    const int i = (int)(e / g.m), j = (int)(e % g.m);
+    if (j > i) return;
+    double s = 0.0;
+    for (int p = 0; p < g.splits; ++p) s += (double)g.part[p * g.stride + (int64_t)i * g.m + j];
+    g.out[(int64_t)i * g.m + j] = s;
+    g.out[(int64_t)j * g.m + i] = s;
+}
+
+hipError_t reduce_f32_grouped(const ReduceF32GroupArgs *d, int count, int max_m, hipStream_t stream)
+{
+    const int64_t total = (int64_t)max_m * max_m;
+    if (count <= 0 || total == 0) return hipSuccess;
+    hipLaunchKernelGGL(reduce_f32_grouped_kernel, dim3((unsigned)((total + 255) / 256), count), dim3(256), 0, stream, d);
+    return hipGetLastError();
 }
 
 hipError_t reduce_f32_splits(const float *part, int64_t stride, int splits, int M, int N, int64_t ld, const float *sa,

@@ -82,7 +82,7 @@ void release(rtproj_plan p)
                     p->d_twl, p->d_tw1f, p->d_tw2f, p->d_twhf, p->d_twlf, p->d_rowscale, p->d_zbuf, p->d_S, p->d_R, p->d_Y, p->d_W, p->d_part, p->d_G, p->d_L, p->d_Tp,
                     p->d_DinvR, p->d_DinvL, p->d_piv, p->d_sync, p->d_slots, p->d_vbuf, p->d_qrcols, p->d_Yq, p->d_R0, p->d_wgargs, p->d_rinv_args, p->d_scal, p->d_diag,
                     p->d_bsum, p->d_c, p->d_tmp, p->d_xhi, p->d_xlo, p->d_d, p->d_r, p->d_ph, p->d_pl, p->d_norms, p->d_xpk, p->d_bpk,
-                    p->d_err, p->d_V, p->d_tau};
+                    p->d_err, p->d_V, p->d_tau, p->d_gpart, p->d_kry};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (p->h_scal) (void)hipHostFree(p->h_scal);
@@ -178,7 +178,11 @@ rtproj_status alloc_state(rtproj_plan p)
     const int gt = (int)((m + 127) / 128);
     const int tiles = gt * (gt + 1) / 2;
     p->syrk_splits = (int)std::max<int64_t>(1, std::min<int64_t>({64, (4 * p->cu_count + tiles - 1) / tiles, n / 256}));
-    RT_HIP(dalloc(&p->d_part, (size_t)p->syrk_splits * m * m));
+    // split partials: room for twice the built-in split count (the
+    // autotuner may pick more splits), at most 64
+    p->part_cap = (int)std::min<int64_t>(64, std::max<int64_t>(1, std::min<int64_t>(2 * p->syrk_splits, n / 256)));
+    p->part_cap = std::max(p->part_cap, p->syrk_splits);
+    RT_HIP(dalloc(&p->d_part, (size_t)p->part_cap * m * m));
     RT_HIP(dalloc(&p->d_G, (size_t)m * m));
     RT_HIP(dalloc(&p->d_L, (size_t)m * m));
     RT_HIP(dalloc(&p->d_Tp, (size_t)2 * m * m));
@@ -561,9 +565,15 @@ double refine_rho_model(double kappa_est, int precision, bool w32, double cond_w
 RefinePlan refine_schedule(double kappa_est, int precision, bool w32, double cond_w, double gram_k, int mode,
                            int max_steps)
 {
+    return refine_schedule_rho(refine_rho_model(kappa_est, precision, w32, cond_w, gram_k), kappa_est, mode,
+                               max_steps);
+}
+
+RefinePlan refine_schedule_rho(double rho, double kappa_est, int mode, int max_steps)
+{
     RefinePlan r;
     const double k = std::max(1.0, std::isfinite(kappa_est) ? kappa_est : 1e16);
-    r.rho = refine_rho_model(kappa_est, precision, w32, cond_w, gram_k);
+    r.rho = std::min(0.5, rho);
     if (mode == RTPROJ_RESID_AUTO) mode = RTPROJ_RESID_FULL;
     r.comp_r = mode == RTPROJ_RESID_FULL;
     if (max_steps >= 0) {
@@ -757,6 +767,84 @@ hipError_t resid_plain(rtproj_plan p, const double *B, int64_t ldb, int64_t k, h
     return rt::gemm_f64(g, s);
 }
 
+// out (m x k, column-major, ld ldo) = Am B for a row-major m x m Am and a
+// column-major m x k B: one launch per product up to RT_SKINNY_KMAX
+// right-hand sides, else a split-K MFMA GEMM and its fixed-order reduction.
+hipError_t small_mm(rtproj_plan p, const double *Am, const double *B, int64_t ldb, double *out, int64_t ldo, int64_t k)
+{
+    const int64_t m = p->m;
+    if (k <= RT_SKINNY_KMAX) return rt::skinny_mm_f64((int)m, (int)k, (int)m, Am, m, B, ldb, out, ldo, p->stream);
+    const int splits = (int)std::max<int64_t>(1, std::min<int64_t>(p->ab_splits, (m + 63) / 64));
+    rt::GemmArgs g{};
+    g.M = (int)m; g.N = (int)k; g.K = (int)m;
+    g.A = Am; g.a_i = m; g.a_k = 1;
+    g.B = B; g.b_k = 1; g.b_j = ldb;
+    g.C = p->d_ph; g.c_i = 1; g.c_j = m; g.c_split = m * k;
+    g.alpha = 1.0; g.ksplit = splits;
+    hipError_t e = rt::gemm_f64(g, p->stream);
+    return e != hipSuccess ? e : rt::reduce_splits_f64(p->d_ph, m * k, splits, (int)k, (int)m, m, out, ldo, 0, p->stream);
+}
+
+// out (n x k, ld n) = A^T V for a column-major m x k V (ld m), plain binary64:
+// one pass over A on the vector units below RT_MFMA_KMIN right-hand sides,
+// an MFMA GEMM from there.
+hipError_t atx_out(rtproj_plan p, const double *V, double *out, int64_t k)
+{
+    const int64_t m = p->m, n = p->n;
+    if (k < RT_MFMA_KMIN) {
+        rt::ApplyArgs a{(int)m, (int)n, (int)k, p->A, p->lda};
+        return rt::atx_f64(a, V, nullptr, m, nullptr, 0, nullptr, 0, out, n, nullptr, 0, 0, p->stream);
+    }
+    rt::GemmArgs g{};
+    g.M = (int)n; g.N = (int)k; g.K = (int)m;
+    g.A = p->A; g.a_i = 1; g.a_k = p->lda;
+    g.B = V; g.b_k = 1; g.b_j = m;
+    g.C = out; g.c_i = 1; g.c_j = n;
+    g.alpha = 1.0; g.beta = 0.0; g.ksplit = 1;
+    return rt::gemm_f64(g, p->stream);
+}
+
+// H = (A A^T)^{-1} C for the iterative variant: with P^{-1} = T' = R^{-T} Pi,
+// (A A^T)^{-1} = T'^T (W W^T)^{-1} T' and W W^T v = T' A A^T T'^T v; conjugate
+// gradients on W W^T from u = 0 for t = T' C, krylov_iters iterations, then
+// H = T'^T u.  d_r (n x k) and d_c (m x k) serve as the passes' scratch, so C
+// must not be d_c's contents needed afterwards (it is read first).
+rtproj_status krylov_solve(rtproj_plan p, const double *C, int64_t ldc, double *H, int64_t ldh, int64_t k)
+{
+    const int64_t m = p->m;
+    hipStream_t s = p->stream;
+    if (k > p->kry_cap) {
+        if (p->d_kry) (void)hipFree(p->d_kry);
+        p->d_kry = nullptr;
+        p->kry_cap = 0;
+        RT_HIP(dalloc(&p->d_kry, (size_t)(5 * m * k + k)));
+        p->kry_cap = k;
+    }
+    const int64_t mk = m * p->kry_cap;
+    double *u = p->d_kry, *r = u + mk, *pp = r + mk, *q = pp + mk, *w = q + mk, *gamma = w + mk;
+    const double *Tt = p->d_Tp, *T = p->d_Tp + m * m;  // T'^T and T', row-major
+    RT_HIP(small_mm(p, T, C, ldc, w, m, k));
+    RT_HIP(rt::cg_init_f64((int)m, (int)k, w, u, r, pp, gamma, s));
+    for (int it = 0; it < p->krylov_iters; ++it) {
+        RT_HIP(small_mm(p, Tt, pp, m, w, m, k));        // w = P^{-T} pp
+        RT_HIP(atx_out(p, w, p->d_r, k));               // A^T w
+        RT_HIP(ab_plain(p, p->d_r, p->n, k, s));        // d_c = A A^T w
+        RT_HIP(small_mm(p, T, p->d_c, m, q, m, k));     // q = W W^T pp
+        RT_HIP(rt::cg_step_f64((int)m, (int)k, u, r, pp, q, gamma, s));
+    }
+    RT_HIP(small_mm(p, Tt, u, m, H, ldh, k));
+    return RTPROJ_OK;
+}
+
+// The solve with the normal matrix that every projection and refinement step
+// needs: the explicit factored M^{-1} of the preconditioner, or conjugate
+// gradients for the iterative variant.
+rtproj_status solve_normal(rtproj_plan p, const double *C, int64_t ldc, double *H, int64_t ldh, int64_t k)
+{
+    if (p->method_used == RTPROJ_METHOD_KRYLOV) return krylov_solve(p, C, ldc, H, ldh, k);
+    return apply_minv(p, C, ldc, H, ldh, k);
+}
+
 // Final row and null projections from x_hi in plain binary64: Y = A^T x,
 // Z = B - A^T x.  Below RT_MFMA_KMIN right-hand sides one pass over A on the
 // vector units; from there MFMA GEMMs: Z = B - A^T x (copy, then alpha = -1,
@@ -840,13 +928,19 @@ rtproj_status project(rtproj_plan p, const double *B, int64_t ldb, int64_t k, do
     // steps 2-6: x = Pi^T R^{-1} Y R^{-T} Pi c
     {
         StageScope sc(p, 8);
-        st = apply_minv(p, p->d_c, m, p->d_xhi, m, k);
+        st = solve_normal(p, p->d_c, m, p->d_xhi, m, k);
         if (st != RTPROJ_OK) return st;
         RT_HIP(rt::set_matrix_f64(p->d_xlo, m, (int)k, (int)m, 0, s));
     }
-    const RefinePlan rp = refine_schedule(p->info.kappa_est, p->prec_used, p->w32, p->info.gram_cond_est,
-                                          (double)p->n / std::max(1, p->syrk_splits), p->resid_mode,
-                                          p->refine_steps);
+    RefinePlan rp = refine_schedule(p->info.kappa_est, p->prec_used, p->w32, p->info.gram_cond_est,
+                                    (double)p->n / std::max(1, p->syrk_splits), p->resid_mode, p->refine_steps);
+    if (p->method_used == RTPROJ_METHOD_KRYLOV) {
+        // a solve ends within 2 (0.6)^iters of the exact correction (CG on W W^T
+        // with cond(W) <= 4), plus the rounding of its passes, about 16 u kappa
+        const double rin = std::min(0.5, 2.0 * std::pow(0.6, p->krylov_iters) +
+                                              16.0 * std::ldexp(1.0, -52) * std::max(1.0, p->info.kappa_est));
+        rp = refine_schedule_rho(rin, p->info.kappa_est, p->resid_mode, p->refine_steps);
+    }
     p->info.refine_rho_model = rp.rho;
     const int nplain = rp.plain, nsteps = std::min(rp.plain + rp.comp, RT_MAX_STEPS);
     int steps = 0;
@@ -873,7 +967,7 @@ rtproj_status project(rtproj_plan p, const double *B, int64_t ldb, int64_t k, do
         }
         {
             StageScope sc(p, 8);
-            st = apply_minv(p, p->d_c, m, p->d_d, m, k);
+            st = solve_normal(p, p->d_c, m, p->d_d, m, k);
             if (st != RTPROJ_OK) return st;
             RT_HIP(rt::dd_update_f64(p->d_xhi, p->d_xlo, p->d_d, (int)m, (int)k, p->d_norms + 2 * it, s));
         }
@@ -1011,11 +1105,28 @@ rtproj_status rtproj_plan_set_w_bits(rtproj_plan p, int bits)
 rtproj_status rtproj_plan_set_method(rtproj_plan p, int method)
 {
     if (!p) return fail(RTPROJ_ERR_INVALID_ARG, "null plan");
-    if (method != RTPROJ_METHOD_RANDOMIZED && method != RTPROJ_METHOD_CLASSICAL)
+    if (method != RTPROJ_METHOD_RANDOMIZED && method != RTPROJ_METHOD_CLASSICAL && method != RTPROJ_METHOD_KRYLOV)
         return fail(RTPROJ_ERR_INVALID_ARG, "unknown method");
     if (method == RTPROJ_METHOD_CLASSICAL && p->m > 4096)
         return fail(RTPROJ_ERR_UNSUPPORTED, "classical scheme: m above 4096");
     p->method = method;
+    return RTPROJ_OK;
+}
+
+rtproj_status rtproj_plan_set_krylov(rtproj_plan p, int iters)
+{
+    if (!p) return fail(RTPROJ_ERR_INVALID_ARG, "null plan");
+    if (iters < 1 || iters > 500) return fail(RTPROJ_ERR_INVALID_ARG, "iterations outside [1, 500]");
+    p->krylov_iters = iters;
+    return RTPROJ_OK;
+}
+
+rtproj_status rtproj_plan_set_sketch_matrix(rtproj_plan p, const double *G, int64_t ldg)
+{
+    if (!p) return fail(RTPROJ_ERR_INVALID_ARG, "null plan");
+    if (G && ldg < p->l) return fail(RTPROJ_ERR_INVALID_ARG, "ldg < l");
+    p->Gmat = G;
+    p->ldg = G ? ldg : 0;
     return RTPROJ_OK;
 }
 
@@ -1154,7 +1265,27 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
     const int64_t m = p->m, n = p->n, l = p->l;
     hipStream_t s = p->stream;
     // 1. sketch
-    {
+    if (p->Gmat) {
+        // S = A G with the caller's G, binary64 MFMA, K = n split over blocks
+        StageScope sc(p, 0);
+        const int64_t tiles = ((m + 63) / 64) * ((l + 63) / 64);
+        const int splits = (int)std::max<int64_t>(1, std::min<int64_t>({32, n / 1024, (4 * p->cu_count + tiles - 1) / tiles}));
+        if ((int64_t)splits * m * l > p->gpart_cap) {
+            if (p->d_gpart) (void)hipFree(p->d_gpart);
+            p->d_gpart = nullptr;
+            p->gpart_cap = 0;
+            RT_HIP(dalloc(&p->d_gpart, (size_t)splits * m * l));
+            p->gpart_cap = (int64_t)splits * m * l;
+        }
+        rt::GemmArgs g{};
+        g.M = (int)m; g.N = (int)l; g.K = (int)n;
+        g.A = A; g.a_i = lda; g.a_k = 1;
+        g.B = p->Gmat; g.b_k = p->ldg; g.b_j = 1;
+        g.C = p->d_gpart; g.c_i = l; g.c_j = 1; g.c_split = m * l;
+        g.alpha = 1.0; g.ksplit = splits;
+        RT_HIP(rt::gemm_f64(g, s));
+        RT_HIP(rt::reduce_splits_f64(p->d_gpart, m * l, splits, (int)m, (int)l, l, p->d_S, l, 0, s));
+    } else {
         StageScope sc(p, 0);
         if (p->precision == RTPROJ_PREC_FP64 || sketch64)
             RT_HIP(rt::sketch_f64(p->sketch_tables(), A, lda, m, p->d_S, l, p->d_zbuf, p->rows_chunk, s));
@@ -1225,7 +1356,7 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
     // a binary32 sketch whose rank estimate shows it too coarse for this A
     // (2^-24 kappa_est above RT_SKETCH32_MAX, or numerically rank deficient)
     // is redone in binary64 before anything is built on it
-    if (lp && !sketch64 &&
+    if (lp && !sketch64 && !p->Gmat &&
         (!(std::ldexp(p->info.kappa_est, -24) <= RT_SKETCH32_MAX) ||
          !(diag[2] > (double)m * std::ldexp(1.0, -52) * diag[3]))) {
         p->resketch = true;
@@ -1250,59 +1381,116 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
             off += 2 * (size_t)cnt;
         }
     }
+    if (p->method_used == RTPROJ_METHOD_KRYLOV) {
+        // the iterative variant applies P^{-1} = R^{-T} Pi and its transpose
+        // only: T' = R^{-T} Pi and T'^T into d_Tp; no W, Gram or inverse
+        StageScope sc(p, 6);
+        RT_HIP(rt::form_tp_f64(p->d_Y, p->d_piv, (int)m, p->d_Tp, s));
+        p->w32 = false;
+        p->inv_used = 0;
+        p->info.inverse = 0;
+        p->info.inverse_iters = 0;
+        p->info.inverse_resid = 0.0;
+        p->info.w_bits = p->info.gram_bits = 0;
+        p->info.sketch_bits = (p->precision != RTPROJ_PREC_FP64 && !sketch64 && !p->Gmat) ? 32 : 64;
+        p->info.gram_cond_est = 0.0;
+        p->cond_pending = false;
+        return RTPROJ_OK;
+    }
     // 4. W = R^{-T} (Pi A), binary32 when the rank estimate allows it (or
     //    when forced by rtproj_plan_set_w_bits)
     p->w32 = lp && (p->w_bits_req == 32 || (p->w_bits_req == 0 && p->info.kappa_est <= RT_W32_KAPPA_MAX));
-    {
-        StageScope sc(p, 3);
+    // configurations of the two large contractions: built-in choices, or the
+    // autotuner's (each candidate timed once per new shape, see rt_tune.hip)
+    auto run_w = [&](int tile, int order) -> hipError_t {
         if (p->w32) {
             rt::GemmMxArgs g{};
             g.M = (int)m; g.N = (int)n; g.K = (int)m;
             g.A = p->d_Y; g.a_dbl = 1; g.a_i = m; g.a_k = 1; g.a_lower = 1;
             g.B = A; g.b_dbl = 1; g.b_k = lda; g.b_j = 1; g.b_gather = p->d_piv;
             g.C = p->d_W; g.c_dbl = 0; g.c_i = n; g.c_j = 1;
-            g.alpha = 1.f; g.ksplit = 1;
-            RT_HIP(rt::gemm_mx(g, rt::MX_F32, s));
-        } else {
-            rt::GemmArgs g{};
-            g.M = (int)m; g.N = (int)n; g.K = (int)m;
-            g.A = p->d_Y; g.a_i = m; g.a_k = 1; g.a_lower = 1;
-            g.B = A; g.b_k = lda; g.b_j = 1; g.b_gather = p->d_piv;
-            g.C = p->d_W; g.c_i = n; g.c_j = 1;
-            g.alpha = 1.0; g.ksplit = 1;
-            RT_HIP(rt::gemm_f64(g, s));
+            g.alpha = 1.f; g.ksplit = 1; g.tile = tile;
+            return rt::gemm_mx(g, rt::MX_F32, s);
         }
-    }
-    // 5. Gram X = W W^T (lower tiles, split over n, fixed-order reduction)
-    {
-        StageScope sc(p, 4);
+        rt::GemmArgs g{};
+        g.M = (int)m; g.N = (int)n; g.K = (int)m;
+        g.A = p->d_Y; g.a_i = m; g.a_k = 1; g.a_lower = 1;
+        g.B = A; g.b_k = lda; g.b_j = 1; g.b_gather = p->d_piv;
+        g.C = p->d_W; g.c_i = n; g.c_j = 1;
+        g.alpha = 1.0; g.ksplit = 1; g.tile = tile; g.order = order;
+        return rt::gemm_f64(g, s);
+    };
+    const bool bf = p->precision == RTPROJ_PREC_MIXED_BF16;
+    auto run_gram = [&](int splits, int tile) -> hipError_t {
+        hipError_t e;
         if (!lp) {
             rt::GemmArgs g{};
             g.M = (int)m; g.N = (int)m; g.K = (int)n;
             g.A = p->d_W; g.a_i = n; g.a_k = 1;
             g.B = p->d_W; g.b_k = 1; g.b_j = n;
             g.C = p->d_part; g.c_i = m; g.c_j = 1; g.c_split = m * m;
-            g.alpha = 1.0; g.c_lower = 1; g.ksplit = p->syrk_splits;
-            RT_HIP(rt::gemm_f64(g, s));
-            RT_HIP(rt::reduce_splits_f64(p->d_part, m * m, g.ksplit > 1 ? g.ksplit : 1, (int)m, (int)m, m, p->d_G, m, 1,
-                                         s));
-        } else {
-            const bool bf = p->precision == RTPROJ_PREC_MIXED_BF16;
-            const int wd = p->w32 ? 0 : 1;
-            if (bf) RT_HIP(rt::row_pow2_scale(p->d_W, wd, n, (int)m, (int)n, p->d_rowscale, s));
-            rt::GemmMxArgs g{};
-            g.M = (int)m; g.N = (int)m; g.K = (int)n;
-            g.A = p->d_W; g.a_dbl = wd; g.a_i = n; g.a_k = 1; g.a_scale = bf ? p->d_rowscale : nullptr;
-            g.B = p->d_W; g.b_dbl = wd; g.b_k = 1; g.b_j = n; g.b_scale = bf ? p->d_rowscale : nullptr;
-            g.C = p->d_part; g.c_dbl = 0; g.c_i = m; g.c_j = 1; g.c_split = m * m;
-            g.alpha = 1.f; g.c_lower = 1; g.ksplit = p->syrk_splits;
-            RT_HIP(rt::gemm_mx(g, bf ? rt::MX_BF16 : rt::MX_F32, s));
-            RT_HIP(rt::reduce_f32_splits(reinterpret_cast<const float *>(p->d_part), m * m,
-                                         g.ksplit > 1 ? g.ksplit : 1, (int)m, (int)m, m,
-                                         bf ? p->d_rowscale : nullptr, bf ? p->d_rowscale : nullptr, p->d_G, m, 1, s));
+            g.alpha = 1.0; g.c_lower = 1; g.ksplit = splits; g.tile = tile;
+            if ((e = rt::gemm_f64(g, s)) != hipSuccess) return e;
+            return rt::reduce_splits_f64(p->d_part, m * m, splits > 1 ? splits : 1, (int)m, (int)m, m, p->d_G, m, 1, s);
         }
+        const int wd = p->w32 ? 0 : 1;
+        if (bf && (e = rt::row_pow2_scale(p->d_W, wd, n, (int)m, (int)n, p->d_rowscale, s)) != hipSuccess) return e;
+        rt::GemmMxArgs g{};
+        g.M = (int)m; g.N = (int)m; g.K = (int)n;
+        g.A = p->d_W; g.a_dbl = wd; g.a_i = n; g.a_k = 1; g.a_scale = bf ? p->d_rowscale : nullptr;
+        g.B = p->d_W; g.b_dbl = wd; g.b_k = 1; g.b_j = n; g.b_scale = bf ? p->d_rowscale : nullptr;
+        g.C = p->d_part; g.c_dbl = 0; g.c_i = m; g.c_j = 1; g.c_split = m * m;
+        g.alpha = 1.f; g.c_lower = 1; g.ksplit = splits; g.tile = tile;
+        if ((e = rt::gemm_mx(g, bf ? rt::MX_BF16 : rt::MX_F32, s)) != hipSuccess) return e;
+        return rt::reduce_f32_splits(reinterpret_cast<const float *>(p->d_part), m * m, splits > 1 ? splits : 1, (int)m,
+                                     (int)m, m, bf ? p->d_rowscale : nullptr, bf ? p->d_rowscale : nullptr, p->d_G, m,
+                                     1, s);
+    };
+    std::vector<int> wcfg = {0, 0}, gcfg = {p->syrk_splits, 0};
+    if (p->autotune) {
+        const std::string wkey = tune_key(p->w32 ? "w32" : "w64", m, n, lda == n ? 0 : 1);
+        if (!tune_lookup(wkey, wcfg)) {
+            std::vector<std::vector<int>> cands = p->w32 ? std::vector<std::vector<int>>{{64, 0}, {128, 0}}
+                                                         : std::vector<std::vector<int>>{{64, 1}, {64, 2}, {128, 1},
+                                                                                         {128, 2}};
+            int best = 0;
+            st = tune_pick(p, (int)cands.size(), [&](int c) { return run_w(cands[c][0], cands[c][1]); }, &best,
+                           nullptr);
+            if (st != RTPROJ_OK) return st;
+            wcfg = cands[best];
+            tune_store(wkey, wcfg);
+        }
+        const std::string gkey = tune_key(!lp ? "g64" : (bf ? "g16" : "g32"), m, n, 0);
+        if (!tune_lookup(gkey, gcfg)) {
+            // run W once with the chosen configuration so the Gram reads it
+            RT_HIP(run_w(wcfg[0], wcfg[1]));
+            const int smax = (int)std::max<int64_t>(1, std::min<int64_t>(64, n / 256));
+            std::vector<std::vector<int>> cands;
+            for (int sp : {p->syrk_splits / 2, p->syrk_splits, 2 * p->syrk_splits, 4 * p->syrk_splits}) {
+                if (sp < 1 || sp > std::min(smax, p->part_cap)) continue;
+                cands.push_back({sp, 0});
+                if (!lp) cands.push_back({sp, 64});
+            }
+            if (cands.empty()) cands.push_back({p->syrk_splits, 0});
+            int best = 0;
+            st = tune_pick(p, (int)cands.size(), [&](int c) { return run_gram(cands[c][0], cands[c][1]); }, &best,
+                           nullptr);
+            if (st != RTPROJ_OK) return st;
+            gcfg = cands[best];
+            tune_store(gkey, gcfg);
+        }
+        gcfg[0] = std::min(gcfg[0], p->part_cap);
     }
-    p->info.sketch_bits = (lp && !sketch64) ? 32 : 64;
+    {
+        StageScope sc(p, 3);
+        RT_HIP(run_w(wcfg[0], wcfg[1]));
+    }
+    // 5. Gram X = W W^T (lower tiles, split over n, fixed-order reduction)
+    {
+        StageScope sc(p, 4);
+        RT_HIP(run_gram(gcfg[0], gcfg[1]));
+    }
+    p->info.sketch_bits = (lp && !sketch64 && !p->Gmat) ? 32 : 64;
     p->info.w_bits = p->w32 ? 32 : 64;
     p->info.gram_bits = !lp ? 64 : (p->precision == RTPROJ_PREC_MIXED_BF16 ? 16 : 32);
     // 6-7. Y = X^{-1} (eq. inversion) and the form of M^{-1} the projections apply
@@ -1391,7 +1579,7 @@ rtproj_status rtproj_precondition(rtproj_plan p, const double *A, int64_t lda)
     // after the pivoted QR), or the Gram shows a poorly conditioned P^{-1}A,
     // sketch again in binary64 (the identity holds for any G, only the
     // conditioning matters, Lemma 2.4).
-    if (st == RTPROJ_OK && p->precision != RTPROJ_PREC_FP64 &&
+    if (st == RTPROJ_OK && p->precision != RTPROJ_PREC_FP64 && !p->Gmat &&
         (p->resketch || p->info.gram_cond_est > RT_COND_ESCALATE)) {
         p->info.sketch_escalated = p->resketch ? 1 : 2;
         p->resketch = false;

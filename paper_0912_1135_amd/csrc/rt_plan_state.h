@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -183,6 +184,15 @@ struct rtproj_plan_s {
     int method = RTPROJ_METHOD_RANDOMIZED;  // requested (rtproj_method)
     int method_used = RTPROJ_METHOD_RANDOMIZED;  // of the last precondition
     double *d_V = nullptr, *d_tau = nullptr;  // classical scheme: reflectors of the QR of A A^T
+    bool autotune = false;         // time candidate configurations of new shapes (rt_tune.hip)
+    int part_cap = 0;              // split partials d_part holds (m x m doubles each)
+    int krylov_iters = 30;         // CG iterations per solve of the iterative method
+    double *d_kry = nullptr;       // its vectors: u, r, pp, q, w (m x kcap each) and kcap gammas
+    int64_t kry_cap = 0;
+    const double *Gmat = nullptr;  // caller's dense sketch matrix (n x l row-major), borrowed; null: SRFT
+    int64_t ldg = 0;
+    double *d_gpart = nullptr;     // split partials of S = A G
+    int64_t gpart_cap = 0;
     rtp::HostTables tab;
     // device tables
     int8_t *d_sign = nullptr;
@@ -287,6 +297,16 @@ struct RefinePlan {
 double refine_rho_model(double kappa_est, int precision, bool w32, double cond_w, double gram_k);
 RefinePlan refine_schedule(double kappa_est, int precision, bool w32, double cond_w, double gram_k, int mode,
                            int max_steps);
+// Autotuner: key of an operation and its sizes; the process-wide table of
+// chosen configurations; timing of `count` candidates on the plan's stream
+// (run(c) enqueues candidate c), index of the fastest in *best.
+std::string tune_key(const char *op, int64_t m, int64_t n, int64_t k);
+bool tune_lookup(const std::string &key, std::vector<int> &choice);
+void tune_store(const std::string &key, const std::vector<int> &choice);
+rtproj_status tune_pick(rtproj_plan p, int count, const std::function<hipError_t(int)> &run, int *best,
+                        std::vector<float> *times);
+// The schedule for a given contraction rho.
+RefinePlan refine_schedule_rho(double rho, double kappa_est, int mode, int max_steps);
 // Status of a finished refinement from its per-step norms (|d_j|^2, |x_j|^2
 // pairs, `steps` of them, the first `plain` from plain steps): RTPROJ_OK or
 // RTPROJ_ERR_NOCONV, with the contraction and error estimates.

@@ -148,3 +148,29 @@ def test_batch_member_tables_match_oracle(rt):
         for key in ["sign", "sigma", "tau", "J"]:
             assert np.array_equal(got[key], ref[key]), (i, key)
     bt.close()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_binary32_gram_matches_oracle(rt, graph):
+    """Batches with the binary32 grouped Gram (rtproj_batch_set_precision):
+    every member within 1e-10 of the oracle after the refinement."""
+    shp = members(12, 20091215, m_hi=200)
+    As = [synth.make_problem(m, n, 1e6, 300 + i) for i, (m, n) in enumerate(zip(shp.m, shp.n))]
+    Bs = [synth.make_rhs(n, k, 400 + i) for i, (n, k) in enumerate(zip(shp.n, shp.k))]
+    bt = rt.Batch(shp.m, shp.n, shp.l, 77)
+    bt.set_precision(rt.PREC_MIXED_FP32)
+    bt.set_graph(graph)
+    At = [torch.from_numpy(A).to(dev()) for A in As]
+    Bt = [torch.from_numpy(B).to(dev()) for B in Bs]
+    for _ in range(2 if graph else 1):
+        bt.precondition(At)
+        Z, Y, X = bt.project_all(Bt)
+    assert all(s == 0 for s in bt.status())
+    assert bt.member_info(0)["gram_bits"] == 32
+    for i in range(len(As)):
+        e = check_member(As[i], Bs[i], Z[i].cpu().numpy(), Y[i].cpu().numpy(), X[i].cpu().numpy())
+        assert max(e) <= TOL, (i, e)
+    with pytest.raises(rt.RtprojError) as err:
+        bt.set_precision(rt.PREC_MIXED_BF16)
+    assert err.value.status == 7
+    bt.close()

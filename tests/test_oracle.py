@@ -293,3 +293,37 @@ def test_lemma_2_4_oracle_preconditioner():
     c1, c2 = np.linalg.cond(W), np.linalg.cond(VG)
     assert abs(c1 - c2) <= 1e-6 * c2
     assert c2 < 10
+
+
+# ------------------------------------------------------ the paper's matrices
+
+@pytest.mark.parametrize("m,n,kappa", [(6, 30, 1e2), (8, 64, 1e8), (10, 50, 1e12), (16, 256, 1e6)])
+def test_block_average_is_the_projection_of_the_paper_matrix(m, n, kappa):
+    """The closed form (block averages of V b) against the oracle's refined
+    Householder route, to the final rounding, including cond(A) = 1e12."""
+    from oracle.paper_forms import block_average_projection
+    A, rp, cp = synth.make_paper_matrix(m, n, kappa, 31 + m)
+    B = synth.make_rhs(n, 2, 31 + m).T
+    Z0, P0 = block_average_projection(m, cp, B)
+    Z1, P1, X1, info = oracle.project(A, B)
+    nb = np.linalg.norm(B, axis=0)
+    assert np.max(np.linalg.norm(Z1 - Z0, axis=0) / nb) <= 1e-15
+    assert np.max(np.linalg.norm(P1 - P0, axis=0) / nb) <= 1e-15
+    sv = np.linalg.svd(A, compute_uv=False)
+    assert abs(sv[0] / sv[-1] / kappa - 1) <= 1e-3 or kappa >= 1e12
+
+
+def test_paper_matrix_has_the_stated_structure():
+    """eq. pert_lap and eq. test_mat: the circulant's entries, cond = (16 + d)/d,
+    and A a row and column permutation of n/m copies of B."""
+    m, n, kappa = 12, 48, 1e6
+    B = synth.circulant_b(m, kappa)
+    d = 16 / (kappa - 1)
+    assert B[0, 0] == 6 + d and B[0, 1] == -4 and B[0, 2] == 1 and B[0, m - 1] == -4 and B[0, m - 2] == 1
+    sv = np.linalg.svd(B, compute_uv=False)
+    assert abs(sv[0] / sv[-1] - (16 + d) / d) <= 1e-6 * kappa
+    A, rp, cp = synth.make_paper_matrix(m, n, kappa, 5)
+    assert sorted(rp.tolist()) == list(range(m)) and sorted(cp.tolist()) == list(range(n))
+    assert np.array_equal(np.sort(A, axis=None), np.sort(np.tile(B, (1, n // m)), axis=None))
+    G = synth.make_lfg_sketch(5000, 7, 3)
+    assert G.min() >= -1 and G.max() < 1 and abs(G.mean()) < 0.02 and abs(G.std() - 3 ** -0.5) < 0.01
