@@ -353,6 +353,24 @@ rtproj_status rtproj_project_all(rtproj_plan plan, const double *B, int64_t ldb,
                                  double *Z, int64_t ldz, double *Y, int64_t ldy,
                                  double *X, int64_t ldx);
 
+/*
+ * As rtproj_project_all, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the projection's workspace (for k right-hand sides) is taken
+ * from a static 64 MiB device array that the library holds on every GPU it
+ * runs on until the process ends, not from buffers the plan grows.  The
+ * call allocates nothing; the plan itself (created and preconditioned
+ * beforehand) and the caller's B and outputs are used as by
+ * rtproj_project_all.  RTPROJ_ERR_UNSUPPORTED for a plan preconditioned
+ * with RTPROJ_METHOD_KRYLOV, and when the workspace for (m, n, k) exceeds
+ * 64 MiB (about m k (5 + 2 splits) + 2 n k doubles; split
+ * the right-hand sides over several calls).  All calls on one GPU share the
+ * array and every call overwrites it: calls that overlap in time on one GPU
+ * (different streams, threads) race; order them on one stream.
+ */
+rtproj_status rtproj_project_all_noalloc(rtproj_plan plan, const double *B, int64_t ldb, int64_t k,
+                                         double *Z, int64_t ldz, double *Y, int64_t ldy, double *X, int64_t ldx);
+
 /* Enable (1, also resets the accumulated stage times) or disable (0) the
  * per-stage event timing reported in rtproj_info.t_stage_ms. */
 rtproj_status rtproj_plan_set_timing(rtproj_plan plan, int enable);

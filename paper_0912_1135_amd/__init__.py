@@ -85,6 +85,7 @@ def lib():
         L.rtproj_project_row.argtypes = [vp, vp, i64, i64, vp, i64]
         L.rtproj_lstsq.argtypes = [vp, vp, i64, i64, vp, i64]
         L.rtproj_project_all.argtypes = [vp, vp, i64, i64, vp, i64, vp, i64, vp, i64]
+        L.rtproj_project_all_noalloc.argtypes = [vp, vp, i64, i64, vp, i64, vp, i64, vp, i64]
         L.rtproj_plan_info.argtypes = [vp, ctypes.POINTER(_Info)]
         L.rtproj_plan_set_timing.argtypes = [vp, ip]
         L.rtproj_plan_export.argtypes = [vp, vp, i64, vp, vp, vp]
@@ -119,6 +120,7 @@ def lib():
                      "rtproj_plan_set_autotune", "rtproj_autotune_save", "rtproj_autotune_load",
                      "rtproj_precondition",
                      "rtproj_project_null", "rtproj_project_row", "rtproj_lstsq", "rtproj_project_all",
+                     "rtproj_project_all_noalloc",
                      "rtproj_plan_info", "rtproj_plan_export", "rtproj_sketch_tables",
                      "rtproj_plan_set_timing", "rtproj_batch_create", "rtproj_batch_destroy",
                      "rtproj_batch_set_stream", "rtproj_batch_set_refinement", "rtproj_batch_set_graph",
@@ -284,6 +286,19 @@ class Plan:
                                         _ptr(Z), Z.stride(0) if Z is not None else 0,
                                         _ptr(Y), Y.stride(0) if Y is not None else 0,
                                         _ptr(X), X.stride(0) if X is not None else 0))
+        return Z, Y, X
+
+    def project_all_noalloc(self, B, Z, Y, X):
+        """rtproj_project_all_noalloc: as project_all with caller-given outputs
+        (None to skip one), the workspace from the library's static array."""
+        k = self._rhs(B)
+        for t, name, rows, cols in ((Z, "Z", k, self.n), (Y, "Y", k, self.n), (X, "X", k, self.m)):
+            if t is not None:
+                _check_tensor(t, name, rows, cols, B.device)
+        _check(lib().rtproj_project_all_noalloc(self.handle, _ptr(B), B.stride(0), k,
+                                                _ptr(Z), Z.stride(0) if Z is not None else 0,
+                                                _ptr(Y), Y.stride(0) if Y is not None else 0,
+                                                _ptr(X), X.stride(0) if X is not None else 0))
         return Z, Y, X
 
     def set_timing(self, enable: bool):

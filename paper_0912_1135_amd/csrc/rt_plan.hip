@@ -1053,6 +1053,12 @@ rtproj_status rtproj_plan_create(int64_t m, int64_t n, int64_t l, uint64_t seed,
     }
     p->cu_count = prop.multiProcessorCount;
     p->lds_max = prop.sharedMemPerBlock;
+    // set-up of the static projection workspace on this device (once per device)
+    if (resolve_static_workspace(p->device) != RTPROJ_OK) {
+        const std::string msg = g_last_error;
+        delete p;
+        return fail(RTPROJ_ERR_DEVICE, msg);
+    }
     draw_tables(seed, n, l, p->tab);
     rtproj_status st = upload_tables(p);
     if (st == RTPROJ_OK) st = alloc_state(p);

@@ -283,6 +283,9 @@ rtproj_status ensure_k(rtproj_plan p, int64_t k);
 // pointers (the body of rtproj_project_all).
 rtproj_status project(rtproj_plan p, const double *B, int64_t ldb, int64_t k, double *Z, int64_t ldz, double *Y,
                       int64_t ldy, double *X, int64_t ldx);
+// Device address of the library's static projection workspace on the
+// current device, resolved once per device (at plan creation).
+rtproj_status resolve_static_workspace(int device);
 // A refinement schedule (see rtproj_plan_set_refinement): `plain` steps with
 // binary64 residuals, then `comp` steps whose contraction s = A r (and, with
 // comp_r, the residual r = b - A^T x) is compensated; the final A^T x is
