@@ -120,8 +120,13 @@ typedef enum {
     RTPROJ_RESID_PLAIN = 1,    /* every residual in plain binary64              */
     RTPROJ_RESID_S_ONLY = 2,   /* r and the final A^T x plain, s = A r
                                   compensated in the compensated steps          */
-    RTPROJ_RESID_FULL = 3      /* r, s and the final A^T x compensated in the
-                                  compensated steps (x kept double-binary64)    */
+    RTPROJ_RESID_FULL = 3      /* r and s compensated in the compensated steps
+                                  (x kept double-binary64); the final
+                                  z = b - A^T x is the last compensated r minus
+                                  A^T d for that step's correction d, a plain
+                                  product (|d| is the error left in x before
+                                  it); the iterative variant recomputes
+                                  A^T x compensated                            */
 } rtproj_residual;
 
 /* Method of a plan.  Both return the same x, A^* x and b - A^* x in exact
@@ -175,7 +180,8 @@ typedef struct {
      * 9 refinement residual b - A^T x, 10 refinement product A r,
      * 11 final A^T x and b - A^T x, 12 the small factor R0 of the two-stage
      * pivoted QR; 9, 10 and 11 count the compensated passes, and the plain
-     * binary64 ones are 13 (residual), 14 (product A r) and 15 (final). */
+     * binary64 ones are 13 (residual), 14 (product A r) and 15 (final,
+     * including the final pass formed from the last compensated residual). */
     double t_stage_ms[16];
     int64_t stage_calls[16];
     int qr_mode;               /* rtproj_qr_mode used by the last precondition       */
@@ -308,8 +314,9 @@ rtproj_status rtproj_plan_set_inverse(rtproj_plan plan, int method);
  * steps while the
  * error is above that floor, then, unless the floor itself is below the goal
  * 1e-11, compensated steps until rho^s times the error is <= 1e-11.  In
- * RTPROJ_RESID_AUTO the compensated steps compensate r and s and the final
- * A^T x is compensated whenever a compensated step ran.  An explicit
+ * RTPROJ_RESID_AUTO the compensated steps compensate r and s, and after
+ * them the final projections come from the last compensated residual as in
+ * RTPROJ_RESID_FULL.  An explicit
  * max_steps runs that many compensated steps (plain ones in
  * RTPROJ_RESID_PLAIN).
  */

@@ -598,6 +598,29 @@ __global__ void sub_cols_kernel(const double *B, int64_t ldb, const double *C, i
     out[(int64_t)j * ldo + i] = v;
 }
 
+// Outputs from a final null projection r: Y = B - r and Z = r, each
+// optional.  One thread reads B and r at an index before it writes there, so
+// Y or Z may be B itself.
+__device__ __forceinline__ void finish_cols_body(const FinishGroupArgs &g, int64_t e)
+{
+    if (e >= (int64_t)g.rows * g.cols) return;
+    const int j = (int)(e / g.rows), i = (int)(e % g.rows);
+    const double r = g.r[(int64_t)j * g.ldr + i];
+    const double y = g.Y ? g.B[(int64_t)j * g.ldb + i] - r : 0.0;
+    if (g.Y) g.Y[(int64_t)j * g.ldy + i] = y;
+    if (g.Z) g.Z[(int64_t)j * g.ldz + i] = r;
+}
+
+__global__ void finish_cols_kernel(FinishGroupArgs g)
+{
+    finish_cols_body(g, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ void finish_cols_grouped(const FinishGroupArgs *gs)
+{
+    finish_cols_body(gs[blockIdx.y], (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 __global__ void copy_cols_grouped(const CopyGroupArgs *gs)
 {
     const CopyGroupArgs g = gs[blockIdx.y];
@@ -776,6 +799,21 @@ hipError_t dd_update_grouped_f64(const DdGroupArgs *d, int count, hipStream_t st
 {
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(dd_update_grouped, dim3(count), dim3(256), 0, stream, d);
+    return hipGetLastError();
+}
+
+hipError_t finish_cols_f64(const FinishGroupArgs &g, hipStream_t stream)
+{
+    const int64_t total = (int64_t)g.rows * g.cols;
+    if (total == 0 || (!g.Y && !g.Z)) return hipSuccess;
+    hipLaunchKernelGGL(finish_cols_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, g);
+    return hipGetLastError();
+}
+
+hipError_t finish_cols_grouped_f64(const FinishGroupArgs *d, int count, int64_t max_total, hipStream_t stream)
+{
+    if (count <= 0 || max_total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(finish_cols_grouped, dim3((unsigned)((max_total + 255) / 256), count), dim3(256), 0, stream, d);
     return hipGetLastError();
 }
 

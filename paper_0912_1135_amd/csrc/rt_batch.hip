@@ -24,7 +24,7 @@ namespace {
 
 enum OpKind {
     OP_GEMM, OP_REDUCE, OP_SKETCH, OP_COPY, OP_SET0, OP_SET1, OP_SHIFT, OP_CHOL, OP_TRIINV, OP_QRCPWG, OP_RDIAG,
-    OP_FORMTP, OP_ZERO, OP_AB, OP_ABRED, OP_ATX, OP_DDUPD, OP_IOTA, OP_SCALE, OP_GEMM32, OP_RED32
+    OP_FORMTP, OP_ZERO, OP_AB, OP_ABRED, OP_ATX, OP_DDUPD, OP_IOTA, OP_SCALE, OP_GEMM32, OP_RED32, OP_FINISH
 };
 
 struct Op {
@@ -75,7 +75,7 @@ struct rtproj_batch_s {
     int precision = RTPROJ_PREC_FP64;  // the preconditioner's Gram: binary64 or binary32 (MIXED_FP32)
     int prec_used = RTPROJ_PREC_FP64;  // of the last precondition
     int plain_steps = 0, comp_steps = 2;  // schedule of the last projection
-    bool comp_final = true;               // its final A^T x compensated
+    bool comp_final = true;               // its final pass after compensated steps
     int last_steps = 0, last_plain = 0;   // steps of the last projection (norms recorded)
     std::vector<int64_t> last_k;          // right-hand sides per member in it
     int use_graph = 0;
@@ -604,8 +604,50 @@ void build_project(Program &P, rtproj_batch b, const double *const *A, const int
         }
         P.push(Op{OP_DDUPD, P.add(u), (int)cnt});
     }
+    const bool from_r = nsteps > 0 && b->comp_final && nsteps - 1 >= b->plain_steps;
+    if (from_r) {
+        // the last step was compensated: its residual r = b - A^T x_prev is in
+        // d_r and its correction d in d_d, so z = r - A^T d with a plain
+        // product (|d| is the error of x_prev), Y = B - z, Z = z
+        P.stage = 15;
+        if (*std::max_element(kk.begin(), kk.end()) < RT_MFMA_KMIN) {
+            std::vector<rt::AtxGroupArgs> a(cnt);
+            for (int64_t i = 0; i < cnt; ++i) {
+                rtproj_plan p = b->sub[i];
+                a[i] = rt::AtxGroupArgs{rt::ApplyArgs{(int)p->m, (int)p->n, (int)kk[i], A[i], lda[i]}, p->d_d, nullptr,
+                                        p->m, p->d_r, p->n, p->d_r, p->n, nullptr, 0, nullptr, 0};
+            }
+            rec_atx(P, b, a, 0);
+        } else {
+            std::vector<rt::GemmArgs> g(cnt);
+            for (int64_t i = 0; i < cnt; ++i) {
+                rtproj_plan p = b->sub[i];
+                rt::GemmArgs &q = g[i];
+                q.M = (int)p->n; q.N = (int)kk[i]; q.K = (int)p->m;
+                q.A = A[i]; q.a_i = 1; q.a_k = lda[i];
+                q.B = p->d_d; q.b_k = 1; q.b_j = p->m;
+                q.C = p->d_r; q.c_i = 1; q.c_j = p->n;
+                q.alpha = -1.0; q.beta = 1.0; q.ksplit = 1;
+                if (kk[i] == 0) q.M = 0;
+            }
+            rec_gemm(P, g);
+        }
+        std::vector<rt::FinishGroupArgs> f(cnt);
+        int64_t tot = 0;
+        for (int64_t i = 0; i < cnt; ++i) {
+            rtproj_plan p = b->sub[i];
+            double *yi = Y ? Y[i] : nullptr, *zi = Z ? Z[i] : nullptr;
+            f[i] = rt::FinishGroupArgs{p->d_r, p->n, B[i], ldb[i], yi, yi ? ldy[i] : 0, zi, zi ? ldz[i] : 0,
+                                       (int)p->n, (int)kk[i]};
+            if (!yi && !zi) f[i].cols = 0;
+            tot = std::max(tot, (int64_t)f[i].rows * f[i].cols);
+        }
+        Op o{OP_FINISH, P.add(f), (int)cnt};
+        o.total = tot;
+        P.push(o);
+    }
     P.stage = 11;
-    {
+    if (!from_r) {
         std::vector<rt::AtxGroupArgs> a(cnt);
         for (int64_t i = 0; i < cnt; ++i) {
             rtproj_plan p = b->sub[i];
@@ -665,6 +707,7 @@ hipError_t run_op(const Op &o, const unsigned char *arena, hipStream_t s)
     case OP_SCALE: return rt::scale_cols_grouped_f64((const rt::ScaleGroupArgs *)d, o.count, s);
     case OP_GEMM32: return rt::gemm_f32_grouped_lower((const rt::GemmMxArgs *)d, o.count, o.i0, o.i1, s);
     case OP_RED32: return rt::reduce_f32_grouped((const rt::ReduceF32GroupArgs *)d, o.count, o.i0, s);
+    case OP_FINISH: return rt::finish_cols_grouped_f64((const rt::FinishGroupArgs *)d, o.count, o.total, s);
     }
     return hipErrorInvalidValue;
 }

@@ -225,6 +225,17 @@ hipError_t chol_diag_f64(const double *X, int64_t ldx, int m, int nb, int b, dou
 // Set a row-major m x n matrix to the identity (or zero if ident = 0).
 // grouped forms of the factor kernels (one problem per blockIdx.y or .x)
 struct CholGroupArgs { const double *X; int64_t ldx; int m; double *L; int64_t ldl; double *Dinv; int *err; };
+// Cholesky G = L L^T of a row-major m x m SPD matrix in one cooperative
+// launch (64 x 64 tiles owned by blocks, flags between tasks).  G's lower
+// triangle is read and overwritten by the trailing updates; L's lower
+// triangle is written (the caller clears the rest); Dinv gets the inverses of
+// L's 64 x 64 diagonal blocks (identity-padded past m).  flags: nb + nb (nb +
+// 1) / 2 words (nb = ceil(m / 64)) that hold no value equal to epoch before
+// the call.  *err: 1 a pivot not positive and finite, 3 a wait timed out.
+struct CholCoopArgs { double *G; int64_t ldg; int m; double *L; int64_t ldl; double *Dinv; int *err; unsigned *flags; unsigned epoch; };
+// Blocks for the cooperative Cholesky on this device (0: not available).
+int chol_coop_blocks(int m, int device);
+hipError_t chol_coop_f64(const CholCoopArgs &a, int blocks, hipStream_t stream);
 hipError_t chol_diag_grouped_f64(const CholGroupArgs *d, int count, int nb, int b, hipStream_t stream);
 struct TriInvGroupArgs { const double *T; int64_t t_i, t_j; int m; double *Dinv; };
 hipError_t tri_diag_inv_grouped_f64(const TriInvGroupArgs *d, int count, int max_m, int nb, hipStream_t stream);
@@ -320,6 +331,10 @@ struct ScaleGroupArgs { const double *A; int64_t lda; const double *d; double *o
 // out = A diag(d) per problem (column scaling)
 hipError_t scale_cols_grouped_f64(const ScaleGroupArgs *d, int count, hipStream_t stream);
 struct CopyGroupArgs { const double *src; int64_t lds; double *dst; int64_t ldd; int rows, cols; double *zero_out; int64_t ldz; };
+// Y = B - r and Z = r (column-major rows x cols; Y or Z null to skip; either may be B)
+struct FinishGroupArgs { const double *r; int64_t ldr; const double *B; int64_t ldb; double *Y; int64_t ldy; double *Z; int64_t ldz; int rows, cols; };
+hipError_t finish_cols_f64(const FinishGroupArgs &g, hipStream_t stream);
+hipError_t finish_cols_grouped_f64(const FinishGroupArgs *d, int count, int64_t max_total, hipStream_t stream);
 hipError_t copy_cols_grouped_f64(const CopyGroupArgs *d, int count, int64_t max_total, hipStream_t stream);
 
 // (Xhi, Xlo) += D (double-binary64 update); norms[0] = |D|_F^2, norms[1] = |Xhi|_F^2.

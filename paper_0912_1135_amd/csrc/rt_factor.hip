@@ -3,6 +3,8 @@
 // so that every off-diagonal step is an MFMA GEMM), the Cholesky of one
 // diagonal block of the Gram (the factorization that replaces the explicit
 // inverse Y = X^{-1} of eq. inversion), and helpers.
+#include <algorithm>
+
 #include "rt_common.h"
 
 namespace rt {
@@ -403,6 +405,335 @@ __global__ __launch_bounds__(256) void sum_blocks_sqrt_kernel(const double *bsum
     if (threadIdx.x == 0) out[0] = __builtin_sqrt(red[0]);
 }
 
+// ------------------------------------------------------------------------
+// Blocked right-looking Cholesky G = L L^T in one cooperative launch.
+//
+// The lower triangle of 64 x 64 tiles is numbered column by column,
+// t(i, j) = j nb - j (j - 1) / 2 + (i - j), and block b owns the tiles with
+// t = b mod (grid size) for the whole factorization, visiting them in that
+// order at every step k:
+//   diagonal (k, k): factor it (one wave), X = L_kk^{-1} (the block), write
+//     L_kk, publish X as Dinv[k] and raise the step's diagonal flag;
+//   panel (i, k), i > k: wait for the diagonal flag, L_ik = A_ik X^T on
+//     MFMA, publish L_ik and raise the tile's panel flag;
+//   update (i, j), k < j <= i: wait for the panel flags of (i, k) and (j, k),
+//     A_ij -= L_ik L_jk^T on MFMA.
+// Every tile of G is read and written only by its owner, so a tile's own
+// updates are ordinary accesses; data one block hands to another (X and the
+// panels) is written and read with device-scope accesses, coherent across the
+// XCDs' L2s, and its flag is raised only after those stores have completed.
+// The tasks of step k wait only on tasks of step k that come first in this
+// order or on earlier steps, and the launch is cooperative (all blocks
+// resident), so every wait ends; a wait that spins too long records an error
+// and the block goes on, so the grid always drains.  Flags hold the call's
+// epoch: a flag is raised when it equals the epoch, so no clearing is needed
+// between calls with increasing epochs.
+constexpr int CC_T = 256;
+constexpr int CC_MAXOWN = 64;  // tiles per block at most
+constexpr long CC_SPIN_LIMIT = 1L << 20;
+
+__device__ __forceinline__ void cc_store(double *p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double cc_load(const double *p)
+{
+    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void cc_wait_stores()
+{
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+__device__ __forceinline__ int cc_tile(int i, int j, int nb) { return j * nb - j * (j - 1) / 2 + (i - j); }
+
+// Tile transfers: thread t moves elements (r, c) = (t / 64 + 4 s, t % 64) for
+// s = 0..15 of a 64 x 64 tile.  Every load is issued unconditionally from a
+// clamped address and zeroed by a select, so that all sixteen of a thread's
+// loads are in flight at once (a masked load becomes a branch that waits for
+// it).  Rows r >= nr read as zero.
+constexpr int CC_E = NBMAX * NBMAX / CC_T;
+
+__device__ __forceinline__ void cc_tile_to_lds(const double *src, int64_t ld, int nr, bool coherent, double *dst)
+{
+    const int c = threadIdx.x & 63, rb = threadIdx.x >> 6;
+    double v[CC_E];
+#pragma unroll
+    for (int s = 0; s < CC_E; ++s) {
+        const int r = rb + 4 * s;
+        const double *q = src + (int64_t)min(r, nr - 1) * ld + c;
+        v[s] = coherent ? cc_load(q) : *q;
+    }
+#pragma unroll
+    for (int s = 0; s < CC_E; ++s) {
+        const int r = rb + 4 * s;
+        dst[r * LDP + c] = r < nr ? v[s] : 0.0;
+    }
+}
+
+// Thread 0 waits until both flags hold the epoch (b may equal a).  A wait
+// that spins too long sets *err = 3, and every wait gives up as soon as it
+// sees that value, so after one timeout the grid drains quickly.  Then the
+// block is released.
+__device__ __forceinline__ void cc_wait(const unsigned *fa, const unsigned *fb, unsigned epoch, int *err)
+{
+    if (threadIdx.x == 0) {
+        long spins = 0;
+        while (__hip_atomic_load(const_cast<unsigned *>(fa), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch ||
+               __hip_atomic_load(const_cast<unsigned *>(fb), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+            __builtin_amdgcn_s_sleep(1);
+            ++spins;
+            if (spins > CC_SPIN_LIMIT) {
+                __hip_atomic_store(err, 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            if ((spins & 255) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 3) break;
+        }
+    }
+    __syncthreads();
+}
+
+// All stores of the block have completed; then thread 0 raises the flag.
+__device__ __forceinline__ void cc_raise(unsigned *f, unsigned epoch)
+{
+    cc_wait_stores();
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(f, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// acc = P Q^T for 64 x 64 P, Q in LDS (row stride LDP); wave w holds the
+// 32 x 32 quadrant (w / 2, w % 2) as 2 x 2 MFMA tiles.
+__device__ __forceinline__ void cc_pqt(const double *P, const double *Q, double4v (&acc)[2][2])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wm = wave >> 1, wn = wave & 1;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = double4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int kk = 0; kk < NBMAX; kk += 4) {
+        double av[2], bv[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) av[a] = P[(wm * 32 + a * 16 + (lane & 15)) * LDP + kk + (lane >> 4)];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) bv[b] = Q[(wn * 32 + b * 16 + (lane & 15)) * LDP + kk + (lane >> 4)];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+}
+
+// Row and column of element r of the accumulator (a, b) in this lane.
+__device__ __forceinline__ int cc_row(int a, int r)
+{
+    return ((threadIdx.x >> 6) >> 1) * 32 + a * 16 + mfma16_row(threadIdx.x & 63, r);
+}
+__device__ __forceinline__ int cc_col(int b) { return ((threadIdx.x >> 6) & 1) * 32 + b * 16 + mfma16_col(threadIdx.x & 63); }
+
+// Cholesky of the 64 x 64 lower triangle in T (LDS) in place by the block's
+// four waves: lane i of wave w keeps row i, columns 16 w .. 16 w + 15, in
+// registers.  At step j the wave owning column j takes the pivot from its
+// lane j, forms column j of L and publishes it in pub[j & 1]; after one block
+// barrier every wave updates its columns c > j with L[i][j] L[c][j] (sixteen
+// broadcast reads and sixteen FMAs a lane).  The strict upper triangle is
+// zeroed.  Returns, in every thread, whether a pivot was not positive and
+// finite.
+__device__ __forceinline__ bool cc_chol64(double *T, double (*pub)[NBMAX], int *s_bad)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double a[16];
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) a[cc] = T[lane * LDP + 16 * w + cc];
+    if (threadIdx.x == 0) *s_bad = 0;
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < NBMAX; ++j) {
+        if (w == (j >> 4)) {
+            const double d = lane_value(a[j & 15], j);
+            bad |= !(d > 0.0 && d < INFINITY);
+            const double ljj = __builtin_sqrt(d);
+            const double lij = (lane == j) ? ljj : (lane > j ? a[j & 15] / ljj : 0.0);
+            a[j & 15] = lij;
+            pub[j & 1][lane] = lij;
+        }
+        __syncthreads();
+        // waves past column j's wave update all their columns; its own wave
+        // the columns after j (a compile-time range); earlier waves none
+        if (w > (j >> 4)) {
+            const double li = pub[j & 1][lane];
+#pragma unroll
+            for (int cc = 0; cc < 16; ++cc) a[cc] = __builtin_fma(-li, pub[j & 1][16 * w + cc], a[cc]);
+        } else if (w == (j >> 4)) {
+            const double li = pub[j & 1][lane];
+#pragma unroll
+            for (int cc = (j & 15) + 1; cc < 16; ++cc) a[cc] = __builtin_fma(-li, pub[j & 1][16 * w + cc], a[cc]);
+        }
+    }
+    if (bad) *s_bad = 1;
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) {
+        const int c = 16 * w + cc;
+        T[lane * LDP + c] = c <= lane ? a[cc] : 0.0;
+    }
+    __syncthreads();
+    return *s_bad != 0;
+}
+
+// X = L^{-1} (lower, 64 x 64, LDS row stride LDP, strict upper triangle
+// zero; X may not alias L) by the block: thread t solves column j = t / 4 of
+// L X = I together with the three other lanes of its quad, lane q keeping the
+// entries of rows 4 s + q in registers.  Row i: each lane sums L[i][c] x[c]
+// over its rows c, two shuffles add the quad's four parts, and the lane of
+// row i keeps x[i] = (delta_ij - sum) / L[i][i].  Rows c >= i still hold
+// x[c] = 0 and meet L[i][c] = 0 above the diagonal, so their terms are exact
+// zeros and the sum needs no mask.  Fully unrolled, so the reads of L are
+// issued ahead of the sums.
+__device__ __forceinline__ void cc_lower_inverse(const double *L, double *X, double *invd)
+{
+    const int j = threadIdx.x >> 2, q = threadIdx.x & 3;
+    if (threadIdx.x < NBMAX) invd[threadIdx.x] = 1.0 / L[threadIdx.x * LDP + threadIdx.x];
+    __syncthreads();
+    double xr[16];
+#pragma unroll
+    for (int s2 = 0; s2 < 16; ++s2) xr[s2] = 0.0;
+#pragma unroll
+    for (int i = 0; i < NBMAX; ++i) {
+        double sq = 0.0;
+#pragma unroll
+        for (int s2 = 0; s2 < 16; ++s2) {
+            if (4 * s2 >= i) break;  // rows 4 s2 + q >= i contribute nothing
+            sq = __builtin_fma(L[i * LDP + 4 * s2 + q], xr[s2], sq);
+        }
+        sq += __shfl_xor(sq, 1, 64);
+        sq += __shfl_xor(sq, 2, 64);
+        const double xi = ((i == j ? 1.0 : 0.0) - sq) * invd[i];
+        xr[i >> 2] = (q == (i & 3)) ? xi : xr[i >> 2];
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < 16; ++s2) X[(4 * s2 + q) * LDP + j] = xr[s2];
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(CC_T) void chol_coop_kernel(CholCoopArgs g)
+{
+    static_assert(CC_T == 4 * NBMAX, "four waves; a quad of lanes per column of the inverse");
+    __shared__ double P[NBMAX * LDP];
+    __shared__ double Q[NBMAX * LDP];
+    __shared__ double pub[2][NBMAX];
+    __shared__ double invd[NBMAX];
+    __shared__ short own_i[CC_MAXOWN], own_j[CC_MAXOWN];
+    __shared__ int s_nown, s_bad;
+    const int m = g.m, nb = (m + NBMAX - 1) / NBMAX, ntiles = nb * (nb + 1) / 2;
+    const int B = gridDim.x;
+    unsigned *dflag = g.flags, *pflag = g.flags + nb;
+    if (threadIdx.x == 0) {
+        int n = 0, j = 0, start = 0;
+        for (int t = blockIdx.x; t < ntiles && n < CC_MAXOWN; t += B) {
+            while (start + (nb - j) <= t) { start += nb - j; ++j; }
+            own_j[n] = (short)j;
+            own_i[n] = (short)(j + (t - start));
+            ++n;
+        }
+        s_nown = n;
+    }
+    __syncthreads();
+    const int nown = s_nown;
+    const int tid = threadIdx.x;
+    for (int k = 0; k < nb; ++k) {
+        for (int q = 0; q < nown; ++q) {
+            const int i = own_i[q], j = own_j[q];
+            if (j < k) continue;
+            const int r0 = i * NBMAX, c0 = j * NBMAX;
+            const int nr = min(NBMAX, m - r0), nc = min(NBMAX, m - c0);
+            __syncthreads();  // the previous task's LDS reads are done
+            if (j == k && i == k) {
+                // diagonal: factor, invert, publish
+                {
+                    const int c = tid & 63, rb = tid >> 6;
+                    double v[CC_E];
+#pragma unroll
+                    for (int s2 = 0; s2 < CC_E; ++s2) {
+                        const int r = rb + 4 * s2;
+                        v[s2] = g.G[(int64_t)(r0 + min(r, nr - 1)) * g.ldg + r0 + min(c, nr - 1)];
+                    }
+#pragma unroll
+                    for (int s2 = 0; s2 < CC_E; ++s2) {
+                        const int r = rb + 4 * s2;
+                        P[r * LDP + c] = (r < nr && c < nr) ? (c <= r ? v[s2] : 0.0) : (r == c ? 1.0 : 0.0);
+                    }
+                }
+                __syncthreads();
+                if (cc_chol64(P, pub, &s_bad) && tid == 0)
+                    __hip_atomic_store(g.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                cc_lower_inverse(P, Q, invd);
+                double *X = g.Dinv + (int64_t)k * NBMAX * NBMAX;
+                {
+                    const int c = tid & 63, rb = tid >> 6;
+#pragma unroll
+                    for (int s2 = 0; s2 < CC_E; ++s2) {
+                        const int r = rb + 4 * s2;
+                        cc_store(X + r * NBMAX + c, Q[r * LDP + c]);
+                        if (r < nr && c < nr && c <= r) g.L[(int64_t)(r0 + r) * g.ldl + r0 + c] = P[r * LDP + c];
+                    }
+                }
+                cc_raise(dflag + k, g.epoch);
+            } else if (j == k) {
+                // panel: L_ik = A_ik X^T
+                cc_wait(dflag + k, dflag + k, g.epoch, g.err);
+                cc_tile_to_lds(g.Dinv + (int64_t)k * NBMAX * NBMAX, NBMAX, NBMAX, true, Q);
+                cc_tile_to_lds(g.G + (int64_t)r0 * g.ldg + c0, g.ldg, nr, false, P);  // nc = 64: k < nb - 1
+                __syncthreads();
+                double4v acc[2][2];
+                cc_pqt(P, Q, acc);
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int rr = cc_row(a, r), cc = cc_col(b);
+                            if (rr < nr && cc < nc) cc_store(g.L + (int64_t)(r0 + rr) * g.ldl + c0 + cc, acc[a][b][r]);
+                        }
+                cc_raise(pflag + cc_tile(i, k, nb), g.epoch);
+            } else {
+                // update: A_ij -= L_ik L_jk^T
+                cc_wait(pflag + cc_tile(i, k, nb), pflag + cc_tile(j, k, nb), g.epoch, g.err);
+                const int k0 = k * NBMAX;  // column block k is full: k < j <= nb - 1
+                cc_tile_to_lds(g.L + (int64_t)r0 * g.ldl + k0, g.ldl, nr, true, P);
+                cc_tile_to_lds(g.L + (int64_t)c0 * g.ldl + k0, g.ldl, nc, true, Q);
+                __syncthreads();
+                // this block's own tile of G: straight-line loads (clamped),
+                // then the product, then the masked stores
+                double gv[2][2][4];
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            gv[a][b][r] = g.G[(int64_t)(r0 + min(cc_row(a, r), nr - 1)) * g.ldg + c0 +
+                                              min(cc_col(b), nc - 1)];
+                double4v acc[2][2];
+                cc_pqt(P, Q, acc);
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int rr = cc_row(a, r), cc = cc_col(b);
+                            if (rr < nr && cc < nc && (i > j || cc <= rr))
+                                g.G[(int64_t)(r0 + rr) * g.ldg + c0 + cc] = gv[a][b][r] - acc[a][b][r];
+                        }
+            }
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t form_tp_f64(const double *T, const int32_t *piv, int m, double *out, hipStream_t stream)
@@ -426,6 +757,28 @@ hipError_t chol_diag_f64(const double *X, int64_t ldx, int m, int nb, int b, dou
     if (nb != NBMAX) return hipErrorInvalidValue;
     hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(NBMAX), 0, stream, X, ldx, m, nb, b, L, ldl, Dinv, err);
     return hipGetLastError();
+}
+
+int chol_coop_blocks(int m, int device)
+{
+    const int nb = (m + NBMAX - 1) / NBMAX, ntiles = nb * (nb + 1) / 2;
+    int cus = 0, per = 0, coop = 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) != hipSuccess || !coop) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, chol_coop_kernel, CC_T, 0) != hipSuccess || per < 1) return 0;
+    const int blocks = std::min(ntiles, cus);  // one block per compute unit at most
+    if ((ntiles + blocks - 1) / blocks > CC_MAXOWN) return 0;
+    return blocks;
+}
+
+hipError_t chol_coop_f64(const CholCoopArgs &a, int blocks, hipStream_t stream)
+{
+    const int nb = (a.m + NBMAX - 1) / NBMAX, ntiles = nb * (nb + 1) / 2;
+    if (a.m <= 0) return hipSuccess;
+    if (blocks < 1 || (ntiles + blocks - 1) / blocks > CC_MAXOWN) return hipErrorInvalidValue;
+    CholCoopArgs g = a;
+    void *args[] = {(void *)&g};
+    return hipLaunchCooperativeKernel((const void *)chol_coop_kernel, dim3(blocks), dim3(CC_T), args, 0, stream);
 }
 
 hipError_t shift_diag_f64(double *G, int64_t ld, int m, double c, hipStream_t stream)

@@ -82,7 +82,7 @@ void release(rtproj_plan p)
                     p->d_twl, p->d_tw1f, p->d_tw2f, p->d_twhf, p->d_twlf, p->d_rowscale, p->d_zbuf, p->d_S, p->d_R, p->d_Y, p->d_W, p->d_part, p->d_G, p->d_L, p->d_Tp,
                     p->d_DinvR, p->d_DinvL, p->d_piv, p->d_sync, p->d_slots, p->d_vbuf, p->d_qrcols, p->d_Yq, p->d_R0, p->d_wgargs, p->d_rinv_args, p->d_scal, p->d_diag,
                     p->d_bsum, p->d_c, p->d_tmp, p->d_xhi, p->d_xlo, p->d_d, p->d_r, p->d_ph, p->d_pl, p->d_norms, p->d_xpk, p->d_bpk,
-                    p->d_err, p->d_V, p->d_tau, p->d_gpart, p->d_kry};
+                    p->d_err, p->d_V, p->d_tau, p->d_gpart, p->d_kry, p->d_cflags};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (p->h_scal) (void)hipHostFree(p->h_scal);
@@ -227,6 +227,13 @@ rtproj_status alloc_state(rtproj_plan p)
     RT_HIP(dalloc(&p->d_diag, 8));
     RT_HIP(dalloc(&p->d_err, 4));
     RT_HIP(dalloc(&p->d_rowscale, (size_t)m));
+    p->chol_blocks = rt::chol_coop_blocks((int)m, p->device);
+    if (p->chol_blocks > 0) {
+        const int64_t nflags = nblk + nblk * (nblk + 1) / 2;
+        RT_HIP(dalloc(&p->d_cflags, (size_t)nflags));
+        RT_HIP(rt::zero_u32(p->d_cflags, (int)nflags, p->stream));
+        RT_HIP(hipStreamSynchronize(p->stream));  // cleared before any stream the caller sets uses them
+    }
     // recursive-doubling inverse of R^T: level s joins pairs of inverted
     // diagonal blocks of size S = NB 2^s: for the pair at rows/cols c0..c0+S
     // (X11) and r0 = c0 + S .. r0 + s2 (X22), T = L21 X11 goes to d_L's block
@@ -349,11 +356,21 @@ rtproj_status trsm_lower(rtproj_plan p, const double *Lp, int64_t l_i, int64_t l
 // Blocked right-looking Cholesky G = L L^T of the m x m matrix G (row-major,
 // lower part read and overwritten by the trailing updates) into L; Dinv gets
 // the inverses of L's diagonal blocks.  A failed pivot is flagged in d_err.
+// One cooperative launch where the device allows it, else one launch per
+// diagonal block, panel and trailing update.
 rtproj_status cholesky(rtproj_plan p, double *G, double *L, double *Dinv)
 {
     const int64_t m = p->m;
     const int64_t nblk = (m + NB - 1) / NB;
     RT_HIP(rt::set_matrix_f64(L, m, (int)m, (int)m, 0, p->stream));
+    if (p->chol_blocks > 0) {
+        // one cooperative launch; flags hold the call's epoch (never 0, the
+        // value they were cleared to)
+        if (++p->chol_epoch == 0) ++p->chol_epoch;
+        rt::CholCoopArgs a{G, m, (int)m, L, m, Dinv, p->d_err, p->d_cflags, p->chol_epoch};
+        RT_HIP(rt::chol_coop_f64(a, p->chol_blocks, p->stream));
+        return RTPROJ_OK;
+    }
     for (int64_t b = 0; b < nblk; ++b) {
         const int64_t r0 = b * NB, nbb = std::min<int64_t>(NB, m - r0);
         RT_HIP(rt::chol_diag_f64(G, m, (int)m, NB, (int)b, L, m, Dinv, p->d_err, p->stream));
@@ -879,6 +896,33 @@ hipError_t final_plain(rtproj_plan p, const double *B, int64_t ldb, int64_t k, d
     return Z ? rt::sub_cols_f64(B, ldb, Y, ldy, Z, ldz, (int)n, (int)k, s) : hipSuccess;
 }
 
+// Final projections after a compensated last step.  That step left the
+// residual r = b - A^T x_prev (compensated, rounded once) in d_r and its
+// correction d in d_d, with x = x_prev + d; then z = b - A^T x = r - A^T d.
+// The plain binary64 product A^T d errs by about u |A^T| |d|, and |d| is the
+// error of x_prev, so z keeps the accuracy of the compensated residual
+// without a second compensated pass over A.  Y = B - z.  d_r ends holding z.
+hipError_t final_from_residual(rtproj_plan p, const double *B, int64_t ldb, int64_t k, double *Z, int64_t ldz,
+                               double *Y, int64_t ldy, hipStream_t s)
+{
+    const int64_t m = p->m, n = p->n;
+    hipError_t e;
+    if (k < RT_MFMA_KMIN) {
+        rt::ApplyArgs a{(int)m, (int)n, (int)k, p->A, p->lda};
+        e = rt::atx_f64(a, p->d_d, nullptr, m, p->d_r, n, nullptr, 0, nullptr, 0, p->d_r, n, 0, s);
+    } else {
+        rt::GemmArgs g{};
+        g.M = (int)n; g.N = (int)k; g.K = (int)m;
+        g.A = p->A; g.a_i = 1; g.a_k = p->lda;
+        g.B = p->d_d; g.b_k = 1; g.b_j = m;
+        g.C = p->d_r; g.c_i = 1; g.c_j = n;
+        g.alpha = -1.0; g.beta = 1.0; g.ksplit = 1;
+        e = rt::gemm_f64(g, s);
+    }
+    if (e != hipSuccess) return e;
+    return rt::finish_cols_f64(rt::FinishGroupArgs{p->d_r, n, B, ldb, Y, ldy, Z, ldz, (int)n, (int)k}, s);
+}
+
 rtproj_status project(rtproj_plan p, const double *B, int64_t ldb, int64_t k, double *Z, int64_t ldz, double *Y,
                       int64_t ldy, double *X, int64_t ldx)
 {
@@ -945,11 +989,13 @@ rtproj_status project(rtproj_plan p, const double *B, int64_t ldb, int64_t k, do
     const int nplain = rp.plain, nsteps = std::min(rp.plain + rp.comp, RT_MAX_STEPS);
     int steps = 0;
     double ratio = 0.0;
+    bool last_dd_r = false;
     for (int it = 0; it < nsteps; ++it) {
         // plain binary64 residuals while the error is above their floor,
         // compensated (Dot2) ones for the last steps
         const bool comp = it >= nplain;
         const bool dd_r = comp && rp.comp_r;
+        last_dd_r = dd_r;
         {
             StageScope sc(p, dd_r ? 9 : 13);
             if (dd_r) RT_HIP(rt::atx_f64(a, p->d_xhi, p->d_xlo, m, B, ldb, p->d_r, n, nullptr, 0, nullptr, 0, 1, s,
@@ -980,10 +1026,15 @@ rtproj_status project(rtproj_plan p, const double *B, int64_t ldb, int64_t k, do
             if (ratio <= p->refine_rtol) break;
         }
     }
-    // step 7: b~ = A^T x, z = b - b~
+    // step 7: b~ = A^T x, z = b - b~; after a compensated step from that
+    // step's residual (the conjugate-gradient solves reuse d_r as scratch, so
+    // that method evaluates the final pass compensated in full)
     if (Z || Y) {
-        StageScope sc(p, steps > 0 && rp.comp_final ? 11 : 15);
-        if (steps > 0 && rp.comp_final)
+        const bool comp_final = steps > 0 && rp.comp_final;
+        const bool from_r = comp_final && last_dd_r && p->method_used != RTPROJ_METHOD_KRYLOV;
+        StageScope sc(p, comp_final && !from_r ? 11 : 15);
+        if (from_r) RT_HIP(final_from_residual(p, B, ldb, k, Z, ldz, Y, ldy, s));
+        else if (comp_final)
             RT_HIP(rt::atx_f64(a, p->d_xhi, p->d_xlo, m, B, ldb, nullptr, 0, Y, ldy, Z, ldz, 1, s, p->d_xpk));
         else RT_HIP(final_plain(p, B, ldb, k, Z, ldz, Y, ldy, s));
     }
@@ -1335,6 +1386,7 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
         int r0err = 0;
         RT_HIP(hipMemcpyAsync(&r0err, p->d_err, 4, hipMemcpyDeviceToHost, s));
         RT_HIP(hipStreamSynchronize(s));
+        if (r0err == 3) return fail(RTPROJ_ERR_DEVICE, "cooperative Cholesky: a wait timed out");
         if (r0err && mode != RTPROJ_QR_DIRECT) {
             // the Cholesky QR broke down (S^T too ill-conditioned even for the
             // shifted first pass): factor S^T directly
@@ -1547,6 +1599,7 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
     RT_HIP(hipMemcpyAsync(ldiag, p->d_diag, 32, hipMemcpyDeviceToHost, s));
     RT_HIP(hipMemcpyAsync(&cerr, p->d_err, 4, hipMemcpyDeviceToHost, s));
     RT_HIP(hipStreamSynchronize(s));
+    if (cerr == 3) return fail(RTPROJ_ERR_DEVICE, "cooperative Cholesky: a wait timed out");
     if (cerr) return fail(RTPROJ_ERR_RANK, "Cholesky of the preconditioned Gram broke down");
     // max/min of diag(L) bounds cond(P^{-1}A) from below (about 3 for a
     // healthy sketch with l = 4m, Observation 3.2)

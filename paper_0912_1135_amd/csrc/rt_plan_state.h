@@ -210,6 +210,11 @@ struct rtproj_plan_s {
     double *d_slots = nullptr, *d_vbuf = nullptr, *d_qrcols = nullptr, *d_scal = nullptr, *d_diag = nullptr;
     int *d_err = nullptr;
     float *d_rowscale = nullptr;
+    // the cooperative Cholesky: blocks on this device (0: the blocked
+    // multi-launch form), its task flags and the epoch of the last call
+    int chol_blocks = 0;
+    unsigned *d_cflags = nullptr;
+    unsigned chol_epoch = 0;
     int qr_blocks = 0;         // cooperative blocks for the l x m QRCP (direct mode)
     int qr_blocks0 = 0;        // cooperative blocks for the m x m QRCP of R0
     int qr_reg_l = 0, qr_reg_m = 0;  // blocks of the register-resident form (0: not applicable)
