@@ -69,7 +69,7 @@ extern "C" rtproj_status rtproj_project_all_noalloc(rtproj_plan p, const double 
     // point the plan's projection buffers into the static array for this call
     double *saved[ProjLayout::NBUF];
     const int64_t saved_kcap = p->kcap;
-    const int saved_ab = p->ab_splits, saved_sx = p->ab_sx_splits;
+    const int saved_ab = p->ab_splits, saved_sx = p->ab_sx_splits, saved_mma = p->ab_mma_splits;
     unsigned char *cur = static_cast<unsigned char *>(base);
     for (int i = 0; i < ProjLayout::NBUF; ++i) {
         double **b = proj_buffers(p, i);
@@ -80,10 +80,12 @@ extern "C" rtproj_status rtproj_project_all_noalloc(rtproj_plan p, const double 
     p->kcap = k;
     p->ab_splits = L.ab_splits;
     p->ab_sx_splits = L.ab_sx_splits;
+    p->ab_mma_splits = L.ab_mma_splits;
     const rtproj_status st = project(p, B, ldb, k, Z, ldz, Y, ldy, X, ldx);
     for (int i = 0; i < ProjLayout::NBUF; ++i) *proj_buffers(p, i) = saved[i];
     p->kcap = saved_kcap;
     p->ab_splits = saved_ab;
     p->ab_sx_splits = saved_sx;
+    p->ab_mma_splits = saved_mma;
     return st;
 }

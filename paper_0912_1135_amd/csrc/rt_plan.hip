@@ -71,6 +71,72 @@ void collect_timing(rtproj_plan p)
     p->pending.clear();
 }
 
+// Argument blocks of the recursive-doubling inverse X = L^{-1} of the m x m
+// lower-triangular L read as L(i, j) = Lp[i l_i + j l_j], X and the scratch T
+// row-major m x m: level s joins pairs of inverted diagonal blocks of size
+// S = NB 2^s; for the pair at rows/cols c0 .. c0 + S (X11) and r0 = c0 + S ..
+// r0 + s2 (X22), T = L21 X11 goes to T's block (r0, c0), then X21 = -X22 T
+// to the same block of X (the inverse of [L11 0; L21 L22] is
+// [X11 0; -X22 L21 X11 X22]).
+hipError_t build_tri_inverse(int64_t m, const double *Lp, int64_t l_i, int64_t l_j, double *X, double *T,
+                             TriInverse &out)
+{
+    std::vector<rt::GemmArgs> all;
+    out.count.clear();
+    out.shape1.clear();
+    out.shape2.clear();
+    for (int64_t S = NB; S < m; S *= 2) {
+        std::vector<rt::GemmArgs> g1, g2;
+        for (int64_t c0 = 0; c0 + S < m; c0 += 2 * S) {
+            const int64_t r0 = c0 + S, s1 = S, s2 = std::min<int64_t>(S, m - r0);
+            rt::GemmArgs a{};
+            a.M = (int)s2; a.N = (int)s1; a.K = (int)s1;
+            a.A = Lp + r0 * l_i + c0 * l_j; a.a_i = l_i; a.a_k = l_j;
+            a.B = X + c0 * m + c0; a.b_k = m; a.b_j = 1;
+            a.C = T + r0 * m + c0; a.c_i = m; a.c_j = 1;
+            a.alpha = 1.0; a.ksplit = 1;
+            g1.push_back(a);
+            rt::GemmArgs b{};
+            b.M = (int)s2; b.N = (int)s1; b.K = (int)s2;
+            b.A = X + r0 * m + r0; b.a_i = m; b.a_k = 1;
+            b.B = T + r0 * m + c0; b.b_k = m; b.b_j = 1;
+            b.C = X + r0 * m + c0; b.c_i = m; b.c_j = 1;
+            b.alpha = -1.0; b.ksplit = 1;
+            g2.push_back(b);
+        }
+        rt::GemmShape h1{}, h2{};
+        h1.M = h2.M = (int)S; h1.N = h2.N = (int)S; h1.ksplit = h2.ksplit = 1;
+        h1.a_kc = l_j == 1 ? 1 : 0; h1.b_kc = 0; h2.a_kc = 1; h2.b_kc = 0;
+        out.count.push_back((int)g1.size());
+        out.shape1.push_back(h1);
+        out.shape2.push_back(h2);
+        all.insert(all.end(), g1.begin(), g1.end());
+        all.insert(all.end(), g2.begin(), g2.end());
+    }
+    if (all.empty()) return hipSuccess;
+    hipError_t e = hipMalloc(&out.d_args, all.size() * sizeof(rt::GemmArgs));
+    if (e != hipSuccess) return e;
+    return hipMemcpy(out.d_args, all.data(), all.size() * sizeof(rt::GemmArgs), hipMemcpyHostToDevice);
+}
+
+// X = L^{-1} from the inverted diagonal blocks Dinv (placed into a cleared X)
+// and the levels of t, on the plan's stream.
+hipError_t run_tri_inverse(rtproj_plan p, const TriInverse &t, const double *Dinv, double *X)
+{
+    const int64_t m = p->m;
+    hipStream_t s = p->stream;
+    hipError_t e = rt::set_matrix_f64(X, m, (int)m, (int)m, 0, s);
+    if (e == hipSuccess) e = rt::place_diag_blocks_f64(Dinv, (int)m, NB, X, m, s);
+    size_t off = 0;
+    for (size_t lv = 0; lv < t.count.size() && e == hipSuccess; ++lv) {
+        const int cnt = t.count[lv];
+        e = rt::gemm_f64_grouped(t.d_args + off, cnt, t.shape1[lv], s);
+        if (e == hipSuccess) e = rt::gemm_f64_grouped(t.d_args + off + cnt, cnt, t.shape2[lv], s);
+        off += 2 * (size_t)cnt;
+    }
+    return e;
+}
+
 void release(rtproj_plan p)
 {
     for (auto &e : p->pending) {
@@ -80,7 +146,7 @@ void release(rtproj_plan p)
     p->pending.clear();
     void *bufs[] = {p->d_sign, p->d_sigma, p->d_tauinv, p->d_sel_off, p->d_sel, p->d_tw1, p->d_tw2, p->d_twh,
                     p->d_twl, p->d_tw1f, p->d_tw2f, p->d_twhf, p->d_twlf, p->d_rowscale, p->d_zbuf, p->d_S, p->d_R, p->d_Y, p->d_W, p->d_part, p->d_G, p->d_L, p->d_Tp,
-                    p->d_DinvR, p->d_DinvL, p->d_piv, p->d_sync, p->d_slots, p->d_vbuf, p->d_qrcols, p->d_Yq, p->d_R0, p->d_wgargs, p->d_rinv_args, p->d_scal, p->d_diag,
+                    p->d_DinvR, p->d_DinvL, p->d_piv, p->d_sync, p->d_slots, p->d_vbuf, p->d_qrcols, p->d_Yq, p->d_R0, p->d_wgargs, p->rinv.d_args, p->linv[0].d_args, p->linv[1].d_args, p->d_Linv, p->d_Yq2, p->d_scal, p->d_diag,
                     p->d_bsum, p->d_c, p->d_tmp, p->d_xhi, p->d_xlo, p->d_d, p->d_r, p->d_ph, p->d_pl, p->d_norms, p->d_xpk, p->d_bpk,
                     p->d_err, p->d_V, p->d_tau, p->d_gpart, p->d_kry, p->d_cflags};
     for (void *b : bufs)
@@ -234,46 +300,15 @@ rtproj_status alloc_state(rtproj_plan p)
         RT_HIP(rt::zero_u32(p->d_cflags, (int)nflags, p->stream));
         RT_HIP(hipStreamSynchronize(p->stream));  // cleared before any stream the caller sets uses them
     }
-    // recursive-doubling inverse of R^T: level s joins pairs of inverted
-    // diagonal blocks of size S = NB 2^s: for the pair at rows/cols c0..c0+S
-    // (X11) and r0 = c0 + S .. r0 + s2 (X22), T = L21 X11 goes to d_L's block
-    // (r0, c0), then X21 = -X22 T to the same block of d_Y.  L = R^T, read as
-    // L(i, j) = R[j m + i].
-    {
-        std::vector<rt::GemmArgs> all;
-        for (int64_t S = NB; S < m; S *= 2) {
-            std::vector<rt::GemmArgs> g1, g2;
-            for (int64_t c0 = 0; c0 + S < m; c0 += 2 * S) {
-                const int64_t r0 = c0 + S, s1 = S, s2 = std::min<int64_t>(S, m - r0);
-                rt::GemmArgs a{};
-                a.M = (int)s2; a.N = (int)s1; a.K = (int)s1;
-                a.A = p->d_R + c0 * m + r0; a.a_i = 1; a.a_k = m;
-                a.B = p->d_Y + c0 * m + c0; a.b_k = m; a.b_j = 1;
-                a.C = p->d_L + r0 * m + c0; a.c_i = m; a.c_j = 1;
-                a.alpha = 1.0; a.ksplit = 1;
-                g1.push_back(a);
-                rt::GemmArgs b{};
-                b.M = (int)s2; b.N = (int)s1; b.K = (int)s2;
-                b.A = p->d_Y + r0 * m + r0; b.a_i = m; b.a_k = 1;
-                b.B = p->d_L + r0 * m + c0; b.b_k = m; b.b_j = 1;
-                b.C = p->d_Y + r0 * m + c0; b.c_i = m; b.c_j = 1;
-                b.alpha = -1.0; b.ksplit = 1;
-                g2.push_back(b);
-            }
-            rt::GemmShape h1{}, h2{};
-            h1.M = h2.M = (int)S; h1.N = h2.N = (int)S; h1.ksplit = h2.ksplit = 1;
-            h1.a_kc = 0; h1.b_kc = 0; h2.a_kc = 1; h2.b_kc = 0;
-            p->rinv_count.push_back((int)g1.size());
-            p->rinv_shape1.push_back(h1);
-            p->rinv_shape2.push_back(h2);
-            all.insert(all.end(), g1.begin(), g1.end());
-            all.insert(all.end(), g2.begin(), g2.end());
-        }
-        if (!all.empty()) {
-            RT_HIP(hipMalloc(&p->d_rinv_args, all.size() * sizeof(rt::GemmArgs)));
-            RT_HIP(hipMemcpy(p->d_rinv_args, all.data(), all.size() * sizeof(rt::GemmArgs), hipMemcpyHostToDevice));
-        }
-    }
+    // recursive-doubling inverses: R^{-T} (L = R^T, read as L(i, j) =
+    // R[j m + i]) into d_Y with d_L as scratch; for the two-stage QR the
+    // inverses of the first two Cholesky factors (in d_L and d_Y, row-major)
+    // into d_Linv with d_G as scratch
+    RT_HIP(build_tri_inverse(m, p->d_R, 1, m, p->d_Y, p->d_L, p->rinv));
+    RT_HIP(dalloc(&p->d_Linv, (size_t)m * m));
+    RT_HIP(dalloc(&p->d_Yq2, (size_t)m * l));
+    RT_HIP(build_tri_inverse(m, p->d_L, m, 1, p->d_Linv, p->d_G, p->linv[0]));
+    RT_HIP(build_tri_inverse(m, p->d_Y, m, 1, p->d_Linv, p->d_G, p->linv[1]));
     return RTPROJ_OK;
 }
 
@@ -283,7 +318,12 @@ ProjLayout proj_layout(int64_t m, int64_t n, int64_t k, int cu_count)
     const int64_t rb = (m + 31) / 32, kb = (k + 31) / 32;  // row blocks x right-hand-side blocks of the A B pass
     L.ab_splits = (int)std::max<int64_t>(1, std::min<int64_t>(n / 256, (4 * cu_count + rb * kb - 1) / (rb * kb)));
     L.ab_sx_splits = rt::ab_sx_splits(m, n, k, cu_count);
-    const int64_t psplits = std::max<int64_t>(L.ab_splits, L.ab_sx_splits);
+    // the MFMA GEMM form: about four 64 x 64 tile blocks per compute unit, so
+    // that resident blocks hide each other's load latency (one block per
+    // unit leaves the two-chunk load ring exposed)
+    const int64_t tiles = ((m + 63) / 64) * ((k + 63) / 64);
+    L.ab_mma_splits = (int)std::max<int64_t>(1, std::min<int64_t>({64, n / 256, (4 * cu_count + tiles - 1) / tiles}));
+    const int64_t psplits = std::max<int64_t>({(int64_t)L.ab_splits, (int64_t)L.ab_sx_splits, (int64_t)L.ab_mma_splits});
     // c, tmp, xhi, xlo, d (m k each), r (n k), ph, pl (split partials), bpk, norms, xpk
     const int64_t cnt[ProjLayout::NBUF] = {m * k, m * k, m * k, m * k, m * k, n * k, psplits * m * k,
                                            psplits * m * k, rt::ab_pack_size(n, k), 2 * RT_MAX_STEPS,
@@ -317,39 +357,9 @@ rtproj_status ensure_k(rtproj_plan p, int64_t k)
     const ProjLayout L = proj_layout(p->m, p->n, k, p->cu_count);
     p->ab_splits = L.ab_splits;
     p->ab_sx_splits = L.ab_sx_splits;
+    p->ab_mma_splits = L.ab_mma_splits;
     for (int i = 0; i < ProjLayout::NBUF; ++i) RT_HIP(dalloc(proj_buffers(p, i), (size_t)L.count[i]));
     p->kcap = k;
-    return RTPROJ_OK;
-}
-
-// In-place blocked forward substitution L X = B for the m x m lower-triangular
-// L(i,j) = Lp[i*l_i + j*l_j] with inverted diagonal blocks Dinv; B (row-major
-// m x ncols, ld ldb) is overwritten by X.  rhs_lower: B is lower triangular
-// (then so is X, and the columns right of each block stay zero).
-rtproj_status trsm_lower(rtproj_plan p, const double *Lp, int64_t l_i, int64_t l_j, const double *Dinv, double *B,
-                         int64_t ldb, int64_t m, int64_t ncols, bool rhs_lower)
-{
-    const int64_t nblk = (m + NB - 1) / NB;
-    for (int64_t b = 0; b < nblk; ++b) {
-        const int64_t r0 = b * NB, nbb = std::min<int64_t>(NB, m - r0);
-        const int64_t cols = rhs_lower ? std::min<int64_t>(ncols, r0 + nbb) : ncols;
-        rt::GemmArgs g{};
-        g.M = (int)nbb; g.N = (int)cols; g.K = (int)nbb;
-        g.A = Dinv + b * NB * NB; g.a_i = NB; g.a_k = 1;
-        g.B = B + r0 * ldb; g.b_k = ldb; g.b_j = 1;
-        g.C = B + r0 * ldb; g.c_i = ldb; g.c_j = 1;
-        g.alpha = 1.0; g.beta = 0.0; g.ksplit = 1;
-        RT_HIP(rt::gemm_f64(g, p->stream));
-        const int64_t rest = m - r0 - nbb;
-        if (rest <= 0) continue;
-        rt::GemmArgs u{};
-        u.M = (int)rest; u.N = (int)cols; u.K = (int)nbb;
-        u.A = Lp + (r0 + nbb) * l_i + r0 * l_j; u.a_i = l_i; u.a_k = l_j;
-        u.B = B + r0 * ldb; u.b_k = ldb; u.b_j = 1;
-        u.C = B + (r0 + nbb) * ldb; u.c_i = ldb; u.c_j = 1;
-        u.alpha = -1.0; u.beta = 1.0; u.ksplit = 1;
-        RT_HIP(rt::gemm_f64(u, p->stream));
-    }
     return RTPROJ_OK;
 }
 
@@ -524,16 +534,27 @@ rtproj_status r0_factor(rtproj_plan p)
 {
     const int64_t m = p->m, l = p->l;
     hipStream_t s = p->stream;
-    RT_HIP(hipMemcpyAsync(p->d_Yq, p->d_S, (size_t)m * l * sizeof(double), hipMemcpyDeviceToDevice, s));
     const double shift = 11.0 * ((double)l * (double)m + (double)m * (double)(m + 1)) * std::ldexp(1.0, -53);
     double *Ls[3] = {p->d_L, p->d_Y, p->d_Tp};  // free until the preconditioner's own factors
+    // iterates: S, then L1^{-1} S in d_Yq, then L2^{-1} L1^{-1} S in d_Yq2
+    const double *Yin[3] = {p->d_S, p->d_Yq, p->d_Yq2};
     rtproj_status st;
     for (int it = 0; it < 3; ++it) {
-        if ((st = gram_f64(p, p->d_Yq, l, l, p->d_G)) != RTPROJ_OK) return st;
+        if ((st = gram_f64(p, Yin[it], l, l, p->d_G)) != RTPROJ_OK) return st;
         if (it == 0) RT_HIP(rt::shift_diag_f64(p->d_G, m, (int)m, shift, s));
         if ((st = cholesky(p, p->d_G, Ls[it], p->d_DinvL)) != RTPROJ_OK) return st;
-        if (it < 2 && (st = trsm_lower(p, Ls[it], m, 1, p->d_DinvL, p->d_Yq, l, m, l, false)) != RTPROJ_OK)
-            return st;
+        if (it < 2) {
+            // next iterate L^{-1} Y: the explicit inverse (its diagonal blocks
+            // come from the Cholesky), then one triangular MFMA product
+            RT_HIP(run_tri_inverse(p, p->linv[it], p->d_DinvL, p->d_Linv));
+            rt::GemmArgs g{};
+            g.M = (int)m; g.N = (int)l; g.K = (int)m;
+            g.A = p->d_Linv; g.a_i = m; g.a_k = 1; g.a_lower = 1;
+            g.B = Yin[it]; g.b_k = l; g.b_j = 1;
+            g.C = const_cast<double *>(Yin[it + 1]); g.c_i = l; g.c_j = 1;
+            g.alpha = 1.0; g.ksplit = 1;
+            RT_HIP(rt::gemm_f64(g, s));
+        }
     }
     // R0^T = (L1 L2) L3, products of lower-triangular factors
     for (int pass = 0; pass < 2; ++pass) {
@@ -759,9 +780,10 @@ hipError_t ab_plain(rtproj_plan p, const double *B, int64_t ldb, int64_t k, hipS
     g.A = p->A; g.a_i = p->lda; g.a_k = 1;
     g.B = B; g.b_k = 1; g.b_j = ldb;
     g.C = p->d_ph; g.c_i = 1; g.c_j = m; g.c_split = m * k;
-    g.alpha = 1.0; g.ksplit = p->ab_splits;
+    g.alpha = 1.0; g.ksplit = p->ab_mma_splits;
     hipError_t e = rt::gemm_f64(g, s);
-    return e != hipSuccess ? e : rt::reduce_splits_f64(p->d_ph, m * k, p->ab_splits, (int)k, (int)m, m, p->d_c, m, 0, s);
+    return e != hipSuccess ? e
+                           : rt::reduce_splits_f64(p->d_ph, m * k, p->ab_mma_splits, (int)k, (int)m, m, p->d_c, m, 0, s);
 }
 
 // d_r (n x k) = B - A^T x_hi in plain binary64 (refinement steps above the
@@ -1429,15 +1451,7 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
     {
         StageScope sc(p, 2);
         RT_HIP(rt::tri_diag_inv_f64(p->d_R, 1, m, (int)m, NB, p->d_DinvR, s));
-        RT_HIP(rt::set_matrix_f64(p->d_Y, m, (int)m, (int)m, 0, s));
-        RT_HIP(rt::place_diag_blocks_f64(p->d_DinvR, (int)m, NB, p->d_Y, m, s));
-        size_t off = 0;
-        for (size_t lv = 0; lv < p->rinv_count.size(); ++lv) {
-            const int cnt = p->rinv_count[lv];
-            RT_HIP(rt::gemm_f64_grouped(p->d_rinv_args + off, cnt, p->rinv_shape1[lv], s));
-            RT_HIP(rt::gemm_f64_grouped(p->d_rinv_args + off + cnt, cnt, p->rinv_shape2[lv], s));
-            off += 2 * (size_t)cnt;
-        }
+        RT_HIP(run_tri_inverse(p, p->rinv, p->d_DinvR, p->d_Y));
     }
     if (p->method_used == RTPROJ_METHOD_KRYLOV) {
         // the iterative variant applies P^{-1} = R^{-T} Pi and its transpose
@@ -1586,11 +1600,20 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
         st = cholesky(p, p->d_G, p->d_L, p->d_DinvL);
     }
     if (st != RTPROJ_OK) return st;
-    // 7. T = L^{-1} R^{-T} (in place in d_Y), T' = T Pi
+    // 7. T = L^{-1} R^{-T}, T' = T Pi: the explicit L^{-1} (into d_Linv, its
+    //    diagonal blocks from the Cholesky, d_G as scratch), then the product
+    //    of the two lower-triangular factors into d_G
     {
         StageScope sc(p, 6);
-        st = trsm_lower(p, p->d_L, m, 1, p->d_DinvL, p->d_Y, m, m, m, true);
-        if (st == RTPROJ_OK) RT_HIP(rt::form_tp_f64(p->d_Y, p->d_piv, (int)m, p->d_Tp, s));
+        RT_HIP(run_tri_inverse(p, p->linv[0], p->d_DinvL, p->d_Linv));
+        rt::GemmArgs g{};
+        g.M = (int)m; g.N = (int)m; g.K = (int)m;
+        g.A = p->d_Linv; g.a_i = m; g.a_k = 1; g.a_lower = 1;
+        g.B = p->d_Y; g.b_k = m; g.b_j = 1;
+        g.C = p->d_G; g.c_i = m; g.c_j = 1;
+        g.alpha = 1.0; g.ksplit = 1;
+        RT_HIP(rt::gemm_f64(g, s));
+        RT_HIP(rt::form_tp_f64(p->d_G, p->d_piv, (int)m, p->d_Tp, s));
     }
     if (st != RTPROJ_OK) return st;
     int cerr = 0;

@@ -161,6 +161,16 @@ hipError_t dalloc(T **p, size_t count)
 
 }  // namespace rtp
 
+// Grouped products of the recursive-doubling inverse X = L^{-1} of an m x m
+// lower-triangular L (see build_tri_inverse): per level, the pairs joined and
+// the launch shapes of its two grouped products; d_args holds every level's
+// argument blocks (first products, then second products, level by level).
+struct TriInverse {
+    rt::GemmArgs *d_args = nullptr;
+    std::vector<int> count;
+    std::vector<rt::GemmShape> shape1, shape2;
+};
+
 struct rtproj_plan_s {
     int64_t m = 0, n = 0, l = 0;
     uint64_t seed = 0;
@@ -228,14 +238,16 @@ struct rtproj_plan_s {
     // R^{-T} by recursive doubling: per level, the grouped products
     // T = L21 X11 and X21 = -X22 T over all block pairs (device argument
     // arrays built at plan creation)
-    rt::GemmArgs *d_rinv_args = nullptr;
-    std::vector<int> rinv_count;                 // pairs per level
-    std::vector<rt::GemmShape> rinv_shape1, rinv_shape2;
+    TriInverse rinv;           // R^{-T} into d_Y (scratch d_L)
+    TriInverse linv[2];        // two-stage: L^{-1} of the first two Cholesky factors (d_L, d_Y) into d_Linv (scratch d_G)
+    double *d_Linv = nullptr;  // two-stage: inverse of the current Cholesky factor
+    double *d_Yq2 = nullptr;   // two-stage: the next m x l iterate of the Cholesky QR
     bool w32 = false;          // P^{-1}A held in binary32 by the last precondition
     int syrk_splits = 1;
     // projection workspace
     int64_t kcap = 0;
     int ab_splits = 1;
+    int ab_mma_splits = 1;     // K splits of the MFMA form of A B (many right-hand sides)
     double *d_c = nullptr, *d_tmp = nullptr, *d_xhi = nullptr, *d_xlo = nullptr, *d_d = nullptr, *d_r = nullptr;
     double *d_ph = nullptr, *d_pl = nullptr, *d_norms = nullptr;
     double *d_bpk = nullptr;   // right-hand sides packed for the scalar-load A B pass (ab_pack_size(n, k))
@@ -275,7 +287,7 @@ namespace rtp {
 // tmp, xhi, xlo, d, r, ph, pl, bpk, norms, xpk.
 struct ProjLayout {
     static constexpr int NBUF = 11;
-    int ab_splits = 1, ab_sx_splits = 1;
+    int ab_splits = 1, ab_sx_splits = 1, ab_mma_splits = 1;
     int64_t count[NBUF] = {};
     size_t bytes() const;  // every buffer rounded up to 256 bytes
 };
