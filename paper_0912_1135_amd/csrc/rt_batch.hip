@@ -646,8 +646,40 @@ void build_project(Program &P, rtproj_batch b, const double *const *A, const int
         o.total = tot;
         P.push(o);
     }
-    P.stage = 11;
-    if (!from_r) {
+    const bool final_comp = nsteps > 0 && b->comp_final;
+    if (!from_r && !final_comp && *std::max_element(kk.begin(), kk.end()) >= RT_MFMA_KMIN) {
+        // plain final pass with many right-hand sides on MFMA: d_r = B, then
+        // d_r -= A^T x_hi (grouped GEMM), then Y = B - d_r and Z = d_r
+        P.stage = 15;
+        std::vector<rt::CopyGroupArgs> cp(cnt);
+        std::vector<rt::GemmArgs> g(cnt);
+        std::vector<rt::FinishGroupArgs> f(cnt);
+        int64_t tot = 0;
+        for (int64_t i = 0; i < cnt; ++i) {
+            rtproj_plan p = b->sub[i];
+            cp[i] = rt::CopyGroupArgs{B[i], ldb[i], p->d_r, p->n, (int)p->n, (int)kk[i], nullptr, 0};
+            rt::GemmArgs &q = g[i];
+            q.M = (int)p->n; q.N = (int)kk[i]; q.K = (int)p->m;
+            q.A = A[i]; q.a_i = 1; q.a_k = lda[i];
+            q.B = p->d_xhi; q.b_k = 1; q.b_j = p->m;
+            q.C = p->d_r; q.c_i = 1; q.c_j = p->n;
+            q.alpha = -1.0; q.beta = 1.0; q.ksplit = 1;
+            if (kk[i] == 0) q.M = 0;
+            double *yi = Y ? Y[i] : nullptr, *zi = Z ? Z[i] : nullptr;
+            f[i] = rt::FinishGroupArgs{p->d_r, p->n, B[i], ldb[i], yi, yi ? ldy[i] : 0, zi, zi ? ldz[i] : 0,
+                                       (int)p->n, (int)kk[i]};
+            if (!yi && !zi) { f[i].cols = 0; cp[i].cols = 0; q.M = 0; }
+            tot = std::max(tot, p->n * kk[i]);
+        }
+        Op oc{OP_COPY, P.add(cp), (int)cnt};
+        oc.total = tot;
+        P.push(oc);
+        rec_gemm(P, g);
+        Op of{OP_FINISH, P.add(f), (int)cnt};
+        of.total = tot;
+        P.push(of);
+    } else if (!from_r) {
+        P.stage = 11;
         std::vector<rt::AtxGroupArgs> a(cnt);
         for (int64_t i = 0; i < cnt; ++i) {
             rtproj_plan p = b->sub[i];
@@ -656,8 +688,9 @@ void build_project(Program &P, rtproj_batch b, const double *const *A, const int
                                     Z ? Z[i] : nullptr, Z ? ldz[i] : 0};
             if (!(Y && Y[i]) && !(Z && Z[i])) a[i].a.k = 0;
         }
-        rec_atx(P, b, a, nsteps > 0 && b->comp_final ? 1 : 0);
+        rec_atx(P, b, a, final_comp ? 1 : 0);
     }
+    P.stage = 11;
     if (X) {
         std::vector<rt::CopyGroupArgs> cp(cnt);
         int64_t tot = 0;

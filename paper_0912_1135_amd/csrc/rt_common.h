@@ -62,7 +62,9 @@ struct GemmArgs {
     int a_lower, c_lower, ksplit;
     int small_tiles;  // 1: 64 x 64 tiles whatever M, N (more blocks for small products)
     int tile;         // 0: chosen from the shape; 64 or 128 forces the square tile size
+    int tile_n;       // with tile: 0 square; 128 (tile 64) or 64 (tile 128) for a 64 x 128 or 128 x 64 tile
     int order;        // 0: tile order chosen from the shape; 1 plain; 2 XCD-grouped
+    int c_f32;        // 1: C is binary32 (each result rounded once; beta must be 0, no K split)
 };
 
 // Launches GEMM with 64x64 or 128x128 tiles (chosen from M, N unless

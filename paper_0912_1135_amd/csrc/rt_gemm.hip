@@ -205,10 +205,15 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmArgs &g, int bx, int by,
                 const int i = i0 + wm * (BM / 2) + a * 16 + mfma16_row(lane, r);
                 const int j = j0 + wn * (BN / 2) + b * 16 + mfma16_col(lane);
                 if (i < g.M && j < g.N) {
-                    double *p = C + (int64_t)i * g.c_i + (int64_t)j * g.c_j;
-                    double v = g.alpha * acc[a][b][r];
-                    if (use_beta) v += g.beta * *p;
-                    *p = v;
+                    const int64_t off = (int64_t)i * g.c_i + (int64_t)j * g.c_j;
+                    if (g.c_f32) {
+                        reinterpret_cast<float *>(g.C)[off] = (float)(g.alpha * acc[a][b][r]);
+                    } else {
+                        double *p = C + off;
+                        double v = g.alpha * acc[a][b][r];
+                        if (use_beta) v += g.beta * *p;
+                        *p = v;
+                    }
                 }
             }
 }
@@ -524,6 +529,9 @@ hipError_t sq_mm_f64(int m, const double *A, const double *B, double *out, doubl
 hipError_t gemm_f64(const GemmArgs &g, hipStream_t stream)
 {
     if (g.M <= 0 || g.N <= 0) return hipSuccess;
+    if (g.c_f32 && (g.beta != 0.0 || g.ksplit > 1)) return hipErrorInvalidValue;
+    if (g.tile == 64 && g.tile_n == 128) return launch_tile<64, 128>(g, stream);
+    if (g.tile == 128 && g.tile_n == 64) return launch_tile<128, 64>(g, stream);
     if (g.tile == 128) return launch_tile<128, 128>(g, stream);
     if (g.tile == 64) return launch_tile<64, 64>(g, stream);
     // triangular A (P^{-1}A): 64-row tiles measured faster than 128-row ones

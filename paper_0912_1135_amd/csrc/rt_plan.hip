@@ -1474,7 +1474,7 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
     p->w32 = lp && (p->w_bits_req == 32 || (p->w_bits_req == 0 && p->info.kappa_est <= RT_W32_KAPPA_MAX));
     // configurations of the two large contractions: built-in choices, or the
     // autotuner's (each candidate timed once per new shape, see rt_tune.hip)
-    auto run_w = [&](int tile, int order) -> hipError_t {
+    auto run_w = [&](int tile, int order, int tile_n) -> hipError_t {
         if (p->w32) {
             rt::GemmMxArgs g{};
             g.M = (int)m; g.N = (int)n; g.K = (int)m;
@@ -1484,12 +1484,14 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
             g.alpha = 1.f; g.ksplit = 1; g.tile = tile;
             return rt::gemm_mx(g, rt::MX_F32, s);
         }
+        // binary64 products; with a binary32 or bfloat16 Gram, which rounds
+        // its inputs to binary32 first, stored as binary32 already
         rt::GemmArgs g{};
         g.M = (int)m; g.N = (int)n; g.K = (int)m;
         g.A = p->d_Y; g.a_i = m; g.a_k = 1; g.a_lower = 1;
         g.B = A; g.b_k = lda; g.b_j = 1; g.b_gather = p->d_piv;
-        g.C = p->d_W; g.c_i = n; g.c_j = 1;
-        g.alpha = 1.0; g.ksplit = 1; g.tile = tile; g.order = order;
+        g.C = p->d_W; g.c_i = n; g.c_j = 1; g.c_f32 = lp ? 1 : 0;
+        g.alpha = 1.0; g.ksplit = 1; g.tile = tile; g.tile_n = tile_n; g.order = order;
         return rt::gemm_f64(g, s);
     };
     const bool bf = p->precision == RTPROJ_PREC_MIXED_BF16;
@@ -1505,7 +1507,7 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
             if ((e = rt::gemm_f64(g, s)) != hipSuccess) return e;
             return rt::reduce_splits_f64(p->d_part, m * m, splits > 1 ? splits : 1, (int)m, (int)m, m, p->d_G, m, 1, s);
         }
-        const int wd = p->w32 ? 0 : 1;
+        const int wd = 0;  // W is binary32 in the mixed forms (either product)
         if (bf && (e = rt::row_pow2_scale(p->d_W, wd, n, (int)m, (int)n, p->d_rowscale, s)) != hipSuccess) return e;
         rt::GemmMxArgs g{};
         g.M = (int)m; g.N = (int)m; g.K = (int)n;
@@ -1518,16 +1520,19 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
                                      (int)m, m, bf ? p->d_rowscale : nullptr, bf ? p->d_rowscale : nullptr, p->d_G, m,
                                      1, s);
     };
-    std::vector<int> wcfg = {0, 0}, gcfg = {p->syrk_splits, 0};
+    std::vector<int> wcfg = {0, 0, 0}, gcfg = {p->syrk_splits, 0};
     if (p->autotune) {
         const std::string wkey = tune_key(p->w32 ? "w32" : "w64", m, n, lda == n ? 0 : 1);
         if (!tune_lookup(wkey, wcfg)) {
-            std::vector<std::vector<int>> cands = p->w32 ? std::vector<std::vector<int>>{{64, 0}, {128, 0}}
-                                                         : std::vector<std::vector<int>>{{64, 1}, {64, 2}, {128, 1},
-                                                                                         {128, 2}};
+            // (tile, order, tile_n): square and rectangular binary64 tiles in
+            // both tile orders
+            std::vector<std::vector<int>> cands =
+                p->w32 ? std::vector<std::vector<int>>{{64, 0, 0}, {128, 0, 0}}
+                       : std::vector<std::vector<int>>{{64, 1, 0},  {64, 2, 0},  {128, 1, 0},  {128, 2, 0},
+                                                       {64, 1, 128}, {64, 2, 128}, {128, 1, 64}, {128, 2, 64}};
             int best = 0;
-            st = tune_pick(p, (int)cands.size(), [&](int c) { return run_w(cands[c][0], cands[c][1]); }, &best,
-                           nullptr);
+            st = tune_pick(p, (int)cands.size(), [&](int c) { return run_w(cands[c][0], cands[c][1], cands[c][2]); },
+                           &best, nullptr);
             if (st != RTPROJ_OK) return st;
             wcfg = cands[best];
             tune_store(wkey, wcfg);
@@ -1535,7 +1540,7 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
         const std::string gkey = tune_key(!lp ? "g64" : (bf ? "g16" : "g32"), m, n, 0);
         if (!tune_lookup(gkey, gcfg)) {
             // run W once with the chosen configuration so the Gram reads it
-            RT_HIP(run_w(wcfg[0], wcfg[1]));
+            RT_HIP(run_w(wcfg[0], wcfg[1], wcfg.size() > 2 ? wcfg[2] : 0));
             const int smax = (int)std::max<int64_t>(1, std::min<int64_t>(64, n / 256));
             std::vector<std::vector<int>> cands;
             for (int sp : {p->syrk_splits / 2, p->syrk_splits, 2 * p->syrk_splits, 4 * p->syrk_splits}) {
@@ -1555,7 +1560,7 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
     }
     {
         StageScope sc(p, 3);
-        RT_HIP(run_w(wcfg[0], wcfg[1]));
+        RT_HIP(run_w(wcfg[0], wcfg[1], wcfg.size() > 2 ? wcfg[2] : 0));
     }
     // 5. Gram X = W W^T (lower tiles, split over n, fixed-order reduction)
     {
