@@ -129,6 +129,23 @@ typedef enum {
                                   A^T x compensated                            */
 } rtproj_residual;
 
+/* Arithmetic of the compensated products r = b - A^T x and s = A r inside
+ * the compensated refinement steps (Remark 4.3).  Both evaluate the same
+ * quantities to well beyond binary64; the integer form is exact on the digit
+ * grid it keeps: every dot product is taken on one power-of-two scale per
+ * row of the operand and per right-hand side, its operands are split into
+ * 13 signed 6-bit digits, the digit products are summed exactly in int32 on
+ * the int8 matrix cores, and the pairs of digit positions s + t <= 14 are
+ * combined in double-binary64 (omitted terms below about 2^-62 of the
+ * largest term's scale at 2048 terms). */
+typedef enum {
+    RTPROJ_COMP_AUTO = 0,      /* the integer form from 16 right-hand sides on
+                                  (and m <= 65536), Dot2 below                 */
+    RTPROJ_COMP_DOT2 = 1,      /* Dot2 (TwoProd and TwoSum) on the vector units */
+    RTPROJ_COMP_INT8 = 2       /* exact digit products on the int8 matrix cores
+                                  (m <= 65536; else Dot2)                       */
+} rtproj_compensation;
+
 /* Method of a plan.  Both return the same x, A^* x and b - A^* x in exact
  * arithmetic; they differ in rounding (Sec. 1) and cost (Sec. 5). */
 typedef enum {
@@ -207,6 +224,8 @@ typedef struct {
     double refine_rho_model;   /* contraction per step the schedule was planned with
                                   (see rtproj_plan_set_refinement)                  */
     int method;                /* rtproj_method of the last precondition             */
+    int comp_method;           /* rtproj_compensation of the last projection's
+                                  compensated steps (0 when none ran)            */
 } rtproj_info;
 
 /*
@@ -286,6 +305,11 @@ int rtproj_autotune_entries(void);
 /* Arithmetic of the refinement residuals (rtproj_residual); default
  * RTPROJ_RESID_AUTO.  Takes effect at the next projection. */
 rtproj_status rtproj_plan_set_residual(rtproj_plan plan, int mode);
+
+/* Form of the compensated products (rtproj_compensation); default
+ * RTPROJ_COMP_AUTO.  Takes effect at the next projection (the integer form
+ * allocates its digit buffers then). */
+rtproj_status rtproj_plan_set_compensation(rtproj_plan plan, int method);
 
 /* Method of the pivoted QR of the sketch (rtproj_qr_mode).  Takes effect at
  * the next rtproj_precondition; RTPROJ_ERR_UNSUPPORTED if the mode cannot

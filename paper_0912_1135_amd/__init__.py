@@ -43,7 +43,7 @@ class _Info(ctypes.Structure):
                 ("inverse_resid", ctypes.c_double), ("refine_plain", ctypes.c_int), ("refine_comp", ctypes.c_int),
                 ("resid_mode", ctypes.c_int), ("refine_status", ctypes.c_int), ("refine_rho_est", ctypes.c_double),
                 ("refine_err_est", ctypes.c_double), ("refine_rho_model", ctypes.c_double),
-                ("method", ctypes.c_int)]
+                ("method", ctypes.c_int), ("comp_method", ctypes.c_int)]
 
 STAGES = ["sketch", "qrcp", "rinv_trsm", "w_gemm", "gram_syrk", "gram_inv", "minv_form", "ab",
           "minv", "refine_atx", "refine_ab", "final_atx", "qr_r0", "refine_atx_plain", "refine_ab_plain",
@@ -52,6 +52,7 @@ QR_AUTO, QR_DIRECT, QR_TWO_STAGE, QR_TWO_STAGE_WG = 0, 1, 2, 3
 INV_AUTO, INV_NEWTON_SCHULZ, INV_CHOLESKY = 0, 1, 2
 RESID_AUTO, RESID_PLAIN, RESID_S_ONLY, RESID_FULL = 0, 1, 2, 3
 METHOD_RANDOMIZED, METHOD_CLASSICAL, METHOD_KRYLOV = 0, 1, 2
+COMP_AUTO, COMP_DOT2, COMP_INT8 = 0, 1, 2
 
 
 def lib():
@@ -71,6 +72,7 @@ def lib():
         L.rtproj_plan_set_qr.argtypes = [vp, ip]
         L.rtproj_plan_set_inverse.argtypes = [vp, ip]
         L.rtproj_plan_set_residual.argtypes = [vp, ip]
+        L.rtproj_plan_set_compensation.argtypes = [vp, ip]
         L.rtproj_plan_set_method.argtypes = [vp, ip]
         L.rtproj_plan_set_sketch_matrix.argtypes = [vp, vp, i64]
         L.rtproj_plan_set_krylov.argtypes = [vp, ip]
@@ -115,7 +117,7 @@ def lib():
         L.rtproj_last_error.restype = ctypes.c_char_p
         for name in ["rtproj_plan_create", "rtproj_plan_destroy", "rtproj_plan_set_stream",
                      "rtproj_plan_set_precision", "rtproj_plan_set_refinement", "rtproj_plan_set_qr", "rtproj_plan_set_inverse",
-                     "rtproj_plan_set_residual", "rtproj_plan_set_w_bits", "rtproj_plan_status",
+                     "rtproj_plan_set_residual", "rtproj_plan_set_compensation", "rtproj_plan_set_w_bits", "rtproj_plan_status",
                      "rtproj_plan_set_method", "rtproj_plan_set_sketch_matrix", "rtproj_plan_set_krylov",
                      "rtproj_plan_set_autotune", "rtproj_autotune_save", "rtproj_autotune_load",
                      "rtproj_precondition",
@@ -203,6 +205,12 @@ class Plan:
     def set_residual(self, mode: int):
         """Arithmetic of the refinement residuals (RESID_AUTO, RESID_PLAIN, RESID_S_ONLY, RESID_FULL)."""
         _check(lib().rtproj_plan_set_residual(self.handle, mode))
+
+    def set_compensation(self, method: int):
+        """Form of the compensated products of the refinement: COMP_AUTO (the
+        int8 matrix cores from 16 right-hand sides on), COMP_DOT2 (vector
+        units) or COMP_INT8 (exact digit products on the int8 matrix cores)."""
+        _check(lib().rtproj_plan_set_compensation(self.handle, method))
 
     def set_method(self, method: int):
         """METHOD_RANDOMIZED (default), METHOD_CLASSICAL (eq. basic_identity

@@ -139,6 +139,37 @@ hipError_t reduce_f32_splits(const float *part, int64_t stride, int splits, int 
 hipError_t row_pow2_scale(const void *W, int is_dbl, int64_t ldw, int m, int n, float *scale, hipStream_t stream);
 hipError_t to_f32(const double *src, int64_t lds, float *dst, int64_t ldd, int m, int64_t n, hipStream_t stream);
 
+// ---------------------------------------------------------------- exact int8 products
+// Compensated residual products on the int8 matrix cores (digit splitting, see
+// rt_ozaki.hip).  OZ_S signed 6-bit digits per operand, digit pairs with
+// s + t <= OZ_D kept, at most OZ_KMAX terms per int32 partial sum.
+constexpr int OZ_D = 14;
+constexpr int OZ_S = OZ_D - 1;
+constexpr int64_t OZ_KMAX = 65536;
+struct OzArgs {
+    int R, K, k;               // A-operand rows, reduction length, right-hand sides
+    const double *A; int64_t lda;
+    const int *rowexp;         // exponent per A-operand row (columns of A for A^T x, rows for A r)
+    const int8_t *dig;         // right-hand-side digits dig[(t kpad + c) Kpad + kk]
+    int kpad; int64_t Kpad;    // right-hand sides and K padded to multiples of 64
+    const int *bexp;           // exponent per right-hand side
+    int64_t kchunk;            // K per split (multiple of 64, at most OZ_KMAX)
+    const double *B; int64_t ldb; double *Rout; int64_t ldr;  // A^T x: Rout = B - A^T x
+    double *ph, *pl;           // A r: double-binary64 partials [split][c][row]
+};
+// Splits of K for the A r product and the K per split.
+int oz_splits(int64_t K, int64_t tiles, int cu_count);
+int64_t oz_kchunk(int64_t K, int splits);
+// colexp[j] (n) and rowexp[i] (m): exponents e with |A_ij| < 2^e over A's
+// columns and rows (INT_MIN for an all-zero one).
+hipError_t oz_exponents_f64(const double *A, int64_t lda, int m, int n, int *colexp, int *rowexp, hipStream_t s);
+// Digits of the columns of the rows x k column-major vh (+ vl when not null)
+// on per-column scales exp[c] (computed here): dig[(t kpad + c) rows_pad + row].
+hipError_t oz_digits_f64(const double *vh, const double *vl, int64_t ld, int rows, int k, int64_t rows_pad, int kpad,
+                         int *exp, int8_t *dig, hipStream_t s);
+// trans = 1: Rout = B - A^T x (K = m, one split); trans = 0: split partials of A r.
+hipError_t oz_mm(const OzArgs &g, int trans, int splits, hipStream_t s);
+
 // ---------------------------------------------------------------- sketch
 struct SketchTables {
     int64_t n, np, n1, n2, l;

@@ -58,7 +58,7 @@ extern "C" rtproj_status rtproj_project_all_noalloc(rtproj_plan p, const double 
     if (k <= 0) return project(p, B, ldb, k, Z, ldz, Y, ldy, X, ldx);  // no-op or argument error
     if (p->method_used == RTPROJ_METHOD_KRYLOV)
         return fail(RTPROJ_ERR_UNSUPPORTED, "the iterative method's vectors are not in the static workspace");
-    const ProjLayout L = proj_layout(p->m, p->n, k, p->cu_count);
+    const ProjLayout L = proj_layout(p->m, p->n, k, p->cu_count, use_oz(p, k));
     const size_t need = L.bytes();
     if (need > RT_STATIC_WS_BYTES)
         return fail(RTPROJ_ERR_UNSUPPORTED,
@@ -70,6 +70,8 @@ extern "C" rtproj_status rtproj_project_all_noalloc(rtproj_plan p, const double 
     double *saved[ProjLayout::NBUF];
     const int64_t saved_kcap = p->kcap;
     const int saved_ab = p->ab_splits, saved_sx = p->ab_sx_splits, saved_mma = p->ab_mma_splits;
+    const int saved_oz = p->oz_splits;
+    const bool saved_ozr = p->oz_ready;
     unsigned char *cur = static_cast<unsigned char *>(base);
     for (int i = 0; i < ProjLayout::NBUF; ++i) {
         double **b = proj_buffers(p, i);
@@ -81,11 +83,15 @@ extern "C" rtproj_status rtproj_project_all_noalloc(rtproj_plan p, const double 
     p->ab_splits = L.ab_splits;
     p->ab_sx_splits = L.ab_sx_splits;
     p->ab_mma_splits = L.ab_mma_splits;
+    p->oz_splits = L.oz_splits;
+    p->oz_ready = L.oz;
     const rtproj_status st = project(p, B, ldb, k, Z, ldz, Y, ldy, X, ldx);
     for (int i = 0; i < ProjLayout::NBUF; ++i) *proj_buffers(p, i) = saved[i];
     p->kcap = saved_kcap;
     p->ab_splits = saved_ab;
     p->ab_sx_splits = saved_sx;
     p->ab_mma_splits = saved_mma;
+    p->oz_splits = saved_oz;
+    p->oz_ready = saved_ozr;
     return st;
 }

@@ -1,0 +1,334 @@
+// Compensated residual products of the refinement (Remark 4.3) on the int8
+// matrix cores, exact in integer arithmetic (the splitting of Ozaki, Ogita,
+// Oishi and Rump, 2012):
+//
+//   every dot product sum_k u_k v_k of a row of the A operand with a
+//   right-hand side is taken on a common binary scale per row (2^e, all
+//   |u_k| < 2^e) and per right-hand side (2^f); each scaled value is written
+//   as a sum of OZ_S signed 6-bit digits, u 2^-e = sum_s alpha_s 2^(-6s)
+//   (|alpha_1| <= 64, later |alpha_s| <= 33).  The digit products
+//   P_st = sum_k alpha_s,k beta_t,k are exact in int32 (v_mfma_i32_16x16x64_i8
+//   accumulates in int32, and the sums stay below 2^31), and
+//   sum_k u_k v_k = 2^(e+f) sum_{s,t} 2^(-6(s+t)) P_st
+//   up to the digits and pairs left out.  The pairs with s + t <= OZ_D are
+//   kept, summed per diagonal d = s + t in int32, and the diagonals combined
+//   in double-binary64 (TwoSum).  With OZ_D = 14 the omitted terms are below
+//   2^(e+f) K D 2^(6 - 6 OZ_D) in magnitude, about 2^-62 of the scale of the
+//   largest term at K = 2048 (and the digits of binary64 A are exact for
+//   every entry within 2^-25 of its row's largest).
+//
+// Two products use it: r = B - A^T x (x double-binary64; the A-operand rows
+// are A's columns, K = m, the whole sum in one block) and s = A r (r binary64;
+// the rows are A's rows, K = n split over blocks, double-binary64 partials
+// summed by the compensated split reduction).  A's digits are formed on the
+// fly from binary64 A for each 64 x 64 tile; the right-hand sides' digits
+// come from a small digit kernel.
+#include <algorithm>
+#include <climits>
+
+#include "rt_common.h"
+
+namespace rt {
+
+namespace {
+
+constexpr int OZ_T = 256;
+constexpr int OZ_TILE = 64;        // A-operand rows and right-hand sides per block; K per chunk
+constexpr int OZ_LD = OZ_TILE + 16;  // LDS row stride in bytes (16-byte reads of 8 lanes on distinct banks)
+typedef int int4v __attribute__((ext_vector_type(4)));
+
+// Exponent e with |v| < 2^e (frexp's), INT_MIN for zero.
+__device__ __forceinline__ int oz_exp(double v)
+{
+    int e = 0;
+    (void)frexp(v, &e);
+    return v == 0.0 ? INT_MIN : e;
+}
+
+__global__ void oz_fill_kernel(int *p, int n, int v)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Column and row exponents of the m x n row-major A, one 64 x 64 tile per
+// block: thread t takes column j0 + t % 64 and rows i0 + 16 (t / 64) + u.
+__global__ __launch_bounds__(256) void oz_aexp_kernel(const double *A, int64_t lda, int m, int n, int *colexp,
+                                                      int *rowexp)
+{
+    __shared__ int cmax[64], rmax[64];
+    const int t = threadIdx.x;
+    if (t < 64) { cmax[t] = INT_MIN; rmax[t] = INT_MIN; }
+    __syncthreads();
+    const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+    const int j = j0 + (t & 63), ib = 16 * (t >> 6);
+    int cm = INT_MIN;
+    if (j < n) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int i = min(i0 + ib + u, m - 1);
+            v[u] = A[(int64_t)i * lda + j];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            if (i0 + ib + u >= m) break;
+            const int e = oz_exp(v[u]);
+            cm = max(cm, e);
+            atomicMax(&rmax[ib + u], e);
+        }
+        atomicMax(&cmax[t & 63], cm);
+    }
+    __syncthreads();
+    if (t < 64 && j0 + t < n && cmax[t] != INT_MIN) atomicMax(&colexp[j0 + t], cmax[t]);
+    if (t >= 64 && t < 128 && i0 + t - 64 < m && rmax[t - 64] != INT_MIN) atomicMax(&rowexp[i0 + t - 64], rmax[t - 64]);
+}
+
+// Exponent of every column of the rows x k column-major V: blockIdx.x = column,
+// blockIdx.y = a run of 8192 rows; max into exp[c] (cleared to INT_MIN).
+__global__ __launch_bounds__(256) void oz_colexp_kernel(const double *V, int64_t ld, int rows, int *exp)
+{
+    __shared__ int red[256];
+    const int c = blockIdx.x;
+    const int r0 = blockIdx.y * 8192, r1 = min(rows, r0 + 8192);
+    int e = INT_MIN;
+    for (int i = r0 + threadIdx.x; i < r1; i += 256) e = max(e, oz_exp(V[(int64_t)c * ld + i]));
+    red[threadIdx.x] = e;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && red[0] != INT_MIN) atomicMax(&exp[c], red[0]);
+}
+
+// Digits of the right-hand sides (vh + vl, or vh alone) on their column
+// scales: dig[(t kpad + c) rows_pad + row], t < OZ_S, zero past rows and k.
+// The leading digit of a double-binary64 value is rounded from its high part
+// and corrected by one when the low part carries the remainder past 1/2.
+template <bool DD>
+__global__ __launch_bounds__(256) void oz_digits_kernel(const double *vh, const double *vl, int64_t ld, int rows,
+                                                        int k, int64_t rows_pad, int kpad, const int *exp,
+                                                        int8_t *dig)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= rows_pad * kpad) return;
+    const int c = (int)(e / rows_pad);
+    const int64_t row = e % rows_pad;
+    double h = 0.0, l = 0.0;
+    const int ex = c < k ? exp[c] : INT_MIN;
+    if (c < k && row < rows && ex != INT_MIN) {
+        h = ldexp(vh[(int64_t)c * ld + row], -ex);
+        if (DD) l = ldexp(vl[(int64_t)c * ld + row], -ex);
+    }
+#pragma unroll
+    for (int t = 0; t < OZ_S; ++t) {
+        h *= 64.0;
+        l *= 64.0;
+        double d = rint(h);
+        if (DD) {
+            double s, err;
+            two_sum(h - d, l, s, err);  // h - d is exact
+            if (s > 0.5) { d += 1.0; s -= 1.0; }
+            else if (s < -0.5) { d -= 1.0; s += 1.0; }
+            h = s;
+            l = err;
+        } else {
+            h -= d;
+        }
+        dig[((int64_t)t * kpad + c) * rows_pad + row] = (int8_t)(int)d;
+    }
+}
+
+// One 64 x 64 tile (A-operand rows r0.., right-hand sides c0..) over the K
+// range of split blockIdx.z.  TRANS: the A-operand rows are A's columns (A^T x,
+// K = m); otherwise A's rows (A r, K = n).
+template <bool TRANS>
+__global__ __launch_bounds__(OZ_T) void oz_mm_kernel(OzArgs g)
+{
+    __shared__ __attribute__((aligned(16))) int8_t As[OZ_S][OZ_TILE * OZ_LD];
+    __shared__ __attribute__((aligned(16))) int8_t Bs[OZ_S][OZ_TILE * OZ_LD];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int r0 = blockIdx.x * OZ_TILE, c0 = blockIdx.y * OZ_TILE;
+    const int64_t kbeg = (int64_t)blockIdx.z * g.kchunk;
+    const int64_t kend = min((int64_t)g.K, kbeg + g.kchunk);
+    // (an empty split of A r still writes its zero partials below)
+    // this thread's part of the A tile: one A-operand row, 16 consecutive k
+    const int lrow = TRANS ? (tid & 63) : (tid >> 2);
+    const int lk = TRANS ? 16 * (tid >> 6) : 16 * (tid & 3);
+    const int grow = r0 + lrow;
+    const bool rok = grow < g.R;
+    const int ex = rok ? g.rowexp[grow] : INT_MIN;
+    const bool live = ex != INT_MIN;  // (an all-zero row has no scale)
+    const int growc = rok ? grow : g.R - 1;
+    // this thread's part of the B digits: right-hand side c0 + bc, 16 k from bk
+    const int bc = tid >> 2, bk = 16 * (tid & 3);
+
+    int4v acc[OZ_D - 1][4];
+#pragma unroll
+    for (int d = 0; d < OZ_D - 1; ++d)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) acc[d][ct] = int4v{0, 0, 0, 0};
+
+    for (int64_t k0 = kbeg; k0 < kend; k0 += OZ_TILE) {
+        // A values (clamped addresses, zero outside), then their digits
+        double av[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int64_t kk = k0 + lk + u;
+            const int64_t kc = kk < kend ? kk : kend - 1;
+            const double v = TRANS ? g.A[kc * g.lda + growc] : g.A[(int64_t)growc * g.lda + kc];
+            av[u] = (live && kk < kend) ? ldexp(v, -ex) : 0.0;
+        }
+        // B digits of this chunk (padded: always in range)
+        int4v bl[OZ_S];
+#pragma unroll
+        for (int t = 0; t < OZ_S; ++t)
+            bl[t] = *reinterpret_cast<const int4v *>(g.dig + ((int64_t)t * g.kpad + c0 + bc) * g.Kpad + k0 + bk);
+        __syncthreads();  // the previous chunk's operand reads are done
+#pragma unroll
+        for (int t = 0; t < OZ_S; ++t) *reinterpret_cast<int4v *>(&Bs[t][bc * OZ_LD + bk]) = bl[t];
+        // A digits, four elements (one 32-bit word per plane) at a time
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int wd[OZ_S];
+#pragma unroll
+            for (int s2 = 0; s2 < OZ_S; ++s2) wd[s2] = 0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                double v = av[4 * q + u];
+#pragma unroll
+                for (int s2 = 0; s2 < OZ_S; ++s2) {
+                    v *= 64.0;
+                    const double d = rint(v);
+                    v -= d;
+                    wd[s2] |= ((int)d & 0xff) << (8 * u);
+                }
+            }
+#pragma unroll
+            for (int s2 = 0; s2 < OZ_S; ++s2) *reinterpret_cast<int *>(&As[s2][lrow * OZ_LD + lk + 4 * q]) = wd[s2];
+        }
+        __syncthreads();
+        int4v aop[OZ_S];
+#pragma unroll
+        for (int s = 0; s < OZ_S; ++s)
+            aop[s] = *reinterpret_cast<const int4v *>(&As[s][(16 * w + (lane & 15)) * OZ_LD + 16 * (lane >> 4)]);
+        // digit plane t of the right-hand sides against every A plane s with
+        // s + t on a kept diagonal; the next plane's four operands are read
+        // while these products run (no deeper: a fully hoisted schedule would
+        // hold all 52 operands in registers)
+        auto bop_at = [&](int t, int ct) {
+            return *reinterpret_cast<const int4v *>(&Bs[t][(16 * ct + (lane & 15)) * OZ_LD + 16 * (lane >> 4)]);
+        };
+        int4v bcur[4], bnext[4];
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) bcur[ct] = bop_at(0, ct);
+#pragma unroll
+        for (int t = 0; t < OZ_S; ++t) {
+            if (t + 1 < OZ_S)
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct) bnext[ct] = bop_at(t + 1, ct);
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+                for (int s = 0; s + t <= OZ_D - 2; ++s)
+                    acc[s + t][ct] = __builtin_amdgcn_mfma_i32_16x16x64_i8(aop[s], bcur[ct], acc[s + t][ct], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) bcur[ct] = bnext[ct];
+        }
+    }
+
+    // diagonals to double-binary64, smallest first: sum 2^(-6(d+2)) Q_d, then
+    // the scale 2^(e+f) (exact)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = r0 + 16 * w + 4 * (lane >> 4) + r;
+            const int c = c0 + 16 * ct + (lane & 15);
+            if (row >= g.R || c >= g.k) continue;
+            const int er = g.rowexp[row], ec = g.bexp[c];
+            double hi = 0.0, lo = 0.0;
+            if (er != INT_MIN && ec != INT_MIN) {
+#pragma unroll
+                for (int d = OZ_D - 2; d >= 0; --d) {
+                    const double t = ldexp((double)acc[d][ct][r], -6 * (d + 2));
+                    double s, err;
+                    two_sum(hi, t, s, err);
+                    hi = s;
+                    lo += err;
+                }
+                double s, err;
+                two_sum(hi, lo, s, err);
+                hi = ldexp(s, er + ec);
+                lo = ldexp(err, er + ec);
+            }
+            if (TRANS) {
+                // r = B - (hi + lo), rounded once
+                double d, e;
+                two_sum(g.B[(int64_t)c * g.ldb + row], -hi, d, e);
+                g.Rout[(int64_t)c * g.ldr + row] = d + (e - lo);
+            } else {
+                const int64_t idx = ((int64_t)blockIdx.z * g.k + c) * g.R + row;
+                g.ph[idx] = hi;
+                g.pl[idx] = lo;
+            }
+        }
+}
+
+}  // namespace
+
+int oz_splits(int64_t K, int64_t tiles, int cu_count)
+{
+    // split K so that the grid holds about four blocks per compute unit, each
+    // split at least 1024 long and at most OZ_KMAX (the int32 bound)
+    int64_t s = std::max<int64_t>(1, (4 * (int64_t)cu_count + tiles - 1) / std::max<int64_t>(1, tiles));
+    s = std::min<int64_t>(s, std::max<int64_t>(1, K / 1024));
+    s = std::max<int64_t>(s, (K + OZ_KMAX - OZ_TILE - 1) / (OZ_KMAX - OZ_TILE));  // rounded chunks stay <= OZ_KMAX
+    return (int)std::min<int64_t>(s, 64);
+}
+
+int64_t oz_kchunk(int64_t K, int splits)
+{
+    const int64_t c = (K + splits - 1) / splits;
+    return (c + OZ_TILE - 1) / OZ_TILE * OZ_TILE;
+}
+
+hipError_t oz_exponents_f64(const double *A, int64_t lda, int m, int n, int *colexp, int *rowexp, hipStream_t s)
+{
+    hipLaunchKernelGGL(oz_fill_kernel, dim3((n + 255) / 256), dim3(256), 0, s, colexp, n, INT_MIN);
+    hipLaunchKernelGGL(oz_fill_kernel, dim3((m + 255) / 256), dim3(256), 0, s, rowexp, m, INT_MIN);
+    hipLaunchKernelGGL(oz_aexp_kernel, dim3((n + 63) / 64, (m + 63) / 64), dim3(256), 0, s, A, lda, m, n, colexp,
+                       rowexp);
+    return hipGetLastError();
+}
+
+hipError_t oz_digits_f64(const double *vh, const double *vl, int64_t ld, int rows, int k, int64_t rows_pad, int kpad,
+                         int *exp, int8_t *dig, hipStream_t s)
+{
+    if (k <= 0 || rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(oz_fill_kernel, dim3((k + 255) / 256), dim3(256), 0, s, exp, k, INT_MIN);
+    hipLaunchKernelGGL(oz_colexp_kernel, dim3(k, (rows + 8191) / 8192), dim3(256), 0, s, vh, ld, rows, exp);
+    const int64_t total = rows_pad * kpad;
+    if (vl)
+        hipLaunchKernelGGL(oz_digits_kernel<true>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, vh, vl, ld,
+                           rows, k, rows_pad, kpad, (const int *)exp, dig);
+    else
+        hipLaunchKernelGGL(oz_digits_kernel<false>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, vh, vl, ld,
+                           rows, k, rows_pad, kpad, (const int *)exp, dig);
+    return hipGetLastError();
+}
+
+hipError_t oz_mm(const OzArgs &g, int trans, int splits, hipStream_t s)
+{
+    if (g.R <= 0 || g.k <= 0) return hipSuccess;
+    if (g.kchunk % OZ_TILE || g.Kpad % OZ_TILE || g.kpad % OZ_TILE || g.kchunk > OZ_KMAX) return hipErrorInvalidValue;
+    if (trans && splits != 1) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((g.R + OZ_TILE - 1) / OZ_TILE), (unsigned)(g.kpad / OZ_TILE), (unsigned)splits);
+    if (trans) hipLaunchKernelGGL(oz_mm_kernel<true>, grid, dim3(OZ_T), 0, s, g);
+    else hipLaunchKernelGGL(oz_mm_kernel<false>, grid, dim3(OZ_T), 0, s, g);
+    return hipGetLastError();
+}
+
+}  // namespace rt

@@ -148,7 +148,8 @@ void release(rtproj_plan p)
                     p->d_twl, p->d_tw1f, p->d_tw2f, p->d_twhf, p->d_twlf, p->d_rowscale, p->d_zbuf, p->d_S, p->d_R, p->d_Y, p->d_W, p->d_part, p->d_G, p->d_L, p->d_Tp,
                     p->d_DinvR, p->d_DinvL, p->d_piv, p->d_sync, p->d_slots, p->d_vbuf, p->d_qrcols, p->d_Yq, p->d_R0, p->d_wgargs, p->rinv.d_args, p->linv[0].d_args, p->linv[1].d_args, p->d_Linv, p->d_Yq2, p->d_scal, p->d_diag,
                     p->d_bsum, p->d_c, p->d_tmp, p->d_xhi, p->d_xlo, p->d_d, p->d_r, p->d_ph, p->d_pl, p->d_norms, p->d_xpk, p->d_bpk,
-                    p->d_err, p->d_V, p->d_tau, p->d_gpart, p->d_kry, p->d_cflags};
+                    p->d_err, p->d_V, p->d_tau, p->d_gpart, p->d_kry, p->d_cflags,
+                    p->d_oz_xdig, p->d_oz_rdig, p->d_oz_bexp, p->d_colexp, p->d_rowexp};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (p->h_scal) (void)hipHostFree(p->h_scal);
@@ -293,6 +294,8 @@ rtproj_status alloc_state(rtproj_plan p)
     RT_HIP(dalloc(&p->d_diag, 8));
     RT_HIP(dalloc(&p->d_err, 4));
     RT_HIP(dalloc(&p->d_rowscale, (size_t)m));
+    RT_HIP(dalloc(&p->d_colexp, (size_t)n));
+    RT_HIP(dalloc(&p->d_rowexp, (size_t)m));
     p->chol_blocks = rt::chol_coop_blocks((int)m, p->device);
     if (p->chol_blocks > 0) {
         const int64_t nflags = nblk + nblk * (nblk + 1) / 2;
@@ -312,7 +315,13 @@ rtproj_status alloc_state(rtproj_plan p)
     return RTPROJ_OK;
 }
 
-ProjLayout proj_layout(int64_t m, int64_t n, int64_t k, int cu_count)
+bool use_oz(rtproj_plan p, int64_t k)
+{
+    if (p->comp_method == RTPROJ_COMP_DOT2 || p->m > rt::OZ_KMAX) return false;
+    return p->comp_method == RTPROJ_COMP_INT8 || k >= RT_OZ_KMIN;
+}
+
+ProjLayout proj_layout(int64_t m, int64_t n, int64_t k, int cu_count, bool oz)
 {
     ProjLayout L;
     const int64_t rb = (m + 31) / 32, kb = (k + 31) / 32;  // row blocks x right-hand-side blocks of the A B pass
@@ -323,11 +332,24 @@ ProjLayout proj_layout(int64_t m, int64_t n, int64_t k, int cu_count)
     // unit leaves the two-chunk load ring exposed)
     const int64_t tiles = ((m + 63) / 64) * ((k + 63) / 64);
     L.ab_mma_splits = (int)std::max<int64_t>(1, std::min<int64_t>({64, n / 256, (4 * cu_count + tiles - 1) / tiles}));
-    const int64_t psplits = std::max<int64_t>({(int64_t)L.ab_splits, (int64_t)L.ab_sx_splits, (int64_t)L.ab_mma_splits});
+    const int64_t kpad = (k + 63) / 64 * 64, mpad = (m + 63) / 64 * 64, npad = (n + 63) / 64 * 64;
+    L.oz = oz;
+    if (oz) {
+        // the split count that the rounded chunk length really gives (every
+        // split non-empty)
+        const int s0 = rt::oz_splits(n, ((m + 63) / 64) * (kpad / 64), cu_count);
+        const int64_t kc = rt::oz_kchunk(n, s0);
+        L.oz_splits = (int)((n + kc - 1) / kc);
+    }
+    const int64_t psplits = std::max<int64_t>({(int64_t)L.ab_splits, (int64_t)L.ab_sx_splits, (int64_t)L.ab_mma_splits,
+                                               (int64_t)L.oz_splits});
     // c, tmp, xhi, xlo, d (m k each), r (n k), ph, pl (split partials), bpk, norms, xpk
     const int64_t cnt[ProjLayout::NBUF] = {m * k, m * k, m * k, m * k, m * k, n * k, psplits * m * k,
                                            psplits * m * k, rt::ab_pack_size(n, k), 2 * RT_MAX_STEPS,
-                                           rt::atx_pack_size(m, k)};
+                                           rt::atx_pack_size(m, k),
+                                           oz ? (rt::OZ_S * kpad * mpad + 7) / 8 : 1,
+                                           oz ? (rt::OZ_S * kpad * npad + 7) / 8 : 1,
+                                           oz ? kpad : 1};
     for (int i = 0; i < ProjLayout::NBUF; ++i) L.count[i] = std::max<int64_t>(1, cnt[i]);
     return L;
 }
@@ -342,24 +364,30 @@ size_t ProjLayout::bytes() const
 double **proj_buffers(rtproj_plan p, int i)
 {
     double **bufs[ProjLayout::NBUF] = {&p->d_c, &p->d_tmp, &p->d_xhi, &p->d_xlo, &p->d_d, &p->d_r,
-                                       &p->d_ph, &p->d_pl, &p->d_bpk, &p->d_norms, &p->d_xpk};
+                                       &p->d_ph, &p->d_pl, &p->d_bpk, &p->d_norms, &p->d_xpk,
+                                       &p->d_oz_xdig, &p->d_oz_rdig, &p->d_oz_bexp};
     return bufs[i];
 }
 
 rtproj_status ensure_k(rtproj_plan p, int64_t k)
 {
-    if (k <= p->kcap) return RTPROJ_OK;
+    const bool oz = use_oz(p, std::max(k, p->kcap));
+    if (k <= p->kcap && (!oz || p->oz_ready)) return RTPROJ_OK;
+    k = std::max(k, p->kcap);
     for (int i = 0; i < ProjLayout::NBUF; ++i) {
         double **b = proj_buffers(p, i);
         if (*b) { (void)hipFree(*b); *b = nullptr; }
     }
     p->kcap = 0;
-    const ProjLayout L = proj_layout(p->m, p->n, k, p->cu_count);
+    p->oz_ready = false;
+    const ProjLayout L = proj_layout(p->m, p->n, k, p->cu_count, oz);
     p->ab_splits = L.ab_splits;
     p->ab_sx_splits = L.ab_sx_splits;
     p->ab_mma_splits = L.ab_mma_splits;
+    p->oz_splits = L.oz_splits;
     for (int i = 0; i < ProjLayout::NBUF; ++i) RT_HIP(dalloc(proj_buffers(p, i), (size_t)L.count[i]));
     p->kcap = k;
+    p->oz_ready = oz;
     return RTPROJ_OK;
 }
 
@@ -945,6 +973,54 @@ hipError_t final_from_residual(rtproj_plan p, const double *B, int64_t ldb, int6
     return rt::finish_cols_f64(rt::FinishGroupArgs{p->d_r, n, B, ldb, Y, ldy, Z, ldz, (int)n, (int)k}, s);
 }
 
+// Exponents of A's columns and rows for the int8-MFMA products, computed once
+// per preconditioned A (at its first compensated step).
+hipError_t oz_ensure_exp(rtproj_plan p, hipStream_t s)
+{
+    if (p->oz_exp_valid) return hipSuccess;
+    hipError_t e = rt::oz_exponents_f64(p->A, p->lda, (int)p->m, (int)p->n, p->d_colexp, p->d_rowexp, s);
+    if (e == hipSuccess) p->oz_exp_valid = true;
+    return e;
+}
+
+// d_r = B - A^T (x_hi + x_lo), exact digit products on the int8 matrix cores
+// (K = m in one block per tile).
+hipError_t oz_resid(rtproj_plan p, const double *B, int64_t ldb, int64_t k, hipStream_t s)
+{
+    const int64_t m = p->m, n = p->n, kpad = (k + 63) / 64 * 64, mpad = (m + 63) / 64 * 64;
+    int *bexp = reinterpret_cast<int *>(p->d_oz_bexp);
+    int8_t *xd = reinterpret_cast<int8_t *>(p->d_oz_xdig);
+    hipError_t e = oz_ensure_exp(p, s);
+    if (e == hipSuccess) e = rt::oz_digits_f64(p->d_xhi, p->d_xlo, m, (int)m, (int)k, mpad, (int)kpad, bexp, xd, s);
+    if (e != hipSuccess) return e;
+    rt::OzArgs g{};
+    g.R = (int)n; g.K = (int)m; g.k = (int)k;
+    g.A = p->A; g.lda = p->lda; g.rowexp = p->d_colexp;
+    g.dig = xd; g.kpad = (int)kpad; g.Kpad = mpad; g.bexp = bexp; g.kchunk = mpad;
+    g.B = B; g.ldb = ldb; g.Rout = p->d_r; g.ldr = n;
+    return rt::oz_mm(g, 1, 1, s);
+}
+
+// d_c = A d_r, exact digit products on the int8 matrix cores, K = n split
+// over blocks, double-binary64 partials summed by the compensated reduction.
+hipError_t oz_ar(rtproj_plan p, int64_t k, hipStream_t s)
+{
+    const int64_t m = p->m, n = p->n, kpad = (k + 63) / 64 * 64, npad = (n + 63) / 64 * 64;
+    int *bexp = reinterpret_cast<int *>(p->d_oz_bexp);
+    int8_t *rd = reinterpret_cast<int8_t *>(p->d_oz_rdig);
+    hipError_t e = oz_ensure_exp(p, s);
+    if (e == hipSuccess) e = rt::oz_digits_f64(p->d_r, nullptr, n, (int)n, (int)k, npad, (int)kpad, bexp, rd, s);
+    if (e != hipSuccess) return e;
+    rt::OzArgs g{};
+    g.R = (int)m; g.K = (int)n; g.k = (int)k;
+    g.A = p->A; g.lda = p->lda; g.rowexp = p->d_rowexp;
+    g.dig = rd; g.kpad = (int)kpad; g.Kpad = npad; g.bexp = bexp;
+    g.kchunk = rt::oz_kchunk(n, p->oz_splits);
+    g.ph = p->d_ph; g.pl = p->d_pl;
+    if ((e = rt::oz_mm(g, 0, p->oz_splits, s)) != hipSuccess) return e;
+    return rt::ab_reduce_f64(p->d_ph, p->d_pl, (int)m, (int)k, p->oz_splits, 1, p->d_c, m, s);
+}
+
 rtproj_status project(rtproj_plan p, const double *B, int64_t ldb, int64_t k, double *Z, int64_t ldz, double *Y,
                       int64_t ldy, double *X, int64_t ldx)
 {
@@ -1012,21 +1088,29 @@ rtproj_status project(rtproj_plan p, const double *B, int64_t ldb, int64_t k, do
     int steps = 0;
     double ratio = 0.0;
     bool last_dd_r = false;
+    // compensated products on the int8 matrix cores when the plan's setting
+    // and k allow it (the workspace was sized for it by ensure_k)
+    const bool oz = p->oz_ready && use_oz(p, k) && p->method_used != RTPROJ_METHOD_KRYLOV;
+    int comp_used = 0;
     for (int it = 0; it < nsteps; ++it) {
         // plain binary64 residuals while the error is above their floor,
         // compensated (Dot2) ones for the last steps
         const bool comp = it >= nplain;
         const bool dd_r = comp && rp.comp_r;
         last_dd_r = dd_r;
+        if (comp) comp_used = oz ? RTPROJ_COMP_INT8 : RTPROJ_COMP_DOT2;
         {
             StageScope sc(p, dd_r ? 9 : 13);
-            if (dd_r) RT_HIP(rt::atx_f64(a, p->d_xhi, p->d_xlo, m, B, ldb, p->d_r, n, nullptr, 0, nullptr, 0, 1, s,
-                                         p->d_xpk));
+            if (dd_r && oz) RT_HIP(oz_resid(p, B, ldb, k, s));
+            else if (dd_r) RT_HIP(rt::atx_f64(a, p->d_xhi, p->d_xlo, m, B, ldb, p->d_r, n, nullptr, 0, nullptr, 0, 1, s,
+                                              p->d_xpk));
             else RT_HIP(resid_plain(p, B, ldb, k, s));
         }
         {
             StageScope sc(p, comp ? 10 : 14);
-            if (comp) {
+            if (comp && oz) {
+                RT_HIP(oz_ar(p, k, s));
+            } else if (comp) {
                 RT_HIP(rt::ab_partial_f64(a, p->d_r, n, p->ab_splits, p->d_ph, p->d_pl, 1, s));
                 RT_HIP(rt::ab_reduce_f64(p->d_ph, p->d_pl, (int)m, (int)k, p->ab_splits, 1, p->d_c, m, s));
             } else {
@@ -1062,6 +1146,7 @@ rtproj_status project(rtproj_plan p, const double *B, int64_t ldb, int64_t k, do
     }
     if (X) RT_HIP(rt::copy_cols_f64(p->d_xhi, m, X, ldx, (int)m, (int)k, nullptr, 0, s));
     p->info.refine_steps = steps;
+    p->info.comp_method = comp_used;
     p->info.refine_plain = std::min(steps, nplain);
     p->info.refine_comp = steps - p->info.refine_plain;
     p->info.resid_mode = p->resid_mode == RTPROJ_RESID_AUTO ? RTPROJ_RESID_FULL : p->resid_mode;
@@ -1217,6 +1302,15 @@ rtproj_status rtproj_plan_set_residual(rtproj_plan p, int mode)
     return RTPROJ_OK;
 }
 
+rtproj_status rtproj_plan_set_compensation(rtproj_plan p, int method)
+{
+    if (!p) return fail(RTPROJ_ERR_INVALID_ARG, "null plan");
+    if (method < RTPROJ_COMP_AUTO || method > RTPROJ_COMP_INT8)
+        return fail(RTPROJ_ERR_INVALID_ARG, "unknown compensation method");
+    p->comp_method = method;
+    return RTPROJ_OK;
+}
+
 rtproj_status rtproj_plan_set_qr(rtproj_plan p, int mode)
 {
     if (!p) return fail(RTPROJ_ERR_INVALID_ARG, "null plan");
@@ -1341,6 +1435,7 @@ rtproj_status precondition_classical(rtproj_plan p, const double *A, int64_t lda
 // One pass of the preconditioner; sketch64 forces the binary64 sketch.
 rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, bool sketch64)
 {
+    p->oz_exp_valid = false;  // the int8-MFMA exponents describe the previous A
     const int64_t m = p->m, n = p->n, l = p->l;
     hipStream_t s = p->stream;
     // 1. sketch

@@ -32,6 +32,8 @@ extern thread_local std::string g_last_error;
 constexpr int NB = 64;  // block size of the triangular solves and the Cholesky
 // right-hand sides from which the plain binary64 A-passes run as MFMA GEMMs
 constexpr int64_t RT_MFMA_KMIN = 32;
+// right-hand sides from which the compensated products take the int8-MFMA form
+constexpr int64_t RT_OZ_KMIN = 16;
 // P^{-1}A is formed in binary32 only while the rank estimate of the pivoted QR
 // is at most this: its rounding error grows like 2^-24 kappa and must leave
 // the refinement a contraction well below 1.
@@ -248,6 +250,13 @@ struct rtproj_plan_s {
     int64_t kcap = 0;
     int ab_splits = 1;
     int ab_mma_splits = 1;     // K splits of the MFMA form of A B (many right-hand sides)
+    int oz_splits = 1;         // K splits of the int8-MFMA compensated A r
+    bool oz_ready = false;     // the int8-MFMA buffers are sized for kcap
+    double *d_oz_xdig = nullptr, *d_oz_rdig = nullptr, *d_oz_bexp = nullptr;  // (byte and int storage)
+    int comp_method = RTPROJ_COMP_AUTO;
+    int comp_used = 0;         // compensation form of the last projection's compensated steps
+    int *d_colexp = nullptr, *d_rowexp = nullptr;  // exponents of A's columns and rows (int8-MFMA form)
+    bool oz_exp_valid = false; // they describe the current A
     double *d_c = nullptr, *d_tmp = nullptr, *d_xhi = nullptr, *d_xlo = nullptr, *d_d = nullptr, *d_r = nullptr;
     double *d_ph = nullptr, *d_pl = nullptr, *d_norms = nullptr;
     double *d_bpk = nullptr;   // right-hand sides packed for the scalar-load A B pass (ab_pack_size(n, k))
@@ -284,14 +293,22 @@ namespace rtp {
 
 // Projection workspace for k right-hand sides: the split counts of the A B
 // passes and the element count (doubles) of each buffer, in the order c,
-// tmp, xhi, xlo, d, r, ph, pl, bpk, norms, xpk.
+// tmp, xhi, xlo, d, r, ph, pl, bpk, norms, xpk, and for the int8-MFMA
+// compensated products (oz) the digits of x, the digits of r and the
+// right-hand-side exponents.
 struct ProjLayout {
-    static constexpr int NBUF = 11;
+    static constexpr int NBUF = 14;
     int ab_splits = 1, ab_sx_splits = 1, ab_mma_splits = 1;
+    int oz_splits = 1;         // K splits of the int8-MFMA A r (when oz)
+    bool oz = false;           // the int8-MFMA buffers are sized (else one element each)
     int64_t count[NBUF] = {};
     size_t bytes() const;  // every buffer rounded up to 256 bytes
 };
-ProjLayout proj_layout(int64_t m, int64_t n, int64_t k, int cu_count);
+ProjLayout proj_layout(int64_t m, int64_t n, int64_t k, int cu_count, bool oz);
+// Whether the compensated products of a projection with k right-hand sides
+// take the int8-MFMA form (the plan's setting; automatic: from 16 right-hand
+// sides on, when m fits one int32 partial sum).
+bool use_oz(rtproj_plan p, int64_t k);
 // The plan's pointer to projection buffer i (order of ProjLayout::count).
 double **proj_buffers(rtproj_plan p, int i);
 // Grows the projection workspace of p to k right-hand sides.
