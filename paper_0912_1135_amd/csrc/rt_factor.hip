@@ -410,8 +410,10 @@ __global__ __launch_bounds__(256) void sum_blocks_sqrt_kernel(const double *bsum
 //
 // The lower triangle of 64 x 64 tiles is numbered column by column,
 // t(i, j) = j nb - j (j - 1) / 2 + (i - j), and block b owns the tiles with
-// t = b mod (grid size) for the whole factorization, visiting them in that
-// order at every step k:
+// t = b mod (grid size) for the whole factorization (a sub-diagonal tile
+// (j + 1, j) belongs to the owner of (j + 1, j + 1) instead, which keeps the
+// chain panel -> update -> next diagonal factor inside one block), visiting
+// them in column order at every step k:
 //   diagonal (k, k): factor it (one wave), X = L_kk^{-1} (the block), write
 //     L_kk, publish X as Dinv[k] and raise the step's diagonal flag;
 //   panel (i, k), i > k: wait for the diagonal flag, L_ik = A_ik X^T on
@@ -631,11 +633,34 @@ __global__ __launch_bounds__(CC_T) void chol_coop_kernel(CholCoopArgs g)
     const int B = gridDim.x;
     unsigned *dflag = g.flags, *pflag = g.flags + nb;
     if (threadIdx.x == 0) {
-        int n = 0, j = 0, start = 0;
-        for (int t = blockIdx.x; t < ntiles && n < CC_MAXOWN; t += B) {
-            while (start + (nb - j) <= t) { start += nb - j; ++j; }
-            own_j[n] = (short)j;
-            own_i[n] = (short)(j + (t - start));
+        // the tiles t = b mod B except the sub-diagonal ones (j + 1, j), which
+        // go to the owner of the diagonal tile (j + 1, j + 1) so that the
+        // panel task on them, the update of that diagonal tile and its
+        // factorization follow one another in one block; merged in column
+        // order
+        const int b = blockIdx.x;
+        int n = 0, jr = 0, start = 0, t = b, js = 0;
+        while (js < nb - 1 && cc_tile(js + 1, js + 1, nb) % B != b) ++js;
+        for (;;) {
+            int ir = -1;
+            while (t < ntiles) {
+                while (start + (nb - jr) <= t) { start += nb - jr; ++jr; }
+                ir = jr + (t - start);
+                if (ir != jr + 1) break;
+                t += B;
+            }
+            const bool has_r = t < ntiles, has_s = js < nb - 1;
+            if ((!has_r && !has_s) || n >= CC_MAXOWN) break;
+            if (has_r && (!has_s || t < cc_tile(js + 1, js, nb))) {
+                own_i[n] = (short)ir;
+                own_j[n] = (short)jr;
+                t += B;
+            } else {
+                own_i[n] = (short)(js + 1);
+                own_j[n] = (short)js;
+                ++js;
+                while (js < nb - 1 && cc_tile(js + 1, js + 1, nb) % B != b) ++js;
+            }
             ++n;
         }
         s_nown = n;
@@ -767,7 +792,7 @@ int chol_coop_blocks(int m, int device)
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, chol_coop_kernel, CC_T, 0) != hipSuccess || per < 1) return 0;
     const int blocks = std::min(ntiles, cus);  // one block per compute unit at most
-    if ((ntiles + blocks - 1) / blocks > CC_MAXOWN) return 0;
+    if ((ntiles + blocks - 1) / blocks + (nb + blocks - 1) / blocks > CC_MAXOWN) return 0;
     return blocks;
 }
 
@@ -775,7 +800,8 @@ hipError_t chol_coop_f64(const CholCoopArgs &a, int blocks, hipStream_t stream)
 {
     const int nb = (a.m + NBMAX - 1) / NBMAX, ntiles = nb * (nb + 1) / 2;
     if (a.m <= 0) return hipSuccess;
-    if (blocks < 1 || (ntiles + blocks - 1) / blocks > CC_MAXOWN) return hipErrorInvalidValue;
+    if (blocks < 1 || (ntiles + blocks - 1) / blocks + (nb + blocks - 1) / blocks > CC_MAXOWN)
+        return hipErrorInvalidValue;
     CholCoopArgs g = a;
     void *args[] = {(void *)&g};
     return hipLaunchCooperativeKernel((const void *)chol_coop_kernel, dim3(blocks), dim3(CC_T), args, 0, stream);

@@ -62,23 +62,23 @@ __global__ __launch_bounds__(256) void oz_aexp_kernel(const double *A, int64_t l
     __syncthreads();
     const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
     const int j = j0 + (t & 63), ib = 16 * (t >> 6);
+    const bool jok = j < n;
+    const int jc = jok ? j : n - 1;
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = A[(int64_t)min(i0 + ib + u, m - 1) * lda + jc];
     int cm = INT_MIN;
-    if (j < n) {
-        double v[16];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int i = min(i0 + ib + u, m - 1);
-            v[u] = A[(int64_t)i * lda + j];
-        }
+    for (int u = 0; u < 16; ++u) {
+        // a wave holds one row's 64 columns: its maximum by shuffles, then
+        // one LDS atomic per wave and row
+        int e = (jok && i0 + ib + u < m) ? oz_exp(v[u]) : INT_MIN;
+        cm = max(cm, e);
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            if (i0 + ib + u >= m) break;
-            const int e = oz_exp(v[u]);
-            cm = max(cm, e);
-            atomicMax(&rmax[ib + u], e);
-        }
-        atomicMax(&cmax[t & 63], cm);
+        for (int o = 32; o > 0; o >>= 1) e = max(e, __shfl_xor(e, o, 64));
+        if ((t & 63) == 0 && e != INT_MIN) atomicMax(&rmax[ib + u], e);
     }
+    if (jok && cm != INT_MIN) atomicMax(&cmax[t & 63], cm);
     __syncthreads();
     if (t < 64 && j0 + t < n && cmax[t] != INT_MIN) atomicMax(&colexp[j0 + t], cmax[t]);
     if (t >= 64 && t < 128 && i0 + t - 64 < m && rmax[t - 64] != INT_MIN) atomicMax(&rowexp[i0 + t - 64], rmax[t - 64]);
@@ -170,21 +170,24 @@ __global__ __launch_bounds__(OZ_T) void oz_mm_kernel(OzArgs g)
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) acc[d][ct] = int4v{0, 0, 0, 0};
 
-    for (int64_t k0 = kbeg; k0 < kend; k0 += OZ_TILE) {
-        // A values (clamped addresses, zero outside), then their digits
-        double av[16];
+    // chunk loads: raw A values (clamped addresses) and the B digits (padded:
+    // always in range); issued one chunk ahead, before the current chunk's
+    // products, and used only after them
+    double av[16];
+    int4v bl[OZ_S];
+    auto load_chunk = [&](int64_t k0) {
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
             const int64_t kk = k0 + lk + u;
             const int64_t kc = kk < kend ? kk : kend - 1;
-            const double v = TRANS ? g.A[kc * g.lda + growc] : g.A[(int64_t)growc * g.lda + kc];
-            av[u] = (live && kk < kend) ? ldexp(v, -ex) : 0.0;
+            av[u] = TRANS ? g.A[kc * g.lda + growc] : g.A[(int64_t)growc * g.lda + kc];
         }
-        // B digits of this chunk (padded: always in range)
-        int4v bl[OZ_S];
 #pragma unroll
         for (int t = 0; t < OZ_S; ++t)
             bl[t] = *reinterpret_cast<const int4v *>(g.dig + ((int64_t)t * g.kpad + c0 + bc) * g.Kpad + k0 + bk);
+    };
+    if (kbeg < kend) load_chunk(kbeg);
+    for (int64_t k0 = kbeg; k0 < kend; k0 += OZ_TILE) {
         __syncthreads();  // the previous chunk's operand reads are done
 #pragma unroll
         for (int t = 0; t < OZ_S; ++t) *reinterpret_cast<int4v *>(&Bs[t][bc * OZ_LD + bk]) = bl[t];
@@ -196,7 +199,8 @@ __global__ __launch_bounds__(OZ_T) void oz_mm_kernel(OzArgs g)
             for (int s2 = 0; s2 < OZ_S; ++s2) wd[s2] = 0;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                double v = av[4 * q + u];
+                // scaled to the row's power of two (zero outside the range)
+                double v = (live && k0 + lk + 4 * q + u < kend) ? ldexp(av[4 * q + u], -ex) : 0.0;
 #pragma unroll
                 for (int s2 = 0; s2 < OZ_S; ++s2) {
                     v *= 64.0;
@@ -209,6 +213,7 @@ __global__ __launch_bounds__(OZ_T) void oz_mm_kernel(OzArgs g)
             for (int s2 = 0; s2 < OZ_S; ++s2) *reinterpret_cast<int *>(&As[s2][lrow * OZ_LD + lk + 4 * q]) = wd[s2];
         }
         __syncthreads();
+        if (k0 + OZ_TILE < kend) load_chunk(k0 + OZ_TILE);  // in flight during the products
         int4v aop[OZ_S];
 #pragma unroll
         for (int s = 0; s < OZ_S; ++s)
