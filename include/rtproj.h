@@ -446,7 +446,10 @@ rtproj_status rtproj_sketch_tables(rtproj_plan plan, int64_t *dims3, int8_t *sig
  * m[i] <= 2048), preconditioned and projected together with ONE grouped
  * launch per stage of the path for all members.  The pivoted QR of member i
  * is the two-stage form (S^T = Q0 R0 by shifted Cholesky QR, then the QRCP of
- * R0 in one workgroup per member), so no step waits on the host: rank tests
+ * R0, in one workgroup per member or, for few large members, in a group of
+ * blocks per member that synchronize only among themselves; the batch picks
+ * the faster from the sizes and rtproj_batch_info reports it as qr_mode
+ * RTPROJ_QR_TWO_STAGE_WG or RTPROJ_QR_TWO_STAGE), so no step waits on the host: rank tests
  * and factorization breakdowns are reported afterwards by
  * rtproj_batch_status.  Member i's sketch seed is the first output of
  * SplitMix64 seeded with seed XOR i.  Arithmetic is binary64 with
@@ -487,9 +490,11 @@ rtproj_status rtproj_batch_precondition(rtproj_batch batch, const double *const 
 /* As rtproj_batch_precondition for the column-scaled matrices A[i] diag(d[i])
  * (an interior-point step rescales a fixed A by a positive diagonal):
  * col_scale[i] points to n[i] doubles on the device, or is NULL for an
- * unscaled member.  Scaled members are copied once per call into a buffer the
- * batch owns (m[i] n[i] doubles), which the projections then use; A[i] and
- * col_scale[i] need not outlive the call. */
+ * unscaled member.  No scaled copy is made: every pass that reads a scaled
+ * member's A forms its elements A[i][r][t] * d[t] as it loads them (the
+ * products with A rounded element by element as a scaled copy would be), so
+ * col_scale[i] is borrowed like A[i] and must stay valid and unchanged until
+ * the last projection that uses this preconditioning. */
 rtproj_status rtproj_batch_precondition_scaled(rtproj_batch batch, const double *const *A, const int64_t *lda,
                                               const double *const *col_scale);
 /* As rtproj_project_all per member; Z, Y, X (or their entries) may be NULL;
@@ -499,10 +504,12 @@ rtproj_status rtproj_batch_project_all(rtproj_batch batch, const double *const *
                                        const int64_t *ldy, double *const *X, const int64_t *ldx);
 /* Waits for the batch's stream and reports, per member (per_member may be
  * NULL), RTPROJ_OK, RTPROJ_ERR_RANK (|R_mm| <= m 2^-52 |R_11|, a NaN in A,
- * or a Cholesky breakdown) or RTPROJ_ERR_NOCONV (the member's refinement in
+ * or a Cholesky breakdown), RTPROJ_ERR_DEVICE (a block barrier of the grouped
+ * pivoted QR timed out) or RTPROJ_ERR_NOCONV (the member's refinement in
  * the last rtproj_batch_project_all did not converge, judged as in
  * rtproj_plan_status); returns RTPROJ_ERR_RANK if any member has it, else
- * RTPROJ_ERR_NOCONV if any member has it, else RTPROJ_OK. */
+ * RTPROJ_ERR_DEVICE if any member has it, else RTPROJ_ERR_NOCONV if any
+ * member has it, else RTPROJ_OK. */
 rtproj_status rtproj_batch_status(rtproj_batch batch, int *per_member);
 /* Per-stage device time of the batch (stage indices as in rtproj_info),
  * accumulated while enabled; only eager (non-graph) calls are timed, and a

@@ -479,7 +479,8 @@ class Batch:
 
     def precondition(self, As, col_scales=None):
         """As[i]: (m_i, n_i) float64 CUDA tensors; col_scales[i] (optional):
-        (n_i,) float64 CUDA tensors, member i then works on A[i] diag(d[i])."""
+        (n_i,) float64 CUDA tensors, member i then works on A[i] diag(d[i]).
+        Both are borrowed (kept referenced here) until the next precondition."""
         assert len(As) == self.count
         for i, A in enumerate(As):
             _check_tensor(A, f"A[{i}]", self.ms[i], self.ns[i])
@@ -495,6 +496,7 @@ class Batch:
             _check(lib().rtproj_batch_precondition_scaled(self.handle, _ptrs(As), _i64s([A.stride(0) for A in As]),
                                                           _ptrs(col_scales)))
         self._A = list(As)  # borrowed
+        self._D = list(col_scales) if col_scales is not None else None  # borrowed alike
 
     def project_all(self, Bs, Zs=None, Ys=None, Xs=None):
         """Bs[i]: (k_i, n_i) float64 CUDA tensors; outputs are allocated when

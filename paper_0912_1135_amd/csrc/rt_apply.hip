@@ -69,8 +69,10 @@ __device__ __forceinline__ void ab_partial_body(const ApplyArgs &a, const double
     auto load = [&](int64_t tb) {
         const int64_t t = tb + tt;
         const bool tin = t < t1;
+        // a column-scaled operand: each element rounded as A[i][t] * cs[t]
+        const double ct = a.cs ? *(tin ? a.cs + t : &g_zero) : 1.0;
 #pragma unroll
-        for (int q = 0; q < NA; ++q) ra[q] = *((arow[q] && tin) ? arow[q] + t : &g_zero);
+        for (int q = 0; q < NA; ++q) ra[q] = *((arow[q] && tin) ? arow[q] + t : &g_zero) * ct;
 #pragma unroll
         for (int q = 0; q < NB; ++q) rb[q] = *((bcol[q] && tin) ? bcol[q] + t : &g_zero);
     };
@@ -184,7 +186,7 @@ constexpr int ATX_MC = 64;  // rows of x staged in LDS at a time
 // y(t, j) = sum_i A[i][t] (xhi[i][j] + xlo[i][j]); then
 //   mode 0: R = round(B - y)
 //   mode 1: Y = round(y), Z = round(B - y)
-template <bool DD, int KJ>
+template <bool DD, int KJ, bool SC = false>
 __device__ __forceinline__ void atx_body(const ApplyArgs &a, const double *xhi, const double *xlo, int64_t ldx,
                                          const double *B, int64_t ldb, double *Rout, int64_t ldr, double *Y,
                                          int64_t ldy, double *Z, int64_t ldz, int bx, int by)
@@ -199,6 +201,9 @@ __device__ __forceinline__ void atx_body(const ApplyArgs &a, const double *xhi, 
 #pragma unroll
     for (int j = 0; j < KJ; ++j) { s[j] = 0.0; c[j] = 0.0; }
     const bool active = t < a.n;
+    // SC: a column-scaled operand, each element rounded as A[i][t] * cs[t]
+    // (members without a scaling multiply by one)
+    const double ct = (SC && a.cs && active) ? a.cs[t] : 1.0;
     for (int i0 = 0; i0 < a.m; i0 += ATX_MC) {
         const int mc = min(ATX_MC, a.m - i0);
         for (int e = threadIdx.x; e < ATX_MC * KJ; e += ATX_T) {
@@ -214,7 +219,10 @@ __device__ __forceinline__ void atx_body(const ApplyArgs &a, const double *xhi, 
                 // eight loads in flight before the 8 x 16 compensated updates
                 double av[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) av[u] = (ii + u < mc) ? ap[(int64_t)(ii + u) * a.lda] : 0.0;
+                for (int u = 0; u < 8; ++u) {
+                    av[u] = (ii + u < mc) ? ap[(int64_t)(ii + u) * a.lda] : 0.0;
+                    if (SC) av[u] *= ct;
+                }
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
 #pragma unroll
@@ -254,11 +262,11 @@ __global__ __launch_bounds__(ATX_T) void atx_kernel(ApplyArgs a, const double *x
     atx_body<DD, KJ>(a, xhi, xlo, ldx, B, ldb, Rout, ldr, Y, ldy, Z, ldz, blockIdx.x, blockIdx.y);
 }
 
-template <bool DD, int KJ>
+template <bool DD, int KJ, bool SC>
 __global__ __launch_bounds__(ATX_T) void atx_grouped(const AtxGroupArgs *gs)
 {
     const AtxGroupArgs g = gs[blockIdx.z];
-    atx_body<DD, KJ>(g.a, g.xhi, g.xlo, g.ldx, g.B, g.ldb, g.Rout, g.ldr, g.Y, g.ldy, g.Z, g.ldz, blockIdx.x,
+    atx_body<DD, KJ, SC>(g.a, g.xhi, g.xlo, g.ldx, g.B, g.ldb, g.Rout, g.ldr, g.Y, g.ldy, g.Z, g.ldz, blockIdx.x,
                      blockIdx.y);
 }
 
@@ -574,11 +582,13 @@ __global__ __launch_bounds__(256) void dd_update_grouped(const DdGroupArgs *gs)
 }
 
 __device__ __forceinline__ void copy_cols_body(const double *src, int64_t lds, double *dst, int64_t ldd, int rows,
-                                               int cols, double *zero_out, int64_t ldz, int64_t e)
+                                               int cols, double *zero_out, int64_t ldz, int64_t e,
+                                               const double *rs = nullptr)
 {
     if (e >= (int64_t)rows * cols) return;
     const int j = (int)(e / rows), i = (int)(e % rows);
-    dst[(int64_t)j * ldd + i] = src[(int64_t)j * lds + i];
+    const double v = src[(int64_t)j * lds + i];
+    dst[(int64_t)j * ldd + i] = rs ? v * rs[i] : v;
     if (zero_out) zero_out[(int64_t)j * ldz + i] = 0.0;
 }
 
@@ -625,7 +635,7 @@ __global__ void copy_cols_grouped(const CopyGroupArgs *gs)
 {
     const CopyGroupArgs g = gs[blockIdx.y];
     copy_cols_body(g.src, g.lds, g.dst, g.ldd, g.rows, g.cols, g.zero_out, g.ldz,
-                   (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+                   (int64_t)blockIdx.x * blockDim.x + threadIdx.x, g.rs);
 }
 
 }  // namespace
@@ -739,29 +749,6 @@ hipError_t copy_cols_f64(const double *src, int64_t lds, double *dst, int64_t ld
     return hipGetLastError();
 }
 
-namespace {
-
-// out (m x n, ld ldo) = A diag(d): row i of out is row i of A times d
-// element by element (one problem per blockIdx.y).
-__global__ __launch_bounds__(256) void scale_cols_grouped(const ScaleGroupArgs *gs)
-{
-    const ScaleGroupArgs g = gs[blockIdx.y];
-    const int64_t total = (int64_t)g.m * g.n;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
-        const int64_t i = e / g.n, j = e - i * g.n;
-        g.out[i * g.ldo + j] = g.A[i * g.lda + j] * g.d[j];
-    }
-}
-
-}  // namespace
-
-hipError_t scale_cols_grouped_f64(const ScaleGroupArgs *d, int count, hipStream_t stream)
-{
-    if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(scale_cols_grouped, dim3(2048, count), dim3(256), 0, stream, d);
-    return hipGetLastError();
-}
-
 hipError_t ab_partial_grouped_f64(const AbGroupArgs *d, int count, int max_m, int max_k, int max_splits, int dd,
                                   hipStream_t stream)
 {
@@ -783,13 +770,16 @@ hipError_t ab_reduce_grouped_f64(const AbGroupArgs *d, int count, int64_t max_mk
     return hipGetLastError();
 }
 
-hipError_t atx_grouped_f64(const AtxGroupArgs *d, int count, int64_t max_n, int max_k, int dd, hipStream_t stream)
+hipError_t atx_grouped_f64(const AtxGroupArgs *d, int count, int64_t max_n, int max_k, int dd, int scaled,
+                           hipStream_t stream)
 {
     if (count <= 0 || max_n <= 0 || max_k <= 0) return hipSuccess;
     const int kj = atx_kj(max_k, dd);
     dim3 grid((unsigned)((max_n + ATX_T - 1) / ATX_T), (max_k + kj - 1) / kj, count);
 #define ATX_CASE(DD_, KJ_) \
-    if (!!dd == DD_ && kj == KJ_) hipLaunchKernelGGL((atx_grouped<DD_, KJ_>), grid, dim3(ATX_T), 0, stream, d);
+    if (!!dd == DD_ && kj == KJ_)                                                                                    \
+        hipLaunchKernelGGL(scaled ? (atx_grouped<DD_, KJ_, true>) : (atx_grouped<DD_, KJ_, false>), grid, dim3(ATX_T), \
+                           0, stream, d);
     ATX_CASE(true, 16) ATX_CASE(false, 16) ATX_CASE(false, 32) ATX_CASE(false, 64)
 #undef ATX_CASE
     return hipGetLastError();

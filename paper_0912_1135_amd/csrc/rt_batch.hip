@@ -12,8 +12,11 @@
 // rtproj_batch_status.
 //
 // Per member the path is the one of rt_plan.hip with the two-stage pivoted
-// QR (S^T = Q0 R0 by shifted Cholesky QR, then the single-workgroup QRCP of
-// R0, one workgroup per member) so that no step needs a grid-wide barrier.
+// QR (S^T = Q0 R0 by shifted Cholesky QR, then the pivoted QR of R0).  That
+// QR runs either one workgroup per member (no grid-wide barrier; best for
+// many small members) or as the register-resident form with a group of
+// blocks per member, each group synchronized on its own (best for few large
+// members), whichever a cost estimate finds faster for the batch.
 #include "rt_plan_state.h"
 
 #include <map>
@@ -24,7 +27,8 @@ namespace {
 
 enum OpKind {
     OP_GEMM, OP_REDUCE, OP_SKETCH, OP_COPY, OP_SET0, OP_SET1, OP_SHIFT, OP_CHOL, OP_TRIINV, OP_QRCPWG, OP_RDIAG,
-    OP_FORMTP, OP_ZERO, OP_AB, OP_ABRED, OP_ATX, OP_DDUPD, OP_IOTA, OP_SCALE, OP_GEMM32, OP_RED32, OP_FINISH
+    OP_FORMTP, OP_ZERO, OP_AB, OP_ABRED, OP_ATX, OP_DDUPD, OP_IOTA, OP_GEMM32, OP_RED32, OP_FINISH,
+    OP_QRCPGRP
 };
 
 struct Op {
@@ -84,7 +88,10 @@ struct rtproj_batch_s {
     int64_t stage_calls[16] = {};
     int64_t max_m = 0, max_n = 0, max_l = 0;
     double *d_diag_all = nullptr;  // count x 8: |R| ends of R (4), of the Gram factor (4)
-    std::vector<double *> scaled;  // per member: A diag(d) when a column scaling is given
+    std::vector<const double *> cscale;  // per member: d of A diag(d) (borrowed), or null
+    rt::QrcpGrpShape qr_grp;        // grouped pivoted QR of R0 (per_launch 0: one workgroup per member)
+    double *d_qrw = nullptr;        // its candidate slots and columns, per member from qrw_off[i]
+    std::vector<int64_t> qrw_off;
     bool ready = false;
     // one program and arena per entry point, plus its captured graph
     struct Slot {
@@ -277,7 +284,8 @@ void rec_trsm(Program &P, rtproj_batch b, const std::vector<const double *> &Lp,
     }
 }
 
-void build_precondition(Program &P, rtproj_batch b, const double *const *A, const int64_t *lda)
+void build_precondition(Program &P, rtproj_batch b, const double *const *A, const int64_t *lda,
+                        const double *const *cs)
 {
     const int64_t cnt = b->count;
     // 1. sketches: one grouped launch pair per padded Fourier length and band
@@ -293,7 +301,7 @@ void build_precondition(Program &P, rtproj_batch b, const double *const *A, cons
             for (int64_t i : cls.second) {
                 rtproj_plan p = b->sub[i];
                 v.push_back(rt::SketchGroupArgs{p->sketch_tables(), A[i], lda[i], p->m, p->d_S, p->l, p->d_zbuf,
-                                                p->rows_chunk});
+                                                p->rows_chunk, cs[i]});
                 o.ss.max_n1 = std::max(o.ss.max_n1, p->tab.n1);
                 o.ss.max_n2 = std::max(o.ss.max_n2, p->tab.n2);
                 o.ss.max_rows_chunk = std::max(o.ss.max_rows_chunk, p->rows_chunk);
@@ -318,6 +326,7 @@ void build_precondition(Program &P, rtproj_batch b, const double *const *A, cons
         std::vector<unsigned *> flags;
         for (int64_t i = 0; i < cnt; ++i) {
             flags.push_back(reinterpret_cast<unsigned *>(b->sub[i]->d_err));
+            flags.push_back(b->sub[i]->d_sync);      // the grouped QR's arrival counter
             flags.push_back(b->sub[i]->d_sync + 2);
         }
         o.off = P.add(flags);
@@ -384,13 +393,39 @@ void build_precondition(Program &P, rtproj_batch b, const double *const *A, cons
         Op io{OP_IOTA, P.add(pv), (int)cnt};
         io.i0 = (int)b->max_m;
         P.push(io);
-        std::vector<rt::QrcpWgArgs> q(cnt);
-        for (int64_t i = 0; i < cnt; ++i) {
-            rtproj_plan p = b->sub[i];
-            q[i] = rt::QrcpWgArgs{p->d_R0, p->m, (int)p->m, (int)p->m, p->d_R, p->d_piv,
-                                  reinterpret_cast<int *>(p->d_sync + 2)};
+        if (b->qr_grp.per_launch > 0) {
+            // groups of blocks per member, as many members per launch as stay resident
+            const rt::QrcpGrpShape &sh = b->qr_grp;
+            for (int64_t c0 = 0; c0 < cnt; c0 += sh.per_launch) {
+                std::vector<rt::QrcpGrpArgs> q;
+                for (int64_t i = c0; i < std::min<int64_t>(cnt, c0 + sh.per_launch); ++i) {
+                    rtproj_plan p = b->sub[i];
+                    const int G = (int)((p->m + sh.nc - 1) / sh.nc);
+                    rt::QrcpWork w;
+                    w.counter = p->d_sync;
+                    w.flag = p->d_sync + 1;
+                    w.err = reinterpret_cast<int *>(p->d_sync + 2);
+                    w.slots = b->d_qrw + b->qrw_off[i];
+                    w.vbuf = w.slots + 4 * G;
+                    q.push_back(rt::QrcpGrpArgs{p->d_R0, p->m, (int)p->m, (int)p->m, p->d_R, p->d_piv, w, G});
+                }
+                Op o{OP_QRCPGRP, P.add(q), (int)q.size()};
+                o.i0 = sh.nc;
+                o.i1 = sh.rpt;
+                o.i2 = sh.threads;
+                o.dd = sh.gmax;
+                o.total = sh.per_launch;
+                P.push(o);
+            }
+        } else {
+            std::vector<rt::QrcpWgArgs> q(cnt);
+            for (int64_t i = 0; i < cnt; ++i) {
+                rtproj_plan p = b->sub[i];
+                q[i] = rt::QrcpWgArgs{p->d_R0, p->m, (int)p->m, (int)p->m, p->d_R, p->d_piv,
+                                      reinterpret_cast<int *>(p->d_sync + 2)};
+            }
+            P.push(Op{OP_QRCPWG, P.add(q), (int)cnt});
         }
-        P.push(Op{OP_QRCPWG, P.add(q), (int)cnt});
         std::vector<rt::MatGroupArgs> rd(cnt);
         for (int64_t i = 0; i < cnt; ++i)
             rd[i] = rt::MatGroupArgs{Rm[i], mm[i], (int)mm[i], (int)mm[i], 0.0, nullptr, b->d_diag_all + 8 * i};
@@ -422,6 +457,7 @@ void build_precondition(Program &P, rtproj_batch b, const double *const *A, cons
             a.A = p->d_Y; a.a_i = p->m; a.a_k = 1; a.a_lower = 1;
             a.B = A[i]; a.b_k = lda[i]; a.b_j = 1; a.b_gather = p->d_piv;
             a.C = p->d_W; a.c_i = p->n; a.c_j = 1;
+            a.c_cs = cs[i];  // R^{-T} Pi (A D) = (R^{-T} Pi A) D
             a.alpha = 1.0; a.ksplit = 1;
         }
         rec_gemm(P, g);
@@ -480,13 +516,31 @@ void rec_minv(Program &P, rtproj_batch b, const std::vector<int64_t> &k, const s
     }
 }
 
+// c = A B per member (A column-scaled by cs[i] when given).  The MFMA form
+// takes a scaled member as A (D B), with D B written to d_r first (B may be
+// d_r itself: scaled in place).
 void rec_ab(Program &P, rtproj_batch b, const std::vector<int64_t> &k, const double *const *A, const int64_t *lda,
-            const std::vector<const double *> &B, const std::vector<int64_t> &ldb, int dd)
+            const double *const *cs, std::vector<const double *> B, std::vector<int64_t> ldb, int dd)
 {
     const int64_t cnt = b->count;
     const int64_t kmax = *std::max_element(k.begin(), k.end());
     if (!dd && kmax >= RT_MFMA_KMIN) {
         // plain product with many right-hand sides: MFMA GEMM split over n
+        std::vector<rt::CopyGroupArgs> sc;
+        int64_t tot = 0;
+        for (int64_t i = 0; i < cnt; ++i) {
+            rtproj_plan p = b->sub[i];
+            if (!cs[i] || k[i] == 0) continue;
+            sc.push_back(rt::CopyGroupArgs{B[i], ldb[i], p->d_r, p->n, (int)p->n, (int)k[i], nullptr, 0, cs[i]});
+            tot = std::max(tot, p->n * k[i]);
+            B[i] = p->d_r;
+            ldb[i] = p->n;
+        }
+        if (!sc.empty()) {
+            Op o{OP_COPY, P.add(sc), (int)sc.size()};
+            o.total = tot;
+            P.push(o);
+        }
         std::vector<rt::GemmArgs> g(cnt);
         std::vector<rt::ReduceGroupArgs> r(cnt);
         for (int64_t i = 0; i < cnt; ++i) {
@@ -510,8 +564,8 @@ void rec_ab(Program &P, rtproj_batch b, const std::vector<int64_t> &k, const dou
     o.dd = dd;
     for (int64_t i = 0; i < cnt; ++i) {
         rtproj_plan p = b->sub[i];
-        v[i] = rt::AbGroupArgs{rt::ApplyArgs{(int)p->m, (int)p->n, (int)k[i], A[i], lda[i]}, B[i], ldb[i], p->ab_splits,
-                               p->d_ph, p->d_pl, p->d_c, p->m};
+        v[i] = rt::AbGroupArgs{rt::ApplyArgs{(int)p->m, (int)p->n, (int)k[i], A[i], lda[i], cs[i]}, B[i], ldb[i],
+                               p->ab_splits, p->d_ph, p->d_pl, p->d_c, p->m};
         o.i0 = std::max<int>(o.i0, (int)p->m);
         o.i1 = std::max<int>(o.i1, (int)k[i]);
         o.i2 = std::max<int>(o.i2, p->ab_splits);
@@ -531,12 +585,14 @@ void rec_atx(Program &P, rtproj_batch b, const std::vector<rt::AtxGroupArgs> &v,
     for (const auto &a : v) {
         o.total = std::max<int64_t>(o.total, a.a.n);
         o.i1 = std::max(o.i1, a.a.k);
+        if (a.a.cs) o.i0 = 1;  // some member is column-scaled
     }
     (void)b;
     P.push(o);
 }
 
-void build_project(Program &P, rtproj_batch b, const double *const *A, const int64_t *lda, const double *const *B,
+void build_project(Program &P, rtproj_batch b, const double *const *A, const int64_t *lda, const double *const *cs,
+                   const double *const *B,
                    const int64_t *ldb, const int64_t *k, double *const *Z, const int64_t *ldz, double *const *Y,
                    const int64_t *ldy, double *const *X, const int64_t *ldx)
 {
@@ -550,7 +606,7 @@ void build_project(Program &P, rtproj_batch b, const double *const *A, const int
     }
     // c = A b; x = M^{-1} c; xlo = 0
     P.stage = 7;
-    rec_ab(P, b, kk, A, lda, Bv, lb, 0);
+    rec_ab(P, b, kk, A, lda, cs, Bv, lb, 0);
     P.stage = 8;
     rec_minv(P, b, kk, c, xhi);
     {
@@ -564,10 +620,10 @@ void build_project(Program &P, rtproj_batch b, const double *const *A, const int
         std::vector<rt::AtxGroupArgs> a(cnt);
         for (int64_t i = 0; i < cnt; ++i) {
             rtproj_plan p = b->sub[i];
-            a[i] = rt::AtxGroupArgs{rt::ApplyArgs{(int)p->m, (int)p->n, (int)kk[i], A[i], lda[i]}, p->d_xhi, p->d_xlo,
+            a[i] = rt::AtxGroupArgs{rt::ApplyArgs{(int)p->m, (int)p->n, (int)kk[i], A[i], lda[i], cs[i]}, p->d_xhi, p->d_xlo,
                                     p->m, B[i], ldb[i], p->d_r, p->n, nullptr, 0, nullptr, 0};
         }
-        P.stage = 9;
+        P.stage = comp ? 9 : 13;  // compensated or plain residual
         if (comp || *std::max_element(kk.begin(), kk.end()) < RT_MFMA_KMIN) {
             rec_atx(P, b, a, comp);
         } else {
@@ -582,7 +638,7 @@ void build_project(Program &P, rtproj_batch b, const double *const *A, const int
                 tot = std::max(tot, p->n * kk[i]);
                 rt::GemmArgs &q = g[i];
                 q.M = (int)p->n; q.N = (int)kk[i]; q.K = (int)p->m;
-                q.A = A[i]; q.a_i = 1; q.a_k = lda[i];
+                q.A = A[i]; q.a_i = 1; q.a_k = lda[i]; q.c_rs = cs[i];  // (A D)^T x = D (A^T x)
                 q.B = p->d_xhi; q.b_k = 1; q.b_j = p->m;
                 q.C = p->d_r; q.c_i = 1; q.c_j = p->n;
                 q.alpha = -1.0; q.beta = 1.0; q.ksplit = 1;
@@ -593,8 +649,8 @@ void build_project(Program &P, rtproj_batch b, const double *const *A, const int
             P.push(o);
             rec_gemm(P, g);
         }
-        P.stage = 10;
-        rec_ab(P, b, kk, A, lda, r, nn, comp);
+        P.stage = comp ? 10 : 14;
+        rec_ab(P, b, kk, A, lda, cs, r, nn, comp);
         P.stage = 8;
         rec_minv(P, b, kk, c, dd);
         std::vector<rt::DdGroupArgs> u(cnt);
@@ -614,7 +670,7 @@ void build_project(Program &P, rtproj_batch b, const double *const *A, const int
             std::vector<rt::AtxGroupArgs> a(cnt);
             for (int64_t i = 0; i < cnt; ++i) {
                 rtproj_plan p = b->sub[i];
-                a[i] = rt::AtxGroupArgs{rt::ApplyArgs{(int)p->m, (int)p->n, (int)kk[i], A[i], lda[i]}, p->d_d, nullptr,
+                a[i] = rt::AtxGroupArgs{rt::ApplyArgs{(int)p->m, (int)p->n, (int)kk[i], A[i], lda[i], cs[i]}, p->d_d, nullptr,
                                         p->m, p->d_r, p->n, p->d_r, p->n, nullptr, 0, nullptr, 0};
             }
             rec_atx(P, b, a, 0);
@@ -624,7 +680,7 @@ void build_project(Program &P, rtproj_batch b, const double *const *A, const int
                 rtproj_plan p = b->sub[i];
                 rt::GemmArgs &q = g[i];
                 q.M = (int)p->n; q.N = (int)kk[i]; q.K = (int)p->m;
-                q.A = A[i]; q.a_i = 1; q.a_k = lda[i];
+                q.A = A[i]; q.a_i = 1; q.a_k = lda[i]; q.c_rs = cs[i];  // (A D)^T x = D (A^T x)
                 q.B = p->d_d; q.b_k = 1; q.b_j = p->m;
                 q.C = p->d_r; q.c_i = 1; q.c_j = p->n;
                 q.alpha = -1.0; q.beta = 1.0; q.ksplit = 1;
@@ -660,7 +716,7 @@ void build_project(Program &P, rtproj_batch b, const double *const *A, const int
             cp[i] = rt::CopyGroupArgs{B[i], ldb[i], p->d_r, p->n, (int)p->n, (int)kk[i], nullptr, 0};
             rt::GemmArgs &q = g[i];
             q.M = (int)p->n; q.N = (int)kk[i]; q.K = (int)p->m;
-            q.A = A[i]; q.a_i = 1; q.a_k = lda[i];
+            q.A = A[i]; q.a_i = 1; q.a_k = lda[i]; q.c_rs = cs[i];  // (A D)^T x = D (A^T x)
             q.B = p->d_xhi; q.b_k = 1; q.b_j = p->m;
             q.C = p->d_r; q.c_i = 1; q.c_j = p->n;
             q.alpha = -1.0; q.beta = 1.0; q.ksplit = 1;
@@ -679,18 +735,19 @@ void build_project(Program &P, rtproj_batch b, const double *const *A, const int
         of.total = tot;
         P.push(of);
     } else if (!from_r) {
-        P.stage = 11;
+        P.stage = final_comp ? 11 : 15;
         std::vector<rt::AtxGroupArgs> a(cnt);
         for (int64_t i = 0; i < cnt; ++i) {
             rtproj_plan p = b->sub[i];
-            a[i] = rt::AtxGroupArgs{rt::ApplyArgs{(int)p->m, (int)p->n, (int)kk[i], A[i], lda[i]}, p->d_xhi, p->d_xlo,
+            a[i] = rt::AtxGroupArgs{rt::ApplyArgs{(int)p->m, (int)p->n, (int)kk[i], A[i], lda[i], cs[i]}, p->d_xhi, p->d_xlo,
                                     p->m, B[i], ldb[i], nullptr, 0, Y ? Y[i] : nullptr, Y ? ldy[i] : 0,
                                     Z ? Z[i] : nullptr, Z ? ldz[i] : 0};
             if (!(Y && Y[i]) && !(Z && Z[i])) a[i].a.k = 0;
         }
         rec_atx(P, b, a, final_comp ? 1 : 0);
     }
-    P.stage = 11;
+    // x to the outputs, accounted to the final pass that ran
+    P.stage = (!from_r && final_comp) ? 11 : 15;
     if (X) {
         std::vector<rt::CopyGroupArgs> cp(cnt);
         int64_t tot = 0;
@@ -727,6 +784,11 @@ hipError_t run_op(const Op &o, const unsigned char *arena, hipStream_t s)
     case OP_CHOL: return rt::chol_diag_grouped_f64((const rt::CholGroupArgs *)d, o.count, NBB, o.i0, s);
     case OP_TRIINV: return rt::tri_diag_inv_grouped_f64((const rt::TriInvGroupArgs *)d, o.count, o.i0, NBB, s);
     case OP_QRCPWG: return rt::qrcp_wg_f64((const rt::QrcpWgArgs *)d, o.count, s);
+    case OP_QRCPGRP: {
+        rt::QrcpGrpShape sh;
+        sh.nc = o.i0; sh.rpt = o.i1; sh.threads = o.i2; sh.gmax = o.dd; sh.per_launch = (int)o.total;
+        return rt::qrcp_grp_f64((const rt::QrcpGrpArgs *)d, o.count, sh, s);
+    }
     case OP_RDIAG: return rt::rdiag_grouped_f64((const rt::MatGroupArgs *)d, o.count, s);
     case OP_FORMTP: return rt::form_tp_grouped_f64((const rt::MatGroupArgs *)d, o.count, o.total, s);
     case OP_ZERO:
@@ -734,10 +796,9 @@ hipError_t run_op(const Op &o, const unsigned char *arena, hipStream_t s)
         return hipGetLastError();
     case OP_AB: return rt::ab_partial_grouped_f64((const rt::AbGroupArgs *)d, o.count, o.i0, o.i1, o.i2, o.dd, s);
     case OP_ABRED: return rt::ab_reduce_grouped_f64((const rt::AbGroupArgs *)d, o.count, o.total, o.dd, s);
-    case OP_ATX: return rt::atx_grouped_f64((const rt::AtxGroupArgs *)d, o.count, o.total, o.i1, o.dd, s);
+    case OP_ATX: return rt::atx_grouped_f64((const rt::AtxGroupArgs *)d, o.count, o.total, o.i1, o.dd, o.i0, s);
     case OP_DDUPD: return rt::dd_update_grouped_f64((const rt::DdGroupArgs *)d, o.count, s);
     case OP_IOTA: return rt::iota_grouped_i32((const rt::MatGroupArgs *)d, o.count, o.i0, s);
-    case OP_SCALE: return rt::scale_cols_grouped_f64((const rt::ScaleGroupArgs *)d, o.count, s);
     case OP_GEMM32: return rt::gemm_f32_grouped_lower((const rt::GemmMxArgs *)d, o.count, o.i0, o.i1, s);
     case OP_RED32: return rt::reduce_f32_grouped((const rt::ReduceF32GroupArgs *)d, o.count, o.i0, s);
     case OP_FINISH: return rt::finish_cols_grouped_f64((const rt::FinishGroupArgs *)d, o.count, o.total, s);
@@ -841,6 +902,25 @@ rtproj_status run_program(rtproj_batch b, rtproj_batch_s::Slot &slot, const Prog
     return RTPROJ_OK;
 }
 
+// Whether the grouped pivoted QR of the R0 factors beats one workgroup per
+// member, from per-step costs measured on this part: a workgroup streams its
+// trailing matrix through L2 at every step (read and write at about 27 GB/s
+// per workgroup, plus about 1.5 us of block barriers), while a group of
+// blocks is bound by its exchange between blocks (about 8 us per step at
+// m = 1024) and runs as many members at once as stay resident.
+bool grouped_qr_faster(const int64_t *m, int64_t count, int cu, const rt::QrcpGrpShape &sh)
+{
+    double wg = 0.0, grp = 0.0;
+    for (int64_t i = 0; i < count; ++i) {
+        const double mi = (double)m[i];
+        wg = std::max(wg, mi * mi * mi * 16.0 / (3.0 * 27e9) + 1.5e-6 * mi);
+        grp = std::max(grp, 8e-6 * mi);
+    }
+    wg *= (double)((count + cu - 1) / cu);
+    grp *= (double)((count + sh.per_launch - 1) / sh.per_launch);
+    return grp < wg;
+}
+
 }  // namespace
 
 extern "C" {
@@ -855,6 +935,7 @@ rtproj_status rtproj_batch_create(int64_t count, const int64_t *m, const int64_t
     for (int64_t i = 0; i < count; ++i) {
         if (m[i] < 1 || n[i] < m[i] || l[i] < m[i] || l[i] > n[i])
             return fail(RTPROJ_ERR_INVALID_ARG, "member " + std::to_string(i) + ": need 1 <= m <= l <= n");
+        // (the grouped form of the QR of R0 reaches no further on 256 compute units)
         if (m[i] > rt::qrcp_wg_max_cols() || m[i] > rt::qrcp_wg_max_rows())
             return fail(RTPROJ_ERR_UNSUPPORTED, "member " + std::to_string(i) + ": m above the batched QR limit");
     }
@@ -878,6 +959,32 @@ rtproj_status rtproj_batch_create(int64_t count, const int64_t *m, const int64_t
         rtproj_batch_destroy(b);
         return fail(RTPROJ_ERR_ALLOC, "device allocation failed");
     }
+    // the pivoted QR of R0: one workgroup per member or a group of blocks per member
+    {
+        const int cu = b->sub[0]->cu_count;
+        const bool wg_ok = b->max_m <= rt::qrcp_wg_max_cols() && b->max_m <= rt::qrcp_wg_max_rows();
+        rt::QrcpGrpShape sh;
+        const bool grp_ok = rt::qrcp_grp_shape((int)b->max_m, (int)b->max_m, cu, &sh);
+        if (!wg_ok && !grp_ok) {
+            rtproj_batch_destroy(b);
+            return fail(RTPROJ_ERR_UNSUPPORTED, "a member's m is above the batched QR limits");
+        }
+        if (grp_ok && (!wg_ok || grouped_qr_faster(m, count, cu, sh))) {
+            b->qr_grp = sh;
+            b->qrw_off.resize(count);
+            int64_t tot = 0;
+            for (int64_t i = 0; i < count; ++i) {
+                const int64_t G = (m[i] + sh.nc - 1) / sh.nc;
+                b->qrw_off[i] = tot;
+                tot += 4 * G + 2 * G * m[i];
+            }
+            if (hipMalloc((void **)&b->d_qrw, (size_t)tot * sizeof(double)) != hipSuccess) {
+                b->d_qrw = nullptr;
+                rtproj_batch_destroy(b);
+                return fail(RTPROJ_ERR_ALLOC, "device allocation failed");
+            }
+        }
+    }
     *out = b;
     return RTPROJ_OK;
 }
@@ -890,8 +997,7 @@ rtproj_status rtproj_batch_destroy(rtproj_batch b)
     for (rtproj_plan p : b->sub)
         if (p) rtproj_plan_destroy(p);
     if (b->d_diag_all) (void)hipFree(b->d_diag_all);
-    for (double *q : b->scaled)
-        if (q) (void)hipFree(q);
+    if (b->d_qrw) (void)hipFree(b->d_qrw);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     delete b;
     return RTPROJ_OK;
@@ -944,7 +1050,7 @@ rtproj_status rtproj_batch_info(rtproj_batch b, rtproj_info *out)
     std::memset(out, 0, sizeof(*out));
     out->m = b->max_m; out->n = b->max_n; out->l = b->max_l;
     out->refine_steps = b->plain_steps + b->comp_steps;
-    out->qr_mode = RTPROJ_QR_TWO_STAGE_WG;
+    out->qr_mode = b->qr_grp.per_launch > 0 ? RTPROJ_QR_TWO_STAGE : RTPROJ_QR_TWO_STAGE_WG;
     for (int s = 0; s < 16; ++s) { out->t_stage_ms[s] = b->t_stage_ms[s]; out->stage_calls[s] = b->stage_calls[s]; }
     return RTPROJ_OK;
 }
@@ -959,33 +1065,19 @@ rtproj_status rtproj_batch_precondition_scaled(rtproj_batch b, const double *con
         if (lda[i] < b->sub[i]->n) return fail(RTPROJ_ERR_INVALID_ARG, "member " + std::to_string(i) + ": lda < n");
     }
     b->ready = false;
-    // members with a column scaling work on their own copy A diag(d)
-    std::vector<const double *> Aw(A, A + b->count);
-    std::vector<int64_t> lw(lda, lda + b->count);
-    std::vector<rt::ScaleGroupArgs> sc;
-    if (col_scale) {
-        if (b->scaled.empty()) b->scaled.assign(b->count, nullptr);
-        for (int64_t i = 0; i < b->count; ++i) {
-            if (!col_scale[i]) continue;
-            rtproj_plan p = b->sub[i];
-            if (!b->scaled[i]) RT_HIP(hipMalloc((void **)&b->scaled[i], (size_t)p->m * p->n * sizeof(double)));
-            sc.push_back(rt::ScaleGroupArgs{A[i], lda[i], col_scale[i], b->scaled[i], p->n, (int)p->m, (int)p->n});
-            Aw[i] = b->scaled[i];
-            lw[i] = p->n;
-        }
-    }
+    // a column-scaled member borrows d as it borrows A: every pass that reads
+    // A applies the scaling itself, and no scaled copy is made
+    b->cscale.assign(b->count, nullptr);
+    if (col_scale)
+        for (int64_t i = 0; i < b->count; ++i) b->cscale[i] = col_scale[i];
     b->prec_used = b->precision;
     Program P;
-    if (!sc.empty()) {
-        P.stage = 0;
-        P.push(Op{OP_SCALE, P.add(sc), (int)sc.size()});
-    }
-    build_precondition(P, b, Aw.data(), lw.data());
+    build_precondition(P, b, A, lda, b->cscale.data());
     rtproj_status st = run_program(b, b->pre, P);
     if (st != RTPROJ_OK) return st;
     for (int64_t i = 0; i < b->count; ++i) {
-        b->sub[i]->A = Aw[i];
-        b->sub[i]->lda = lw[i];
+        b->sub[i]->A = A[i];
+        b->sub[i]->lda = lda[i];
     }
     b->ready = true;
     return RTPROJ_OK;
@@ -1052,7 +1144,7 @@ rtproj_status rtproj_batch_project_all(rtproj_batch b, const double *const *B, c
     std::vector<int64_t> lda(b->count);
     for (int64_t i = 0; i < b->count; ++i) { A[i] = b->sub[i]->A; lda[i] = b->sub[i]->lda; }
     Program P;
-    build_project(P, b, A.data(), lda.data(), B, ldb, k, Z, ldz, Y, ldy, X, ldx);
+    build_project(P, b, A.data(), lda.data(), b->cscale.data(), B, ldb, k, Z, ldz, Y, ldy, X, ldx);
     b->last_steps = std::min(b->plain_steps + b->comp_steps, RT_MAX_STEPS);
     b->last_plain = std::min(b->plain_steps, b->last_steps);
     b->last_k.assign(k, k + b->count);
@@ -1091,6 +1183,7 @@ rtproj_status rtproj_batch_status(rtproj_batch b, int *per_member)
             p->info.refine_status = st;
         }
         if (qerr[i] || cerr[i] || !(d[2] > (double)p->m * std::ldexp(1.0, -52) * d[3])) st = RTPROJ_ERR_RANK;
+        if (qerr[i] == 1) st = RTPROJ_ERR_DEVICE;  // the grouped QR's barrier timed out
         p->info.kappa_est = d[2] > 0 ? d[3] / d[2] : INFINITY;
         p->info.rdiag_min = d[2];
         p->info.gram_cond_est = d[6] > 0 ? d[7] / d[6] : INFINITY;
@@ -1100,10 +1193,14 @@ rtproj_status rtproj_batch_status(rtproj_batch b, int *per_member)
         p->info.gram_bits = b->prec_used == RTPROJ_PREC_MIXED_FP32 ? 32 : 64;
         p->info.sketch_bits = p->info.w_bits = 64;
         if (per_member) per_member[i] = st;
-        if (st == RTPROJ_ERR_RANK || (st != RTPROJ_OK && worst == RTPROJ_OK)) worst = st;
+        // precedence: rank deficiency, then a device error, then non-convergence
+        if (st == RTPROJ_ERR_RANK || (st == RTPROJ_ERR_DEVICE && worst != RTPROJ_ERR_RANK) ||
+            (st != RTPROJ_OK && worst == RTPROJ_OK))
+            worst = st;
     }
     if (worst == RTPROJ_ERR_RANK)
         return fail(worst, "at least one member is rank deficient or its factorization broke down");
+    if (worst == RTPROJ_ERR_DEVICE) return fail(worst, "pivoted QR: a member's block barrier timed out");
     if (worst != RTPROJ_OK) return fail(worst, "the refinement of at least one member did not converge");
     return RTPROJ_OK;
 }
@@ -1123,7 +1220,7 @@ rtproj_status rtproj_batch_member_info(rtproj_batch b, int64_t i, rtproj_info *o
     out->refine_steps = b->plain_steps + b->comp_steps;
     out->refine_plain = b->plain_steps;
     out->refine_comp = b->comp_steps;
-    out->qr_mode = RTPROJ_QR_TWO_STAGE_WG;
+    out->qr_mode = b->qr_grp.per_launch > 0 ? RTPROJ_QR_TWO_STAGE : RTPROJ_QR_TWO_STAGE_WG;
     return RTPROJ_OK;
 }
 

@@ -65,6 +65,8 @@ struct GemmArgs {
     int tile_n;       // with tile: 0 square; 128 (tile 64) or 64 (tile 128) for a 64 x 128 or 128 x 64 tile
     int order;        // 0: tile order chosen from the shape; 1 plain; 2 XCD-grouped
     int c_f32;        // 1: C is binary32 (each result rounded once; beta must be 0, no K split)
+    // optional output scalings: C[i][j] = alpha (A B)[i][j] c_rs[i] c_cs[j] (+ beta C)
+    const double *c_rs = nullptr, *c_cs = nullptr;
 };
 
 // Launches GEMM with 64x64 or 128x128 tiles (chosen from M, N unless
@@ -193,6 +195,7 @@ hipError_t sketch_f64(const SketchTables &t, const double *A, int64_t lda, int64
 struct SketchGroupArgs {
     SketchTables t; const double *A; int64_t lda, m; double *S; int64_t lds;
     double *zbuf; int64_t rows_chunk;
+    const double *cs = nullptr;  // optional: sketch of A diag(cs), each element scaled on load
 };
 struct SketchGroupShape { int64_t max_n1, max_n2, max_rows_chunk; int chunks; };
 hipError_t sketch_grouped_f64(const SketchGroupArgs *d, int count, const SketchGroupShape &sh, hipStream_t stream);
@@ -230,6 +233,24 @@ hipError_t zero_u32(unsigned *p, int n, hipStream_t stream);
 bool qrcp_reg_shape(int rows, int cols, int cu_count, int *nc, int *rpt, int *blocks, int *threads);
 hipError_t qrcp_reg_f64(const double *S, int64_t lds, int rows, int cols, double *R, int32_t *piv,
                         const QrcpWork &w, int cu_count, hipStream_t stream);
+
+// Grouped register-resident form for a batch: member i is factored by its own
+// group of G_i = ceil(cols_i / nc) blocks (the shape chosen for the largest
+// member), synchronized only among themselves through the member's own
+// workspace w (counter zeroed beforehand; slots 4 G_i and vbuf 2 G_i rows_i
+// doubles).  A launch holds at most per_launch members, so that every group
+// is resident at once; the same outputs and error codes as qrcp_reg_f64.
+struct QrcpGrpArgs {
+    const double *S; int64_t lds; int rows, cols;
+    double *R; int32_t *piv;
+    QrcpWork w;
+    int G;
+};
+struct QrcpGrpShape {
+    int nc = 0, rpt = 0, threads = 0, gmax = 0, per_launch = 0;
+};
+bool qrcp_grp_shape(int max_rows, int max_cols, int cu_count, QrcpGrpShape *sh);
+hipError_t qrcp_grp_f64(const QrcpGrpArgs *d_args, int count, const QrcpGrpShape &sh, hipStream_t stream);
 
 // Column-pivoted QR of one matrix per workgroup (no grid synchronization):
 // M is column-major rows x cols (ld ldm) and is overwritten; R (cols x cols
@@ -318,6 +339,9 @@ hipError_t sum_blocks_sqrt_f64(const double *bsum, int nb, double *out, hipStrea
 struct ApplyArgs {
     int m, n, k;
     const double *A; int64_t lda;
+    // optional column scaling: element (i, t) of the operand is the binary64
+    // product A[i][t] * cs[t] (a column-scaled A without a scaled copy)
+    const double *cs = nullptr;
 };
 hipError_t ab_partial_f64(const ApplyArgs &a, const double *B, int64_t ldb, int splits,
                           double *part_hi, double *part_lo, int dd, hipStream_t stream);
@@ -357,13 +381,17 @@ struct AtxGroupArgs {      // as atx_f64
     ApplyArgs a; const double *xhi, *xlo; int64_t ldx; const double *B; int64_t ldb;
     double *Rout; int64_t ldr; double *Y; int64_t ldy; double *Z; int64_t ldz;
 };
-hipError_t atx_grouped_f64(const AtxGroupArgs *d, int count, int64_t max_n, int max_k, int dd, hipStream_t stream);
+// scaled: some member has a column scaling (a.cs)
+hipError_t atx_grouped_f64(const AtxGroupArgs *d, int count, int64_t max_n, int max_k, int dd, int scaled,
+                           hipStream_t stream);
 struct DdGroupArgs { double *xhi, *xlo; const double *D; int total; double *norms; };
 hipError_t dd_update_grouped_f64(const DdGroupArgs *d, int count, hipStream_t stream);
-struct ScaleGroupArgs { const double *A; int64_t lda; const double *d; double *out; int64_t ldo; int m, n; };
-// out = A diag(d) per problem (column scaling)
-hipError_t scale_cols_grouped_f64(const ScaleGroupArgs *d, int count, hipStream_t stream);
-struct CopyGroupArgs { const double *src; int64_t lds; double *dst; int64_t ldd; int rows, cols; double *zero_out; int64_t ldz; };
+// dst = src (column-major rows x cols; rs: optional row scaling, dst[i][j] =
+// src[i][j] * rs[i], src may be dst); zero_out: optional, set to zero alike
+struct CopyGroupArgs {
+    const double *src; int64_t lds; double *dst; int64_t ldd; int rows, cols; double *zero_out; int64_t ldz;
+    const double *rs = nullptr;
+};
 // Y = B - r and Z = r (column-major rows x cols; Y or Z null to skip; either may be B)
 struct FinishGroupArgs { const double *r; int64_t ldr; const double *B; int64_t ldb; double *Y; int64_t ldy; double *Z; int64_t ldz; int rows, cols; };
 hipError_t finish_cols_f64(const FinishGroupArgs &g, hipStream_t stream);

@@ -206,11 +206,13 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmArgs &g, int bx, int by,
                 const int j = j0 + wn * (BN / 2) + b * 16 + mfma16_col(lane);
                 if (i < g.M && j < g.N) {
                     const int64_t off = (int64_t)i * g.c_i + (int64_t)j * g.c_j;
+                    double v = g.alpha * acc[a][b][r];
+                    if (g.c_rs) v *= g.c_rs[i];
+                    if (g.c_cs) v *= g.c_cs[j];
                     if (g.c_f32) {
-                        reinterpret_cast<float *>(g.C)[off] = (float)(g.alpha * acc[a][b][r]);
+                        reinterpret_cast<float *>(g.C)[off] = (float)v;
                     } else {
                         double *p = C + off;
-                        double v = g.alpha * acc[a][b][r];
                         if (use_beta) v += g.beta * *p;
                         *p = v;
                     }

@@ -411,16 +411,18 @@ __device__ __forceinline__ void local_best(double s, int ncol, unsigned done, do
     bc = n >= 0.0 ? c : -1;
 }
 
+// Block g of the G blocks that factor one matrix: the whole factorization
+// with the G blocks' only contact through the workspace w.
 template <int NC, int RPT, int TT>
-__global__ __launch_bounds__(TT) void qrcp_reg_kernel(const double *S, int64_t lds, int rows, int cols, double *R,
-                                                        int32_t *piv, QrcpWork w, int G)
+__device__ __forceinline__ void reg_qr_body(const double *S, int64_t lds, int rows, int cols, double *R, int32_t *piv,
+                                            const QrcpWork &w, int G, int g)
 {
     static_assert(NC <= 32 && (NC & (NC - 1)) == 0, "done mask, lane-per-column sums, power of two");
     constexpr int TW = TT / 64;
     __shared__ double red[2][4 * TW][NC];
     __shared__ double s_pn;
     __shared__ int s_p, s_abort;
-    const int g = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+    const int tid = threadIdx.x, lane = tid & 63;
     int ncol = 0;
     while (ncol < NC && g + G * ncol < cols) ++ncol;
     double *hdr = w.slots;  // 2 x G x 2: candidate (norm^2, column)
@@ -575,6 +577,24 @@ __global__ __launch_bounds__(TT) void qrcp_reg_kernel(const double *S, int64_t l
 }
 
 template <int NC, int RPT, int TT>
+__global__ __launch_bounds__(TT) void qrcp_reg_kernel(const double *S, int64_t lds, int rows, int cols, double *R,
+                                                        int32_t *piv, QrcpWork w, int G)
+{
+    reg_qr_body<NC, RPT, TT>(S, lds, rows, cols, R, piv, w, G, blockIdx.x);
+}
+
+// Grouped form: member blockIdx.y is factored by blocks x < its G (the grid is
+// as wide as the largest member's group; the rest leave at once).  Each
+// member synchronizes only its own group, through its own workspace.
+template <int NC, int RPT, int TT>
+__global__ __launch_bounds__(TT) void qrcp_grp_kernel(const QrcpGrpArgs *args)
+{
+    const QrcpGrpArgs a = args[blockIdx.y];
+    if ((int)blockIdx.x >= a.G || a.rows <= 0 || a.cols <= 0) return;
+    reg_qr_body<NC, RPT, TT>(a.S, a.lds, a.rows, a.cols, a.R, a.piv, a.w, a.G, blockIdx.x);
+}
+
+template <int NC, int RPT, int TT>
 hipError_t launch_reg(const double *S, int64_t lds, int rows, int cols, double *R, int32_t *piv, const QrcpWork &w,
                       int G, hipStream_t stream)
 {
@@ -679,6 +699,52 @@ hipError_t qrcp_reg_f64(const double *S, int64_t lds, int rows, int cols, double
     RQ_CASE(4, 16)
 #undef RQ_CASE
     return hipErrorInvalidValue;
+}
+
+// The grouped form's kernel for a (columns per block, rows per thread,
+// threads) shape; null when there is none.
+static const void *grp_kernel_for(int nc, int rpt, int tt)
+{
+#define RG_CASE(NC_, RPT_)                                                                                        \
+    if (nc == NC_ && rpt == RPT_)                                                                                 \
+        return tt == 256 ? (const void *)qrcp_grp_kernel<NC_, RPT_, 256>                                          \
+                         : (const void *)qrcp_grp_kernel<NC_, RPT_, 512>;
+    RG_CASE(4, 1) RG_CASE(8, 1) RG_CASE(16, 1) RG_CASE(32, 1)
+    RG_CASE(4, 2) RG_CASE(8, 2) RG_CASE(16, 2)
+    RG_CASE(4, 4) RG_CASE(8, 4) RG_CASE(16, 4)
+    RG_CASE(4, 8) RG_CASE(8, 8)
+    RG_CASE(4, 16)
+#undef RG_CASE
+    return nullptr;
+}
+
+bool qrcp_grp_shape(int max_rows, int max_cols, int cu_count, QrcpGrpShape *sh)
+{
+    int nc, rpt, g, tt;
+    if (!qrcp_reg_shape(max_rows, max_cols, cu_count, &nc, &rpt, &g, &tt)) return false;
+    const void *fn = grp_kernel_for(nc, rpt, tt);
+    if (!fn) return false;
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, tt, 0) != hipSuccess || per < 1) return false;
+    sh->nc = nc;
+    sh->rpt = rpt;
+    sh->threads = tt;
+    sh->gmax = g;
+    // members whose groups are resident together (a group's blocks wait on
+    // each other, so a launch never holds more than the device keeps resident)
+    sh->per_launch = std::max(1, per * cu_count / g);
+    return true;
+}
+
+hipError_t qrcp_grp_f64(const QrcpGrpArgs *d_args, int count, const QrcpGrpShape &sh, hipStream_t stream)
+{
+    if (count <= 0) return hipSuccess;
+    if (count > sh.per_launch) return hipErrorInvalidValue;
+    const void *fn = grp_kernel_for(sh.nc, sh.rpt, sh.threads);
+    if (!fn) return hipErrorInvalidValue;
+    const QrcpGrpArgs *a = d_args;
+    void *args[] = {(void *)&a};
+    return hipLaunchKernel(fn, dim3(sh.gmax, count), dim3(sh.threads), args, 0, stream);
 }
 
 hipError_t zero_u32(unsigned *p, int n, hipStream_t stream)

@@ -148,7 +148,7 @@ constexpr int SK_U = 8;  // gathers in flight per thread
 template <typename R>
 __device__ __forceinline__ void sketch_pass1_body(const SketchTables &t, const double *A, int64_t lda, int64_t m,
                                                   int64_t row0, cpx<R> *zbuf, int tw_cols, int bits1, int bx,
-                                                  int64_t pair)
+                                                  int64_t pair, const double *cs = nullptr)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     typedef cpx<R> cplx;
@@ -193,7 +193,9 @@ __device__ __forceinline__ void sketch_pass1_body(const SketchTables &t, const d
                 const int64_t src = (int64_t)s_sigma[t1] * n2 + u0 + j;
                 dst[q] = j * ld1 + (int)bitrev((unsigned)t1, bits1);
                 if (src < t.n) {
-                    sg[q] = (double)t.sign[src];
+                    // the sign of D, times the column scaling when A is scaled
+                    // (sign * (a * c) rounds as a * (sign * c))
+                    sg[q] = cs ? (double)t.sign[src] * cs[src] : (double)t.sign[src];
                     v0[q] = a0[src];
                     if (has1) v1[q] = a1[src];
                 }
@@ -313,7 +315,7 @@ __global__ __launch_bounds__(256) void sketch_pass1_grouped(const SketchGroupArg
     if ((int64_t)blockIdx.y >= (rows + 1) / 2) return;  // pairs of this member's chunk only
     const SketchGeom geo = sketch_geom<R>(g.t);
     sketch_pass1_body<R>(g.t, g.A, g.lda, g.m, row0, reinterpret_cast<cpx<R> *>(g.zbuf), geo.tw_cols, geo.bits1,
-                         blockIdx.x, blockIdx.y);
+                         blockIdx.x, blockIdx.y, g.cs);
 }
 
 template <typename R>

@@ -112,13 +112,17 @@ def test_batch_member_equals_single_plan(rt):
     bt.close()
 
 
-def test_batch_column_scaled_members_match_oracle(rt):
+@pytest.mark.parametrize("k", [3, 40])
+def test_batch_column_scaled_members_match_oracle(rt, k):
     """Interior-point shape: one base A, member t works on A diag(d_t) with
-    d_t = 10^U(-6, 6); each member against the oracle on the scaled matrix."""
+    d_t = 10^U(-6, 6), the scaling applied by every pass that reads A (no
+    scaled copy); each member against the oracle on the scaled matrix formed
+    on the host.  k = 40 takes the MFMA forms of the plain products (D b
+    formed first, scaled GEMM outputs), k = 3 the vector forms."""
     m, n, l, steps = 40, 1500, 160, 4
     A = synth.make_problem(m, n, 1e4, 77)
     D = synth.make_scalings(n, steps, 77)
-    Bs = [synth.make_rhs(n, 3, 900 + t) for t in range(steps)]
+    Bs = [synth.make_rhs(n, k, 900 + t) for t in range(steps)]
     bt = rt.Batch([m] * steps, [n] * steps, [l] * steps, 13)
     bt.set_graph(True)
     At = torch.from_numpy(A).to(dev())
@@ -173,4 +177,45 @@ def test_batch_binary32_gram_matches_oracle(rt, graph):
     with pytest.raises(rt.RtprojError) as err:
         bt.set_precision(rt.PREC_MIXED_BF16)
     assert err.value.status == 7
+    bt.close()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_grouped_pivoted_qr_matches_oracle(rt, graph):
+    """Few large members: the pivoted QR of R0 runs as a group of blocks per
+    member (each group with its own barrier; chosen over one workgroup per
+    member for these sizes).  The second call replays the captured graphs, so
+    the groups' arrival counters must start from zero again."""
+    ms = [640, 300, 520]
+    ns = [8 * m for m in ms]
+    ls = [4 * m for m in ms]
+    As = [synth.make_problem(m, n, 1e8, 1300 + i) for i, (m, n) in enumerate(zip(ms, ns))]
+    Bs = [synth.make_rhs(n, 2, 1400 + i) for i, n in enumerate(ns)]
+    bt = rt.Batch(ms, ns, ls, 23)
+    bt.set_graph(graph)
+    At = [torch.from_numpy(A).to(dev()) for A in As]
+    Bt = [torch.from_numpy(B).to(dev()) for B in Bs]
+    for rep in range(2):
+        bt.precondition(At)
+        assert bt.info()["qr_mode"] == rt.QR_TWO_STAGE
+        Z, Y, X = bt.project_all(Bt)
+        assert bt.status() == [0] * len(As)
+        for i in range(len(As)):
+            e = check_member(As[i], Bs[i], Z[i].cpu().numpy(), Y[i].cpu().numpy(), X[i].cpu().numpy())
+            print(f"rep {rep} member {i} m {ms[i]}: e_z {e[0]:.3g} e_p {e[1]:.3g} e_x {e[2]:.3g}")
+            assert max(e) <= TOL, (rep, i, e)
+    bt.close()
+
+
+def test_batch_grouped_pivoted_qr_flags_rank_deficient_member(rt):
+    ms = [520, 600]
+    ns = [6 * m for m in ms]
+    ls = [4 * m for m in ms]
+    As = [synth.make_problem(m, n, 1e3, 1500 + i) for i, (m, n) in enumerate(zip(ms, ns))]
+    As[1][-1] = As[1][0]  # duplicate row: rank m - 1
+    bt = rt.Batch(ms, ns, ls, 29)
+    bt.precondition([torch.from_numpy(A).to(dev()) for A in As])
+    assert bt.info()["qr_mode"] == rt.QR_TWO_STAGE
+    st = bt.status()
+    assert st[1] == 5 and st[0] == 0, st
     bt.close()
