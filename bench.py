@@ -48,6 +48,11 @@ PEAK_FP64_TFLOPS = 78.6          # matrix and vector (FMA = 2 flops)
 PEAK_FP32_TFLOPS = 157.3         # MFMA binary32
 PEAK_BF16_TFLOPS = 2500.0        # MFMA bfloat16, dense
 PEAK_FP64_VALU_TOPS = 39.3       # FP64 VALU instructions/s: 256 CU x 64 lanes x 2.4 GHz
+PEAK_INT8_TOPS = 5000.0          # MFMA int8, dense
+# digit pairs the integer compensated products multiply: 13 signed 6-bit
+# digits per operand, pairs (s, t) with s + t <= 12
+OZ_PAIRS = sum(d + 1 for d in range(13))
+COMP_INT8 = 2
 
 PRECISIONS = {"fp64": 0, "mixed_fp32": 1, "mixed_bf16": 2}
 
@@ -57,12 +62,14 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def stage_work(name, dims, prec="fp64", w_bits=64, inv=(2, 0)):
+def stage_work(name, dims, prec="fp64", w_bits=64, inv=(2, 0), comp=1):
     """Algorithmic work per launch of a stage summed over the problems in
     `dims` (a list of (m, n, l, k)): (bound, amount, kind, peak).  `inv` is
-    (method, iterations) of the Gram's inverse: 1 Newton-Schulz, 2 Cholesky."""
+    (method, iterations) of the Gram's inverse: 1 Newton-Schulz, 2 Cholesky;
+    `comp` the form of the compensated products: 1 Dot2, 2 int8 digits."""
     tot = 0.0
     ns = inv[0] == 1
+    int8 = comp == COMP_INT8 and name in ("refine_atx", "refine_ab")
     for (m, n, l, k) in dims:
         if name == "sketch":
             tot += 8.0 * m * n + 8.0 * m * l                               # read A, write S
@@ -83,19 +90,23 @@ def stage_work(name, dims, prec="fp64", w_bits=64, inv=(2, 0)):
         elif name == "gram_syrk":
             tot += 1.0 * m * (m + 1) * n
         elif name in ("ab", "refine_atx_plain", "refine_ab_plain", "final_atx_plain"):
-            if k >= 32 and name != "ab":
+            if k >= 32:
                 tot += 2.0 * m * n * k                                      # MFMA GEMM flops
             else:
                 tot += 8.0 * m * n + 8.0 * n * k                            # read A and B (or x and r)
+        elif int8:
+            tot += OZ_PAIRS * 2.0 * m * n * k                               # int8 products of digit pairs
         elif name in ("refine_atx", "refine_ab", "final_atx"):
             tot += 10.0 * m * n * k                                         # Dot2: 10 FP64 ops per term
         else:
             return None, 0.0, None, None
     plain_pass = name in ("refine_atx_plain", "refine_ab_plain", "final_atx_plain")
-    if name in ("sketch", "ab") or (name == "minv_form" and ns) or (plain_pass and dims[0][3] < 32):
+    if name == "sketch" or (name == "minv_form" and ns) or ((plain_pass or name == "ab") and dims[0][3] < 32):
         return "hbm", tot, "bytes", PEAK_HBM_GBS
     if name == "qrcp":
         return "alu", tot, "flops", PEAK_FP64_TFLOPS
+    if int8:
+        return "mfma", tot, "ops", PEAK_INT8_TOPS
     if name in ("refine_atx", "refine_ab", "final_atx"):
         return "alu", tot, "ops", PEAK_FP64_VALU_TOPS
     if name == "gram_syrk" and prec == "mixed_bf16":
@@ -162,7 +173,8 @@ def stage_table(info, steps, dims, prec, w_bits):
             continue
         d = {"ms_per_step": tot / steps, "ms_per_launch": tot / calls, "launches_per_step": calls / steps}
         bound, amt, kind, peak = stage_work(name, dims, prec, w_bits,
-                                            (info.get("inverse", 2), info.get("inverse_iters", 0)))
+                                            (info.get("inverse", 2), info.get("inverse_iters", 0)),
+                                            info.get("comp_method", 1))
         if bound is not None:
             sec = d["ms_per_launch"] / 1e3
             if bound == "hbm":
