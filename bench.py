@@ -70,6 +70,9 @@ def stage_work(name, dims, prec="fp64", w_bits=64, inv=(2, 0), comp=1):
     tot = 0.0
     ns = inv[0] == 1
     int8 = comp == COMP_INT8 and name in ("refine_atx", "refine_ab")
+    # plain products take the MFMA form for every problem once the largest
+    # k reaches 32 (a batch decides for all its members at once)
+    mfma_k = max(d[3] for d in dims) >= 32
     for (m, n, l, k) in dims:
         if name == "sketch":
             tot += 8.0 * m * n + 8.0 * m * l                               # read A, write S
@@ -90,7 +93,7 @@ def stage_work(name, dims, prec="fp64", w_bits=64, inv=(2, 0), comp=1):
         elif name == "gram_syrk":
             tot += 1.0 * m * (m + 1) * n
         elif name in ("ab", "refine_atx_plain", "refine_ab_plain", "final_atx_plain"):
-            if k >= 32:
+            if mfma_k:
                 tot += 2.0 * m * n * k                                      # MFMA GEMM flops
             else:
                 tot += 8.0 * m * n + 8.0 * n * k                            # read A and B (or x and r)
@@ -101,7 +104,7 @@ def stage_work(name, dims, prec="fp64", w_bits=64, inv=(2, 0), comp=1):
         else:
             return None, 0.0, None, None
     plain_pass = name in ("refine_atx_plain", "refine_ab_plain", "final_atx_plain")
-    if name == "sketch" or (name == "minv_form" and ns) or ((plain_pass or name == "ab") and dims[0][3] < 32):
+    if name == "sketch" or (name == "minv_form" and ns) or ((plain_pass or name == "ab") and not mfma_k):
         return "hbm", tot, "bytes", PEAK_HBM_GBS
     if name == "qrcp":
         return "alu", tot, "flops", PEAK_FP64_TFLOPS
