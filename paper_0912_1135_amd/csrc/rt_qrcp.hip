@@ -3,12 +3,15 @@
 // remaining column with the largest trailing 2-norm (ties: lowest index).
 //
 // One cooperative launch.  Block g owns columns j = g, g + G, g + 2G, ... of
-// the input and keeps them for the whole factorization in LDS (or, for
-// sketches too tall for LDS, in a private slice of global memory).  Each step
-// costs ONE grid barrier:
+// the input and keeps them for the whole factorization in registers (or in
+// LDS, or, for sketches too tall for LDS, in a private slice of global
+// memory).  Each step costs ONE exchange between the blocks:
 //   1. every block posts its best remaining column (trailing norm^2, index,
 //      and the trailing part of the column itself) to a double-buffered slot;
-//   2. grid barrier;
+//   2. the blocks meet: in the register form each block tags its own slot
+//      with the step once its posts have completed, and every block polls the
+//      G tags (loads issued together); the LDS forms count arrivals on one
+//      counter instead;
 //   3. every block reads the G candidates, agrees on the pivot p (largest
 //      norm, lowest index) and rebuilds the reflector H = I - tau v v^T
 //      (v[k] = 1, beta = -sign(alpha)|x|) from p's posted column;
@@ -29,6 +32,7 @@ namespace {
 constexpr int QR_THREADS = 256;
 constexpr int QR_MAXCOL = 16;  // columns per block
 constexpr long SPIN_LIMIT = 1L << 20;
+constexpr int QR_TAG_SLOTS = 4;  // header tags per lane of the polling wave: the register form takes G <= 256
 
 __device__ __forceinline__ double wave_sum(double v)
 {
@@ -425,7 +429,7 @@ __device__ __forceinline__ void reg_qr_body(const double *S, int64_t lds, int ro
     const int tid = threadIdx.x, lane = tid & 63;
     int ncol = 0;
     while (ncol < NC && g + G * ncol < cols) ++ncol;
-    double *hdr = w.slots;  // 2 x G x 2: candidate (norm^2, column)
+    double *hdr = w.slots;  // 2 x G x 2: candidate norm^2, tagged column (zeroed before the launch)
     double *cand = w.vbuf;  // 2 x G x rows: candidate columns
 
     double x[NC][RPT];
@@ -465,27 +469,56 @@ __device__ __forceinline__ void reg_qr_body(const double *S, int64_t lds, int ro
                 if (i >= k && i < rows) st_dev(dst + i, val);
             }
         }
-        if (tid == 0) {
-            st_dev(hdr + (buf * G + g) * 2 + 0, bn);
-            st_dev(hdr + (buf * G + g) * 2 + 1, bc >= 0 ? (double)(g + G * bc) : -1.0);
-        }
+        if (tid == 0) st_dev(hdr + (buf * G + g) * 2 + 0, bn);
         wait_mem();
         __syncthreads();
-        // 2. grid barrier (arrival counter is monotonic across steps)
-        if (tid == 0) {
-            __hip_atomic_fetch_add(w.counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (!spin_until(w.counter, (unsigned)(k + 1) * (unsigned)G, w.err)) s_abort = 1;
-        }
-        __syncthreads();
-        if (s_abort) return;
-        // 3. agree on the pivot (wave 0 scans the G candidate headers)
+        // 2. arrival and pivot in one exchange: each block tags its own header
+        // word (step + 1 in the high half, its candidate column + 1 in the
+        // low half) once its posts have completed; wave 0 polls all G tags
+        // with the loads issued together (no shared counter, no serialized
+        // atomics), then reads the norms and picks the pivot
         if (tid < 64) {
+            unsigned long long *tw = reinterpret_cast<unsigned long long *>(hdr);
+            const unsigned want = (unsigned)(k + 1);
+            if (tid == 0)
+                __hip_atomic_store(tw + (buf * G + g) * 2 + 1,
+                                   ((unsigned long long)want << 32) | (unsigned)(bc >= 0 ? g + G * bc + 1 : 0),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            unsigned long long tv[QR_TAG_SLOTS];
+            long spins = 0;
+            for (;;) {
+#pragma unroll
+                for (int u = 0; u < QR_TAG_SLOTS; ++u) {
+                    const int q = lane + 64 * u;
+                    tv[u] = q < G ? __hip_atomic_load(tw + (buf * G + q) * 2 + 1, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT)
+                                  : ((unsigned long long)want << 32);
+                }
+                bool mine = true;
+#pragma unroll
+                for (int u = 0; u < QR_TAG_SLOTS; ++u) mine = mine && (unsigned)(tv[u] >> 32) == want;
+                if (__all(mine)) break;
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > SPIN_LIMIT) {
+                    if (tid == 0) {
+                        __hip_atomic_store(w.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        s_abort = 1;
+                    }
+                    break;
+                }
+            }
+            double qn[QR_TAG_SLOTS];
+#pragma unroll
+            for (int u = 0; u < QR_TAG_SLOTS; ++u) {
+                const int q = lane + 64 * u;
+                qn[u] = q < G ? ld_dev(hdr + (buf * G + q) * 2 + 0) : -2.0;
+            }
             double n = -2.0;
             int j = 0x7fffffff;
-            for (int q = lane; q < G; q += 64) {
-                const double qn = ld_dev(hdr + (buf * G + q) * 2 + 0);
-                const int qj = (int)ld_dev(hdr + (buf * G + q) * 2 + 1);
-                if (qj >= 0 && cand_better(qn, qj, n, j)) { n = qn; j = qj; }
+#pragma unroll
+            for (int u = 0; u < QR_TAG_SLOTS; ++u) {
+                const int qj = (int)(unsigned)(tv[u] & 0xffffffffull) - 1;
+                if (lane + 64 * u < G && qj >= 0 && cand_better(qn[u], qj, n, j)) { n = qn[u]; j = qj; }
             }
             wave_best(n, j);
             if (tid == 0) {
@@ -494,6 +527,7 @@ __device__ __forceinline__ void reg_qr_body(const double *S, int64_t lds, int ro
             }
         }
         __syncthreads();
+        if (s_abort) return;
         const int p = s_p;
         if (p < 0 || p >= cols) {
             if (tid == 0 && g == 0) __hip_atomic_store(w.err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -650,35 +684,45 @@ int qrcp_max_blocks(int rows, int cols, int cu_count, size_t lds_max, int *globa
     return G <= cu_count ? G : -1;
 }
 
-// Register form: TT threads per block, rows per thread RPT = 1, 2, 4, 8 or 16
-// and NC columns per block with NC * RPT <= 64 (registers), NC aimed at
-// about 64 blocks.  256 threads when that still gives at most 64 blocks (fewer
-// waves to combine per step: measured faster), else 512 (rows <= 8192).
-static bool reg_shape_for(int tt, int rows, int cols, int cu_count, int *nc_out, int *rpt_out, int *g_out)
+// Register form: 256 threads per block with RPT = 1, 2, 4, 8 or 16 rows per
+// thread (rows <= 4096; 512 threads with 16 rows each up to 8192), and NC
+// columns per block (a power of two, NC * RPT <= 64 for registers; 32 only
+// for one row per thread).  Measured on the tagged exchange, whose cost
+// barely grows with the block count: fewer waves per block and less work
+// per block per step win, so 256 threads and the fewest columns per block
+// whose block count G fits the device (one block per compute unit) and the
+// polling wave (G <= 256).  At 2048 x 2048: 8 columns, 256 blocks, 6.4 us
+// per step, against 7.8 us with 16 columns and 128 blocks.
+static bool reg_geometry(int rows, int *rpt_out, int *tt_out, int *cap_out)
 {
-    int rpt = 1;
+    int tt = 256, rpt = 1;
     while (rpt * tt < rows) rpt <<= 1;
-    if (rpt > 16) return false;
-    const int cap = rpt == 1 ? 32 : (rpt == 2 ? 16 : 64 / rpt);
-    int want = (cols + 63) / 64, nc = 4;
-    while (nc < want && nc < cap) nc <<= 1;
-    if (nc > cap) nc = cap;
-    const int G = (cols + nc - 1) / nc;
-    if (G > cu_count) return false;
-    *nc_out = nc;
+    if (rpt > 16) {
+        tt = 512;
+        rpt = 1;
+        while (rpt * tt < rows) rpt <<= 1;
+        if (rpt > 16) return false;
+    }
     *rpt_out = rpt;
-    *g_out = G;
+    *tt_out = tt;
+    *cap_out = rpt == 1 ? 32 : (rpt == 2 ? 16 : 64 / rpt);
     return true;
 }
 
 bool qrcp_reg_shape(int rows, int cols, int cu_count, int *nc_out, int *rpt_out, int *g_out, int *tt_out)
 {
-    if (reg_shape_for(256, rows, cols, cu_count, nc_out, rpt_out, g_out) && *g_out <= 64) {
-        *tt_out = 256;
-        return true;
-    }
-    *tt_out = 512;
-    return reg_shape_for(512, rows, cols, cu_count, nc_out, rpt_out, g_out);
+    int rpt, tt, cap;
+    if (!reg_geometry(rows, &rpt, &tt, &cap)) return false;
+    const int gmax = std::min(cu_count, 64 * QR_TAG_SLOTS);
+    int nc = 4;
+    while (nc < cap && (cols + nc - 1) / nc > gmax) nc <<= 1;
+    const int G = (cols + nc - 1) / nc;
+    if (G > gmax) return false;
+    *nc_out = nc;
+    *rpt_out = rpt;
+    *g_out = G;
+    *tt_out = tt;
+    return true;
 }
 
 hipError_t qrcp_reg_f64(const double *S, int64_t lds, int rows, int cols, double *R, int32_t *piv, const QrcpWork &w,
@@ -686,7 +730,8 @@ hipError_t qrcp_reg_f64(const double *S, int64_t lds, int rows, int cols, double
 {
     int nc, rpt, G, tt;
     if (!qrcp_reg_shape(rows, cols, cu_count, &nc, &rpt, &G, &tt)) return hipErrorInvalidValue;
-    hipError_t e = zero_u32(w.counter, 4, stream);
+    hipError_t e = zero_u32(w.counter, 4, stream);  // counter, flag, err
+    if (e == hipSuccess) e = zero_u32(reinterpret_cast<unsigned *>(w.slots), 8 * G, stream);  // header tags
     if (e != hipSuccess) return e;
 #define RQ_CASE(NC_, RPT_)                                                                                        \
     if (nc == NC_ && rpt == RPT_)                                                                                 \
@@ -699,6 +744,12 @@ hipError_t qrcp_reg_f64(const double *S, int64_t lds, int rows, int cols, double
     RQ_CASE(4, 16)
 #undef RQ_CASE
     return hipErrorInvalidValue;
+}
+
+static __global__ void grp_zero_kernel(const QrcpGrpArgs *args)
+{
+    const QrcpGrpArgs a = args[blockIdx.x];
+    for (int i = threadIdx.x; i < 4 * a.G; i += blockDim.x) reinterpret_cast<unsigned long long *>(a.w.slots)[i] = 0ull;
 }
 
 // The grouped form's kernel for a (columns per block, rows per thread,
@@ -720,8 +771,12 @@ static const void *grp_kernel_for(int nc, int rpt, int tt)
 
 bool qrcp_grp_shape(int max_rows, int max_cols, int cu_count, QrcpGrpShape *sh)
 {
-    int nc, rpt, g, tt;
-    if (!qrcp_reg_shape(max_rows, max_cols, cu_count, &nc, &rpt, &g, &tt)) return false;
+    // the widest blocks: the fewest blocks per member, so that the most
+    // members run at once
+    int rpt, tt, nc;
+    if (!reg_geometry(max_rows, &rpt, &tt, &nc)) return false;
+    const int g = (max_cols + nc - 1) / nc;
+    if (g > std::min(cu_count, 64 * QR_TAG_SLOTS)) return false;
     const void *fn = grp_kernel_for(nc, rpt, tt);
     if (!fn) return false;
     int per = 0;
@@ -742,6 +797,8 @@ hipError_t qrcp_grp_f64(const QrcpGrpArgs *d_args, int count, const QrcpGrpShape
     if (count > sh.per_launch) return hipErrorInvalidValue;
     const void *fn = grp_kernel_for(sh.nc, sh.rpt, sh.threads);
     if (!fn) return hipErrorInvalidValue;
+    // every member's header tags start from zero (a kernel, so that graph replays clear them too)
+    hipLaunchKernelGGL(grp_zero_kernel, dim3(count), dim3(256), 0, stream, d_args);
     const QrcpGrpArgs *a = d_args;
     void *args[] = {(void *)&a};
     return hipLaunchKernel(fn, dim3(sh.gmax, count), dim3(sh.threads), args, 0, stream);
