@@ -536,15 +536,15 @@ __device__ __forceinline__ int cc_row(int a, int r)
 }
 __device__ __forceinline__ int cc_col(int b) { return ((threadIdx.x >> 6) & 1) * 32 + b * 16 + mfma16_col(threadIdx.x & 63); }
 
-// Cholesky of the 64 x 64 lower triangle in T (LDS) in place by the block's
-// four waves: lane i of wave w keeps row i, columns 16 w .. 16 w + 15, in
-// registers.  At step j the wave owning column j takes the pivot from its
-// lane j, forms column j of L and publishes it in pub[j & 1]; after one block
-// barrier every wave updates its columns c > j with L[i][j] L[c][j] (sixteen
-// broadcast reads and sixteen FMAs a lane).  The strict upper triangle is
-// zeroed.  Returns, in every thread, whether a pivot was not positive and
-// finite.
-__device__ __forceinline__ bool cc_chol64(double *T, double (*pub)[NBMAX], int *s_bad)
+// Cholesky of the diagonal task's 64 x 64 tile (lower triangle of T, LDS) in
+// place, blocked by 16 columns: wave w owns columns
+// 16w .. 16w + 15 (lane = row).  Block column B is factored by wave B alone,
+// column by column in registers (the pivot and the block's other entries of
+// the new column come from the lanes that hold them, no block barrier), then
+// published to LDS; after one block barrier the later waves subtract its
+// rank-16 contribution from their columns.  Four barriers in all instead of
+// one per column.  Wk: 2 x 64 x 17 doubles of LDS scratch.
+__device__ __forceinline__ bool cc_chol64(double *T, double *Wk, int *s_bad)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     double a[16];
@@ -553,26 +553,37 @@ __device__ __forceinline__ bool cc_chol64(double *T, double (*pub)[NBMAX], int *
     if (threadIdx.x == 0) *s_bad = 0;
     bool bad = false;
 #pragma unroll
-    for (int j = 0; j < NBMAX; ++j) {
-        if (w == (j >> 4)) {
-            const double d = lane_value(a[j & 15], j);
-            bad |= !(d > 0.0 && d < INFINITY);
-            const double ljj = __builtin_sqrt(d);
-            const double lij = (lane == j) ? ljj : (lane > j ? a[j & 15] / ljj : 0.0);
-            a[j & 15] = lij;
-            pub[j & 1][lane] = lij;
+    for (int B = 0; B < 4; ++B) {
+        double *pb = Wk + (B & 1) * (NBMAX * 17);
+        if (w == B) {
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) {
+                const int j = 16 * B + jj;
+                const double d = lane_value(a[jj], j);
+                bad |= !(d > 0.0 && d < INFINITY);
+                // 1/sqrt(d): the hardware estimate and one Newton step
+                // (e = 1 - d y^2, y += y e / 2), within an ulp or two;
+                // l_jj = d / sqrt(d)
+                const double y0 = __builtin_amdgcn_rsq(d);
+                const double e0 = __builtin_fma(-d * y0, y0, 1.0);
+                const double inv = __builtin_fma(0.5 * y0, e0, y0);
+                const double ljj = d * inv;
+                const double lij = (lane == j) ? ljj : (lane > j ? a[jj] * inv : 0.0);
+                a[jj] = lij;
+#pragma unroll
+                for (int cc = jj + 1; cc < 16; ++cc) a[cc] = __builtin_fma(-lij, lane_value(lij, 16 * B + cc), a[cc]);
+            }
+#pragma unroll
+            for (int cc = 0; cc < 16; ++cc) pb[lane * 17 + cc] = a[cc];
         }
         __syncthreads();
-        // waves past column j's wave update all their columns; its own wave
-        // the columns after j (a compile-time range); earlier waves none
-        if (w > (j >> 4)) {
-            const double li = pub[j & 1][lane];
+        if (w > B) {
 #pragma unroll
-            for (int cc = 0; cc < 16; ++cc) a[cc] = __builtin_fma(-li, pub[j & 1][16 * w + cc], a[cc]);
-        } else if (w == (j >> 4)) {
-            const double li = pub[j & 1][lane];
+            for (int t = 0; t < 16; ++t) {
+                const double li = pb[lane * 17 + t];
 #pragma unroll
-            for (int cc = (j & 15) + 1; cc < 16; ++cc) a[cc] = __builtin_fma(-li, pub[j & 1][16 * w + cc], a[cc]);
+                for (int cc = 0; cc < 16; ++cc) a[cc] = __builtin_fma(-li, pb[(16 * w + cc) * 17 + t], a[cc]);
+            }
         }
     }
     if (bad) *s_bad = 1;
@@ -585,39 +596,71 @@ __device__ __forceinline__ bool cc_chol64(double *T, double (*pub)[NBMAX], int *
     return *s_bad != 0;
 }
 
-// X = L^{-1} (lower, 64 x 64, LDS row stride LDP, strict upper triangle
-// zero; X may not alias L) by the block: thread t solves column j = t / 4 of
-// L X = I together with the three other lanes of its quad, lane q keeping the
-// entries of rows 4 s + q in registers.  Row i: each lane sums L[i][c] x[c]
-// over its rows c, two shuffles add the quad's four parts, and the lane of
-// row i keeps x[i] = (delta_ij - sum) / L[i][i].  Rows c >= i still hold
-// x[c] = 0 and meet L[i][c] = 0 above the diagonal, so their terms are exact
-// zeros and the sum needs no mask.  Fully unrolled, so the reads of L are
-// issued ahead of the sums.
-__device__ __forceinline__ void cc_lower_inverse(const double *L, double *X, double *invd)
+// Blocked X = L^{-1} (64 x 64 lower, LDS stride LDP; X may not alias L):
+// first wave w inverts the diagonal block L_ww (16 x 16) by forward
+// substitution (a quad of lanes per column: lane q keeps rows 4 s + q) and
+// zeroes its block row above the diagonal; then, for d = 1, 2, 3, wave j
+// forms X_ij (i = j + d) = -X_ii sum_{k=j}^{i-1} L_ik X_kj from blocks of
+// earlier levels, through a 16 x 16 scratch per wave (scr: 4 x 16 x 17).
+__device__ __forceinline__ void cc_lower_inverse(const double *L, double *X, double *invd, double *scr)
 {
-    const int j = threadIdx.x >> 2, q = threadIdx.x & 3;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (threadIdx.x < NBMAX) invd[threadIdx.x] = 1.0 / L[threadIdx.x * LDP + threadIdx.x];
     __syncthreads();
-    double xr[16];
+    {
+        const int jc = lane >> 2, q = lane & 3, o = 16 * w;
+        double xr[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int s2 = 0; s2 < 16; ++s2) xr[s2] = 0.0;
+        for (int ii = 0; ii < 16; ++ii) {
+            double sq = 0.0;
 #pragma unroll
-    for (int i = 0; i < NBMAX; ++i) {
-        double sq = 0.0;
-#pragma unroll
-        for (int s2 = 0; s2 < 16; ++s2) {
-            if (4 * s2 >= i) break;  // rows 4 s2 + q >= i contribute nothing
-            sq = __builtin_fma(L[i * LDP + 4 * s2 + q], xr[s2], sq);
+            for (int s2 = 0; s2 < 4; ++s2) {
+                if (4 * s2 >= ii) break;
+                sq = __builtin_fma(L[(o + ii) * LDP + o + 4 * s2 + q], xr[s2], sq);
+            }
+            sq += __shfl_xor(sq, 1, 64);
+            sq += __shfl_xor(sq, 2, 64);
+            const double xi = ((ii == jc ? 1.0 : 0.0) - sq) * invd[o + ii];
+            xr[ii >> 2] = (q == (ii & 3)) ? xi : xr[ii >> 2];
         }
-        sq += __shfl_xor(sq, 1, 64);
-        sq += __shfl_xor(sq, 2, 64);
-        const double xi = ((i == j ? 1.0 : 0.0) - sq) * invd[i];
-        xr[i >> 2] = (q == (i & 3)) ? xi : xr[i >> 2];
-    }
 #pragma unroll
-    for (int s2 = 0; s2 < 16; ++s2) X[(4 * s2 + q) * LDP + j] = xr[s2];
+        for (int s2 = 0; s2 < 4; ++s2) X[(o + 4 * s2 + q) * LDP + o + jc] = xr[s2];
+        for (int e = lane; e < 16 * (48 - o); e += 64) X[(o + e / (48 - o)) * LDP + o + 16 + e % (48 - o)] = 0.0;
+    }
     __syncthreads();
+    const int r = lane >> 2, c0 = 4 * (lane & 3);
+    double *S = scr + w * (16 * 17);
+#pragma unroll
+    for (int d = 1; d < 4; ++d) {
+        const int j = w, i = w + d;
+        const bool act = i < 4;
+        if (act) {
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int k = j; k < i; ++k) {
+#pragma unroll
+                for (int t = 0; t < 16; ++t) {
+                    const double lv = L[(16 * i + r) * LDP + 16 * k + t];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) acc[u] = __builtin_fma(lv, X[(16 * k + t) * LDP + 16 * j + c0 + u], acc[u]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) S[r * 17 + c0 + u] = acc[u];
+        }
+        __syncthreads();
+        if (act) {
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const double xv = X[(16 * i + r) * LDP + 16 * i + t];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[u] = __builtin_fma(xv, S[t * 17 + c0 + u], acc[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) X[(16 * i + r) * LDP + 16 * j + c0 + u] = -acc[u];
+        }
+        __syncthreads();
+    }
 }
 
 __global__ __launch_bounds__(CC_T) void chol_coop_kernel(CholCoopArgs g)
@@ -625,8 +668,8 @@ __global__ __launch_bounds__(CC_T) void chol_coop_kernel(CholCoopArgs g)
     static_assert(CC_T == 4 * NBMAX, "four waves; a quad of lanes per column of the inverse");
     __shared__ double P[NBMAX * LDP];
     __shared__ double Q[NBMAX * LDP];
-    __shared__ double pub[2][NBMAX];
     __shared__ double invd[NBMAX];
+    __shared__ double scr[4 * 16 * 17];
     __shared__ short own_i[CC_MAXOWN], own_j[CC_MAXOWN];
     __shared__ int s_nown, s_bad;
     const int m = g.m, nb = (m + NBMAX - 1) / NBMAX, ntiles = nb * (nb + 1) / 2;
@@ -692,9 +735,9 @@ __global__ __launch_bounds__(CC_T) void chol_coop_kernel(CholCoopArgs g)
                     }
                 }
                 __syncthreads();
-                if (cc_chol64(P, pub, &s_bad) && tid == 0)
+                if (cc_chol64(P, Q, &s_bad) && tid == 0)
                     __hip_atomic_store(g.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                cc_lower_inverse(P, Q, invd);
+                cc_lower_inverse(P, Q, invd, scr);
                 double *X = g.Dinv + (int64_t)k * NBMAX * NBMAX;
                 {
                     const int c = tid & 63, rb = tid >> 6;
