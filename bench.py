@@ -49,9 +49,9 @@ PEAK_FP32_TFLOPS = 157.3         # MFMA binary32
 PEAK_BF16_TFLOPS = 2500.0        # MFMA bfloat16, dense
 PEAK_FP64_VALU_TOPS = 39.3       # FP64 VALU instructions/s: 256 CU x 64 lanes x 2.4 GHz
 PEAK_INT8_TOPS = 5000.0          # MFMA int8, dense
-# digit pairs the integer compensated products multiply: 13 signed 6-bit
-# digits per operand, pairs (s, t) with s + t <= 12
-OZ_PAIRS = sum(d + 1 for d in range(13))
+# digit pairs the integer compensated products multiply: 11 signed base-128
+# digits per operand (s, t = 0..10), pairs with s + t <= 11
+OZ_PAIRS = sum(1 for s_ in range(11) for t_ in range(11) if s_ + t_ <= 11)
 COMP_INT8 = 2
 
 PRECISIONS = {"fp64": 0, "mixed_fp32": 1, "mixed_bf16": 2}

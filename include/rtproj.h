@@ -140,10 +140,10 @@ typedef enum {
  * largest term's scale at 2048 terms). */
 typedef enum {
     RTPROJ_COMP_AUTO = 0,      /* the integer form from 16 right-hand sides on
-                                  (and m <= 65536), Dot2 below                 */
+                                  (and m <= 32768), Dot2 below                 */
     RTPROJ_COMP_DOT2 = 1,      /* Dot2 (TwoProd and TwoSum) on the vector units */
     RTPROJ_COMP_INT8 = 2       /* exact digit products on the int8 matrix cores
-                                  (m <= 65536; else Dot2)                       */
+                                  (m <= 32768; else Dot2)                       */
 } rtproj_compensation;
 
 /* Method of a plan.  Both return the same x, A^* x and b - A^* x in exact

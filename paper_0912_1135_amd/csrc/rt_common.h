@@ -143,11 +143,12 @@ hipError_t to_f32(const double *src, int64_t lds, float *dst, int64_t ldd, int m
 
 // ---------------------------------------------------------------- exact int8 products
 // Compensated residual products on the int8 matrix cores (digit splitting, see
-// rt_ozaki.hip).  OZ_S signed 6-bit digits per operand, digit pairs with
-// s + t <= OZ_D kept, at most OZ_KMAX terms per int32 partial sum.
-constexpr int OZ_D = 14;
-constexpr int OZ_S = OZ_D - 1;
-constexpr int64_t OZ_KMAX = 65536;
+// rt_ozaki.hip).  OZ_S signed base-128 digits per operand, digit pairs on the
+// OZ_NDIAG diagonals s + t < OZ_NDIAG (digits counted from 0) kept, at most
+// OZ_KMAX terms per int32 partial sum.
+constexpr int OZ_S = 11;
+constexpr int OZ_NDIAG = 12;
+constexpr int64_t OZ_KMAX = 32768;
 struct OzArgs {
     int R, K, k;               // A-operand rows, reduction length, right-hand sides
     const double *A; int64_t lda;

@@ -4,18 +4,21 @@
 //
 //   every dot product sum_k u_k v_k of a row of the A operand with a
 //   right-hand side is taken on a common binary scale per row (2^e, all
-//   |u_k| < 2^e) and per right-hand side (2^f); each scaled value is written
-//   as a sum of OZ_S signed 6-bit digits, u 2^-e = sum_s alpha_s 2^(-6s)
-//   (|alpha_1| <= 64, later |alpha_s| <= 33).  The digit products
-//   P_st = sum_k alpha_s,k beta_t,k are exact in int32 (v_mfma_i32_16x16x64_i8
-//   accumulates in int32, and the sums stay below 2^31), and
-//   sum_k u_k v_k = 2^(e+f) sum_{s,t} 2^(-6(s+t)) P_st
-//   up to the digits and pairs left out.  The pairs with s + t <= OZ_D are
-//   kept, summed per diagonal d = s + t in int32, and the diagonals combined
-//   in double-binary64 (TwoSum).  With OZ_D = 14 the omitted terms are below
-//   2^(e+f) K D 2^(6 - 6 OZ_D) in magnitude, about 2^-62 of the scale of the
-//   largest term at K = 2048 (and the digits of binary64 A are exact for
-//   every entry within 2^-25 of its row's largest).
+//   |u_k| < 2^e) and per right-hand side (2^f); each value on the halved
+//   scale, |u 2^-(e+1)| < 1/2, is written as a sum of OZ_S = 11 signed
+//   base-128 digits, u 2^-(e+1) = sum_{s=0}^{10} alpha_s 128^-(s+1) + rho
+//   with |alpha_s| <= 64 (65 for a double-binary64 right-hand side, whose
+//   leading digit may carry) and |rho| <= 2^-78.  The digit products
+//   P_st = sum_k alpha_s,k beta_t,k are exact in int32
+//   (v_mfma_i32_16x16x64_i8 accumulates in int32; a diagonal holds at most
+//   11 pairs, 11 * 65^2 * K < 2^31 for K <= OZ_KMAX = 32768), and
+//   sum_k u_k v_k = 2^(e+f+2) sum_{s,t} 128^-(s+t+2) P_st
+//   up to the digits and pairs left out.  The pairs on the OZ_NDIAG = 12
+//   diagonals s + t <= 11 (76 of 121) are kept, summed per diagonal in
+//   int32, and the diagonals combined in double-binary64 (TwoSum).  The
+//   omitted pairs and the remainders rho add up to less than
+//   2^(e+f) K 2^-75 in magnitude: about 2^-64 of the scale of the largest
+//   term at K = 2048, 2^-57 at K = 262144.
 //
 // Two products use it: r = B - A^T x (x double-binary64; the A-operand rows
 // are A's columns, K = m, the whole sum in one block) and s = A r (r binary64;
@@ -33,6 +36,7 @@ namespace rt {
 namespace {
 
 constexpr int OZ_T = 256;
+constexpr double OZ_ROUND = 6755399441055744.0;  // 1.5 * 2^52: x + OZ_ROUND rounds x to an integer for |x| < 2^51
 constexpr int OZ_TILE = 64;        // A-operand rows and right-hand sides per block; K per chunk
 constexpr int OZ_LD = OZ_TILE + 16;  // LDS row stride in bytes (16-byte reads of 8 lanes on distinct banks)
 typedef int int4v __attribute__((ext_vector_type(4)));
@@ -102,10 +106,11 @@ __global__ __launch_bounds__(256) void oz_colexp_kernel(const double *V, int64_t
     if (threadIdx.x == 0 && red[0] != INT_MIN) atomicMax(&exp[c], red[0]);
 }
 
-// Digits of the right-hand sides (vh + vl, or vh alone) on their column
-// scales: dig[(t kpad + c) rows_pad + row], t < OZ_S, zero past rows and k.
-// The leading digit of a double-binary64 value is rounded from its high part
-// and corrected by one when the low part carries the remainder past 1/2.
+// Digits of the right-hand sides (vh + vl, or vh alone) on their halved
+// column scales 2^(f+1): dig[(t kpad + c) rows_pad + row], t < OZ_S, zero
+// past rows and k.  Each digit of a double-binary64 value is rounded from its
+// high part and corrected by one when the low part carries the remainder
+// past 1/2.
 template <bool DD>
 __global__ __launch_bounds__(256) void oz_digits_kernel(const double *vh, const double *vl, int64_t ld, int rows,
                                                         int k, int64_t rows_pad, int kpad, const int *exp,
@@ -118,13 +123,13 @@ __global__ __launch_bounds__(256) void oz_digits_kernel(const double *vh, const 
     double h = 0.0, l = 0.0;
     const int ex = c < k ? exp[c] : INT_MIN;
     if (c < k && row < rows && ex != INT_MIN) {
-        h = ldexp(vh[(int64_t)c * ld + row], -ex);
-        if (DD) l = ldexp(vl[(int64_t)c * ld + row], -ex);
+        h = ldexp(vh[(int64_t)c * ld + row], -ex - 1);
+        if (DD) l = ldexp(vl[(int64_t)c * ld + row], -ex - 1);
     }
 #pragma unroll
     for (int t = 0; t < OZ_S; ++t) {
-        h *= 64.0;
-        l *= 64.0;
+        h *= 128.0;
+        l *= 128.0;
         double d = rint(h);
         if (DD) {
             double s, err;
@@ -164,9 +169,9 @@ __global__ __launch_bounds__(OZ_T) void oz_mm_kernel(OzArgs g)
     // this thread's part of the B digits: right-hand side c0 + bc, 16 k from bk
     const int bc = tid >> 2, bk = 16 * (tid & 3);
 
-    int4v acc[OZ_D - 1][4];
+    int4v acc[OZ_NDIAG][4];
 #pragma unroll
-    for (int d = 0; d < OZ_D - 1; ++d)
+    for (int d = 0; d < OZ_NDIAG; ++d)
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) acc[d][ct] = int4v{0, 0, 0, 0};
 
@@ -199,14 +204,18 @@ __global__ __launch_bounds__(OZ_T) void oz_mm_kernel(OzArgs g)
             for (int s2 = 0; s2 < OZ_S; ++s2) wd[s2] = 0;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                // scaled to the row's power of two (zero outside the range)
-                double v = (live && k0 + lk + 4 * q + u < kend) ? ldexp(av[4 * q + u], -ex) : 0.0;
+                // on the row's halved power-of-two scale (zero outside the
+                // range), |v| < 1/2; digit d = round(128 v) by adding and
+                // subtracting 1.5 * 2^52, whose sum keeps d (two's
+                // complement) in the low word of its bits
+                double v = (live && k0 + lk + 4 * q + u < kend) ? ldexp(av[4 * q + u], -ex - 1) : 0.0;
 #pragma unroll
                 for (int s2 = 0; s2 < OZ_S; ++s2) {
-                    v *= 64.0;
-                    const double d = rint(v);
+                    v *= 128.0;
+                    const double t = v + OZ_ROUND;
+                    const double d = t - OZ_ROUND;
                     v -= d;
-                    wd[s2] |= ((int)d & 0xff) << (8 * u);
+                    wd[s2] |= ((int)(unsigned)__builtin_bit_cast(unsigned long long, t) & 0xff) << (8 * u);
                 }
             }
 #pragma unroll
@@ -236,7 +245,7 @@ __global__ __launch_bounds__(OZ_T) void oz_mm_kernel(OzArgs g)
 #pragma unroll
             for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
-                for (int s = 0; s + t <= OZ_D - 2; ++s)
+                for (int s = 0; s < OZ_S && s + t < OZ_NDIAG; ++s)
                     acc[s + t][ct] = __builtin_amdgcn_mfma_i32_16x16x64_i8(aop[s], bcur[ct], acc[s + t][ct], 0, 0, 0);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -244,8 +253,8 @@ __global__ __launch_bounds__(OZ_T) void oz_mm_kernel(OzArgs g)
         }
     }
 
-    // diagonals to double-binary64, smallest first: sum 2^(-6(d+2)) Q_d, then
-    // the scale 2^(e+f) (exact)
+    // diagonals to double-binary64, smallest first: sum 128^-(d+2) Q_d, then
+    // the scale 2^(e+f+2) (exact)
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
@@ -257,8 +266,8 @@ __global__ __launch_bounds__(OZ_T) void oz_mm_kernel(OzArgs g)
             double hi = 0.0, lo = 0.0;
             if (er != INT_MIN && ec != INT_MIN) {
 #pragma unroll
-                for (int d = OZ_D - 2; d >= 0; --d) {
-                    const double t = ldexp((double)acc[d][ct][r], -6 * (d + 2));
+                for (int d = OZ_NDIAG - 1; d >= 0; --d) {
+                    const double t = ldexp((double)acc[d][ct][r], -7 * (d + 2));
                     double s, err;
                     two_sum(hi, t, s, err);
                     hi = s;
@@ -266,8 +275,8 @@ __global__ __launch_bounds__(OZ_T) void oz_mm_kernel(OzArgs g)
                 }
                 double s, err;
                 two_sum(hi, lo, s, err);
-                hi = ldexp(s, er + ec);
-                lo = ldexp(err, er + ec);
+                hi = ldexp(s, er + ec + 2);
+                lo = ldexp(err, er + ec + 2);
             }
             if (TRANS) {
                 // r = B - (hi + lo), rounded once
