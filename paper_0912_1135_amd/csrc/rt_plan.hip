@@ -245,10 +245,28 @@ rtproj_status alloc_state(rtproj_plan p)
     const int gt = (int)((m + 127) / 128);
     const int tiles = gt * (gt + 1) / 2;
     p->syrk_splits = (int)std::max<int64_t>(1, std::min<int64_t>({64, (4 * p->cu_count + tiles - 1) / tiles, n / 256}));
+    {
+        // K splits of the Gram of P^-1 A: of the counts from half to twice
+        // the one above, the one whose last round of lower 128 x 128 tile
+        // blocks fills the compute units best (2048 x 262144: 15 splits,
+        // 2040 blocks in 7.97 rounds; 8 splits left the fifth round a
+        // quarter full)
+        const int64_t sp0 = p->syrk_splits;
+        const int64_t hi = std::max<int64_t>(1, std::min<int64_t>({64, 2 * sp0, n / 256}));
+        const int64_t lo = std::max<int64_t>(1, std::min<int64_t>(sp0 / 2, hi));
+        int64_t best = lo;
+        double best_fill = -1.0;
+        for (int64_t sp = lo; sp <= hi; ++sp) {
+            const int64_t blocks = tiles * sp, rounds = (blocks + p->cu_count - 1) / p->cu_count;
+            const double fill = (double)blocks / (double)(rounds * p->cu_count);
+            if (fill > best_fill + 1e-9) { best_fill = fill; best = sp; }
+        }
+        p->wgram_splits = (int)best;
+    }
     // split partials: room for twice the built-in split count (the
     // autotuner may pick more splits), at most 64
     p->part_cap = (int)std::min<int64_t>(64, std::max<int64_t>(1, std::min<int64_t>(2 * p->syrk_splits, n / 256)));
-    p->part_cap = std::max(p->part_cap, p->syrk_splits);
+    p->part_cap = std::max({p->part_cap, p->syrk_splits, p->wgram_splits});
     RT_HIP(dalloc(&p->d_part, (size_t)p->part_cap * m * m));
     RT_HIP(dalloc(&p->d_G, (size_t)m * m));
     RT_HIP(dalloc(&p->d_L, (size_t)m * m));
@@ -1075,7 +1093,7 @@ rtproj_status project(rtproj_plan p, const double *B, int64_t ldb, int64_t k, do
         RT_HIP(rt::set_matrix_f64(p->d_xlo, m, (int)k, (int)m, 0, s));
     }
     RefinePlan rp = refine_schedule(p->info.kappa_est, p->prec_used, p->w32, p->info.gram_cond_est,
-                                    (double)p->n / std::max(1, p->syrk_splits), p->resid_mode, p->refine_steps);
+                                    (double)p->n / std::max(1, p->gram_splits_used), p->resid_mode, p->refine_steps);
     if (p->method_used == RTPROJ_METHOD_KRYLOV) {
         // a solve ends within 2 (0.6)^iters of the exact correction (CG on W W^T
         // with cond(W) <= 4), plus the rounding of its passes, about 16 u kappa
@@ -1615,7 +1633,7 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
                                      (int)m, m, bf ? p->d_rowscale : nullptr, bf ? p->d_rowscale : nullptr, p->d_G, m,
                                      1, s);
     };
-    std::vector<int> wcfg = {0, 0, 0}, gcfg = {p->syrk_splits, 0};
+    std::vector<int> wcfg = {0, 0, 0}, gcfg = {p->wgram_splits, 0};
     if (p->autotune) {
         const std::string wkey = tune_key(p->w32 ? "w32" : "w64", m, n, lda == n ? 0 : 1);
         if (!tune_lookup(wkey, wcfg)) {
@@ -1637,13 +1655,19 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
             // run W once with the chosen configuration so the Gram reads it
             RT_HIP(run_w(wcfg[0], wcfg[1], wcfg.size() > 2 ? wcfg[2] : 0));
             const int smax = (int)std::max<int64_t>(1, std::min<int64_t>(64, n / 256));
+            // binary32 partials take half the room of binary64 ones
+            const int cap = std::min(smax, lp ? 2 * p->part_cap : p->part_cap);
             std::vector<std::vector<int>> cands;
-            for (int sp : {p->syrk_splits / 2, p->syrk_splits, 2 * p->syrk_splits, 4 * p->syrk_splits}) {
-                if (sp < 1 || sp > std::min(smax, p->part_cap)) continue;
+            for (int sp : {p->syrk_splits / 2, p->syrk_splits, 2 * p->syrk_splits, 4 * p->syrk_splits,
+                           p->wgram_splits, 2 * p->wgram_splits}) {
+                if (sp < 1 || sp > cap) continue;
+                bool seen = false;
+                for (const auto &c : cands) seen = seen || c[0] == sp;
+                if (seen) continue;
                 cands.push_back({sp, 0});
                 if (!lp) cands.push_back({sp, 64});
             }
-            if (cands.empty()) cands.push_back({p->syrk_splits, 0});
+            if (cands.empty()) cands.push_back({p->wgram_splits, 0});
             int best = 0;
             st = tune_pick(p, (int)cands.size(), [&](int c) { return run_gram(cands[c][0], cands[c][1]); }, &best,
                            nullptr);
@@ -1651,7 +1675,7 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
             gcfg = cands[best];
             tune_store(gkey, gcfg);
         }
-        gcfg[0] = std::min(gcfg[0], p->part_cap);
+        gcfg[0] = std::min(gcfg[0], lp ? 2 * p->part_cap : p->part_cap);
     }
     {
         StageScope sc(p, 3);
@@ -1661,6 +1685,7 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
     {
         StageScope sc(p, 4);
         RT_HIP(run_gram(gcfg[0], gcfg[1]));
+        p->gram_splits_used = std::max(1, gcfg[0]);
     }
     p->info.sketch_bits = (lp && !sketch64 && !p->Gmat) ? 32 : 64;
     p->info.w_bits = p->w32 ? 32 : 64;

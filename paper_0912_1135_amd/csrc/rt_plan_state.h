@@ -246,6 +246,8 @@ struct rtproj_plan_s {
     double *d_Yq2 = nullptr;   // two-stage: the next m x l iterate of the Cholesky QR
     bool w32 = false;          // P^{-1}A held in binary32 by the last precondition
     int syrk_splits = 1;
+    int wgram_splits = 1;  // K splits of the Gram of P^-1 A (balanced over the compute units)
+    int gram_splits_used = 1;  // those of the last precondition (the refinement schedule's Gram term)
     // projection workspace
     int64_t kcap = 0;
     int ab_splits = 1;
