@@ -711,12 +711,34 @@ __global__ __launch_bounds__(CC_T) void chol_coop_kernel(CholCoopArgs g)
     __syncthreads();
     const int nown = s_nown;
     const int tid = threadIdx.x;
+    // factor the diagonal tile kk held in P (lower triangle, the identity
+    // past m), invert the factor, store both and raise the tile's flag
+    auto factor_publish = [&](int kk, int nr) {
+        const int r0 = kk * NBMAX;
+        __syncthreads();
+        if (cc_chol64(P, Q, &s_bad) && tid == 0)
+            __hip_atomic_store(g.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        cc_lower_inverse(P, Q, invd, scr);
+        double *X = g.Dinv + (int64_t)kk * NBMAX * NBMAX;
+        const int c = tid & 63, rb = tid >> 6;
+#pragma unroll
+        for (int s2 = 0; s2 < CC_E; ++s2) {
+            const int r = rb + 4 * s2;
+            cc_store(X + r * NBMAX + c, Q[r * LDP + c]);
+            if (r < nr && c < nr && c <= r) g.L[(int64_t)(r0 + r) * g.ldl + r0 + c] = P[r * LDP + c];
+        }
+        cc_raise(dflag + kk, g.epoch);
+    };
+    // diagonal tile factored early (see the panel task below), -1: none
+    int diag_done = -1;
     for (int k = 0; k < nb; ++k) {
         for (int q = 0; q < nown; ++q) {
             const int i = own_i[q], j = own_j[q];
             if (j < k) continue;
+            if (i == j && diag_done == i) continue;  // its last update and factorization are done
             const int r0 = i * NBMAX, c0 = j * NBMAX;
             const int nr = min(NBMAX, m - r0), nc = min(NBMAX, m - c0);
+            int fac = -1;  // diagonal tile to factor from P after this task
             __syncthreads();  // the previous task's LDS reads are done
             if (j == k && i == k) {
                 // diagonal: factor, invert, publish
@@ -734,21 +756,7 @@ __global__ __launch_bounds__(CC_T) void chol_coop_kernel(CholCoopArgs g)
                         P[r * LDP + c] = (r < nr && c < nr) ? (c <= r ? v[s2] : 0.0) : (r == c ? 1.0 : 0.0);
                     }
                 }
-                __syncthreads();
-                if (cc_chol64(P, Q, &s_bad) && tid == 0)
-                    __hip_atomic_store(g.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                cc_lower_inverse(P, Q, invd, scr);
-                double *X = g.Dinv + (int64_t)k * NBMAX * NBMAX;
-                {
-                    const int c = tid & 63, rb = tid >> 6;
-#pragma unroll
-                    for (int s2 = 0; s2 < CC_E; ++s2) {
-                        const int r = rb + 4 * s2;
-                        cc_store(X + r * NBMAX + c, Q[r * LDP + c]);
-                        if (r < nr && c < nr && c <= r) g.L[(int64_t)(r0 + r) * g.ldl + r0 + c] = P[r * LDP + c];
-                    }
-                }
-                cc_raise(dflag + k, g.epoch);
+                fac = k;
             } else if (j == k) {
                 // panel: L_ik = A_ik X^T
                 cc_wait(dflag + k, dflag + k, g.epoch, g.err);
@@ -766,7 +774,50 @@ __global__ __launch_bounds__(CC_T) void chol_coop_kernel(CholCoopArgs g)
                             const int rr = cc_row(a, r), cc = cc_col(b);
                             if (rr < nr && cc < nc) cc_store(g.L + (int64_t)(r0 + rr) * g.ldl + c0 + cc, acc[a][b][r]);
                         }
-                cc_raise(pflag + cc_tile(i, k, nb), g.epoch);
+                if (i != k + 1) {
+                    cc_raise(pflag + cc_tile(i, k, nb), g.epoch);
+                    continue;
+                }
+                // (the diagonal tile has the panel's rows: nr)
+                // This block also owns the diagonal tile (k + 1, k + 1), whose
+                // last update is the one by this panel: apply it from LDS and
+                // factor the tile at once, ahead of the step's other tasks
+                // (it waits on nothing outside this block).
+                __syncthreads();  // the panel product's LDS reads are done
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int rr = cc_row(a, r), cc = cc_col(b);
+                            P[rr * LDP + cc] = rr < nr ? acc[a][b][r] : 0.0;
+                        }
+                cc_raise(pflag + cc_tile(i, k, nb), g.epoch);  // (its barrier also orders the LDS writes)
+                // the diagonal tile's values load while the update product runs
+                double gv[2][2][4];
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            gv[a][b][r] = g.G[(int64_t)(r0 + min(cc_row(a, r), nr - 1)) * g.ldg + r0 +
+                                              min(cc_col(b), nr - 1)];
+                cc_pqt(P, P, acc);
+                __syncthreads();  // the update product's LDS reads are done
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int rr = cc_row(a, r), cc = cc_col(b);
+                            P[rr * LDP + cc] = (rr < nr && cc < nr) ? (cc <= rr ? gv[a][b][r] - acc[a][b][r] : 0.0)
+                                                                    : (rr == cc ? 1.0 : 0.0);
+                        }
+                fac = k + 1;
+                diag_done = k + 1;
             } else {
                 // update: A_ij -= L_ik L_jk^T
                 cc_wait(pflag + cc_tile(i, k, nb), pflag + cc_tile(j, k, nb), g.epoch, g.err);
@@ -798,6 +849,7 @@ __global__ __launch_bounds__(CC_T) void chol_coop_kernel(CholCoopArgs g)
                                 g.G[(int64_t)(r0 + rr) * g.ldg + c0 + cc] = gv[a][b][r] - acc[a][b][r];
                         }
             }
+            if (fac >= 0) factor_publish(fac, nr);
         }
     }
 }
