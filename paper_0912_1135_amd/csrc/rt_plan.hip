@@ -454,7 +454,10 @@ rtproj_status cholesky(rtproj_plan p, double *G, double *L, double *Dinv)
 
 // G (m x m, row-major, both triangles) = A A^T for the row-major m x K
 // matrix A: lower tiles on MFMA, split over K, fixed-order reduction.
-rtproj_status gram_f64(rtproj_plan p, const double *A, int64_t lda, int64_t K, double *G)
+// G = A A^T (m x m, both triangles) for row-major m x K A: lower tiles
+// (tile 0: chosen from the shape; 64: 64 x 64) split over K (splits 0: the
+// plan's default), then the fixed-order reduction of the splits.
+hipError_t gram_f64_cfg(rtproj_plan p, const double *A, int64_t lda, int64_t K, double *G, int tile, int splits)
 {
     const int64_t m = p->m;
     rt::GemmArgs g{};
@@ -462,10 +465,17 @@ rtproj_status gram_f64(rtproj_plan p, const double *A, int64_t lda, int64_t K, d
     g.A = A; g.a_i = lda; g.a_k = 1;
     g.B = A; g.b_k = 1; g.b_j = lda;
     g.C = p->d_part; g.c_i = m; g.c_j = 1; g.c_split = m * m;
-    g.alpha = 1.0; g.c_lower = 1;
-    g.ksplit = (int)std::max<int64_t>(1, std::min<int64_t>(p->syrk_splits, K / 256));
-    RT_HIP(rt::gemm_f64(g, p->stream));
-    RT_HIP(rt::reduce_splits_f64(p->d_part, m * m, g.ksplit, (int)m, (int)m, m, G, m, 1, p->stream));
+    g.alpha = 1.0; g.c_lower = 1; g.tile = tile;
+    const int64_t sp = splits > 0 ? splits : p->syrk_splits;
+    g.ksplit = (int)std::max<int64_t>(1, std::min<int64_t>({sp, K / 256, (int64_t)p->part_cap}));
+    hipError_t e = rt::gemm_f64(g, p->stream);
+    if (e != hipSuccess) return e;
+    return rt::reduce_splits_f64(p->d_part, m * m, g.ksplit, (int)m, (int)m, m, G, m, 1, p->stream);
+}
+
+rtproj_status gram_f64(rtproj_plan p, const double *A, int64_t lda, int64_t K, double *G)
+{
+    RT_HIP(gram_f64_cfg(p, A, lda, K, G, 0, 0));
     return RTPROJ_OK;
 }
 
@@ -585,8 +595,29 @@ rtproj_status r0_factor(rtproj_plan p)
     // iterates: S, then L1^{-1} S in d_Yq, then L2^{-1} L1^{-1} S in d_Yq2
     const double *Yin[3] = {p->d_S, p->d_Yq, p->d_Yq2};
     rtproj_status st;
+    // the iterates' Grams (m x m from K = l) are short in K: with autotuning
+    // the tile and split are measured on the first iterate (its Gram is then
+    // formed again with the choice)
+    std::vector<int> rcfg = {0, 0};
+    if (p->autotune) {
+        const std::string key = tune_key("r0g", m, l, 0);
+        if (!tune_lookup(key, rcfg)) {
+            std::vector<std::vector<int>> cands;
+            for (int tile : {0, 64})
+                for (int sp : {p->syrk_splits / 2, p->syrk_splits, 2 * p->syrk_splits})
+                    if (sp >= 1 && sp <= p->part_cap && sp <= l / 256) cands.push_back({tile, sp});
+            if (cands.empty()) cands.push_back({0, 0});
+            int best = 0;
+            st = tune_pick(p, (int)cands.size(),
+                           [&](int c) { return gram_f64_cfg(p, Yin[0], l, l, p->d_G, cands[c][0], cands[c][1]); },
+                           &best, nullptr);
+            if (st != RTPROJ_OK) return st;
+            rcfg = cands[best];
+            tune_store(key, rcfg);
+        }
+    }
     for (int it = 0; it < 3; ++it) {
-        if ((st = gram_f64(p, Yin[it], l, l, p->d_G)) != RTPROJ_OK) return st;
+        RT_HIP(gram_f64_cfg(p, Yin[it], l, l, p->d_G, rcfg[0], rcfg[1]));
         if (it == 0) RT_HIP(rt::shift_diag_f64(p->d_G, m, (int)m, shift, s));
         if ((st = cholesky(p, p->d_G, Ls[it], p->d_DinvL)) != RTPROJ_OK) return st;
         if (it < 2) {
