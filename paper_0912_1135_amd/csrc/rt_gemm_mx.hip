@@ -193,6 +193,142 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmMxArgs g)
     gemm_f32_tile<BM, BN, A_KC, B_KC, DBL, GB>(g, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
+// Both operands K-contiguous binary32 (the Gram of a row-major matrix), no
+// scales, no gather, K, the row strides and the base addresses multiples of
+// 4 floats.  Each thread moves 16-byte pieces along k into LDS rows of KV + 4
+// floats.  Inside every group of 16 k the contraction order is permuted the
+// same way for both operands (lane group q takes k = 4 q + s at MFMA step s),
+// so one 16-byte LDS read gives a lane its operands for four steps.  On a
+// lower-triangle grid whose block count is a multiple of 8 the blocks are
+// renumbered so that each XCD (blocks are dealt to the 8 XCDs in turn) runs a
+// contiguous range of K splits: its L2 then serves every tile of a split from
+// one read of the split's rows.
+constexpr int KV = 32;
+
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void gemm_f32_kc_kernel(GemmMxArgs g)
+{
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    constexpr int LDK = KV + 4;
+    __shared__ __attribute__((aligned(16))) float As[2][BM * LDK];
+    __shared__ __attribute__((aligned(16))) float Bs[2][BN * LDK];
+    constexpr int TM = BM / 32, TN = BN / 32;
+    constexpr int Q = KV / 4;  // 16-byte pieces per row and chunk
+    constexpr int NA = BM * Q / 256, NB = BN * Q / 256;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    int bx = blockIdx.x, bz = blockIdx.z;
+    int ti, tj;
+    if (g.c_lower) {
+        const int64_t total = (int64_t)gridDim.x * gridDim.z;
+        if ((total & 7) == 0) {
+            const int64_t L = bx + (int64_t)gridDim.x * bz;
+            const int64_t N = (L & 7) * (total >> 3) + (L >> 3);
+            bx = (int)(N % gridDim.x);
+            bz = (int)(N / gridDim.x);
+        }
+        const int t = bx;
+        ti = (int)((__builtin_sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+        while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+        while (ti * (ti + 1) / 2 > t) --ti;
+        tj = t - ti * (ti + 1) / 2;
+    } else {
+        ti = blockIdx.y;
+        tj = bx;
+    }
+    const int i0 = ti * BM, j0 = tj * BN;
+    int kbeg = 0, kend = g.K;
+    if (g.ksplit > 1) {
+        int ks = (g.K + g.ksplit - 1) / g.ksplit;
+        ks = (ks + KV - 1) / KV * KV;
+        kbeg = bz * ks;
+        kend = min(g.K, kbeg + ks);
+    }
+    const int nch = kend > kbeg ? (kend - kbeg + KV - 1) / KV : 0;
+    const float *Ap = static_cast<const float *>(g.A);
+    const float *Bp = static_cast<const float *>(g.B);
+    // piece e of this thread: row x / Q, k offset 4 (x % Q), x = tid + 256 e
+    int64_t a_off[NA], b_off[NB];
+    bool a_in[NA], b_in[NB];
+    const int kq = 4 * (tid % Q);
+#pragma unroll
+    for (int e = 0; e < NA; ++e) {
+        const int i = i0 + (tid + 256 * e) / Q;
+        a_in[e] = i < g.M;
+        a_off[e] = (int64_t)(a_in[e] ? i : g.M - 1) * g.a_i;
+    }
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+        const int j = j0 + (tid + 256 * e) / Q;
+        b_in[e] = j < g.N;
+        b_off[e] = (int64_t)(b_in[e] ? j : g.N - 1) * g.b_j;
+    }
+    f4 ra[NA], rb[NB];
+    // kend and every k below are multiples of 4: a piece is wholly in or out;
+    // out-of-range pieces load from a clamped address and are zeroed
+    auto load = [&](int c) {
+        const int k = kbeg + c * KV + kq;
+        const bool kin = k < kend;
+        const int kc = kin ? k : kend - 4;
+#pragma unroll
+        for (int e = 0; e < NA; ++e) {
+            const f4 v = *reinterpret_cast<const f4 *>(Ap + a_off[e] + kc);
+            ra[e] = (kin && a_in[e]) ? v : f4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+        for (int e = 0; e < NB; ++e) {
+            const f4 v = *reinterpret_cast<const f4 *>(Bp + b_off[e] + kc);
+            rb[e] = (kin && b_in[e]) ? v : f4{0.f, 0.f, 0.f, 0.f};
+        }
+    };
+    f4 acc[TM][TN];
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+    if (nch > 0) load(0);
+    for (int t = 0; t < nch; ++t) {
+        const int buf = t & 1;
+#pragma unroll
+        for (int e = 0; e < NA; ++e) *reinterpret_cast<f4 *>(&As[buf][((tid + 256 * e) / Q) * LDK + kq]) = ra[e];
+#pragma unroll
+        for (int e = 0; e < NB; ++e) *reinterpret_cast<f4 *>(&Bs[buf][((tid + 256 * e) / Q) * LDK + kq]) = rb[e];
+        __syncthreads();
+        if (t + 1 < nch) load(t + 1);
+#pragma unroll
+        for (int h = 0; h < KV / 16; ++h) {
+            f4 av[TM], bv[TN];
+#pragma unroll
+            for (int a = 0; a < TM; ++a)
+                av[a] = *reinterpret_cast<const f4 *>(
+                    &As[buf][(wm * (BM / 2) + a * 16 + (lane & 15)) * LDK + 16 * h + 4 * (lane >> 4)]);
+#pragma unroll
+            for (int b = 0; b < TN; ++b)
+                bv[b] = *reinterpret_cast<const f4 *>(
+                    &Bs[buf][(wn * (BN / 2) + b * 16 + (lane & 15)) * LDK + 16 * h + 4 * (lane >> 4)]);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int a = 0; a < TM; ++a)
+#pragma unroll
+                    for (int b = 0; b < TN; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a][s], bv[b][s], acc[a][b], 0, 0, 0);
+        }
+    }
+    const int64_t coff = g.ksplit > 1 ? (int64_t)bz * g.c_split : 0;
+    float *C = static_cast<float *>(g.C);
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + wm * (BM / 2) + a * 16 + 4 * (lane >> 4) + r;
+                const int j = j0 + wn * (BN / 2) + b * 16 + (lane & 15);
+                if (i < g.M && j < g.N) C[coff + (int64_t)i * g.c_i + (int64_t)j * g.c_j] = g.alpha * acc[a][b][r];
+            }
+}
+
 // Grouped launch (batches): member blockIdx.z / ksmax, split blockIdx.z % ksmax.
 template <int BM, int BN, bool A_KC, bool B_KC, bool DBL>
 __global__ __launch_bounds__(256) void gemm_f32_grouped_kernel(const GemmMxArgs *gs, int ksmax)
@@ -355,6 +491,15 @@ hipError_t launch32_st(const GemmMxArgs &g, dim3 grid, hipStream_t s)
     return hipGetLastError();
 }
 
+// Operands that gemm_f32_kc_kernel takes: binary32, K-contiguous, unscaled,
+// ungathered, full (not triangular), 16-byte aligned rows and K % 4 == 0.
+bool kc_fast(const GemmMxArgs &g)
+{
+    return !g.a_dbl && !g.b_dbl && !g.c_dbl && g.a_k == 1 && g.b_k == 1 && !g.a_gather && !g.b_gather &&
+           !g.a_scale && !g.b_scale && !g.a_lower && g.K % 4 == 0 && g.a_i % 4 == 0 && g.b_j % 4 == 0 &&
+           (reinterpret_cast<uintptr_t>(g.A) & 15) == 0 && (reinterpret_cast<uintptr_t>(g.B) & 15) == 0;
+}
+
 template <int BM, int BN>
 hipError_t launch32(const GemmMxArgs &g, hipStream_t s)
 {
@@ -362,6 +507,10 @@ hipError_t launch32(const GemmMxArgs &g, hipStream_t s)
     dim3 grid = g.c_lower ? dim3(gm * (gm + 1) / 2, 1, g.ksplit > 1 ? g.ksplit : 1)
                           : dim3(gn, gm, g.ksplit > 1 ? g.ksplit : 1);
     if (g.a_dbl != g.b_dbl) return hipErrorInvalidValue;  // operands share their storage type
+    if (kc_fast(g)) {
+        hipLaunchKernelGGL((gemm_f32_kc_kernel<BM, BN>), grid, dim3(256), 0, s, g);
+        return hipGetLastError();
+    }
     return g.a_dbl ? launch32_st<BM, BN, true>(g, grid, s) : launch32_st<BM, BN, false>(g, grid, s);
 }
 

@@ -432,6 +432,27 @@ def test_exported_minv_inverts_the_normal_matrix(rt, method):
     plan.close()
 
 
+@pytest.mark.parametrize("n", [20000, 20002])
+def test_exported_minv_binary32_gram(rt, n):
+    """The binary32 Gram (P^{-1}A)(P^{-1}A)^T on MFMA, seen through M^{-1}:
+    n % 4 == 0 takes the 16-byte-load Gram kernel, n % 4 == 2 the general
+    one; m = 300 leaves ragged 128-row tiles.  Binary32 products of a well
+    conditioned W give |M^{-1} A A^T - I| of order 1e-5; a wrong tile, split
+    or contraction order gives O(1)."""
+    m, l, seed = 300, 1200, 47
+    A = synth.make_problem(m, n, 10.0, seed)
+    plan = rt.Plan(m, n, l, seed)
+    plan.set_precision(1)
+    plan.set_inverse(rt.INV_CHOLESKY)
+    plan.precondition(torch.from_numpy(A).to(dev()))
+    info = plan.info()
+    assert info["gram_bits"] == 32 and info["w_bits"] == 32
+    Mi = plan.export()["Minv"].cpu().numpy()
+    E = Mi @ (A @ A.T) - np.eye(m)
+    assert np.linalg.norm(E, 2) <= 1e-3, np.linalg.norm(E, 2)
+    plan.close()
+
+
 def test_inverse_method_argument_checks(rt):
     plan = rt.Plan(8, 100, 32, 0)
     with pytest.raises(rt.RtprojError) as e:
