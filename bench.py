@@ -8,8 +8,9 @@ compensated refinement), all through the C ABI.
 
 Workloads (seeded synthetic inputs, A = U diag(sigma) V^T with Haar factors):
   mixed_2048x262144 (default) m=2048, n=262144, sigma 1 -> 1e-8, l=8192, k=64;
-                             the binary32 form (main line) against the
-                             binary64 and bfloat16 forms on the same inputs
+                             the split-bfloat16 Gram form (main line)
+                             against the binary32-Gram, binary64 and
+                             bfloat16 forms on the same inputs
   plain_512x65536            m=512, n=65536, sigma 1 -> 1e-10, l=2048, k=16;
                              binary64, plus the mixed forms on the same inputs
   plain_64x4096              m=64, n=4096, sigma 1 -> 1e-6, l=256, k=1
@@ -54,7 +55,7 @@ PEAK_INT8_TOPS = 5000.0          # MFMA int8, dense
 OZ_PAIRS = sum(1 for s_ in range(11) for t_ in range(11) if s_ + t_ <= 11)
 COMP_INT8 = 2
 
-PRECISIONS = {"fp64": 0, "mixed_fp32": 1, "mixed_bf16": 2}
+PRECISIONS = {"fp64": 0, "mixed_fp32": 1, "mixed_bf16": 2, "mixed_bf16x3": 3}
 
 
 def log(msg):
@@ -79,9 +80,10 @@ def stage_work(name, dims, prec="fp64", w_bits=64, inv=(2, 0), comp=1):
         elif name == "qrcp":
             tot += 2.0 * l * m * m - 2.0 * m ** 3 / 3
         elif name == "qr_r0":
-            # shifted Cholesky QR: three Grams m(m+1)l, two solves m^2 l,
-            # three Cholesky m^3/3 and two triangular products m^3/3
-            tot += 3.0 * m * (m + 1) * l + 2.0 * m * m * l + 5.0 * m ** 3 / 3
+            # shifted Cholesky QR and one more pass: two Grams m(m+1)l, one
+            # solve m^2 l, two Cholesky m^3/3, one triangular inverse m^3/3
+            # and one triangular product m^3/3
+            tot += 2.0 * m * (m + 1) * l + 1.0 * m * m * l + 4.0 * m ** 3 / 3
         elif name == "rinv_trsm":
             tot += m ** 3 / 3.0
         elif name == "gram_inv":
@@ -116,6 +118,8 @@ def stage_work(name, dims, prec="fp64", w_bits=64, inv=(2, 0), comp=1):
         return "mfma", tot, "flops", PEAK_BF16_TFLOPS
     if name == "gram_syrk" and prec == "mixed_fp32":
         return "mfma", tot, "flops", PEAK_FP32_TFLOPS
+    if name == "gram_syrk" and prec == "mixed_bf16x3":
+        return "mfma", 3.0 * tot, "flops", PEAK_BF16_TFLOPS                # three bfloat16 products
     if name == "w_gemm" and w_bits == 32:
         return "mfma", tot, "flops", PEAK_FP32_TFLOPS
     return "mfma", tot, "flops", PEAK_FP64_TFLOPS
@@ -175,7 +179,9 @@ def stage_table(info, steps, dims, prec, w_bits):
         if not calls:
             continue
         d = {"ms_per_step": tot / steps, "ms_per_launch": tot / calls, "launches_per_step": calls / steps}
-        bound, amt, kind, peak = stage_work(name, dims, prec, w_bits,
+        # the split-bfloat16 precision takes the binary32 Gram when n % 4 != 0
+        gp = "mixed_fp32" if prec == "mixed_bf16x3" and info.get("gram_bits") == 32 else prec
+        bound, amt, kind, peak = stage_work(name, dims, gp, w_bits,
                                             (info.get("inverse", 2), info.get("inverse_iters", 0)),
                                             info.get("comp_method", 1))
         if bound is not None:
@@ -252,7 +258,7 @@ def run_single(args, rt, synth, np, torch):
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
     mixed_wl = args.workload.startswith("mixed")
-    main_prec = args.precision or ("mixed_fp32" if mixed_wl else "fp64")
+    main_prec = args.precision or ("mixed_bf16x3" if mixed_wl else "fp64")
     forms_to_run = [main_prec] + ([] if args.no_forms else [p for p in PRECISIONS if p != main_prec])
     dims = [(m, n, l, k)]
     forms, outputs, unrefined, main = {}, {}, {}, None
@@ -296,7 +302,7 @@ def run_single(args, rt, synth, np, torch):
     ms_per_step, info, stages, steps = main
     value = k / (ms_per_step / 1e3)
     paper = None if args.no_forms else paper_columns(rt, torch, np, At, Bt, m, n, l, k, seed, kappa, main_prec)
-    bits = {"fp64": "f64", "mixed_fp32": "f64+f32", "mixed_bf16": "f64+bf16"}[main_prec]
+    bits = {"fp64": "f64", "mixed_fp32": "f64+f32", "mixed_bf16": "f64+bf16", "mixed_bf16x3": "f64+f32+bf16x3"}[main_prec]
     result = {
         "metric": METRIC, "value": value, "unit": "projections/s", "n_gpus": 1, "steps": steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
@@ -787,7 +793,7 @@ def main():
                     choices=["plain_512x65536", "plain_64x4096", "mixed_2048x262144", "batch_256",
                              "ipm_1024x131072", "paper_400x1000000", "complex_512x32768"])
     ap.add_argument("--precision", default=None, choices=list(PRECISIONS),
-                    help="form of the main line (default: fp64, or mixed_fp32 for the mixed workload)")
+                    help="form of the main line (default: fp64, or mixed_bf16x3 for the mixed workload)")
     ap.add_argument("--no-forms", action="store_true", help="time only the main precision")
     ap.add_argument("--form-steps", type=int, default=10, help="timed steps of the other precision forms")
     ap.add_argument("--refine-steps", type=int, default=-1, help="-1: chosen from the pivoted-QR rank estimate")

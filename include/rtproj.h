@@ -76,9 +76,15 @@ typedef enum {
                                    the sketch is redone in binary64 when its rank
                                    estimate shows it too coarse (2^-24 kappa_est >
                                    1) or the Gram shows cond(P^{-1}A) > 10          */
-    RTPROJ_PREC_MIXED_BF16 = 2  /* binary32 sketch; Gram from row-scaled (powers of
+    RTPROJ_PREC_MIXED_BF16 = 2, /* binary32 sketch; Gram from row-scaled (powers of
                                    two) bfloat16 P^{-1}A on MFMA with binary32
                                    accumulation; P^{-1}A as in MIXED_FP32             */
+    RTPROJ_PREC_MIXED_BF16X3 = 3 /* as MIXED_FP32, the Gram from binary32 P^{-1}A split
+                                   into bfloat16 halves w = hi + lo (+ about 2^-16 w):
+                                   hi lo^T + lo hi^T + hi hi^T on bfloat16 MFMA with
+                                   binary32 accumulation (about 2^-16 relative per
+                                   product).  Needs n % 4 == 0; otherwise the Gram
+                                   is binary32 as in MIXED_FP32 (gram_bits 32)       */
 } rtproj_precision;
 
 /* How the pivoted QR of the sketch (eq. QR_decomp) is computed.  All modes
@@ -89,8 +95,12 @@ typedef enum {
     RTPROJ_QR_AUTO = 0,         /* chosen by the plan from the sizes              */
     RTPROJ_QR_DIRECT = 1,       /* Householder QRCP of S^T (l x m), one
                                    cooperative launch                            */
-    RTPROJ_QR_TWO_STAGE = 2,    /* S^T = Q0 R0 by shifted Cholesky QR (three
-                                   Gram/Cholesky passes on MFMA, binary64), then
+    RTPROJ_QR_TWO_STAGE = 2,    /* the factor R0 of S^T = Q0 R0 by shifted
+                                   Cholesky QR and one unshifted pass (two
+                                   Gram/Cholesky passes on MFMA, binary64;
+                                   Q0 is not formed; a third pass when the
+                                   second factor's diagonal spans more than
+                                   1e5, a nearly rank-deficient sketch), then
                                    the cooperative QRCP of R0 (m x m)            */
     RTPROJ_QR_TWO_STAGE_WG = 3  /* as 2, the QRCP of R0 in one workgroup         */
 } rtproj_qr_mode;
@@ -180,7 +190,8 @@ typedef struct {
     double refine_last_ratio;  /* |dx| / |x| of the last refinement step             */
     int qrcp_blocks;           /* workgroups of the cooperative pivoted QR           */
     int sketch_bits, w_bits, gram_bits; /* precisions used by the last precondition:
-                                   64 binary64, 32 binary32, 16 bfloat16             */
+                                   64 binary64, 32 binary32, 16 bfloat16, 17 split
+                                   bfloat16 (hi + lo halves)                         */
     int sketch_escalated;      /* a binary32 sketch was redone in binary64: 1 right
                                   after the pivoted QR (2^-24 kappa_est > 1, or a
                                   failed rank test), 2 after the Gram (gram_cond_est
@@ -445,7 +456,7 @@ rtproj_status rtproj_sketch_tables(rtproj_plan plan, int64_t *dims3, int8_t *sig
  * m[i] x n[i] matrix sketched to l[i] columns, 1 <= m[i] <= l[i] <= n[i],
  * m[i] <= 2048), preconditioned and projected together with ONE grouped
  * launch per stage of the path for all members.  The pivoted QR of member i
- * is the two-stage form (S^T = Q0 R0 by shifted Cholesky QR, then the QRCP of
+ * is the two-stage form (R0 of S^T = Q0 R0 by shifted Cholesky QR, then the QRCP of
  * R0, in one workgroup per member or, for few large members, in a group of
  * blocks per member that synchronize only among themselves; the batch picks
  * the faster from the sizes and rtproj_batch_info reports it as qr_mode

@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librtproj.so")
 _lib = None
 
-PREC_FP64, PREC_MIXED_FP32, PREC_MIXED_BF16 = 0, 1, 2
+PREC_FP64, PREC_MIXED_FP32, PREC_MIXED_BF16, PREC_MIXED_BF16X3 = 0, 1, 2, 3
 STATUS = {0: "OK", 1: "ERR_INVALID_ARG", 2: "ERR_ALLOC", 3: "ERR_DEVICE", 4: "ERR_STATE",
           5: "ERR_RANK", 6: "ERR_NOCONV", 7: "ERR_UNSUPPORTED"}
 

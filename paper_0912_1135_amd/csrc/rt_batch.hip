@@ -333,7 +333,9 @@ void build_precondition(Program &P, rtproj_batch b, const double *const *A, cons
         o.count = (int)flags.size();
         P.push(o);
     }
-    // 2a. R0 by shifted Cholesky QR
+    // 2a. R0 by shifted Cholesky QR with all three passes: a graph cannot
+    // skip the third on a device-side test, and it is what resolves a
+    // member's numerical rank deficiency to about u |S|
     P.stage = 12;
     {
         std::vector<rt::CopyGroupArgs> c(cnt);
@@ -1023,7 +1025,8 @@ rtproj_status rtproj_batch_set_precision(rtproj_batch b, int precision)
 {
     if (!b) return fail(RTPROJ_ERR_INVALID_ARG, "null batch");
     if (precision != RTPROJ_PREC_FP64 && precision != RTPROJ_PREC_MIXED_FP32)
-        return fail(precision == RTPROJ_PREC_MIXED_BF16 ? RTPROJ_ERR_UNSUPPORTED : RTPROJ_ERR_INVALID_ARG,
+        return fail(precision == RTPROJ_PREC_MIXED_BF16 || precision == RTPROJ_PREC_MIXED_BF16X3
+                        ? RTPROJ_ERR_UNSUPPORTED : RTPROJ_ERR_INVALID_ARG,
                     "batches take RTPROJ_PREC_FP64 or RTPROJ_PREC_MIXED_FP32");
     b->precision = precision;
     return RTPROJ_OK;

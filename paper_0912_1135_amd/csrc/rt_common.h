@@ -114,7 +114,7 @@ hipError_t reduce_splits_f64(const double *part, int64_t stride, int splits, int
 // binary32 accumulation.  A/B are read from binary64 (x_dbl = 1) or binary32
 // storage, multiplied by the optional power-of-two scales a_scale[i] /
 // b_scale[j] and rounded; C is written as binary64 (c_dbl = 1) or binary32.
-enum { MX_F32 = 0, MX_BF16 = 1 };
+enum { MX_F32 = 0, MX_BF16 = 1, MX_BF16X3 = 2 };
 struct GemmMxArgs {
     int M, N, K;
     const void *A; int a_dbl; int64_t a_i, a_k; const int32_t *a_gather; const float *a_scale;
@@ -125,6 +125,10 @@ struct GemmMxArgs {
     int tile;         // binary32: 0 chosen from the shape; 64 or 128 forces it
 };
 hipError_t gemm_mx(const GemmMxArgs &g, int mode, hipStream_t stream);
+// MX_BF16X3 takes binary32, K-contiguous, unscaled, ungathered, full operands
+// with 16-byte aligned rows and K % 4 == 0 (the Gram of a row-major binary32
+// matrix whose row length is a multiple of 4).
+bool gemm_mx_bf16x3_ok(const GemmMxArgs &g);
 // Grouped binary32 Gram of binary64 operands (batches): the lower 64 x 64
 // tiles of each member's C = A B (A, B K-contiguous), K split ksmax ways
 // (members with fewer splits skip the extra ones); then the binary64

@@ -2,6 +2,8 @@
 // binary32 accumulation:
 //   * MX_F32:  v_mfma_f32_16x16x4_f32   (binary32 operands)
 //   * MX_BF16: v_mfma_f32_16x16x32_bf16 (bfloat16 operands)
+//   * MX_BF16X3: three v_mfma_f32_16x16x32_bf16 per product, on binary32
+//     operands split into bfloat16 halves (hi + lo)
 // Operands are read from binary64 or binary32 storage and rounded on the way
 // into LDS; an optional per-row (A) / per-column (B) power-of-two scale is
 // applied before the rounding (exact).  Used for P^{-1}A in binary32 and for
@@ -337,6 +339,161 @@ __global__ __launch_bounds__(256) void gemm_f32_grouped_kernel(const GemmMxArgs 
     gemm_f32_tile<BM, BN, A_KC, B_KC, DBL, false>(g, blockIdx.x, blockIdx.y, blockIdx.z % ksmax);
 }
 
+// Split-bfloat16 product of binary32 operands (same operand conditions as
+// gemm_f32_kc_kernel).  Each element w is written to LDS as two bfloat16
+// halves, hi = bf16(w) and lo = bf16(w - hi) (w - hi is exact in binary32),
+// and every 32 k of a 16 x 16 output tile take three bfloat16 MFMAs,
+// lo hi^T + hi lo^T + hi hi^T, accumulated in binary32; the products of two
+// bfloat16 values are exact in binary32, so the only error besides the
+// accumulation is the dropped lo lo^T and the rounding of lo, together at
+// most about 2^-16 |w| |v| per product.  LDS rows hold KV + 8 bfloat16
+// (80 bytes: 16-byte aligned, conflict-free for the 16-lane reads).
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void gemm_bf16x3_kc_kernel(GemmMxArgs g)
+{
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+    typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+    constexpr int LDB = KV + 8;
+    __shared__ __attribute__((aligned(16))) __bf16 Ah[2][BM * LDB];
+    __shared__ __attribute__((aligned(16))) __bf16 Al[2][BM * LDB];
+    __shared__ __attribute__((aligned(16))) __bf16 Bh[2][BN * LDB];
+    __shared__ __attribute__((aligned(16))) __bf16 Bl[2][BN * LDB];
+    constexpr int TM = BM / 32, TN = BN / 32;
+    constexpr int Q = KV / 4;
+    constexpr int NA = BM * Q / 256, NB = BN * Q / 256;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    int bx = blockIdx.x, bz = blockIdx.z;
+    int ti, tj;
+    if (g.c_lower) {
+        const int64_t total = (int64_t)gridDim.x * gridDim.z;
+        if ((total & 7) == 0) {
+            const int64_t L = bx + (int64_t)gridDim.x * bz;
+            const int64_t N = (L & 7) * (total >> 3) + (L >> 3);
+            bx = (int)(N % gridDim.x);
+            bz = (int)(N / gridDim.x);
+        }
+        const int t = bx;
+        ti = (int)((__builtin_sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+        while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+        while (ti * (ti + 1) / 2 > t) --ti;
+        tj = t - ti * (ti + 1) / 2;
+    } else {
+        ti = blockIdx.y;
+        tj = bx;
+    }
+    const int i0 = ti * BM, j0 = tj * BN;
+    int kbeg = 0, kend = g.K;
+    if (g.ksplit > 1) {
+        int ks = (g.K + g.ksplit - 1) / g.ksplit;
+        ks = (ks + KV - 1) / KV * KV;
+        kbeg = bz * ks;
+        kend = min(g.K, kbeg + ks);
+    }
+    const int nch = kend > kbeg ? (kend - kbeg + KV - 1) / KV : 0;
+    const float *Ap = static_cast<const float *>(g.A);
+    const float *Bp = static_cast<const float *>(g.B);
+    int64_t a_off[NA], b_off[NB];
+    bool a_in[NA], b_in[NB];
+    const int kq = 4 * (tid % Q);
+#pragma unroll
+    for (int e = 0; e < NA; ++e) {
+        const int i = i0 + (tid + 256 * e) / Q;
+        a_in[e] = i < g.M;
+        a_off[e] = (int64_t)(a_in[e] ? i : g.M - 1) * g.a_i;
+    }
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+        const int j = j0 + (tid + 256 * e) / Q;
+        b_in[e] = j < g.N;
+        b_off[e] = (int64_t)(b_in[e] ? j : g.N - 1) * g.b_j;
+    }
+    f4 ra[NA], rb[NB];
+    auto load = [&](int c) {
+        const int k = kbeg + c * KV + kq;
+        const bool kin = k < kend;
+        const int kc = kin ? k : kend - 4;
+#pragma unroll
+        for (int e = 0; e < NA; ++e) {
+            const f4 v = *reinterpret_cast<const f4 *>(Ap + a_off[e] + kc);
+            ra[e] = (kin && a_in[e]) ? v : f4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+        for (int e = 0; e < NB; ++e) {
+            const f4 v = *reinterpret_cast<const f4 *>(Bp + b_off[e] + kc);
+            rb[e] = (kin && b_in[e]) ? v : f4{0.f, 0.f, 0.f, 0.f};
+        }
+    };
+    auto split = [](const f4 &v, bf4 &hi, bf4 &lo) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            hi[u] = (__bf16)v[u];
+            lo[u] = (__bf16)(v[u] - (float)hi[u]);
+        }
+    };
+    f4 acc[TM][TN];
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+    if (nch > 0) load(0);
+    for (int t = 0; t < nch; ++t) {
+        const int buf = t & 1;
+#pragma unroll
+        for (int e = 0; e < NA; ++e) {
+            bf4 hi, lo;
+            split(ra[e], hi, lo);
+            const int o = ((tid + 256 * e) / Q) * LDB + kq;
+            *reinterpret_cast<bf4 *>(&Ah[buf][o]) = hi;
+            *reinterpret_cast<bf4 *>(&Al[buf][o]) = lo;
+        }
+#pragma unroll
+        for (int e = 0; e < NB; ++e) {
+            bf4 hi, lo;
+            split(rb[e], hi, lo);
+            const int o = ((tid + 256 * e) / Q) * LDB + kq;
+            *reinterpret_cast<bf4 *>(&Bh[buf][o]) = hi;
+            *reinterpret_cast<bf4 *>(&Bl[buf][o]) = lo;
+        }
+        __syncthreads();
+        if (t + 1 < nch) load(t + 1);
+        bf8 ah[TM], al[TM], bh[TN], bl[TN];
+#pragma unroll
+        for (int a = 0; a < TM; ++a) {
+            const int o = (wm * (BM / 2) + a * 16 + (lane & 15)) * LDB + 8 * (lane >> 4);
+            ah[a] = *reinterpret_cast<const bf8 *>(&Ah[buf][o]);
+            al[a] = *reinterpret_cast<const bf8 *>(&Al[buf][o]);
+        }
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+            const int o = (wn * (BN / 2) + b * 16 + (lane & 15)) * LDB + 8 * (lane >> 4);
+            bh[b] = *reinterpret_cast<const bf8 *>(&Bh[buf][o]);
+            bl[b] = *reinterpret_cast<const bf8 *>(&Bl[buf][o]);
+        }
+#pragma unroll
+        for (int a = 0; a < TM; ++a)
+#pragma unroll
+            for (int b = 0; b < TN; ++b) {
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+            }
+    }
+    const int64_t coff = g.ksplit > 1 ? (int64_t)bz * g.c_split : 0;
+    float *C = static_cast<float *>(g.C);
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + wm * (BM / 2) + a * 16 + 4 * (lane >> 4) + r;
+                const int j = j0 + wn * (BN / 2) + b * 16 + (lane & 15);
+                if (i < g.M && j < g.N) C[coff + (int64_t)i * g.c_i + (int64_t)j * g.c_j] = g.alpha * acc[a][b][r];
+            }
+}
+
 // ---------------------------------------------------------------- bfloat16
 // Both operands K-contiguous (the Gram of a row-major matrix): LDS tiles are
 // [mn][KB + 8] bfloat16, so each lane's 8 consecutive k are one 16-byte read
@@ -564,9 +721,19 @@ __global__ void to_f32_kernel(const double *src, int64_t lds, float *dst, int64_
 
 }  // namespace
 
+bool gemm_mx_bf16x3_ok(const GemmMxArgs &g) { return kc_fast(g); }
+
 hipError_t gemm_mx(const GemmMxArgs &g, int mode, hipStream_t stream)
 {
     if (g.M <= 0 || g.N <= 0) return hipSuccess;
+    if (mode == MX_BF16X3) {
+        if (!kc_fast(g)) return hipErrorInvalidValue;
+        const int gm = (g.M + 127) / 128, gn = (g.N + 127) / 128;
+        dim3 grid = g.c_lower ? dim3(gm * (gm + 1) / 2, 1, g.ksplit > 1 ? g.ksplit : 1)
+                              : dim3(gn, gm, g.ksplit > 1 ? g.ksplit : 1);
+        hipLaunchKernelGGL((gemm_bf16x3_kc_kernel<128, 128>), grid, dim3(256), 0, stream, g);
+        return hipGetLastError();
+    }
     if (mode == MX_BF16) {
         if (g.a_k != 1 || g.b_k != 1 || g.a_gather || g.b_gather || g.a_lower) return hipErrorInvalidValue;
         const int gm = (g.M + 127) / 128, gn = (g.N + 127) / 128;

@@ -296,8 +296,9 @@ rtproj_status alloc_state(rtproj_plan p)
     if (gcols || gcols0)
         RT_HIP(dalloc(&p->d_qrcols, (size_t)16 * std::max<int64_t>(gcols ? p->qr_blocks * l : 0,
                                                                      gcols0 ? p->qr_blocks0 * m : 0)));
-    // two-stage pivoted QR: iterate of the Cholesky QR and R0
+    // two-stage pivoted QR: iterates of the Cholesky QR and R0
     RT_HIP(dalloc(&p->d_Yq, (size_t)m * l));
+    RT_HIP(dalloc(&p->d_Yq2, (size_t)m * l));
     RT_HIP(dalloc(&p->d_R0, (size_t)m * m));
     {
         rt::QrcpWgArgs wa{};
@@ -322,12 +323,12 @@ rtproj_status alloc_state(rtproj_plan p)
         RT_HIP(hipStreamSynchronize(p->stream));  // cleared before any stream the caller sets uses them
     }
     // recursive-doubling inverses: R^{-T} (L = R^T, read as L(i, j) =
-    // R[j m + i]) into d_Y with d_L as scratch; for the two-stage QR the
-    // inverses of the first two Cholesky factors (in d_L and d_Y, row-major)
-    // into d_Linv with d_G as scratch
+    // R[j m + i]) into d_Y with d_L as scratch; the inverses of Cholesky
+    // factors in d_L (the Cholesky QR's first factor, and the Gram's) and
+    // d_Y (the Cholesky QR's second factor), row-major, into d_Linv with d_G
+    // as scratch
     RT_HIP(build_tri_inverse(m, p->d_R, 1, m, p->d_Y, p->d_L, p->rinv));
     RT_HIP(dalloc(&p->d_Linv, (size_t)m * m));
-    RT_HIP(dalloc(&p->d_Yq2, (size_t)m * l));
     RT_HIP(build_tri_inverse(m, p->d_L, m, 1, p->d_Linv, p->d_G, p->linv[0]));
     RT_HIP(build_tri_inverse(m, p->d_Y, m, 1, p->d_Linv, p->d_G, p->linv[1]));
     return RTPROJ_OK;
@@ -578,14 +579,24 @@ rtproj_status form_factors_ns(rtproj_plan p)
     return RTPROJ_OK;
 }
 
-// First stage of the two-stage pivoted QR: S^T = Q0 R0 by shifted Cholesky
-// QR (Fukaya, Kannan, Nakatsukasa, Yamamoto, Yanagisawa 2020): with X = S^T,
+// First stage of the two-stage pivoted QR: the factor R0 of S^T = Q0 R0 by
+// shifted Cholesky QR (Fukaya, Kannan, Nakatsukasa, Yamamoto, Yanagisawa
+// 2020) and one unshifted pass: with X = S^T,
 //   R1^T R1 = X^T X + s I,  s = 11 (l m + m (m+1)) 2^-53 |X|_F^2,
-//   Q1 = X R1^{-1}, then two unshifted passes Q_{j+1} = Q_j R_{j+1}^{-1},
-//   R0 = R3 R2 R1.
-// Working with transposes: Y = Q^T = L^{-1} S and R0^T = L1 L2 L3 (lower),
-// which is R0 in column-major order, the layout the second stage reads.
-// Sets d_err when a Cholesky fails (then the direct method is used).
+//   Q1 = X R1^{-1},  R2^T R2 = Q1^T Q1,  R0 = R2 R1.
+// The second stage needs R0 only, never Q0: R0^T R0 = R1^T Q1^T Q1 R1 is
+// X^T X up to R1^T E R1 with |E| of order u (the shift cancels, Q1 being
+// formed from X and not from its Gram), so R0^{-T} X^T X R0^{-1} is the
+// identity up to about u cond(Q1)^2.  The published method's third pass,
+// Q2 = Q1 R2^{-1}, R3^T R3 = Q2^T Q2, R0 = R3 R2 R1, makes Q0 orthonormal,
+// which only matters here when Q1 is itself nearly rank deficient (X
+// numerically rank deficient below the shift): then R2 resolves the
+// smallest singular values of X only to about sqrt(u) |X| and the rank test
+// would miss them.  So the third pass runs when diag(R2) spans more than
+// 1 / RT_CQR_THIRD (read back after the second Cholesky).  Working with
+// transposes: Y = Q^T = L^{-1} S and R0^T = L1 L2 (L3), lower, which is R0
+// in column-major order, the layout the second stage reads.  Sets d_err
+// when a Cholesky fails (then the direct method is used).
 rtproj_status r0_factor(rtproj_plan p)
 {
     const int64_t m = p->m, l = p->l;
@@ -616,11 +627,23 @@ rtproj_status r0_factor(rtproj_plan p)
             tune_store(key, rcfg);
         }
     }
-    for (int it = 0; it < 3; ++it) {
+    int passes = 2;
+    for (int it = 0; it < passes; ++it) {
         RT_HIP(gram_f64_cfg(p, Yin[it], l, l, p->d_G, rcfg[0], rcfg[1]));
         if (it == 0) RT_HIP(rt::shift_diag_f64(p->d_G, m, (int)m, shift, s));
         if ((st = cholesky(p, p->d_G, Ls[it], p->d_DinvL)) != RTPROJ_OK) return st;
-        if (it < 2) {
+        if (it == 1) {
+            double d2[4];
+            int cerr = 0;
+            RT_HIP(rt::rdiag_ends_f64(Ls[1], m, (int)m, p->d_diag, s));
+            RT_HIP(hipMemcpyAsync(d2, p->d_diag, 32, hipMemcpyDeviceToHost, s));
+            RT_HIP(hipMemcpyAsync(&cerr, p->d_err, 4, hipMemcpyDeviceToHost, s));
+            RT_HIP(hipStreamSynchronize(s));
+            if (cerr) return RTPROJ_OK;  // the caller reads d_err and factors S^T directly
+            if (!(d2[2] > RT_CQR_THIRD * d2[3])) passes = 3;
+        }
+        p->r0_passes = passes;
+        if (it + 1 < passes) {
             // next iterate L^{-1} Y: the explicit inverse (its diagonal blocks
             // come from the Cholesky), then one triangular MFMA product
             RT_HIP(run_tri_inverse(p, p->linv[it], p->d_DinvL, p->d_Linv));
@@ -633,13 +656,13 @@ rtproj_status r0_factor(rtproj_plan p)
             RT_HIP(rt::gemm_f64(g, s));
         }
     }
-    // R0^T = (L1 L2) L3, products of lower-triangular factors
-    for (int pass = 0; pass < 2; ++pass) {
+    // R0^T = L1 L2 (then times L3), products of lower-triangular factors
+    for (int pass = 0; pass + 1 < passes; ++pass) {
         rt::GemmArgs g{};
         g.M = (int)m; g.N = (int)m; g.K = (int)m;
         g.A = pass == 0 ? Ls[0] : p->d_G; g.a_i = m; g.a_k = 1; g.a_lower = 1;
-        g.B = pass == 0 ? Ls[1] : Ls[2]; g.b_k = m; g.b_j = 1;
-        g.C = pass == 0 ? p->d_G : p->d_R0; g.c_i = m; g.c_j = 1;
+        g.B = Ls[pass + 1]; g.b_k = m; g.b_j = 1;
+        g.C = pass + 2 == passes ? p->d_R0 : p->d_G; g.c_i = m; g.c_j = 1;
         g.alpha = 1.0; g.ksplit = 1;
         RT_HIP(rt::gemm_f64(g, s));
     }
@@ -657,7 +680,8 @@ bool ld_ok(int64_t ld, int64_t need) { return ld >= need && ld > 0; }
 //   - a binary32 Gram accumulated on MFMA in binary32 over K terms per
 //     split: u_32 K / 32 (measured u_32 K / 117 at K = 256 and 32768), times
 //     cond(P^{-1}A)^2 / 9 relative to a healthy preconditioner (cond ~ 3);
-//     a bfloat16 Gram adds the rounding of its inputs, 4e-3 (measured 3.9e-3).
+//     a bfloat16 Gram adds the rounding of its inputs, 4e-3 (measured 3.9e-3);
+//     a split-bfloat16 Gram (hi + lo halves, three products) 2^-8 of that.
 // A step with a plain binary64 residual takes the error to max(rho e, F)
 // with the floor F = RT_FLOOR_C u kappa; a compensated step to rho e (its
 // own floor is near u^2 kappa^2).  Plain steps cost a tenth of a compensated
@@ -671,9 +695,9 @@ double refine_rho_model(double kappa_est, int precision, bool w32, double cond_w
     const double wterm = w32 ? 2.0 * std::ldexp(1.0, -23) * k : 16.0 * std::ldexp(1.0, -52) * k;
     const double c2 = std::max(1.0, cond_w * cond_w / 9.0);
     double gram = 0.0;
-    if (precision == RTPROJ_PREC_MIXED_FP32 || precision == RTPROJ_PREC_MIXED_BF16)
-        gram = std::ldexp(1.0, -24) * std::max(1.0, gram_k) / 32.0 * c2;
+    if (precision != RTPROJ_PREC_FP64) gram = std::ldexp(1.0, -24) * std::max(1.0, gram_k) / 32.0 * c2;
     if (precision == RTPROJ_PREC_MIXED_BF16) gram += 4e-3 * c2;
+    if (precision == RTPROJ_PREC_MIXED_BF16X3) gram += 4e-3 / 256.0 * c2;
     return std::min(0.5, wterm + gram);
 }
 
@@ -1301,7 +1325,8 @@ rtproj_status rtproj_plan_set_stream(rtproj_plan p, void *stream)
 rtproj_status rtproj_plan_set_precision(rtproj_plan p, int precision)
 {
     if (!p) return fail(RTPROJ_ERR_INVALID_ARG, "null plan");
-    if (precision != RTPROJ_PREC_FP64 && precision != RTPROJ_PREC_MIXED_FP32 && precision != RTPROJ_PREC_MIXED_BF16)
+    if (precision != RTPROJ_PREC_FP64 && precision != RTPROJ_PREC_MIXED_FP32 && precision != RTPROJ_PREC_MIXED_BF16 &&
+        precision != RTPROJ_PREC_MIXED_BF16X3)
         return fail(RTPROJ_ERR_INVALID_ARG, "unknown precision");
     p->precision = precision;
     return RTPROJ_OK;
@@ -1639,6 +1664,9 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
         return rt::gemm_f64(g, s);
     };
     const bool bf = p->precision == RTPROJ_PREC_MIXED_BF16;
+    // the split-bfloat16 Gram needs W's rows 16-byte aligned (n % 4 == 0);
+    // otherwise that precision takes the binary32 Gram
+    bool x3 = false;
     auto run_gram = [&](int splits, int tile) -> hipError_t {
         hipError_t e;
         if (!lp) {
@@ -1659,7 +1687,8 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
         g.B = p->d_W; g.b_dbl = wd; g.b_k = 1; g.b_j = n; g.b_scale = bf ? p->d_rowscale : nullptr;
         g.C = p->d_part; g.c_dbl = 0; g.c_i = m; g.c_j = 1; g.c_split = m * m;
         g.alpha = 1.f; g.c_lower = 1; g.ksplit = splits; g.tile = tile;
-        if ((e = rt::gemm_mx(g, bf ? rt::MX_BF16 : rt::MX_F32, s)) != hipSuccess) return e;
+        x3 = p->precision == RTPROJ_PREC_MIXED_BF16X3 && rt::gemm_mx_bf16x3_ok(g);
+        if ((e = rt::gemm_mx(g, bf ? rt::MX_BF16 : (x3 ? rt::MX_BF16X3 : rt::MX_F32), s)) != hipSuccess) return e;
         return rt::reduce_f32_splits(reinterpret_cast<const float *>(p->d_part), m * m, splits > 1 ? splits : 1, (int)m,
                                      (int)m, m, bf ? p->d_rowscale : nullptr, bf ? p->d_rowscale : nullptr, p->d_G, m,
                                      1, s);
@@ -1681,7 +1710,8 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
             wcfg = cands[best];
             tune_store(wkey, wcfg);
         }
-        const std::string gkey = tune_key(!lp ? "g64" : (bf ? "g16" : "g32"), m, n, 0);
+        const bool x3req = p->precision == RTPROJ_PREC_MIXED_BF16X3;
+        const std::string gkey = tune_key(!lp ? "g64" : (bf ? "g16" : (x3req ? "g3" : "g32")), m, n, 0);
         if (!tune_lookup(gkey, gcfg)) {
             // run W once with the chosen configuration so the Gram reads it
             RT_HIP(run_w(wcfg[0], wcfg[1], wcfg.size() > 2 ? wcfg[2] : 0));
@@ -1720,7 +1750,7 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
     }
     p->info.sketch_bits = (lp && !sketch64 && !p->Gmat) ? 32 : 64;
     p->info.w_bits = p->w32 ? 32 : 64;
-    p->info.gram_bits = !lp ? 64 : (p->precision == RTPROJ_PREC_MIXED_BF16 ? 16 : 32);
+    p->info.gram_bits = !lp ? 64 : (bf ? 16 : (x3 ? 17 : 32));
     // 6-7. Y = X^{-1} (eq. inversion) and the form of M^{-1} the projections apply
     p->inv_used = p->inv_method != RTPROJ_INV_AUTO ? p->inv_method
                   : (m <= RT_NS_MAX_M ? RTPROJ_INV_NEWTON_SCHULZ : RTPROJ_INV_CHOLESKY);

@@ -41,6 +41,11 @@ constexpr double RT_W32_KAPPA_MAX = 1e5;
 // Reduced-precision modes redo the sketch in binary64 when max/min diag of
 // the Gram's Cholesky factor exceeds this (a healthy preconditioner gives ~3).
 constexpr double RT_COND_ESCALATE = 10.0;
+// Two-stage QR: a third Cholesky QR pass runs when the second factor's
+// diagonal spans more than 1 / RT_CQR_THIRD (its iterate nearly rank
+// deficient, so the two-pass R0 would resolve the smallest singular values
+// of the sketch only to about sqrt(u) |S|).
+constexpr double RT_CQR_THIRD = 1e-5;
 // Automatic choice of the Gram inverse: Newton-Schulz (about a dozen pairs of
 // m^3 products, latency-light) up to this m, the blocked Cholesky (m^3 / 3,
 // but a chain of small diagonal steps) above it.
@@ -235,15 +240,16 @@ struct rtproj_plan_s {
     int inv_used = 0;          // RTPROJ_INV_NEWTON_SCHULZ or RTPROJ_INV_CHOLESKY, last precondition
     double *d_bsum = nullptr;  // block sums of squares of the Newton-Schulz residual (ns_bsum_count(m))
     double *d_Yq = nullptr;    // two-stage: the m x l iterate of the Cholesky QR
+    double *d_Yq2 = nullptr;   // two-stage: the third pass's m x l iterate
+    int r0_passes = 0;         // two-stage: Cholesky QR passes of the last R0 (2 or 3)
     double *d_R0 = nullptr;    // two-stage: R0^T (lower, row-major m x m)
     rt::QrcpWgArgs *d_wgargs = nullptr;
     // R^{-T} by recursive doubling: per level, the grouped products
     // T = L21 X11 and X21 = -X22 T over all block pairs (device argument
     // arrays built at plan creation)
     TriInverse rinv;           // R^{-T} into d_Y (scratch d_L)
-    TriInverse linv[2];        // two-stage: L^{-1} of the first two Cholesky factors (d_L, d_Y) into d_Linv (scratch d_G)
+    TriInverse linv[2];        // L^{-1} of the Cholesky factors in d_L and d_Y into d_Linv (scratch d_G)
     double *d_Linv = nullptr;  // two-stage: inverse of the current Cholesky factor
-    double *d_Yq2 = nullptr;   // two-stage: the next m x l iterate of the Cholesky QR
     bool w32 = false;          // P^{-1}A held in binary32 by the last precondition
     int syrk_splits = 1;
     int wgram_splits = 1;  // K splits of the Gram of P^-1 A (balanced over the compute units)
