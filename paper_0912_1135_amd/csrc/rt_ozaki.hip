@@ -24,8 +24,9 @@
 // are A's columns, K = m, the whole sum in one block) and s = A r (r binary64;
 // the rows are A's rows, K = n split over blocks, double-binary64 partials
 // summed by the compensated split reduction).  A's digits are formed on the
-// fly from binary64 A for each 64 x 64 tile; the right-hand sides' digits
-// come from a small digit kernel.
+// fly from binary64 A for each 64 x 64 tile, three or four digits per
+// binary64 rounding (oz_digit_group); the right-hand sides' digits come from
+// a small digit kernel.
 #include <algorithm>
 #include <climits>
 
@@ -35,7 +36,7 @@ namespace rt {
 
 namespace {
 
-constexpr int OZ_T = 256;
+constexpr int OZ_T = 512;
 constexpr double OZ_ROUND = 6755399441055744.0;  // 1.5 * 2^52: x + OZ_ROUND rounds x to an integer for |x| < 2^51
 constexpr int OZ_TILE = 64;        // A-operand rows and right-hand sides per block; K per chunk
 constexpr int OZ_LD = OZ_TILE + 16;  // LDS row stride in bytes (16-byte reads of 8 lanes on distinct banks)
@@ -145,122 +146,149 @@ __global__ __launch_bounds__(256) void oz_digits_kernel(const double *vh, const 
     }
 }
 
+// Digits s0 .. s0 + J - 1 of a value v with |v| <= 1/2 on the frame of digit
+// s0: D = round(128^J v) in one binary64 rounding (adding 1.5 * 2^52, whose
+// sum t keeps D, |D| <= 2^(7J-1) < 2^31, in two's complement in the low word
+// of its bits), then D's balanced base-128 digits from the least
+// significant: digit i is the signed 7-bit field at bit 7i of
+// E_i = D + 64 (128^i - 1) / 127, the top digit all of E_{J-1} above bit
+// 7(J-1) (so in [-64, 64]).  v becomes 128^J v - D, exact, |v| <= 1/2 on
+// the next frame.  Digit s lands in byte u of wd[s].
+static_assert(OZ_S == 11, "the digit groups below cover 4 + 4 + 3 digits");
+template <int J, bool LAST>
+__device__ __forceinline__ void oz_digit_group(double &v, int u, int (&wd)[OZ_S], int s0)
+{
+    constexpr double sc = (double)(1 << (7 * J));
+    const double t = __builtin_fma(v, sc, OZ_ROUND);
+    if (!LAST) v = __builtin_fma(v, sc, -(t - OZ_ROUND));
+    int E = (int)(unsigned)__builtin_bit_cast(unsigned long long, t);
+#pragma unroll
+    for (int i = 0; i < J; ++i) {
+        const int dg = i + 1 < J ? __builtin_amdgcn_sbfe(E, 7 * i, 7) : (E >> (7 * i));
+        wd[s0 + J - 1 - i] |= (dg & 0xff) << (8 * u);
+        E += 64 << (7 * i);
+    }
+}
+
 // One 64 x 64 tile (A-operand rows r0.., right-hand sides c0..) over the K
 // range of split blockIdx.z.  TRANS: the A-operand rows are A's columns (A^T x,
-// K = m); otherwise A's rows (A r, K = n).
+// K = m); otherwise A's rows (A r, K = n).  Eight waves: wave w takes the 16
+// rows 16 (w % 4) .. and the 32 right-hand sides 32 (w / 4) .., so that its
+// 12 x 2 accumulator tiles (96 registers) leave room for two waves per SIMD,
+// which hide each other's issue and LDS stalls; each thread forms the digits
+// of 8 of the tile's A values per chunk.
 template <bool TRANS>
 __global__ __launch_bounds__(OZ_T) void oz_mm_kernel(OzArgs g)
 {
     __shared__ __attribute__((aligned(16))) int8_t As[OZ_S][OZ_TILE * OZ_LD];
     __shared__ __attribute__((aligned(16))) int8_t Bs[OZ_S][OZ_TILE * OZ_LD];
+    typedef int int2v __attribute__((ext_vector_type(2)));
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int rw = w & 3, ch = w >> 2;
     const int r0 = blockIdx.x * OZ_TILE, c0 = blockIdx.y * OZ_TILE;
     const int64_t kbeg = (int64_t)blockIdx.z * g.kchunk;
     const int64_t kend = min((int64_t)g.K, kbeg + g.kchunk);
     // (an empty split of A r still writes its zero partials below)
-    // this thread's part of the A tile: one A-operand row, 16 consecutive k
-    const int lrow = TRANS ? (tid & 63) : (tid >> 2);
-    const int lk = TRANS ? 16 * (tid >> 6) : 16 * (tid & 3);
+    // this thread's part of the A tile: one A-operand row, 8 consecutive k
+    const int lrow = TRANS ? (tid & 63) : (tid >> 3);
+    const int lk = TRANS ? 8 * (tid >> 6) : 8 * (tid & 7);
     const int grow = r0 + lrow;
     const bool rok = grow < g.R;
     const int ex = rok ? g.rowexp[grow] : INT_MIN;
     const bool live = ex != INT_MIN;  // (an all-zero row has no scale)
     const int growc = rok ? grow : g.R - 1;
-    // this thread's part of the B digits: right-hand side c0 + bc, 16 k from bk
-    const int bc = tid >> 2, bk = 16 * (tid & 3);
+    // this thread's part of the B digits: right-hand side c0 + bc, 8 k from bk
+    const int bc = tid >> 3, bk = 8 * (tid & 7);
 
-    int4v acc[OZ_NDIAG][4];
+    int4v acc[OZ_NDIAG][2];
 #pragma unroll
     for (int d = 0; d < OZ_NDIAG; ++d)
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct) acc[d][ct] = int4v{0, 0, 0, 0};
+        for (int ct = 0; ct < 2; ++ct) acc[d][ct] = int4v{0, 0, 0, 0};
 
     // chunk loads: raw A values (clamped addresses) and the B digits (padded:
     // always in range); issued one chunk ahead, before the current chunk's
     // products, and used only after them
-    double av[16];
-    int4v bl[OZ_S];
+    double av[8];
+    int2v bl[OZ_S];
     auto load_chunk = [&](int64_t k0) {
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
+        for (int u = 0; u < 8; ++u) {
             const int64_t kk = k0 + lk + u;
             const int64_t kc = kk < kend ? kk : kend - 1;
             av[u] = TRANS ? g.A[kc * g.lda + growc] : g.A[(int64_t)growc * g.lda + kc];
         }
 #pragma unroll
         for (int t = 0; t < OZ_S; ++t)
-            bl[t] = *reinterpret_cast<const int4v *>(g.dig + ((int64_t)t * g.kpad + c0 + bc) * g.Kpad + k0 + bk);
+            bl[t] = *reinterpret_cast<const int2v *>(g.dig + ((int64_t)t * g.kpad + c0 + bc) * g.Kpad + k0 + bk);
     };
     if (kbeg < kend) load_chunk(kbeg);
     for (int64_t k0 = kbeg; k0 < kend; k0 += OZ_TILE) {
         __syncthreads();  // the previous chunk's operand reads are done
 #pragma unroll
-        for (int t = 0; t < OZ_S; ++t) *reinterpret_cast<int4v *>(&Bs[t][bc * OZ_LD + bk]) = bl[t];
-        // A digits, four elements (one 32-bit word per plane) at a time
+        for (int t = 0; t < OZ_S; ++t) *reinterpret_cast<int2v *>(&Bs[t][bc * OZ_LD + bk]) = bl[t];
+        // A digits of 8 elements: two 32-bit words per plane, one 8-byte store
+        {
+            int wd[2][OZ_S];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            int wd[OZ_S];
+            for (int q = 0; q < 2; ++q)
 #pragma unroll
-            for (int s2 = 0; s2 < OZ_S; ++s2) wd[s2] = 0;
+                for (int s2 = 0; s2 < OZ_S; ++s2) wd[q][s2] = 0;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                // on the row's halved power-of-two scale (zero outside the
-                // range), |v| < 1/2; digit d = round(128 v) by adding and
-                // subtracting 1.5 * 2^52, whose sum keeps d (two's
-                // complement) in the low word of its bits
-                double v = (live && k0 + lk + 4 * q + u < kend) ? ldexp(av[4 * q + u], -ex - 1) : 0.0;
+            for (int q = 0; q < 2; ++q)
 #pragma unroll
-                for (int s2 = 0; s2 < OZ_S; ++s2) {
-                    v *= 128.0;
-                    const double t = v + OZ_ROUND;
-                    const double d = t - OZ_ROUND;
-                    v -= d;
-                    wd[s2] |= ((int)(unsigned)__builtin_bit_cast(unsigned long long, t) & 0xff) << (8 * u);
+                for (int u = 0; u < 4; ++u) {
+                    // on the row's halved power-of-two scale (zero outside the
+                    // range), |v| < 1/2; digits in groups of 4, 4 and 3
+                    double v = (live && k0 + lk + 4 * q + u < kend) ? ldexp(av[4 * q + u], -ex - 1) : 0.0;
+                    oz_digit_group<4, false>(v, u, wd[q], 0);
+                    oz_digit_group<4, false>(v, u, wd[q], 4);
+                    oz_digit_group<3, true>(v, u, wd[q], 8);
                 }
-            }
 #pragma unroll
-            for (int s2 = 0; s2 < OZ_S; ++s2) *reinterpret_cast<int *>(&As[s2][lrow * OZ_LD + lk + 4 * q]) = wd[s2];
+            for (int s2 = 0; s2 < OZ_S; ++s2)
+                *reinterpret_cast<int2v *>(&As[s2][lrow * OZ_LD + lk]) = int2v{wd[0][s2], wd[1][s2]};
         }
         __syncthreads();
         if (k0 + OZ_TILE < kend) load_chunk(k0 + OZ_TILE);  // in flight during the products
         int4v aop[OZ_S];
 #pragma unroll
         for (int s = 0; s < OZ_S; ++s)
-            aop[s] = *reinterpret_cast<const int4v *>(&As[s][(16 * w + (lane & 15)) * OZ_LD + 16 * (lane >> 4)]);
+            aop[s] = *reinterpret_cast<const int4v *>(&As[s][(16 * rw + (lane & 15)) * OZ_LD + 16 * (lane >> 4)]);
         // digit plane t of the right-hand sides against every A plane s with
-        // s + t on a kept diagonal; the next plane's four operands are read
-        // while these products run (no deeper: a fully hoisted schedule would
-        // hold all 52 operands in registers)
+        // s + t on a kept diagonal; the next plane's operands are read while
+        // these products run
         auto bop_at = [&](int t, int ct) {
-            return *reinterpret_cast<const int4v *>(&Bs[t][(16 * ct + (lane & 15)) * OZ_LD + 16 * (lane >> 4)]);
+            return *reinterpret_cast<const int4v *>(
+                &Bs[t][(16 * (2 * ch + ct) + (lane & 15)) * OZ_LD + 16 * (lane >> 4)]);
         };
-        int4v bcur[4], bnext[4];
+        int4v bcur[2], bnext[2];
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct) bcur[ct] = bop_at(0, ct);
+        for (int ct = 0; ct < 2; ++ct) bcur[ct] = bop_at(0, ct);
 #pragma unroll
         for (int t = 0; t < OZ_S; ++t) {
             if (t + 1 < OZ_S)
 #pragma unroll
-                for (int ct = 0; ct < 4; ++ct) bnext[ct] = bop_at(t + 1, ct);
+                for (int ct = 0; ct < 2; ++ct) bnext[ct] = bop_at(t + 1, ct);
 #pragma unroll
-            for (int ct = 0; ct < 4; ++ct)
+            for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
                 for (int s = 0; s < OZ_S && s + t < OZ_NDIAG; ++s)
                     acc[s + t][ct] = __builtin_amdgcn_mfma_i32_16x16x64_i8(aop[s], bcur[ct], acc[s + t][ct], 0, 0, 0);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int ct = 0; ct < 4; ++ct) bcur[ct] = bnext[ct];
+            for (int ct = 0; ct < 2; ++ct) bcur[ct] = bnext[ct];
         }
     }
 
     // diagonals to double-binary64, smallest first: sum 128^-(d+2) Q_d, then
     // the scale 2^(e+f+2) (exact)
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct)
+    for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int row = r0 + 16 * w + 4 * (lane >> 4) + r;
-            const int c = c0 + 16 * ct + (lane & 15);
+            const int row = r0 + 16 * rw + 4 * (lane >> 4) + r;
+            const int c = c0 + 16 * (2 * ch + ct) + (lane & 15);
             if (row >= g.R || c >= g.k) continue;
             const int er = g.rowexp[row], ec = g.bexp[c];
             double hi = 0.0, lo = 0.0;
