@@ -346,19 +346,28 @@ __global__ __launch_bounds__(256) void gemm_f32_grouped_kernel(const GemmMxArgs 
 // lo hi^T + hi lo^T + hi hi^T, accumulated in binary32; the products of two
 // bfloat16 values are exact in binary32, so the only error besides the
 // accumulation is the dropped lo lo^T and the rounding of lo, together at
-// most about 2^-16 |w| |v| per product.  LDS rows hold KV + 8 bfloat16
-// (80 bytes: 16-byte aligned, conflict-free for the 16-lane reads).
+// most about 2^-16 |w| |v| per product.
+//
+// LDS rows hold the KV = 32 bfloat16 of a row (64 bytes, no padding), their
+// four 16-byte units XOR-swizzled by (row / 4) % 4: the 16 lanes of an MFMA
+// operand read (16 rows, one unit) and the 32 lanes of an 8-byte store
+// (4 rows, 8 slots) then hit distinct banks.  Global loads run two chunks
+// ahead of the products (two register sets, the loop unrolled by two).
+__device__ __forceinline__ int x3_off(int row, int unit)
+{
+    return row * KV + 8 * (unit ^ ((row >> 2) & 3));  // in bfloat16 elements
+}
+
 template <int BM, int BN>
-__global__ __launch_bounds__(256) void gemm_bf16x3_kc_kernel(GemmMxArgs g)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_bf16x3_kc_kernel(GemmMxArgs g)
 {
     typedef float f4 __attribute__((ext_vector_type(4)));
     typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
     typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-    constexpr int LDB = KV + 8;
-    __shared__ __attribute__((aligned(16))) __bf16 Ah[2][BM * LDB];
-    __shared__ __attribute__((aligned(16))) __bf16 Al[2][BM * LDB];
-    __shared__ __attribute__((aligned(16))) __bf16 Bh[2][BN * LDB];
-    __shared__ __attribute__((aligned(16))) __bf16 Bl[2][BN * LDB];
+    __shared__ __attribute__((aligned(16))) __bf16 Ah[2][BM * KV];
+    __shared__ __attribute__((aligned(16))) __bf16 Al[2][BM * KV];
+    __shared__ __attribute__((aligned(16))) __bf16 Bh[2][BN * KV];
+    __shared__ __attribute__((aligned(16))) __bf16 Bl[2][BN * KV];
     constexpr int TM = BM / 32, TN = BN / 32;
     constexpr int Q = KV / 4;
     constexpr int NA = BM * Q / 256, NB = BN * Q / 256;
@@ -394,9 +403,10 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kc_kernel(GemmMxArgs g)
     const int nch = kend > kbeg ? (kend - kbeg + KV - 1) / KV : 0;
     const float *Ap = static_cast<const float *>(g.A);
     const float *Bp = static_cast<const float *>(g.B);
+    // piece e of this thread: row (tid + 256 e) / Q, 8-byte slot tid % Q
     int64_t a_off[NA], b_off[NB];
     bool a_in[NA], b_in[NB];
-    const int kq = 4 * (tid % Q);
+    const int slot = tid % Q, kq = 4 * slot;
 #pragma unroll
     for (int e = 0; e < NA; ++e) {
         const int i = i0 + (tid + 256 * e) / Q;
@@ -409,8 +419,8 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kc_kernel(GemmMxArgs g)
         b_in[e] = j < g.N;
         b_off[e] = (int64_t)(b_in[e] ? j : g.N - 1) * g.b_j;
     }
-    f4 ra[NA], rb[NB];
-    auto load = [&](int c) {
+    f4 ra0[NA], rb0[NB], ra1[NA], rb1[NB];
+    auto load = [&](int c, f4 (&ra)[NA], f4 (&rb)[NB]) {
         const int k = kbeg + c * KV + kq;
         const bool kin = k < kend;
         const int kc = kin ? k : kend - 4;
@@ -425,11 +435,20 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kc_kernel(GemmMxArgs g)
             rb[e] = (kin && b_in[e]) ? v : f4{0.f, 0.f, 0.f, 0.f};
         }
     };
-    auto split = [](const f4 &v, bf4 &hi, bf4 &lo) {
+    auto store = [&](int buf, const f4 (&ra)[NA], const f4 (&rb)[NB]) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            hi[u] = (__bf16)v[u];
-            lo[u] = (__bf16)(v[u] - (float)hi[u]);
+        for (int e = 0; e < NA + NB; ++e) {
+            const f4 v = e < NA ? ra[e] : rb[e - NA];
+            bf4 hi, lo;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                hi[u] = (__bf16)v[u];
+                lo[u] = (__bf16)(v[u] - (float)hi[u]);
+            }
+            const int row = (tid + 256 * (e < NA ? e : e - NA)) / Q;
+            const int o = x3_off(row, slot >> 1) + 4 * (slot & 1);
+            *reinterpret_cast<bf4 *>(e < NA ? &Ah[buf][o] : &Bh[buf][o]) = hi;
+            *reinterpret_cast<bf4 *>(e < NA ? &Al[buf][o] : &Bl[buf][o]) = lo;
         }
     };
     f4 acc[TM][TN];
@@ -437,37 +456,17 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kc_kernel(GemmMxArgs g)
     for (int a = 0; a < TM; ++a)
 #pragma unroll
         for (int b = 0; b < TN; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
-    if (nch > 0) load(0);
-    for (int t = 0; t < nch; ++t) {
-        const int buf = t & 1;
-#pragma unroll
-        for (int e = 0; e < NA; ++e) {
-            bf4 hi, lo;
-            split(ra[e], hi, lo);
-            const int o = ((tid + 256 * e) / Q) * LDB + kq;
-            *reinterpret_cast<bf4 *>(&Ah[buf][o]) = hi;
-            *reinterpret_cast<bf4 *>(&Al[buf][o]) = lo;
-        }
-#pragma unroll
-        for (int e = 0; e < NB; ++e) {
-            bf4 hi, lo;
-            split(rb[e], hi, lo);
-            const int o = ((tid + 256 * e) / Q) * LDB + kq;
-            *reinterpret_cast<bf4 *>(&Bh[buf][o]) = hi;
-            *reinterpret_cast<bf4 *>(&Bl[buf][o]) = lo;
-        }
-        __syncthreads();
-        if (t + 1 < nch) load(t + 1);
+    auto products = [&](int buf) {
         bf8 ah[TM], al[TM], bh[TN], bl[TN];
 #pragma unroll
         for (int a = 0; a < TM; ++a) {
-            const int o = (wm * (BM / 2) + a * 16 + (lane & 15)) * LDB + 8 * (lane >> 4);
+            const int o = x3_off(wm * (BM / 2) + a * 16 + (lane & 15), lane >> 4);
             ah[a] = *reinterpret_cast<const bf8 *>(&Ah[buf][o]);
             al[a] = *reinterpret_cast<const bf8 *>(&Al[buf][o]);
         }
 #pragma unroll
         for (int b = 0; b < TN; ++b) {
-            const int o = (wn * (BN / 2) + b * 16 + (lane & 15)) * LDB + 8 * (lane >> 4);
+            const int o = x3_off(wn * (BN / 2) + b * 16 + (lane & 15), lane >> 4);
             bh[b] = *reinterpret_cast<const bf8 *>(&Bh[buf][o]);
             bl[b] = *reinterpret_cast<const bf8 *>(&Bl[buf][o]);
         }
@@ -479,6 +478,26 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kc_kernel(GemmMxArgs g)
                 acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
                 acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
             }
+    };
+    // chunk t comes from register set t % 2 and LDS buffer t % 2; the loads
+    // of chunk t + 2 go into that set once it is in LDS
+    if (nch > 0) load(0, ra0, rb0);
+    if (nch > 1) load(1, ra1, rb1);
+    int t = 0;
+    for (; t + 1 < nch; t += 2) {
+        store(0, ra0, rb0);
+        __syncthreads();
+        if (t + 2 < nch) load(t + 2, ra0, rb0);
+        products(0);
+        store(1, ra1, rb1);
+        __syncthreads();
+        if (t + 3 < nch) load(t + 3, ra1, rb1);
+        products(1);
+    }
+    if (t < nch) {
+        store(0, ra0, rb0);
+        __syncthreads();
+        products(0);
     }
     const int64_t coff = g.ksplit > 1 ? (int64_t)bz * g.c_split : 0;
     float *C = static_cast<float *>(g.C);
