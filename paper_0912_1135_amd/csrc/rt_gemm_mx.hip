@@ -419,26 +419,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
         b_in[e] = j < g.N;
         b_off[e] = (int64_t)(b_in[e] ? j : g.N - 1) * g.b_j;
     }
+    // raw loads (from clamped addresses); the range masks are applied when
+    // the chunk is stored, so that no instruction waits on a load before the
+    // products it runs behind
     f4 ra0[NA], rb0[NB], ra1[NA], rb1[NB];
     auto load = [&](int c, f4 (&ra)[NA], f4 (&rb)[NB]) {
         const int k = kbeg + c * KV + kq;
-        const bool kin = k < kend;
-        const int kc = kin ? k : kend - 4;
+        const int kc = k < kend ? k : kend - 4;
 #pragma unroll
-        for (int e = 0; e < NA; ++e) {
-            const f4 v = *reinterpret_cast<const f4 *>(Ap + a_off[e] + kc);
-            ra[e] = (kin && a_in[e]) ? v : f4{0.f, 0.f, 0.f, 0.f};
-        }
+        for (int e = 0; e < NA; ++e) ra[e] = *reinterpret_cast<const f4 *>(Ap + a_off[e] + kc);
 #pragma unroll
-        for (int e = 0; e < NB; ++e) {
-            const f4 v = *reinterpret_cast<const f4 *>(Bp + b_off[e] + kc);
-            rb[e] = (kin && b_in[e]) ? v : f4{0.f, 0.f, 0.f, 0.f};
-        }
+        for (int e = 0; e < NB; ++e) rb[e] = *reinterpret_cast<const f4 *>(Bp + b_off[e] + kc);
     };
-    auto store = [&](int buf, const f4 (&ra)[NA], const f4 (&rb)[NB]) {
+    auto store = [&](int buf, int c, const f4 (&ra)[NA], const f4 (&rb)[NB]) {
+        const bool kin = kbeg + c * KV + kq < kend;
 #pragma unroll
         for (int e = 0; e < NA + NB; ++e) {
-            const f4 v = e < NA ? ra[e] : rb[e - NA];
+            const bool ok = kin && (e < NA ? a_in[e] : b_in[e - NA]);
+            const f4 v = ok ? (e < NA ? ra[e] : rb[e - NA]) : f4{0.f, 0.f, 0.f, 0.f};
             bf4 hi, lo;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -481,21 +479,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
     };
     // chunk t comes from register set t % 2 and LDS buffer t % 2; the loads
     // of chunk t + 2 go into that set once it is in LDS
-    if (nch > 0) load(0, ra0, rb0);
-    if (nch > 1) load(1, ra1, rb1);
+    if (nch > 0) {
+        load(0, ra0, rb0);
+        load(1, ra1, rb1);
+    }
+    // (loads past the last chunk read clamped, valid addresses and go
+    // unused; issuing them unconditionally keeps the wait counts exact)
     int t = 0;
     for (; t + 1 < nch; t += 2) {
-        store(0, ra0, rb0);
+        store(0, t, ra0, rb0);
         __syncthreads();
-        if (t + 2 < nch) load(t + 2, ra0, rb0);
+        load(t + 2, ra0, rb0);
+        __builtin_amdgcn_sched_barrier(0);
         products(0);
-        store(1, ra1, rb1);
+        store(1, t + 1, ra1, rb1);
         __syncthreads();
-        if (t + 3 < nch) load(t + 3, ra1, rb1);
+        load(t + 3, ra1, rb1);
+        __builtin_amdgcn_sched_barrier(0);
         products(1);
     }
     if (t < nch) {
-        store(0, ra0, rb0);
+        store(0, t, ra0, rb0);
         __syncthreads();
         products(0);
     }
