@@ -348,6 +348,10 @@ __global__ __launch_bounds__(256) void gemm_f32_grouped_kernel(const GemmMxArgs 
 // accumulation is the dropped lo lo^T and the rounding of lo, together at
 // most about 2^-16 |w| |v| per product.
 //
+// X3 = false is the plain bfloat16 product of the same operands, each scaled
+// first by its optional power-of-two row (A) / column (B) scale: only hi,
+// one MFMA per 32 k.
+//
 // LDS rows hold the KV = 32 bfloat16 of a row (64 bytes, no padding), their
 // four 16-byte units XOR-swizzled by (row / 4) % 4: the 16 lanes of an MFMA
 // operand read (16 rows, one unit) and the 32 lanes of an 8-byte store
@@ -358,16 +362,17 @@ __device__ __forceinline__ int x3_off(int row, int unit)
     return row * KV + 8 * (unit ^ ((row >> 2) & 3));  // in bfloat16 elements
 }
 
-template <int BM, int BN>
+template <int BM, int BN, bool X3>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_bf16x3_kc_kernel(GemmMxArgs g)
 {
     typedef float f4 __attribute__((ext_vector_type(4)));
     typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
     typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+    constexpr int LO = X3 ? 1 : 0;  // the lo halves take no LDS in the plain form
     __shared__ __attribute__((aligned(16))) __bf16 Ah[2][BM * KV];
-    __shared__ __attribute__((aligned(16))) __bf16 Al[2][BM * KV];
+    __shared__ __attribute__((aligned(16))) __bf16 Al[2][LO ? BM * KV : 8];
     __shared__ __attribute__((aligned(16))) __bf16 Bh[2][BN * KV];
-    __shared__ __attribute__((aligned(16))) __bf16 Bl[2][BN * KV];
+    __shared__ __attribute__((aligned(16))) __bf16 Bl[2][LO ? BN * KV : 8];
     constexpr int TM = BM / 32, TN = BN / 32;
     constexpr int Q = KV / 4;
     constexpr int NA = BM * Q / 256, NB = BN * Q / 256;
@@ -406,18 +411,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
     // piece e of this thread: row (tid + 256 e) / Q, 8-byte slot tid % Q
     int64_t a_off[NA], b_off[NB];
     bool a_in[NA], b_in[NB];
+    float a_sc[NA], b_sc[NB];
     const int slot = tid % Q, kq = 4 * slot;
 #pragma unroll
     for (int e = 0; e < NA; ++e) {
         const int i = i0 + (tid + 256 * e) / Q;
         a_in[e] = i < g.M;
-        a_off[e] = (int64_t)(a_in[e] ? i : g.M - 1) * g.a_i;
+        const int ic = a_in[e] ? i : g.M - 1;
+        a_off[e] = (int64_t)ic * g.a_i;
+        a_sc[e] = (!X3 && g.a_scale) ? g.a_scale[ic] : 1.f;
     }
 #pragma unroll
     for (int e = 0; e < NB; ++e) {
         const int j = j0 + (tid + 256 * e) / Q;
         b_in[e] = j < g.N;
-        b_off[e] = (int64_t)(b_in[e] ? j : g.N - 1) * g.b_j;
+        const int jc = b_in[e] ? j : g.N - 1;
+        b_off[e] = (int64_t)jc * g.b_j;
+        b_sc[e] = (!X3 && g.b_scale) ? g.b_scale[jc] : 1.f;
     }
     // raw loads (from clamped addresses); the range masks are applied when
     // the chunk is stored, so that no instruction waits on a load before the
@@ -437,16 +447,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
         for (int e = 0; e < NA + NB; ++e) {
             const bool ok = kin && (e < NA ? a_in[e] : b_in[e - NA]);
             const f4 v = ok ? (e < NA ? ra[e] : rb[e - NA]) : f4{0.f, 0.f, 0.f, 0.f};
+            const float sc = X3 ? 1.f : (e < NA ? a_sc[e] : b_sc[e - NA]);
             bf4 hi, lo;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                hi[u] = (__bf16)v[u];
-                lo[u] = (__bf16)(v[u] - (float)hi[u]);
+                hi[u] = (__bf16)(X3 ? v[u] : v[u] * sc);  // the scales are powers of two: exact
+                if constexpr (X3) lo[u] = (__bf16)(v[u] - (float)hi[u]);
             }
             const int row = (tid + 256 * (e < NA ? e : e - NA)) / Q;
             const int o = x3_off(row, slot >> 1) + 4 * (slot & 1);
             *reinterpret_cast<bf4 *>(e < NA ? &Ah[buf][o] : &Bh[buf][o]) = hi;
-            *reinterpret_cast<bf4 *>(e < NA ? &Al[buf][o] : &Bl[buf][o]) = lo;
+            if constexpr (X3) *reinterpret_cast<bf4 *>(e < NA ? &Al[buf][o] : &Bl[buf][o]) = lo;
         }
     };
     f4 acc[TM][TN];
@@ -456,24 +467,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
         for (int b = 0; b < TN; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
     auto products = [&](int buf) {
         bf8 ah[TM], al[TM], bh[TN], bl[TN];
+        (void)al;
+        (void)bl;
 #pragma unroll
         for (int a = 0; a < TM; ++a) {
             const int o = x3_off(wm * (BM / 2) + a * 16 + (lane & 15), lane >> 4);
             ah[a] = *reinterpret_cast<const bf8 *>(&Ah[buf][o]);
-            al[a] = *reinterpret_cast<const bf8 *>(&Al[buf][o]);
+            if constexpr (X3) al[a] = *reinterpret_cast<const bf8 *>(&Al[buf][o]);
         }
 #pragma unroll
         for (int b = 0; b < TN; ++b) {
             const int o = x3_off(wn * (BN / 2) + b * 16 + (lane & 15), lane >> 4);
             bh[b] = *reinterpret_cast<const bf8 *>(&Bh[buf][o]);
-            bl[b] = *reinterpret_cast<const bf8 *>(&Bl[buf][o]);
+            if constexpr (X3) bl[b] = *reinterpret_cast<const bf8 *>(&Bl[buf][o]);
         }
 #pragma unroll
         for (int a = 0; a < TM; ++a)
 #pragma unroll
             for (int b = 0; b < TN; ++b) {
-                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
-                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+                if constexpr (X3) {
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+                }
                 acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
             }
     };
@@ -671,13 +686,15 @@ hipError_t launch32_st(const GemmMxArgs &g, dim3 grid, hipStream_t s)
     return hipGetLastError();
 }
 
-// Operands that gemm_f32_kc_kernel takes: binary32, K-contiguous, unscaled,
+// Operands that gemm_f32_kc_kernel and gemm_bf16x3_kc_kernel take: binary32,
+// K-contiguous, unscaled (scaled allowed for the plain bfloat16 form),
 // ungathered, full (not triangular), 16-byte aligned rows and K % 4 == 0.
-bool kc_fast(const GemmMxArgs &g)
+bool kc_fast(const GemmMxArgs &g, bool scales_ok = false)
 {
     return !g.a_dbl && !g.b_dbl && !g.c_dbl && g.a_k == 1 && g.b_k == 1 && !g.a_gather && !g.b_gather &&
-           !g.a_scale && !g.b_scale && !g.a_lower && g.K % 4 == 0 && g.a_i % 4 == 0 && g.b_j % 4 == 0 &&
-           (reinterpret_cast<uintptr_t>(g.A) & 15) == 0 && (reinterpret_cast<uintptr_t>(g.B) & 15) == 0;
+           (scales_ok || (!g.a_scale && !g.b_scale)) && !g.a_lower && g.K % 4 == 0 && g.a_i % 4 == 0 &&
+           g.b_j % 4 == 0 && (reinterpret_cast<uintptr_t>(g.A) & 15) == 0 &&
+           (reinterpret_cast<uintptr_t>(g.B) & 15) == 0;
 }
 
 template <int BM, int BN>
@@ -754,7 +771,7 @@ hipError_t gemm_mx(const GemmMxArgs &g, int mode, hipStream_t stream)
         const int gm = (g.M + 127) / 128, gn = (g.N + 127) / 128;
         dim3 grid = g.c_lower ? dim3(gm * (gm + 1) / 2, 1, g.ksplit > 1 ? g.ksplit : 1)
                               : dim3(gn, gm, g.ksplit > 1 ? g.ksplit : 1);
-        hipLaunchKernelGGL((gemm_bf16x3_kc_kernel<128, 128>), grid, dim3(256), 0, stream, g);
+        hipLaunchKernelGGL((gemm_bf16x3_kc_kernel<128, 128, true>), grid, dim3(256), 0, stream, g);
         return hipGetLastError();
     }
     if (mode == MX_BF16) {
@@ -763,6 +780,11 @@ hipError_t gemm_mx(const GemmMxArgs &g, int mode, hipStream_t stream)
         dim3 grid = g.c_lower ? dim3(gm * (gm + 1) / 2, 1, g.ksplit > 1 ? g.ksplit : 1)
                               : dim3(gn, gm, g.ksplit > 1 ? g.ksplit : 1);
         if (g.a_dbl != g.b_dbl) return hipErrorInvalidValue;
+        if (kc_fast(g, true)) {
+            // binary32 operands with 16-byte rows: the LDS-swizzled kernel, one product
+            hipLaunchKernelGGL((gemm_bf16x3_kc_kernel<128, 128, false>), grid, dim3(256), 0, stream, g);
+            return hipGetLastError();
+        }
         if (g.a_dbl) hipLaunchKernelGGL((gemm_bf16_kernel<128, 128, true>), grid, dim3(256), 0, stream, g);
         else hipLaunchKernelGGL((gemm_bf16_kernel<128, 128, false>), grid, dim3(256), 0, stream, g);
         return hipGetLastError();
