@@ -241,7 +241,11 @@ rtproj_status alloc_state(rtproj_plan p)
     RT_HIP(dalloc(&p->d_S, (size_t)m * l));
     RT_HIP(dalloc(&p->d_R, (size_t)m * m));
     RT_HIP(dalloc(&p->d_Y, (size_t)m * m));
-    RT_HIP(dalloc(&p->d_W, (size_t)m * n));
+    // W's rows are padded by 32 elements (128 or 256 bytes): with a
+    // power-of-two n the unpadded rows would all fall on the same L2 sets,
+    // and the Gram's row panels could not stay cached
+    p->ldw = n + 32;
+    RT_HIP(dalloc(&p->d_W, (size_t)m * p->ldw));
     const int gt = (int)((m + 127) / 128);
     const int tiles = gt * (gt + 1) / 2;
     p->syrk_splits = (int)std::max<int64_t>(1, std::min<int64_t>({64, (4 * p->cu_count + tiles - 1) / tiles, n / 256}));
@@ -1649,7 +1653,7 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
             g.M = (int)m; g.N = (int)n; g.K = (int)m;
             g.A = p->d_Y; g.a_dbl = 1; g.a_i = m; g.a_k = 1; g.a_lower = 1;
             g.B = A; g.b_dbl = 1; g.b_k = lda; g.b_j = 1; g.b_gather = p->d_piv;
-            g.C = p->d_W; g.c_dbl = 0; g.c_i = n; g.c_j = 1;
+            g.C = p->d_W; g.c_dbl = 0; g.c_i = p->ldw; g.c_j = 1;
             g.alpha = 1.f; g.ksplit = 1; g.tile = tile;
             return rt::gemm_mx(g, rt::MX_F32, s);
         }
@@ -1659,7 +1663,7 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
         g.M = (int)m; g.N = (int)n; g.K = (int)m;
         g.A = p->d_Y; g.a_i = m; g.a_k = 1; g.a_lower = 1;
         g.B = A; g.b_k = lda; g.b_j = 1; g.b_gather = p->d_piv;
-        g.C = p->d_W; g.c_i = n; g.c_j = 1; g.c_f32 = lp ? 1 : 0;
+        g.C = p->d_W; g.c_i = p->ldw; g.c_j = 1; g.c_f32 = lp ? 1 : 0;
         g.alpha = 1.0; g.ksplit = 1; g.tile = tile; g.tile_n = tile_n; g.order = order;
         return rt::gemm_f64(g, s);
     };
@@ -1672,19 +1676,19 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
         if (!lp) {
             rt::GemmArgs g{};
             g.M = (int)m; g.N = (int)m; g.K = (int)n;
-            g.A = p->d_W; g.a_i = n; g.a_k = 1;
-            g.B = p->d_W; g.b_k = 1; g.b_j = n;
+            g.A = p->d_W; g.a_i = p->ldw; g.a_k = 1;
+            g.B = p->d_W; g.b_k = 1; g.b_j = p->ldw;
             g.C = p->d_part; g.c_i = m; g.c_j = 1; g.c_split = m * m;
             g.alpha = 1.0; g.c_lower = 1; g.ksplit = splits; g.tile = tile;
             if ((e = rt::gemm_f64(g, s)) != hipSuccess) return e;
             return rt::reduce_splits_f64(p->d_part, m * m, splits > 1 ? splits : 1, (int)m, (int)m, m, p->d_G, m, 1, s);
         }
         const int wd = 0;  // W is binary32 in the mixed forms (either product)
-        if (bf && (e = rt::row_pow2_scale(p->d_W, wd, n, (int)m, (int)n, p->d_rowscale, s)) != hipSuccess) return e;
+        if (bf && (e = rt::row_pow2_scale(p->d_W, wd, p->ldw, (int)m, (int)n, p->d_rowscale, s)) != hipSuccess) return e;
         rt::GemmMxArgs g{};
         g.M = (int)m; g.N = (int)m; g.K = (int)n;
-        g.A = p->d_W; g.a_dbl = wd; g.a_i = n; g.a_k = 1; g.a_scale = bf ? p->d_rowscale : nullptr;
-        g.B = p->d_W; g.b_dbl = wd; g.b_k = 1; g.b_j = n; g.b_scale = bf ? p->d_rowscale : nullptr;
+        g.A = p->d_W; g.a_dbl = wd; g.a_i = p->ldw; g.a_k = 1; g.a_scale = bf ? p->d_rowscale : nullptr;
+        g.B = p->d_W; g.b_dbl = wd; g.b_k = 1; g.b_j = p->ldw; g.b_scale = bf ? p->d_rowscale : nullptr;
         g.C = p->d_part; g.c_dbl = 0; g.c_i = m; g.c_j = 1; g.c_split = m * m;
         g.alpha = 1.f; g.c_lower = 1; g.ksplit = splits; g.tile = tile;
         x3 = p->precision == RTPROJ_PREC_MIXED_BF16X3 && rt::gemm_mx_bf16x3_ok(g);

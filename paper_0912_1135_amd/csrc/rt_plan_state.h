@@ -221,6 +221,7 @@ struct rtproj_plan_s {
     double *d_zbuf = nullptr;
     int64_t rows_chunk = 0;
     double *d_S = nullptr, *d_R = nullptr, *d_Y = nullptr, *d_W = nullptr, *d_part = nullptr;
+    int64_t ldw = 0;           // row stride of d_W (elements of its storage type)
     double *d_G = nullptr, *d_L = nullptr, *d_Tp = nullptr, *d_DinvR = nullptr, *d_DinvL = nullptr;
     int32_t *d_piv = nullptr;
     unsigned *d_sync = nullptr;

@@ -54,3 +54,27 @@ def test_autotuned_plan_matches_oracle(rt, prec, tmp_path):
     with pytest.raises(rt.RtprojError):
         rt.autotune_load(bad)
     plan.close()
+
+
+@pytest.mark.parametrize("cfg", ["64 1 0", "64 2 0", "64 2 128", "128 1 64"])
+def test_forced_product_configuration_matches_oracle(rt, cfg, tmp_path):
+    """P^{-1}A in a configuration set through a loaded table (tile, order,
+    tile_n): the plain and XCD-grouped orders with square and rectangular
+    tiles at 1024 rows."""
+    m, n, l, k, seed = 1024, 8192, 4096, 3, 151
+    A = synth.make_problem(m, n, 1e6, seed)
+    B = synth.make_rhs(n, k, seed)
+    path = str(tmp_path / "forced.txt")
+    open(path, "w").write(f"w64:{m}x{n}x0 {cfg}\n")
+    rt.autotune_load(path)
+    plan = rt.Plan(m, n, l, seed)
+    plan.set_autotune(True)
+    plan.precondition(torch.from_numpy(A).to("cuda"))
+    Z, Y, X = [t.cpu().numpy() for t in plan.project_all(torch.from_numpy(B).to("cuda"))]
+    plan.status()
+    Zr, Yr, Xr, _ = oracle.project(A, B.T)
+    nb = np.linalg.norm(B, axis=1)
+    assert np.max(np.linalg.norm(Z - Zr.T, axis=1) / nb) <= TOL
+    assert np.max(np.linalg.norm(Y - Yr.T, axis=1) / nb) <= TOL
+    assert np.max(np.linalg.norm(X - Xr.T, axis=1) / np.linalg.norm(Xr.T, axis=1)) <= TOL
+    plan.close()
