@@ -362,8 +362,13 @@ __device__ __forceinline__ int x3_off(int row, int unit)
     return row * KV + 8 * (unit ^ ((row >> 2) & 3));  // in bfloat16 elements
 }
 
+// Tiles of BM x BN with 64 x 64 per wave: 128 x 128 on four waves, or
+// 256 x 128 on eight (a quarter less operand traffic per output); a lower-
+// triangle grid of 256 x 128 tiles numbers tile (I, J), J <= 2I + 1, as
+// I (I + 1) + J.
 template <int BM, int BN, bool X3>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_bf16x3_kc_kernel(GemmMxArgs g)
+__global__ __launch_bounds__(BM * BN / 64) __attribute__((amdgpu_waves_per_eu(2))) void gemm_bf16x3_kc_kernel(
+    GemmMxArgs g)
 {
     typedef float f4 __attribute__((ext_vector_type(4)));
     typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
@@ -373,11 +378,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
     __shared__ __attribute__((aligned(16))) __bf16 Al[2][LO ? BM * KV : 8];
     __shared__ __attribute__((aligned(16))) __bf16 Bh[2][BN * KV];
     __shared__ __attribute__((aligned(16))) __bf16 Bl[2][LO ? BN * KV : 8];
-    constexpr int TM = BM / 32, TN = BN / 32;
+    static_assert(BN == 128 && (BM == 128 || BM == 256), "128 x 128 or 256 x 128 tiles");
+    constexpr int NT = BM * BN / 64;  // threads: one wave per 64 x 64
+    constexpr int WM = BM / 64;       // waves along M
+    constexpr int TM = 4, TN = 4;
     constexpr int Q = KV / 4;
-    constexpr int NA = BM * Q / 256, NB = BN * Q / 256;
+    constexpr int NA = BM * Q / NT, NB = BN * Q / NT;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave % WM, wn = wave / WM;
     int bx = blockIdx.x, bz = blockIdx.z;
     int ti, tj;
     if (g.c_lower) {
@@ -389,15 +397,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
             bz = (int)(N / gridDim.x);
         }
         const int t = bx;
-        ti = (int)((__builtin_sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-        while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
-        while (ti * (ti + 1) / 2 > t) --ti;
-        tj = t - ti * (ti + 1) / 2;
+        if constexpr (BM == BN) {
+            ti = (int)((__builtin_sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+            while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+            while (ti * (ti + 1) / 2 > t) --ti;
+            tj = t - ti * (ti + 1) / 2;
+        } else {
+            ti = (int)((__builtin_sqrt(4.0 * t + 1.0) - 1.0) * 0.5);
+            while ((ti + 1) * (ti + 2) <= t) ++ti;
+            while (ti * (ti + 1) > t) --ti;
+            tj = t - ti * (ti + 1);
+        }
     } else {
         ti = blockIdx.y;
         tj = bx;
     }
     const int i0 = ti * BM, j0 = tj * BN;
+    // (a 256 x 128 lower grid's last tiles can lie wholly right of column M;
+    // the reduction never reads them)
+    if (j0 >= g.N) return;
     int kbeg = 0, kend = g.K;
     if (g.ksplit > 1) {
         int ks = (g.K + g.ksplit - 1) / g.ksplit;
@@ -408,14 +426,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
     const int nch = kend > kbeg ? (kend - kbeg + KV - 1) / KV : 0;
     const float *Ap = static_cast<const float *>(g.A);
     const float *Bp = static_cast<const float *>(g.B);
-    // piece e of this thread: row (tid + 256 e) / Q, 8-byte slot tid % Q
+    // piece e of this thread: row (tid + NT e) / Q, 8-byte slot tid % Q
     int64_t a_off[NA], b_off[NB];
     bool a_in[NA], b_in[NB];
     float a_sc[NA], b_sc[NB];
     const int slot = tid % Q, kq = 4 * slot;
 #pragma unroll
     for (int e = 0; e < NA; ++e) {
-        const int i = i0 + (tid + 256 * e) / Q;
+        const int i = i0 + (tid + NT * e) / Q;
         a_in[e] = i < g.M;
         const int ic = a_in[e] ? i : g.M - 1;
         a_off[e] = (int64_t)ic * g.a_i;
@@ -423,7 +441,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
     }
 #pragma unroll
     for (int e = 0; e < NB; ++e) {
-        const int j = j0 + (tid + 256 * e) / Q;
+        const int j = j0 + (tid + NT * e) / Q;
         b_in[e] = j < g.N;
         const int jc = b_in[e] ? j : g.N - 1;
         b_off[e] = (int64_t)jc * g.b_j;
@@ -454,7 +472,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
                 hi[u] = (__bf16)(X3 ? v[u] : v[u] * sc);  // the scales are powers of two: exact
                 if constexpr (X3) lo[u] = (__bf16)(v[u] - (float)hi[u]);
             }
-            const int row = (tid + 256 * (e < NA ? e : e - NA)) / Q;
+            const int row = (tid + NT * (e < NA ? e : e - NA)) / Q;
             const int o = x3_off(row, slot >> 1) + 4 * (slot & 1);
             *reinterpret_cast<bf4 *>(e < NA ? &Ah[buf][o] : &Bh[buf][o]) = hi;
             if constexpr (X3) *reinterpret_cast<bf4 *>(e < NA ? &Al[buf][o] : &Bl[buf][o]) = lo;
@@ -471,13 +489,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
         (void)bl;
 #pragma unroll
         for (int a = 0; a < TM; ++a) {
-            const int o = x3_off(wm * (BM / 2) + a * 16 + (lane & 15), lane >> 4);
+            const int o = x3_off(wm * 64 + a * 16 + (lane & 15), lane >> 4);
             ah[a] = *reinterpret_cast<const bf8 *>(&Ah[buf][o]);
             if constexpr (X3) al[a] = *reinterpret_cast<const bf8 *>(&Al[buf][o]);
         }
 #pragma unroll
         for (int b = 0; b < TN; ++b) {
-            const int o = x3_off(wn * (BN / 2) + b * 16 + (lane & 15), lane >> 4);
+            const int o = x3_off(wn * 64 + b * 16 + (lane & 15), lane >> 4);
             bh[b] = *reinterpret_cast<const bf8 *>(&Bh[buf][o]);
             if constexpr (X3) bl[b] = *reinterpret_cast<const bf8 *>(&Bl[buf][o]);
         }
@@ -526,8 +544,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
         for (int b = 0; b < TN; ++b)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int i = i0 + wm * (BM / 2) + a * 16 + 4 * (lane >> 4) + r;
-                const int j = j0 + wn * (BN / 2) + b * 16 + (lane & 15);
+                const int i = i0 + wm * 64 + a * 16 + 4 * (lane >> 4) + r;
+                const int j = j0 + wn * 64 + b * 16 + (lane & 15);
                 if (i < g.M && j < g.N) C[coff + (int64_t)i * g.c_i + (int64_t)j * g.c_j] = g.alpha * acc[a][b][r];
             }
 }
@@ -759,6 +777,24 @@ __global__ void to_f32_kernel(const double *src, int64_t lds, float *dst, int64_
     dst[(int64_t)i * ldd + j] = (float)src[(int64_t)i * lds + j];
 }
 
+// The split (X3) or plain bfloat16 product of binary32 operands: 256 x 128
+// tiles for a lower-triangle grid unless tile == 128, else 128 x 128.
+template <bool X3>
+hipError_t launch_bf16_kc(const GemmMxArgs &g, hipStream_t stream)
+{
+    const unsigned ks = g.ksplit > 1 ? g.ksplit : 1;
+    if (g.c_lower && g.tile != 128) {
+        const int gi = (g.M + 255) / 256;
+        hipLaunchKernelGGL((gemm_bf16x3_kc_kernel<256, 128, X3>), dim3(gi * (gi + 1), 1, ks), dim3(512), 0, stream,
+                           g);
+        return hipGetLastError();
+    }
+    const int gm = (g.M + 127) / 128, gn = (g.N + 127) / 128;
+    const dim3 grid = g.c_lower ? dim3(gm * (gm + 1) / 2, 1, ks) : dim3(gn, gm, ks);
+    hipLaunchKernelGGL((gemm_bf16x3_kc_kernel<128, 128, X3>), grid, dim3(256), 0, stream, g);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 bool gemm_mx_bf16x3_ok(const GemmMxArgs &g) { return kc_fast(g); }
@@ -768,11 +804,7 @@ hipError_t gemm_mx(const GemmMxArgs &g, int mode, hipStream_t stream)
     if (g.M <= 0 || g.N <= 0) return hipSuccess;
     if (mode == MX_BF16X3) {
         if (!kc_fast(g)) return hipErrorInvalidValue;
-        const int gm = (g.M + 127) / 128, gn = (g.N + 127) / 128;
-        dim3 grid = g.c_lower ? dim3(gm * (gm + 1) / 2, 1, g.ksplit > 1 ? g.ksplit : 1)
-                              : dim3(gn, gm, g.ksplit > 1 ? g.ksplit : 1);
-        hipLaunchKernelGGL((gemm_bf16x3_kc_kernel<128, 128, true>), grid, dim3(256), 0, stream, g);
-        return hipGetLastError();
+        return launch_bf16_kc<true>(g, stream);
     }
     if (mode == MX_BF16) {
         if (g.a_k != 1 || g.b_k != 1 || g.a_gather || g.b_gather || g.a_lower) return hipErrorInvalidValue;
@@ -780,11 +812,8 @@ hipError_t gemm_mx(const GemmMxArgs &g, int mode, hipStream_t stream)
         dim3 grid = g.c_lower ? dim3(gm * (gm + 1) / 2, 1, g.ksplit > 1 ? g.ksplit : 1)
                               : dim3(gn, gm, g.ksplit > 1 ? g.ksplit : 1);
         if (g.a_dbl != g.b_dbl) return hipErrorInvalidValue;
-        if (kc_fast(g, true)) {
-            // binary32 operands with 16-byte rows: the LDS-swizzled kernel, one product
-            hipLaunchKernelGGL((gemm_bf16x3_kc_kernel<128, 128, false>), grid, dim3(256), 0, stream, g);
-            return hipGetLastError();
-        }
+        // binary32 operands with 16-byte rows: the LDS-swizzled kernel, one product
+        if (kc_fast(g, true)) return launch_bf16_kc<false>(g, stream);
         if (g.a_dbl) hipLaunchKernelGGL((gemm_bf16_kernel<128, 128, true>), grid, dim3(256), 0, stream, g);
         else hipLaunchKernelGGL((gemm_bf16_kernel<128, 128, false>), grid, dim3(256), 0, stream, g);
         return hipGetLastError();

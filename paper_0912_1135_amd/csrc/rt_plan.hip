@@ -1731,6 +1731,7 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
                 if (seen) continue;
                 cands.push_back({sp, 0});
                 if (!lp) cands.push_back({sp, 64});
+                if (bf || x3req) cands.push_back({sp, 128});  // 128 x 128 instead of 256 x 128 tiles
             }
             if (cands.empty()) cands.push_back({p->wgram_splits, 0});
             int best = 0;
