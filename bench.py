@@ -591,6 +591,21 @@ def run_batch(args, rt, synth, np, torch):
     ms32 = (time.perf_counter() - t1b) * 1e3 / args.steps
     status32 = bt.status()
     log(f"batch (graph, binary32 Gram): {ms32:.3f} ms per step")
+    # and with the split-bfloat16 grouped Gram (its outputs are the ones
+    # checked against the oracle below)
+    bt.set_precision(3)
+    for _ in range(args.warmup):
+        bt.precondition(At)
+        bt.project_all(Bt, Z, Y, X)
+    torch.cuda.synchronize()
+    t1c = time.perf_counter()
+    for _ in range(args.steps):
+        bt.precondition(At)
+        bt.project_all(Bt, Z, Y, X)
+    torch.cuda.synchronize()
+    msx3 = (time.perf_counter() - t1c) * 1e3 / args.steps
+    statusx3 = bt.status()
+    log(f"batch (graph, split-bfloat16 Gram): {msx3:.3f} ms per step")
     value = ksum / (ms_per_step / 1e3)
     # baseline on the same GPU: one binary64 plan per member, one after another
     plans = [rt.Plan(m, n, l, 0) for m, n, l in zip(shp.m, shp.n, shp.l)]
@@ -623,6 +638,9 @@ def run_batch(args, rt, synth, np, torch):
         "forms": {"batch_graph": {"value": value, "ms_per_step": ms_per_step},
                   "batch_graph_fp32_gram": {"value": ksum / (ms32 / 1e3), "ms_per_step": ms32,
                                             "member_status_nonzero": [i for i, s in enumerate(status32) if s != 0]},
+                  "batch_graph_bf16x3_gram": {"value": ksum / (msx3 / 1e3), "ms_per_step": msx3,
+                                              "member_status_nonzero": [i for i, s in enumerate(statusx3)
+                                                                        if s != 0]},
                   "loop_of_plans": {"value": loop_value, "ms_per_step": (t4 - t3) * 1e3}},
         "member_status_nonzero": [i for i, s in enumerate(status) if s != 0],
     }
@@ -644,7 +662,7 @@ def run_batch(args, rt, synth, np, torch):
             worst = [max(a, b) for a, b in zip(worst, e)]
         t6 = time.perf_counter()
         result["parity"] = {"members_checked": pick, "e_z": worst[0], "e_p": worst[1], "e_x": worst[2],
-                            "tol": TOL, "pass": max(worst) <= TOL, "form": "batch_graph_fp32_gram (last run)"}
+                            "tol": TOL, "pass": max(worst) <= TOL, "form": "batch_graph_bf16x3_gram (last run)"}
         if not args.no_cpu_baseline:
             cpu_sample = {"value": kdone / (t6 - t5), "unit": "projections/s", "cores": threads, "kind": "oracle",
                           "sample": f"members {pick} of the same batch (all their right-hand sides, "
@@ -703,8 +721,7 @@ def run_ipm(args, rt, synth, np, torch):
     ms_per_step = (t2 - t1) * 1e3 / args.steps
     value = steps * k / (ms_per_step / 1e3)
     log(f"batch of {steps} steps (graph): {ms_per_step:.1f} ms")
-    # the same sequence with the binary32 grouped Gram (its outputs are the
-    # ones checked against the oracle below)
+    # the same sequence with the binary32 grouped Gram
     bt.set_precision(1)
     for _ in range(args.warmup):
         bt.precondition([At] * steps, Dt)
@@ -719,6 +736,22 @@ def run_ipm(args, rt, synth, np, torch):
     status32 = bt.status()
     refine32 = bt.info()["refine_steps"]
     log(f"batch of {steps} steps (graph, binary32 Gram): {ms32:.1f} ms, {refine32} refinement steps")
+    # and with the split-bfloat16 grouped Gram (binary32 P^{-1}A); its
+    # outputs are the ones checked against the oracle below
+    bt.set_precision(3)
+    for _ in range(args.warmup):
+        bt.precondition([At] * steps, Dt)
+        bt.project_all(Bt, Z, Y, X)
+    torch.cuda.synchronize()
+    t1c = time.perf_counter()
+    for _ in range(args.steps):
+        bt.precondition([At] * steps, Dt)
+        bt.project_all(Bt, Z, Y, X)
+    torch.cuda.synchronize()
+    msx3 = (time.perf_counter() - t1c) * 1e3 / args.steps
+    statusx3 = bt.status()
+    refinex3 = bt.info()["refine_steps"]
+    log(f"batch of {steps} steps (graph, split-bfloat16 Gram): {msx3:.1f} ms, {refinex3} refinement steps")
     # the sequential loop: one plan, A D_t formed on the device, step by step
     plan = rt.Plan(m, n, l, seed)
     Ad = torch.empty_like(At)
@@ -753,6 +786,10 @@ def run_ipm(args, rt, synth, np, torch):
                   "batch_graph_fp32_gram": {"value": steps * k / (ms32 / 1e3), "ms_per_step": ms32,
                                             "refine_steps": refine32,
                                             "member_status_nonzero": [i for i, s_ in enumerate(status32) if s_ != 0]},
+                  "batch_graph_bf16x3_gram": {"value": steps * k / (msx3 / 1e3), "ms_per_step": msx3,
+                                              "refine_steps": refinex3,
+                                              "member_status_nonzero": [i for i, s_ in enumerate(statusx3)
+                                                                        if s_ != 0]},
                   "loop_of_steps": {"value": loop_value, "ms_per_step": (t4 - t3) * 1e3}},
         "member_status_nonzero": [i for i, s_ in enumerate(status) if s_ != 0],
     }
@@ -774,7 +811,7 @@ def run_ipm(args, rt, synth, np, torch):
         t6 = time.perf_counter()
         result["parity"] = {"steps_checked": pick, "columns_per_step": 2, "e_z": worst[0], "e_p": worst[1],
                             "e_x": worst[2], "tol": TOL, "pass": max(worst) <= TOL,
-                            "form": "batch_graph_fp32_gram (last run)"}
+                            "form": "batch_graph_bf16x3_gram (last run)"}
         if not args.no_cpu_baseline:
             cpu_sample = {"value": 2 * len(pick) / (t6 - t5), "unit": "projections/s", "cores": threads,
                           "kind": "oracle", "sample": f"2 right-hand sides of steps {pick} ({t6 - t5:.1f} s)"}

@@ -487,11 +487,15 @@ rtproj_status rtproj_batch_set_stream(rtproj_batch batch, void *hip_stream);
  * estimate (plain binary64 residuals above their floor, compensated after),
  * which reads the estimates once per projection call (a short host wait). */
 rtproj_status rtproj_batch_set_refinement(rtproj_batch batch, int steps);
-/* Precision of every member's preconditioner: RTPROJ_PREC_FP64 (default)
- * or RTPROJ_PREC_MIXED_FP32, whose Gram of P^{-1}A runs on binary32 MFMA
- * (grouped over the members) with binary64 operands and reduction; the
- * sketch, P^{-1}A, the factorizations and the refinement residuals stay
- * binary64, and the refinement schedule accounts for the binary32 Gram
+/* Precision of every member's preconditioner: RTPROJ_PREC_FP64 (default);
+ * RTPROJ_PREC_MIXED_FP32, whose Gram of P^{-1}A runs on binary32 MFMA
+ * (grouped over the members) with binary64 operands and reduction; or
+ * RTPROJ_PREC_MIXED_BF16X3, whose P^{-1}A is stored in binary32 and whose
+ * Gram is the split-bfloat16 one (hi + lo halves, three bfloat16 products,
+ * grouped over the members) when every member has n % 4 == 0, else the
+ * binary32 one (member info reports gram_bits 17 or 32).  The sketch, the
+ * products themselves, the factorizations and the refinement residuals stay
+ * binary64, and the refinement schedule accounts for the Gram's rounding
  * (Remark 4.3).  RTPROJ_ERR_UNSUPPORTED for RTPROJ_PREC_MIXED_BF16.  Takes
  * effect at the next rtproj_batch_precondition. */
 rtproj_status rtproj_batch_set_precision(rtproj_batch batch, int precision);

@@ -474,7 +474,8 @@ class Batch:
         _check(lib().rtproj_batch_set_graph(self.handle, 1 if enable else 0))
 
     def set_precision(self, precision: int):
-        """PREC_FP64 (default) or PREC_MIXED_FP32 (binary32 Gram on MFMA)."""
+        """PREC_FP64 (default), PREC_MIXED_FP32 (binary32 Gram on MFMA) or
+        PREC_MIXED_BF16X3 (split-bfloat16 Gram of binary32 P^{-1}A)."""
         _check(lib().rtproj_batch_set_precision(self.handle, precision))
 
     def precondition(self, As, col_scales=None):

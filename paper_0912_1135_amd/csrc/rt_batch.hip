@@ -28,7 +28,7 @@ namespace {
 enum OpKind {
     OP_GEMM, OP_REDUCE, OP_SKETCH, OP_COPY, OP_SET0, OP_SET1, OP_SHIFT, OP_CHOL, OP_TRIINV, OP_QRCPWG, OP_RDIAG,
     OP_FORMTP, OP_ZERO, OP_AB, OP_ABRED, OP_ATX, OP_DDUPD, OP_IOTA, OP_GEMM32, OP_RED32, OP_FINISH,
-    OP_QRCPGRP
+    OP_QRCPGRP, OP_GEMMX3
 };
 
 struct Op {
@@ -78,6 +78,7 @@ struct rtproj_batch_s {
     int refine_steps = -1;  // -1: schedule from the members' rank estimates
     int precision = RTPROJ_PREC_FP64;  // the preconditioner's Gram: binary64 or binary32 (MIXED_FP32)
     int prec_used = RTPROJ_PREC_FP64;  // of the last precondition
+    bool x3 = false;                   // the last precondition's Grams were split bfloat16
     int plain_steps = 0, comp_steps = 2;  // schedule of the last projection
     bool comp_final = true;               // its final pass after compensated steps
     int last_steps = 0, last_plain = 0;   // steps of the last projection (norms recorded)
@@ -173,6 +174,38 @@ void rec_gram32(Program &P, rtproj_batch b, const std::vector<const double *> &X
         mmax = std::max<int>(mmax, (int)m);
     }
     Op o{OP_GEMM32, P.add(g), (int)b->count};
+    o.i0 = mmax;
+    o.i1 = ksmax;
+    P.push(o);
+    Op q{OP_RED32, P.add(r), (int)b->count};
+    q.i0 = mmax;
+    P.push(q);
+}
+
+// C as rec_gram32, from binary32 X (row stride ldx floats, 16-byte rows):
+// the split-bfloat16 Gram on MFMA (hi + lo halves, three products), lower
+// 256 x 128 tiles split over K, reduced in binary64 into both triangles.
+void rec_gram_x3(Program &P, rtproj_batch b, const std::vector<const float *> &X, const std::vector<int64_t> &ldx,
+                 const std::vector<int64_t> &K, const std::vector<double *> &C)
+{
+    std::vector<rt::GemmMxArgs> g(b->count);
+    std::vector<rt::ReduceF32GroupArgs> r(b->count);
+    int ksmax = 1, mmax = 0;
+    for (int64_t i = 0; i < b->count; ++i) {
+        rtproj_plan p = b->sub[i];
+        const int64_t m = p->m;
+        rt::GemmMxArgs &a = g[i];
+        a.M = (int)m; a.N = (int)m; a.K = (int)K[i];
+        a.A = X[i]; a.a_dbl = 0; a.a_i = ldx[i]; a.a_k = 1;
+        a.B = X[i]; a.b_dbl = 0; a.b_k = 1; a.b_j = ldx[i];
+        a.C = p->d_part; a.c_dbl = 0; a.c_i = m; a.c_j = 1; a.c_split = m * m;
+        a.alpha = 1.f; a.c_lower = 1;
+        a.ksplit = (int)std::max<int64_t>(1, std::min<int64_t>(p->syrk_splits, K[i] / 256));
+        r[i] = rt::ReduceF32GroupArgs{reinterpret_cast<const float *>(p->d_part), m * m, a.ksplit, (int)m, C[i]};
+        ksmax = std::max(ksmax, a.ksplit);
+        mmax = std::max<int>(mmax, (int)m);
+    }
+    Op o{OP_GEMMX3, P.add(g), (int)b->count};
     o.i0 = mmax;
     o.i1 = ksmax;
     P.push(o);
@@ -458,7 +491,8 @@ void build_precondition(Program &P, rtproj_batch b, const double *const *A, cons
             a.M = (int)p->m; a.N = (int)p->n; a.K = (int)p->m;
             a.A = p->d_Y; a.a_i = p->m; a.a_k = 1; a.a_lower = 1;
             a.B = A[i]; a.b_k = lda[i]; a.b_j = 1; a.b_gather = p->d_piv;
-            a.C = p->d_W; a.c_i = p->n; a.c_j = 1;
+            a.C = p->d_W; a.c_i = b->x3 ? p->ldw : p->n; a.c_j = 1;
+            a.c_f32 = b->x3 ? 1 : 0;  // binary32 W (padded rows) for the split-bfloat16 Gram
             a.c_cs = cs[i];  // R^{-T} Pi (A D) = (R^{-T} Pi A) D
             a.alpha = 1.0; a.ksplit = 1;
         }
@@ -470,8 +504,19 @@ void build_precondition(Program &P, rtproj_batch b, const double *const *A, cons
         std::vector<int64_t> nn(cnt);
         for (int64_t i = 0; i < cnt; ++i) { W[i] = b->sub[i]->d_W; nn[i] = b->sub[i]->n; }
         P.stage = 4;
-        if (b->prec_used == RTPROJ_PREC_MIXED_FP32) rec_gram32(P, b, W, nn, nn, G);
-        else rec_gram(P, b, W, nn, nn, G);
+        if (b->x3) {
+            std::vector<const float *> Wf(cnt);
+            std::vector<int64_t> lw(cnt);
+            for (int64_t i = 0; i < cnt; ++i) {
+                Wf[i] = reinterpret_cast<const float *>(b->sub[i]->d_W);
+                lw[i] = b->sub[i]->ldw;
+            }
+            rec_gram_x3(P, b, Wf, lw, nn, G);
+        } else if (b->prec_used != RTPROJ_PREC_FP64) {
+            rec_gram32(P, b, W, nn, nn, G);
+        } else {
+            rec_gram(P, b, W, nn, nn, G);
+        }
         P.stage = 5;
         rec_cholesky(P, b, G, Lm);
     }
@@ -802,6 +847,7 @@ hipError_t run_op(const Op &o, const unsigned char *arena, hipStream_t s)
     case OP_DDUPD: return rt::dd_update_grouped_f64((const rt::DdGroupArgs *)d, o.count, s);
     case OP_IOTA: return rt::iota_grouped_i32((const rt::MatGroupArgs *)d, o.count, o.i0, s);
     case OP_GEMM32: return rt::gemm_f32_grouped_lower((const rt::GemmMxArgs *)d, o.count, o.i0, o.i1, s);
+    case OP_GEMMX3: return rt::gemm_bf16x3_grouped_lower((const rt::GemmMxArgs *)d, o.count, o.i0, o.i1, s);
     case OP_RED32: return rt::reduce_f32_grouped((const rt::ReduceF32GroupArgs *)d, o.count, o.i0, s);
     case OP_FINISH: return rt::finish_cols_grouped_f64((const rt::FinishGroupArgs *)d, o.count, o.total, s);
     }
@@ -1024,10 +1070,9 @@ rtproj_status rtproj_batch_set_refinement(rtproj_batch b, int steps)
 rtproj_status rtproj_batch_set_precision(rtproj_batch b, int precision)
 {
     if (!b) return fail(RTPROJ_ERR_INVALID_ARG, "null batch");
-    if (precision != RTPROJ_PREC_FP64 && precision != RTPROJ_PREC_MIXED_FP32)
-        return fail(precision == RTPROJ_PREC_MIXED_BF16 || precision == RTPROJ_PREC_MIXED_BF16X3
-                        ? RTPROJ_ERR_UNSUPPORTED : RTPROJ_ERR_INVALID_ARG,
-                    "batches take RTPROJ_PREC_FP64 or RTPROJ_PREC_MIXED_FP32");
+    if (precision != RTPROJ_PREC_FP64 && precision != RTPROJ_PREC_MIXED_FP32 && precision != RTPROJ_PREC_MIXED_BF16X3)
+        return fail(precision == RTPROJ_PREC_MIXED_BF16 ? RTPROJ_ERR_UNSUPPORTED : RTPROJ_ERR_INVALID_ARG,
+                    "batches take RTPROJ_PREC_FP64, RTPROJ_PREC_MIXED_FP32 or RTPROJ_PREC_MIXED_BF16X3");
     b->precision = precision;
     return RTPROJ_OK;
 }
@@ -1074,6 +1119,10 @@ rtproj_status rtproj_batch_precondition_scaled(rtproj_batch b, const double *con
     if (col_scale)
         for (int64_t i = 0; i < b->count; ++i) b->cscale[i] = col_scale[i];
     b->prec_used = b->precision;
+    // the split-bfloat16 Gram reads 16-byte rows of binary32 W: every member
+    // needs n % 4 == 0, else the batch takes the binary32 Gram
+    b->x3 = b->prec_used == RTPROJ_PREC_MIXED_BF16X3;
+    for (int64_t i = 0; i < b->count && b->x3; ++i) b->x3 = b->sub[i]->n % 4 == 0;
     Program P;
     build_precondition(P, b, A, lda, b->cscale.data());
     rtproj_status st = run_program(b, b->pre, P);
@@ -1193,7 +1242,7 @@ rtproj_status rtproj_batch_status(rtproj_batch b, int *per_member)
         p->info.inverse = RTPROJ_INV_CHOLESKY;
         p->inv_used = RTPROJ_INV_CHOLESKY;
         p->info.precision = b->prec_used;
-        p->info.gram_bits = b->prec_used == RTPROJ_PREC_MIXED_FP32 ? 32 : 64;
+        p->info.gram_bits = b->x3 ? 17 : (b->prec_used != RTPROJ_PREC_FP64 ? 32 : 64);
         p->info.sketch_bits = p->info.w_bits = 64;
         if (per_member) per_member[i] = st;
         // precedence: rank deficiency, then a device error, then non-convergence

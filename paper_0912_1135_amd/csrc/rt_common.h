@@ -129,6 +129,10 @@ hipError_t gemm_mx(const GemmMxArgs &g, int mode, hipStream_t stream);
 // with 16-byte aligned rows and K % 4 == 0 (the Gram of a row-major binary32
 // matrix whose row length is a multiple of 4).
 bool gemm_mx_bf16x3_ok(const GemmMxArgs &g);
+// Grouped split-bfloat16 Gram (batches): the lower 256 x 128 tiles of each
+// member's binary32 partials C = A B (binary32 A, B as MX_BF16X3 takes them),
+// K split ksmax ways (members with fewer splits skip the extra ones).
+hipError_t gemm_bf16x3_grouped_lower(const GemmMxArgs *d_args, int count, int max_m, int ksmax, hipStream_t stream);
 // Grouped binary32 Gram of binary64 operands (batches): the lower 64 x 64
 // tiles of each member's C = A B (A, B K-contiguous), K split ksmax ways
 // (members with fewer splits skip the extra ones); then the binary64

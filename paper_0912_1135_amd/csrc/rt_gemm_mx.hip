@@ -367,8 +367,7 @@ __device__ __forceinline__ int x3_off(int row, int unit)
 // triangle grid of 256 x 128 tiles numbers tile (I, J), J <= 2I + 1, as
 // I (I + 1) + J.
 template <int BM, int BN, bool X3>
-__global__ __launch_bounds__(BM * BN / 64) __attribute__((amdgpu_waves_per_eu(2))) void gemm_bf16x3_kc_kernel(
-    GemmMxArgs g)
+__device__ __forceinline__ void bf16_kc_tile(const GemmMxArgs &g, int bx, int by, int bz)
 {
     typedef float f4 __attribute__((ext_vector_type(4)));
     typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
@@ -386,16 +385,8 @@ __global__ __launch_bounds__(BM * BN / 64) __attribute__((amdgpu_waves_per_eu(2)
     constexpr int NA = BM * Q / NT, NB = BN * Q / NT;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WM, wn = wave / WM;
-    int bx = blockIdx.x, bz = blockIdx.z;
     int ti, tj;
     if (g.c_lower) {
-        const int64_t total = (int64_t)gridDim.x * gridDim.z;
-        if ((total & 7) == 0) {
-            const int64_t L = bx + (int64_t)gridDim.x * bz;
-            const int64_t N = (L & 7) * (total >> 3) + (L >> 3);
-            bx = (int)(N % gridDim.x);
-            bz = (int)(N / gridDim.x);
-        }
         const int t = bx;
         if constexpr (BM == BN) {
             ti = (int)((__builtin_sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
@@ -409,13 +400,14 @@ __global__ __launch_bounds__(BM * BN / 64) __attribute__((amdgpu_waves_per_eu(2)
             tj = t - ti * (ti + 1);
         }
     } else {
-        ti = blockIdx.y;
+        ti = by;
         tj = bx;
     }
     const int i0 = ti * BM, j0 = tj * BN;
-    // (a 256 x 128 lower grid's last tiles can lie wholly right of column M;
-    // the reduction never reads them)
-    if (j0 >= g.N) return;
+    // (a 256 x 128 lower grid's last tiles can lie wholly right of column M,
+    // and a grouped grid covers its largest member: the reduction never
+    // reads such tiles)
+    if (i0 >= g.M || j0 >= g.N) return;
     int kbeg = 0, kend = g.K;
     if (g.ksplit > 1) {
         int ks = (g.K + g.ksplit - 1) / g.ksplit;
@@ -548,6 +540,35 @@ __global__ __launch_bounds__(BM * BN / 64) __attribute__((amdgpu_waves_per_eu(2)
                 const int j = j0 + wn * 64 + b * 16 + (lane & 15);
                 if (i < g.M && j < g.N) C[coff + (int64_t)i * g.c_i + (int64_t)j * g.c_j] = g.alpha * acc[a][b][r];
             }
+}
+
+template <int BM, int BN, bool X3>
+__global__ __launch_bounds__(BM * BN / 64) __attribute__((amdgpu_waves_per_eu(2))) void gemm_bf16x3_kc_kernel(
+    GemmMxArgs g)
+{
+    int bx = blockIdx.x, bz = blockIdx.z;
+    if (g.c_lower) {
+        const int64_t total = (int64_t)gridDim.x * gridDim.z;
+        if ((total & 7) == 0) {
+            const int64_t L = bx + (int64_t)gridDim.x * bz;
+            const int64_t N = (L & 7) * (total >> 3) + (L >> 3);
+            bx = (int)(N % gridDim.x);
+            bz = (int)(N / gridDim.x);
+        }
+    }
+    bf16_kc_tile<BM, BN, X3>(g, bx, blockIdx.y, bz);
+}
+
+// Grouped lower-triangle launch (batches): member blockIdx.z / ksmax, split
+// blockIdx.z % ksmax; members with fewer splits or smaller m skip the rest.
+template <int BM, int BN>
+__global__ __launch_bounds__(BM * BN / 64) __attribute__((amdgpu_waves_per_eu(2))) void gemm_bf16x3_grouped_kernel(
+    const GemmMxArgs *gs, int ksmax)
+{
+    const GemmMxArgs g = gs[blockIdx.z / ksmax];
+    const int bz = blockIdx.z % ksmax;
+    if (bz >= (g.ksplit > 1 ? g.ksplit : 1)) return;
+    bf16_kc_tile<BM, BN, true>(g, blockIdx.x, 0, bz);
 }
 
 // ---------------------------------------------------------------- bfloat16
@@ -798,6 +819,15 @@ hipError_t launch_bf16_kc(const GemmMxArgs &g, hipStream_t stream)
 }  // namespace
 
 bool gemm_mx_bf16x3_ok(const GemmMxArgs &g) { return kc_fast(g); }
+
+hipError_t gemm_bf16x3_grouped_lower(const GemmMxArgs *d_args, int count, int max_m, int ksmax, hipStream_t stream)
+{
+    if (count <= 0 || max_m <= 0) return hipSuccess;
+    const int gi = (max_m + 255) / 256;
+    hipLaunchKernelGGL((gemm_bf16x3_grouped_kernel<256, 128>), dim3(gi * (gi + 1), 1, count * ksmax), dim3(512), 0,
+                       stream, d_args, ksmax);
+    return hipGetLastError();
+}
 
 hipError_t gemm_mx(const GemmMxArgs &g, int mode, hipStream_t stream)
 {

@@ -181,6 +181,70 @@ def test_batch_binary32_gram_matches_oracle(rt, graph):
 
 
 @pytest.mark.parametrize("graph", [False, True])
+def test_batch_split_bf16_gram_matches_oracle(rt, graph):
+    """Batches with the grouped split-bfloat16 Gram of binary32 P^{-1}A
+    (lower 256 x 128 tiles, members of uneven m: ragged tiles, tiles right of
+    a member's column m, members with fewer K splits): every member within
+    1e-10 of the oracle after the refinement, twice when replayed from the
+    graph."""
+    ms = [40, 130, 257, 300, 96]
+    ns = [8 * m for m in ms]
+    ls = [4 * m for m in ms]
+    ks = [3, 1, 5, 2, 4]
+    As = [synth.make_problem(m, n, 1e6, 310 + i) for i, (m, n) in enumerate(zip(ms, ns))]
+    Bs = [synth.make_rhs(n, k, 410 + i) for i, (n, k) in enumerate(zip(ns, ks))]
+    bt = rt.Batch(ms, ns, ls, 78)
+    bt.set_precision(rt.PREC_MIXED_BF16X3)
+    bt.set_graph(graph)
+    At = [torch.from_numpy(A).to(dev()) for A in As]
+    Bt = [torch.from_numpy(B).to(dev()) for B in Bs]
+    for rep in range(2 if graph else 1):
+        bt.precondition(At)
+        Z, Y, X = bt.project_all(Bt)
+        assert all(s == 0 for s in bt.status())
+        assert all(bt.member_info(i)["gram_bits"] == 17 for i in range(len(ms)))
+        for i in range(len(As)):
+            e = check_member(As[i], Bs[i], Z[i].cpu().numpy(), Y[i].cpu().numpy(), X[i].cpu().numpy())
+            assert max(e) <= TOL, (rep, i, e)
+    bt.close()
+
+
+def test_batch_split_bf16_gram_column_scaled_and_fallback(rt):
+    """The interior-point shape with the split-bfloat16 Gram (P^{-1}A written
+    in binary32 with its column scaling), and a batch with a member whose n
+    is not a multiple of 4, which takes the binary32 Gram for all members."""
+    m, n, l, steps = 64, 2048, 256, 3
+    A = synth.make_problem(m, n, 1e4, 79)
+    D = synth.make_scalings(n, steps, 79)
+    Bs = [synth.make_rhs(n, 5, 950 + t) for t in range(steps)]
+    bt = rt.Batch([m] * steps, [n] * steps, [l] * steps, 14)
+    bt.set_precision(rt.PREC_MIXED_BF16X3)
+    At = torch.from_numpy(A).to(dev())
+    Dt = [torch.from_numpy(np.ascontiguousarray(D[t])).to(dev()) for t in range(steps)]
+    bt.precondition([At] * steps, Dt)
+    Z, Y, X = bt.project_all([torch.from_numpy(B).to(dev()) for B in Bs])
+    assert bt.status() == [0] * steps
+    assert bt.member_info(0)["gram_bits"] == 17
+    for t in range(steps):
+        e = check_member(A * D[t][None, :], Bs[t], Z[t].cpu().numpy(), Y[t].cpu().numpy(), X[t].cpu().numpy())
+        assert max(e) <= TOL, (t, e)
+    bt.close()
+    ms, ns = [48, 64], [1000, 1002]
+    As = [synth.make_problem(mm, nn, 1e5, 320 + i) for i, (mm, nn) in enumerate(zip(ms, ns))]
+    Bs = [synth.make_rhs(nn, 2, 420 + i) for i, nn in enumerate(ns)]
+    bt = rt.Batch(ms, ns, [4 * mm for mm in ms], 15)
+    bt.set_precision(rt.PREC_MIXED_BF16X3)
+    bt.precondition([torch.from_numpy(A).to(dev()) for A in As])
+    Z, Y, X = bt.project_all([torch.from_numpy(B).to(dev()) for B in Bs])
+    assert bt.status() == [0, 0]
+    assert bt.member_info(1)["gram_bits"] == 32
+    for i in range(2):
+        e = check_member(As[i], Bs[i], Z[i].cpu().numpy(), Y[i].cpu().numpy(), X[i].cpu().numpy())
+        assert max(e) <= TOL, (i, e)
+    bt.close()
+
+
+@pytest.mark.parametrize("graph", [False, True])
 def test_batch_grouped_pivoted_qr_matches_oracle(rt, graph):
     """Few large members: the pivoted QR of R0 runs as a group of blocks per
     member (each group with its own barrier; chosen over one workgroup per
