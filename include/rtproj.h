@@ -493,11 +493,16 @@ rtproj_status rtproj_batch_set_refinement(rtproj_batch batch, int steps);
  * RTPROJ_PREC_MIXED_BF16X3, whose P^{-1}A is stored in binary32 and whose
  * Gram is the split-bfloat16 one (hi + lo halves, three bfloat16 products,
  * grouped over the members) when every member has n % 4 == 0, else the
- * binary32 one (member info reports gram_bits 17 or 32).  The sketch, the
- * products themselves, the factorizations and the refinement residuals stay
- * binary64, and the refinement schedule accounts for the Gram's rounding
- * (Remark 4.3).  RTPROJ_ERR_UNSUPPORTED for RTPROJ_PREC_MIXED_BF16.  Takes
- * effect at the next rtproj_batch_precondition. */
+ * binary32 one (member info reports gram_bits 17 or 32).  Both reduced
+ * precisions sketch in binary32 arithmetic and then read every member's rank
+ * estimate once (a short host wait in rtproj_batch_precondition): when a
+ * member's sketch proves too coarse (2^-24 kappa_est > 1, a failed rank test,
+ * or a Gram condition estimate above 10) all members are sketched again in
+ * binary64 (member info: sketch_bits, sketch_escalated).  The products
+ * themselves, the factorizations and the refinement residuals stay binary64,
+ * and the refinement schedule accounts for the Gram's rounding (Remark 4.3).
+ * RTPROJ_ERR_UNSUPPORTED for RTPROJ_PREC_MIXED_BF16.  Takes effect at the
+ * next rtproj_batch_precondition. */
 rtproj_status rtproj_batch_set_precision(rtproj_batch batch, int precision);
 /* 1: capture each entry point's launches into a HIP graph and replay it. */
 rtproj_status rtproj_batch_set_graph(rtproj_batch batch, int enable);

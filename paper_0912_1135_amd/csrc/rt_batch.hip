@@ -79,6 +79,8 @@ struct rtproj_batch_s {
     int precision = RTPROJ_PREC_FP64;  // the preconditioner's Gram: binary64 or binary32 (MIXED_FP32)
     int prec_used = RTPROJ_PREC_FP64;  // of the last precondition
     bool x3 = false;                   // the last precondition's Grams were split bfloat16
+    bool sketch64 = true;              // the last precondition sketched in binary64
+    bool escalated = false;            // ... after a binary32 sketch proved too coarse
     int plain_steps = 0, comp_steps = 2;  // schedule of the last projection
     bool comp_final = true;               // its final pass after compensated steps
     int last_steps = 0, last_plain = 0;   // steps of the last projection (norms recorded)
@@ -331,6 +333,7 @@ void build_precondition(Program &P, rtproj_batch b, const double *const *A, cons
         for (const auto &cls : by_np) {
             std::vector<rt::SketchGroupArgs> v;
             Op o{OP_SKETCH, 0, (int)cls.second.size()};
+            o.i0 = b->sketch64 ? 0 : 1;  // 1: binary32 arithmetic
             for (int64_t i : cls.second) {
                 rtproj_plan p = b->sub[i];
                 v.push_back(rt::SketchGroupArgs{p->sketch_tables(), A[i], lda[i], p->m, p->d_S, p->l, p->d_zbuf,
@@ -823,7 +826,9 @@ hipError_t run_op(const Op &o, const unsigned char *arena, hipStream_t s)
     switch (o.kind) {
     case OP_GEMM: return rt::gemm_f64_grouped((const rt::GemmArgs *)d, o.count, o.gs, s);
     case OP_REDUCE: return rt::reduce_splits_grouped_f64((const rt::ReduceGroupArgs *)d, o.count, o.total, s);
-    case OP_SKETCH: return rt::sketch_grouped_f64((const rt::SketchGroupArgs *)d, o.count, o.ss, s);
+    case OP_SKETCH:
+        return o.i0 ? rt::sketch_grouped_f32((const rt::SketchGroupArgs *)d, o.count, o.ss, s)
+                    : rt::sketch_grouped_f64((const rt::SketchGroupArgs *)d, o.count, o.ss, s);
     case OP_COPY: return rt::copy_cols_grouped_f64((const rt::CopyGroupArgs *)d, o.count, o.total, s);
     case OP_SET0: return rt::set_matrix_grouped_f64((const rt::MatGroupArgs *)d, o.count, o.total, 0, s);
     case OP_SET1: return rt::set_matrix_grouped_f64((const rt::MatGroupArgs *)d, o.count, o.total, 1, s);
@@ -1123,10 +1128,34 @@ rtproj_status rtproj_batch_precondition_scaled(rtproj_batch b, const double *con
     // needs n % 4 == 0, else the batch takes the binary32 Gram
     b->x3 = b->prec_used == RTPROJ_PREC_MIXED_BF16X3;
     for (int64_t i = 0; i < b->count && b->x3; ++i) b->x3 = b->sub[i]->n % 4 == 0;
-    Program P;
-    build_precondition(P, b, A, lda, b->cscale.data());
-    rtproj_status st = run_program(b, b->pre, P);
-    if (st != RTPROJ_OK) return st;
+    // the reduced precisions sketch in binary32; when that proves too coarse
+    // for any member (as for plans: 2^-24 kappa_est above RT_SKETCH32_MAX, a
+    // failed rank test, or a Gram condition estimate above RT_COND_ESCALATE),
+    // every member is sketched again in binary64
+    b->sketch64 = b->prec_used == RTPROJ_PREC_FP64;
+    b->escalated = false;
+    for (;;) {
+        Program P;
+        build_precondition(P, b, A, lda, b->cscale.data());
+        rtproj_status st = run_program(b, b->pre, P);
+        if (st != RTPROJ_OK) return st;
+        if (b->sketch64) break;
+        std::vector<double> diag((size_t)b->count * 8);
+        RT_HIP(hipMemcpyAsync(diag.data(), b->d_diag_all, diag.size() * sizeof(double), hipMemcpyDeviceToHost,
+                              b->stream));
+        RT_HIP(hipStreamSynchronize(b->stream));
+        bool coarse = false;
+        for (int64_t i = 0; i < b->count && !coarse; ++i) {
+            const double *d = diag.data() + 8 * i;
+            const double kap = d[2] > 0 ? d[3] / d[2] : INFINITY;
+            const double cw = d[6] > 0 ? d[7] / d[6] : INFINITY;
+            coarse = !(std::ldexp(kap, -24) <= RT_SKETCH32_MAX) ||
+                     !(d[2] > (double)b->sub[i]->m * std::ldexp(1.0, -52) * d[3]) || !(cw <= RT_COND_ESCALATE);
+        }
+        if (!coarse) break;
+        b->sketch64 = true;
+        b->escalated = true;
+    }
     for (int64_t i = 0; i < b->count; ++i) {
         b->sub[i]->A = A[i];
         b->sub[i]->lda = lda[i];
@@ -1243,7 +1272,9 @@ rtproj_status rtproj_batch_status(rtproj_batch b, int *per_member)
         p->inv_used = RTPROJ_INV_CHOLESKY;
         p->info.precision = b->prec_used;
         p->info.gram_bits = b->x3 ? 17 : (b->prec_used != RTPROJ_PREC_FP64 ? 32 : 64);
-        p->info.sketch_bits = p->info.w_bits = 64;
+        p->info.w_bits = 64;
+        p->info.sketch_bits = b->sketch64 ? 64 : 32;
+        p->info.sketch_escalated = b->escalated ? 1 : 0;
         if (per_member) per_member[i] = st;
         // precedence: rank deficiency, then a device error, then non-convergence
         if (st == RTPROJ_ERR_RANK || (st == RTPROJ_ERR_DEVICE && worst != RTPROJ_ERR_RANK) ||

@@ -208,6 +208,9 @@ struct SketchGroupArgs {
 };
 struct SketchGroupShape { int64_t max_n1, max_n2, max_rows_chunk; int chunks; };
 hipError_t sketch_grouped_f64(const SketchGroupArgs *d, int count, const SketchGroupShape &sh, hipStream_t stream);
+// The same in binary32 arithmetic (binary32 tables and intermediate; S
+// written in binary64 as the binary32 plan sketch does).
+hipError_t sketch_grouped_f32(const SketchGroupArgs *d, int count, const SketchGroupShape &sh, hipStream_t stream);
 // Same sketch with the transform in binary32 (A rounded on load; S written in
 // binary64).
 hipError_t sketch_f32(const SketchTables &t, const double *A, int64_t lda, int64_t m,

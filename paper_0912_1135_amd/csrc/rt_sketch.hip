@@ -405,6 +405,11 @@ hipError_t sketch_grouped_f64(const SketchGroupArgs *d, int count, const SketchG
     return sketch_grouped_run<double>(d, count, sh, stream);
 }
 
+hipError_t sketch_grouped_f32(const SketchGroupArgs *d, int count, const SketchGroupShape &sh, hipStream_t stream)
+{
+    return sketch_grouped_run<float>(d, count, sh, stream);
+}
+
 hipError_t sketch_f64(const SketchTables &t, const double *A, int64_t lda, int64_t m, double *S, int64_t lds,
                       double *zbuf, int64_t rows_chunk, hipStream_t stream)
 {

@@ -244,6 +244,29 @@ def test_batch_split_bf16_gram_column_scaled_and_fallback(rt):
     bt.close()
 
 
+@pytest.mark.parametrize("prec", [1, 3])
+def test_batch_binary32_sketch_escalates_for_an_ill_conditioned_member(rt, prec):
+    """The reduced batch precisions sketch in binary32; a member with
+    cond(A) = 1e10 makes that sketch too coarse (2^-24 kappa_est > 1), so the
+    batch sketches every member again in binary64, and all of them still
+    match the oracle.  Without such a member the sketch stays binary32."""
+    ms, ns = [48, 64], [1024, 2048]
+    for kappas, want_bits in (([1e5, 1e5], 32), ([1e5, 1e10], 64)):
+        As = [synth.make_problem(m, n, kp, 330 + i) for i, (m, n, kp) in enumerate(zip(ms, ns, kappas))]
+        Bs = [synth.make_rhs(n, 3, 430 + i) for i, n in enumerate(ns)]
+        bt = rt.Batch(ms, ns, [4 * m for m in ms], 16)
+        bt.set_precision(prec)
+        bt.precondition([torch.from_numpy(A).to(dev()) for A in As])
+        Z, Y, X = bt.project_all([torch.from_numpy(B).to(dev()) for B in Bs])
+        assert bt.status() == [0, 0]
+        for i in range(2):
+            info = bt.member_info(i)
+            assert info["sketch_bits"] == want_bits and info["sketch_escalated"] == (1 if want_bits == 64 else 0)
+            e = check_member(As[i], Bs[i], Z[i].cpu().numpy(), Y[i].cpu().numpy(), X[i].cpu().numpy())
+            assert max(e) <= TOL, (kappas, i, e)
+        bt.close()
+
+
 @pytest.mark.parametrize("graph", [False, True])
 def test_batch_grouped_pivoted_qr_matches_oracle(rt, graph):
     """Few large members: the pivoted QR of R0 runs as a group of blocks per
