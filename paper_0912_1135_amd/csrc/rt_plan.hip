@@ -1541,8 +1541,8 @@ rtproj_status precondition_impl(rtproj_plan p, const double *A, int64_t lda, boo
         StageScope sc(p, 0);
         if (p->precision == RTPROJ_PREC_FP64 || sketch64)
             RT_HIP(rt::sketch_f64(p->sketch_tables(), A, lda, m, p->d_S, l, p->d_zbuf, p->rows_chunk, s));
-        else
-            RT_HIP(rt::sketch_f32(p->sketch_tables(), A, lda, m, p->d_S, l, p->d_zbuf, p->rows_chunk, s));
+        else  // complex binary32 fits twice the rows in the buffer sized for binary64 (fewer, fuller launches)
+            RT_HIP(rt::sketch_f32(p->sketch_tables(), A, lda, m, p->d_S, l, p->d_zbuf, 2 * p->rows_chunk, s));
     }
     // 2. pivoted QR of S^T, directly or on the small factor R0 of S^T
     double diag[4];
