@@ -41,11 +41,14 @@ __device__ __forceinline__ unsigned bitrev(unsigned x, int bits)
 // stored column after column in LDS with column stride ld (input already in
 // bit-reversed order).  tw: len/2 twiddles exp(-2 pi i j / len) in LDS.
 //
-// Up to four consecutive radix-2 stages (half-sizes h, 2h, 4h, 8h) run in
+// Up to MAXB consecutive radix-2 stages (half-sizes h, 2h, 4h, 8h) run in
 // registers: a thread loads the 2^B elements base + j h (base = blk 2^B h +
 // pos, pos < h) that those stages combine, applies the same butterflies the
-// stage-by-stage form would (so the result is bitwise the same), and writes
-// them back; one block barrier per group of stages instead of one per stage.
+// stage-by-stage form would, and writes them back; one block barrier per
+// group of stages instead of one per stage.  Different groupings can still
+// differ in the last bit, where the compiler fuses a product into a
+// multiply-add in one shape of the code and not in another, so every kernel
+// that must agree bitwise uses the same MAXB.
 // Consecutive threads take consecutive columns, whose stride ld = len + 1
 // puts their accesses on distinct banks.
 template <typename R, int B>
@@ -81,13 +84,13 @@ __device__ __forceinline__ void fft_stage_group(cpx<R> *buf, int len, int ld, in
     }
 }
 
-template <typename R>
-__device__ void lds_fft_cols(cpx<R> *buf, int len, int ld, int cols, const cpx<R> *tw)
+template <typename R, int MAXB = 4>
+__device__ __forceinline__ void lds_fft_cols(cpx<R> *buf, int len, int ld, int cols, const cpx<R> *tw)
 {
     for (int h = 1; h < len;) {
         int rem = 0;
         while ((h << rem) < len) ++rem;  // stages left
-        switch (rem < 4 ? rem : 4) {
+        switch (rem < MAXB ? rem : MAXB) {
         case 4: fft_stage_group<R, 4>(buf, len, ld, cols, tw, h); h <<= 4; break;
         case 3: fft_stage_group<R, 3>(buf, len, ld, cols, tw, h); h <<= 3; break;
         case 2: fft_stage_group<R, 2>(buf, len, ld, cols, tw, h); h <<= 2; break;
@@ -123,6 +126,13 @@ __host__ __device__ inline SketchGeom sketch_geom(const SketchTables &t)
     g.bits2 = ilog2(t.n2);
     return g;
 }
+
+// Stages per register pass of the pass-1 column transforms: three in
+// binary32, whose pipelined pass holds 32 gathered elements per thread in
+// flight beside them, four in binary64; the plain, pipelined and grouped
+// pass 1 all use it, so a plan's sketch and a batch member's agree bitwise.
+template <typename R>
+struct Pass1Stages { static constexpr int value = sizeof(R) == 4 ? 3 : 4; };
 
 // Dynamic LDS of pass 1 (bytes), in this order: n1/2 twiddles of the
 // n1-point FFT, the tw_cols x n1 columns, the two-level twiddle tables of
@@ -206,7 +216,7 @@ __device__ __forceinline__ void sketch_pass1_body(const SketchTables &t, const d
             if (dst[q] >= 0) buf[dst[q]] = cplx{(R)(sg[q] * v0[q]), (R)(sg[q] * v1[q])};
     }
     __syncthreads();
-    lds_fft_cols(buf, n1, ld1, tw_cols, tw);
+    lds_fft_cols<R, Pass1Stages<R>::value>(buf, n1, ld1, tw_cols, tw);
     const int tl_mask = nl - 1;
     cplx *zp = zbuf + pair * t.np;
     for (int e = threadIdx.x; e < total; e += blockDim.x) {
@@ -222,6 +232,100 @@ __global__ __launch_bounds__(256) void sketch_pass1(SketchTables t, const double
                                                     int64_t row0, cpx<R> *zbuf, int tw_cols, int bits1)
 {
     sketch_pass1_body<R>(t, A, lda, m, row0, zbuf, tw_cols, bits1, blockIdx.x, blockIdx.y);
+}
+
+// Pass 1 for one column group and a run of row pairs (pair = blockIdx.y,
+// + gridDim.y, ...), software-pipelined: the gathers of the next pair are
+// issued right after the current pair is staged in LDS, so they stay in
+// flight through its transform and its stores (block barriers wait for LDS
+// only).  Q = n1 * tw_cols / 256 elements per thread, all of them loaded and
+// stored unconditionally: rows past m and positions past n are read clamped
+// and zeroed when staged, so the memory counters stay exact across the loop.
+// A thread's elements share j = tid % tw_cols, so their signs and padding
+// flags are two bit masks held for the whole run.  Same arithmetic per
+// element and per column as sketch_pass1 (bitwise the same intermediate).
+template <typename R, int Q>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void sketch_pass1_pipe(
+    SketchTables t, const double *A, int64_t lda, int64_t m, int64_t row0, int64_t npairs, cpx<R> *zbuf, int tw_cols,
+    int bits1)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    typedef cpx<R> cplx;
+    cplx *smem = reinterpret_cast<cplx *>(smem_raw);
+    const int n1 = (int)t.n1, n2 = (int)t.n2;
+    const int nh = (int)(t.np >> t.tl_bits), nl = 1 << t.tl_bits;
+    cplx *tw = smem;
+    const int ld1 = n1 + 1;
+    cplx *buf = tw + (n1 >> 1);
+    cplx *th = buf + (int64_t)tw_cols * ld1;
+    cplx *tlo = th + nh;
+    int *s_sigma = reinterpret_cast<int *>(tlo + nl);
+    int *s_tinv = s_sigma + n1;
+    const int u0 = blockIdx.x * tw_cols;
+    if (u0 >= n2 || (int64_t)blockIdx.y >= npairs) return;
+    const cplx *tw1 = reinterpret_cast<const cplx *>(sizeof(R) == 8 ? (const void *)t.tw1 : (const void *)t.tw1f);
+    const cplx *twh = reinterpret_cast<const cplx *>(sizeof(R) == 8 ? (const void *)t.twh : (const void *)t.twhf);
+    const cplx *twl = reinterpret_cast<const cplx *>(sizeof(R) == 8 ? (const void *)t.twl : (const void *)t.twlf);
+    for (int e = threadIdx.x; e < (n1 >> 1); e += blockDim.x) tw[e] = tw1[e];
+    for (int e = threadIdx.x; e < nh; e += blockDim.x) th[e] = twh[e];
+    for (int e = threadIdx.x; e < nl; e += blockDim.x) tlo[e] = twl[e];
+    for (int e = threadIdx.x; e < n1; e += blockDim.x) s_sigma[e] = t.sigma[e];
+    for (int e = threadIdx.x; e < tw_cols; e += blockDim.x) s_tinv[e] = t.tau_inv[u0 + e];
+    __syncthreads();
+    // element q of this thread: e = tid + 256 q, t1 = e / tw_cols, j = tid % tw_cols
+    const int j = threadIdx.x % tw_cols, t1_0 = threadIdx.x / tw_cols, t1_step = 256 / tw_cols;
+    unsigned neg = 0, pad = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int64_t x = (int64_t)s_sigma[t1_0 + q * t1_step] * n2 + u0 + j;
+        if (x >= t.n) pad |= 1u << q;
+        else if (t.sign[x] < 0) neg |= 1u << q;
+    }
+    double v0[Q], v1[Q];
+    // positions are re-read from the staged permutation at every gather
+    // rather than held (registers go to the data in flight)
+    // (32-bit byte offsets from the two row bases: the host takes this path
+    // only when a row of A spans less than 4 GiB)
+    auto gather = [&](int64_t pr) {
+        const int64_t r0 = row0 + 2 * pr;
+        const char *a0 = reinterpret_cast<const char *>(A + r0 * lda);
+        const char *a1 = reinterpret_cast<const char *>(A + (r0 + 1 < m ? r0 + 1 : r0) * lda);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const unsigned x = (unsigned)s_sigma[t1_0 + q * t1_step] * (unsigned)n2 + (unsigned)(u0 + j);
+            const unsigned off = (x < (unsigned)t.n ? x : (unsigned)t.n - 1u) * 8u;
+            v0[q] = *reinterpret_cast<const double *>(a0 + off);
+            v1[q] = *reinterpret_cast<const double *>(a1 + off);
+        }
+    };
+    const int tl_mask = nl - 1;
+    int64_t pair = blockIdx.y;
+    gather(pair);
+    for (; pair < npairs; pair += gridDim.y) {
+        const bool has1 = row0 + 2 * pair + 1 < m;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int t1 = t1_0 + q * t1_step;
+            const double a = (pad >> q) & 1 ? 0.0 : ((neg >> q) & 1 ? -v0[q] : v0[q]);
+            const double v = has1 ? v1[q] : 0.0;  // a missing odd row: a signed zero, as sign * 0
+            const double b = (pad >> q) & 1 ? 0.0 : ((neg >> q) & 1 ? -v : v);
+            buf[j * ld1 + (int)bitrev((unsigned)t1, bits1)] = cplx{(R)a, (R)b};
+        }
+        __syncthreads();
+        // the next pair of this block (the last one re-reads its own pair)
+        const int64_t nxt = pair + gridDim.y;
+        gather(nxt < npairs ? nxt : pair);
+        lds_fft_cols<R, Pass1Stages<R>::value>(buf, n1, ld1, tw_cols, tw);
+        cplx *zp = zbuf + pair * t.np;
+#pragma unroll 2
+        for (int q = 0; q < Q; ++q) {
+            const int k1 = t1_0 + q * t1_step;
+            const int idx = s_tinv[j] * k1;
+            const cplx w = cmul(th[idx >> t.tl_bits], tlo[idx & tl_mask]);
+            zp[(int64_t)k1 * n2 + u0 + j] = cmul(buf[(int64_t)j * ld1 + k1], w);
+        }
+        __syncthreads();
+    }
 }
 
 template <typename R>
@@ -347,11 +451,37 @@ hipError_t sketch_run(const SketchTables &t, const double *A, int64_t lda, int64
     if (ea != hipSuccess) return ea;
     ea = hipFuncSetAttribute((const void *)sketch_pass2<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm2);
     if (ea != hipSuccess) return ea;
+    // the pipelined pass 1 when each thread holds 16 or 32 elements of the
+    // n1 x tw_cols column group, with as many blocks per pair range as fill
+    // the device once (each then walks its share of the pairs)
+    const int q1 = (int)((int64_t)n1 * tw_cols / 256);
+    const bool pipe = (q1 == 16 || q1 == 32) && (int64_t)q1 * 256 == (int64_t)n1 * tw_cols && t.np * 8 < (int64_t(1) << 32);
+    int resident = 0;
+    if (pipe) {
+        const void *kf = q1 == 16 ? (const void *)sketch_pass1_pipe<R, 16> : (const void *)sketch_pass1_pipe<R, 32>;
+        if ((ea = hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm1)) != hipSuccess) return ea;
+        int per_cu = 0, dev = 0, cus = 0;
+        if ((ea = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kf, 256, sm1)) != hipSuccess) return ea;
+        if ((ea = hipGetDevice(&dev)) != hipSuccess) return ea;
+        if ((ea = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return ea;
+        resident = std::max(1, per_cu) * std::max(1, cus);
+    }
     for (int64_t row0 = 0; row0 < m; row0 += rows_chunk) {
         const int64_t rows = std::min<int64_t>(rows_chunk, m - row0);
         const int64_t npairs = (rows + 1) / 2;
-        hipLaunchKernelGGL(sketch_pass1<R>, dim3(n2 / tw_cols, (unsigned)npairs), dim3(256), sm1, stream, t, A, lda,
-                           m, row0, z, tw_cols, bits1);
+        if (pipe) {
+            const int gx = n2 / tw_cols;
+            const int64_t gy = std::min<int64_t>(npairs, std::max(1, resident / gx));
+            if (q1 == 16)
+                hipLaunchKernelGGL((sketch_pass1_pipe<R, 16>), dim3(gx, (unsigned)gy), dim3(256), sm1, stream, t, A, lda,
+                                   m, row0, npairs, z, tw_cols, bits1);
+            else
+                hipLaunchKernelGGL((sketch_pass1_pipe<R, 32>), dim3(gx, (unsigned)gy), dim3(256), sm1, stream, t, A, lda,
+                                   m, row0, npairs, z, tw_cols, bits1);
+        } else {
+            hipLaunchKernelGGL(sketch_pass1<R>, dim3(n2 / tw_cols, (unsigned)npairs), dim3(256), sm1, stream, t, A, lda,
+                               m, row0, z, tw_cols, bits1);
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(sketch_pass2<R>, dim3(n1 / 2 + 1, (unsigned)((npairs + cp - 1) / cp)), dim3(256), sm2, stream,
