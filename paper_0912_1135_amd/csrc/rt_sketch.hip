@@ -128,11 +128,14 @@ __host__ __device__ inline SketchGeom sketch_geom(const SketchTables &t)
 }
 
 // Stages per register pass of the pass-1 column transforms: three in
-// binary32, whose pipelined pass holds 32 gathered elements per thread in
+// binary32, whose pipelined passes hold 32 gathered elements per thread in
 // flight beside them, four in binary64; the plain, pipelined and grouped
-// pass 1 all use it, so a plan's sketch and a batch member's agree bitwise.
+// passes all use it, so a plan's sketch and a batch member's agree bitwise.
 template <typename R>
 struct Pass1Stages { static constexpr int value = sizeof(R) == 4 ? 3 : 4; };
+// The same for the row transforms of pass 2.
+template <typename R>
+struct Pass2Stages { static constexpr int value = sizeof(R) == 4 ? 3 : 4; };
 
 // Dynamic LDS of pass 1 (bytes), in this order: n1/2 twiddles of the
 // n1-point FFT, the tw_cols x n1 columns, the two-level twiddle tables of
@@ -375,7 +378,7 @@ __device__ __forceinline__ void sketch_pass2_body(const SketchTables &t, int64_t
     __syncthreads();
     // FFT every loaded column; columns are laid out p*2 + col, so transform
     // 2*pc columns (an unused second column is harmless zero work when ncol = 1).
-    lds_fft_cols(buf, n2, ld2, pc * 2, tw);
+    lds_fft_cols<R, Pass2Stages<R>::value>(buf, n2, ld2, pc * 2, tw);
     const int beg = t.sel_off[w], cnt = t.sel_off[w + 1] - beg;
     const double sc1 = 1.0 / __builtin_sqrt((double)t.l);
     const double sc2 = __builtin_sqrt(2.0) * sc1;
@@ -406,6 +409,93 @@ __global__ __launch_bounds__(256) void sketch_pass2(SketchTables t, int64_t m, i
                                                     const cpx<R> *zbuf, double *S, int64_t lds, int cp, int bits2)
 {
     sketch_pass2_body<R>(t, m, row0, npairs, zbuf, S, lds, cp, bits2, blockIdx.x, blockIdx.y);
+}
+
+// Pass 2, software-pipelined like pass 1: the tasks (k1 pair w, group of cp
+// row pairs), numbered w fastest, are dealt round-robin to the blocks, and a
+// block gathers its next task's columns while the current one is
+// transformed and written out.  Q = 2 cp n2 / 256 elements per thread, all
+// loaded unconditionally: a single-column pair (w = 0 or n1/2) loads its
+// column twice and a short last group repeats its last row pair; neither
+// copy is written out.  Same per-column arithmetic as sketch_pass2.
+template <typename R, int Q>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void sketch_pass2_pipe(
+    SketchTables t, int64_t m, int64_t row0, int64_t npairs, const cpx<R> *zbuf, double *S, int64_t lds, int cp,
+    int bits2)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    typedef cpx<R> cplx;
+    cplx *smem = reinterpret_cast<cplx *>(smem_raw);
+    const int n1 = (int)t.n1, n2 = (int)t.n2;
+    cplx *tw = smem;
+    const int ld2 = n2 + 1;
+    cplx *buf = smem + (n2 >> 1);
+    int *s_tinv = reinterpret_cast<int *>(buf + (int64_t)cp * 2 * ld2);
+    const int gx = n1 / 2 + 1;
+    const int64_t ngroups = (npairs + cp - 1) / cp, ntasks = ngroups * gx;
+    if ((int64_t)blockIdx.x >= ntasks) return;
+    const cplx *tw2 = reinterpret_cast<const cplx *>(sizeof(R) == 8 ? (const void *)t.tw2 : (const void *)t.tw2f);
+    for (int e = threadIdx.x; e < (n2 >> 1); e += blockDim.x) tw[e] = tw2[e];
+    for (int e = threadIdx.x; e < n2; e += blockDim.x) s_tinv[e] = t.tau_inv[e];
+    __syncthreads();
+    cplx v[Q];
+    // (32-bit byte offsets from the group's base: the host takes this path
+    // only when cp row pairs of the intermediate span less than 4 GiB)
+    auto gather = [&](int64_t task) {
+        const int w = (int)(task % gx);
+        const int64_t p0 = task / gx * cp;
+        const int ka = w, kb = (n1 - w) % n1;
+        const int plast = (int)min<int64_t>(cp, npairs - p0) - 1;
+        const char *zb = reinterpret_cast<const char *>(zbuf + p0 * t.np);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int e = threadIdx.x + 256 * q;
+            const int c = e >> bits2, u = e & (n2 - 1);
+            const int p = min(c >> 1, plast);
+            const unsigned k1 = (unsigned)((c & 1) ? kb : ka);
+            const unsigned off = ((unsigned)p * (unsigned)t.np + k1 * (unsigned)n2 + (unsigned)u) * (unsigned)sizeof(cplx);
+            v[q] = *reinterpret_cast<const cplx *>(zb + off);
+        }
+    };
+    const double sc1 = 1.0 / __builtin_sqrt((double)t.l);
+    const double sc2 = __builtin_sqrt(2.0) * sc1;
+    const int64_t half = t.np >> 1;
+    int64_t task = blockIdx.x;
+    gather(task);
+    for (; task < ntasks; task += gridDim.x) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int e = threadIdx.x + 256 * q;
+            const int c = e >> bits2, u = e & (n2 - 1);
+            buf[c * ld2 + (int)bitrev((unsigned)s_tinv[u], bits2)] = v[q];
+        }
+        __syncthreads();
+        const int64_t nx = task + gridDim.x;
+        gather(nx < ntasks ? nx : task);
+        lds_fft_cols<R, Pass2Stages<R>::value>(buf, n2, ld2, cp * 2, tw);
+        const int w = (int)(task % gx), ka = w;
+        const int64_t p0 = task / gx * cp;
+        const int pc = (int)min<int64_t>(cp, npairs - p0);
+        const int beg = t.sel_off[w], cnt = t.sel_off[w + 1] - beg;
+        for (int e = threadIdx.x; e < cnt * pc; e += blockDim.x) {
+            const int p = e / cnt, s = e - p * cnt;
+            const int32_t *ent = t.sel + 3 * (beg + s);
+            const int64_t k = ent[0];
+            const int part = ent[1], q = ent[2];
+            const int k1 = (int)(k % n1), k2 = (int)(k / n1);
+            const int64_t kp = (t.np - k) % t.np;
+            const int kp1 = (int)(kp % n1), kp2 = (int)(kp / n1);
+            const cplx y = buf[(int64_t)(p * 2 + (k1 == ka ? 0 : 1)) * ld2 + k2];
+            const cplx yp = buf[(int64_t)(p * 2 + (kp1 == ka ? 0 : 1)) * ld2 + kp2];
+            const double ar = 0.5 * ((double)y.re + (double)yp.re), ai = 0.5 * ((double)y.im - (double)yp.im);
+            const double br = 0.5 * ((double)y.im + (double)yp.im), bi = -0.5 * ((double)y.re - (double)yp.re);
+            const double sc = (k == 0 || k == half) ? sc1 : sc2;
+            const int64_t r0 = row0 + 2 * (p0 + p);
+            S[r0 * lds + q] = sc * (part ? ai : ar);
+            if (r0 + 1 < m) S[(r0 + 1) * lds + q] = sc * (part ? bi : br);
+        }
+        __syncthreads();
+    }
 }
 
 // Grouped passes: member blockIdx.z; chunk c covers rows [c*rows_chunk, ...).
@@ -454,17 +544,37 @@ hipError_t sketch_run(const SketchTables &t, const double *A, int64_t lda, int64
     // the pipelined pass 1 when each thread holds 16 or 32 elements of the
     // n1 x tw_cols column group, with as many blocks per pair range as fill
     // the device once (each then walks its share of the pairs)
+    // (32 elements per thread occur in binary32 only: binary64 halves
+    // tw_cols and cp for the same LDS, so its forms are not instantiated)
+    constexpr int QB = sizeof(R) == 4 ? 32 : 16;
     const int q1 = (int)((int64_t)n1 * tw_cols / 256);
-    const bool pipe = (q1 == 16 || q1 == 32) && (int64_t)q1 * 256 == (int64_t)n1 * tw_cols && t.np * 8 < (int64_t(1) << 32);
+    const bool pipe = (q1 == 16 || q1 == QB) && (int64_t)q1 * 256 == (int64_t)n1 * tw_cols && t.np * 8 < (int64_t(1) << 32);
     int resident = 0;
     if (pipe) {
-        const void *kf = q1 == 16 ? (const void *)sketch_pass1_pipe<R, 16> : (const void *)sketch_pass1_pipe<R, 32>;
+        const void *kf = q1 == 16 ? (const void *)sketch_pass1_pipe<R, 16> : (const void *)sketch_pass1_pipe<R, QB>;
         if ((ea = hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm1)) != hipSuccess) return ea;
         int per_cu = 0, dev = 0, cus = 0;
         if ((ea = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kf, 256, sm1)) != hipSuccess) return ea;
         if ((ea = hipGetDevice(&dev)) != hipSuccess) return ea;
         if ((ea = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return ea;
         resident = std::max(1, per_cu) * std::max(1, cus);
+    }
+    // the pipelined pass 2 in binary32 when each thread holds 16 or 32
+    // elements of the 2 cp columns, as many blocks as are resident at once
+    // (in binary64 it measured slower than the plain pass 2: 6.5 against
+    // 5.7 ms for both passes at 2048 x 262144)
+    const int q2 = (int)((int64_t)2 * cp * n2 / 256);
+    const bool pipe2 = sizeof(R) == 4 && (q2 == 16 || q2 == QB) && (int64_t)q2 * 256 == (int64_t)2 * cp * n2 &&
+                       (int64_t)cp * t.np * csz < (int64_t(1) << 32);
+    int64_t resident2 = 0;
+    if (pipe2) {
+        const void *kf = q2 == 16 ? (const void *)sketch_pass2_pipe<R, 16> : (const void *)sketch_pass2_pipe<R, QB>;
+        if ((ea = hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm2)) != hipSuccess) return ea;
+        int per_cu = 0, dev = 0, cus = 0;
+        if ((ea = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kf, 256, sm2)) != hipSuccess) return ea;
+        if ((ea = hipGetDevice(&dev)) != hipSuccess) return ea;
+        if ((ea = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return ea;
+        resident2 = (int64_t)std::max(1, per_cu) * std::max(1, cus);
     }
     for (int64_t row0 = 0; row0 < m; row0 += rows_chunk) {
         const int64_t rows = std::min<int64_t>(rows_chunk, m - row0);
@@ -476,7 +586,7 @@ hipError_t sketch_run(const SketchTables &t, const double *A, int64_t lda, int64
                 hipLaunchKernelGGL((sketch_pass1_pipe<R, 16>), dim3(gx, (unsigned)gy), dim3(256), sm1, stream, t, A, lda,
                                    m, row0, npairs, z, tw_cols, bits1);
             else
-                hipLaunchKernelGGL((sketch_pass1_pipe<R, 32>), dim3(gx, (unsigned)gy), dim3(256), sm1, stream, t, A, lda,
+                hipLaunchKernelGGL((sketch_pass1_pipe<R, QB>), dim3(gx, (unsigned)gy), dim3(256), sm1, stream, t, A, lda,
                                    m, row0, npairs, z, tw_cols, bits1);
         } else {
             hipLaunchKernelGGL(sketch_pass1<R>, dim3(n2 / tw_cols, (unsigned)npairs), dim3(256), sm1, stream, t, A, lda,
@@ -484,8 +594,19 @@ hipError_t sketch_run(const SketchTables &t, const double *A, int64_t lda, int64
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(sketch_pass2<R>, dim3(n1 / 2 + 1, (unsigned)((npairs + cp - 1) / cp)), dim3(256), sm2, stream,
-                           t, m, row0, npairs, (const cplx *)z, S, lds, cp, bits2);
+        if (pipe2) {
+            const int64_t ntasks = (npairs + cp - 1) / cp * (n1 / 2 + 1);
+            const unsigned gb = (unsigned)std::min<int64_t>(ntasks, resident2);
+            if (q2 == 16)
+                hipLaunchKernelGGL((sketch_pass2_pipe<R, 16>), dim3(gb), dim3(256), sm2, stream, t, m, row0, npairs,
+                                   (const cplx *)z, S, lds, cp, bits2);
+            else
+                hipLaunchKernelGGL((sketch_pass2_pipe<R, QB>), dim3(gb), dim3(256), sm2, stream, t, m, row0, npairs,
+                                   (const cplx *)z, S, lds, cp, bits2);
+        } else {
+            hipLaunchKernelGGL(sketch_pass2<R>, dim3(n1 / 2 + 1, (unsigned)((npairs + cp - 1) / cp)), dim3(256), sm2,
+                               stream, t, m, row0, npairs, (const cplx *)z, S, lds, cp, bits2);
+        }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -303,6 +303,27 @@ def test_fp32_sketch_matches_oracle(rt):
     plan.close()
 
 
+@pytest.mark.parametrize("m,n,l,precision", [(37, 65436, 512, 0), (37, 65436, 512, 1), (9, 262137, 64, 0),
+                                               (9, 262137, 64, 1), (300, 262144, 1024, 0), (300, 262144, 1024, 1)])
+def test_long_row_sketch_matches_oracle(rt, m, n, l, precision):
+    """Transforms of 2^16 and 2^18 points, where both passes walk runs of row
+    pairs with the next gathers in flight: odd m (a last pair with one row),
+    n short of the padded length, and a last group of row pairs shorter than
+    the others, in binary64 and binary32."""
+    A = np.random.default_rng(4000 + m).standard_normal((m, n))
+    plan = rt.Plan(m, n, l, 21)
+    plan.set_precision(precision)
+    plan.precondition(torch.from_numpy(A).to(dev()))
+    assert plan.info()["sketch_bits"] == (64 if precision == 0 else 32)
+    S = plan.export()["S"].cpu().numpy()
+    Sr = oracle.srft_sketch(A, 21, l)
+    np_ = oracle.srft_dims(n)[0]
+    u = 2.0 ** -52 if precision == 0 else 2.0 ** -23
+    tol = 64 * u * np.log2(np_) * np.linalg.norm(A, axis=1)
+    assert np.all(np.linalg.norm(S - Sr, axis=1) <= tol)
+    plan.close()
+
+
 def test_bf16_gram_needs_refinement(rt):
     """Unrefined, the bfloat16 Gram leaves errors far above binary64 rounding;
     the refinement of Remark 4.3 brings them under the tolerance."""
