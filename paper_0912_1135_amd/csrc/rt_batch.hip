@@ -334,6 +334,7 @@ void build_precondition(Program &P, rtproj_batch b, const double *const *A, cons
             std::vector<rt::SketchGroupArgs> v;
             Op o{OP_SKETCH, 0, (int)cls.second.size()};
             o.i0 = b->sketch64 ? 0 : 1;  // 1: binary32 arithmetic
+            o.ss.one_length = true;      // the class shares its padded length
             for (int64_t i : cls.second) {
                 rtproj_plan p = b->sub[i];
                 v.push_back(rt::SketchGroupArgs{p->sketch_tables(), A[i], lda[i], p->m, p->d_S, p->l, p->d_zbuf,

@@ -206,7 +206,9 @@ struct SketchGroupArgs {
     double *zbuf; int64_t rows_chunk;
     const double *cs = nullptr;  // optional: sketch of A diag(cs), each element scaled on load
 };
-struct SketchGroupShape { int64_t max_n1, max_n2, max_rows_chunk; int chunks; };
+// one_length: every member has the same padded Fourier length, hence one
+// transform geometry (the pipelined passes need it).
+struct SketchGroupShape { int64_t max_n1, max_n2, max_rows_chunk; int chunks; bool one_length = false; };
 hipError_t sketch_grouped_f64(const SketchGroupArgs *d, int count, const SketchGroupShape &sh, hipStream_t stream);
 // The same in binary32 arithmetic (binary32 tables and intermediate; S
 // written in binary64 as the binary32 plan sketch does).

@@ -247,10 +247,15 @@ __global__ __launch_bounds__(256) void sketch_pass1(SketchTables t, const double
 // A thread's elements share j = tid % tw_cols, so their signs and padding
 // flags are two bit masks held for the whole run.  Same arithmetic per
 // element and per column as sketch_pass1 (bitwise the same intermediate).
+//
+// With a column scaling cs (a batch member's A diag(cs)), each element is
+// scaled when staged, cs re-read per row pair from the cache in groups of
+// eight so that only eight scales are live beside the gathered data; the
+// product rounds as the plain pass's sign * cs times the element does.
 template <typename R, int Q>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void sketch_pass1_pipe(
-    SketchTables t, const double *A, int64_t lda, int64_t m, int64_t row0, int64_t npairs, cpx<R> *zbuf, int tw_cols,
-    int bits1)
+__device__ __forceinline__ void pass1_pipe_body(const SketchTables &t, const double *A, int64_t lda, int64_t m,
+                                                int64_t row0, int64_t npairs, cpx<R> *zbuf, int tw_cols, int bits1,
+                                                int bx, int64_t by, int64_t gy, const double *cs)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     typedef cpx<R> cplx;
@@ -264,8 +269,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
     cplx *tlo = th + nh;
     int *s_sigma = reinterpret_cast<int *>(tlo + nl);
     int *s_tinv = s_sigma + n1;
-    const int u0 = blockIdx.x * tw_cols;
-    if (u0 >= n2 || (int64_t)blockIdx.y >= npairs) return;
+    const int u0 = bx * tw_cols;
+    if (u0 >= n2 || by >= npairs) return;
     const cplx *tw1 = reinterpret_cast<const cplx *>(sizeof(R) == 8 ? (const void *)t.tw1 : (const void *)t.tw1f);
     const cplx *twh = reinterpret_cast<const cplx *>(sizeof(R) == 8 ? (const void *)t.twh : (const void *)t.twhf);
     const cplx *twl = reinterpret_cast<const cplx *>(sizeof(R) == 8 ? (const void *)t.twl : (const void *)t.twlf);
@@ -302,21 +307,42 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
         }
     };
     const int tl_mask = nl - 1;
-    int64_t pair = blockIdx.y;
+    int64_t pair = by;
     gather(pair);
-    for (; pair < npairs; pair += gridDim.y) {
+    for (; pair < npairs; pair += gy) {
         const bool has1 = row0 + 2 * pair + 1 < m;
+        if (cs) {
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int t1 = t1_0 + q * t1_step;
-            const double a = (pad >> q) & 1 ? 0.0 : ((neg >> q) & 1 ? -v0[q] : v0[q]);
-            const double v = has1 ? v1[q] : 0.0;  // a missing odd row: a signed zero, as sign * 0
-            const double b = (pad >> q) & 1 ? 0.0 : ((neg >> q) & 1 ? -v : v);
-            buf[j * ld1 + (int)bitrev((unsigned)t1, bits1)] = cplx{(R)a, (R)b};
+            for (int q0 = 0; q0 < Q; q0 += 8) {
+                double c[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int64_t x = (int64_t)s_sigma[t1_0 + (q0 + i) * t1_step] * n2 + u0 + j;
+                    c[i] = cs[x < t.n ? x : t.n - 1];
+                }
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int q = q0 + i, t1 = t1_0 + q * t1_step;
+                    const double s0 = c[i] * v0[q], s1 = c[i] * (has1 ? v1[q] : 0.0);
+                    const double a = (pad >> q) & 1 ? 0.0 : ((neg >> q) & 1 ? -s0 : s0);
+                    const double b = (pad >> q) & 1 ? 0.0 : ((neg >> q) & 1 ? -s1 : s1);
+                    buf[j * ld1 + (int)bitrev((unsigned)t1, bits1)] = cplx{(R)a, (R)b};
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int t1 = t1_0 + q * t1_step;
+                const double a = (pad >> q) & 1 ? 0.0 : ((neg >> q) & 1 ? -v0[q] : v0[q]);
+                const double v = has1 ? v1[q] : 0.0;  // a missing odd row: a signed zero, as sign * 0
+                const double b = (pad >> q) & 1 ? 0.0 : ((neg >> q) & 1 ? -v : v);
+                buf[j * ld1 + (int)bitrev((unsigned)t1, bits1)] = cplx{(R)a, (R)b};
+            }
         }
         __syncthreads();
         // the next pair of this block (the last one re-reads its own pair)
-        const int64_t nxt = pair + gridDim.y;
+        const int64_t nxt = pair + gy;
         gather(nxt < npairs ? nxt : pair);
         lds_fft_cols<R, Pass1Stages<R>::value>(buf, n1, ld1, tw_cols, tw);
         cplx *zp = zbuf + pair * t.np;
@@ -329,6 +355,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
         }
         __syncthreads();
     }
+}
+
+template <typename R, int Q>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void sketch_pass1_pipe(
+    SketchTables t, const double *A, int64_t lda, int64_t m, int64_t row0, int64_t npairs, cpx<R> *zbuf, int tw_cols,
+    int bits1)
+{
+    pass1_pipe_body<R, Q>(t, A, lda, m, row0, npairs, zbuf, tw_cols, bits1, blockIdx.x, blockIdx.y, gridDim.y, nullptr);
 }
 
 template <typename R>
@@ -419,9 +453,9 @@ __global__ __launch_bounds__(256) void sketch_pass2(SketchTables t, int64_t m, i
 // column twice and a short last group repeats its last row pair; neither
 // copy is written out.  Same per-column arithmetic as sketch_pass2.
 template <typename R, int Q>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void sketch_pass2_pipe(
-    SketchTables t, int64_t m, int64_t row0, int64_t npairs, const cpx<R> *zbuf, double *S, int64_t lds, int cp,
-    int bits2)
+__device__ __forceinline__ void pass2_pipe_body(const SketchTables &t, int64_t m, int64_t row0, int64_t npairs,
+                                                const cpx<R> *zbuf, double *S, int64_t lds, int cp, int bits2,
+                                                int64_t b0, int64_t nb)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     typedef cpx<R> cplx;
@@ -433,7 +467,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
     int *s_tinv = reinterpret_cast<int *>(buf + (int64_t)cp * 2 * ld2);
     const int gx = n1 / 2 + 1;
     const int64_t ngroups = (npairs + cp - 1) / cp, ntasks = ngroups * gx;
-    if ((int64_t)blockIdx.x >= ntasks) return;
+    if (b0 >= ntasks) return;
     const cplx *tw2 = reinterpret_cast<const cplx *>(sizeof(R) == 8 ? (const void *)t.tw2 : (const void *)t.tw2f);
     for (int e = threadIdx.x; e < (n2 >> 1); e += blockDim.x) tw[e] = tw2[e];
     for (int e = threadIdx.x; e < n2; e += blockDim.x) s_tinv[e] = t.tau_inv[e];
@@ -460,9 +494,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
     const double sc1 = 1.0 / __builtin_sqrt((double)t.l);
     const double sc2 = __builtin_sqrt(2.0) * sc1;
     const int64_t half = t.np >> 1;
-    int64_t task = blockIdx.x;
+    int64_t task = b0;
     gather(task);
-    for (; task < ntasks; task += gridDim.x) {
+    for (; task < ntasks; task += nb) {
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int e = threadIdx.x + 256 * q;
@@ -470,7 +504,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
             buf[c * ld2 + (int)bitrev((unsigned)s_tinv[u], bits2)] = v[q];
         }
         __syncthreads();
-        const int64_t nx = task + gridDim.x;
+        const int64_t nx = task + nb;
         gather(nx < ntasks ? nx : task);
         lds_fft_cols<R, Pass2Stages<R>::value>(buf, n2, ld2, cp * 2, tw);
         const int w = (int)(task % gx), ka = w;
@@ -498,6 +532,41 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
     }
 }
 
+template <typename R, int Q>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void sketch_pass2_pipe(
+    SketchTables t, int64_t m, int64_t row0, int64_t npairs, const cpx<R> *zbuf, double *S, int64_t lds, int cp,
+    int bits2)
+{
+    pass2_pipe_body<R, Q>(t, m, row0, npairs, zbuf, S, lds, cp, bits2, blockIdx.x, gridDim.x);
+}
+
+// Grouped pipelined passes (members of one Fourier length, so one geometry):
+// member blockIdx.z, chunk c of its rows; pass 1 walks the member's pairs in
+// steps of gridDim.y, pass 2 its tasks in steps of gridDim.x.
+template <typename R, int Q>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void sketch_pass1_pipe_grouped(
+    const SketchGroupArgs *gs, int chunk, int tw_cols, int bits1)
+{
+    const SketchGroupArgs &g = gs[blockIdx.z];
+    const int64_t row0 = (int64_t)chunk * g.rows_chunk;
+    if (row0 >= g.m) return;
+    const int64_t npairs = (min(g.rows_chunk, g.m - row0) + 1) / 2;
+    pass1_pipe_body<R, Q>(g.t, g.A, g.lda, g.m, row0, npairs, reinterpret_cast<cpx<R> *>(g.zbuf), tw_cols, bits1,
+                          blockIdx.x, blockIdx.y, gridDim.y, g.cs);
+}
+
+template <typename R, int Q>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void sketch_pass2_pipe_grouped(
+    const SketchGroupArgs *gs, int chunk, int cp, int bits2)
+{
+    const SketchGroupArgs &g = gs[blockIdx.z];
+    const int64_t row0 = (int64_t)chunk * g.rows_chunk;
+    if (row0 >= g.m) return;
+    const int64_t npairs = (min(g.rows_chunk, g.m - row0) + 1) / 2;
+    pass2_pipe_body<R, Q>(g.t, g.m, row0, npairs, reinterpret_cast<const cpx<R> *>(g.zbuf), g.S, g.lds, cp, bits2,
+                          blockIdx.x, gridDim.x);
+}
+
 // Grouped passes: member blockIdx.z; chunk c covers rows [c*rows_chunk, ...).
 template <typename R>
 __global__ __launch_bounds__(256) void sketch_pass1_grouped(const SketchGroupArgs *gs, int chunk)
@@ -522,6 +591,18 @@ __global__ __launch_bounds__(256) void sketch_pass2_grouped(const SketchGroupArg
     const SketchGeom geo = sketch_geom<R>(g.t);
     sketch_pass2_body<R>(g.t, g.m, row0, (rows + 1) / 2, reinterpret_cast<const cpx<R> *>(g.zbuf), g.S, g.lds, geo.cp,
                          geo.bits2, blockIdx.x, blockIdx.y);
+}
+
+// Blocks of kernel kf (256 threads, smem bytes of LDS) resident on the
+// whole device at once.
+hipError_t resident_blocks(const void *kf, size_t smem, int64_t *out)
+{
+    int per_cu = 0, dev = 0, cus = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kf, 256, smem);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    *out = (int64_t)std::max(1, per_cu) * std::max(1, cus);
+    return e;
 }
 
 template <typename R>
@@ -640,10 +721,54 @@ hipError_t sketch_grouped_run(const SketchGroupArgs *d, int count, const SketchG
     e = hipFuncSetAttribute((const void *)sketch_pass2_grouped<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm2);
     if (e != hipSuccess) return e;
     const int64_t max_pairs = (sh.max_rows_chunk + 1) / 2;
+    // pipelined passes when every member has one geometry that qualifies (as
+    // for a single plan), with the resident blocks shared among the members
+    constexpr int QB = sizeof(R) == 4 ? 32 : 16;
+    const SketchGeom geo = sketch_geom<R>(tmax);
+    const int64_t n1 = sh.max_n1, n2 = sh.max_n2, np = n1 * n2;
+    const int q1 = (int)(n1 * geo.tw_cols / 256), q2 = (int)(2 * geo.cp * n2 / 256);
+    const bool pipe1 = sh.one_length && (q1 == 16 || q1 == QB) && (int64_t)q1 * 256 == n1 * geo.tw_cols &&
+                       np * 8 < (int64_t(1) << 32);
+    const bool pipe2 = sh.one_length && sizeof(R) == 4 && (q2 == 16 || q2 == QB) &&
+                       (int64_t)q2 * 256 == 2 * geo.cp * n2 && geo.cp * np * csz < (int64_t(1) << 32);
+    const size_t psm1 = pass1_smem<R>(n1, n2, geo.tw_cols), psm2 = pass2_smem<R>(n2, geo.cp);
+    const void *k1 = q1 == 16 ? (const void *)sketch_pass1_pipe_grouped<R, 16> : (const void *)sketch_pass1_pipe_grouped<R, QB>;
+    const void *k2 = q2 == 16 ? (const void *)sketch_pass2_pipe_grouped<R, 16> : (const void *)sketch_pass2_pipe_grouped<R, QB>;
+    int64_t res1 = 0, res2 = 0;
+    if (pipe1) {
+        if ((e = hipFuncSetAttribute(k1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)psm1)) != hipSuccess) return e;
+        if ((e = resident_blocks(k1, psm1, &res1)) != hipSuccess) return e;
+    }
+    if (pipe2) {
+        if ((e = hipFuncSetAttribute(k2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)psm2)) != hipSuccess) return e;
+        if ((e = resident_blocks(k2, psm2, &res2)) != hipSuccess) return e;
+    }
+    const int pgx = (int)(n2 / geo.tw_cols);
+    const int64_t pgy = std::min<int64_t>(max_pairs, std::max<int64_t>(1, res1 / ((int64_t)pgx * count)));
+    const int64_t ntasks = (max_pairs + geo.cp - 1) / geo.cp * (n1 / 2 + 1);
+    const int64_t pnb = std::min<int64_t>(ntasks, std::max<int64_t>(1, res2 / count));
     for (int c = 0; c < sh.chunks; ++c) {
-        hipLaunchKernelGGL(sketch_pass1_grouped<R>, dim3(gx1, (unsigned)max_pairs, count), dim3(256), sm1, stream, d, c);
+        if (pipe1) {
+            if (q1 == 16)
+                hipLaunchKernelGGL((sketch_pass1_pipe_grouped<R, 16>), dim3(pgx, (unsigned)pgy, count), dim3(256), psm1,
+                                   stream, d, c, geo.tw_cols, geo.bits1);
+            else
+                hipLaunchKernelGGL((sketch_pass1_pipe_grouped<R, QB>), dim3(pgx, (unsigned)pgy, count), dim3(256), psm1,
+                                   stream, d, c, geo.tw_cols, geo.bits1);
+        } else {
+            hipLaunchKernelGGL(sketch_pass1_grouped<R>, dim3(gx1, (unsigned)max_pairs, count), dim3(256), sm1, stream, d, c);
+        }
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(sketch_pass2_grouped<R>, dim3(gx2, (unsigned)max_pairs, count), dim3(256), sm2, stream, d, c);
+        if (pipe2) {
+            if (q2 == 16)
+                hipLaunchKernelGGL((sketch_pass2_pipe_grouped<R, 16>), dim3((unsigned)pnb, 1, count), dim3(256), psm2,
+                                   stream, d, c, geo.cp, geo.bits2);
+            else
+                hipLaunchKernelGGL((sketch_pass2_pipe_grouped<R, QB>), dim3((unsigned)pnb, 1, count), dim3(256), psm2,
+                                   stream, d, c, geo.cp, geo.bits2);
+        } else {
+            hipLaunchKernelGGL(sketch_pass2_grouped<R>, dim3(gx2, (unsigned)max_pairs, count), dim3(256), sm2, stream, d, c);
+        }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;

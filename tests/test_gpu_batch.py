@@ -244,6 +244,46 @@ def test_batch_split_bf16_gram_column_scaled_and_fallback(rt):
     bt.close()
 
 
+@pytest.mark.parametrize("prec", [0, 3])
+def test_batch_long_rows_column_scaled(rt, prec):
+    """Members long enough for the pipelined grouped sketch passes (2^16-point
+    transforms, n short of the padded length, odd m), each on A diag(d_t).
+    A wrong sketch would still refine to the right projection, so each
+    member's Gram condition estimate (1.5-3 for a sound preconditioner) is
+    checked too, and in binary64 its rank estimate against a single plan's
+    on the scaled matrix with the member's seed (the same sketch)."""
+    m, n, l, steps, seed = 37, 65436, 148, 3, 16
+    A = synth.make_problem(m, n, 1e4, 81)
+    # d_t = 10^U(-3, 3) keeps R's trailing diagonal accurate enough to compare
+    # rank estimates; 10^U(-1, 1) keeps the binary32 sketch (no escalation)
+    lo = 3.0 if prec == 0 else 1.0
+    D = 10.0 ** np.random.default_rng(81).uniform(-lo, lo, size=(steps, n))
+    Bs = [synth.make_rhs(n, 3, 960 + t) for t in range(steps)]
+    bt = rt.Batch([m] * steps, [n] * steps, [l] * steps, seed)
+    bt.set_precision(prec)
+    bt.set_graph(True)
+    At = torch.from_numpy(A).to(dev())
+    Dt = [torch.from_numpy(np.ascontiguousarray(D[t])).to(dev()) for t in range(steps)]
+    for rep in range(2):  # the second call replays the captured graphs
+        bt.precondition([At] * steps, Dt)
+        Z, Y, X = bt.project_all([torch.from_numpy(B).to(dev()) for B in Bs])
+        assert bt.status() == [0] * steps
+        for t in range(steps):
+            info = bt.member_info(t)
+            assert info["sketch_bits"] == (64 if prec == 0 else 32), (t, info["sketch_bits"])
+            assert info["gram_cond_est"] <= 10.0, (rep, t, info["gram_cond_est"])
+            e = check_member(A * D[t][None, :], Bs[t], Z[t].cpu().numpy(), Y[t].cpu().numpy(), X[t].cpu().numpy())
+            assert max(e) <= TOL, (rep, t, e)
+    if prec == 0:
+        for t in range(steps):
+            plan = rt.Plan(m, n, l, oracle.instance_seed(seed, t))
+            plan.precondition(torch.from_numpy(A * D[t][None, :]).to(dev()))
+            k_plan, k_member = plan.info()["kappa_est"], bt.member_info(t)["kappa_est"]
+            assert abs(k_member - k_plan) <= 1e-4 * k_plan, (t, k_member, k_plan)
+            plan.close()
+    bt.close()
+
+
 @pytest.mark.parametrize("prec", [1, 3])
 def test_batch_binary32_sketch_escalates_for_an_ill_conditioned_member(rt, prec):
     """The reduced batch precisions sketch in binary32; a member with
