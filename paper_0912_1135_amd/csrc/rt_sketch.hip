@@ -237,8 +237,8 @@ __global__ __launch_bounds__(256) void sketch_pass1(SketchTables t, const double
     sketch_pass1_body<R>(t, A, lda, m, row0, zbuf, tw_cols, bits1, blockIdx.x, blockIdx.y);
 }
 
-// Pass 1 for one column group and a run of row pairs (pair = blockIdx.y,
-// + gridDim.y, ...), software-pipelined: the gathers of the next pair are
+// Pass 1 for column group bx and a run of row pairs (pair = by, by + gy,
+// ...), software-pipelined: the gathers of the next pair are
 // issued right after the current pair is staged in LDS, so they stay in
 // flight through its transform and its stores (block barriers wait for LDS
 // only).  Q = n1 * tw_cols / 256 elements per thread, all of them loaded and
@@ -446,7 +446,8 @@ __global__ __launch_bounds__(256) void sketch_pass2(SketchTables t, int64_t m, i
 }
 
 // Pass 2, software-pipelined like pass 1: the tasks (k1 pair w, group of cp
-// row pairs), numbered w fastest, are dealt round-robin to the blocks, and a
+// row pairs), numbered w fastest, are dealt round-robin to nb blocks (block
+// b0 takes tasks b0, b0 + nb, ...), and a
 // block gathers its next task's columns while the current one is
 // transformed and written out.  Q = 2 cp n2 / 256 elements per thread, all
 // loaded unconditionally: a single-column pair (w = 0 or n1/2) loads its
