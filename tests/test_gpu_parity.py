@@ -304,12 +304,14 @@ def test_fp32_sketch_matches_oracle(rt):
 
 
 @pytest.mark.parametrize("m,n,l,precision", [(37, 65436, 512, 0), (37, 65436, 512, 1), (9, 262137, 64, 0),
-                                               (9, 262137, 64, 1), (300, 262144, 1024, 0), (300, 262144, 1024, 1)])
+                                               (9, 262137, 64, 1), (300, 262144, 1024, 0), (300, 262144, 1024, 1),
+                                               (1, 65537, 16, 1), (3, 131072, 24, 0), (3, 131072, 24, 1)])
 def test_long_row_sketch_matches_oracle(rt, m, n, l, precision):
-    """Transforms of 2^16 and 2^18 points, where both passes walk runs of row
-    pairs with the next gathers in flight: odd m (a last pair with one row),
-    n short of the padded length, and a last group of row pairs shorter than
-    the others, in binary64 and binary32."""
+    """Transforms of 2^16 to 2^18 points, where both passes walk runs of row
+    pairs with the next gathers in flight: odd m (a last pair with one row,
+    down to a single row), n short of the padded length, a last group of row
+    pairs shorter than the others, and a 512 x 256 grid (n1 != n2), in
+    binary64 and binary32."""
     A = np.random.default_rng(4000 + m).standard_normal((m, n))
     plan = rt.Plan(m, n, l, 21)
     plan.set_precision(precision)
