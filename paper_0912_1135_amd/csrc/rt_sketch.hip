@@ -643,8 +643,9 @@ hipError_t sketch_run(const SketchTables &t, const double *A, int64_t lda, int64
     }
     // the pipelined pass 2 in binary32 when each thread holds 16 or 32
     // elements of the 2 cp columns, as many blocks as are resident at once
-    // (in binary64 it measured slower than the plain pass 2: 6.5 against
-    // 5.7 ms for both passes at 2048 x 262144)
+    // (in binary64 it measured slower than the plain pass 2: 6.5, or 6.4 with
+    // three stages per register pass, against 5.7 ms for both passes at
+    // 2048 x 262144)
     const int q2 = (int)((int64_t)2 * cp * n2 / 256);
     const bool pipe2 = sizeof(R) == 4 && (q2 == 16 || q2 == QB) && (int64_t)q2 * 256 == (int64_t)2 * cp * n2 &&
                        (int64_t)cp * t.np * csz < (int64_t(1) << 32);
