@@ -250,7 +250,7 @@ __global__ __launch_bounds__(256) void sketch_pass1(SketchTables t, const double
 //
 // With a column scaling cs (a batch member's A diag(cs)), each element is
 // scaled when staged, cs re-read per row pair from the cache in groups of
-// eight so that only eight scales are live beside the gathered data; the
+// min(Q, 8) so that only that many scales are live beside the gathered data; the
 // product rounds as the plain pass's sign * cs times the element does.
 template <typename R, int Q>
 __device__ __forceinline__ void pass1_pipe_body(const SketchTables &t, const double *A, int64_t lda, int64_t m,
@@ -312,16 +312,18 @@ __device__ __forceinline__ void pass1_pipe_body(const SketchTables &t, const dou
     for (; pair < npairs; pair += gy) {
         const bool has1 = row0 + 2 * pair + 1 < m;
         if (cs) {
+            constexpr int CG = Q < 8 ? Q : 8;  // scales per group, never past the Q elements
+            static_assert(Q % CG == 0, "whole groups of scales");
 #pragma unroll
-            for (int q0 = 0; q0 < Q; q0 += 8) {
-                double c[8];
+            for (int q0 = 0; q0 < Q; q0 += CG) {
+                double c[CG];
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
+                for (int i = 0; i < CG; ++i) {
                     const int64_t x = (int64_t)s_sigma[t1_0 + (q0 + i) * t1_step] * n2 + u0 + j;
                     c[i] = cs[x < t.n ? x : t.n - 1];
                 }
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
+                for (int i = 0; i < CG; ++i) {
                     const int q = q0 + i, t1 = t1_0 + q * t1_step;
                     const double s0 = c[i] * v0[q], s1 = c[i] * (has1 ? v1[q] : 0.0);
                     const double a = (pad >> q) & 1 ? 0.0 : ((neg >> q) & 1 ? -s0 : s0);
@@ -606,6 +608,24 @@ hipError_t resident_blocks(const void *kf, size_t smem, int64_t *out)
     return e;
 }
 
+// The pipelined kernels by elements per thread, 16 or 32 (32 in binary32
+// only, where QB = 32), for launches through hipLaunchKernel.  Shorter rows
+// (4 or 8 elements per thread, as in batches of short members) measured no
+// gain over the plain passes and take those.
+template <typename R, int QB>
+const void *pass1_pipe_kernel(int q, bool grouped)
+{
+    if (q == 16) return grouped ? (const void *)sketch_pass1_pipe_grouped<R, 16> : (const void *)sketch_pass1_pipe<R, 16>;
+    return grouped ? (const void *)sketch_pass1_pipe_grouped<R, QB> : (const void *)sketch_pass1_pipe<R, QB>;
+}
+template <typename R, int QB>
+const void *pass2_pipe_kernel(int q, bool grouped)
+{
+    if (q == 16) return grouped ? (const void *)sketch_pass2_pipe_grouped<R, 16> : (const void *)sketch_pass2_pipe<R, 16>;
+    return grouped ? (const void *)sketch_pass2_pipe_grouped<R, QB> : (const void *)sketch_pass2_pipe<R, QB>;
+}
+inline bool pipe_q(int q, int qb) { return q == 16 || q == qb; }
+
 template <typename R>
 hipError_t sketch_run(const SketchTables &t, const double *A, int64_t lda, int64_t m, double *S, int64_t lds,
                       void *zbuf, int64_t rows_chunk, hipStream_t stream)
@@ -630,10 +650,11 @@ hipError_t sketch_run(const SketchTables &t, const double *A, int64_t lda, int64
     // tw_cols and cp for the same LDS, so its forms are not instantiated)
     constexpr int QB = sizeof(R) == 4 ? 32 : 16;
     const int q1 = (int)((int64_t)n1 * tw_cols / 256);
-    const bool pipe = (q1 == 16 || q1 == QB) && (int64_t)q1 * 256 == (int64_t)n1 * tw_cols && t.np * 8 < (int64_t(1) << 32);
+    const bool pipe = pipe_q(q1, QB) && (int64_t)q1 * 256 == (int64_t)n1 * tw_cols && t.np * 8 < (int64_t(1) << 32);
+    const void *kp1 = pipe ? pass1_pipe_kernel<R, QB>(q1, false) : nullptr;
     int resident = 0;
     if (pipe) {
-        const void *kf = q1 == 16 ? (const void *)sketch_pass1_pipe<R, 16> : (const void *)sketch_pass1_pipe<R, QB>;
+        const void *kf = kp1;
         if ((ea = hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm1)) != hipSuccess) return ea;
         int per_cu = 0, dev = 0, cus = 0;
         if ((ea = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kf, 256, sm1)) != hipSuccess) return ea;
@@ -647,11 +668,12 @@ hipError_t sketch_run(const SketchTables &t, const double *A, int64_t lda, int64
     // three stages per register pass, against 5.7 ms for both passes at
     // 2048 x 262144)
     const int q2 = (int)((int64_t)2 * cp * n2 / 256);
-    const bool pipe2 = sizeof(R) == 4 && (q2 == 16 || q2 == QB) && (int64_t)q2 * 256 == (int64_t)2 * cp * n2 &&
+    const bool pipe2 = sizeof(R) == 4 && pipe_q(q2, QB) && (int64_t)q2 * 256 == (int64_t)2 * cp * n2 &&
                        (int64_t)cp * t.np * csz < (int64_t(1) << 32);
+    const void *kp2 = pipe2 ? pass2_pipe_kernel<R, QB>(q2, false) : nullptr;
     int64_t resident2 = 0;
     if (pipe2) {
-        const void *kf = q2 == 16 ? (const void *)sketch_pass2_pipe<R, 16> : (const void *)sketch_pass2_pipe<R, QB>;
+        const void *kf = kp2;
         if ((ea = hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm2)) != hipSuccess) return ea;
         int per_cu = 0, dev = 0, cus = 0;
         if ((ea = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kf, 256, sm2)) != hipSuccess) return ea;
@@ -665,12 +687,13 @@ hipError_t sketch_run(const SketchTables &t, const double *A, int64_t lda, int64
         if (pipe) {
             const int gx = n2 / tw_cols;
             const int64_t gy = std::min<int64_t>(npairs, std::max(1, resident / gx));
-            if (q1 == 16)
-                hipLaunchKernelGGL((sketch_pass1_pipe<R, 16>), dim3(gx, (unsigned)gy), dim3(256), sm1, stream, t, A, lda,
-                                   m, row0, npairs, z, tw_cols, bits1);
-            else
-                hipLaunchKernelGGL((sketch_pass1_pipe<R, QB>), dim3(gx, (unsigned)gy), dim3(256), sm1, stream, t, A, lda,
-                                   m, row0, npairs, z, tw_cols, bits1);
+            SketchTables ta = t;
+            const double *aa = A;
+            int64_t la = lda, ma = m, ra = row0, pa = npairs;
+            cplx *za = z;
+            int twa = tw_cols, ba = bits1;
+            void *args[] = {&ta, &aa, &la, &ma, &ra, &pa, &za, &twa, &ba};
+            if ((ea = hipLaunchKernel(kp1, dim3(gx, (unsigned)gy), dim3(256), args, sm1, stream)) != hipSuccess) return ea;
         } else {
             hipLaunchKernelGGL(sketch_pass1<R>, dim3(n2 / tw_cols, (unsigned)npairs), dim3(256), sm1, stream, t, A, lda,
                                m, row0, z, tw_cols, bits1);
@@ -680,12 +703,13 @@ hipError_t sketch_run(const SketchTables &t, const double *A, int64_t lda, int64
         if (pipe2) {
             const int64_t ntasks = (npairs + cp - 1) / cp * (n1 / 2 + 1);
             const unsigned gb = (unsigned)std::min<int64_t>(ntasks, resident2);
-            if (q2 == 16)
-                hipLaunchKernelGGL((sketch_pass2_pipe<R, 16>), dim3(gb), dim3(256), sm2, stream, t, m, row0, npairs,
-                                   (const cplx *)z, S, lds, cp, bits2);
-            else
-                hipLaunchKernelGGL((sketch_pass2_pipe<R, QB>), dim3(gb), dim3(256), sm2, stream, t, m, row0, npairs,
-                                   (const cplx *)z, S, lds, cp, bits2);
+            SketchTables ta = t;
+            int64_t ma = m, ra = row0, pa = npairs, la = lds;
+            const cplx *za = z;
+            double *sa = S;
+            int cpa = cp, ba = bits2;
+            void *args[] = {&ta, &ma, &ra, &pa, &za, &sa, &la, &cpa, &ba};
+            if ((ea = hipLaunchKernel(kp2, dim3(gb), dim3(256), args, sm2, stream)) != hipSuccess) return ea;
         } else {
             hipLaunchKernelGGL(sketch_pass2<R>, dim3(n1 / 2 + 1, (unsigned)((npairs + cp - 1) / cp)), dim3(256), sm2,
                                stream, t, m, row0, npairs, (const cplx *)z, S, lds, cp, bits2);
@@ -729,13 +753,13 @@ hipError_t sketch_grouped_run(const SketchGroupArgs *d, int count, const SketchG
     const SketchGeom geo = sketch_geom<R>(tmax);
     const int64_t n1 = sh.max_n1, n2 = sh.max_n2, np = n1 * n2;
     const int q1 = (int)(n1 * geo.tw_cols / 256), q2 = (int)(2 * geo.cp * n2 / 256);
-    const bool pipe1 = sh.one_length && (q1 == 16 || q1 == QB) && (int64_t)q1 * 256 == n1 * geo.tw_cols &&
+    const bool pipe1 = sh.one_length && pipe_q(q1, QB) && (int64_t)q1 * 256 == n1 * geo.tw_cols &&
                        np * 8 < (int64_t(1) << 32);
-    const bool pipe2 = sh.one_length && sizeof(R) == 4 && (q2 == 16 || q2 == QB) &&
+    const bool pipe2 = sh.one_length && sizeof(R) == 4 && pipe_q(q2, QB) &&
                        (int64_t)q2 * 256 == 2 * geo.cp * n2 && geo.cp * np * csz < (int64_t(1) << 32);
     const size_t psm1 = pass1_smem<R>(n1, n2, geo.tw_cols), psm2 = pass2_smem<R>(n2, geo.cp);
-    const void *k1 = q1 == 16 ? (const void *)sketch_pass1_pipe_grouped<R, 16> : (const void *)sketch_pass1_pipe_grouped<R, QB>;
-    const void *k2 = q2 == 16 ? (const void *)sketch_pass2_pipe_grouped<R, 16> : (const void *)sketch_pass2_pipe_grouped<R, QB>;
+    const void *k1 = pipe1 ? pass1_pipe_kernel<R, QB>(q1, true) : nullptr;
+    const void *k2 = pipe2 ? pass2_pipe_kernel<R, QB>(q2, true) : nullptr;
     int64_t res1 = 0, res2 = 0;
     if (pipe1) {
         if ((e = hipFuncSetAttribute(k1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)psm1)) != hipSuccess) return e;
@@ -751,23 +775,21 @@ hipError_t sketch_grouped_run(const SketchGroupArgs *d, int count, const SketchG
     const int64_t pnb = std::min<int64_t>(ntasks, std::max<int64_t>(1, res2 / count));
     for (int c = 0; c < sh.chunks; ++c) {
         if (pipe1) {
-            if (q1 == 16)
-                hipLaunchKernelGGL((sketch_pass1_pipe_grouped<R, 16>), dim3(pgx, (unsigned)pgy, count), dim3(256), psm1,
-                                   stream, d, c, geo.tw_cols, geo.bits1);
-            else
-                hipLaunchKernelGGL((sketch_pass1_pipe_grouped<R, QB>), dim3(pgx, (unsigned)pgy, count), dim3(256), psm1,
-                                   stream, d, c, geo.tw_cols, geo.bits1);
+            const SketchGroupArgs *da = d;
+            int ca = c, twa = geo.tw_cols, ba = geo.bits1;
+            void *args[] = {&da, &ca, &twa, &ba};
+            if ((e = hipLaunchKernel(k1, dim3(pgx, (unsigned)pgy, count), dim3(256), args, psm1, stream)) != hipSuccess)
+                return e;
         } else {
             hipLaunchKernelGGL(sketch_pass1_grouped<R>, dim3(gx1, (unsigned)max_pairs, count), dim3(256), sm1, stream, d, c);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (pipe2) {
-            if (q2 == 16)
-                hipLaunchKernelGGL((sketch_pass2_pipe_grouped<R, 16>), dim3((unsigned)pnb, 1, count), dim3(256), psm2,
-                                   stream, d, c, geo.cp, geo.bits2);
-            else
-                hipLaunchKernelGGL((sketch_pass2_pipe_grouped<R, QB>), dim3((unsigned)pnb, 1, count), dim3(256), psm2,
-                                   stream, d, c, geo.cp, geo.bits2);
+            const SketchGroupArgs *da = d;
+            int ca = c, cpa = geo.cp, ba = geo.bits2;
+            void *args[] = {&da, &ca, &cpa, &ba};
+            if ((e = hipLaunchKernel(k2, dim3((unsigned)pnb, 1, count), dim3(256), args, psm2, stream)) != hipSuccess)
+                return e;
         } else {
             hipLaunchKernelGGL(sketch_pass2_grouped<R>, dim3(gx2, (unsigned)max_pairs, count), dim3(256), sm2, stream, d, c);
         }
